@@ -1,0 +1,252 @@
+"""Pins for the oracle's ray caster and its adjoint (CPU only).
+
+Closed forms (constant-density slab: A = 1 - (1-a)^n), a dense regular-grid brute force using
+scipy's trilinear interpolation and numpy.interp transfer tables, geometric properties of the
+rays, early-termination bounds, and central finite differences of the FP64 forward for the
+adjoint."""
+import math
+
+import numpy as np
+import pytest
+
+from helpers import bf_render_dense, const_tf, np_mip
+from paper_1407_2074_amd import synth
+from paper_1407_2074_amd.synth import View
+
+
+def _full(C, dims):
+    Dx, Dy, Dz = dims
+    return np.full((Dz, Dy, Dx), (1 << C) - 1, np.uint8)
+
+
+def _axis_view(dims, C, alpha, rgb, margin=5.0, step=0.5):
+    Dx, Dy, Dz = dims
+    pos, rgba = const_tf(C, alpha, rgb)
+    win = np.array([[0.0, 4095.0]] * C, np.float32)
+    return View(eye=np.array([Dx + margin, Dy / 2, Dz / 2], np.float32),
+                target=np.array([0.0, Dy / 2, Dz / 2], np.float32),
+                up=np.array([0, 0, 1], np.float32), width=1, height=1, tf_pos=pos,
+                tf_rgba=rgba, window=win, step=step)
+
+
+def test_slab_closed_form_one_channel(orc):
+    dims = (16, 12, 10)
+    v0 = np.full((1, 10, 12, 16), 2000, np.uint16)
+    t = orc.Tree(v0, _full(1, dims), 4, 0, 1)
+    a, rgb = 0.0625, (0.25, 0.5, 0.75)          # exact in float32
+    v = _axis_view(dims, 1, [a], [rgb])
+    (img,), (ns,), _ = t.render([v], want_info=True)
+    n = 2 * dims[0]
+    assert ns[0, 0] == n
+    A = 1 - (1 - a) ** n
+    assert abs(img[0, 0, 3] - A) < 1e-14
+    assert np.allclose(img[0, 0, :3], np.array(rgb) * A, atol=1e-14)
+
+
+def test_slab_closed_form_three_channels(orc):
+    dims = (24, 8, 8)
+    v0 = np.full((3, 8, 8, 24), 1500, np.uint16)
+    t = orc.Tree(v0, _full(3, dims), 8, 0, 1)
+    # the control points are float32: use their exact values in the closed form
+    a = np.array([0.02, 0.05, 0.11], np.float32).astype(np.float64)
+    rgb = np.array([[1.0, 0.2, 0.1], [0.1, 0.9, 0.3], [0.3, 0.3, 1.0]],
+                   np.float32).astype(np.float64)
+    v = _axis_view(dims, 3, a, rgb, margin=3.25)
+    (img,), (ns,), _ = t.render([v], want_info=True)
+    n = 2 * dims[0]
+    assert ns[0, 0] == n
+    T = np.prod(1 - a)
+    assert abs(img[0, 0, 3] - (1 - T ** n)) < 1e-13
+    per_pos = sum(rgb[c] * a[c] * np.prod(1 - a[:c]) for c in range(3))
+    assert np.allclose(img[0, 0, :3], per_pos * (1 - T ** n) / (1 - T), atol=1e-13)
+
+
+def test_homogeneous_volume_per_ray_closed_form(orc):
+    """Any constant volume: A = 1-(1-a)^n per pixel, n within one of the float64 chord/step."""
+    dims = (20, 14, 9)
+    v0 = np.full((1, 9, 14, 20), 700, np.uint16)
+    t = orc.Tree(v0, _full(1, dims), 4, 0, 1)
+    a = 0.03
+    pos, rgba = const_tf(1, [a], [(1, 1, 1)])
+    eye, tgt, up = synth.orbit_camera(dims, 33.0, 21.0)
+    v = View(eye=eye, target=tgt, up=up, width=24, height=20, tf_pos=pos, tf_rgba=rgba,
+             window=np.array([[0, 4095]], np.float32), step=0.5)
+    (img,), (ns,), _ = t.render([v], want_info=True)
+    assert np.allclose(img[..., 3], 1 - (1 - a) ** ns, atol=1e-13)
+    rays, lh = t.rays(v)
+    d = rays[..., 3:6].astype(np.float64)
+    o = rays[..., :3].astype(np.float64)
+    D = np.array(dims, np.float64)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        ta, tb = (0 - o) / d, (D - o) / d
+    t0 = np.maximum(np.nanmax(np.minimum(ta, tb), -1), 0)
+    t1 = np.nanmin(np.maximum(ta, tb), -1)
+    hit = t1 > t0
+    assert np.array_equal(hit, lh[..., 1] == 1)
+    est = np.where(hit, (t1 - t0) / 0.5, 0)
+    assert np.all(np.abs(ns - est) <= 1.0 + 1e-6)
+    assert (ns > 0).sum() > 100
+
+
+def _random_case(dims, C=3, seed=5, blobs=6):
+    vol = synth.gen_volume(dims, C, seed=seed, n_blobs=blobs)
+    return vol
+
+
+@pytest.mark.parametrize("lod", [0, 1, 2, -1])
+def test_dense_bruteforce_equals_octree_render(orc, lod):
+    """Threshold 0 and everything inserted: every node holds a brick, so octree casting must
+    equal plain regular-grid casting on the mipmap level."""
+    dims, M, C = (30, 22, 17), 4, 3
+    vol = _random_case(dims, C)
+    t = orc.Tree(vol, _full(C, dims), M, 0, 0)
+    levels = np_mip(vol, M)
+    v = synth.make_view(dims, C, 1, az=37.0, el=18.0, width=40, height=33, lod=lod,
+                        clips=[(1.0, 0.0, 0.0, 6.0)], dist_scale=0.7 if lod < 0 else 1.0)
+    # a bright TF so the comparison is not dominated by transparent samples
+    v.tf_pos[:, 1] = 0.005
+    (img,) = t.render([v])
+    ref = bf_render_dense(levels, dims, v, t.N)
+    assert img[..., 3].max() > 0.05
+    assert np.max(np.abs(img - ref)) < 1e-10
+
+
+def test_per_ray_lod_uses_footprint(orc):
+    dims, M = (64, 64, 64), 4
+    vol = _random_case(dims, 1, blobs=4)
+    t = orc.Tree(vol, _full(1, dims), M, 0, 0)
+    v = synth.make_view(dims, 1, 1, az=10, el=5, width=16, height=16, lod=-1)
+    rays, lh = t.rays(v)
+    th = math.tan(math.radians(15.0))
+    w = rays[..., 6].astype(np.float64) * 2 * th / 16
+    hit = lh[..., 1] == 1
+    ref = np.clip(np.floor(np.log2(w[hit])), 0, t.N)
+    # away from exact powers of two the float64 footprint decides the same level
+    safe = np.abs(np.log2(w[hit]) - np.round(np.log2(w[hit]))) > 1e-4
+    assert np.array_equal(lh[..., 0][hit][safe], ref[safe])
+    assert len(np.unique(lh[..., 0][hit])) >= 1 and lh[..., 0][hit].max() >= 1
+
+
+def test_ray_geometry_properties(orc):
+    dims = (40, 30, 20)
+    vol = np.full((1, 20, 30, 40), 100, np.uint16)
+    t = orc.Tree(vol, _full(1, dims), 4, 0, 0)
+    v = synth.make_view(dims, 1, 1, az=60, el=-25, width=31, height=21,
+                        clips=[(0.3, -0.5, 0.8, 2.0)])
+    rays, lh = t.rays(v)
+    d = rays[..., 3:6].astype(np.float64)
+    assert np.allclose(np.linalg.norm(d, axis=-1), 1.0, atol=1e-6)
+    f = np.asarray(v.target, np.float64) - np.asarray(v.eye, np.float64)
+    assert np.allclose(d[10, 15], f / np.linalg.norm(f), atol=1e-6)       # centre pixel
+    # corner pixel angle: tan = th*sqrt((W-1)^2/W^2*(W/H)^2 + (H-1)^2/H^2)
+    th = math.tan(math.radians(15))
+    cosang = d[0, 0] @ (f / np.linalg.norm(f))
+    exp = math.atan(th * math.hypot(30 / 31 * 31 / 21, 20 / 21))
+    assert abs(math.acos(min(1.0, cosang)) - exp) < 1e-5
+    hit = lh[..., 1] == 1
+    o = rays[..., :3].astype(np.float64)
+    p0 = o + rays[..., 6:7] * d
+    n = np.array([0.3, -0.5, 0.8])
+    on_box = np.any((np.abs(p0) < 1e-3) | (np.abs(p0 - np.array(dims)) < 1e-3), axis=-1)
+    on_clip = np.abs(p0 @ n - 2.0) < 1e-3
+    assert np.all((on_box | on_clip)[hit])
+    inside = np.all((p0 > -1e-3) & (p0 < np.array(dims) + 1e-3), -1) & (p0 @ n >= 2.0 - 1e-3)
+    assert np.all(inside[hit])
+    assert hit.sum() > 50 and (~hit).sum() > 0
+
+
+def test_early_termination_bound(orc):
+    dims, M, C = (32, 32, 32), 8, 3
+    vol = _random_case(dims, C, blobs=30)
+    t = orc.Tree(vol, _full(C, dims), M, 0, 0)
+    v = synth.make_view(dims, C, 1, az=15, el=40, width=24, height=24)
+    v.tf_rgba[:, 2:, 3] = 0.6
+    v.tf_pos[:, 1] = 0.001
+    (ref,) = t.render([v])
+    v.ert_alpha = 0.9
+    (img,), _, mg = t.render([v], want_info=True)
+    assert (ref[..., 3] >= 0.9).sum() > 20
+    diff = ref - img
+    assert diff.min() > -1e-12 and diff.max() <= 0.1 + 1e-12
+    assert np.all(img[..., 3][ref[..., 3] >= 0.9] >= 0.9)
+    m = mg[0][ref[..., 3] == 0]
+    assert np.all(np.isinf(m) | (m > 0))
+
+
+def _loss_and_grad_setup(dims, C, seed=3):
+    vol = synth.gen_volume(dims, C, seed=seed, n_blobs=5, dtype="f32")
+    return vol
+
+
+def _loss(orc, vol, views, M, tgt):
+    t = orc.Tree(vol, _full(vol.shape[0], vol.shape[:0:-1]), M, 0, 0)
+    imgs = t.render(views)
+    return sum(float(((i - g) ** 2).sum()) for i, g in zip(imgs, tgt)), t, imgs
+
+
+def test_adjoint_slab_closed_form(orc):
+    """dA/da = n (1-a)^(n-1) for the constant slab, through the control-point alphas."""
+    dims = (16, 12, 10)
+    v0 = np.full((1, 10, 12, 16), 2000, np.uint16)
+    t = orc.Tree(v0, _full(1, dims), 4, 0, 1)
+    a = 0.0625
+    v = _axis_view(dims, 1, [a], [(0.25, 0.5, 0.75)])
+    g = np.zeros((1, 1, 4))
+    g[0, 0, 3] = 1.0
+    dctrl, _ = t.render_grad([v], [g], want_voxels=False)
+    n = 2 * dims[0]
+    assert abs(dctrl[0, 0, :, 3].sum() - n * (1 - a) ** (n - 1)) < 1e-12
+
+
+def test_adjoint_matches_central_differences(orc):
+    """FP64 adjoint vs central differences (eps 1e-3) of the FP64 forward: transfer-function
+    RGBA (the image is polynomial in them) and voxel values with a linear TF (no kinks)."""
+    dims, M, C = (12, 10, 8), 4, 3
+    vol = _loss_and_grad_setup(dims, C)
+    rng = np.random.default_rng(0)
+    v = synth.make_view(dims, C, 4, az=30, el=20, width=12, height=10, dtype="f32")
+    v.tf_pos[:, 1] = 0.004
+    v.tf_rgba[:, 2:, 3] = 0.2
+    tgt = [np.zeros((10, 12, 4))]
+    L0, t, imgs = _loss(orc, vol, [v], M, tgt)
+    gI = [2 * (imgs[0] - tgt[0])]
+    dctrl, dvox = t.render_grad([v], gI)
+    eps = 1e-3
+    checked = 0
+    for _ in range(25):
+        c, j, q = rng.integers(C), rng.integers(8), rng.integers(4)
+        x = float(v.tf_rgba[c, j, q])
+        hi, lo = np.float32(x + eps), np.float32(x - eps)
+        v.tf_rgba[c, j, q] = hi
+        Lp, _, _ = _loss(orc, vol, [v], M, tgt)
+        v.tf_rgba[c, j, q] = lo
+        Lm, _, _ = _loss(orc, vol, [v], M, tgt)
+        v.tf_rgba[c, j, q] = x
+        fd = (Lp - Lm) / (float(hi) - float(lo))
+        # central differences are O(eps^2): 1e-4 relative leaves room for that and nothing else
+        assert abs(fd - dctrl[0, c, j, q]) <= 1e-4 * max(abs(fd), 1e-2), (c, j, q, fd,
+                                                                          dctrl[0, c, j, q])
+        checked += 1
+    # voxel gradients: a linear TF makes the image smooth in the voxel values
+    lin = synth.make_view(dims, C, 4, az=30, el=20, width=12, height=10, dtype="f32")
+    lin.tf_pos[:] = np.linspace(0, 1, 8, dtype=np.float32)
+    for c in range(C):
+        lin.tf_rgba[c] = np.linspace([0.1, 0.2, 0.3, 0.0], [0.9, 0.6, 0.4, 0.3], 8)
+    lin.window[:, 1] = float(vol.max()) * 1.01
+    L0, t, imgs = _loss(orc, vol, [lin], M, tgt)
+    _, dvox = t.render_grad([lin], [2 * (imgs[0] - tgt[0])])
+    flat = np.argsort(-np.abs(dvox).ravel())[:200]
+    for k in rng.choice(flat, 25, replace=False):
+        idx = np.unravel_index(k, dvox.shape)
+        x = float(vol[idx])
+        vol[idx] = np.float32(x + eps)
+        hi = float(vol[idx])
+        Lp, _, _ = _loss(orc, vol, [lin], M, tgt)
+        vol[idx] = np.float32(x - eps)
+        lo = float(vol[idx])
+        Lm, _, _ = _loss(orc, vol, [lin], M, tgt)
+        vol[idx] = np.float32(x)
+        fd = (Lp - Lm) / (hi - lo)
+        assert abs(fd - dvox[idx]) <= 1e-4 * max(abs(fd), 1e-3), (idx, fd, dvox[idx])
+        checked += 1
+    assert checked == 50
