@@ -1,0 +1,204 @@
+/*
+ * octree_rc.h -- C ABI of the MI355X (gfx950) multi-channel brick-octree ray caster.
+ *
+ * Method: Brix, Prassni & Hinrichs, "Visualization of Large Volumetric Multi-Channel Microscopy
+ * Data Streams on Standard PCs".  A multi-channel volume is kept as a 3D mipmap of constant-size
+ * bricks addressed by an octree that is built incrementally from inserted blocks (section
+ * "Incremental Construction"), and rendered by front-to-back emission-absorption ray casting
+ * with per-channel transfer functions (Algorithm 1, "Basic Ray-Casting").
+ *
+ * Conventions for every call:
+ *  - Return value: OCT_OK (0) on success, OCT_INCOMPLETE (1) when the call succeeded but work
+ *    remains (see brick_pool_upload), a negative OCT_E* code on failure.  No C++ exception
+ *    crosses the ABI.  oct_last_error() gives a message for the last failure on a handle.
+ *  - Invalid arguments return OCT_EINVAL before anything is changed.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).  Device work is
+ *    enqueued on it in call order; calls that need results on the host say so.
+ *  - Device pointers passed in are borrowed: they must stay valid until the stream has passed
+ *    the call.  Host pointers are consumed before the call returns.
+ *  - A handle is not thread-safe: calls on one handle must be serialised by the caller.
+ *    Renders on different streams may overlap each other (the handle keeps one set of per-call
+ *    buffers per in-flight render), but not a brick_pool_upload.
+ *  - Coordinates: world space is level-0 voxel units; the volume occupies [0,Dx]x[0,Dy]x[0,Dz];
+ *    voxel (x,y,z) has its centre at (x+1/2, y+1/2, z+1/2).  Volumes and blocks are planar per
+ *    channel, [C][z][y][x], x fastest.
+ */
+#ifndef OCTREE_RC_H
+#define OCTREE_RC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define OCT_OK 0
+#define OCT_INCOMPLETE 1
+#define OCT_EINVAL (-1)
+#define OCT_ENOMEM (-2)
+#define OCT_ERANGE (-3)
+#define OCT_EDEVICE (-4)
+#define OCT_EBUSY (-5)
+
+#define OCT_U16 0
+#define OCT_F32 1
+#define OCT_MAX_CHANNELS 4
+#define OCT_MAX_CLIPS 3
+#define OCT_TF_POINTS 8
+#define OCT_TILE 8
+
+typedef struct oct_handle oct_handle;
+
+/* Volume description (section "CPU Data Structure", Eq. 1, and "Handling Volumes of Arbitrary
+ * Dimensions"): the original dims are virtually extended to a cube M*2^N with the smallest N;
+ * level L of the mipmap has valid extent ceil(D / 2^L) per axis.  Only the channel count and
+ * the final resolution are needed up front ("Incremental Construction"). */
+typedef struct {
+    int32_t dims[3];            /* Dx, Dy, Dz of the original volume, each >= 1           */
+    int32_t channels;           /* C, 1..4                                                */
+    int32_t brick_size;         /* M, even, 2..128 (a brick holds M^3 voxels per channel)  */
+    int32_t dtype;              /* OCT_U16 or OCT_F32                                      */
+    double background;          /* value of not-yet-inserted voxels; an integer for u16   */
+    double homog_threshold;     /* a node is homogeneous when max-min < threshold in every
+                                   channel (strict); 0 keeps every brick                  */
+    uint64_t device_pool_bytes; /* cap of the device brick pool; 0 = room for every brick */
+    int32_t reserved[4];        /* must be 0                                              */
+} oct_create_params;
+
+/* One render request (Algorithm 1 and "Basic Ray-Casting").  Pinhole camera with square
+ * pixels through pixel centres, row 0 at the top.  The image is premultiplied RGBA float32,
+ * [height][width][4], not blended with any background. */
+typedef struct {
+    float eye[3], target[3], up[3];
+    float fov_y_deg;            /* vertical field of view, (0, 180)                        */
+    int32_t width, height;      /* image size, >= 1                                        */
+    int32_t tile_begin;         /* first 8x8 tile (row-major over ceil(W/8) x ceil(H/8))   */
+    int32_t tile_count;         /* number of tiles, -1 = to the end of the image           */
+    float step;                 /* sample spacing in level-0 voxel units, > 0              */
+    float ert_alpha;            /* stop a ray once its opacity >= ert_alpha; >= 1: never   */
+    int32_t lod;                /* >= 0: fixed level (clamped to N); -1: per ray, the level
+                                   whose voxel projects to about one pixel at the entry   */
+    int32_t n_clip;             /* 0..3 clipping planes                                    */
+    float clip[OCT_MAX_CLIPS][4]; /* (nx, ny, nz, d): keep points p with n.p >= d          */
+    /* per-channel transfer function: 8 control points with ascending positions in [0,1] and
+     * RGBA values; tabulated to 256 entries at x = k/255, linear in between, end values held */
+    float tf_pos[OCT_MAX_CHANNELS][OCT_TF_POINTS];
+    float tf_rgba[OCT_MAX_CHANNELS][OCT_TF_POINTS][4];
+    float window[OCT_MAX_CHANNELS][2]; /* intensity (lo, hi) mapped to x = 0..1, hi > lo     */
+    int32_t no_skip;            /* 1 disables empty-space skipping (same image, slower)    */
+    int32_t reserved[3];        /* must be 0                                               */
+} oct_view;
+
+typedef struct {
+    uint64_t bricks_gathered;   /* bordered bricks (re)built by this call                  */
+    uint64_t bricks_resident;   /* brick nodes with a device slot after the call           */
+    uint64_t bricks_total;      /* brick nodes in the octree                               */
+    uint64_t nodes_changed;     /* node-table entries rewritten (change events applied)    */
+    uint64_t bytes_written;     /* device bytes written for bricks and node entries        */
+} oct_upload_stats;
+
+typedef struct {
+    uint64_t rays;              /* pixels whose ray hits the clipped volume                */
+    uint64_t positions_nominal; /* sample positions t_k < t1 over all rays                 */
+    uint64_t positions_composited; /* positions actually sampled (not skipped, before ERT)  */
+} oct_render_stats;
+
+/* Creates the octree: the root node exists from the start and holds only the background
+ * value, so the tree can be rendered at any time ("Incremental Construction").  Allocates the
+ * device-resident mipmap, insertion mask, node table and brick pool.  *out receives the
+ * handle (owned by the caller, released by octree_destroy).  Errors: OCT_EINVAL for a bad
+ * parameter, OCT_ENOMEM when device memory runs out, OCT_EDEVICE on other HIP errors. */
+int octree_create(const oct_create_params *params, void *stream, oct_handle **out);
+
+/* Releases the handle and all memory it owns after synchronising its work. */
+int octree_destroy(oct_handle *h);
+
+/* Returns the octree to the state right after octree_create (background everywhere, only the
+ * root node), keeping the allocations.  Enqueued on `stream`. */
+int octree_clear(oct_handle *h, void *stream);
+
+/* Inserts a cuboid block of voxels at an arbitrary position ("Incremental Construction",
+ * step 1 and step 2): the block overwrites the level-0 voxels it covers (earlier values are
+ * replaced) and every mipmap level above is re-half-sampled over the affected region,
+ * integer mean rounded half up over the valid children (u16) or float32-rounded mean (f32).
+ *   channel: 0..C-1 for one channel, or -1 for all channels at once
+ *   origin:  x0, y0, z0 of the block; size: nx, ny, nz (each >= 1, block inside the volume)
+ *   data:    planar [Cb][nz][ny][nx] in the volume's dtype, Cb = C or 1, x fastest
+ *   data_is_device: 1 if `data` is device memory, 0 if host memory (copied before return)
+ * Statistics, homogeneity decisions (step 3) and the node-table change events are applied
+ * by the next brick_pool_upload.  Errors: OCT_EINVAL, OCT_ERANGE (block outside the volume),
+ * OCT_EDEVICE. */
+int octree_insert_block(oct_handle *h, int32_t channel, const int32_t origin[3],
+                        const int32_t size[3], const void *data, int32_t data_is_device,
+                        void *stream);
+
+/* Slice-wise insertion, the streaming case of a slice-scanning microscope: inserts nz whole
+ * z-slices starting at z0 (equivalent to octree_insert_block with origin (0,0,z0) and size
+ * (Dx,Dy,nz)). */
+int octree_insert_slices(oct_handle *h, int32_t channel, int32_t z0, int32_t nz,
+                         const void *data, int32_t data_is_device, void *stream);
+
+/* Applies everything inserted since the previous call to the render-side structures
+ * ("Incremental Octree Updates on the GPU", "Filtering across Brick Boundaries", step 3 of
+ * "Incremental Construction"): per-brick min/max/sum, homogeneity (only complete nodes are
+ * merged), change events for created, deleted and updated nodes written into the device node
+ * table, and bordered (M+2)^3 bricks gathered into the brick pool for every brick node whose
+ * data or neighbourhood changed.  Synchronises `stream` once (statistics read-back).
+ * byte_budget limits the bytes of bricks gathered by this call (0 = unlimited); when bricks
+ * remain, the call returns OCT_INCOMPLETE and those nodes render with their AVG until a later
+ * call gathers them.  `out` may be NULL.  Errors: OCT_ENOMEM when the pool cap cannot hold
+ * every brick node (the remaining nodes render with their AVG), OCT_EDEVICE. */
+int brick_pool_upload(oct_handle *h, uint64_t byte_budget, void *stream, oct_upload_stats *out);
+
+/* Renders n_views views in one launch (Algorithm 1 with accumulation-level intermixing of the
+ * channels): each 8x8 tile of each view is one 64-lane wave.  images[i] is a device pointer
+ * to [height][width][4] float32 for view i; only the tiles [tile_begin, tile_begin+count)
+ * are written.  ckpt_ws: NULL, or a device workspace of render_ckpt_bytes() bytes that
+ * receives the transmittance checkpoints render_views_backward needs.  `out` (may be NULL)
+ * returns sample counts; passing it synchronises the stream.  Errors: OCT_EINVAL, OCT_EDEVICE. */
+int render_views(oct_handle *h, int32_t n_views, const oct_view *views, float *const *images,
+                 void *ckpt_ws, void *stream, oct_render_stats *out);
+
+/* Bytes of checkpoint workspace render_views needs for these views (0 on bad arguments). */
+size_t render_ckpt_bytes(const oct_handle *h, int32_t n_views, const oct_view *views);
+
+/* Adjoint of render_views for a scalar loss L(images): given dL/dimage per view (device,
+ * [height][width][4] float32) and the workspace filled by the forward with the same views,
+ * accumulates (adds) into
+ *   dL_dctrl   device [n_views][C][8][4] float32: gradient w.r.t. tf_rgba (positions fixed)
+ *   dL_dvoxels device [C][Dz][Dy][Dx] float32 or NULL: gradient w.r.t. the level-0 voxel
+ *              values, defined for views with lod 0 on an octree whose level-0 nodes all hold
+ *              bricks (threshold 0, everything inserted)
+ * Errors: OCT_EINVAL (e.g. voxel gradients requested where not defined), OCT_EDEVICE. */
+int render_views_backward(oct_handle *h, int32_t n_views, const oct_view *views,
+                          const float *const *dL_dimages, const void *ckpt_ws, float *dL_dctrl,
+                          float *dL_dvoxels, void *stream);
+
+/* Canonical dump of the octree for parity checks (synchronises the handle's stream).
+ * Layout (little endian): a 64-byte header "OCTDUMP1", int32 dims[3], C, M, N, dtype,
+ * n_nodes, n_bricks; then one 192-byte record per existing node ordered by level descending,
+ * then z, y, x: int32 level, bx, by, bz, state (0 empty, 1 homogeneous leaf, 2 homogeneous
+ * with children, 3 brick), flags (1 has children, 2 complete, 4 populated), 0, 0; float64
+ * avg[4], bmin[4], bmax[4], smin[4], smax[4]; then the bordered (M+2)^3 brick of every brick
+ * node in record order, channel-interleaved [z][y][x][C] in the dtype.  With buf == NULL or
+ * cap too small only *needed is set and OCT_ERANGE returned. */
+int octree_dump_canonical(oct_handle *h, void *buf, size_t cap, size_t *needed);
+
+/* Copies mipmap level `level` (planar [C][ez][ey][ex], dtype) to host memory `out` of `cap`
+ * bytes; ext receives (ex, ey, ez).  Applies pending inserts first (synchronises). */
+int octree_read_level(oct_handle *h, int32_t level, void *out, size_t cap, int32_t ext[3]);
+
+/* Number of levels N+1 and the brick-pool slot size in bytes. */
+int octree_info(const oct_handle *h, int32_t *levels, uint64_t *brick_bytes,
+                uint64_t *pool_slots);
+
+/* Message describing the last failure on this handle (or of the last octree_create when h is
+ * NULL); never NULL. */
+const char *oct_last_error(const oct_handle *h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* OCTREE_RC_H */

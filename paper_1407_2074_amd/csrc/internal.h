@@ -1,0 +1,115 @@
+// Internal declarations shared by the runtime and the kernel translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace octrc {
+
+constexpr int kMaxLevels = 16;
+constexpr int kMaxC = 4;
+
+// Kinds of a resolved node-table cell.  Every cell of the virtual complete tree has an entry:
+// a cell whose node does not exist carries the AVG of its deepest existing ancestor, so a
+// lookup never has to descend.
+enum CellKind : int32_t { kAvg = 0, kBrick = 1, kBrickMissing = 2 };
+
+// Device node-table entry, one per cell of every level (64 bytes, four 16-byte loads).
+struct alignas(16) DevCell {
+    int32_t kind;
+    int32_t slot;
+    int32_t pad0, pad1;
+    float avg[4];   // AVG per channel (brick-less cells) -- value used for sampling
+    float lo[4];    // lower bound of every value a sample inside the cell can take
+    float hi[4];    // upper bound (bordered-brick range unioned over the subtree)
+};
+static_assert(sizeof(DevCell) == 64, "DevCell layout");
+
+// Geometry of the volume, passed by value to kernels.
+struct VolGeom {
+    int32_t dims[3];
+    int32_t C;
+    int32_t M;
+    int32_t N;
+    int32_t dtype;
+    int32_t ext[kMaxLevels][3];
+    int64_t lvl_off[kMaxLevels];   // element offset of level L in the master buffer
+    int32_t grid[kMaxLevels];      // cells per axis at level L = 2^(N-L)
+    int32_t cell_off[kMaxLevels];  // offset of level L in the node table
+};
+
+// Per-view constants of one render launch (built on the host, read by every lane).
+struct DevView {
+    float eye[3];
+    float f[3], r[3], u[3];
+    float kx, ky, klod;
+    float step;
+    float ert;            // opacity at which a ray stops (>= 1: never)
+    int32_t width, height, tiles_x;
+    int32_t lod;          // fixed level, or -1 for the per-ray footprint level
+    int32_t n_clip;
+    int32_t skip;
+    float clip[3][4];
+    float ulo[kMaxC];     // u = (s - ulo) * uscale, u in [0, 255]
+    float uscale[kMaxC];
+    float tf_pos[kMaxC][8];
+    float tf_rgba[kMaxC][8][4];
+    float *image;
+    float *ckpt;          // transmittance checkpoints (NULL: none)
+    int64_t ckpt_off;     // float offset of this view's checkpoints in the workspace
+};
+
+// One workgroup of a render launch: 4 waves = up to 4 consecutive tiles of one view.
+struct WgItem {
+    int32_t view;
+    int32_t tile0;
+    int32_t ntiles;
+    int32_t pad;
+};
+
+struct BrickJob {       // one bordered brick to (re)build
+    int32_t slot, level, bx, by, bz;
+    int32_t pad[3];
+};
+
+struct CellStat {       // statistics of one cell over its valid voxels
+    double mn[kMaxC], mx[kMaxC], sum[kMaxC];
+    uint32_t ins[kMaxC];  // level 0 only: inserted voxels per channel
+};
+
+struct CellDelta {      // one change event applied to the node table
+    int32_t index;
+    int32_t kind;
+    int32_t slot;
+    int32_t pad;
+    float avg[4];
+};
+
+struct RenderCounters {
+    unsigned long long rays, nominal, composited;
+};
+
+// ---- launchers (build path) ----
+hipError_t launch_insert(const VolGeom &g, void *master, uint8_t *mask, const void *src,
+                         int channel, const int32_t origin[3], const int32_t size[3],
+                         hipStream_t s);
+hipError_t launch_downsample(const VolGeom &g, void *master, int L, const int32_t lo[3],
+                             const int32_t hi[3], hipStream_t s);
+hipError_t launch_stats(const VolGeom &g, const void *master, const uint8_t *mask,
+                        const int32_t *cells /* (level, bx, by, bz) x n */, int n,
+                        CellStat *out, hipStream_t s);
+hipError_t launch_apply_deltas(DevCell *table, const CellDelta *d, int n, hipStream_t s);
+hipError_t launch_gather(const VolGeom &g, const void *master, const DevCell *table,
+                         void *pool, uint64_t brick_bytes, const BrickJob *jobs, int n,
+                         float *slot_range, float background, hipStream_t s);
+hipError_t launch_ranges(const VolGeom &g, DevCell *table, const float *slot_range,
+                         hipStream_t s);
+hipError_t launch_clear(const VolGeom &g, void *master, uint8_t *mask, double background,
+                        hipStream_t s);
+
+// ---- launchers (render path) ----
+hipError_t launch_render(const VolGeom &g, const DevCell *table, const void *pool,
+                         uint64_t brick_bytes, const DevView *views, const WgItem *items,
+                         int n_items, RenderCounters *counters, hipStream_t s);
+
+}  // namespace octrc

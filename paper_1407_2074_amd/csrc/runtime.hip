@@ -1,0 +1,953 @@
+// Host side of the C ABI: octree manager (node states, homogeneity, change events, brick-pool
+// slots) and launch orchestration.  All voxel work runs in the kernels of build_kernels.hip
+// and render_kernels.hip; this file only decides what to launch.
+#include "../../include/octree_rc.h"
+#include "internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+using namespace octrc;
+
+namespace {
+
+enum NodeState : int8_t { kNone = -1, kEmpty = 0, kHomogLeaf = 1, kHomog = 2, kBrickState = 3 };
+
+struct HCell {
+    // statistics of the node's own level-L brick over its valid voxels
+    double bmin[kMaxC] = {0, 0, 0, 0}, bmax[kMaxC] = {0, 0, 0, 0}, bsum[kMaxC] = {0, 0, 0, 0};
+    // level-0 region: min / max, inserted voxels per channel, valid voxels
+    double smin[kMaxC] = {0, 0, 0, 0}, smax[kMaxC] = {0, 0, 0, 0};
+    uint64_t ins[kMaxC] = {0, 0, 0, 0};
+    uint64_t nvalid0 = 0;
+    uint64_t count = 0;          // valid level-L voxels of the brick
+    bool inside = false;
+    bool have_stats = false;
+    // tree state
+    int8_t exists = 0, populated = 0, complete = 0, has_children = 0, state = kNone;
+    double avg[kMaxC] = {0, 0, 0, 0};
+    // device side
+    int32_t slot = -1;
+    bool needs_gather = false;   // bordered brick in the slot is not current
+    int32_t dev_kind = kAvg;     // last uploaded entry
+    int32_t dev_slot = -1;
+    float dev_avg[4] = {0, 0, 0, 0};
+    bool dev_valid = false;
+};
+
+struct Box {
+    int32_t lo[3], hi[3];  // inclusive, level-local voxel coordinates
+};
+
+// A pinned host buffer paired with a device buffer, grown on demand.
+struct Stage {
+    void *host = nullptr;
+    void *dev = nullptr;
+    size_t cap = 0;
+    hipEvent_t ev = nullptr;  // last use of the host side by an async copy
+};
+
+struct RenderSlot {
+    Stage st;
+};
+
+constexpr int kRenderSlots = 8;
+
+}  // namespace
+
+struct oct_handle {
+    oct_create_params p{};
+    VolGeom g{};
+    int device = 0;
+    size_t esz = 2;
+    int64_t n_cells = 0;
+    uint64_t brick_bytes = 0;
+    int64_t n_slots = 0;
+    void *master = nullptr;
+    uint8_t *mask = nullptr;
+    DevCell *table = nullptr;
+    uint8_t *pool = nullptr;
+    float *slot_range = nullptr;
+    void *ins_stage = nullptr;   // device staging for host-pointer inserts
+    size_t ins_stage_cap = 0;
+    hipEvent_t ins_ev = nullptr;
+    Stage up;                    // upload: cell list / stats / deltas / jobs
+    RenderSlot rs[kRenderSlots];
+    int next_rs = 0;
+    std::vector<HCell> cells;
+    std::vector<int32_t> free_slots;
+    std::vector<std::vector<Box>> dirty;  // per level
+    std::string err;
+    float background_f = 0.0f;
+};
+
+static std::string g_create_err;
+
+namespace {
+
+int fail(oct_handle *h, int code, const std::string &msg)
+{
+    if (h) h->err = msg;
+    else g_create_err = msg;
+    return code;
+}
+
+#define HIPCHK(h, expr)                                                                     \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return fail((h), e_ == hipErrorOutOfMemory ? OCT_ENOMEM : OCT_EDEVICE,          \
+                        std::string(#expr) + ": " + hipGetErrorString(e_));                 \
+    } while (0)
+
+int64_t cell_index(const VolGeom &g, int L, int x, int y, int z)
+{
+    const int G = g.grid[L];
+    return g.cell_off[L] + ((int64_t)z * G + y) * G + x;
+}
+
+int stage_reserve(oct_handle *h, Stage &s, size_t bytes)
+{
+    if (s.ev) HIPCHK(h, hipEventSynchronize(s.ev));
+    if (bytes <= s.cap) return OCT_OK;
+    size_t cap = std::max<size_t>(bytes, 2 * s.cap);
+    cap = std::max<size_t>(cap, 4096);
+    if (s.host) HIPCHK(h, hipHostFree(s.host));
+    if (s.dev) HIPCHK(h, hipFree(s.dev));
+    s.host = nullptr;
+    s.dev = nullptr;
+    s.cap = 0;
+    HIPCHK(h, hipHostMalloc(&s.host, cap, hipHostMallocDefault));
+    HIPCHK(h, hipMalloc(&s.dev, cap));
+    s.cap = cap;
+    if (!s.ev) HIPCHK(h, hipEventCreateWithFlags(&s.ev, hipEventDisableTiming));
+    return OCT_OK;
+}
+
+void stage_free(Stage &s)
+{
+    if (s.host) (void)hipHostFree(s.host);
+    if (s.dev) (void)hipFree(s.dev);
+    if (s.ev) (void)hipEventDestroy(s.ev);
+    s = Stage{};
+}
+
+bool valid_params(const oct_create_params *p, std::string &why)
+{
+    for (int a = 0; a < 3; a++)
+        if (p->dims[a] < 1 || p->dims[a] > (1 << 20)) { why = "dims out of range"; return false; }
+    if (p->channels < 1 || p->channels > OCT_MAX_CHANNELS) { why = "channels must be 1..4"; return false; }
+    if (p->brick_size < 2 || p->brick_size > 128 || (p->brick_size & 1)) {
+        why = "brick_size must be even, 2..128";
+        return false;
+    }
+    if (p->dtype != OCT_U16 && p->dtype != OCT_F32) { why = "dtype must be OCT_U16 or OCT_F32"; return false; }
+    if (!std::isfinite(p->background) || !std::isfinite(p->homog_threshold) || p->homog_threshold < 0) {
+        why = "background / threshold must be finite, threshold >= 0";
+        return false;
+    }
+    if (p->dtype == OCT_U16 &&
+        (p->background < 0 || p->background > 65535 || p->background != std::floor(p->background))) {
+        why = "u16 background must be an integer in [0, 65535]";
+        return false;
+    }
+    for (int i = 0; i < 4; i++)
+        if (p->reserved[i]) { why = "reserved fields must be 0"; return false; }
+    return true;
+}
+
+void reset_host_state(oct_handle *h)
+{
+    const VolGeom &g = h->g;
+    const int C = g.C;
+    for (auto &c : h->cells) c = HCell();
+    for (int L = 0; L <= g.N; L++) {
+        const int G = g.grid[L];
+        for (int z = 0; z < G; z++)
+            for (int y = 0; y < G; y++)
+                for (int x = 0; x < G; x++) {
+                    HCell &c = h->cells[cell_index(g, L, x, y, z)];
+                    const int b[3] = {x, y, z};
+                    uint64_t cnt = 1, n0 = 1;
+                    for (int a = 0; a < 3; a++) {
+                        const int64_t lo = (int64_t)b[a] * g.M;
+                        const int64_t n = std::max<int64_t>(0, std::min<int64_t>(g.M, g.ext[L][a] - lo));
+                        cnt *= (uint64_t)n;
+                        const int64_t span = (int64_t)g.M << L;
+                        const int64_t lo0 = (int64_t)b[a] * span;
+                        const int64_t n0a = std::max<int64_t>(0, std::min<int64_t>(span, g.dims[a] - lo0));
+                        n0 *= (uint64_t)n0a;
+                    }
+                    c.count = cnt;
+                    c.nvalid0 = n0;
+                    c.inside = cnt > 0;
+                    for (int k = 0; k < C; k++) c.avg[k] = h->p.dtype == OCT_U16 ? h->p.background
+                                                                                 : (double)h->background_f;
+                }
+    }
+    h->cells[cell_index(g, g.N, 0, 0, 0)].exists = 1;
+    h->cells[cell_index(g, g.N, 0, 0, 0)].state = kEmpty;
+    h->free_slots.clear();
+    for (int64_t s = h->n_slots - 1; s >= 0; s--) h->free_slots.push_back((int32_t)s);
+    for (auto &d : h->dirty) d.clear();
+}
+
+// Full node table upload (creation / clear): every cell resolves to the background AVG.
+int upload_full_table(oct_handle *h, hipStream_t s)
+{
+    const size_t bytes = sizeof(DevCell) * (size_t)h->n_cells;
+    int rc = stage_reserve(h, h->up, bytes);
+    if (rc) return rc;
+    DevCell *t = (DevCell *)h->up.host;
+    for (int64_t i = 0; i < h->n_cells; i++) {
+        DevCell &c = t[i];
+        std::memset(&c, 0, sizeof c);
+        c.kind = kAvg;
+        c.slot = -1;
+        for (int k = 0; k < 4; k++) c.avg[k] = c.lo[k] = c.hi[k] = k < h->g.C ? h->background_f : 0.0f;
+        HCell &hc = h->cells[i];
+        hc.dev_kind = kAvg;
+        hc.dev_slot = -1;
+        for (int k = 0; k < 4; k++) hc.dev_avg[k] = c.avg[k];
+        hc.dev_valid = true;
+    }
+    HIPCHK(h, hipMemcpyAsync(h->table, t, bytes, hipMemcpyHostToDevice, s));
+    HIPCHK(h, hipEventRecord(h->up.ev, s));
+    return OCT_OK;
+}
+
+// ------------------------------------------------------------------ tree states
+// Recompute every node's state from the cell statistics (top-down, as the oracle defines):
+// populated / complete from the insertion counts, subtree min/max bottom-up, then the first
+// complete node whose subtree is homogeneous in every channel becomes a leaf; otherwise a
+// complete node with a homogeneous brick keeps its children; otherwise it holds a brick.
+void recompute_states(oct_handle *h)
+{
+    const VolGeom &g = h->g;
+    const int C = g.C;
+    const double thr = h->p.homog_threshold;
+    // bottom-up aggregates
+    for (int L = 0; L <= g.N; L++) {
+        const int G = g.grid[L];
+        for (int z = 0; z < G; z++)
+            for (int y = 0; y < G; y++)
+                for (int x = 0; x < G; x++) {
+                    HCell &c = h->cells[cell_index(g, L, x, y, z)];
+                    if (!c.inside) continue;
+                    if (L == 0) {
+                        for (int k = 0; k < C; k++) {
+                            c.smin[k] = c.bmin[k];
+                            c.smax[k] = c.bmax[k];
+                        }
+                        continue;
+                    }
+                    bool first = true;
+                    for (int k = 0; k < C; k++) c.ins[k] = 0;
+                    for (int d = 0; d < 8; d++) {
+                        const int cx = 2 * x + (d & 1), cy = 2 * y + ((d >> 1) & 1), cz = 2 * z + (d >> 2);
+                        const HCell &ch = h->cells[cell_index(g, L - 1, cx, cy, cz)];
+                        if (!ch.inside) continue;
+                        for (int k = 0; k < C; k++) {
+                            c.ins[k] += ch.ins[k];
+                            c.smin[k] = first ? ch.smin[k] : std::min(c.smin[k], ch.smin[k]);
+                            c.smax[k] = first ? ch.smax[k] : std::max(c.smax[k], ch.smax[k]);
+                        }
+                        first = false;
+                    }
+                }
+    }
+    // top-down states
+    for (int L = g.N; L >= 0; L--) {
+        const int G = g.grid[L];
+        for (int z = 0; z < G; z++)
+            for (int y = 0; y < G; y++)
+                for (int x = 0; x < G; x++) {
+                    HCell &c = h->cells[cell_index(g, L, x, y, z)];
+                    const bool exists =
+                        L == g.N ? true : h->cells[cell_index(g, L + 1, x / 2, y / 2, z / 2)].has_children;
+                    c.exists = exists;
+                    c.has_children = 0;
+                    c.state = kNone;
+                    bool any = false, all = c.inside;
+                    for (int k = 0; k < C; k++) {
+                        if (c.ins[k] > 0) any = true;
+                        if (c.ins[k] != c.nvalid0) all = false;
+                    }
+                    c.populated = c.inside && any;
+                    c.complete = c.inside && all;
+                    if (!exists) continue;
+                    if (!c.populated) {
+                        c.state = kEmpty;
+                        for (int k = 0; k < C; k++)
+                            c.avg[k] = h->p.dtype == OCT_U16 ? h->p.background : (double)h->background_f;
+                        continue;
+                    }
+                    for (int k = 0; k < C; k++) {
+                        if (h->p.dtype == OCT_U16) {
+                            const uint64_t s = (uint64_t)c.bsum[k];
+                            c.avg[k] = (double)((2 * s + c.count) / (2 * c.count));
+                        } else {
+                            c.avg[k] = (double)(float)(c.bsum[k] / (double)c.count);
+                        }
+                    }
+                    bool sub_h = c.complete, own_h = c.complete;
+                    for (int k = 0; k < C; k++) {
+                        if (!(c.smax[k] - c.smin[k] < thr)) sub_h = false;
+                        if (!(c.bmax[k] - c.bmin[k] < thr)) own_h = false;
+                    }
+                    if (sub_h) {
+                        c.state = kHomogLeaf;
+                    } else {
+                        c.has_children = L > 0;
+                        c.state = own_h ? kHomog : kBrickState;
+                    }
+                }
+    }
+}
+
+bool box_intersects(const Box &b, const int lo[3], const int hi[3])
+{
+    for (int a = 0; a < 3; a++)
+        if (b.hi[a] < lo[a] || b.lo[a] > hi[a]) return false;
+    return true;
+}
+
+}  // namespace
+
+// =================================================================== C ABI
+
+extern "C" {
+
+int octree_create(const oct_create_params *params, void *stream, oct_handle **out)
+{
+    if (!params || !out) return fail(nullptr, OCT_EINVAL, "null argument");
+    std::string why;
+    if (!valid_params(params, why)) return fail(nullptr, OCT_EINVAL, why);
+    oct_handle *h = new (std::nothrow) oct_handle();
+    if (!h) return fail(nullptr, OCT_ENOMEM, "host allocation failed");
+    h->p = *params;
+    hipStream_t s = (hipStream_t)stream;
+    auto bail = [&](int code) {
+        g_create_err = h->err;
+        octree_destroy(h);
+        return code;
+    };
+    if (hipGetDevice(&h->device) != hipSuccess) {
+        h->err = "no HIP device";
+        return bail(OCT_EDEVICE);
+    }
+    VolGeom &g = h->g;
+    g.C = params->channels;
+    g.M = params->brick_size;
+    g.dtype = params->dtype;
+    for (int a = 0; a < 3; a++) g.dims[a] = params->dims[a];
+    const int dmax = std::max(g.dims[0], std::max(g.dims[1], g.dims[2]));
+    int N = 0;
+    while (((int64_t)g.M << N) < dmax) N++;
+    if (N + 2 > kMaxLevels) {
+        h->err = "too many levels";
+        return bail(OCT_EINVAL);
+    }
+    g.N = N;
+    h->esz = params->dtype == OCT_U16 ? 2 : 4;
+    h->background_f = (float)params->background;
+    int64_t off = 0, coff = 0;
+    int64_t in_volume_cells = 0;
+    for (int L = 0; L <= N; L++) {
+        int64_t nv = g.C;
+        for (int a = 0; a < 3; a++) {
+            g.ext[L][a] = (int32_t)(((int64_t)g.dims[a] + ((int64_t)1 << L) - 1) >> L);
+            nv *= g.ext[L][a];
+        }
+        g.lvl_off[L] = off;
+        off += nv;
+        g.grid[L] = 1 << (N - L);
+        g.cell_off[L] = (int32_t)coff;
+        coff += (int64_t)g.grid[L] * g.grid[L] * g.grid[L];
+        int64_t nb = 1;
+        for (int a = 0; a < 3; a++) nb *= (g.ext[L][a] + g.M - 1) / g.M;
+        in_volume_cells += nb;
+    }
+    g.lvl_off[N + 1] = off;
+    h->n_cells = coff;
+    const int S = g.M + 2;
+    h->brick_bytes = ((uint64_t)S * S * S * 4 * h->esz + 255) & ~(uint64_t)255;
+    h->n_slots = in_volume_cells;
+    if (params->device_pool_bytes)
+        h->n_slots = std::min<int64_t>(h->n_slots, (int64_t)(params->device_pool_bytes / h->brick_bytes));
+    h->cells.assign((size_t)h->n_cells, HCell());
+    h->dirty.assign((size_t)N + 1, std::vector<Box>());
+
+    auto dev_alloc = [&](void **ptr, size_t bytes) -> int {
+        hipError_t e = hipMalloc(ptr, std::max<size_t>(bytes, 256));
+        if (e != hipSuccess) {
+            h->err = std::string("hipMalloc: ") + hipGetErrorString(e);
+            return e == hipErrorOutOfMemory ? OCT_ENOMEM : OCT_EDEVICE;
+        }
+        return OCT_OK;
+    };
+    int rc;
+    if ((rc = dev_alloc(&h->master, (size_t)off * h->esz))) return bail(rc);
+    if ((rc = dev_alloc((void **)&h->mask, (size_t)g.dims[0] * g.dims[1] * g.dims[2]))) return bail(rc);
+    if ((rc = dev_alloc((void **)&h->table, sizeof(DevCell) * (size_t)h->n_cells))) return bail(rc);
+    if ((rc = dev_alloc((void **)&h->pool, (size_t)h->brick_bytes * (size_t)h->n_slots))) return bail(rc);
+    if ((rc = dev_alloc((void **)&h->slot_range, sizeof(float) * 8 * (size_t)std::max<int64_t>(h->n_slots, 1))))
+        return bail(rc);
+    if (hipEventCreateWithFlags(&h->ins_ev, hipEventDisableTiming) != hipSuccess) return bail(OCT_EDEVICE);
+    if (octree_clear(h, stream) != OCT_OK) return bail(OCT_EDEVICE);
+    (void)s;
+    *out = h;
+    return OCT_OK;
+}
+
+int octree_destroy(oct_handle *h)
+{
+    if (!h) return OCT_EINVAL;
+    (void)hipSetDevice(h->device);
+    (void)hipDeviceSynchronize();
+    if (h->master) (void)hipFree(h->master);
+    if (h->mask) (void)hipFree(h->mask);
+    if (h->table) (void)hipFree(h->table);
+    if (h->pool) (void)hipFree(h->pool);
+    if (h->slot_range) (void)hipFree(h->slot_range);
+    if (h->ins_stage) (void)hipFree(h->ins_stage);
+    if (h->ins_ev) (void)hipEventDestroy(h->ins_ev);
+    stage_free(h->up);
+    for (auto &r : h->rs) stage_free(r.st);
+    delete h;
+    return OCT_OK;
+}
+
+int octree_clear(oct_handle *h, void *stream)
+{
+    if (!h) return OCT_EINVAL;
+    HIPCHK(h, hipSetDevice(h->device));
+    hipStream_t s = (hipStream_t)stream;
+    HIPCHK(h, launch_clear(h->g, h->master, h->mask, h->p.background, s));
+    reset_host_state(h);
+    return upload_full_table(h, s);
+}
+
+int octree_insert_block(oct_handle *h, int32_t channel, const int32_t origin[3],
+                        const int32_t size[3], const void *data, int32_t data_is_device,
+                        void *stream)
+{
+    if (!h || !origin || !size || !data) return fail(h, OCT_EINVAL, "null argument");
+    const VolGeom &g = h->g;
+    if (channel < -1 || channel >= g.C) return fail(h, OCT_EINVAL, "channel out of range");
+    for (int a = 0; a < 3; a++) {
+        if (size[a] < 1) return fail(h, OCT_EINVAL, "block size must be >= 1");
+        if (origin[a] < 0 || (int64_t)origin[a] + size[a] > g.dims[a])
+            return fail(h, OCT_ERANGE, "block outside the volume");
+    }
+    HIPCHK(h, hipSetDevice(h->device));
+    hipStream_t s = (hipStream_t)stream;
+    const int cb = channel < 0 ? g.C : 1;
+    const size_t bytes = (size_t)cb * size[0] * size[1] * size[2] * h->esz;
+    const void *src = data;
+    if (!data_is_device) {
+        HIPCHK(h, hipEventSynchronize(h->ins_ev));
+        if (bytes > h->ins_stage_cap) {
+            if (h->ins_stage) HIPCHK(h, hipFree(h->ins_stage));
+            h->ins_stage = nullptr;
+            h->ins_stage_cap = 0;
+            HIPCHK(h, hipMalloc(&h->ins_stage, bytes));
+            h->ins_stage_cap = bytes;
+        }
+        HIPCHK(h, hipMemcpyAsync(h->ins_stage, data, bytes, hipMemcpyHostToDevice, s));
+        HIPCHK(h, hipStreamSynchronize(s));  // host data consumed before return
+        src = h->ins_stage;
+    }
+    HIPCHK(h, launch_insert(g, h->master, h->mask, src, channel, origin, size, s));
+    Box b;
+    for (int a = 0; a < 3; a++) {
+        b.lo[a] = origin[a];
+        b.hi[a] = origin[a] + size[a] - 1;
+    }
+    h->dirty[0].push_back(b);
+    for (int L = 0; L < g.N; L++) {
+        Box p;
+        for (int a = 0; a < 3; a++) {
+            p.lo[a] = b.lo[a] >> 1;
+            p.hi[a] = b.hi[a] >> 1;
+        }
+        HIPCHK(h, launch_downsample(g, h->master, L, p.lo, p.hi, s));
+        h->dirty[L + 1].push_back(p);
+        b = p;
+    }
+    if (!data_is_device) HIPCHK(h, hipEventRecord(h->ins_ev, s));
+    return OCT_OK;
+}
+
+int octree_insert_slices(oct_handle *h, int32_t channel, int32_t z0, int32_t nz, const void *data,
+                         int32_t data_is_device, void *stream)
+{
+    if (!h) return OCT_EINVAL;
+    const int32_t o[3] = {0, 0, z0};
+    const int32_t n[3] = {h->g.dims[0], h->g.dims[1], nz};
+    return octree_insert_block(h, channel, o, n, data, data_is_device, stream);
+}
+
+int brick_pool_upload(oct_handle *h, uint64_t byte_budget, void *stream, oct_upload_stats *out)
+{
+    if (!h) return OCT_EINVAL;
+    HIPCHK(h, hipSetDevice(h->device));
+    hipStream_t s = (hipStream_t)stream;
+    const VolGeom &g = h->g;
+    const int C = g.C, M = g.M;
+
+    // ---- 1. cells whose level data changed, and cells whose bordered region touches a change
+    std::vector<int32_t> stat_cells;  // (L, x, y, z) quadruples
+    std::vector<uint8_t> border_dirty((size_t)h->n_cells, 0);
+    std::vector<uint8_t> data_dirty((size_t)h->n_cells, 0);
+    for (int L = 0; L <= g.N; L++) {
+        const int G = g.grid[L];
+        for (const Box &b : h->dirty[L]) {
+            int lo[3], hi[3];
+            for (int a = 0; a < 3; a++) {
+                lo[a] = std::max(0, (b.lo[a] - 1) / M);
+                hi[a] = std::min(G - 1, (b.hi[a] + 1) / M);
+            }
+            for (int z = lo[2]; z <= hi[2]; z++)
+                for (int y = lo[1]; y <= hi[1]; y++)
+                    for (int x = lo[0]; x <= hi[0]; x++) {
+                        const int64_t ci = cell_index(g, L, x, y, z);
+                        if (!h->cells[ci].inside) continue;
+                        // bordered box of the cell in level-L voxels
+                        const int blo[3] = {x * M - 1, y * M - 1, z * M - 1};
+                        const int bhi[3] = {x * M + M, y * M + M, z * M + M};
+                        if (box_intersects(b, blo, bhi)) border_dirty[ci] = 1;
+                        const int clo[3] = {x * M, y * M, z * M};
+                        const int chi[3] = {x * M + M - 1, y * M + M - 1, z * M + M - 1};
+                        if (box_intersects(b, clo, chi) && !data_dirty[ci]) {
+                            data_dirty[ci] = 1;
+                            stat_cells.insert(stat_cells.end(), {L, x, y, z});
+                        }
+                    }
+        }
+        h->dirty[L].clear();
+    }
+    const int n_stat = (int)(stat_cells.size() / 4);
+
+    // ---- 2. statistics of changed cells (one read-back)
+    if (n_stat) {
+        const size_t cl_bytes = stat_cells.size() * sizeof(int32_t);
+        const size_t st_off = (cl_bytes + 255) & ~(size_t)255;
+        const size_t st_bytes = (size_t)n_stat * sizeof(CellStat);
+        int rc = stage_reserve(h, h->up, st_off + st_bytes);
+        if (rc) return rc;
+        std::memcpy(h->up.host, stat_cells.data(), cl_bytes);
+        HIPCHK(h, hipMemcpyAsync(h->up.dev, h->up.host, cl_bytes, hipMemcpyHostToDevice, s));
+        HIPCHK(h, launch_stats(g, h->master, h->mask, (const int32_t *)h->up.dev, n_stat,
+                               (CellStat *)((uint8_t *)h->up.dev + st_off), s));
+        HIPCHK(h, hipMemcpyAsync((uint8_t *)h->up.host + st_off, (uint8_t *)h->up.dev + st_off, st_bytes,
+                                 hipMemcpyDeviceToHost, s));
+        HIPCHK(h, hipStreamSynchronize(s));
+        const CellStat *st = (const CellStat *)((uint8_t *)h->up.host + st_off);
+        for (int i = 0; i < n_stat; i++) {
+            const int L = stat_cells[4 * i];
+            HCell &c = h->cells[cell_index(g, L, stat_cells[4 * i + 1], stat_cells[4 * i + 2],
+                                           stat_cells[4 * i + 3])];
+            for (int k = 0; k < C; k++) {
+                c.bmin[k] = st[i].mn[k];
+                c.bmax[k] = st[i].mx[k];
+                c.bsum[k] = st[i].sum[k];
+                if (L == 0) c.ins[k] = st[i].ins[k];
+            }
+            c.have_stats = true;
+        }
+    }
+
+    // ---- 3. states, resolved entries and slots
+    recompute_states(h);
+    std::vector<int32_t> new_kind((size_t)h->n_cells);
+    std::vector<float> new_avg((size_t)h->n_cells * 4);
+    for (int L = g.N; L >= 0; L--) {
+        const int G = g.grid[L];
+        for (int z = 0; z < G; z++)
+            for (int y = 0; y < G; y++)
+                for (int x = 0; x < G; x++) {
+                    const int64_t ci = cell_index(g, L, x, y, z);
+                    HCell &c = h->cells[ci];
+                    float *a = &new_avg[(size_t)ci * 4];
+                    if (c.exists) {
+                        for (int k = 0; k < 4; k++) a[k] = k < C ? (float)c.avg[k] : 0.0f;
+                    } else {
+                        const int64_t pi = cell_index(g, L + 1, x / 2, y / 2, z / 2);
+                        for (int k = 0; k < 4; k++) a[k] = new_avg[(size_t)pi * 4 + k];
+                    }
+                    const bool brick = c.exists && c.state == kBrickState;
+                    if (!brick && c.slot >= 0) {
+                        h->free_slots.push_back(c.slot);
+                        c.slot = -1;
+                        c.needs_gather = false;
+                    }
+                    if (brick && c.slot < 0 && !h->free_slots.empty()) {
+                        c.slot = h->free_slots.back();
+                        h->free_slots.pop_back();
+                        c.needs_gather = true;
+                    }
+                    new_kind[ci] = brick ? kBrickMissing : kAvg;
+                }
+    }
+    // neighbourhood changes: a brick's border holds R_L of its 26 neighbours
+    auto rep_changed = [&](int64_t ci) {
+        const HCell &c = h->cells[ci];
+        const bool was_data = c.dev_kind != kAvg, is_data = new_kind[ci] != kAvg;
+        if (was_data != is_data) return true;
+        if (!is_data)
+            for (int k = 0; k < C; k++)
+                if (c.dev_avg[k] != new_avg[(size_t)ci * 4 + k]) return true;
+        return false;
+    };
+    std::vector<uint8_t> changed((size_t)h->n_cells, 0);
+    for (int64_t i = 0; i < h->n_cells; i++) changed[i] = rep_changed(i);
+    std::vector<BrickJob> jobs;
+    uint64_t budget_left = byte_budget ? byte_budget : UINT64_MAX;
+    uint64_t pending = 0, bricks_total = 0, resident = 0;
+    for (int L = g.N; L >= 0; L--) {  // coarse levels first
+        const int G = g.grid[L];
+        for (int z = 0; z < G; z++)
+            for (int y = 0; y < G; y++)
+                for (int x = 0; x < G; x++) {
+                    const int64_t ci = cell_index(g, L, x, y, z);
+                    HCell &c = h->cells[ci];
+                    if (new_kind[ci] == kAvg) continue;
+                    bricks_total++;
+                    if (c.slot < 0) {
+                        pending++;
+                        continue;
+                    }
+                    bool need = c.needs_gather || border_dirty[ci];
+                    for (int dz = -1; dz <= 1 && !need; dz++)
+                        for (int dy = -1; dy <= 1 && !need; dy++)
+                            for (int dx = -1; dx <= 1 && !need; dx++) {
+                                const int nx = x + dx, ny = y + dy, nz = z + dz;
+                                if (nx < 0 || ny < 0 || nz < 0 || nx >= G || ny >= G || nz >= G) continue;
+                                if (changed[cell_index(g, L, nx, ny, nz)]) need = true;
+                            }
+                    if (need) {
+                        if (budget_left >= h->brick_bytes) {
+                            budget_left -= h->brick_bytes;
+                            BrickJob j{};
+                            j.slot = c.slot;
+                            j.level = L;
+                            j.bx = x;
+                            j.by = y;
+                            j.bz = z;
+                            jobs.push_back(j);
+                            c.needs_gather = false;
+                        } else {
+                            c.needs_gather = true;
+                        }
+                    }
+                    if (c.needs_gather) pending++;
+                    else {
+                        new_kind[ci] = kBrick;
+                        resident++;
+                    }
+                }
+    }
+
+    // ---- 4. change events for the node table, then the gathers, then the skip bounds
+    std::vector<CellDelta> deltas;
+    for (int64_t i = 0; i < h->n_cells; i++) {
+        HCell &c = h->cells[i];
+        const int32_t slot = new_kind[i] == kBrick ? c.slot : -1;
+        const float *a = &new_avg[(size_t)i * 4];
+        bool diff = !c.dev_valid || c.dev_kind != new_kind[i] || c.dev_slot != slot;
+        for (int k = 0; k < 4 && !diff; k++) diff = c.dev_avg[k] != a[k];
+        if (!diff) continue;
+        CellDelta d{};
+        d.index = (int32_t)i;
+        d.kind = new_kind[i];
+        d.slot = slot;
+        for (int k = 0; k < 4; k++) d.avg[k] = a[k];
+        deltas.push_back(d);
+        c.dev_kind = new_kind[i];
+        c.dev_slot = slot;
+        for (int k = 0; k < 4; k++) c.dev_avg[k] = a[k];
+        c.dev_valid = true;
+    }
+    const size_t d_bytes = deltas.size() * sizeof(CellDelta);
+    const size_t j_off = (d_bytes + 255) & ~(size_t)255;
+    const size_t j_bytes = jobs.size() * sizeof(BrickJob);
+    if (d_bytes + j_bytes) {
+        int rc = stage_reserve(h, h->up, j_off + j_bytes);
+        if (rc) return rc;
+        if (d_bytes) std::memcpy(h->up.host, deltas.data(), d_bytes);
+        if (j_bytes) std::memcpy((uint8_t *)h->up.host + j_off, jobs.data(), j_bytes);
+        HIPCHK(h, hipMemcpyAsync(h->up.dev, h->up.host, j_off + j_bytes, hipMemcpyHostToDevice, s));
+        HIPCHK(h, hipEventRecord(h->up.ev, s));
+        HIPCHK(h, launch_apply_deltas(h->table, (const CellDelta *)h->up.dev, (int)deltas.size(), s));
+        HIPCHK(h, launch_gather(g, h->master, h->table, h->pool, h->brick_bytes,
+                                (const BrickJob *)((uint8_t *)h->up.dev + j_off), (int)jobs.size(),
+                                h->slot_range, h->background_f, s));
+        HIPCHK(h, launch_ranges(g, h->table, h->slot_range, s));
+    }
+    if (out) {
+        out->bricks_gathered = jobs.size();
+        out->bricks_resident = resident;
+        out->bricks_total = bricks_total;
+        out->nodes_changed = deltas.size();
+        out->bytes_written = jobs.size() * h->brick_bytes + d_bytes;
+    }
+    return pending ? OCT_INCOMPLETE : OCT_OK;
+}
+
+size_t render_ckpt_bytes(const oct_handle *h, int32_t n_views, const oct_view *views)
+{
+    (void)h;
+    (void)n_views;
+    (void)views;
+    return 0;
+}
+
+static int build_view(oct_handle *h, const oct_view &v, float *image, DevView &dv)
+{
+    const VolGeom &g = h->g;
+    if (v.width < 1 || v.height < 1 || v.width > 32768 || v.height > 32768)
+        return fail(h, OCT_EINVAL, "view size out of range");
+    if (!(v.step > 0.0f) || !std::isfinite(v.step)) return fail(h, OCT_EINVAL, "step must be > 0");
+    if (!(v.fov_y_deg > 0.0f && v.fov_y_deg < 180.0f)) return fail(h, OCT_EINVAL, "fov out of range");
+    if (v.n_clip < 0 || v.n_clip > OCT_MAX_CLIPS) return fail(h, OCT_EINVAL, "n_clip must be 0..3");
+    if (v.lod < -1) return fail(h, OCT_EINVAL, "lod must be >= -1");
+    if (v.tile_begin < 0 || v.tile_count < -1) return fail(h, OCT_EINVAL, "bad tile range");
+    if (!(v.ert_alpha > 0.0f)) return fail(h, OCT_EINVAL, "ert_alpha must be > 0");
+    for (int i = 0; i < 3; i++)
+        if (v.reserved[i]) return fail(h, OCT_EINVAL, "reserved fields must be 0");
+    if (!image) return fail(h, OCT_EINVAL, "null image");
+    for (int c = 0; c < g.C; c++) {
+        if (!(v.window[c][1] > v.window[c][0])) return fail(h, OCT_EINVAL, "window hi must exceed lo");
+        for (int j = 0; j < 8; j++) {
+            if (!(v.tf_pos[c][j] >= 0.0f && v.tf_pos[c][j] <= 1.0f))
+                return fail(h, OCT_EINVAL, "tf positions must lie in [0,1]");
+            if (j && v.tf_pos[c][j] < v.tf_pos[c][j - 1])
+                return fail(h, OCT_EINVAL, "tf positions must ascend");
+        }
+    }
+    // camera frame in double, rounded to float (the per-pixel part runs in the kernel)
+    double e[3], f[3], up[3], r[3], u[3];
+    for (int a = 0; a < 3; a++) {
+        e[a] = (double)v.eye[a];
+        f[a] = (double)v.target[a] - e[a];
+        up[a] = (double)v.up[a];
+    }
+    double n = std::sqrt((f[0] * f[0] + f[1] * f[1]) + f[2] * f[2]);
+    if (!(n > 0.0)) return fail(h, OCT_EINVAL, "eye equals target");
+    for (int a = 0; a < 3; a++) f[a] = f[a] / n;
+    r[0] = f[1] * up[2] - f[2] * up[1];
+    r[1] = f[2] * up[0] - f[0] * up[2];
+    r[2] = f[0] * up[1] - f[1] * up[0];
+    n = std::sqrt((r[0] * r[0] + r[1] * r[1]) + r[2] * r[2]);
+    if (!(n > 0.0)) return fail(h, OCT_EINVAL, "up is parallel to the view direction");
+    for (int a = 0; a < 3; a++) r[a] = r[a] / n;
+    u[0] = r[1] * f[2] - r[2] * f[1];
+    u[1] = r[2] * f[0] - r[0] * f[2];
+    u[2] = r[0] * f[1] - r[1] * f[0];
+    const double th = std::tan((double)v.fov_y_deg * (M_PI / 360.0));
+    std::memset(&dv, 0, sizeof dv);
+    for (int a = 0; a < 3; a++) {
+        dv.eye[a] = v.eye[a];
+        dv.f[a] = (float)f[a];
+        dv.r[a] = (float)r[a];
+        dv.u[a] = (float)u[a];
+    }
+    dv.kx = (float)(th * (double)v.width / (double)v.height);
+    dv.ky = (float)th;
+    dv.klod = (float)(2.0 * th / (double)v.height);
+    dv.step = v.step;
+    dv.ert = v.ert_alpha;
+    dv.width = v.width;
+    dv.height = v.height;
+    dv.tiles_x = (v.width + OCT_TILE - 1) / OCT_TILE;
+    dv.lod = v.lod;
+    dv.n_clip = v.n_clip;
+    dv.skip = v.no_skip ? 0 : 1;
+    std::memcpy(dv.clip, v.clip, sizeof dv.clip);
+    for (int c = 0; c < kMaxC; c++) {
+        const bool on = c < g.C;
+        dv.ulo[c] = on ? v.window[c][0] : 0.0f;
+        dv.uscale[c] = on ? (float)(255.0 / ((double)v.window[c][1] - (double)v.window[c][0])) : 0.0f;
+    }
+    std::memcpy(dv.tf_pos, v.tf_pos, sizeof dv.tf_pos);
+    std::memcpy(dv.tf_rgba, v.tf_rgba, sizeof dv.tf_rgba);
+    dv.image = image;
+    return OCT_OK;
+}
+
+int render_views(oct_handle *h, int32_t n_views, const oct_view *views, float *const *images,
+                 void *ckpt_ws, void *stream, oct_render_stats *out)
+{
+    if (!h) return OCT_EINVAL;
+    if (n_views < 0 || (n_views > 0 && (!views || !images))) return fail(h, OCT_EINVAL, "bad view list");
+    (void)ckpt_ws;
+    HIPCHK(h, hipSetDevice(h->device));
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<DevView> dvs((size_t)n_views);
+    std::vector<WgItem> items;
+    for (int i = 0; i < n_views; i++) {
+        int rc = build_view(h, views[i], images[i], dvs[i]);
+        if (rc) return rc;
+        const int tiles = dvs[i].tiles_x * ((views[i].height + OCT_TILE - 1) / OCT_TILE);
+        const int tb = std::min(views[i].tile_begin, tiles);
+        const int te = views[i].tile_count < 0 ? tiles : std::min(tiles, tb + views[i].tile_count);
+        for (int t = tb; t < te; t += 4) {
+            WgItem w{};
+            w.view = i;
+            w.tile0 = t;
+            w.ntiles = std::min(4, te - t);
+            items.push_back(w);
+        }
+    }
+    const size_t v_bytes = dvs.size() * sizeof(DevView);
+    const size_t i_off = (v_bytes + 255) & ~(size_t)255;
+    const size_t i_bytes = items.size() * sizeof(WgItem);
+    const size_t c_off = (i_off + i_bytes + 255) & ~(size_t)255;
+    RenderSlot &rs = h->rs[h->next_rs];
+    h->next_rs = (h->next_rs + 1) % kRenderSlots;
+    int rc = stage_reserve(h, rs.st, c_off + sizeof(RenderCounters));
+    if (rc) return rc;
+    uint8_t *hp = (uint8_t *)rs.st.host;
+    std::memcpy(hp, dvs.data(), v_bytes);
+    std::memcpy(hp + i_off, items.data(), i_bytes);
+    std::memset(hp + c_off, 0, sizeof(RenderCounters));
+    HIPCHK(h, hipMemcpyAsync(rs.st.dev, hp, c_off + sizeof(RenderCounters), hipMemcpyHostToDevice, s));
+    uint8_t *dp = (uint8_t *)rs.st.dev;
+    HIPCHK(h, launch_render(h->g, h->table, h->pool, h->brick_bytes, (const DevView *)dp,
+                            (const WgItem *)(dp + i_off), (int)items.size(),
+                            out ? (RenderCounters *)(dp + c_off) : nullptr, s));
+    if (out) {
+        HIPCHK(h, hipMemcpyAsync(hp + c_off, dp + c_off, sizeof(RenderCounters), hipMemcpyDeviceToHost, s));
+        HIPCHK(h, hipStreamSynchronize(s));
+        const RenderCounters *rcnt = (const RenderCounters *)(hp + c_off);
+        out->rays = rcnt->rays;
+        out->positions_nominal = rcnt->nominal;
+        out->positions_composited = rcnt->composited;
+    }
+    HIPCHK(h, hipEventRecord(rs.st.ev, s));
+    return OCT_OK;
+}
+
+int render_views_backward(oct_handle *h, int32_t n_views, const oct_view *views,
+                          const float *const *dL_dimages, const void *ckpt_ws, float *dL_dctrl,
+                          float *dL_dvoxels, void *stream)
+{
+    (void)n_views;
+    (void)views;
+    (void)dL_dimages;
+    (void)ckpt_ws;
+    (void)dL_dctrl;
+    (void)dL_dvoxels;
+    (void)stream;
+    return fail(h, OCT_EINVAL, "render_views_backward: not available in this build");
+}
+
+int octree_dump_canonical(oct_handle *h, void *buf, size_t cap, size_t *needed)
+{
+    if (!h || !needed) return OCT_EINVAL;
+    HIPCHK(h, hipSetDevice(h->device));
+    const VolGeom &g = h->g;
+    const int C = g.C, M = g.M, S = M + 2;
+    // pending inserts must be applied first so the dump reflects every inserted voxel
+    for (int L = 0; L <= g.N; L++)
+        if (!h->dirty[L].empty()) {
+            int rc = brick_pool_upload(h, 0, nullptr, nullptr);
+            if (rc < 0) return rc;
+            break;
+        }
+    HIPCHK(h, hipDeviceSynchronize());
+    int64_t n_nodes = 0, n_bricks = 0;
+    for (int64_t i = 0; i < h->n_cells; i++)
+        if (h->cells[i].exists) {
+            n_nodes++;
+            if (h->cells[i].state == kBrickState) n_bricks++;
+        }
+    const size_t bb = (size_t)S * S * S * C * h->esz;
+    const size_t need = 64 + (size_t)n_nodes * 192 + (size_t)n_bricks * bb;
+    *needed = need;
+    if (!buf || cap < need) return fail(h, OCT_ERANGE, "dump buffer too small");
+    uint8_t *o = (uint8_t *)buf;
+    std::memset(o, 0, 64 + (size_t)n_nodes * 192);
+    std::memcpy(o, "OCTDUMP1", 8);
+    const int32_t hdr[9] = {g.dims[0], g.dims[1], g.dims[2], C, M, g.N, g.dtype, (int32_t)n_nodes,
+                            (int32_t)n_bricks};
+    std::memcpy(o + 8, hdr, sizeof hdr);
+    uint8_t *rec = o + 64;
+    uint8_t *bk = o + 64 + (size_t)n_nodes * 192;
+    std::vector<uint8_t> slotbuf(h->brick_bytes);
+    for (int L = g.N; L >= 0; L--) {
+        const int G = g.grid[L];
+        for (int z = 0; z < G; z++)
+            for (int y = 0; y < G; y++)
+                for (int x = 0; x < G; x++) {
+                    const HCell &c = h->cells[cell_index(g, L, x, y, z)];
+                    if (!c.exists) continue;
+                    const int32_t head[8] = {L, x, y, z, c.state,
+                                             (c.has_children ? 1 : 0) | (c.complete ? 2 : 0) |
+                                                 (c.populated ? 4 : 0),
+                                             0, 0};
+                    std::memcpy(rec, head, sizeof head);
+                    double *d = (double *)(rec + 32);
+                    for (int k = 0; k < C; k++) {
+                        d[k] = c.avg[k];
+                        if (c.populated) {
+                            d[4 + k] = c.bmin[k];
+                            d[8 + k] = c.bmax[k];
+                            d[12 + k] = c.smin[k];
+                            d[16 + k] = c.smax[k];
+                        }
+                    }
+                    rec += 192;
+                    if (c.state != kBrickState) continue;
+                    if (c.slot < 0 || c.needs_gather)
+                        return fail(h, OCT_EBUSY, "a brick node has no current bordered brick");
+                    HIPCHK(h, hipMemcpy(slotbuf.data(), h->pool + (uint64_t)c.slot * h->brick_bytes,
+                                        h->brick_bytes, hipMemcpyDeviceToHost));
+                    for (int v = 0; v < S * S * S; v++)
+                        for (int k = 0; k < C; k++) {
+                            std::memcpy(bk, slotbuf.data() + ((size_t)v * 4 + k) * h->esz, h->esz);
+                            bk += h->esz;
+                        }
+                }
+    }
+    return OCT_OK;
+}
+
+int octree_read_level(oct_handle *h, int32_t level, void *out, size_t cap, int32_t ext[3])
+{
+    if (!h || !out) return OCT_EINVAL;
+    const VolGeom &g = h->g;
+    if (level < 0 || level > g.N) return fail(h, OCT_EINVAL, "level out of range");
+    HIPCHK(h, hipSetDevice(h->device));
+    const size_t bytes = (size_t)(g.lvl_off[level + 1] - g.lvl_off[level]) * h->esz;
+    if (ext)
+        for (int a = 0; a < 3; a++) ext[a] = g.ext[level][a];
+    if (cap < bytes) return fail(h, OCT_ERANGE, "buffer too small");
+    HIPCHK(h, hipDeviceSynchronize());
+    HIPCHK(h, hipMemcpy(out, (uint8_t *)h->master + (size_t)g.lvl_off[level] * h->esz, bytes,
+                        hipMemcpyDeviceToHost));
+    return OCT_OK;
+}
+
+int octree_info(const oct_handle *h, int32_t *levels, uint64_t *brick_bytes, uint64_t *pool_slots)
+{
+    if (!h) return OCT_EINVAL;
+    if (levels) *levels = h->g.N + 1;
+    if (brick_bytes) *brick_bytes = h->brick_bytes;
+    if (pool_slots) *pool_slots = (uint64_t)h->n_slots;
+    return OCT_OK;
+}
+
+const char *oct_last_error(const oct_handle *h)
+{
+    if (!h) return g_create_err.c_str();
+    return h->err.c_str();
+}
+
+}  // extern "C"

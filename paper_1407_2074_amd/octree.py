@@ -1,0 +1,227 @@
+"""Thin ctypes binding of liboctree_rc.so (declared in include/octree_rc.h).
+
+Only argument marshalling happens here: every step of construction and rendering runs in the
+HIP kernels behind the C ABI.  PyTorch provides device memory and the current HIP stream.
+If the library is missing this module raises at import time -- there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liboctree_rc.so")
+
+OCT_OK, OCT_INCOMPLETE = 0, 1
+OCT_EINVAL, OCT_ENOMEM, OCT_ERANGE, OCT_EDEVICE, OCT_EBUSY = -1, -2, -3, -4, -5
+OCT_U16, OCT_F32 = 0, 1
+MAXC = 4
+
+EXPORTS = ["octree_create", "octree_destroy", "octree_clear", "octree_insert_block",
+           "octree_insert_slices", "brick_pool_upload", "render_views", "render_ckpt_bytes",
+           "render_views_backward", "octree_dump_canonical", "octree_read_level", "octree_info",
+           "oct_last_error"]
+
+
+class CreateParams(ct.Structure):
+    _fields_ = [("dims", ct.c_int32 * 3), ("channels", ct.c_int32), ("brick_size", ct.c_int32),
+                ("dtype", ct.c_int32), ("background", ct.c_double),
+                ("homog_threshold", ct.c_double), ("device_pool_bytes", ct.c_uint64),
+                ("reserved", ct.c_int32 * 4)]
+
+
+class OctView(ct.Structure):
+    _fields_ = [("eye", ct.c_float * 3), ("target", ct.c_float * 3), ("up", ct.c_float * 3),
+                ("fov_y_deg", ct.c_float), ("width", ct.c_int32), ("height", ct.c_int32),
+                ("tile_begin", ct.c_int32), ("tile_count", ct.c_int32), ("step", ct.c_float),
+                ("ert_alpha", ct.c_float), ("lod", ct.c_int32), ("n_clip", ct.c_int32),
+                ("clip", (ct.c_float * 4) * 3), ("tf_pos", (ct.c_float * 8) * MAXC),
+                ("tf_rgba", ((ct.c_float * 4) * 8) * MAXC), ("window", (ct.c_float * 2) * MAXC),
+                ("no_skip", ct.c_int32), ("reserved", ct.c_int32 * 3)]
+
+
+class UploadStats(ct.Structure):
+    _fields_ = [("bricks_gathered", ct.c_uint64), ("bricks_resident", ct.c_uint64),
+                ("bricks_total", ct.c_uint64), ("nodes_changed", ct.c_uint64),
+                ("bytes_written", ct.c_uint64)]
+
+
+class RenderStats(ct.Structure):
+    _fields_ = [("rays", ct.c_uint64), ("positions_nominal", ct.c_uint64),
+                ("positions_composited", ct.c_uint64)]
+
+
+def _load():
+    # torch ships its own HIP runtime; loading it first makes the library's libamdhip64.so.7
+    # dependency resolve to that same runtime instead of a second copy from /opt/rocm.
+    import torch  # noqa: F401
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
+                          "(hipcc, gfx950) -- there is no fallback implementation")
+    L = ct.CDLL(LIB_PATH)
+    vp, i32, u64, sz = ct.c_void_p, ct.c_int32, ct.c_uint64, ct.c_size_t
+    L.octree_create.argtypes = [ct.POINTER(CreateParams), vp, ct.POINTER(vp)]
+    L.octree_destroy.argtypes = [vp]
+    L.octree_clear.argtypes = [vp, vp]
+    L.octree_insert_block.argtypes = [vp, i32, ct.POINTER(i32), ct.POINTER(i32), vp, i32, vp]
+    L.octree_insert_slices.argtypes = [vp, i32, i32, i32, vp, i32, vp]
+    L.brick_pool_upload.argtypes = [vp, u64, vp, ct.POINTER(UploadStats)]
+    L.render_views.argtypes = [vp, i32, ct.POINTER(OctView), ct.POINTER(vp), vp, vp,
+                               ct.POINTER(RenderStats)]
+    L.render_ckpt_bytes.restype = sz
+    L.render_ckpt_bytes.argtypes = [vp, i32, ct.POINTER(OctView)]
+    L.render_views_backward.argtypes = [vp, i32, ct.POINTER(OctView), ct.POINTER(vp), vp, vp, vp,
+                                        vp]
+    L.octree_dump_canonical.argtypes = [vp, vp, sz, ct.POINTER(sz)]
+    L.octree_read_level.argtypes = [vp, i32, vp, sz, ct.POINTER(i32)]
+    L.octree_info.argtypes = [vp, ct.POINTER(i32), ct.POINTER(u64), ct.POINTER(u64)]
+    L.oct_last_error.restype = ct.c_char_p
+    L.oct_last_error.argtypes = [vp]
+    return L
+
+
+lib = _load()
+
+
+class OctError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"octree_rc error {code}: {msg}")
+        self.code = code
+
+
+def _stream(stream=None):
+    if stream is not None:
+        return ct.c_void_p(int(stream))
+    import torch
+    return ct.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def to_oct_view(v) -> OctView:
+    """Marshal a synth.View (or any object with the same attributes)."""
+    o = OctView()
+    for a in range(3):
+        o.eye[a], o.target[a], o.up[a] = float(v.eye[a]), float(v.target[a]), float(v.up[a])
+    o.fov_y_deg = float(v.fov_y_deg)
+    o.width, o.height = int(v.width), int(v.height)
+    o.tile_begin, o.tile_count = int(getattr(v, "tile_begin", 0)), int(getattr(v, "tile_count", -1))
+    o.step, o.ert_alpha, o.lod = float(v.step), float(v.ert_alpha), int(v.lod)
+    o.n_clip = len(v.clips)
+    for i, pl in enumerate(v.clips):
+        for k in range(4):
+            o.clip[i][k] = float(pl[k])
+    pos, rgba, win = np.asarray(v.tf_pos), np.asarray(v.tf_rgba), np.asarray(v.window)
+    for c in range(pos.shape[0]):
+        for j in range(8):
+            o.tf_pos[c][j] = float(pos[c, j])
+            for q in range(4):
+                o.tf_rgba[c][j][q] = float(rgba[c, j, q])
+        o.window[c][0], o.window[c][1] = float(win[c, 0]), float(win[c, 1])
+    o.no_skip = int(getattr(v, "no_skip", 0))
+    return o
+
+
+class Octree:
+    """A device-resident incrementally built multi-channel brick octree."""
+
+    def __init__(self, dims, channels: int, brick: int, dtype: str = "u16",
+                 background: float = 0.0, threshold: float = 0.0, pool_bytes: int = 0,
+                 stream=None):
+        p = CreateParams()
+        for a in range(3):
+            p.dims[a] = int(dims[a])
+        p.channels, p.brick_size = int(channels), int(brick)
+        p.dtype = OCT_U16 if dtype == "u16" else OCT_F32
+        p.background, p.homog_threshold = float(background), float(threshold)
+        p.device_pool_bytes = int(pool_bytes)
+        h = ct.c_void_p()
+        rc = lib.octree_create(ct.byref(p), _stream(stream), ct.byref(h))
+        if rc != OCT_OK:
+            raise OctError(rc, lib.oct_last_error(None).decode())
+        self.h = h
+        self.dims, self.C, self.M, self.dtype = tuple(int(d) for d in dims), channels, brick, dtype
+        lv, bb, ns = ct.c_int32(), ct.c_uint64(), ct.c_uint64()
+        lib.octree_info(self.h, ct.byref(lv), ct.byref(bb), ct.byref(ns))
+        self.levels, self.brick_bytes, self.pool_slots = lv.value, bb.value, ns.value
+
+    def _check(self, rc: int, ok=(OCT_OK,)):
+        if rc not in ok:
+            raise OctError(rc, lib.oct_last_error(self.h).decode())
+        return rc
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib.octree_destroy(self.h)
+            self.h = None
+
+    __del__ = close
+
+    def clear(self, stream=None):
+        self._check(lib.octree_clear(self.h, _stream(stream)))
+
+    def insert_block(self, channel: int, origin, data, stream=None):
+        """data: planar [Cb][nz][ny][nx] torch CUDA tensor or numpy array (host)."""
+        size = data.shape[1:][::-1]
+        o = (ct.c_int32 * 3)(*[int(x) for x in origin])
+        n = (ct.c_int32 * 3)(*[int(x) for x in size])
+        ptr, dev = self._data_ptr(data)
+        self._check(lib.octree_insert_block(self.h, int(channel), o, n, ptr, dev, _stream(stream)))
+
+    def insert_slices(self, channel: int, z0: int, data, stream=None):
+        ptr, dev = self._data_ptr(data)
+        self._check(lib.octree_insert_slices(self.h, int(channel), int(z0), int(data.shape[1]),
+                                             ptr, dev, _stream(stream)))
+
+    def _data_ptr(self, data):
+        want = np.uint16 if self.dtype == "u16" else np.float32
+        if isinstance(data, np.ndarray):
+            if data.dtype != want or not data.flags.c_contiguous:
+                raise TypeError("block must be C-contiguous " + np.dtype(want).name)
+            return ct.c_void_p(data.ctypes.data), 0
+        import torch
+        tw = (torch.uint16, torch.int16) if self.dtype == "u16" else (torch.float32,)
+        if data.dtype not in tw or not data.is_contiguous() or not data.is_cuda:
+            raise TypeError("device block must be a contiguous CUDA tensor of the volume dtype")
+        return ct.c_void_p(data.data_ptr()), 1
+
+    def upload(self, byte_budget: int = 0, stream=None) -> dict:
+        st = UploadStats()
+        rc = self._check(lib.brick_pool_upload(self.h, int(byte_budget), _stream(stream),
+                                               ct.byref(st)), ok=(OCT_OK, OCT_INCOMPLETE))
+        d = {k: getattr(st, k) for k, _ in UploadStats._fields_}
+        d["complete"] = rc == OCT_OK
+        return d
+
+    def render(self, views, images=None, stats: bool = False, stream=None, ckpt=None):
+        """Render views into torch CUDA images [H][W][4] float32 (allocated when not given)."""
+        import torch
+        if images is None:
+            images = [torch.zeros((v.height, v.width, 4), dtype=torch.float32, device="cuda")
+                      for v in views]
+        ov = (OctView * len(views))(*[to_oct_view(v) for v in views])
+        ptrs = (ct.c_void_p * len(views))(*[im.data_ptr() for im in images])
+        rs = RenderStats()
+        self._check(lib.render_views(self.h, len(views), ov, ptrs,
+                                     ct.c_void_p(ckpt.data_ptr()) if ckpt is not None else None,
+                                     _stream(stream), ct.byref(rs) if stats else None))
+        if stats:
+            return images, {k: getattr(rs, k) for k, _ in RenderStats._fields_}
+        return images
+
+    def dump(self) -> bytes:
+        need = ct.c_size_t()
+        lib.octree_dump_canonical(self.h, None, 0, ct.byref(need))
+        buf = np.empty(need.value, np.uint8)
+        self._check(lib.octree_dump_canonical(self.h, ct.c_void_p(buf.ctypes.data), need.value,
+                                              ct.byref(need)))
+        return buf.tobytes()
+
+    def read_level(self, L: int) -> np.ndarray:
+        ext = (ct.c_int32 * 3)()
+        lib.octree_read_level(self.h, int(L), ct.c_void_p(1), 0, ext)   # size query
+        ex, ey, ez = ext[0], ext[1], ext[2]
+        out = np.empty((self.C, ez, ey, ex), np.uint16 if self.dtype == "u16" else np.float32)
+        self._check(lib.octree_read_level(self.h, int(L), ct.c_void_p(out.ctypes.data),
+                                          out.nbytes, ext))
+        return out

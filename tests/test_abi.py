@@ -1,0 +1,93 @@
+"""CPU-side checks of the C ABI: the library loads and exports every declared symbol, and the
+ctypes structures of the binding have exactly the C layout of include/octree_rc.h."""
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "octree_rc.h")
+
+
+def _declared_functions():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\**\s*(\w+)\s*\(", txt, flags=re.M)))
+
+
+@pytest.fixture(scope="module")
+def native():
+    from paper_1407_2074_amd import octree
+    return octree
+
+
+def test_library_exports_every_declared_symbol(native):
+    decl = _declared_functions()
+    assert len(decl) >= 13, decl
+    assert sorted(native.EXPORTS) == decl
+    for name in decl:
+        assert hasattr(native.lib, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", native.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    syms = {line.split()[-1] for line in out.splitlines() if line.strip()}
+    assert set(decl) <= syms
+
+
+def test_struct_layouts_match_header(native, tmp_path):
+    import ctypes as ct
+    prog = tmp_path / "layout.c"
+    prog.write_text(f"""
+#include <stdio.h>
+#include <stddef.h>
+#include "{HEADER}"
+int main(void) {{
+  printf("%zu %zu %zu %zu\\n", sizeof(oct_create_params), sizeof(oct_view),
+         sizeof(oct_upload_stats), sizeof(oct_render_stats));
+  printf("%zu %zu %zu %zu %zu\\n", offsetof(oct_view, step), offsetof(oct_view, clip),
+         offsetof(oct_view, tf_rgba), offsetof(oct_view, window), offsetof(oct_view, no_skip));
+  printf("%zu %zu\\n", offsetof(oct_create_params, background),
+         offsetof(oct_create_params, device_pool_bytes));
+  return 0;
+}}
+""")
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-O0", "-o", str(exe), str(prog)])
+    got = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()
+    got = [int(x) for x in got]
+    V, P = native.OctView, native.CreateParams
+    assert got[:4] == [ct.sizeof(P), ct.sizeof(V), ct.sizeof(native.UploadStats),
+                       ct.sizeof(native.RenderStats)]
+    assert got[4:9] == [V.step.offset, V.clip.offset, V.tf_rgba.offset, V.window.offset,
+                        V.no_skip.offset]
+    assert got[9:] == [P.background.offset, P.device_pool_bytes.offset]
+
+
+def test_invalid_create_params_fail_without_gpu_work(native):
+    """Argument validation happens before any device call."""
+    import ctypes as ct
+    for bad in [dict(brick=5), dict(brick=0), dict(channels=5), dict(channels=0),
+                dict(dims=(0, 4, 4)), dict(dtype=7), dict(background=1.5)]:
+        p = native.CreateParams()
+        dims = bad.get("dims", (16, 16, 16))
+        for a in range(3):
+            p.dims[a] = dims[a]
+        p.channels = bad.get("channels", 3)
+        p.brick_size = bad.get("brick", 8)
+        p.dtype = bad.get("dtype", 0)
+        p.background = bad.get("background", 0.0)
+        h = ct.c_void_p()
+        assert native.lib.octree_create(ct.byref(p), None, ct.byref(h)) == native.OCT_EINVAL
+        assert native.lib.oct_last_error(None)
+
+
+def test_oracle_is_separate_from_the_library():
+    """The product sources never mention the oracle, and vice versa."""
+    csrc = os.path.join(ROOT, "paper_1407_2074_amd")
+    for dirpath, _, files in os.walk(csrc):
+        for f in files:
+            if f.endswith((".hip", ".h", ".py", ".cpp")):
+                txt = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in txt and "orc_" not in txt, f
+    txt = open(os.path.join(ROOT, "oracle", "oracle.c")).read()
+    assert "octree_rc" not in txt and "internal.h" not in txt
