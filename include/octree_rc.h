@@ -102,6 +102,7 @@ typedef struct {
     uint64_t rays;              /* pixels whose ray hits the clipped volume                */
     uint64_t positions_nominal; /* sample positions t_k < t1 over all rays                 */
     uint64_t positions_composited; /* positions actually sampled (not skipped, before ERT)  */
+    uint64_t positions_trilinear;  /* of those, positions interpolated inside a brick       */
 } oct_render_stats;
 
 /* Creates the octree: the root node exists from the start and holds only the background

@@ -21,6 +21,11 @@ ST_NONE, ST_EMPTY, ST_HOMOG_LEAF, ST_HOMOG, ST_BRICK = -1, 0, 1, 2, 3
 F_HAS_CHILDREN, F_COMPLETE, F_POPULATED = 1, 2, 4
 
 
+def num_threads() -> int:
+    """OpenMP threads the oracle's renderer uses."""
+    return int(lib().orc_num_threads())
+
+
 def build(force: bool = True) -> str:
     """Compile the oracle (gcc, OpenMP, no floating-point contraction)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
@@ -67,6 +72,9 @@ def lib():
         L.orc_render_grad.argtypes = [ct.c_void_p, ct.c_int, ct.POINTER(OrcView), ct.c_void_p,
                                       ct.c_void_p, ct.c_void_p]
         L.orc_rays.argtypes = [ct.c_void_p, ct.POINTER(OrcView), ct.c_void_p, ct.c_void_p]
+        L.orc_render_rows.argtypes = [ct.c_void_p, ct.POINTER(OrcView), ct.c_void_p,
+                                      ct.c_void_p, ct.c_int, ct.c_int]
+        L.orc_num_threads.restype = ct.c_int
         L.orc_node_info.argtypes = [ct.c_void_p, ct.c_int, ct.c_int, ct.c_int, ct.c_int,
                                     ct.c_void_p, ct.c_void_p, ct.c_void_p]
         _lib = L
@@ -179,6 +187,17 @@ class Tree:
         lib().orc_render_grad(self.h, len(views), ov, P(*[g.ctypes.data for g in gI]),
                               _ptr(dctrl), _ptr(dvox) if dvox is not None else None)
         return dctrl, dvox
+
+    def render_rows(self, view, row_begin: int, row_step: int):
+        """Render only rows row_begin, row_begin + row_step, ... of one view.  Returns the image
+        (other rows zero) and the nominal sample count per pixel."""
+        ov = to_orc_view(view)
+        img = np.zeros((view.height, view.width, 4), np.float64)
+        ns = np.zeros((view.height, view.width), np.int32)
+        if lib().orc_render_rows(self.h, ct.byref(ov), _ptr(img), _ptr(ns), row_begin,
+                                 row_step) != 0:
+            raise ValueError("oracle render rejected the view")
+        return img, ns
 
     def rays(self, view):
         ov = to_orc_view(view)

@@ -43,6 +43,9 @@
  * The trilinear weights are the float32 fractional parts of those positions, promoted to FP64.
  */
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -657,8 +660,37 @@ static void classify(const orc_luts *lu, const orc_view *v, int c, double s, dou
  * ert_margin (optional): per view [H][W] double, the smallest |A - ert| over the early
  * termination tests evaluated on the ray (+inf when ERT is off), for ambiguity detection.
  */
+static int render_rows(const orc_tree *t, int n_views, const orc_view *views,
+                       double *const *images, int32_t *const *nsamp, double *const *ert_margin,
+                       int row_begin, int row_step);
+
 int orc_render(const orc_tree *t, int n_views, const orc_view *views, double *const *images,
                int32_t *const *nsamp, double *const *ert_margin)
+{
+    return render_rows(t, n_views, views, images, nsamp, ert_margin, 0, 1);
+}
+
+/* Same as orc_render for the rows row_begin, row_begin + row_step, ... only (other rows are
+ * left untouched): a bounded sample of a large frame. */
+int orc_render_rows(const orc_tree *t, const orc_view *view, double *image, int32_t *nsamp,
+                    int row_begin, int row_step)
+{
+    if (row_begin < 0 || row_step < 1) return -1;
+    return render_rows(t, 1, view, &image, &nsamp, NULL, row_begin, row_step);
+}
+
+int orc_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+static int render_rows(const orc_tree *t, int n_views, const orc_view *views,
+                       double *const *images, int32_t *const *nsamp, double *const *ert_margin,
+                       int row_begin, int row_step)
 {
     const int C = t->p.channels;
     for (int vi = 0; vi < n_views; vi++) {
@@ -669,8 +701,8 @@ int orc_render(const orc_tree *t, int n_views, const orc_view *views, double *co
         orc_cam cm;
         cam_setup(v, &cm);
         const int W = v->width, H = v->height;
-#pragma omp parallel for schedule(dynamic, 8)
-        for (int j = 0; j < H; j++)
+#pragma omp parallel for schedule(dynamic, 1)
+        for (int j = row_begin; j < H; j += row_step)
             for (int i = 0; i < W; i++) {
                 double *px = images[vi] + ((int64_t)j * W + i) * 4;
                 orc_ray ry;

@@ -86,7 +86,7 @@ struct CellDelta {      // one change event applied to the node table
 };
 
 struct RenderCounters {
-    unsigned long long rays, nominal, composited;
+    unsigned long long rays, nominal, composited, trilinear;
 };
 
 // ---- launchers (build path) ----

@@ -159,7 +159,7 @@ k_render(VolGeom g, const DevCell *__restrict__ table, const uint8_t *__restrict
                            d[2] != 0.0f ? 1.0f / d[2] : INFINITY};
 
     float Tr = 1.0f, Cr = 0.0f, Cg = 0.0f, Cb = 0.0f;
-    int k = 0, composited = 0;
+    int k = 0, composited = 0, trilinear = 0;
     int blo[3] = {1, 1, 1}, bhi[3] = {0, 0, 0};  // cached cell, level-0 voxel box (inclusive)
     int kind = kAvg;
     const uint8_t *base = nullptr;
@@ -241,6 +241,7 @@ k_render(VolGeom g, const DevCell *__restrict__ table, const uint8_t *__restrict
         }
         composited++;
         if (kind == kBrick) {
+            trilinear++;
             float f[3];
             int ii[3];
 #pragma unroll
@@ -336,16 +337,18 @@ k_render(VolGeom g, const DevCell *__restrict__ table, const uint8_t *__restrict
             nominal = kk;
         }
         unsigned long long r = hit ? 1ull : 0ull, nn = (unsigned long long)nominal,
-                           cc = (unsigned long long)composited;
+                           cc = (unsigned long long)composited, tt = (unsigned long long)trilinear;
         for (int off = 32; off > 0; off >>= 1) {
             r += __shfl_xor(r, off, 64);
             nn += __shfl_xor(nn, off, 64);
             cc += __shfl_xor(cc, off, 64);
+            tt += __shfl_xor(tt, off, 64);
         }
         if (lane == 0) {
             atomicAdd(&counters->rays, r);
             atomicAdd(&counters->nominal, nn);
             atomicAdd(&counters->composited, cc);
+            atomicAdd(&counters->trilinear, tt);
         }
     }
 }

@@ -829,6 +829,7 @@ int render_views(oct_handle *h, int32_t n_views, const oct_view *views, float *c
         out->rays = rcnt->rays;
         out->positions_nominal = rcnt->nominal;
         out->positions_composited = rcnt->composited;
+        out->positions_trilinear = rcnt->trilinear;
     }
     HIPCHK(h, hipEventRecord(rs.st.ev, s));
     return OCT_OK;

@@ -50,7 +50,7 @@ class UploadStats(ct.Structure):
 
 class RenderStats(ct.Structure):
     _fields_ = [("rays", ct.c_uint64), ("positions_nominal", ct.c_uint64),
-                ("positions_composited", ct.c_uint64)]
+                ("positions_composited", ct.c_uint64), ("positions_trilinear", ct.c_uint64)]
 
 
 def _load():
