@@ -786,6 +786,9 @@ int orc_render_grad(const orc_tree *t, int n_views, const orc_view *views,
         orc_event *ev = (orc_event *)malloc(cap * sizeof(orc_event));
         for (int j = 0; j < H; j++)
             for (int i = 0; i < W; i++) {
+                const double *gI = dL_dI[vi] + ((int64_t)j * W + i) * 4;
+                if (gI[0] == 0.0 && gI[1] == 0.0 && gI[2] == 0.0 && gI[3] == 0.0)
+                    continue;  /* this ray contributes exactly zero */
                 orc_ray ry;
                 ray_setup(t, v, &cm, i, j, &ry);
                 if (!ry.hit) continue;
@@ -819,7 +822,6 @@ int orc_render_grad(const orc_tree *t, int n_views, const orc_view *views,
                         A += (1.0 - A) * e->rgba[3];
                     }
                 }
-                const double *gI = dL_dI[vi] + ((int64_t)j * W + i) * 4;
                 double gC[3] = {gI[0], gI[1], gI[2]}, gA = gI[3];
                 for (size_t n = ne; n-- > 0;) {
                     orc_event *e = &ev[n];

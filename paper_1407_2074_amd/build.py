@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liboctree_rc.so")
-SOURCES = ["runtime.hip", "build_kernels.hip", "render_kernels.hip"]
+SOURCES = ["runtime.hip", "build_kernels.hip", "render_kernels.hip", "adjoint_kernels.hip"]
 
 # -packed-fp32-ops: never emit packed FP32 VALU instructions.
 # -ffp-contract=off: only the fused multiply-adds written in the source are fused, so the

@@ -1,0 +1,310 @@
+// Adjoint of the forward ray caster: gradients of a scalar image loss with respect to the
+// transfer-function control-point RGBA values and to the level-0 voxel values.
+//
+// The forward stored, per ray, the transmittance T before positions 0, 64, 128, ... and the
+// first position it did not evaluate.  Per 64-position segment, last to first, a lane
+//   1. replays the segment forward from its checkpoint, writing T before each position to a
+//      per-wave scratch area ([position][lane], coalesced), and
+//   2. walks the segment back to front.  With Bc / Ba the colour / opacity of everything
+//      behind an event (as seen with transmittance 1), an event e with transmittance T_e,
+//      opacity a_e and colour rgb_e receives
+//          dL/drgb_e = gC * T_e * a_e
+//          dL/da_e   = T_e * (gC . (rgb_e - Bc) + gA * (1 - Ba))
+//      and then Bc <- a_e rgb_e + (1 - a_e) Bc, Ba <- a_e + (1 - a_e) Ba,
+//      where (gC, gA) = dL/d(pixel RGBA).
+// The event gradient flows into the two table entries it interpolated (LDS accumulator per
+// workgroup, added to the view's table gradient at the end) and, through the table slope and
+// the trilinear weights, into the eight level-0 corner voxels (global float atomics).
+// Every position is evaluated (no empty-space skipping): a zero-opacity sample still has a
+// non-zero gradient with respect to the table.
+#include "raycommon.h"
+
+#include <float.h>
+
+namespace octrc {
+
+namespace {
+
+constexpr int kThreads = 512;
+
+// One sample position: intensity per channel and, for a brick sample, the trilinear corners.
+template <int C>
+struct Sample {
+    float s[C];
+    bool brick;
+    int ii[3];      // lower corner in bordered-brick coordinates
+    float f[3];     // trilinear fractions
+    int org[3];     // level-L index of bordered-brick coordinate 0
+};
+
+template <typename T, int C>
+struct Marcher {
+    const VolGeom &g;
+    const DevCell *table;
+    const uint8_t *pool;
+    uint64_t brick_bytes;
+    int L, csz, G, coff;
+    float scaleL;
+    int blo[3] = {1, 1, 1}, bhi[3] = {0, 0, 0};
+    bool brick = false;
+    const uint8_t *base = nullptr;
+    int org[3] = {0, 0, 0};
+    float avg[C];
+
+    __device__ Marcher(const VolGeom &g_, const DevCell *t, const uint8_t *p, uint64_t bb, int L_)
+        : g(g_), table(t), pool(p), brick_bytes(bb), L(L_)
+    {
+        csz = g.M << L;
+        G = g.grid[L];
+        coff = g.cell_off[L];
+        scaleL = __builtin_ldexpf(1.0f, -L);
+        for (int c = 0; c < C; c++) avg[c] = 0.0f;
+    }
+
+    // Same decisions as the forward: the voxel holding p selects the level-L node; a brick
+    // node is interpolated in its bordered brick, any other node gives its AVG.
+    __device__ void sample(const float p[3], Sample<C> &out)
+    {
+        int v[3];
+#pragma unroll
+        for (int q = 0; q < 3; q++) v[q] = min(max((int)floorf(p[q]), 0), g.dims[q] - 1);
+        if (v[0] < blo[0] || v[0] > bhi[0] || v[1] < blo[1] || v[1] > bhi[1] || v[2] < blo[2] ||
+            v[2] > bhi[2]) {
+            const int cx = v[0] / csz, cy = v[1] / csz, cz = v[2] / csz;
+            const DevCell &cell = table[coff + (cz * G + cy) * G + cx];
+            blo[0] = cx * csz; bhi[0] = blo[0] + csz - 1;
+            blo[1] = cy * csz; bhi[1] = blo[1] + csz - 1;
+            blo[2] = cz * csz; bhi[2] = blo[2] + csz - 1;
+            brick = cell.kind == kBrick;
+            if (brick) {
+                base = pool + (uint64_t)cell.slot * brick_bytes;
+                org[0] = cx * g.M - 1;
+                org[1] = cy * g.M - 1;
+                org[2] = cz * g.M - 1;
+            } else {
+                for (int c = 0; c < C; c++) avg[c] = cell.avg[c];
+            }
+        }
+        out.brick = brick;
+        if (!brick) {
+            for (int c = 0; c < C; c++) out.s[c] = avg[c];
+            return;
+        }
+        const int S = g.M + 2;
+#pragma unroll
+        for (int q = 0; q < 3; q++) {
+            const float qq = p[q] * scaleL - 0.5f;
+            const float lq = qq - (float)org[q];
+            const float fl = floorf(lq);
+            out.f[q] = lq - fl;
+            out.ii[q] = min(max((int)fl, 0), S - 2);
+            out.org[q] = org[q];
+        }
+        const int64_t i0 = ((int64_t)(out.ii[2] * S + out.ii[1]) * S + out.ii[0]) * 4;
+        const int64_t dy = (int64_t)S * 4, dz = (int64_t)S * S * 4;
+        const T *b0 = (const T *)base;
+        float w[8][kMaxC];
+        const int64_t off[8] = {i0, i0 + 4, i0 + dy, i0 + dy + 4,
+                                i0 + dz, i0 + dz + 4, i0 + dz + dy, i0 + dz + dy + 4};
+#pragma unroll
+        for (int k = 0; k < 8; k++)
+            for (int c = 0; c < C; c++) w[k][c] = (float)b0[off[k] + c];
+#pragma unroll
+        for (int c = 0; c < C; c++) {
+            const float c00 = lerpf(w[0][c], w[1][c], out.f[0]);
+            const float c10 = lerpf(w[2][c], w[3][c], out.f[0]);
+            const float c01 = lerpf(w[4][c], w[5][c], out.f[0]);
+            const float c11 = lerpf(w[6][c], w[7][c], out.f[0]);
+            out.s[c] = lerpf(lerpf(c00, c10, out.f[1]), lerpf(c01, c11, out.f[1]), out.f[2]);
+        }
+    }
+};
+
+template <typename T, int C>
+__global__ void __launch_bounds__(kThreads)
+k_render_backward(VolGeom g, const DevCell *__restrict__ table, const uint8_t *__restrict__ pool,
+                  uint64_t brick_bytes, const DevView *__restrict__ views,
+                  const WgItem *__restrict__ items, float *__restrict__ scratch, float *dvox)
+{
+    __shared__ ViewTables<C> tb;
+    __shared__ float s_dlut[C][256][4];
+
+    const WgItem it = items[blockIdx.x];
+    const DevView &V = views[it.view];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int i = threadIdx.x; i < C * 256 * 4; i += kThreads) (&s_dlut[0][0][0])[i] = 0.0f;
+    build_tables<C>(V, tb);   // ends with a barrier
+
+    float ulo[C], usc[C];
+    for (int c = 0; c < C; c++) {
+        ulo[c] = V.ulo[c];
+        usc[c] = V.uscale[c];
+    }
+    const float step = V.step;
+    float *wscr = scratch + ((int64_t)blockIdx.x * kThreads + wave * 64) * kCkptStride;
+
+    if (wave < it.ntiles) {
+        const int tile = it.tile0 + wave;
+        const int px_i = (tile % V.tiles_x) * 8 + (lane & 7);
+        const int px_j = (tile / V.tiles_x) * 8 + (lane >> 3);
+        const bool inside = px_i < V.width && px_j < V.height;
+        const int64_t pix = (int64_t)px_j * V.width + px_i;
+        const Ray ray = setup_ray(V, g, px_i, px_j, inside);
+        const int n_end = ray.hit ? V.nend[pix] : 0;
+        float gC[3] = {0.0f, 0.0f, 0.0f}, gA = 0.0f;
+        if (inside) {
+            const float4 gi = *(const float4 *)(V.dimg + pix * 4);
+            gC[0] = gi.x;
+            gC[1] = gi.y;
+            gC[2] = gi.z;
+            gA = gi.w;
+        }
+        const int64_t nvox0 = (int64_t)g.dims[0] * g.dims[1] * g.dims[2];
+        Marcher<T, C> mf(g, table, pool, brick_bytes, ray.L);
+        Marcher<T, C> mb(g, table, pool, brick_bytes, ray.L);
+        float Bc[3] = {0.0f, 0.0f, 0.0f}, Ba = 0.0f;
+        for (int sg = (n_end + kCkptStride - 1) / kCkptStride - 1; sg >= 0; sg--) {
+            const int k0 = sg * kCkptStride;
+            const int k1 = min(k0 + kCkptStride, n_end);
+            // 1. forward replay: transmittance before each position of the segment
+            float Tr = V.ckpt[pix * V.nseg + sg];
+            for (int k = k0; k < k1; k++) {
+                const float tk = ray.t0 + (float)k * step;
+                float p[3];
+                for (int q = 0; q < 3; q++) {
+                    const float m = tk * ray.d[q];
+                    p[q] = ray.o[q] + m;
+                }
+                wscr[(k - k0) * 64 + lane] = Tr;
+                Sample<C> sm;
+                mf.sample(p, sm);
+                for (int c = 0; c < C; c++) {
+                    const Classified q = classify(sm.s[c], ulo[c], usc[c], tb.lut[c]);
+                    Tr = Tr - Tr * __builtin_fmaf(q.fr, q.de.w, q.e0.w);
+                }
+            }
+            // 2. back-to-front walk
+            for (int k = k1 - 1; k >= k0; k--) {
+                const float tk = ray.t0 + (float)k * step;
+                float p[3];
+                for (int q = 0; q < 3; q++) {
+                    const float m = tk * ray.d[q];
+                    p[q] = ray.o[q] + m;
+                }
+                Sample<C> sm;
+                mb.sample(p, sm);
+                Classified cq[C];
+                float rgba[C][4], Tc[C];
+                float Tp = wscr[(k - k0) * 64 + lane];
+                for (int c = 0; c < C; c++) {
+                    cq[c] = classify(sm.s[c], ulo[c], usc[c], tb.lut[c]);
+                    rgba[c][0] = __builtin_fmaf(cq[c].fr, cq[c].de.x, cq[c].e0.x);
+                    rgba[c][1] = __builtin_fmaf(cq[c].fr, cq[c].de.y, cq[c].e0.y);
+                    rgba[c][2] = __builtin_fmaf(cq[c].fr, cq[c].de.z, cq[c].e0.z);
+                    rgba[c][3] = __builtin_fmaf(cq[c].fr, cq[c].de.w, cq[c].e0.w);
+                    Tc[c] = Tp;
+                    Tp = Tp - Tp * rgba[c][3];
+                }
+                for (int c = C - 1; c >= 0; c--) {
+                    const float a = rgba[c][3];
+                    float gq[4];
+                    for (int q = 0; q < 3; q++) gq[q] = gC[q] * Tc[c] * a;
+                    gq[3] = Tc[c] * (gC[0] * (rgba[c][0] - Bc[0]) + gC[1] * (rgba[c][1] - Bc[1]) +
+                                     gC[2] * (rgba[c][2] - Bc[2]) + gA * (1.0f - Ba));
+                    for (int q = 0; q < 3; q++) Bc[q] = a * rgba[c][q] + (1.0f - a) * Bc[q];
+                    Ba = a + (1.0f - a) * Ba;
+                    const float fr = cq[c].fr;
+                    for (int q = 0; q < 4; q++) {
+                        if (gq[q] != 0.0f) {
+                            atomicAdd(&s_dlut[c][cq[c].i][q], (1.0f - fr) * gq[q]);
+                            atomicAdd(&s_dlut[c][cq[c].i + 1][q], fr * gq[q]);
+                        }
+                    }
+                    if (dvox && sm.brick && cq[c].inside) {
+                        const float4 de = cq[c].de;
+                        const float gs = usc[c] * (gq[0] * de.x + gq[1] * de.y + gq[2] * de.z +
+                                                   gq[3] * de.w);
+                        if (gs != 0.0f) {
+                            float *dv = dvox + (int64_t)c * nvox0;
+                            for (int corner = 0; corner < 8; corner++) {
+                                const int dxx = corner & 1, dyy = (corner >> 1) & 1, dzz = corner >> 2;
+                                const float wgt = (dxx ? sm.f[0] : 1.0f - sm.f[0]) *
+                                                  (dyy ? sm.f[1] : 1.0f - sm.f[1]) *
+                                                  (dzz ? sm.f[2] : 1.0f - sm.f[2]);
+                                const int gx = min(max(sm.org[0] + sm.ii[0] + dxx, 0), g.dims[0] - 1);
+                                const int gy = min(max(sm.org[1] + sm.ii[1] + dyy, 0), g.dims[1] - 1);
+                                const int gz = min(max(sm.org[2] + sm.ii[2] + dzz, 0), g.dims[2] - 1);
+                                atomicAdd(dv + ((int64_t)gz * g.dims[1] + gy) * g.dims[0] + gx, gs * wgt);
+                            }
+                        }
+                    }
+                }
+            }
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < C * 256 * 4; i += kThreads) {
+        const float v = (&s_dlut[0][0][0])[i];
+        if (v != 0.0f) atomicAdd(V.dlut + i, v);
+    }
+}
+
+// dL/dctrl[v][c][j][q] += sum over table entries k of (weight of control point j in entry k)
+// * dL/dtable[v][c][k][q]; the weights are those of the table construction.
+__global__ void k_lut_to_ctrl(const DevView *views, int n_views, int C, float *dctrl)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int q = i & 3, j = (i >> 2) & 7, c = (i >> 5) % C, v = (i >> 5) / C;
+    if (v >= n_views) return;
+    const DevView &V = views[v];
+    float acc = 0.0f;
+    for (int k = 0; k < 256; k++) {
+        int js;
+        float f;
+        tf_segment(V.tf_pos[c], k, js, f);
+        const float gk = V.dlut[(c * 256 + k) * 4 + q];
+        if (js == j) acc += (1.0f - f) * gk;
+        if (js + 1 == j) acc += f * gk;
+    }
+    dctrl[(((int64_t)v * C + c) * 8 + j) * 4 + q] += acc;
+}
+
+template <typename T>
+hipError_t launch_bw_typed(const VolGeom &g, const DevCell *table, const void *pool,
+                           uint64_t brick_bytes, const DevView *views, const WgItem *items,
+                           int n_items, float *scratch, float *dvox, hipStream_t s)
+{
+    const dim3 grid(n_items), block(kThreads);
+    const uint8_t *p = (const uint8_t *)pool;
+    switch (g.C) {
+    case 1: hipLaunchKernelGGL((k_render_backward<T, 1>), grid, block, 0, s, g, table, p, brick_bytes, views, items, scratch, dvox); break;
+    case 2: hipLaunchKernelGGL((k_render_backward<T, 2>), grid, block, 0, s, g, table, p, brick_bytes, views, items, scratch, dvox); break;
+    case 3: hipLaunchKernelGGL((k_render_backward<T, 3>), grid, block, 0, s, g, table, p, brick_bytes, views, items, scratch, dvox); break;
+    default: hipLaunchKernelGGL((k_render_backward<T, 4>), grid, block, 0, s, g, table, p, brick_bytes, views, items, scratch, dvox); break;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_render_backward(const VolGeom &g, const DevCell *table, const void *pool,
+                                  uint64_t brick_bytes, const DevView *views, const WgItem *items,
+                                  int n_items, float *scratch, float *dvox, hipStream_t s)
+{
+    if (n_items == 0) return hipSuccess;
+    if (g.dtype == 0)
+        return launch_bw_typed<uint16_t>(g, table, pool, brick_bytes, views, items, n_items, scratch,
+                                         dvox, s);
+    return launch_bw_typed<float>(g, table, pool, brick_bytes, views, items, n_items, scratch, dvox,
+                                  s);
+}
+
+hipError_t launch_lut_to_ctrl(const DevView *views, int n_views, int C, float *dctrl, hipStream_t s)
+{
+    const int n = n_views * C * 32;
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_lut_to_ctrl, dim3((n + 255) / 256), dim3(256), 0, s, views, n_views, C, dctrl);
+    return hipGetLastError();
+}
+
+}  // namespace octrc

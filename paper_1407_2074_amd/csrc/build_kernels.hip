@@ -123,14 +123,28 @@ struct AddU { __device__ unsigned long long operator()(unsigned long long a,
                                                        unsigned long long b) const { return a + b; } };
 
 // Step 3 inputs: min / max / sum of a cell's valid voxels per channel (+ inserted counts at
-// level 0).  One workgroup per listed cell; rows of the cell are spread over the threads.
+// level 0).  Pass 1 spreads each listed cell over `nsub` workgroups (slabs of z-slices) that
+// write partial results; pass 2 folds the partials of a cell in a fixed order, so the sums
+// (integers for u16, doubles for f32) do not depend on scheduling.
+struct StatPart {
+    float mn[kMaxC], mx[kMaxC];
+    double sum[kMaxC];
+    uint32_t ins[kMaxC];
+};
+
+struct MinF { __device__ float operator()(float a, float b) const { return fminf(a, b); } };
+struct MaxF { __device__ float operator()(float a, float b) const { return fmaxf(a, b); } };
+
 template <typename T>
 __global__ void __launch_bounds__(kThreads)
-k_stats(VolGeom g, const T *master, const uint8_t *mask, const int4 *cells, CellStat *out)
+k_stats_part(VolGeom g, const T *master, const uint8_t *mask, const int4 *cells, int nsub,
+             StatPart *part)
 {
+    __shared__ float sf[kThreads / 64];
     __shared__ double sd[kThreads / 64];
     __shared__ unsigned long long su[kThreads / 64];
-    const int4 cl = cells[blockIdx.x];
+    const int4 cl = cells[blockIdx.x / nsub];
+    const int sub = blockIdx.x % nsub;
     const int L = cl.x;
     const int b[3] = {cl.y, cl.z, cl.w};
     int lo[3], n[3];
@@ -138,50 +152,77 @@ k_stats(VolGeom g, const T *master, const uint8_t *mask, const int4 *cells, Cell
         lo[a] = b[a] * g.M;
         n[a] = min(g.M, g.ext[L][a] - lo[a]);
     }
+    const int zc = (n[2] + nsub - 1) / nsub;
+    const int zs = min(sub * zc, n[2]), ze = min(zs + zc, n[2]);
+    const int rstep = kThreads / n[0];            // rows per pass (n[0] <= 128)
+    const int x = threadIdx.x % n[0], r0 = threadIdx.x / n[0];
+    const bool on = r0 < rstep;
     const int ex = g.ext[L][0], ey = g.ext[L][1];
-    const int rows = n[1] * n[2];
-    CellStat *o = out + blockIdx.x;
+    StatPart *o = part + blockIdx.x;
     for (int c = 0; c < g.C; c++) {
         const T *src = level_ptr(master, g, L, c);
-        double mn = DBL_MAX, mx = -DBL_MAX, sm = 0.0;
-        unsigned long long su_local = 0;
-        for (int i = threadIdx.x; i < rows * n[0]; i += kThreads) {
-            const int x = i % n[0], r = i / n[0];
-            const int y = r % n[1], z = r / n[1];
-            const T v = src[((int64_t)(lo[2] + z) * ey + (lo[1] + y)) * ex + (lo[0] + x)];
-            mn = fmin(mn, (double)v);
-            mx = fmax(mx, (double)v);
-            if constexpr (sizeof(T) == 2) su_local += v;
-            else sm += (double)v;
-        }
-        mn = block_reduce(mn, MinOp{}, sd);
-        mx = block_reduce(mx, MaxOp{}, sd);
-        if constexpr (sizeof(T) == 2) sm = (double)block_reduce(su_local, AddU{}, su);
-        else sm = block_reduce(sm, AddD{}, sd);
+        float mn = FLT_MAX, mx = -FLT_MAX;
+        double sm = 0.0;
+        uint32_t su_local = 0;
+        if (on)
+            for (int z = zs; z < ze; z++)
+                for (int y = r0; y < n[1]; y += rstep) {
+                    const T v = src[((int64_t)(lo[2] + z) * ey + (lo[1] + y)) * ex + (lo[0] + x)];
+                    mn = fminf(mn, (float)v);
+                    mx = fmaxf(mx, (float)v);
+                    if constexpr (sizeof(T) == 2) su_local += v;
+                    else sm += (double)v;
+                }
+        mn = block_reduce(mn, MinF{}, sf);
+        mx = block_reduce(mx, MaxF{}, sf);
+        if constexpr (sizeof(T) == 2)
+            sm = (double)block_reduce((unsigned long long)su_local, AddU{}, su);
+        else
+            sm = block_reduce(sm, AddD{}, sd);
         if (threadIdx.x == 0) {
             o->mn[c] = mn;
             o->mx[c] = mx;
             o->sum[c] = sm;
         }
     }
-    if (L == 0) {
-        unsigned long long cnt[kMaxC] = {0, 0, 0, 0};
-        for (int i = threadIdx.x; i < rows * n[0]; i += kThreads) {
-            const int x = i % n[0], r = i / n[0];
-            const int y = r % n[1], z = r / n[1];
-            const uint32_t bits =
-                mask[((int64_t)(lo[2] + z) * g.dims[1] + (lo[1] + y)) * g.dims[0] + (lo[0] + x)];
-            for (int c = 0; c < g.C; c++) cnt[c] += (bits >> c) & 1u;
-        }
-        for (int c = 0; c < g.C; c++) {
-            const unsigned long long t = block_reduce(cnt[c], AddU{}, su);
-            if (threadIdx.x == 0) o->ins[c] = (uint32_t)t;
-        }
-    } else if (threadIdx.x == 0) {
-        for (int c = 0; c < kMaxC; c++) o->ins[c] = 0;
+    uint32_t cnt[kMaxC] = {0, 0, 0, 0};
+    if (L == 0 && on)
+        for (int z = zs; z < ze; z++)
+            for (int y = r0; y < n[1]; y += rstep) {
+                const uint32_t bits = mask[((int64_t)(lo[2] + z) * g.dims[1] + (lo[1] + y)) *
+                                               g.dims[0] + (lo[0] + x)];
+                for (int c = 0; c < kMaxC; c++) cnt[c] += (bits >> c) & 1u;
+            }
+    for (int c = 0; c < g.C; c++) {
+        const unsigned long long t = block_reduce((unsigned long long)cnt[c], AddU{}, su);
+        if (threadIdx.x == 0) o->ins[c] = (uint32_t)t;
     }
-    if (threadIdx.x == 0)
-        for (int c = g.C; c < kMaxC; c++) o->mn[c] = o->mx[c] = o->sum[c] = 0.0;
+}
+
+__global__ void __launch_bounds__(kThreads)
+k_stats_fold(int n, int nsub, int C, const StatPart *part, CellStat *out)
+{
+    const int i = blockIdx.x * kThreads + threadIdx.x;
+    if (i >= n) return;
+    CellStat r;
+    for (int c = 0; c < kMaxC; c++) {
+        float mn = FLT_MAX, mx = -FLT_MAX;
+        double sm = 0.0;
+        uint32_t ins = 0;
+        if (c < C)
+            for (int k = 0; k < nsub; k++) {
+                const StatPart &p = part[(int64_t)i * nsub + k];
+                mn = fminf(mn, p.mn[c]);
+                mx = fmaxf(mx, p.mx[c]);
+                sm += p.sum[c];
+                ins += p.ins[c];
+            }
+        r.mn[c] = c < C ? (double)mn : 0.0;
+        r.mx[c] = c < C ? (double)mx : 0.0;
+        r.sum[c] = sm;
+        r.ins[c] = ins;
+    }
+    out[i] = r;
 }
 
 // ---------------------------------------------------------------------------------------
@@ -203,7 +244,9 @@ k_apply_deltas(DevCell *table, const CellDelta *d, int n)
 // [b*M-1, b*M+M]^3 with indices clamped to the valid extent, where R_L is the level-L data
 // inside brick cells and the cell's AVG elsewhere.  Channels are interleaved and padded to
 // four lanes, so one 8-byte (u16) or 16-byte (f32) load fetches a voxel of every channel.
-// Also reduces the per-channel min/max of the bordered brick (the skip range of the slot).
+// A job rebuilds the whole brick or only the sub-box its inserted data touched.  It also
+// reduces the per-channel min/max of what it wrote: the slot's skip range is replaced by a
+// whole-brick job and widened by a partial one (a superset stays a valid bound).
 template <typename T>
 __global__ void __launch_bounds__(kThreads)
 k_gather(VolGeom g, const T *master, const DevCell *table, uint8_t *pool, uint64_t brick_bytes,
@@ -211,7 +254,7 @@ k_gather(VolGeom g, const T *master, const DevCell *table, uint8_t *pool, uint64
 {
     __shared__ int s_kind[27];
     __shared__ float s_avg[27][4];
-    __shared__ double sd[kThreads / 64];
+    __shared__ float sf[kThreads / 64];
     const BrickJob job = jobs[blockIdx.x];
     const int L = job.level, M = g.M, S = M + 2, G = g.grid[L];
     const int b[3] = {job.bx, job.by, job.bz};
@@ -238,43 +281,47 @@ k_gather(VolGeom g, const T *master, const DevCell *table, uint8_t *pool, uint64
         mx[c] = -FLT_MAX;
     }
     T *dst = (T *)(pool + (uint64_t)job.slot * brick_bytes);
-    const int total = S * S * S;
-    for (int i = threadIdx.x; i < total; i += kThreads) {
-        const int x = i % S, r = i / S;
-        const int y = r % S, z = r / S;
+    const int nx = job.hi[0] - job.lo[0] + 1;
+    const int rstep = kThreads / nx;
+    const int x = job.lo[0] + threadIdx.x % nx, r0 = threadIdx.x / nx;
+    if (r0 < rstep) {
         const int gx = min(max(b[0] * M - 1 + x, 0), ex - 1);
-        const int gy = min(max(b[1] * M - 1 + y, 0), ey - 1);
-        const int gz = min(max(b[2] * M - 1 + z, 0), ez - 1);
         const int ox = gx < b[0] * M ? 0 : (gx >= b[0] * M + M ? 2 : 1);
-        const int oy = gy < b[1] * M ? 0 : (gy >= b[1] * M + M ? 2 : 1);
-        const int oz = gz < b[2] * M ? 0 : (gz >= b[2] * M + M ? 2 : 1);
-        const int nb = (oz * 3 + oy) * 3 + ox;
-        T v[4];
-        if (s_kind[nb] != kAvg) {
-            const int64_t lin = ((int64_t)gz * ey + gy) * ex + gx;
-            for (int c = 0; c < 4; c++) v[c] = c < g.C ? src[(int64_t)c * nlev + lin] : (T)0;
-        } else {
-            for (int c = 0; c < 4; c++) v[c] = c < g.C ? (T)s_avg[nb][c] : (T)0;
-        }
-        for (int c = 0; c < kMaxC; c++)
-            if (c < g.C) {
-                mn[c] = fminf(mn[c], (float)v[c]);
-                mx[c] = fmaxf(mx[c], (float)v[c]);
+        for (int z = job.lo[2]; z <= job.hi[2]; z++) {
+            const int gz = min(max(b[2] * M - 1 + z, 0), ez - 1);
+            const int oz = gz < b[2] * M ? 0 : (gz >= b[2] * M + M ? 2 : 1);
+            for (int y = job.lo[1] + r0; y <= job.hi[1]; y += rstep) {
+                const int gy = min(max(b[1] * M - 1 + y, 0), ey - 1);
+                const int oy = gy < b[1] * M ? 0 : (gy >= b[1] * M + M ? 2 : 1);
+                const int nb = (oz * 3 + oy) * 3 + ox;
+                T v[4];
+                if (s_kind[nb] != kAvg) {
+                    const int64_t lin = ((int64_t)gz * ey + gy) * ex + gx;
+                    for (int c = 0; c < 4; c++) v[c] = c < g.C ? src[(int64_t)c * nlev + lin] : (T)0;
+                } else {
+                    for (int c = 0; c < 4; c++) v[c] = c < g.C ? (T)s_avg[nb][c] : (T)0;
+                }
+                for (int c = 0; c < kMaxC; c++)
+                    if (c < g.C) {
+                        mn[c] = fminf(mn[c], (float)v[c]);
+                        mx[c] = fmaxf(mx[c], (float)v[c]);
+                    }
+                const int64_t i = ((int64_t)z * S + y) * S + x;
+                if constexpr (sizeof(T) == 2) {
+                    *(ushort4 *)(dst + i * 4) = make_ushort4(v[0], v[1], v[2], v[3]);
+                } else {
+                    *(float4 *)(dst + i * 4) = make_float4(v[0], v[1], v[2], v[3]);
+                }
             }
-        if constexpr (sizeof(T) == 2) {
-            ushort4 w = make_ushort4(v[0], v[1], v[2], v[3]);
-            *(ushort4 *)(dst + (int64_t)i * 4) = w;
-        } else {
-            float4 w = make_float4(v[0], v[1], v[2], v[3]);
-            *(float4 *)(dst + (int64_t)i * 4) = w;
         }
     }
     for (int c = 0; c < g.C; c++) {
-        const double lo = block_reduce((double)mn[c], MinOp{}, sd);
-        const double hi = block_reduce((double)mx[c], MaxOp{}, sd);
+        const float lo = block_reduce(mn[c], MinF{}, sf);
+        const float hi = block_reduce(mx[c], MaxF{}, sf);
         if (threadIdx.x == 0) {
-            slot_range[(int64_t)job.slot * 8 + c] = (float)lo;
-            slot_range[(int64_t)job.slot * 8 + 4 + c] = (float)hi;
+            float *r = slot_range + (int64_t)job.slot * 8;
+            r[c] = job.full ? lo : fminf(r[c], lo);
+            r[4 + c] = job.full ? hi : fmaxf(r[4 + c], hi);
         }
     }
 }
@@ -358,16 +405,27 @@ hipError_t launch_downsample(const VolGeom &g, void *master, int L, const int32_
     return hipGetLastError();
 }
 
+size_t stats_scratch_bytes(const VolGeom &g, int n)
+{
+    return (size_t)n * (size_t)std::max(1, g.M / 4) * sizeof(StatPart);
+}
+
 hipError_t launch_stats(const VolGeom &g, const void *master, const uint8_t *mask,
-                        const int32_t *cells, int n, CellStat *out, hipStream_t s)
+                        const int32_t *cells, int n, void *scratch, CellStat *out, hipStream_t s)
 {
     if (n == 0) return hipSuccess;
+    const int nsub = std::max(1, g.M / 4);
+    StatPart *part = (StatPart *)scratch;
     if (g.dtype == 0)
-        hipLaunchKernelGGL(k_stats<uint16_t>, dim3(n), dim3(kThreads), 0, s, g,
-                           (const uint16_t *)master, mask, (const int4 *)cells, out);
+        hipLaunchKernelGGL(k_stats_part<uint16_t>, dim3(n * nsub), dim3(kThreads), 0, s, g,
+                           (const uint16_t *)master, mask, (const int4 *)cells, nsub, part);
     else
-        hipLaunchKernelGGL(k_stats<float>, dim3(n), dim3(kThreads), 0, s, g, (const float *)master,
-                           mask, (const int4 *)cells, out);
+        hipLaunchKernelGGL(k_stats_part<float>, dim3(n * nsub), dim3(kThreads), 0, s, g,
+                           (const float *)master, mask, (const int4 *)cells, nsub, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_stats_fold, dim3(ceil_div(n, kThreads)), dim3(kThreads), 0, s, n, nsub,
+                       g.C, part, out);
     return hipGetLastError();
 }
 
@@ -404,6 +462,14 @@ hipError_t launch_ranges(const VolGeom &g, DevCell *table, const float *slot_ran
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
+}
+
+hipError_t launch_fill_f32(float *p, int64_t n, float v, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill<float>, dim3((unsigned)std::min<int64_t>(ceil_div(n, kThreads), 65536)),
+                       dim3(kThreads), 0, s, p, n, v);
+    return hipGetLastError();
 }
 
 hipError_t launch_clear(const VolGeom &g, void *master, uint8_t *mask, double background,

@@ -32,6 +32,7 @@ struct VolGeom {
     int32_t M;
     int32_t N;
     int32_t dtype;
+    int32_t mlog2;                 // log2(M) when M is a power of two, else -1
     int32_t ext[kMaxLevels][3];
     int64_t lvl_off[kMaxLevels];   // element offset of level L in the master buffer
     int32_t grid[kMaxLevels];      // cells per axis at level L = 2^(N-L)
@@ -55,11 +56,19 @@ struct DevView {
     float tf_pos[kMaxC][8];
     float tf_rgba[kMaxC][8][4];
     float *image;
-    float *ckpt;          // transmittance checkpoints (NULL: none)
-    int64_t ckpt_off;     // float offset of this view's checkpoints in the workspace
+    // checkpoint workspace of this view (NULL: none): the transmittance before positions
+    // 0, 64, 128, ... of every ray ([pixel][nseg]) and the first position not evaluated
+    float *ckpt;
+    int32_t *nend;
+    int32_t nseg;
+    int32_t pad0;
+    // adjoint only: dL/dimage of this view, dL/dtable accumulator [C][256][4]
+    const float *dimg;
+    float *dlut;
 };
 
-// One workgroup of a render launch: 4 waves = up to 4 consecutive tiles of one view.
+// One workgroup of a render launch: 8 waves = up to 8 consecutive tiles of one view.
+constexpr int kRenderTilesPerWg = 8;
 struct WgItem {
     int32_t view;
     int32_t tile0;
@@ -67,10 +76,13 @@ struct WgItem {
     int32_t pad;
 };
 
-struct BrickJob {       // one bordered brick to (re)build
+struct BrickJob {       // one bordered brick to (re)build, whole or a sub-box of it
     int32_t slot, level, bx, by, bz;
-    int32_t pad[3];
+    int32_t full;       // 1: the sub-box is the whole bordered brick
+    int32_t lo[3], hi[3];  // inclusive sub-box in bordered-brick coordinates 0..M+1
+    int32_t pad[4];
 };
+static_assert(sizeof(BrickJob) == 64, "BrickJob layout");
 
 struct CellStat {       // statistics of one cell over its valid voxels
     double mn[kMaxC], mx[kMaxC], sum[kMaxC];
@@ -95,9 +107,10 @@ hipError_t launch_insert(const VolGeom &g, void *master, uint8_t *mask, const vo
                          hipStream_t s);
 hipError_t launch_downsample(const VolGeom &g, void *master, int L, const int32_t lo[3],
                              const int32_t hi[3], hipStream_t s);
+size_t stats_scratch_bytes(const VolGeom &g, int n);
 hipError_t launch_stats(const VolGeom &g, const void *master, const uint8_t *mask,
                         const int32_t *cells /* (level, bx, by, bz) x n */, int n,
-                        CellStat *out, hipStream_t s);
+                        void *scratch /* stats_scratch_bytes */, CellStat *out, hipStream_t s);
 hipError_t launch_apply_deltas(DevCell *table, const CellDelta *d, int n, hipStream_t s);
 hipError_t launch_gather(const VolGeom &g, const void *master, const DevCell *table,
                          void *pool, uint64_t brick_bytes, const BrickJob *jobs, int n,
@@ -106,10 +119,19 @@ hipError_t launch_ranges(const VolGeom &g, DevCell *table, const float *slot_ran
                          hipStream_t s);
 hipError_t launch_clear(const VolGeom &g, void *master, uint8_t *mask, double background,
                         hipStream_t s);
+hipError_t launch_fill_f32(float *p, int64_t n, float v, hipStream_t s);
 
 // ---- launchers (render path) ----
+constexpr int kCkptStride = 64;   // positions per transmittance checkpoint segment
+
 hipError_t launch_render(const VolGeom &g, const DevCell *table, const void *pool,
                          uint64_t brick_bytes, const DevView *views, const WgItem *items,
                          int n_items, RenderCounters *counters, hipStream_t s);
+// Adjoint: scratch holds kCkptStride floats per lane of the launch (n_items * 512 lanes).
+hipError_t launch_render_backward(const VolGeom &g, const DevCell *table, const void *pool,
+                                  uint64_t brick_bytes, const DevView *views, const WgItem *items,
+                                  int n_items, float *scratch, float *dvox, hipStream_t s);
+hipError_t launch_lut_to_ctrl(const DevView *views, int n_views, int C, float *dctrl,
+                              hipStream_t s);
 
 }  // namespace octrc

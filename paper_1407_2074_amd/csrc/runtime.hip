@@ -79,6 +79,8 @@ struct oct_handle {
     Stage up;                    // upload: cell list / stats / deltas / jobs
     RenderSlot rs[kRenderSlots];
     int next_rs = 0;
+    void *bw_tmp = nullptr;      // adjoint: table-gradient accumulators + replay scratch
+    size_t bw_tmp_cap = 0;
     std::vector<HCell> cells;
     std::vector<int32_t> free_slots;
     std::vector<std::vector<Box>> dirty;  // per level
@@ -354,6 +356,9 @@ int octree_create(const oct_create_params *params, void *stream, oct_handle **ou
         return bail(OCT_EINVAL);
     }
     g.N = N;
+    g.mlog2 = -1;
+    for (int b = 1; b < 8; b++)
+        if (g.M == (1 << b)) g.mlog2 = b;
     h->esz = params->dtype == OCT_U16 ? 2 : 4;
     h->background_f = (float)params->background;
     int64_t off = 0, coff = 0;
@@ -416,6 +421,7 @@ int octree_destroy(oct_handle *h)
     if (h->pool) (void)hipFree(h->pool);
     if (h->slot_range) (void)hipFree(h->slot_range);
     if (h->ins_stage) (void)hipFree(h->ins_stage);
+    if (h->bw_tmp) (void)hipFree(h->bw_tmp);
     if (h->ins_ev) (void)hipEventDestroy(h->ins_ev);
     stage_free(h->up);
     for (auto &r : h->rs) stage_free(r.st);
@@ -503,8 +509,15 @@ int brick_pool_upload(oct_handle *h, uint64_t byte_budget, void *stream, oct_upl
 
     // ---- 1. cells whose level data changed, and cells whose bordered region touches a change
     std::vector<int32_t> stat_cells;  // (L, x, y, z) quadruples
-    std::vector<uint8_t> border_dirty((size_t)h->n_cells, 0);
+    // per cell: bordered-brick sub-box touched by changed data (lo[3], hi[3]; lo > hi = none)
+    std::vector<int32_t> border_box((size_t)h->n_cells * 6);
+    for (int64_t i = 0; i < h->n_cells; i++) {
+        int32_t *bb = &border_box[(size_t)i * 6];
+        bb[0] = bb[1] = bb[2] = 1 << 30;
+        bb[3] = bb[4] = bb[5] = -1;
+    }
     std::vector<uint8_t> data_dirty((size_t)h->n_cells, 0);
+    const int S = M + 2;
     for (int L = 0; L <= g.N; L++) {
         const int G = g.grid[L];
         for (const Box &b : h->dirty[L]) {
@@ -518,10 +531,29 @@ int brick_pool_upload(oct_handle *h, uint64_t byte_budget, void *stream, oct_upl
                     for (int x = lo[0]; x <= hi[0]; x++) {
                         const int64_t ci = cell_index(g, L, x, y, z);
                         if (!h->cells[ci].inside) continue;
-                        // bordered box of the cell in level-L voxels
-                        const int blo[3] = {x * M - 1, y * M - 1, z * M - 1};
-                        const int bhi[3] = {x * M + M, y * M + M, z * M + M};
-                        if (box_intersects(b, blo, bhi)) border_dirty[ci] = 1;
+                        // bordered positions l whose clamped source index lies in the box
+                        const int cb[3] = {x, y, z};
+                        int llo[3], lhi[3];
+                        bool any = true;
+                        for (int a = 0; a < 3; a++) {
+                            llo[a] = S;
+                            lhi[a] = -1;
+                            for (int l = 0; l < S; l++) {
+                                const int gi = std::min(std::max(cb[a] * M - 1 + l, 0), g.ext[L][a] - 1);
+                                if (gi >= b.lo[a] && gi <= b.hi[a]) {
+                                    llo[a] = std::min(llo[a], l);
+                                    lhi[a] = std::max(lhi[a], l);
+                                }
+                            }
+                            if (lhi[a] < 0) any = false;
+                        }
+                        if (any) {
+                            int32_t *bb = &border_box[(size_t)ci * 6];
+                            for (int a = 0; a < 3; a++) {
+                                bb[a] = std::min(bb[a], llo[a]);
+                                bb[3 + a] = std::max(bb[3 + a], lhi[a]);
+                            }
+                        }
                         const int clo[3] = {x * M, y * M, z * M};
                         const int chi[3] = {x * M + M - 1, y * M + M - 1, z * M + M - 1};
                         if (box_intersects(b, clo, chi) && !data_dirty[ci]) {
@@ -539,11 +571,13 @@ int brick_pool_upload(oct_handle *h, uint64_t byte_budget, void *stream, oct_upl
         const size_t cl_bytes = stat_cells.size() * sizeof(int32_t);
         const size_t st_off = (cl_bytes + 255) & ~(size_t)255;
         const size_t st_bytes = (size_t)n_stat * sizeof(CellStat);
-        int rc = stage_reserve(h, h->up, st_off + st_bytes);
+        const size_t sc_off = (st_off + st_bytes + 255) & ~(size_t)255;
+        int rc = stage_reserve(h, h->up, sc_off + stats_scratch_bytes(g, n_stat));
         if (rc) return rc;
         std::memcpy(h->up.host, stat_cells.data(), cl_bytes);
         HIPCHK(h, hipMemcpyAsync(h->up.dev, h->up.host, cl_bytes, hipMemcpyHostToDevice, s));
         HIPCHK(h, launch_stats(g, h->master, h->mask, (const int32_t *)h->up.dev, n_stat,
+                               (uint8_t *)h->up.dev + sc_off,
                                (CellStat *)((uint8_t *)h->up.dev + st_off), s));
         HIPCHK(h, hipMemcpyAsync((uint8_t *)h->up.host + st_off, (uint8_t *)h->up.dev + st_off, st_bytes,
                                  hipMemcpyDeviceToHost, s));
@@ -623,15 +657,18 @@ int brick_pool_upload(oct_handle *h, uint64_t byte_budget, void *stream, oct_upl
                         pending++;
                         continue;
                     }
-                    bool need = c.needs_gather || border_dirty[ci];
-                    for (int dz = -1; dz <= 1 && !need; dz++)
-                        for (int dy = -1; dy <= 1 && !need; dy++)
-                            for (int dx = -1; dx <= 1 && !need; dx++) {
+                    // whole brick: new slot, deferred earlier, or a neighbour changed kind/AVG
+                    bool full = c.needs_gather;
+                    for (int dz = -1; dz <= 1 && !full; dz++)
+                        for (int dy = -1; dy <= 1 && !full; dy++)
+                            for (int dx = -1; dx <= 1 && !full; dx++) {
                                 const int nx = x + dx, ny = y + dy, nz = z + dz;
                                 if (nx < 0 || ny < 0 || nz < 0 || nx >= G || ny >= G || nz >= G) continue;
-                                if (changed[cell_index(g, L, nx, ny, nz)]) need = true;
+                                if (changed[cell_index(g, L, nx, ny, nz)]) full = true;
                             }
-                    if (need) {
+                    const int32_t *bb = &border_box[(size_t)ci * 6];
+                    const bool part = !full && bb[3] >= 0 && bb[4] >= 0 && bb[5] >= 0;
+                    if (full || part) {
                         if (budget_left >= h->brick_bytes) {
                             budget_left -= h->brick_bytes;
                             BrickJob j{};
@@ -640,6 +677,11 @@ int brick_pool_upload(oct_handle *h, uint64_t byte_budget, void *stream, oct_upl
                             j.bx = x;
                             j.by = y;
                             j.bz = z;
+                            j.full = full ? 1 : 0;
+                            for (int a = 0; a < 3; a++) {
+                                j.lo[a] = full ? 0 : bb[a];
+                                j.hi[a] = full ? S - 1 : bb[3 + a];
+                            }
                             jobs.push_back(j);
                             c.needs_gather = false;
                         } else {
@@ -700,12 +742,34 @@ int brick_pool_upload(oct_handle *h, uint64_t byte_budget, void *stream, oct_upl
     return pending ? OCT_INCOMPLETE : OCT_OK;
 }
 
+// Checkpoint workspace: per view, [pixel][nseg] float32 transmittances then [pixel] int32
+// end positions; nseg covers the longest possible ray (the box diagonal) in 64-position
+// segments.
+static int view_nseg(const oct_handle *h, const oct_view &v)
+{
+    const double diag = std::sqrt((double)h->g.dims[0] * h->g.dims[0] +
+                                  (double)h->g.dims[1] * h->g.dims[1] +
+                                  (double)h->g.dims[2] * h->g.dims[2]);
+    const double nmax = std::ceil(diag / (double)v.step) + 2.0;
+    return (int)std::ceil(nmax / kCkptStride);
+}
+
+static size_t view_ckpt_bytes(const oct_handle *h, const oct_view &v)
+{
+    const size_t npix = (size_t)v.width * v.height;
+    const size_t b = npix * (size_t)view_nseg(h, v) * 4 + npix * 4;
+    return (b + 255) & ~(size_t)255;
+}
+
 size_t render_ckpt_bytes(const oct_handle *h, int32_t n_views, const oct_view *views)
 {
-    (void)h;
-    (void)n_views;
-    (void)views;
-    return 0;
+    if (!h || n_views < 0 || (n_views && !views)) return 0;
+    size_t total = 0;
+    for (int i = 0; i < n_views; i++) {
+        if (views[i].width < 1 || views[i].height < 1 || !(views[i].step > 0.0f)) return 0;
+        total += view_ckpt_bytes(h, views[i]);
+    }
+    return total;
 }
 
 static int build_view(oct_handle *h, const oct_view &v, float *image, DevView &dv)
@@ -786,22 +850,29 @@ int render_views(oct_handle *h, int32_t n_views, const oct_view *views, float *c
 {
     if (!h) return OCT_EINVAL;
     if (n_views < 0 || (n_views > 0 && (!views || !images))) return fail(h, OCT_EINVAL, "bad view list");
-    (void)ckpt_ws;
     HIPCHK(h, hipSetDevice(h->device));
     hipStream_t s = (hipStream_t)stream;
     std::vector<DevView> dvs((size_t)n_views);
     std::vector<WgItem> items;
+    size_t ck_off = 0;
     for (int i = 0; i < n_views; i++) {
         int rc = build_view(h, views[i], images[i], dvs[i]);
         if (rc) return rc;
+        if (ckpt_ws) {
+            const size_t npix = (size_t)views[i].width * views[i].height;
+            dvs[i].nseg = view_nseg(h, views[i]);
+            dvs[i].ckpt = (float *)((uint8_t *)ckpt_ws + ck_off);
+            dvs[i].nend = (int32_t *)((uint8_t *)ckpt_ws + ck_off + npix * dvs[i].nseg * 4);
+            ck_off += view_ckpt_bytes(h, views[i]);
+        }
         const int tiles = dvs[i].tiles_x * ((views[i].height + OCT_TILE - 1) / OCT_TILE);
         const int tb = std::min(views[i].tile_begin, tiles);
         const int te = views[i].tile_count < 0 ? tiles : std::min(tiles, tb + views[i].tile_count);
-        for (int t = tb; t < te; t += 4) {
+        for (int t = tb; t < te; t += kRenderTilesPerWg) {
             WgItem w{};
             w.view = i;
             w.tile0 = t;
-            w.ntiles = std::min(4, te - t);
+            w.ntiles = std::min(kRenderTilesPerWg, te - t);
             items.push_back(w);
         }
     }
@@ -839,14 +910,85 @@ int render_views_backward(oct_handle *h, int32_t n_views, const oct_view *views,
                           const float *const *dL_dimages, const void *ckpt_ws, float *dL_dctrl,
                           float *dL_dvoxels, void *stream)
 {
-    (void)n_views;
-    (void)views;
-    (void)dL_dimages;
-    (void)ckpt_ws;
-    (void)dL_dctrl;
-    (void)dL_dvoxels;
-    (void)stream;
-    return fail(h, OCT_EINVAL, "render_views_backward: not available in this build");
+    if (!h) return OCT_EINVAL;
+    if (n_views < 1 || !views || !dL_dimages || !ckpt_ws || !dL_dctrl)
+        return fail(h, OCT_EINVAL, "backward needs views, dL/dimages, the forward workspace and dL/dctrl");
+    const VolGeom &g = h->g;
+    if (dL_dvoxels) {
+        // voxel gradients flow through trilinear weights of level-0 bricks only
+        for (int i = 0; i < n_views; i++)
+            if (views[i].lod != 0) return fail(h, OCT_EINVAL, "voxel gradients need lod 0 views");
+        const int G = g.grid[0];
+        for (int z = 0; z < G; z++)
+            for (int y = 0; y < G; y++)
+                for (int x = 0; x < G; x++) {
+                    const HCell &c = h->cells[cell_index(g, 0, x, y, z)];
+                    if (c.inside && !(c.exists && c.state == kBrickState && c.dev_kind == kBrick))
+                        return fail(h, OCT_EINVAL,
+                                    "voxel gradients need every level-0 node to hold a current brick "
+                                    "(threshold 0, everything inserted and uploaded)");
+                }
+    }
+    HIPCHK(h, hipSetDevice(h->device));
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<DevView> dvs((size_t)n_views);
+    std::vector<WgItem> items;
+    size_t ck_off = 0;
+    const size_t dlut_floats = (size_t)g.C * 256 * 4;
+    for (int i = 0; i < n_views; i++) {
+        int rc = build_view(h, views[i], (float *)dL_dimages[i], dvs[i]);
+        if (rc) return rc;
+        const size_t npix = (size_t)views[i].width * views[i].height;
+        dvs[i].image = nullptr;
+        dvs[i].dimg = dL_dimages[i];
+        dvs[i].nseg = view_nseg(h, views[i]);
+        dvs[i].ckpt = (float *)((uint8_t *)ckpt_ws + ck_off);
+        dvs[i].nend = (int32_t *)((uint8_t *)ckpt_ws + ck_off + npix * dvs[i].nseg * 4);
+        ck_off += view_ckpt_bytes(h, views[i]);
+        const int tiles = dvs[i].tiles_x * ((views[i].height + OCT_TILE - 1) / OCT_TILE);
+        const int tb = std::min(views[i].tile_begin, tiles);
+        const int te = views[i].tile_count < 0 ? tiles : std::min(tiles, tb + views[i].tile_count);
+        for (int t = tb; t < te; t += kRenderTilesPerWg) {
+            WgItem w{};
+            w.view = i;
+            w.tile0 = t;
+            w.ntiles = std::min(kRenderTilesPerWg, te - t);
+            items.push_back(w);
+        }
+    }
+    // device temporaries: per-view table gradients, then the replay scratch
+    const size_t dl_bytes = ((size_t)n_views * dlut_floats * 4 + 255) & ~(size_t)255;
+    const size_t scr_bytes = items.size() * (size_t)kRenderTilesPerWg * 64 * kCkptStride * 4;
+    if (dl_bytes + scr_bytes > h->bw_tmp_cap) {
+        HIPCHK(h, hipStreamSynchronize(s));
+        if (h->bw_tmp) HIPCHK(h, hipFree(h->bw_tmp));
+        h->bw_tmp = nullptr;
+        h->bw_tmp_cap = 0;
+        HIPCHK(h, hipMalloc(&h->bw_tmp, dl_bytes + scr_bytes));
+        h->bw_tmp_cap = dl_bytes + scr_bytes;
+    }
+    float *dlut = (float *)h->bw_tmp;
+    for (int i = 0; i < n_views; i++) dvs[i].dlut = dlut + (size_t)i * dlut_floats;
+    HIPCHK(h, launch_fill_f32(dlut, (int64_t)n_views * dlut_floats, 0.0f, s));
+
+    const size_t v_bytes = dvs.size() * sizeof(DevView);
+    const size_t i_off = (v_bytes + 255) & ~(size_t)255;
+    const size_t i_bytes = items.size() * sizeof(WgItem);
+    RenderSlot &rs = h->rs[h->next_rs];
+    h->next_rs = (h->next_rs + 1) % kRenderSlots;
+    int rc = stage_reserve(h, rs.st, i_off + i_bytes);
+    if (rc) return rc;
+    uint8_t *hp = (uint8_t *)rs.st.host;
+    std::memcpy(hp, dvs.data(), v_bytes);
+    std::memcpy(hp + i_off, items.data(), i_bytes);
+    HIPCHK(h, hipMemcpyAsync(rs.st.dev, hp, i_off + i_bytes, hipMemcpyHostToDevice, s));
+    uint8_t *dp = (uint8_t *)rs.st.dev;
+    HIPCHK(h, launch_render_backward(g, h->table, h->pool, h->brick_bytes, (const DevView *)dp,
+                                     (const WgItem *)(dp + i_off), (int)items.size(),
+                                     (float *)((uint8_t *)h->bw_tmp + dl_bytes), dL_dvoxels, s));
+    HIPCHK(h, launch_lut_to_ctrl((const DevView *)dp, n_views, g.C, dL_dctrl, s));
+    HIPCHK(h, hipEventRecord(rs.st.ev, s));
+    return OCT_OK;
 }
 
 int octree_dump_canonical(oct_handle *h, void *buf, size_t cap, size_t *needed)

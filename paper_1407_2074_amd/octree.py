@@ -209,6 +209,20 @@ class Octree:
             return images, {k: getattr(rs, k) for k, _ in RenderStats._fields_}
         return images
 
+    def ckpt_bytes(self, views) -> int:
+        """Bytes of the checkpoint workspace a differentiable render of these views needs."""
+        ov = (OctView * len(views))(*[to_oct_view(v) for v in views])
+        return int(lib.render_ckpt_bytes(self.h, len(views), ov))
+
+    def render_backward(self, views, dL_dimages, ckpt, dctrl, dvox=None, stream=None):
+        """Accumulate dL/dctrl [n][C][8][4] (and dL/dvoxel [C][Dz][Dy][Dx]) for the loss whose
+        image gradients are dL_dimages, using the workspace of the forward render."""
+        ov = (OctView * len(views))(*[to_oct_view(v) for v in views])
+        gp = (ct.c_void_p * len(views))(*[g.data_ptr() for g in dL_dimages])
+        self._check(lib.render_views_backward(
+            self.h, len(views), ov, gp, ct.c_void_p(ckpt.data_ptr()), ct.c_void_p(dctrl.data_ptr()),
+            ct.c_void_p(dvox.data_ptr()) if dvox is not None else None, _stream(stream)))
+
     def dump(self) -> bytes:
         need = ct.c_size_t()
         lib.octree_dump_canonical(self.h, None, 0, ct.byref(need))
