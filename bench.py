@@ -47,6 +47,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run a plain device copy of this size (counter calibration)")
+    ap.add_argument("--workload", default="stream", choices=["stream", "adjoint", "serve", "views"],
+                    help="stream: streamed build+render (default); adjoint: 256^3 f32 forward + "
+                         "adjoint at 512x512; serve: Poisson request mix; views: 64 views of "
+                         "the 64^3 volume in one launch vs one launch per view")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
@@ -58,6 +62,10 @@ def main():
 
     from paper_1407_2074_amd import synth
     from paper_1407_2074_amd.octree import Octree
+
+    if args.workload != "stream":
+        {"adjoint": bench_adjoint, "serve": bench_serve, "views": bench_views}[args.workload](args)
+        return
 
     cfg = CFG[args.config]
     dims, C, M = cfg["dims"], cfg["C"], cfg["M"]
@@ -160,7 +168,7 @@ def main():
         import oracle
         full = np.full((dims[2], dims[1], dims[0]), (1 << C) - 1, np.uint8)
         ref = oracle.Tree(vol, full, M, background=0, threshold=cfg["thr"])
-        row_step = 4 if args.config == 2 else 1
+        row_step = 2 if args.config == 2 else 1
         tc = time.perf_counter()
         img_ref, ns = ref.render_rows(view, 0, row_step)
         dt = time.perf_counter() - tc
@@ -174,6 +182,153 @@ def main():
                       f"{cfg['width']}x{cfg['height']} frame on the fully built octree "
                       f"({pos} positions, {dt:.2f}s; oracle build excluded)"}
         out["final_frame_max_abs_err_vs_oracle_rows"] = err
+    print(json.dumps(out), flush=True)
+
+
+def _sync_time(fn, reps):
+    import torch
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t) / reps
+
+
+def bench_adjoint(args):
+    """256^3 x 3 f32 (u16 * 2^-16), 64^3 bricks, 512x512 at LOD 0, threshold 0: differentiable
+    forward (with checkpoints) and adjoint of an L2 loss against a target rendered with
+    perturbed transfer functions."""
+    import numpy as np
+    import torch
+
+    from paper_1407_2074_amd import synth
+    from paper_1407_2074_amd.octree import Octree
+    dims, C, M = (256, 256, 256), 3, 64
+    vol = synth.gen_volume(dims, C, seed=4, n_blobs=2000, dtype="f32")
+    t = Octree(dims, C, M, "f32", 0.0, 0.0)
+    t.insert_block(-1, (0, 0, 0), torch.from_numpy(vol).cuda())
+    t.upload()
+    v = synth.make_view(dims, C, 4, az=30.0, el=20.0, width=512, height=512, lod=0, dtype="f32")
+    tv = synth.make_view(dims, C, 4, az=30.0, el=20.0, width=512, height=512, lod=0, dtype="f32")
+    rng = np.random.default_rng(4 * 1000 + 300)
+    tv.tf_rgba = np.clip(tv.tf_rgba + rng.normal(0, 0.05, tv.tf_rgba.shape), 0, 1).astype(np.float32)
+    (tgt,) = t.render([tv])
+    ck = torch.empty(t.ckpt_bytes([v]), dtype=torch.uint8, device="cuda")
+    img = torch.empty((512, 512, 4), dtype=torch.float32, device="cuda")
+    dctrl = torch.zeros((1, C, 8, 4), dtype=torch.float32, device="cuda")
+    dvox = torch.zeros((C, 256, 256, 256), dtype=torch.float32, device="cuda")
+    _, st = t.render([v], images=[img], ckpt=ck, stats=True)
+
+    def fwd():
+        t.render([v], images=[img], ckpt=ck)
+
+    def bwd():
+        t.render_backward([v], [2 * (img - tgt)], ck, dctrl, dvox)
+
+    for _ in range(max(args.warmup, 1)):
+        fwd()
+        bwd()
+    tf = _sync_time(fwd, args.steps)
+    tb = _sync_time(bwd, args.steps)
+    nom, comp = st["positions_nominal"], st["positions_composited"]
+    out = {"metric": "adjoint Gsamples/s", "value": round(nom / (tf + tb) / 1e9, 3),
+           "unit": "Gsamples/s (nominal positions per forward+adjoint)", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": round((tf + tb) * 1e3, 3), "higher_is_better": True,
+           "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "256^3x3 f32, 64^3 bricks, 512x512, LOD 0, L2 loss vs "
+                                  "perturbed-TF target; forward with checkpoints + adjoint"},
+           "forward_ms": round(tf * 1e3, 3), "adjoint_ms": round(tb * 1e3, 3),
+           "forward_gsamples_per_s": round(comp / tf / 1e9, 3),
+           "adjoint_gsamples_per_s": round(nom / tb / 1e9, 3),
+           "positions_nominal": nom, "positions_composited": comp,
+           "voxel_atomics_per_s": round(nom * C * 8 / tb / 1e9, 2)}
+    print(json.dumps(out), flush=True)
+
+
+def bench_serve(args):
+    """Serving: the 512x512x256 streamed-config octree resident; Poisson requests (200/s) with
+    image sizes uniform in {256, 512, 1024, 2048}^2, random orbits, per-request TFs and 0-3
+    clipping planes; framebuffer cap 2 GB."""
+    import numpy as np
+    import torch
+
+    from paper_1407_2074_amd import synth
+    from paper_1407_2074_amd.octree import Octree
+    from paper_1407_2074_amd.serving import Server, poisson_requests
+    dims, C, M = (512, 512, 256), 3, 32
+    vol = synth.gen_volume(dims, C, seed=2, n_blobs=2000)
+    t = Octree(dims, C, M, "u16", 0, 205)
+    t.insert_block(-1, (0, 0, 0), torch.from_numpy(vol.view(np.int16)).cuda())
+    t.upload()
+    n = max(args.steps, 1) * 40
+    reqs = poisson_requests(dims, C, n, rate=200.0, seed=5)
+    # positions per request, counted once (deterministic), not part of the timed run
+    pos = 0
+    for r in reqs:
+        _, st = t.render([r.view], stats=True)
+        pos += st["positions_composited"]
+    warm = poisson_requests(dims, C, 8, rate=1e6, seed=55)
+    Server(t).run(warm, realtime=False)
+    st = Server(t).run(reqs, realtime=True)
+    closed = Server(t).run(poisson_requests(dims, C, n, rate=1e9, seed=5), realtime=False)
+    alone = 0.0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for r in reqs:
+        t.render([r.view])
+    torch.cuda.synchronize()
+    alone = time.perf_counter() - t0
+    out = {"metric": "serving requests/s, p50/p99 latency", "value": round(st.requests_per_s, 2),
+           "unit": "requests/s", "n_gpus": 1, "higher_is_better": True, "data": "synthetic",
+           "config": {"workload": f"{n} Poisson requests at 200/s, sizes {{256..2048}}^2, "
+                                  "512x512x256x3 octree resident"},
+           "offered_rate": 200.0, "latency_p50_ms": round(st.latency_p50_ms, 2),
+           "latency_p99_ms": round(st.latency_p99_ms, 2),
+           "gsamples_per_s": round(pos / st.makespan_s / 1e9, 3),
+           "closed_loop_requests_per_s": round(closed.requests_per_s, 2),
+           "closed_loop_gsamples_per_s": round(pos / closed.makespan_s / 1e9, 3),
+           "one_view_per_launch_gsamples_per_s": round(pos / alone / 1e9, 3),
+           "launches": st.launches, "max_in_flight": st.max_in_flight,
+           "max_fb_bytes": st.max_fb_bytes_in_use}
+    print(json.dumps(out), flush=True)
+
+
+def bench_views(args):
+    """64 views (orbit) of the 64^3 x 3 volume at 128x128 in one launch vs one launch each."""
+    import numpy as np
+    import torch
+
+    from paper_1407_2074_amd import synth
+    from paper_1407_2074_amd.octree import Octree
+    dims, C, M = (64, 64, 64), 3, 16
+    vol = synth.gen_volume(dims, C, seed=1, n_blobs=20)
+    t = Octree(dims, C, M, "u16", 0, 205)
+    t.insert_block(-1, (0, 0, 0), vol)
+    t.upload()
+    views = [synth.make_view(dims, C, 1, az=360.0 * i / 64, el=20.0, width=128, height=128,
+                             clips=[(1.0, 0.0, 0.0, 24.0)]) for i in range(64)]
+    imgs = [torch.empty((128, 128, 4), dtype=torch.float32, device="cuda") for _ in views]
+    _, st = t.render(views, images=imgs, stats=True)
+    for _ in range(3):
+        t.render(views, images=imgs)
+    tb = _sync_time(lambda: t.render(views, images=imgs), max(args.steps, 10))
+
+    def single():
+        for v, im in zip(views, imgs):
+            t.render([v], images=[im])
+
+    single()
+    ts = _sync_time(single, max(args.steps, 10))
+    comp = st["positions_composited"]
+    out = {"metric": "Gsamples/s, 64 views of 64^3 x 3 at 128x128", "value": round(comp / tb / 1e9, 3),
+           "unit": "Gsamples/s", "n_gpus": 1, "higher_is_better": True, "data": "synthetic",
+           "config": {"workload": "64 orbit views, 128x128, clip x >= 24, LOD 0, thr 205"},
+           "batched_us_per_launch": round(tb * 1e6, 1), "us_per_frame": round(tb * 1e6 / 64, 2),
+           "one_view_per_launch_us_per_frame": round(ts * 1e6 / 64, 2),
+           "one_view_per_launch_gsamples_per_s": round(comp / ts / 1e9, 3),
+           "positions_composited": comp}
     print(json.dumps(out), flush=True)
 
 

@@ -62,8 +62,17 @@ typedef struct {
     double background;          /* value of not-yet-inserted voxels; an integer for u16   */
     double homog_threshold;     /* a node is homogeneous when max-min < threshold in every
                                    channel (strict); 0 keeps every brick                  */
-    uint64_t device_pool_bytes; /* cap of the device brick pool; 0 = room for every brick */
-    int32_t reserved[4];        /* must be 0                                              */
+    uint64_t device_pool_bytes; /* cap of the device brick pool; 0 = room for every brick.
+                                   With a cap, bricks are paged in on request ("Data
+                                   Transfer"): renders flag the brick nodes they used and
+                                   the ones they needed but found missing (sampled with
+                                   their AVG meanwhile); brick_pool_upload reads the flags
+                                   and replaces least-recently-used slots, coarser levels
+                                   first                                                  */
+    int32_t master_on_host;     /* 1: the full-resolution mipmap lives in pinned host
+                                   memory (read by the kernels over the host link) instead
+                                   of HBM                                                 */
+    int32_t reserved[3];        /* must be 0                                              */
 } oct_create_params;
 
 /* One render request (Algorithm 1 and "Basic Ray-Casting").  Pinhole camera with square
@@ -92,10 +101,12 @@ typedef struct {
 
 typedef struct {
     uint64_t bricks_gathered;   /* bordered bricks (re)built by this call                  */
-    uint64_t bricks_resident;   /* brick nodes with a device slot after the call           */
+    uint64_t bricks_resident;   /* brick nodes with a current brick after the call         */
     uint64_t bricks_total;      /* brick nodes in the octree                               */
     uint64_t nodes_changed;     /* node-table entries rewritten (change events applied)    */
     uint64_t bytes_written;     /* device bytes written for bricks and node entries        */
+    uint64_t requests_seen;     /* missing bricks the renders since the last call asked for */
+    uint64_t evictions;         /* resident bricks replaced by this call                   */
 } oct_upload_stats;
 
 typedef struct {
@@ -182,8 +193,10 @@ int render_views_backward(oct_handle *h, int32_t n_views, const oct_view *views,
  * then z, y, x: int32 level, bx, by, bz, state (0 empty, 1 homogeneous leaf, 2 homogeneous
  * with children, 3 brick), flags (1 has children, 2 complete, 4 populated), 0, 0; float64
  * avg[4], bmin[4], bmax[4], smin[4], smax[4]; then the bordered (M+2)^3 brick of every brick
- * node in record order, channel-interleaved [z][y][x][C] in the dtype.  With buf == NULL or
- * cap too small only *needed is set and OCT_ERANGE returned. */
+ * node in record order, channel-interleaved [z][y][x][C] in the dtype.  Flag 8 marks a brick
+ * node whose brick is resident in the pool (renders interpolate it; a non-resident one is
+ * sampled with its AVG).  Bricks that are not resident are gathered into a spare slot for
+ * the dump.  With buf == NULL or cap too small only *needed is set and OCT_ERANGE returned. */
 int octree_dump_canonical(oct_handle *h, void *buf, size_t cap, size_t *needed);
 
 /* Copies mipmap level `level` (planar [C][ez][ey][ex], dtype) to host memory `out` of `cap`

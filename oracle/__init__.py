@@ -18,7 +18,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 
 MAXC = 4
 ST_NONE, ST_EMPTY, ST_HOMOG_LEAF, ST_HOMOG, ST_BRICK = -1, 0, 1, 2, 3
-F_HAS_CHILDREN, F_COMPLETE, F_POPULATED = 1, 2, 4
+F_HAS_CHILDREN, F_COMPLETE, F_POPULATED, F_RESIDENT = 1, 2, 4, 8
 
 
 def num_threads() -> int:
@@ -77,6 +77,8 @@ def lib():
         L.orc_num_threads.restype = ct.c_int
         L.orc_node_info.argtypes = [ct.c_void_p, ct.c_int, ct.c_int, ct.c_int, ct.c_int,
                                     ct.c_void_p, ct.c_void_p, ct.c_void_p]
+        L.orc_set_nonresident.argtypes = [ct.c_void_p, ct.c_int, ct.c_int, ct.c_int, ct.c_int,
+                                          ct.c_int]
         _lib = L
     return _lib
 
@@ -162,6 +164,13 @@ class Tree:
         avg = np.zeros(MAXC, np.float64)
         assert lib().orc_node_info(self.h, L, bx, by, bz, _ptr(st), _ptr(fl), _ptr(avg)) == 0
         return int(st[0]), int(fl[0]), avg[:self.C].copy()
+
+    def set_nonresident(self, nodes, nonresident: bool = True):
+        """Mark brick nodes (level, bx, by, bz) whose brick the renderer does not have: they
+        are sampled with their AVG."""
+        for (L, bx, by, bz) in nodes:
+            assert lib().orc_set_nonresident(self.h, int(L), int(bx), int(by), int(bz),
+                                             1 if nonresident else 0) == 0
 
     def render(self, views, want_info: bool = False):
         """Images [H][W][4] float64 per view (plus nominal sample counts and ERT margins)."""

@@ -80,6 +80,7 @@ enum { ST_NONE = -1, ST_EMPTY = 0, ST_HOMOG_LEAF = 1, ST_HOMOG = 2, ST_BRICK = 3
 
 typedef struct {
     int8_t exists, populated, complete, has_children, state;
+    int8_t nonresident;    /* brick node whose brick is not in the render pool: sampled with AVG */
     double avg[ORC_MAXC], bmin[ORC_MAXC], bmax[ORC_MAXC], bsum[ORC_MAXC];
     double smin[ORC_MAXC], smax[ORC_MAXC];
     int64_t count;         /* valid level-L voxels in the node's brick */
@@ -375,7 +376,8 @@ size_t orc_dump(const orc_tree *t, void *buf, size_t cap)
                     if (!nd->exists) continue;
                     int32_t head[8] = {L, bx, by, bz, nd->state,
                                        (nd->has_children ? 1 : 0) | (nd->complete ? 2 : 0) |
-                                           (nd->populated ? 4 : 0),
+                                           (nd->populated ? 4 : 0) |
+                                           (nd->state == ST_BRICK && !nd->nonresident ? 8 : 0),
                                        0, 0};
                     memcpy(rec, head, sizeof head);
                     double *d = (double *)(rec + 32);
@@ -598,7 +600,7 @@ static void sample_geo(const orc_tree *t, int L, const float p[3], orc_sample_ge
         b[a] = (vi >> L) / M;
     }
     const orc_node *nd = node_at(t, L, b[0], b[1], b[2]);
-    g->brick = nd->exists && nd->state == ST_BRICK;
+    g->brick = nd->exists && nd->state == ST_BRICK && !nd->nonresident;
     if (!g->brick) {
         g->cidx = ((int64_t)(v[2] >> L) * e[1] + (v[1] >> L)) * e[0] + (v[0] >> L);
         return;
@@ -886,6 +888,19 @@ int orc_rays(const orc_tree *t, const orc_view *v, float *out, int32_t *lod_hit)
             lod_hit[((int64_t)j * v->width + i) * 2] = ry.L;
             lod_hit[((int64_t)j * v->width + i) * 2 + 1] = ry.hit;
         }
+    return 0;
+}
+
+/* Out-of-core rendering ("Brick Upload from RAM to GPU"): a brick node whose brick is not
+ * resident is sampled with its AVG by the renderer (Algorithm 1, the request branch).  The
+ * residency set is an input: the GPU path reports it.  The bordered bricks of resident
+ * neighbours are unaffected (R_L does not depend on residency). */
+int orc_set_nonresident(orc_tree *t, int L, int bx, int by, int bz, int nonresident)
+{
+    if (L < 0 || L > t->N) return -1;
+    int g = t->G[L];
+    if (bx < 0 || by < 0 || bz < 0 || bx >= g || by >= g || bz >= g) return -1;
+    node_at(t, L, bx, by, bz)->nonresident = (int8_t)(nonresident != 0);
     return 0;
 }
 

@@ -129,7 +129,7 @@ k_render_backward(VolGeom g, const DevCell *__restrict__ table, const uint8_t *_
     __shared__ ViewTables<C> tb;
     __shared__ float s_dlut[C][256][4];
 
-    const WgItem it = items[blockIdx.x];
+    const WgItem it = items[xcd_item(blockIdx.x, gridDim.x)];
     const DevView &V = views[it.view];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     for (int i = threadIdx.x; i < C * 256 * 4; i += kThreads) (&s_dlut[0][0][0])[i] = 0.0f;
@@ -137,8 +137,8 @@ k_render_backward(VolGeom g, const DevCell *__restrict__ table, const uint8_t *_
 
     float ulo[C], usc[C];
     for (int c = 0; c < C; c++) {
-        ulo[c] = V.ulo[c];
         usc[c] = V.uscale[c];
+        ulo[c] = -V.ulo[c] * usc[c];   // table coordinate u = s * usc + ulo
     }
     const float step = V.step;
     float *wscr = scratch + ((int64_t)blockIdx.x * kThreads + wave * 64) * kCkptStride;

@@ -229,14 +229,18 @@ k_stats_fold(int n, int nsub, int C, const StatPart *part, CellStat *out)
 // Change events ("Incremental Octree Updates on the GPU"): rewrite the listed node-table
 // entries.  The bounds lo/hi are recomputed afterwards by k_ranges.
 __global__ void __launch_bounds__(kThreads)
-k_apply_deltas(DevCell *table, const CellDelta *d, int n)
+k_apply_deltas(DevCell *table, float *miss_range, const CellDelta *d, int n)
 {
     const int i = blockIdx.x * kThreads + threadIdx.x;
     if (i >= n) return;
     DevCell &c = table[d[i].index];
     c.kind = d[i].kind;
     c.slot = d[i].slot;
-    for (int k = 0; k < 4; k++) c.avg[k] = d[i].avg[k];
+    for (int k = 0; k < 4; k++) {
+        c.avg[k] = d[i].avg[k];
+        miss_range[(int64_t)d[i].index * 8 + k] = d[i].lo[k];
+        miss_range[(int64_t)d[i].index * 8 + 4 + k] = d[i].hi[k];
+    }
 }
 
 // ---------------------------------------------------------------------------------------
@@ -328,10 +332,12 @@ k_gather(VolGeom g, const T *master, const DevCell *table, uint8_t *pool, uint64
 
 // ---------------------------------------------------------------------------------------
 // Skip bounds, bottom-up one level per launch: a cell's [lo, hi] covers its own sampled
-// values (bordered-brick range for a resident brick, the AVG otherwise) and those of its
-// eight children, so any ancestor whose range maps to zero opacity is empty at every LOD.
+// values (bordered-brick range for a resident brick, a bound of the brick's values for a
+// missing one -- so a missing brick is still requested unless it is surely empty -- and the
+// AVG otherwise) and those of its eight children, so any ancestor whose range maps to zero
+// opacity is empty at every LOD.
 __global__ void __launch_bounds__(kThreads)
-k_ranges(VolGeom g, DevCell *table, const float *slot_range, int L)
+k_ranges(VolGeom g, DevCell *table, const float *slot_range, const float *miss_range, int L)
 {
     const int G = g.grid[L];
     const int64_t n = (int64_t)G * G * G;
@@ -343,6 +349,10 @@ k_ranges(VolGeom g, DevCell *table, const float *slot_range, int L)
         if (c.kind == kBrick) {
             lo[k] = slot_range[(int64_t)c.slot * 8 + k];
             hi[k] = slot_range[(int64_t)c.slot * 8 + 4 + k];
+        } else if (c.kind == kBrickMissing) {
+            const int64_t ci = g.cell_off[L] + i;
+            lo[k] = fminf(c.avg[k], miss_range[ci * 8 + k]);
+            hi[k] = fmaxf(c.avg[k], miss_range[ci * 8 + 4 + k]);
         } else {
             lo[k] = hi[k] = c.avg[k];
         }
@@ -429,11 +439,12 @@ hipError_t launch_stats(const VolGeom &g, const void *master, const uint8_t *mas
     return hipGetLastError();
 }
 
-hipError_t launch_apply_deltas(DevCell *table, const CellDelta *d, int n, hipStream_t s)
+hipError_t launch_apply_deltas(DevCell *table, float *miss_range, const CellDelta *d, int n,
+                               hipStream_t s)
 {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_apply_deltas, dim3(ceil_div(n, kThreads)), dim3(kThreads), 0, s, table, d,
-                       n);
+    hipLaunchKernelGGL(k_apply_deltas, dim3(ceil_div(n, kThreads)), dim3(kThreads), 0, s, table,
+                       miss_range, d, n);
     return hipGetLastError();
 }
 
@@ -452,16 +463,25 @@ hipError_t launch_gather(const VolGeom &g, const void *master, const DevCell *ta
     return hipGetLastError();
 }
 
-hipError_t launch_ranges(const VolGeom &g, DevCell *table, const float *slot_range, hipStream_t s)
+hipError_t launch_ranges(const VolGeom &g, DevCell *table, const float *slot_range,
+                         const float *miss_range, hipStream_t s)
 {
     for (int L = 0; L <= g.N; L++) {
         const int64_t n = (int64_t)g.grid[L] * g.grid[L] * g.grid[L];
         hipLaunchKernelGGL(k_ranges, dim3(ceil_div(n, kThreads)), dim3(kThreads), 0, s, g, table,
-                           slot_range, L);
+                           slot_range, miss_range, L);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
+}
+
+hipError_t launch_fill_u8(uint8_t *p, int64_t n, uint8_t v, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill<uint8_t>, dim3((unsigned)std::min<int64_t>(ceil_div(n, kThreads), 65536)),
+                       dim3(kThreads), 0, s, p, n, v);
+    return hipGetLastError();
 }
 
 hipError_t launch_fill_f32(float *p, int64_t n, float v, hipStream_t s)

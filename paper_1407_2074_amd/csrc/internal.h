@@ -95,7 +95,9 @@ struct CellDelta {      // one change event applied to the node table
     int32_t slot;
     int32_t pad;
     float avg[4];
+    float lo[4], hi[4];  // kBrickMissing: bound of the brick's values (conservative skip range)
 };
+static_assert(sizeof(CellDelta) == 64, "CellDelta layout");
 
 struct RenderCounters {
     unsigned long long rays, nominal, composited, trilinear;
@@ -111,22 +113,26 @@ size_t stats_scratch_bytes(const VolGeom &g, int n);
 hipError_t launch_stats(const VolGeom &g, const void *master, const uint8_t *mask,
                         const int32_t *cells /* (level, bx, by, bz) x n */, int n,
                         void *scratch /* stats_scratch_bytes */, CellStat *out, hipStream_t s);
-hipError_t launch_apply_deltas(DevCell *table, const CellDelta *d, int n, hipStream_t s);
+hipError_t launch_apply_deltas(DevCell *table, float *miss_range, const CellDelta *d, int n,
+                               hipStream_t s);
 hipError_t launch_gather(const VolGeom &g, const void *master, const DevCell *table,
                          void *pool, uint64_t brick_bytes, const BrickJob *jobs, int n,
                          float *slot_range, float background, hipStream_t s);
 hipError_t launch_ranges(const VolGeom &g, DevCell *table, const float *slot_range,
-                         hipStream_t s);
+                         const float *miss_range, hipStream_t s);
 hipError_t launch_clear(const VolGeom &g, void *master, uint8_t *mask, double background,
                         hipStream_t s);
 hipError_t launch_fill_f32(float *p, int64_t n, float v, hipStream_t s);
+hipError_t launch_fill_u8(uint8_t *p, int64_t n, uint8_t v, hipStream_t s);
 
 // ---- launchers (render path) ----
 constexpr int kCkptStride = 64;   // positions per transmittance checkpoint segment
 
+// flags (may be NULL): per node-table cell, set to 1 when a render interpolated the cell's
+// resident brick and to 2 when it needed the cell's brick but found it missing.
 hipError_t launch_render(const VolGeom &g, const DevCell *table, const void *pool,
                          uint64_t brick_bytes, const DevView *views, const WgItem *items,
-                         int n_items, RenderCounters *counters, hipStream_t s);
+                         int n_items, RenderCounters *counters, uint8_t *flags, hipStream_t s);
 // Adjoint: scratch holds kCkptStride floats per lane of the launch (n_items * 512 lanes).
 hipError_t launch_render_backward(const VolGeom &g, const DevCell *table, const void *pool,
                                   uint64_t brick_bytes, const DevView *views, const WgItem *items,

@@ -78,16 +78,18 @@ __device__ inline void build_tables(const DevView &V, ViewTables<C> &tb)
     __syncthreads();
 }
 
+// Table coordinate of intensity s: u = s * usc + ub with usc = 255 / (hi - lo), ub = -lo * usc.
+
 // True when every value in [lo, hi] classifies to zero opacity in every channel: the table
 // entries that interpolation may touch (with one entry of margin each side) are all zero.
 template <int C>
-__device__ inline bool range_transparent(const float *lo, const float *hi, const float *ulo,
+__device__ inline bool range_transparent(const float *lo, const float *hi, const float *ub,
                                          const float *usc, const int (*pref)[257])
 {
 #pragma unroll
     for (int c = 0; c < C; c++) {
-        float ul = (lo[c] - ulo[c]) * usc[c];
-        float uh = (hi[c] - ulo[c]) * usc[c];
+        float ul = __builtin_fmaf(lo[c], usc[c], ub[c]);
+        float uh = __builtin_fmaf(hi[c], usc[c], ub[c]);
         ul = fminf(fmaxf(ul, 0.0f), 255.0f);
         uh = fminf(fmaxf(uh, 0.0f), 255.0f);
         const int il = max((int)ul - 1, 0);
@@ -98,12 +100,23 @@ __device__ inline bool range_transparent(const float *lo, const float *hi, const
 }
 
 template <int C>
-__device__ inline bool cell_transparent(const DevCell &cell, const float *ulo, const float *usc,
+__device__ inline bool cell_transparent(const DevCell &cell, const float *ub, const float *usc,
                                         const int (*pref)[257])
 {
     const float4 clo = *(const float4 *)cell.lo, chi = *(const float4 *)cell.hi;
     const float lo4[4] = {clo.x, clo.y, clo.z, clo.w}, hi4[4] = {chi.x, chi.y, chi.z, chi.w};
-    return range_transparent<C>(lo4, hi4, ulo, usc, pref);
+    return range_transparent<C>(lo4, hi4, ub, usc, pref);
+}
+
+// Workgroup -> work item: the dispatcher deals workgroups round-robin to the 8 XCDs (each with
+// its own L2), so item blocks are reassigned to make XCD x process one contiguous run of items
+// (a band of neighbouring tiles that share bricks) instead of every 8th item.
+__device__ inline int xcd_item(int bid, int n)
+{
+    constexpr int kXcd = 8;
+    const int q = n / kXcd, r = n % kXcd;
+    const int x = bid % kXcd, local = bid / kXcd;
+    return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + local;
 }
 
 struct Ray {
@@ -187,15 +200,16 @@ struct Classified {
     bool inside;     // u was not clamped
 };
 
-__device__ inline Classified classify(float s, float ulo, float usc, const float4 (*lut)[2])
+// u is clamped to [0, 255-] (the largest float below 255), so cell i = trunc(u) <= 254 and
+// the fraction is u - i; at the top end entry 254 + (1 - 2^-16) * slope replaces entry 255.
+__device__ inline Classified classify(float s, float ub, float usc, const float4 (*lut)[2])
 {
     Classified r;
-    const float u0 = (s - ulo) * usc;
+    const float u0 = __builtin_fmaf(s, usc, ub);
     r.inside = u0 > 0.0f && u0 < 255.0f;
-    const float u = fminf(fmaxf(u0, 0.0f), 255.0f);
-    const float fi = fminf(floorf(u), 254.0f);
-    r.fr = u - fi;
-    r.i = (int)fi;
+    const float u = __builtin_amdgcn_fmed3f(u0, 0.0f, 254.99998474121094f);
+    r.i = (int)u;
+    r.fr = __builtin_amdgcn_fractf(u);
     r.e0 = lut[r.i][0];
     r.de = lut[r.i][1];
     return r;

@@ -19,14 +19,14 @@ namespace {
 constexpr int kThreads = 512;   // 8 waves = 8 tiles of one view share the LDS tables
 
 template <typename T, int C>
-__global__ void __launch_bounds__(kThreads)
-k_render(VolGeom g, const DevCell *__restrict__ table, const uint8_t *__restrict__ pool,
-         uint64_t brick_bytes, const DevView *__restrict__ views, const WgItem *__restrict__ items,
-         RenderCounters *counters)
+__device__ __forceinline__ void
+render_body(const VolGeom &g, const DevCell *__restrict__ table, const uint8_t *__restrict__ pool,
+            uint64_t brick_bytes, const DevView *__restrict__ views,
+            const WgItem *__restrict__ items, RenderCounters *counters, uint8_t *flags,
+            ViewTables<C> &tb)
 {
-    __shared__ ViewTables<C> tb;
 
-    const WgItem it = items[blockIdx.x];
+    const WgItem it = items[xcd_item(blockIdx.x, gridDim.x)];
     const DevView &V = views[it.view];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     build_tables<C>(V, tb);
@@ -36,8 +36,8 @@ k_render(VolGeom g, const DevCell *__restrict__ table, const uint8_t *__restrict
     float ulo[C], usc[C];
 #pragma unroll
     for (int c = 0; c < C; c++) {
-        ulo[c] = V.ulo[c];
         usc[c] = V.uscale[c];
+        ulo[c] = -V.ulo[c] * usc[c];   // table coordinate u = s * usc + ulo
     }
     const float step = V.step;
     const float ert_T = V.ert < 1.0f ? 1.0f - V.ert : -1.0f;
@@ -109,7 +109,8 @@ k_render(VolGeom g, const DevCell *__restrict__ table, const uint8_t *__restrict
                     cy = v[1] / csz;
                     cz = v[2] / csz;
                 }
-                const DevCell &cell = table[coff + (cz * G + cy) * G + cx];
+                const int cidx = coff + (cz * G + cy) * G + cx;
+                const DevCell &cell = table[cidx];
                 if (skip && cell_transparent<C>(cell, ulo, usc, tb.pref)) {
                     // widen to the largest transparent ancestor, jump to just before its exit
                     int lev = L, ax = cx, ay = cy, az = cz;
@@ -145,6 +146,7 @@ k_render(VolGeom g, const DevCell *__restrict__ table, const uint8_t *__restrict
                 blo[2] = cz * csz; bhi[2] = blo[2] + csz - 1;
                 const int2 ks = *(const int2 *)&cell.kind;
                 brick = ks.x == kBrick;
+                if (flags && ks.x != kAvg) flags[cidx] = brick ? 1 : 2;  // used / requested
                 if (brick) {
                     base = pool + (uint64_t)ks.y * brick_bytes;
                     org[0] = (float)(cx * g.M - 1);
@@ -278,18 +280,53 @@ k_render(VolGeom g, const DevCell *__restrict__ table, const uint8_t *__restrict
     }
 }
 
+// uint16 bricks fit 6 waves per SIMD in registers; float32 bricks (twice the corner data)
+// keep the compiler's choice.
+template <int C>
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(6)))
+k_render_u16(VolGeom g, const DevCell *__restrict__ table, const uint8_t *__restrict__ pool,
+             uint64_t brick_bytes, const DevView *__restrict__ views,
+             const WgItem *__restrict__ items, RenderCounters *counters, uint8_t *flags)
+{
+    __shared__ ViewTables<C> tb;
+    render_body<uint16_t, C>(g, table, pool, brick_bytes, views, items, counters, flags, tb);
+}
+
+template <int C>
+__global__ void __launch_bounds__(kThreads)
+k_render_f32(VolGeom g, const DevCell *__restrict__ table, const uint8_t *__restrict__ pool,
+             uint64_t brick_bytes, const DevView *__restrict__ views,
+             const WgItem *__restrict__ items, RenderCounters *counters, uint8_t *flags)
+{
+    __shared__ ViewTables<C> tb;
+    render_body<float, C>(g, table, pool, brick_bytes, views, items, counters, flags, tb);
+}
+
+template <typename T, int C>
+void launch_c(const dim3 &grid, const dim3 &block, hipStream_t s, const VolGeom &g,
+              const DevCell *table, const uint8_t *p, uint64_t brick_bytes, const DevView *views,
+              const WgItem *items, RenderCounters *counters, uint8_t *flags)
+{
+    if constexpr (sizeof(T) == 2)
+        hipLaunchKernelGGL((k_render_u16<C>), grid, block, 0, s, g, table, p, brick_bytes, views,
+                           items, counters, flags);
+    else
+        hipLaunchKernelGGL((k_render_f32<C>), grid, block, 0, s, g, table, p, brick_bytes, views,
+                           items, counters, flags);
+}
+
 template <typename T>
 hipError_t launch_typed(const VolGeom &g, const DevCell *table, const void *pool,
                         uint64_t brick_bytes, const DevView *views, const WgItem *items,
-                        int n_items, RenderCounters *counters, hipStream_t s)
+                        int n_items, RenderCounters *counters, uint8_t *flags, hipStream_t s)
 {
     const dim3 grid(n_items), block(kThreads);
     const uint8_t *p = (const uint8_t *)pool;
     switch (g.C) {
-    case 1: hipLaunchKernelGGL((k_render<T, 1>), grid, block, 0, s, g, table, p, brick_bytes, views, items, counters); break;
-    case 2: hipLaunchKernelGGL((k_render<T, 2>), grid, block, 0, s, g, table, p, brick_bytes, views, items, counters); break;
-    case 3: hipLaunchKernelGGL((k_render<T, 3>), grid, block, 0, s, g, table, p, brick_bytes, views, items, counters); break;
-    default: hipLaunchKernelGGL((k_render<T, 4>), grid, block, 0, s, g, table, p, brick_bytes, views, items, counters); break;
+    case 1: launch_c<T, 1>(grid, block, s, g, table, p, brick_bytes, views, items, counters, flags); break;
+    case 2: launch_c<T, 2>(grid, block, s, g, table, p, brick_bytes, views, items, counters, flags); break;
+    case 3: launch_c<T, 3>(grid, block, s, g, table, p, brick_bytes, views, items, counters, flags); break;
+    default: launch_c<T, 4>(grid, block, s, g, table, p, brick_bytes, views, items, counters, flags); break;
     }
     return hipGetLastError();
 }
@@ -298,12 +335,14 @@ hipError_t launch_typed(const VolGeom &g, const DevCell *table, const void *pool
 
 hipError_t launch_render(const VolGeom &g, const DevCell *table, const void *pool,
                          uint64_t brick_bytes, const DevView *views, const WgItem *items,
-                         int n_items, RenderCounters *counters, hipStream_t s)
+                         int n_items, RenderCounters *counters, uint8_t *flags, hipStream_t s)
 {
     if (n_items == 0) return hipSuccess;
     if (g.dtype == 0)
-        return launch_typed<uint16_t>(g, table, pool, brick_bytes, views, items, n_items, counters, s);
-    return launch_typed<float>(g, table, pool, brick_bytes, views, items, n_items, counters, s);
+        return launch_typed<uint16_t>(g, table, pool, brick_bytes, views, items, n_items, counters,
+                                      flags, s);
+    return launch_typed<float>(g, table, pool, brick_bytes, views, items, n_items, counters, flags,
+                               s);
 }
 
 }  // namespace octrc

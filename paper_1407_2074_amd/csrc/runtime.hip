@@ -37,6 +37,7 @@ struct HCell {
     int32_t dev_kind = kAvg;     // last uploaded entry
     int32_t dev_slot = -1;
     float dev_avg[4] = {0, 0, 0, 0};
+    float dev_miss[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     bool dev_valid = false;
 };
 
@@ -81,6 +82,15 @@ struct oct_handle {
     int next_rs = 0;
     void *bw_tmp = nullptr;      // adjoint: table-gradient accumulators + replay scratch
     size_t bw_tmp_cap = 0;
+    // paging (capped pool): render flags per cell, missing-brick value bounds, LRU stamps
+    bool capped = false;
+    bool master_host = false;
+    void *master_alloc = nullptr;  // host allocation when the master lives in pinned memory
+    uint8_t *flags = nullptr;
+    uint8_t *flags_host = nullptr;
+    float *miss_range = nullptr;
+    uint64_t frame = 1;
+    std::vector<uint64_t> last_used;
     std::vector<HCell> cells;
     std::vector<int32_t> free_slots;
     std::vector<std::vector<Box>> dirty;  // per level
@@ -383,8 +393,15 @@ int octree_create(const oct_create_params *params, void *stream, oct_handle **ou
     const int S = g.M + 2;
     h->brick_bytes = ((uint64_t)S * S * S * 4 * h->esz + 255) & ~(uint64_t)255;
     h->n_slots = in_volume_cells;
-    if (params->device_pool_bytes)
+    if (params->device_pool_bytes) {
         h->n_slots = std::min<int64_t>(h->n_slots, (int64_t)(params->device_pool_bytes / h->brick_bytes));
+        h->capped = h->n_slots < in_volume_cells;
+    }
+    if (h->n_slots < 1) {
+        h->err = "device_pool_bytes holds no brick";
+        return bail(OCT_EINVAL);
+    }
+    h->master_host = params->master_on_host != 0;
     h->cells.assign((size_t)h->n_cells, HCell());
     h->dirty.assign((size_t)N + 1, std::vector<Box>());
 
@@ -397,12 +414,29 @@ int octree_create(const oct_create_params *params, void *stream, oct_handle **ou
         return OCT_OK;
     };
     int rc;
-    if ((rc = dev_alloc(&h->master, (size_t)off * h->esz))) return bail(rc);
+    if (h->master_host) {
+        // pinned host memory, mapped for the kernels (they read and write it over the link)
+        hipError_t e = hipHostMalloc(&h->master_alloc, std::max<size_t>((size_t)off * h->esz, 256),
+                                     hipHostMallocMapped);
+        if (e == hipSuccess) e = hipHostGetDevicePointer(&h->master, h->master_alloc, 0);
+        if (e != hipSuccess) {
+            h->err = std::string("pinned master: ") + hipGetErrorString(e);
+            return bail(e == hipErrorOutOfMemory ? OCT_ENOMEM : OCT_EDEVICE);
+        }
+    } else if ((rc = dev_alloc(&h->master, (size_t)off * h->esz))) {
+        return bail(rc);
+    }
     if ((rc = dev_alloc((void **)&h->mask, (size_t)g.dims[0] * g.dims[1] * g.dims[2]))) return bail(rc);
     if ((rc = dev_alloc((void **)&h->table, sizeof(DevCell) * (size_t)h->n_cells))) return bail(rc);
-    if ((rc = dev_alloc((void **)&h->pool, (size_t)h->brick_bytes * (size_t)h->n_slots))) return bail(rc);
-    if ((rc = dev_alloc((void **)&h->slot_range, sizeof(float) * 8 * (size_t)std::max<int64_t>(h->n_slots, 1))))
+    // one spare slot past the pool: canonical dumps gather non-resident bricks into it
+    if ((rc = dev_alloc((void **)&h->pool, (size_t)h->brick_bytes * (size_t)(h->n_slots + 1)))) return bail(rc);
+    if ((rc = dev_alloc((void **)&h->slot_range, sizeof(float) * 8 * (size_t)(h->n_slots + 1))))
         return bail(rc);
+    if ((rc = dev_alloc((void **)&h->flags, (size_t)h->n_cells))) return bail(rc);
+    if ((rc = dev_alloc((void **)&h->miss_range, sizeof(float) * 8 * (size_t)h->n_cells))) return bail(rc);
+    if (hipHostMalloc((void **)&h->flags_host, (size_t)h->n_cells, hipHostMallocDefault) != hipSuccess)
+        return bail(OCT_ENOMEM);
+    h->last_used.assign((size_t)h->n_cells, 0);
     if (hipEventCreateWithFlags(&h->ins_ev, hipEventDisableTiming) != hipSuccess) return bail(OCT_EDEVICE);
     if (octree_clear(h, stream) != OCT_OK) return bail(OCT_EDEVICE);
     (void)s;
@@ -415,7 +449,11 @@ int octree_destroy(oct_handle *h)
     if (!h) return OCT_EINVAL;
     (void)hipSetDevice(h->device);
     (void)hipDeviceSynchronize();
-    if (h->master) (void)hipFree(h->master);
+    if (h->master_alloc) (void)hipHostFree(h->master_alloc);
+    else if (h->master) (void)hipFree(h->master);
+    if (h->flags) (void)hipFree(h->flags);
+    if (h->flags_host) (void)hipHostFree(h->flags_host);
+    if (h->miss_range) (void)hipFree(h->miss_range);
     if (h->mask) (void)hipFree(h->mask);
     if (h->table) (void)hipFree(h->table);
     if (h->pool) (void)hipFree(h->pool);
@@ -435,7 +473,11 @@ int octree_clear(oct_handle *h, void *stream)
     HIPCHK(h, hipSetDevice(h->device));
     hipStream_t s = (hipStream_t)stream;
     HIPCHK(h, launch_clear(h->g, h->master, h->mask, h->p.background, s));
+    HIPCHK(h, launch_fill_u8(h->flags, h->n_cells, 0, s));
+    HIPCHK(h, launch_fill_f32(h->miss_range, h->n_cells * 8, h->background_f, s));
     reset_host_state(h);
+    std::fill(h->last_used.begin(), h->last_used.end(), 0);
+    h->frame = 1;
     return upload_full_table(h, s);
 }
 
@@ -566,6 +608,14 @@ int brick_pool_upload(oct_handle *h, uint64_t byte_budget, void *stream, oct_upl
     }
     const int n_stat = (int)(stat_cells.size() / 4);
 
+    // flags written by the renders since the last call (capped pool only), then cleared
+    if (h->capped) {
+        HIPCHK(h, hipMemcpyAsync(h->flags_host, h->flags, (size_t)h->n_cells, hipMemcpyDeviceToHost, s));
+        HIPCHK(h, launch_fill_u8(h->flags, h->n_cells, 0, s));
+        if (!n_stat) HIPCHK(h, hipStreamSynchronize(s));
+        // synchronised by the statistics read-back below otherwise
+    }
+
     // ---- 2. statistics of changed cells (one read-back)
     if (n_stat) {
         const size_t cl_bytes = stat_cells.size() * sizeof(int32_t);
@@ -597,6 +647,10 @@ int brick_pool_upload(oct_handle *h, uint64_t byte_budget, void *stream, oct_upl
         }
     }
 
+    if (h->capped)
+        for (int64_t i = 0; i < h->n_cells; i++)
+            if (h->flags_host[i] == 1) h->last_used[i] = h->frame;
+
     // ---- 3. states, resolved entries and slots
     recompute_states(h);
     std::vector<int32_t> new_kind((size_t)h->n_cells);
@@ -621,7 +675,9 @@ int brick_pool_upload(oct_handle *h, uint64_t byte_budget, void *stream, oct_upl
                         c.slot = -1;
                         c.needs_gather = false;
                     }
-                    if (brick && c.slot < 0 && !h->free_slots.empty()) {
+                    // an uncapped pool gives every brick node a slot; a capped one pages on
+                    // request (below)
+                    if (!h->capped && brick && c.slot < 0 && !h->free_slots.empty()) {
                         c.slot = h->free_slots.back();
                         h->free_slots.pop_back();
                         c.needs_gather = true;
@@ -643,7 +699,23 @@ int brick_pool_upload(oct_handle *h, uint64_t byte_budget, void *stream, oct_upl
     for (int64_t i = 0; i < h->n_cells; i++) changed[i] = rep_changed(i);
     std::vector<BrickJob> jobs;
     uint64_t budget_left = byte_budget ? byte_budget : UINT64_MAX;
-    uint64_t pending = 0, bricks_total = 0, resident = 0;
+    uint64_t bricks_total = 0;
+    auto push_job = [&](HCell &c, int L, int x, int y, int z, bool full, const int32_t *bb) {
+        BrickJob j{};
+        j.slot = c.slot;
+        j.level = L;
+        j.bx = x;
+        j.by = y;
+        j.bz = z;
+        j.full = full ? 1 : 0;
+        for (int a = 0; a < 3; a++) {
+            j.lo[a] = full ? 0 : bb[a];
+            j.hi[a] = full ? S - 1 : bb[3 + a];
+        }
+        jobs.push_back(j);
+        budget_left -= h->brick_bytes;
+        c.needs_gather = false;
+    };
     for (int L = g.N; L >= 0; L--) {  // coarse levels first
         const int G = g.grid[L];
         for (int z = 0; z < G; z++)
@@ -653,10 +725,7 @@ int brick_pool_upload(oct_handle *h, uint64_t byte_budget, void *stream, oct_upl
                     HCell &c = h->cells[ci];
                     if (new_kind[ci] == kAvg) continue;
                     bricks_total++;
-                    if (c.slot < 0) {
-                        pending++;
-                        continue;
-                    }
+                    if (c.slot < 0) continue;
                     // whole brick: new slot, deferred earlier, or a neighbour changed kind/AVG
                     bool full = c.needs_gather;
                     for (int dz = -1; dz <= 1 && !full; dz++)
@@ -669,51 +738,132 @@ int brick_pool_upload(oct_handle *h, uint64_t byte_budget, void *stream, oct_upl
                     const int32_t *bb = &border_box[(size_t)ci * 6];
                     const bool part = !full && bb[3] >= 0 && bb[4] >= 0 && bb[5] >= 0;
                     if (full || part) {
-                        if (budget_left >= h->brick_bytes) {
-                            budget_left -= h->brick_bytes;
-                            BrickJob j{};
-                            j.slot = c.slot;
-                            j.level = L;
-                            j.bx = x;
-                            j.by = y;
-                            j.bz = z;
-                            j.full = full ? 1 : 0;
-                            for (int a = 0; a < 3; a++) {
-                                j.lo[a] = full ? 0 : bb[a];
-                                j.hi[a] = full ? S - 1 : bb[3 + a];
-                            }
-                            jobs.push_back(j);
-                            c.needs_gather = false;
-                        } else {
-                            c.needs_gather = true;
-                        }
+                        if (budget_left >= h->brick_bytes) push_job(c, L, x, y, z, full, bb);
+                        else c.needs_gather = true;   // stale until gathered: rendered with AVG
                     }
-                    if (c.needs_gather) pending++;
-                    else {
-                        new_kind[ci] = kBrick;
-                        resident++;
-                    }
+                    if (!c.needs_gather) new_kind[ci] = kBrick;
                 }
     }
 
-    // ---- 4. change events for the node table, then the gathers, then the skip bounds
+    // ---- 4. paging ("Brick Upload from RAM to GPU"): requested bricks get slots, coarser
+    // levels first; free slots first, then slots unused by the last renders (least recently
+    // used first), and when those run out a coarser request may take a used finer brick.
+    uint64_t requests_seen = 0, evictions = 0, unserved = 0;
+    if (h->capped) {
+        std::vector<int64_t> reqs, idle, busy;
+        for (int L = g.N; L >= 0; L--) {
+            const int64_t n = (int64_t)g.grid[L] * g.grid[L] * g.grid[L];
+            for (int64_t i = 0; i < n; i++) {
+                const int64_t ci = g.cell_off[L] + i;
+                const HCell &c = h->cells[ci];
+                if (new_kind[ci] == kAvg) continue;
+                if (h->flags_host[ci] == 2 && c.slot < 0) reqs.push_back(ci);
+                if (c.slot >= 0) (h->last_used[ci] == h->frame ? busy : idle).push_back(ci);
+            }
+        }
+        requests_seen = reqs.size();
+        auto level_of = [&](int64_t ci) {
+            int L = 0;
+            while (L < g.N && ci >= g.cell_off[L + 1]) L++;
+            return L;
+        };
+        std::stable_sort(idle.begin(), idle.end(), [&](int64_t a, int64_t b) {
+            if (h->last_used[a] != h->last_used[b]) return h->last_used[a] < h->last_used[b];
+            return level_of(a) < level_of(b);
+        });
+        std::stable_sort(busy.begin(), busy.end(),
+                         [&](int64_t a, int64_t b) { return level_of(a) < level_of(b); });
+        size_t vi = 0, bi = 0;
+        for (int64_t ci : reqs) {
+            if (budget_left < h->brick_bytes) {
+                unserved++;
+                continue;
+            }
+            HCell &c = h->cells[ci];
+            const int L = level_of(ci);
+            int64_t victim = -1;
+            if (h->free_slots.empty()) {
+                if (vi < idle.size()) victim = idle[vi++];
+                else if (bi < busy.size() && level_of(busy[bi]) < L) victim = busy[bi++];
+                else {
+                    unserved++;
+                    continue;
+                }
+                HCell &v = h->cells[victim];
+                h->free_slots.push_back(v.slot);
+                v.slot = -1;
+                v.needs_gather = false;
+                new_kind[victim] = kBrickMissing;
+                evictions++;
+            }
+            c.slot = h->free_slots.back();
+            h->free_slots.pop_back();
+            const int G = g.grid[L];
+            const int64_t li = ci - g.cell_off[L];
+            push_job(c, L, (int)(li % G), (int)((li / G) % G), (int)(li / ((int64_t)G * G)), true,
+                     nullptr);
+            new_kind[ci] = kBrick;
+        }
+        h->frame++;
+    }
+
+    // value bounds of missing bricks (their skip range): the brick and its 26 neighbours
+    std::vector<float> miss((size_t)h->n_cells * 8, 0.0f);
+    uint64_t resident = 0, pending = 0;
+    for (int L = g.N; L >= 0; L--) {
+        const int G = g.grid[L];
+        for (int z = 0; z < G; z++)
+            for (int y = 0; y < G; y++)
+                for (int x = 0; x < G; x++) {
+                    const int64_t ci = cell_index(g, L, x, y, z);
+                    float *m = &miss[(size_t)ci * 8];
+                    for (int k = 0; k < 4; k++) m[k] = m[4 + k] = new_avg[(size_t)ci * 4 + k];
+                    if (new_kind[ci] == kBrick) resident++;
+                    if (new_kind[ci] != kBrickMissing) continue;
+                    if (h->cells[ci].slot >= 0) pending++;
+                    for (int dz = -1; dz <= 1; dz++)
+                        for (int dy = -1; dy <= 1; dy++)
+                            for (int dx = -1; dx <= 1; dx++) {
+                                const int nx = x + dx, ny = y + dy, nz = z + dz;
+                                if (nx < 0 || ny < 0 || nz < 0 || nx >= G || ny >= G || nz >= G) continue;
+                                const int64_t ni = cell_index(g, L, nx, ny, nz);
+                                const HCell &nc = h->cells[ni];
+                                if (!nc.inside) continue;
+                                for (int k = 0; k < C; k++) {
+                                    const float lo = new_kind[ni] != kAvg ? (float)nc.bmin[k] : new_avg[(size_t)ni * 4 + k];
+                                    const float hi = new_kind[ni] != kAvg ? (float)nc.bmax[k] : new_avg[(size_t)ni * 4 + k];
+                                    m[k] = std::min(m[k], lo);
+                                    m[4 + k] = std::max(m[4 + k], hi);
+                                }
+                            }
+                }
+    }
+
+    // ---- 5. change events for the node table, then the gathers, then the skip bounds
     std::vector<CellDelta> deltas;
     for (int64_t i = 0; i < h->n_cells; i++) {
         HCell &c = h->cells[i];
         const int32_t slot = new_kind[i] == kBrick ? c.slot : -1;
         const float *a = &new_avg[(size_t)i * 4];
+        const float *m = &miss[(size_t)i * 8];
         bool diff = !c.dev_valid || c.dev_kind != new_kind[i] || c.dev_slot != slot;
         for (int k = 0; k < 4 && !diff; k++) diff = c.dev_avg[k] != a[k];
+        for (int k = 0; k < 8 && !diff; k++) diff = c.dev_miss[k] != m[k];
         if (!diff) continue;
         CellDelta d{};
         d.index = (int32_t)i;
         d.kind = new_kind[i];
         d.slot = slot;
-        for (int k = 0; k < 4; k++) d.avg[k] = a[k];
+        for (int k = 0; k < 4; k++) {
+            d.avg[k] = a[k];
+            d.lo[k] = m[k];
+            d.hi[k] = m[4 + k];
+        }
         deltas.push_back(d);
         c.dev_kind = new_kind[i];
         c.dev_slot = slot;
         for (int k = 0; k < 4; k++) c.dev_avg[k] = a[k];
+        for (int k = 0; k < 8; k++) c.dev_miss[k] = m[k];
         c.dev_valid = true;
     }
     const size_t d_bytes = deltas.size() * sizeof(CellDelta);
@@ -726,11 +876,12 @@ int brick_pool_upload(oct_handle *h, uint64_t byte_budget, void *stream, oct_upl
         if (j_bytes) std::memcpy((uint8_t *)h->up.host + j_off, jobs.data(), j_bytes);
         HIPCHK(h, hipMemcpyAsync(h->up.dev, h->up.host, j_off + j_bytes, hipMemcpyHostToDevice, s));
         HIPCHK(h, hipEventRecord(h->up.ev, s));
-        HIPCHK(h, launch_apply_deltas(h->table, (const CellDelta *)h->up.dev, (int)deltas.size(), s));
+        HIPCHK(h, launch_apply_deltas(h->table, h->miss_range, (const CellDelta *)h->up.dev,
+                                      (int)deltas.size(), s));
         HIPCHK(h, launch_gather(g, h->master, h->table, h->pool, h->brick_bytes,
                                 (const BrickJob *)((uint8_t *)h->up.dev + j_off), (int)jobs.size(),
                                 h->slot_range, h->background_f, s));
-        HIPCHK(h, launch_ranges(g, h->table, h->slot_range, s));
+        HIPCHK(h, launch_ranges(g, h->table, h->slot_range, h->miss_range, s));
     }
     if (out) {
         out->bricks_gathered = jobs.size();
@@ -738,8 +889,11 @@ int brick_pool_upload(oct_handle *h, uint64_t byte_budget, void *stream, oct_upl
         out->bricks_total = bricks_total;
         out->nodes_changed = deltas.size();
         out->bytes_written = jobs.size() * h->brick_bytes + d_bytes;
+        out->requests_seen = requests_seen;
+        out->evictions = evictions;
     }
-    return pending ? OCT_INCOMPLETE : OCT_OK;
+    if (h->capped) return (pending || unserved) ? OCT_INCOMPLETE : OCT_OK;
+    return resident < bricks_total ? OCT_INCOMPLETE : OCT_OK;
 }
 
 // Checkpoint workspace: per view, [pixel][nseg] float32 transmittances then [pixel] int32
@@ -892,7 +1046,8 @@ int render_views(oct_handle *h, int32_t n_views, const oct_view *views, float *c
     uint8_t *dp = (uint8_t *)rs.st.dev;
     HIPCHK(h, launch_render(h->g, h->table, h->pool, h->brick_bytes, (const DevView *)dp,
                             (const WgItem *)(dp + i_off), (int)items.size(),
-                            out ? (RenderCounters *)(dp + c_off) : nullptr, s));
+                            out ? (RenderCounters *)(dp + c_off) : nullptr,
+                            h->capped ? h->flags : nullptr, s));
     if (out) {
         HIPCHK(h, hipMemcpyAsync(hp + c_off, dp + c_off, sizeof(RenderCounters), hipMemcpyDeviceToHost, s));
         HIPCHK(h, hipStreamSynchronize(s));
@@ -1031,9 +1186,10 @@ int octree_dump_canonical(oct_handle *h, void *buf, size_t cap, size_t *needed)
                 for (int x = 0; x < G; x++) {
                     const HCell &c = h->cells[cell_index(g, L, x, y, z)];
                     if (!c.exists) continue;
+                    const bool resident = c.state == kBrickState && c.dev_kind == kBrick;
                     const int32_t head[8] = {L, x, y, z, c.state,
                                              (c.has_children ? 1 : 0) | (c.complete ? 2 : 0) |
-                                                 (c.populated ? 4 : 0),
+                                                 (c.populated ? 4 : 0) | (resident ? 8 : 0),
                                              0, 0};
                     std::memcpy(rec, head, sizeof head);
                     double *d = (double *)(rec + 32);
@@ -1048,9 +1204,28 @@ int octree_dump_canonical(oct_handle *h, void *buf, size_t cap, size_t *needed)
                     }
                     rec += 192;
                     if (c.state != kBrickState) continue;
-                    if (c.slot < 0 || c.needs_gather)
-                        return fail(h, OCT_EBUSY, "a brick node has no current bordered brick");
-                    HIPCHK(h, hipMemcpy(slotbuf.data(), h->pool + (uint64_t)c.slot * h->brick_bytes,
+                    int64_t slot = c.slot;
+                    if (!resident) {
+                        // gather the bordered brick into the spare slot past the pool
+                        slot = h->n_slots;
+                        int rc = stage_reserve(h, h->up, sizeof(BrickJob));
+                        if (rc) return rc;
+                        BrickJob j{};
+                        j.slot = (int32_t)slot;
+                        j.level = L;
+                        j.bx = x;
+                        j.by = y;
+                        j.bz = z;
+                        j.full = 1;
+                        for (int a = 0; a < 3; a++) j.hi[a] = S - 1;
+                        std::memcpy(h->up.host, &j, sizeof j);
+                        HIPCHK(h, hipMemcpy(h->up.dev, h->up.host, sizeof j, hipMemcpyHostToDevice));
+                        HIPCHK(h, launch_gather(g, h->master, h->table, h->pool, h->brick_bytes,
+                                                (const BrickJob *)h->up.dev, 1, h->slot_range,
+                                                h->background_f, nullptr));
+                        HIPCHK(h, hipDeviceSynchronize());
+                    }
+                    HIPCHK(h, hipMemcpy(slotbuf.data(), h->pool + (uint64_t)slot * h->brick_bytes,
                                         h->brick_bytes, hipMemcpyDeviceToHost));
                     for (int v = 0; v < S * S * S; v++)
                         for (int k = 0; k < C; k++) {

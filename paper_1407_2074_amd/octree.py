@@ -29,7 +29,7 @@ class CreateParams(ct.Structure):
     _fields_ = [("dims", ct.c_int32 * 3), ("channels", ct.c_int32), ("brick_size", ct.c_int32),
                 ("dtype", ct.c_int32), ("background", ct.c_double),
                 ("homog_threshold", ct.c_double), ("device_pool_bytes", ct.c_uint64),
-                ("reserved", ct.c_int32 * 4)]
+                ("master_on_host", ct.c_int32), ("reserved", ct.c_int32 * 3)]
 
 
 class OctView(ct.Structure):
@@ -45,7 +45,8 @@ class OctView(ct.Structure):
 class UploadStats(ct.Structure):
     _fields_ = [("bricks_gathered", ct.c_uint64), ("bricks_resident", ct.c_uint64),
                 ("bricks_total", ct.c_uint64), ("nodes_changed", ct.c_uint64),
-                ("bytes_written", ct.c_uint64)]
+                ("bytes_written", ct.c_uint64), ("requests_seen", ct.c_uint64),
+                ("evictions", ct.c_uint64)]
 
 
 class RenderStats(ct.Structure):
@@ -127,7 +128,7 @@ class Octree:
 
     def __init__(self, dims, channels: int, brick: int, dtype: str = "u16",
                  background: float = 0.0, threshold: float = 0.0, pool_bytes: int = 0,
-                 stream=None):
+                 master_on_host: bool = False, stream=None):
         p = CreateParams()
         for a in range(3):
             p.dims[a] = int(dims[a])
@@ -135,6 +136,7 @@ class Octree:
         p.dtype = OCT_U16 if dtype == "u16" else OCT_F32
         p.background, p.homog_threshold = float(background), float(threshold)
         p.device_pool_bytes = int(pool_bytes)
+        p.master_on_host = 1 if master_on_host else 0
         h = ct.c_void_p()
         rc = lib.octree_create(ct.byref(p), _stream(stream), ct.byref(h))
         if rc != OCT_OK:
