@@ -586,6 +586,7 @@ typedef struct {
     int64_t idx[8];            /* corner voxel linear indices within one channel of R_L */
     double w[8];               /* trilinear weights */
     int64_t cidx;              /* constant case: voxel index */
+    const double *avg;         /* constant case of a non-resident brick node: its AVG */
 } orc_sample_geo;
 
 static void sample_geo(const orc_tree *t, int L, const float p[3], orc_sample_geo *g)
@@ -601,6 +602,7 @@ static void sample_geo(const orc_tree *t, int L, const float p[3], orc_sample_ge
     }
     const orc_node *nd = node_at(t, L, b[0], b[1], b[2]);
     g->brick = nd->exists && nd->state == ST_BRICK && !nd->nonresident;
+    g->avg = (nd->exists && nd->state == ST_BRICK && nd->nonresident) ? nd->avg : NULL;
     if (!g->brick) {
         g->cidx = ((int64_t)(v[2] >> L) * e[1] + (v[1] >> L)) * e[0] + (v[0] >> L);
         return;
@@ -629,7 +631,7 @@ static void sample_geo(const orc_tree *t, int L, const float p[3], orc_sample_ge
 static double sample_value(const orc_tree *t, int L, int c, const orc_sample_geo *g)
 {
     const double *R = t->R[L] + (int64_t)c * lvl_voxels(t, L);
-    if (!g->brick) return R[g->cidx];
+    if (!g->brick) return g->avg ? g->avg[c] : R[g->cidx];
     double s = 0.0;
     for (int k = 0; k < 8; k++) s += g->w[k] * R[g->idx[k]];
     return s;

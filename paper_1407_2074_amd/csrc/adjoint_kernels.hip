@@ -170,6 +170,7 @@ k_render_backward(VolGeom g, const DevCell *__restrict__ table, const uint8_t *_
             float Tr = V.ckpt[pix * V.nseg + sg];
             for (int k = k0; k < k1; k++) {
                 const float tk = ray.t0 + (float)k * step;
+                if (!(tk < ray.t1)) break;
                 float p[3];
                 for (int q = 0; q < 3; q++) {
                     const float m = tk * ray.d[q];
@@ -186,6 +187,7 @@ k_render_backward(VolGeom g, const DevCell *__restrict__ table, const uint8_t *_
             // 2. back-to-front walk
             for (int k = k1 - 1; k >= k0; k--) {
                 const float tk = ray.t0 + (float)k * step;
+                if (!(tk < ray.t1)) continue;
                 float p[3];
                 for (int q = 0; q < 3; q++) {
                     const float m = tk * ray.d[q];

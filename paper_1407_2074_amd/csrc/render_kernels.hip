@@ -250,19 +250,26 @@ render_body(const VolGeom &g, const DevCell *__restrict__ table, const uint8_t *
         k++;
     }
 
+    int nominal = 0;
+    if (ray.hit && (counters || V.nend)) {
+        // positions t_k < t1: start from the estimate and settle with the exact test
+        int kk = max((int)((t1 - t0) / step) - 2, 0);
+        while (t0 + (float)kk * step < t1) kk++;
+        nominal = kk;
+    }
     if (inside) {
         float4 out = make_float4(Cr, Cg, Cb, 1.0f - Tr);
         *(float4 *)(V.image + pix * 4) = out;
-        if (V.nend) V.nend[pix] = ray.hit ? k : 0;
+        // first position not evaluated: after early termination k, otherwise the end of the
+        // ray (a skip may have jumped past it)
+        const int n_end = ray.hit ? (live ? nominal : k) : 0;
+        if (V.nend) V.nend[pix] = n_end;
+        // segments that began inside a final skipped run keep the transmittance of the jump
+        if (ckpt)
+            for (; next_ck < n_end; next_ck += kCkptStride)
+                ckpt[pix * V.nseg + next_ck / kCkptStride] = Tr;
     }
     if (counters) {
-        int nominal = 0;
-        if (ray.hit) {
-            // positions t_k < t1: start from the estimate and settle with the exact test
-            int kk = max((int)((t1 - t0) / step) - 2, 0);
-            while (t0 + (float)kk * step < t1) kk++;
-            nominal = kk;
-        }
         unsigned long long r = ray.hit ? 1ull : 0ull, nn = (unsigned long long)nominal,
                            cc = (unsigned long long)composited, tt = (unsigned long long)trilinear;
         for (int off = 32; off > 0; off >>= 1) {

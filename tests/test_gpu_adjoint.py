@@ -33,9 +33,9 @@ def _views(dims, C, n, w, h, seed=4, dtype="f32"):
     return vs
 
 
-def _gpu_grads(t, views, dL, want_vox=True):
+def _gpu_grads(t, views, dL, want_vox=True, ck_out=None):
     import torch
-    ck = torch.empty(t.ckpt_bytes(views), dtype=torch.uint8, device="cuda")
+    ck = torch.zeros(t.ckpt_bytes(views), dtype=torch.uint8, device="cuda")
     imgs = t.render(views, ckpt=ck)
     g = [torch.from_numpy(x.astype(np.float32)).cuda() for x in dL(imgs)]
     dctrl = torch.zeros((len(views), t.C, 8, 4), dtype=torch.float32, device="cuda")
@@ -43,6 +43,8 @@ def _gpu_grads(t, views, dL, want_vox=True):
     dvox = torch.zeros((t.C, Dz, Dy, Dx), dtype=torch.float32, device="cuda") if want_vox else None
     t.render_backward(views, g, ck, dctrl, dvox)
     torch.cuda.synchronize()
+    if ck_out is not None:
+        ck_out.append(ck.cpu().numpy())
     return imgs, dctrl.cpu().numpy(), (dvox.cpu().numpy() if want_vox else None)
 
 
@@ -144,11 +146,14 @@ def test_adjoint_with_early_termination_and_skipping(orc):
     def dL(imgs):
         return [2 * (imgs[0].cpu().numpy().astype(np.float64) - tgt)]
 
-    _, c_skip, v_skip = _gpu_grads(t, [v], dL)
+    cks = []
+    _, c_skip, v_skip = _gpu_grads(t, [v], dL, ck_out=cks)
     v.no_skip = 1
-    _, c_full, v_full = _gpu_grads(t, [v], dL)
-    np.testing.assert_array_equal(c_skip, c_full)
-    np.testing.assert_array_equal(v_skip, v_full)
+    _, c_full, v_full = _gpu_grads(t, [v], dL, ck_out=cks)
+    # the forward's checkpoints and end positions are bit-identical with and without skipping;
+    # the gradients then differ only by the order of float atomics
+    np.testing.assert_array_equal(cks[0], cks[1])
+    assert _rel(c_skip, c_full) <= 1e-5 and _rel(v_skip, v_full) <= 1e-5
     ref = orc.Tree(vol, _full(C, dims), M, 0.0, 0.0)
     want, _, mg = ref.render([v], want_info=True)
     assert (mg[0] < 1e-5).sum() == 0          # no ambiguous termination in this case

@@ -250,3 +250,49 @@ def test_adjoint_matches_central_differences(orc):
         assert abs(fd - dvox[idx]) <= 1e-4 * max(abs(fd), 1e-3), (idx, fd, dvox[idx])
         checked += 1
     assert checked == 50
+
+
+def test_nonresident_bricks_render_their_avg(orc):
+    """With every brick node marked non-resident, each sample is the AVG of the level-L node
+    holding it: compare with a numpy renderer that looks the AVG up per node directly."""
+    from helpers import f32_rays, np_lut
+    dims, M, C = (24, 20, 16), 4, 2
+    vol = _random_case(dims, C, blobs=5)
+    t = orc.Tree(vol, _full(C, dims), M, 0, 0)
+    hdr, recs, _ = orc.parse_dump(t.dump())
+    t.set_nonresident([tuple(int(x) for x in r["head"][:4]) for r in recs
+                       if r["head"][4] == orc.ST_BRICK])
+    assert not (orc.parse_dump(t.dump())[1]["head"][:, 5] & orc.F_RESIDENT).any()
+    avg = {tuple(int(x) for x in r["head"][:4]): r["avg"][:C] for r in recs}
+    v = synth.make_view(dims, C, 1, az=55.0, el=25.0, width=20, height=18, lod=1)
+    v.tf_pos[:, 1] = 0.005
+    (img,) = t.render([v])
+    o, d, t0, t1, L, hit = f32_rays(v, dims, t.N)
+    luts = [np_lut(v.tf_pos[c], v.tf_rgba[c]) for c in range(C)]
+    ref = np.zeros_like(img)
+    for j in range(v.height):
+        for i in range(v.width):
+            if not hit[j, i]:
+                continue
+            A, col, k = 0.0, np.zeros(3), 0
+            while True:
+                tk = t0[j, i] + np.float32(k) * np.float32(v.step)
+                if not tk < t1[j, i]:
+                    break
+                p = o[j, i] + tk * d[j, i]
+                vox = np.clip(np.floor(p).astype(int), 0, np.array(dims) - 1)
+                lv = int(L[j, i])
+                b = tuple(int(x) for x in ((vox >> lv) // M))
+                for c in range(C):
+                    s = avg[(lv,) + b][c]
+                    x = min(max((s - v.window[c][0]) / (v.window[c][1] - v.window[c][0]), 0), 1)
+                    u = 255 * x
+                    ii = min(int(np.floor(u)), 254)
+                    rgba = luts[c][ii] + (u - ii) * (luts[c][ii + 1] - luts[c][ii])
+                    w = (1 - A) * rgba[3]
+                    col += w * rgba[:3]
+                    A += w
+                k += 1
+            ref[j, i, :3], ref[j, i, 3] = col, A
+    assert img[..., 3].max() > 0.01
+    assert np.abs(img - ref).max() < 1e-12
