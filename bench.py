@@ -47,7 +47,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run a plain device copy of this size (counter calibration)")
-    ap.add_argument("--workload", default="stream", choices=["stream", "adjoint", "serve", "views"],
+    ap.add_argument("--scale", type=int, default=1, choices=[1, 2, 4],
+                    help="paging workload: 1 = 2048x2048x1024, 2 = half and 4 = quarter size")
+    ap.add_argument("--workload", default="stream",
+                    choices=["stream", "adjoint", "serve", "views", "paging"],
                     help="stream: streamed build+render (default); adjoint: 256^3 f32 forward + "
                          "adjoint at 512x512; serve: Poisson request mix; views: 64 views of "
                          "the 64^3 volume in one launch vs one launch per view")
@@ -64,7 +67,8 @@ def main():
     from paper_1407_2074_amd.octree import Octree
 
     if args.workload != "stream":
-        {"adjoint": bench_adjoint, "serve": bench_serve, "views": bench_views}[args.workload](args)
+        {"adjoint": bench_adjoint, "serve": bench_serve, "views": bench_views,
+         "paging": bench_paging}[args.workload](args)
         return
 
     cfg = CFG[args.config]
@@ -329,6 +333,98 @@ def bench_views(args):
            "one_view_per_launch_us_per_frame": round(ts * 1e6 / 64, 2),
            "one_view_per_launch_gsamples_per_s": round(comp / ts / 1e9, 3),
            "positions_composited": comp}
+    print(json.dumps(out), flush=True)
+
+
+def bench_paging(args):
+    """Out-of-core: 3-channel u16 2048x2048x1024 (100k blobs) at --scale 1, 32^3 bricks, the
+    full-resolution mipmap in pinned host memory, device brick pool capped (16 GB at scale 1,
+    divided by scale^3), 1920x1080 views along a 64-frame orbit that dollies from 1.0 to 0.5 of
+    the fitting distance (per-ray LOD, step 0.5, ERT 0.99).  Each frame = render + one
+    brick_pool_upload with a byte budget (bricks are paged in on request).  The last frame is
+    then refined until no brick is missing and compared with an in-core render."""
+    import numpy as np
+    import torch
+
+    from paper_1407_2074_amd import synth
+    from paper_1407_2074_amd.octree import Octree
+    sc = args.scale
+    dims, C, M = (2048 // sc, 2048 // sc, 1024 // sc), 3, 32
+    blobs = 100000 // (sc ** 3)
+    workers = min(16, os.cpu_count() or 1)
+    t_gen = time.perf_counter()
+    vol = synth.gen_volume(dims, C, seed=3, n_blobs=blobs, workers=workers)
+    t_gen = time.perf_counter() - t_gen
+    pool_bytes = (16 << 30) // (sc ** 3)
+    tree = Octree(dims, C, M, "u16", 0, 205, pool_bytes=pool_bytes, master_on_host=True)
+    t_ins = time.perf_counter()
+    zc = 64 // sc
+    for z0 in range(0, dims[2], zc):
+        tree.insert_slices(-1, z0, np.ascontiguousarray(vol[:, z0:z0 + zc]))
+    tree.upload()
+    torch.cuda.synchronize()
+    t_ins = time.perf_counter() - t_ins
+    n_frames = 64
+    budget = (1 << 30) // sc
+    views = []
+    for k in range(n_frames):
+        v = synth.make_view(dims, C, 3, az=360.0 * k / n_frames, el=20.0, width=1920,
+                            height=1080, lod=-1, dist_scale=1.0 - 0.5 * k / (n_frames - 1))
+        v.ert_alpha = 0.99
+        views.append(v)
+    img = torch.empty((1080, 1920, 4), dtype=torch.float32, device="cuda")
+    tree.render([views[0]], images=[img])       # warm-up (also the first requests)
+    tree.upload(byte_budget=budget)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(n_frames)]
+    comp = gathered = requests = evictions = 0
+    t0 = time.perf_counter()
+    up_s = 0.0
+    stream = torch.cuda.current_stream()
+    for k, v in enumerate(views):
+        ev[k][0].record(stream)
+        _, st = tree.render([v], images=[img], stats=True)
+        ev[k][1].record(stream)
+        comp += st["positions_composited"]
+        tu = time.perf_counter()
+        up = tree.upload(byte_budget=budget)
+        up_s += time.perf_counter() - tu
+        gathered += up["bricks_gathered"]
+        requests += up["requests_seen"]
+        evictions += up["evictions"]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    render_s = sum(a.elapsed_time(b) for a, b in ev) / 1e3
+    # refine the last view to convergence, compare with the in-core render of the same view
+    last = views[-1]
+    passes = 0
+    for passes in range(1, 200):
+        (img,) = tree.render([last], images=[img])
+        if tree.upload()["requests_seen"] == 0:
+            break
+    (img,) = tree.render([last], images=[img])
+    paged = img.cpu()
+    del tree
+    incore = Octree(dims, C, M, "u16", 0, 205)
+    for z0 in range(0, dims[2], zc):
+        incore.insert_slices(-1, z0, np.ascontiguousarray(vol[:, z0:z0 + zc]))
+    incore.upload()
+    (ref,) = incore.render([last])
+    same = bool(torch.equal(paged, ref.cpu()))
+    out = {"metric": "out-of-core frames/s over a 64-frame 1080p path", "value":
+           round(n_frames / elapsed, 2), "unit": "frames/s", "n_gpus": 1, "higher_is_better": True,
+           "data": "synthetic", "config": {"workload": f"{dims[0]}x{dims[1]}x{dims[2]}x3 u16, "
+           f"{blobs} blobs, 32^3 bricks, master in pinned host memory, device pool "
+           f"{pool_bytes >> 20} MiB, 1920x1080, ERT 0.99, per-ray LOD, {budget >> 20} MiB "
+           "upload budget per frame"},
+           "render_only_gsamples_per_s": round(comp / render_s / 1e9, 3),
+           "render_ms_per_frame": round(render_s / n_frames * 1e3, 3),
+           "upload_ms_per_frame": round(up_s / n_frames * 1e3, 3),
+           "paged_bricks": gathered, "paged_gb_per_s": round(gathered * incore.brick_bytes / up_s / 1e9, 2),
+           "requests": requests, "evictions": evictions,
+           "converged_passes_last_frame": passes, "converged_equals_in_core": same,
+           "generation_s": round(t_gen, 1), "insert_s": round(t_ins, 2)}
     print(json.dumps(out), flush=True)
 
 

@@ -25,7 +25,7 @@ namespace octrc {
 
 namespace {
 
-constexpr int kThreads = 512;
+constexpr int kThreads = 64 * kRenderTilesPerWg;
 
 // One sample position: intensity per channel and, for a brick sample, the trilinear corners.
 template <int C>

@@ -67,8 +67,12 @@ struct DevView {
     float *dlut;
 };
 
-// One workgroup of a render launch: 8 waves = up to 8 consecutive tiles of one view.
-constexpr int kRenderTilesPerWg = 8;
+// One workgroup of a render launch: up to kRenderTilesPerWg consecutive tiles of one view,
+// one wave each.
+#ifndef OCTRC_RENDER_WAVES
+#define OCTRC_RENDER_WAVES 8
+#endif
+constexpr int kRenderTilesPerWg = OCTRC_RENDER_WAVES;
 struct WgItem {
     int32_t view;
     int32_t tile0;

@@ -16,7 +16,7 @@ namespace octrc {
 
 namespace {
 
-constexpr int kThreads = 512;   // 8 waves = 8 tiles of one view share the LDS tables
+constexpr int kThreads = 64 * kRenderTilesPerWg;   // one wave per tile; the tiles share the tables
 
 template <typename T, int C>
 __device__ __forceinline__ void
@@ -26,7 +26,11 @@ render_body(const VolGeom &g, const DevCell *__restrict__ table, const uint8_t *
             ViewTables<C> &tb)
 {
 
+#ifndef OCTRC_NO_XCD_REMAP
     const WgItem it = items[xcd_item(blockIdx.x, gridDim.x)];
+#else
+    const WgItem it = items[blockIdx.x];
+#endif
     const DevView &V = views[it.view];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     build_tables<C>(V, tb);
@@ -93,6 +97,10 @@ render_body(const VolGeom &g, const DevCell *__restrict__ table, const uint8_t *
             const float m = tk * d[q];
             p[q] = o[q] + m;
         }
+#ifdef OCTRC_NO_COUNTDOWN
+        k_lo = 1;
+        k_hi = 0;
+#endif
         if (k < k_lo || k > k_hi) {
             int v[3];
 #pragma unroll
@@ -290,7 +298,10 @@ render_body(const VolGeom &g, const DevCell *__restrict__ table, const uint8_t *
 // uint16 bricks fit 6 waves per SIMD in registers; float32 bricks (twice the corner data)
 // keep the compiler's choice.
 template <int C>
-__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(6)))
+#ifndef OCTRC_U16_WAVES_PER_EU
+#define OCTRC_U16_WAVES_PER_EU 6
+#endif
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(OCTRC_U16_WAVES_PER_EU)))
 k_render_u16(VolGeom g, const DevCell *__restrict__ table, const uint8_t *__restrict__ pool,
              uint64_t brick_bytes, const DevView *__restrict__ views,
              const WgItem *__restrict__ items, RenderCounters *counters, uint8_t *flags)

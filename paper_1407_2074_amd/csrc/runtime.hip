@@ -168,7 +168,7 @@ bool valid_params(const oct_create_params *p, std::string &why)
         why = "u16 background must be an integer in [0, 65535]";
         return false;
     }
-    for (int i = 0; i < 4; i++)
+    for (int i = 0; i < 3; i++)
         if (p->reserved[i]) { why = "reserved fields must be 0"; return false; }
     return true;
 }

@@ -105,9 +105,26 @@ def gen_slab(dims, channels: int, seed: int, n_blobs: int, z0: int, z1: int,
     return out
 
 
-def gen_volume(dims, channels: int, seed: int, n_blobs: int, dtype: str = "u16") -> np.ndarray:
-    """Whole planar volume [C][Dz][Dy][Dx]."""
-    return gen_slab(dims, channels, seed, n_blobs, 0, dims[2], dtype)
+def _slab_job(args):
+    dims, channels, seed, n_blobs, z0, z1, dtype = args
+    return z0, gen_slab(dims, channels, seed, n_blobs, z0, z1, dtype)
+
+
+def gen_volume(dims, channels: int, seed: int, n_blobs: int, dtype: str = "u16",
+               workers: int = 1) -> np.ndarray:
+    """Whole planar volume [C][Dz][Dy][Dx]; with workers > 1 the z-slabs are generated in
+    parallel processes (identical result: every voxel depends only on its index)."""
+    if workers <= 1:
+        return gen_slab(dims, channels, seed, n_blobs, 0, dims[2], dtype)
+    import multiprocessing as mp
+    dz = dims[2]
+    step = max(1, -(-dz // (4 * workers)))
+    jobs = [(dims, channels, seed, n_blobs, z, min(z + step, dz), dtype) for z in range(0, dz, step)]
+    out = np.empty((channels, dz, dims[1], dims[0]), np.uint16 if dtype == "u16" else np.float32)
+    with mp.get_context("fork").Pool(workers) as pool:
+        for z0, slab in pool.imap_unordered(_slab_job, jobs):
+            out[:, z0:z0 + slab.shape[1]] = slab
+    return out
 
 
 def default_window(dtype: str = "u16"):

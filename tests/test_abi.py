@@ -35,39 +35,34 @@ def test_library_exports_every_declared_symbol(native):
 
 
 def test_struct_layouts_match_header(native, tmp_path):
+    """sizeof and the offset of every field, C compiler vs the ctypes mirrors."""
     import ctypes as ct
+    structs = {"oct_create_params": native.CreateParams, "oct_view": native.OctView,
+               "oct_upload_stats": native.UploadStats, "oct_render_stats": native.RenderStats}
+    lines = []
+    for cname, py in structs.items():
+        lines.append(f'printf("%zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'printf("%zu\\n", offsetof({cname}, {fname}));')
     prog = tmp_path / "layout.c"
-    prog.write_text(f"""
-#include <stdio.h>
-#include <stddef.h>
-#include "{HEADER}"
-int main(void) {{
-  printf("%zu %zu %zu %zu\\n", sizeof(oct_create_params), sizeof(oct_view),
-         sizeof(oct_upload_stats), sizeof(oct_render_stats));
-  printf("%zu %zu %zu %zu %zu\\n", offsetof(oct_view, step), offsetof(oct_view, clip),
-         offsetof(oct_view, tf_rgba), offsetof(oct_view, window), offsetof(oct_view, no_skip));
-  printf("%zu %zu\\n", offsetof(oct_create_params, background),
-         offsetof(oct_create_params, device_pool_bytes));
-  return 0;
-}}
-""")
+    prog.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "' + HEADER + '"\n'
+                    "int main(void) {\n" + "\n".join(lines) + "\nreturn 0;\n}\n")
     exe = tmp_path / "layout"
     subprocess.check_call(["gcc", "-O0", "-o", str(exe), str(prog)])
-    got = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()
-    got = [int(x) for x in got]
-    V, P = native.OctView, native.CreateParams
-    assert got[:4] == [ct.sizeof(P), ct.sizeof(V), ct.sizeof(native.UploadStats),
-                       ct.sizeof(native.RenderStats)]
-    assert got[4:9] == [V.step.offset, V.clip.offset, V.tf_rgba.offset, V.window.offset,
-                        V.no_skip.offset]
-    assert got[9:] == [P.background.offset, P.device_pool_bytes.offset]
+    got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True,
+                                          check=True).stdout.split()]
+    want = []
+    for cname, py in structs.items():
+        want.append(ct.sizeof(py))
+        want.extend(getattr(py, f).offset for f, _ in py._fields_)
+    assert got == want
 
 
 def test_invalid_create_params_fail_without_gpu_work(native):
     """Argument validation happens before any device call."""
     import ctypes as ct
     for bad in [dict(brick=5), dict(brick=0), dict(channels=5), dict(channels=0),
-                dict(dims=(0, 4, 4)), dict(dtype=7), dict(background=1.5)]:
+                dict(dims=(0, 4, 4)), dict(dtype=7), dict(background=1.5), dict(reserved=1)]:
         p = native.CreateParams()
         dims = bad.get("dims", (16, 16, 16))
         for a in range(3):
@@ -76,6 +71,7 @@ def test_invalid_create_params_fail_without_gpu_work(native):
         p.brick_size = bad.get("brick", 8)
         p.dtype = bad.get("dtype", 0)
         p.background = bad.get("background", 0.0)
+        p.reserved[2] = bad.get("reserved", 0)
         h = ct.c_void_p()
         assert native.lib.octree_create(ct.byref(p), None, ct.byref(h)) == native.OCT_EINVAL
         assert native.lib.oct_last_error(None)
