@@ -129,7 +129,7 @@ k_render_backward(VolGeom g, const DevCell *__restrict__ table, const uint8_t *_
     __shared__ ViewTables<C> tb;
     __shared__ float s_dlut[C][256][4];
 
-    const WgItem it = items[xcd_item(blockIdx.x, gridDim.x)];
+    const WgItem it = items[blockIdx.x];
     const DevView &V = views[it.view];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     for (int i = threadIdx.x; i < C * 256 * 4; i += kThreads) (&s_dlut[0][0][0])[i] = 0.0f;

@@ -70,7 +70,7 @@ struct DevView {
 // One workgroup of a render launch: up to kRenderTilesPerWg consecutive tiles of one view,
 // one wave each.
 #ifndef OCTRC_RENDER_WAVES
-#define OCTRC_RENDER_WAVES 8
+#define OCTRC_RENDER_WAVES 4
 #endif
 constexpr int kRenderTilesPerWg = OCTRC_RENDER_WAVES;
 struct WgItem {

@@ -108,17 +108,6 @@ __device__ inline bool cell_transparent(const DevCell &cell, const float *ub, co
     return range_transparent<C>(lo4, hi4, ub, usc, pref);
 }
 
-// Workgroup -> work item: the dispatcher deals workgroups round-robin to the 8 XCDs (each with
-// its own L2), so item blocks are reassigned to make XCD x process one contiguous run of items
-// (a band of neighbouring tiles that share bricks) instead of every 8th item.
-__device__ inline int xcd_item(int bid, int n)
-{
-    constexpr int kXcd = 8;
-    const int q = n / kXcd, r = n % kXcd;
-    const int x = bid % kXcd, local = bid / kXcd;
-    return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + local;
-}
-
 struct Ray {
     float o[3], d[3];
     float t0, t1;

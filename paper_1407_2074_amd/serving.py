@@ -26,7 +26,7 @@ from .octree import Octree
 TILE = 8
 
 
-@dataclasses.dataclass
+@dataclasses.dataclass(eq=False)          # requests compare and hash by identity
 class Request:
     rid: int
     view: object            # synth.View (or same attributes)

@@ -33,8 +33,19 @@ def _tree(vol, slots=0, host=False):
 
 
 def _views():
-    return [synth.make_view(DIMS, C, 12, az=az, el=25.0, width=64, height=64, lod=-1)
-            for az in (10.0, 100.0, 190.0, 280.0)]
+    # alternating fixed levels: the views need different bricks, so a pool holding the largest
+    # single working set cannot hold them all and switching views has to evict
+    return [synth.make_view(DIMS, C, 12, az=az, el=25.0, width=64, height=64, lod=lod)
+            for az, lod in ((10.0, 1), (100.0, 0), (190.0, 1), (280.0, 0))]
+
+
+def _converge(t, v, max_iter=80):
+    for it in range(max_iter):
+        (img,) = t.render([v])
+        st = t.upload()
+        if st["requests_seen"] == 0:
+            return img, st
+    raise AssertionError("paging did not converge")
 
 
 def _oracle_with_residency(orc, vol, dump):
@@ -49,13 +60,24 @@ def _oracle_with_residency(orc, vol, dump):
 def test_paging_converges_to_in_core_image(orc, vol):
     import torch
     full = _tree(vol)
-    t = _tree(vol, slots=120)
-    assert t.pool_slots == 120
+    views = _views()
+    # working set of each view alone: a fresh tree whose pool is one slot short of holding
+    # every brick, so that it pages on request
+    n_all = full.pool_slots - 1
+    ws = []
+    for v in views:
+        t = _tree(vol, slots=n_all)
+        _, st = _converge(t, v)
+        ws.append(st["bricks_resident"])
+        t.close()
+    cap = max(ws)
+    assert cap < sum(ws)
+    t = _tree(vol, slots=cap)
     total_evictions = 0
     checked_partial = False
-    for v in _views():
+    for v in views:
         (want,) = full.render([v])
-        for it in range(60):
+        for it in range(80):
             (img,) = t.render([v])
             if not checked_partial:
                 # nothing is resident yet: the first image uses AVG for every brick node
