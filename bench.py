@@ -30,6 +30,38 @@ FLOPS_TRILINEAR = 12 + 63 + 45
 # 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz x 2 (FMA) -- FP32 without packed math
 PEAK_FP32_TFLOPS = 78.6
 
+# HBM bytes per render launch of the default workload, from FETCH_SIZE / WRITE_SIZE counter
+# runs scaled by the same counters over a plain 1 GiB copy; valid only for the kernel code
+# they were taken on (its sources are hashed without comments, with the compile flags)
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_render_u16_hbm_traffic_stream_512x512x256.md")
+RENDER_SOURCES = ("render_kernels.hip", "raycommon.h", "internal.h")
+
+
+def render_code_hash() -> str:
+    import hashlib
+    import re
+    from paper_1407_2074_amd import build
+    h = hashlib.sha256(" ".join(build.HIPCC_FLAGS).encode())
+    for name in RENDER_SOURCES:
+        txt = open(os.path.join(ROOT, "paper_1407_2074_amd", "csrc", name)).read()
+        txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+        txt = re.sub(r"//[^\n]*", "", txt)
+        h.update(" ".join(txt.split()).encode())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    import re
+    try:
+        txt = open(TRAFFIC_PROFILE).read()
+    except OSError:
+        return None
+    b = re.search(r"traffic_bytes_per_launch:\s*(\d+)", txt)
+    h = re.search(r"kernel_code_sha256:\s*([0-9a-f]{64})", txt)
+    if not b or not h or h.group(1) != render_code_hash():
+        return None
+    return int(b.group(1))
+
 CFG = {
     2: dict(dims=(512, 512, 256), C=3, M=32, seed=2, blobs=2000, thr=205, batch=8,
             width=1024, height=1024, az=45.0, el=30.0, lod=-1),
@@ -162,7 +194,7 @@ def main():
         "build_ms_per_step": round(ms_per_step - render_ms / args.steps, 3),
         "roofline": {"bound": "alu", "achieved": round(achieved_tflops, 3),
                      "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": round(achieved_tflops / PEAK_FP32_TFLOPS, 4), "traffic": None,
+                     "frac": round(achieved_tflops / PEAK_FP32_TFLOPS, 4), "traffic": measured_traffic(),
                      "kernel": "k_render<u16,3>",
                      "flops_per_launch": flops_step // nb},
     }
@@ -340,9 +372,12 @@ def bench_paging(args):
     """Out-of-core: 3-channel u16 2048x2048x1024 (100k blobs) at --scale 1, 32^3 bricks, the
     full-resolution mipmap in pinned host memory, device brick pool capped (16 GB at scale 1,
     divided by scale^3), 1920x1080 views along a 64-frame orbit that dollies from 1.0 to 0.5 of
-    the fitting distance (per-ray LOD, step 0.5, ERT 0.99).  Each frame = render + one
-    brick_pool_upload with a byte budget (bricks are paged in on request).  The last frame is
-    then refined until no brick is missing and compared with an in-core render."""
+    the fitting distance (per-ray LOD, step 0.5, ERT 0.99).  At --scale s the image shrinks by s
+    too, so per-ray LODs and the working set relative to the pool match the full-size case.
+    Each frame = render + one brick_pool_upload with a byte budget (bricks are paged in on
+    request).  The last frame is then refined until no brick is missing (compared with an
+    in-core render) or until the pool cannot take more (over-subscribed: coarser requests
+    have kept their slots, the rest are drawn with AVG)."""
     import numpy as np
     import torch
 
@@ -365,14 +400,15 @@ def bench_paging(args):
     torch.cuda.synchronize()
     t_ins = time.perf_counter() - t_ins
     n_frames = 64
+    W, H = 1920 // sc, 1080 // sc
     budget = (1 << 30) // sc
     views = []
     for k in range(n_frames):
-        v = synth.make_view(dims, C, 3, az=360.0 * k / n_frames, el=20.0, width=1920,
-                            height=1080, lod=-1, dist_scale=1.0 - 0.5 * k / (n_frames - 1))
+        v = synth.make_view(dims, C, 3, az=360.0 * k / n_frames, el=20.0, width=W,
+                            height=H, lod=-1, dist_scale=1.0 - 0.5 * k / (n_frames - 1))
         v.ert_alpha = 0.99
         views.append(v)
-    img = torch.empty((1080, 1920, 4), dtype=torch.float32, device="cuda")
+    img = torch.empty((H, W, 4), dtype=torch.float32, device="cuda")
     tree.render([views[0]], images=[img])       # warm-up (also the first requests)
     tree.upload(byte_budget=budget)
     torch.cuda.synchronize()
@@ -398,32 +434,37 @@ def bench_paging(args):
     render_s = sum(a.elapsed_time(b) for a, b in ev) / 1e3
     # refine the last view to convergence, compare with the in-core render of the same view
     last = views[-1]
-    passes = 0
-    for passes in range(1, 200):
+    passes, unserved, resident = 0, 0, 0
+    for passes in range(1, 400):
         (img,) = tree.render([last], images=[img])
-        if tree.upload()["requests_seen"] == 0:
-            break
+        up = tree.upload()
+        unserved, resident = up["requests_seen"], up["bricks_resident"]
+        if unserved == 0 or (up["bricks_gathered"] == 0 and up["evictions"] == 0):
+            break       # converged, or the pool holds what it can
     (img,) = tree.render([last], images=[img])
     paged = img.cpu()
+    incore_slots = tree.pool_slots
     del tree
     incore = Octree(dims, C, M, "u16", 0, 205)
     for z0 in range(0, dims[2], zc):
         incore.insert_slices(-1, z0, np.ascontiguousarray(vol[:, z0:z0 + zc]))
     incore.upload()
     (ref,) = incore.render([last])
-    same = bool(torch.equal(paged, ref.cpu()))
-    out = {"metric": "out-of-core frames/s over a 64-frame 1080p path", "value":
+    same = bool(torch.equal(paged, ref.cpu())) if unserved == 0 else None
+    out = {"metric": "out-of-core frames/s over a 64-frame orbit-and-dolly path", "value":
            round(n_frames / elapsed, 2), "unit": "frames/s", "n_gpus": 1, "higher_is_better": True,
            "data": "synthetic", "config": {"workload": f"{dims[0]}x{dims[1]}x{dims[2]}x3 u16, "
            f"{blobs} blobs, 32^3 bricks, master in pinned host memory, device pool "
-           f"{pool_bytes >> 20} MiB, 1920x1080, ERT 0.99, per-ray LOD, {budget >> 20} MiB "
+           f"{pool_bytes >> 20} MiB, {W}x{H}, ERT 0.99, per-ray LOD, {budget >> 20} MiB "
            "upload budget per frame"},
            "render_only_gsamples_per_s": round(comp / render_s / 1e9, 3),
            "render_ms_per_frame": round(render_s / n_frames * 1e3, 3),
            "upload_ms_per_frame": round(up_s / n_frames * 1e3, 3),
            "paged_bricks": gathered, "paged_gb_per_s": round(gathered * incore.brick_bytes / up_s / 1e9, 2),
            "requests": requests, "evictions": evictions,
-           "converged_passes_last_frame": passes, "converged_equals_in_core": same,
+           "refine_passes_last_frame": passes, "last_frame_resident_bricks": resident,
+           "last_frame_unserved_requests": unserved, "pool_slots": incore_slots,
+           "converged_equals_in_core": same,
            "generation_s": round(t_gen, 1), "insert_s": round(t_ins, 2)}
     print(json.dumps(out), flush=True)
 

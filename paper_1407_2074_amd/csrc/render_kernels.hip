@@ -1,5 +1,5 @@
 // Forward ray casting (Algorithm 1, "Basic Ray-Casting"), one 64-lane wave per 8x8 pixel tile,
-// eight tiles of one view per 512-thread workgroup.
+// several tiles of one view per workgroup (kRenderTilesPerWg waves).
 //
 // Per workgroup the view's transfer functions are tabulated into LDS (256 RGBA value/slope
 // pairs per channel) together with a prefix count of the entries with non-zero opacity; the
