@@ -17,8 +17,13 @@
  *  - Device pointers passed in are borrowed: they must stay valid until the stream has passed
  *    the call.  Host pointers are consumed before the call returns.
  *  - A handle is not thread-safe: calls on one handle must be serialised by the caller.
- *    Renders on different streams may overlap each other (the handle keeps one set of per-call
- *    buffers per in-flight render), but not a brick_pool_upload.
+ *    Calls may use different streams: the library orders their device work as if all calls
+ *    had been issued on one stream in call order (renders wait for the last upload; inserts
+ *    for the last insert and upload; an upload for the last insert and upload, and -- only
+ *    before it rewrites node table and brick pool -- for every render issued before it).
+ *    Renders on different streams overlap each other, and an upload's statistics pass
+ *    overlaps renders issued before it, so insertion of the next slices can proceed on one
+ *    stream while another renders.
  *  - Coordinates: world space is level-0 voxel units; the volume occupies [0,Dx]x[0,Dy]x[0,Dz];
  *    voxel (x,y,z) has its centre at (x+1/2, y+1/2, z+1/2).  Volumes and blocks are planar per
  *    channel, [C][z][y][x], x fastest.
@@ -159,8 +164,11 @@ int octree_insert_slices(oct_handle *h, int32_t channel, int32_t z0, int32_t nz,
  * data or neighbourhood changed.  Synchronises `stream` once (statistics read-back).
  * byte_budget limits the bytes of bricks gathered by this call (0 = unlimited); when bricks
  * remain, the call returns OCT_INCOMPLETE and those nodes render with their AVG until a later
- * call gathers them.  `out` may be NULL.  Errors: OCT_ENOMEM when the pool cap cannot hold
- * every brick node (the remaining nodes render with their AVG), OCT_EDEVICE. */
+ * call gathers them.  With a capped pool (device_pool_bytes) brick nodes get slots only when
+ * a render has requested them, coarser levels first, replacing the least recently used slots;
+ * the call returns OCT_INCOMPLETE while requests remain unserved or gathers pending, and the
+ * nodes concerned render with their AVG meanwhile.  `out` may be NULL.  Errors: OCT_ENOMEM
+ * (a device or pinned allocation failed), OCT_EDEVICE. */
 int brick_pool_upload(oct_handle *h, uint64_t byte_budget, void *stream, oct_upload_stats *out);
 
 /* Renders n_views views in one launch (Algorithm 1 with accumulation-level intermixing of the
@@ -187,12 +195,12 @@ int render_views_backward(oct_handle *h, int32_t n_views, const oct_view *views,
                           const float *const *dL_dimages, const void *ckpt_ws, float *dL_dctrl,
                           float *dL_dvoxels, void *stream);
 
-/* Canonical dump of the octree for parity checks (synchronises the handle's stream).
+/* Canonical dump of the octree for parity checks (synchronises the device).
  * Layout (little endian): a 64-byte header "OCTDUMP1", int32 dims[3], C, M, N, dtype,
  * n_nodes, n_bricks; then one 192-byte record per existing node ordered by level descending,
  * then z, y, x: int32 level, bx, by, bz, state (0 empty, 1 homogeneous leaf, 2 homogeneous
- * with children, 3 brick), flags (1 has children, 2 complete, 4 populated), 0, 0; float64
- * avg[4], bmin[4], bmax[4], smin[4], smax[4]; then the bordered (M+2)^3 brick of every brick
+ * with children, 3 brick), flags (1 has children, 2 complete, 4 populated, 8 resident), 0,
+ * 0; float64 avg[4], bmin[4], bmax[4], smin[4], smax[4]; then the bordered (M+2)^3 brick of every brick
  * node in record order, channel-interleaved [z][y][x][C] in the dtype.  Flag 8 marks a brick
  * node whose brick is resident in the pool (renders interpolate it; a non-resident one is
  * sampled with its AVG).  Bricks that are not resident are gathered into a spare slot for

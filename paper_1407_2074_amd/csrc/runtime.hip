@@ -77,6 +77,9 @@ struct oct_handle {
     void *ins_stage = nullptr;   // device staging for host-pointer inserts
     size_t ins_stage_cap = 0;
     hipEvent_t ins_ev = nullptr;
+    // cross-stream order: end of the last insert's kernels / of the last upload's device work
+    hipEvent_t ev_insert = nullptr;
+    hipEvent_t ev_upload = nullptr;
     Stage up;                    // upload: cell list / stats / deltas / jobs
     RenderSlot rs[kRenderSlots];
     int next_rs = 0;
@@ -121,6 +124,23 @@ int64_t cell_index(const VolGeom &g, int L, int x, int y, int z)
 {
     const int G = g.grid[L];
     return g.cell_off[L] + ((int64_t)z * G + y) * G + x;
+}
+
+// Calls may use different streams.  Device work is ordered as if every call had been issued
+// on one stream in call order, with one relaxation: an upload's statistics pass (which reads
+// only the mipmap) does not wait for renders issued before it, only its node-table and
+// brick-pool writes do -- so the next batch's insertion and analysis overlap a render.
+int wait_for(oct_handle *h, hipStream_t s, hipEvent_t ev)
+{
+    if (ev) HIPCHK(h, hipStreamWaitEvent(s, ev, 0));
+    return OCT_OK;
+}
+
+int wait_for_renders(oct_handle *h, hipStream_t s)
+{
+    for (auto &r : h->rs)
+        if (r.st.ev) HIPCHK(h, hipStreamWaitEvent(s, r.st.ev, 0));
+    return OCT_OK;
 }
 
 int stage_reserve(oct_handle *h, Stage &s, size_t bytes)
@@ -437,7 +457,10 @@ int octree_create(const oct_create_params *params, void *stream, oct_handle **ou
     if (hipHostMalloc((void **)&h->flags_host, (size_t)h->n_cells, hipHostMallocDefault) != hipSuccess)
         return bail(OCT_ENOMEM);
     h->last_used.assign((size_t)h->n_cells, 0);
-    if (hipEventCreateWithFlags(&h->ins_ev, hipEventDisableTiming) != hipSuccess) return bail(OCT_EDEVICE);
+    if (hipEventCreateWithFlags(&h->ins_ev, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&h->ev_insert, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&h->ev_upload, hipEventDisableTiming) != hipSuccess)
+        return bail(OCT_EDEVICE);
     if (octree_clear(h, stream) != OCT_OK) return bail(OCT_EDEVICE);
     (void)s;
     *out = h;
@@ -461,6 +484,8 @@ int octree_destroy(oct_handle *h)
     if (h->ins_stage) (void)hipFree(h->ins_stage);
     if (h->bw_tmp) (void)hipFree(h->bw_tmp);
     if (h->ins_ev) (void)hipEventDestroy(h->ins_ev);
+    if (h->ev_insert) (void)hipEventDestroy(h->ev_insert);
+    if (h->ev_upload) (void)hipEventDestroy(h->ev_upload);
     stage_free(h->up);
     for (auto &r : h->rs) stage_free(r.st);
     delete h;
@@ -472,13 +497,21 @@ int octree_clear(oct_handle *h, void *stream)
     if (!h) return OCT_EINVAL;
     HIPCHK(h, hipSetDevice(h->device));
     hipStream_t s = (hipStream_t)stream;
+    int rc = wait_for(h, s, h->ev_insert);
+    if (!rc) rc = wait_for(h, s, h->ev_upload);
+    if (!rc) rc = wait_for_renders(h, s);
+    if (rc) return rc;
     HIPCHK(h, launch_clear(h->g, h->master, h->mask, h->p.background, s));
     HIPCHK(h, launch_fill_u8(h->flags, h->n_cells, 0, s));
     HIPCHK(h, launch_fill_f32(h->miss_range, h->n_cells * 8, h->background_f, s));
     reset_host_state(h);
     std::fill(h->last_used.begin(), h->last_used.end(), 0);
     h->frame = 1;
-    return upload_full_table(h, s);
+    rc = upload_full_table(h, s);
+    if (rc) return rc;
+    HIPCHK(h, hipEventRecord(h->ev_insert, s));
+    HIPCHK(h, hipEventRecord(h->ev_upload, s));
+    return OCT_OK;
 }
 
 int octree_insert_block(oct_handle *h, int32_t channel, const int32_t origin[3],
@@ -511,6 +544,9 @@ int octree_insert_block(oct_handle *h, int32_t channel, const int32_t origin[3],
         HIPCHK(h, hipStreamSynchronize(s));  // host data consumed before return
         src = h->ins_stage;
     }
+    int rc = wait_for(h, s, h->ev_insert);     // overlapping inserts, and the last upload's
+    if (!rc) rc = wait_for(h, s, h->ev_upload);  // gathers (they read the mipmap)
+    if (rc) return rc;
     HIPCHK(h, launch_insert(g, h->master, h->mask, src, channel, origin, size, s));
     Box b;
     for (int a = 0; a < 3; a++) {
@@ -529,6 +565,7 @@ int octree_insert_block(oct_handle *h, int32_t channel, const int32_t origin[3],
         b = p;
     }
     if (!data_is_device) HIPCHK(h, hipEventRecord(h->ins_ev, s));
+    HIPCHK(h, hipEventRecord(h->ev_insert, s));
     return OCT_OK;
 }
 
@@ -548,6 +585,12 @@ int brick_pool_upload(oct_handle *h, uint64_t byte_budget, void *stream, oct_upl
     hipStream_t s = (hipStream_t)stream;
     const VolGeom &g = h->g;
     const int C = g.C, M = g.M;
+    {
+        int rc = wait_for(h, s, h->ev_insert);
+        if (!rc) rc = wait_for(h, s, h->ev_upload);
+        if (!rc && h->capped) rc = wait_for_renders(h, s);   // their flags are read first
+        if (rc) return rc;
+    }
 
     // ---- 1. cells whose level data changed, and cells whose bordered region touches a change
     std::vector<int32_t> stat_cells;  // (L, x, y, z) quadruples
@@ -871,6 +914,7 @@ int brick_pool_upload(oct_handle *h, uint64_t byte_budget, void *stream, oct_upl
     const size_t j_bytes = jobs.size() * sizeof(BrickJob);
     if (d_bytes + j_bytes) {
         int rc = stage_reserve(h, h->up, j_off + j_bytes);
+        if (!rc) rc = wait_for_renders(h, s);   // they read the node table and the pool
         if (rc) return rc;
         if (d_bytes) std::memcpy(h->up.host, deltas.data(), d_bytes);
         if (j_bytes) std::memcpy((uint8_t *)h->up.host + j_off, jobs.data(), j_bytes);
@@ -883,6 +927,7 @@ int brick_pool_upload(oct_handle *h, uint64_t byte_budget, void *stream, oct_upl
                                 h->slot_range, h->background_f, s));
         HIPCHK(h, launch_ranges(g, h->table, h->slot_range, h->miss_range, s));
     }
+    HIPCHK(h, hipEventRecord(h->ev_upload, s));
     if (out) {
         out->bricks_gathered = jobs.size();
         out->bricks_resident = resident;
@@ -1043,6 +1088,8 @@ int render_views(oct_handle *h, int32_t n_views, const oct_view *views, float *c
     std::memcpy(hp + i_off, items.data(), i_bytes);
     std::memset(hp + c_off, 0, sizeof(RenderCounters));
     HIPCHK(h, hipMemcpyAsync(rs.st.dev, hp, c_off + sizeof(RenderCounters), hipMemcpyHostToDevice, s));
+    rc = wait_for(h, s, h->ev_upload);   // the node table and pool of the last upload
+    if (rc) return rc;
     uint8_t *dp = (uint8_t *)rs.st.dev;
     HIPCHK(h, launch_render(h->g, h->table, h->pool, h->brick_bytes, (const DevView *)dp,
                             (const WgItem *)(dp + i_off), (int)items.size(),
@@ -1137,6 +1184,8 @@ int render_views_backward(oct_handle *h, int32_t n_views, const oct_view *views,
     std::memcpy(hp, dvs.data(), v_bytes);
     std::memcpy(hp + i_off, items.data(), i_bytes);
     HIPCHK(h, hipMemcpyAsync(rs.st.dev, hp, i_off + i_bytes, hipMemcpyHostToDevice, s));
+    rc = wait_for(h, s, h->ev_upload);
+    if (rc) return rc;
     uint8_t *dp = (uint8_t *)rs.st.dev;
     HIPCHK(h, launch_render_backward(g, h->table, h->pool, h->brick_bytes, (const DevView *)dp,
                                      (const WgItem *)(dp + i_off), (int)items.size(),

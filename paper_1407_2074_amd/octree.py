@@ -93,8 +93,9 @@ class OctError(RuntimeError):
 
 
 def _stream(stream=None):
+    """A torch.cuda.Stream, a raw hipStream_t as an int, or None (torch's current stream)."""
     if stream is not None:
-        return ct.c_void_p(int(stream))
+        return ct.c_void_p(int(getattr(stream, "cuda_stream", stream)))
     import torch
     return ct.c_void_p(torch.cuda.current_stream().cuda_stream)
 
