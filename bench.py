@@ -139,6 +139,9 @@ def main():
             tree.insert_slices(-1, b * cfg["batch"], slabs[b], stream=bstream)
             tree.upload(stream=bstream)
             if events is not None:
+                # the render waits for this upload anyway; waiting before the start event
+                # keeps the timed interval to the render itself
+                stream.wait_stream(bstream)
                 events[b][0].record(stream)
             if stats is not None:
                 _, st = tree.render([view], images=[img], stats=True, stream=stream)

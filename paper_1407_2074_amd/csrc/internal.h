@@ -61,7 +61,13 @@ struct DevView {
     float *ckpt;
     int32_t *nend;
     int32_t nseg;
-    int32_t pad0;
+    // forward without early termination or checkpoints: each ray is marched as nsplit depth
+    // segments by different waves; segment s of a ray with n positions takes positions
+    // [n s / nsplit, n (s+1) / nsplit) and writes (C, T) to part[s][pixel]; a combine pass
+    // composites the segments front to back into the image
+    int32_t nsplit;
+    float *part;
+    int32_t tile_begin, tile_end;   // tiles rendered by this launch (the combine pass's range)
     // adjoint only: dL/dimage of this view, dL/dtable accumulator [C][256][4]
     const float *dimg;
     float *dlut;
@@ -77,7 +83,7 @@ struct WgItem {
     int32_t view;
     int32_t tile0;
     int32_t ntiles;
-    int32_t pad;
+    int32_t seg;      // depth segment of the rays (0 when the view is not split)
 };
 
 struct BrickJob {       // one bordered brick to (re)build, whole or a sub-box of it
@@ -137,6 +143,9 @@ constexpr int kCkptStride = 64;   // positions per transmittance checkpoint segm
 hipError_t launch_render(const VolGeom &g, const DevCell *table, const void *pool,
                          uint64_t brick_bytes, const DevView *views, const WgItem *items,
                          int n_items, RenderCounters *counters, uint8_t *flags, hipStream_t s);
+// Front-to-back composite of the depth segments of every split view into its image.
+hipError_t launch_combine(const DevView *views, const int32_t *split_views, int n_split,
+                          int64_t max_pixels, hipStream_t s);
 // Adjoint: scratch holds kCkptStride floats per lane of the launch (n_items * 512 lanes).
 hipError_t launch_render_backward(const VolGeom &g, const DevCell *table, const void *pool,
                                   uint64_t brick_bytes, const DevView *views, const WgItem *items,

@@ -12,6 +12,8 @@
 
 #include <float.h>
 
+#include <algorithm>
+
 namespace octrc {
 
 namespace {
@@ -68,8 +70,23 @@ render_body(const VolGeom &g, const DevCell *__restrict__ table, const uint8_t *
                            d[1] != 0.0f ? 1.0f / d[1] : INFINITY,
                            d[2] != 0.0f ? 1.0f / d[2] : INFINITY};
 
+    // positions t_k < t1 (the nominal count): from the estimate, settled with the exact test;
+    // needed for the sample counters, the end positions and the depth-segment bounds
+    const bool split = V.nsplit > 1;
+    int nominal = 0;
+    if (ray.hit && (counters || V.nend || split)) {
+        int kk = max((int)((t1 - t0) / step) - 2, 0);
+        while (t0 + (float)kk * step < t1) kk++;
+        nominal = kk;
+    }
+    int k_begin = 0, k_end = 0x7fffffff;
+    if (split) {
+        k_begin = (int)(((int64_t)nominal * it.seg) / V.nsplit);
+        k_end = (int)(((int64_t)nominal * (it.seg + 1)) / V.nsplit);
+    }
+
     float Tr = 1.0f, Cr = 0.0f, Cg = 0.0f, Cb = 0.0f;
-    int k = 0, composited = 0, trilinear = 0, next_ck = 0;
+    int k = k_begin, composited = 0, trilinear = 0, next_ck = 0;
     int blo[3] = {1, 1, 1}, bhi[3] = {0, 0, 0};  // cached cell, level-0 voxel box (inclusive)
     // positions k_lo..k_hi lie at least 1/64 voxel inside the cached cell (and one step away
     // from its faces), so their voxel test can only confirm the cell and is skipped
@@ -84,7 +101,7 @@ render_body(const VolGeom &g, const DevCell *__restrict__ table, const uint8_t *
     bool live = ray.hit;
     while (live) {
         const float tk = t0 + (float)k * step;
-        if (!(tk < t1)) break;
+        if (!(tk < t1) || k >= k_end) break;
         if (ckpt) {
             // transmittance before every 64th position (unchanged across skipped positions)
             for (; next_ck <= k; next_ck += kCkptStride)
@@ -257,14 +274,11 @@ render_body(const VolGeom &g, const DevCell *__restrict__ table, const uint8_t *
         k++;
     }
 
-    int nominal = 0;
-    if (ray.hit && (counters || V.nend)) {
-        // positions t_k < t1: start from the estimate and settle with the exact test
-        int kk = max((int)((t1 - t0) / step) - 2, 0);
-        while (t0 + (float)kk * step < t1) kk++;
-        nominal = kk;
-    }
-    if (inside) {
+    if (inside && split) {
+        // this segment's premultiplied colour and transmittance, for the combine pass
+        const int64_t npix = (int64_t)V.width * V.height;
+        *(float4 *)(V.part + ((int64_t)it.seg * npix + pix) * 4) = make_float4(Cr, Cg, Cb, Tr);
+    } else if (inside) {
         float4 out = make_float4(Cr, Cg, Cb, 1.0f - Tr);
         *(float4 *)(V.image + pix * 4) = out;
         // first position not evaluated: after early termination k, otherwise the end of the
@@ -277,7 +291,9 @@ render_body(const VolGeom &g, const DevCell *__restrict__ table, const uint8_t *
                 ckpt[pix * V.nseg + next_ck / kCkptStride] = Tr;
     }
     if (counters) {
-        unsigned long long r = ray.hit ? 1ull : 0ull, nn = (unsigned long long)nominal,
+        const bool first = it.seg == 0;   // rays and nominal positions counted once
+        unsigned long long r = (ray.hit && first) ? 1ull : 0ull,
+                           nn = first ? (unsigned long long)nominal : 0ull,
                            cc = (unsigned long long)composited, tt = (unsigned long long)trilinear;
         for (int off = 32; off > 0; off >>= 1) {
             r += __shfl_xor(r, off, 64);
@@ -319,6 +335,31 @@ k_render_f32(VolGeom g, const DevCell *__restrict__ table, const uint8_t *__rest
     render_body<float, C>(g, table, pool, brick_bytes, views, items, counters, flags, tb);
 }
 
+// Front-to-back composite of the depth segments: C = C_0 + T_0 (C_1 + T_1 (...)),
+// T = T_0 T_1 ..., written as premultiplied (C, 1 - T) to the pixels of the rendered tiles.
+__global__ void __launch_bounds__(256)
+k_combine(const DevView *__restrict__ views, const int32_t *__restrict__ split_views)
+{
+    const DevView &V = views[split_views[blockIdx.y]];
+    const int64_t npix = (int64_t)V.width * V.height;
+    for (int64_t pix = (int64_t)blockIdx.x * 256 + threadIdx.x; pix < npix;
+         pix += (int64_t)gridDim.x * 256) {
+        const int px = (int)(pix % V.width), py = (int)(pix / V.width);
+        const int tile = (py >> 3) * V.tiles_x + (px >> 3);
+        if (tile < V.tile_begin || tile >= V.tile_end) continue;
+        float4 acc = *(const float4 *)(V.part + pix * 4);
+        float T = acc.w;
+        for (int sg = 1; sg < V.nsplit; sg++) {
+            const float4 q = *(const float4 *)(V.part + ((int64_t)sg * npix + pix) * 4);
+            acc.x = __builtin_fmaf(T, q.x, acc.x);
+            acc.y = __builtin_fmaf(T, q.y, acc.y);
+            acc.z = __builtin_fmaf(T, q.z, acc.z);
+            T = T * q.w;
+        }
+        *(float4 *)(V.image + pix * 4) = make_float4(acc.x, acc.y, acc.z, 1.0f - T);
+    }
+}
+
 template <typename T, int C>
 void launch_c(const dim3 &grid, const dim3 &block, hipStream_t s, const VolGeom &g,
               const DevCell *table, const uint8_t *p, uint64_t brick_bytes, const DevView *views,
@@ -349,6 +390,16 @@ hipError_t launch_typed(const VolGeom &g, const DevCell *table, const void *pool
 }
 
 }  // namespace
+
+hipError_t launch_combine(const DevView *views, const int32_t *split_views, int n_split,
+                          int64_t max_pixels, hipStream_t s)
+{
+    if (n_split <= 0 || max_pixels <= 0) return hipSuccess;
+    const unsigned gx = (unsigned)std::min<int64_t>((max_pixels + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_combine, dim3(gx, (unsigned)n_split), dim3(256), 0, s, views,
+                       split_views);
+    return hipGetLastError();
+}
 
 hipError_t launch_render(const VolGeom &g, const DevCell *table, const void *pool,
                          uint64_t brick_bytes, const DevView *views, const WgItem *items,

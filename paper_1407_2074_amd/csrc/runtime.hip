@@ -55,7 +55,16 @@ struct Stage {
 
 struct RenderSlot {
     Stage st;
+    float *part = nullptr;   // depth-segment results of split views ([nsplit][pixel] float4)
+    size_t part_cap = 0;
 };
+
+// Depth segments per ray for views without early termination or checkpoints: the longest
+// rays set a launch's duration, and splitting them across waves shortens that critical path.
+#ifndef OCTRC_SPLIT
+#define OCTRC_SPLIT 2
+#endif
+constexpr int kSplit = OCTRC_SPLIT;
 
 constexpr int kRenderSlots = 8;
 
@@ -487,7 +496,10 @@ int octree_destroy(oct_handle *h)
     if (h->ev_insert) (void)hipEventDestroy(h->ev_insert);
     if (h->ev_upload) (void)hipEventDestroy(h->ev_upload);
     stage_free(h->up);
-    for (auto &r : h->rs) stage_free(r.st);
+    for (auto &r : h->rs) {
+        stage_free(r.st);
+        if (r.part) (void)hipFree(r.part);
+    }
     delete h;
     return OCT_OK;
 }
@@ -1053,12 +1065,14 @@ int render_views(oct_handle *h, int32_t n_views, const oct_view *views, float *c
     hipStream_t s = (hipStream_t)stream;
     std::vector<DevView> dvs((size_t)n_views);
     std::vector<WgItem> items;
-    size_t ck_off = 0;
+    std::vector<int32_t> split_views;
+    size_t ck_off = 0, part_floats = 0;
+    int64_t max_split_pixels = 0;
     for (int i = 0; i < n_views; i++) {
         int rc = build_view(h, views[i], images[i], dvs[i]);
         if (rc) return rc;
+        const size_t npix = (size_t)views[i].width * views[i].height;
         if (ckpt_ws) {
-            const size_t npix = (size_t)views[i].width * views[i].height;
             dvs[i].nseg = view_nseg(h, views[i]);
             dvs[i].ckpt = (float *)((uint8_t *)ckpt_ws + ck_off);
             dvs[i].nend = (int32_t *)((uint8_t *)ckpt_ws + ck_off + npix * dvs[i].nseg * 4);
@@ -1067,25 +1081,50 @@ int render_views(oct_handle *h, int32_t n_views, const oct_view *views, float *c
         const int tiles = dvs[i].tiles_x * ((views[i].height + OCT_TILE - 1) / OCT_TILE);
         const int tb = std::min(views[i].tile_begin, tiles);
         const int te = views[i].tile_count < 0 ? tiles : std::min(tiles, tb + views[i].tile_count);
-        for (int t = tb; t < te; t += kRenderTilesPerWg) {
-            WgItem w{};
-            w.view = i;
-            w.tile0 = t;
-            w.ntiles = std::min(kRenderTilesPerWg, te - t);
-            items.push_back(w);
+        // early termination makes a later segment depend on the earlier ones; checkpoints
+        // need the whole ray in one wave
+        const int nsplit = (!ckpt_ws && views[i].ert_alpha >= 1.0f && te > tb) ? kSplit : 1;
+        dvs[i].nsplit = nsplit;
+        dvs[i].tile_begin = tb;
+        dvs[i].tile_end = te;
+        if (nsplit > 1) {
+            dvs[i].part = (float *)(uintptr_t)(part_floats * sizeof(float));   // offset for now
+            part_floats += (size_t)nsplit * npix * 4;
+            split_views.push_back(i);
+            max_split_pixels = std::max<int64_t>(max_split_pixels, (int64_t)npix);
         }
+        for (int t = tb; t < te; t += kRenderTilesPerWg)
+            for (int sg = 0; sg < nsplit; sg++) {
+                WgItem w{};
+                w.view = i;
+                w.tile0 = t;
+                w.ntiles = std::min(kRenderTilesPerWg, te - t);
+                w.seg = sg;
+                items.push_back(w);
+            }
     }
     const size_t v_bytes = dvs.size() * sizeof(DevView);
     const size_t i_off = (v_bytes + 255) & ~(size_t)255;
     const size_t i_bytes = items.size() * sizeof(WgItem);
-    const size_t c_off = (i_off + i_bytes + 255) & ~(size_t)255;
+    const size_t sv_off = (i_off + i_bytes + 255) & ~(size_t)255;
+    const size_t sv_bytes = split_views.size() * sizeof(int32_t);
+    const size_t c_off = (sv_off + sv_bytes + 255) & ~(size_t)255;
     RenderSlot &rs = h->rs[h->next_rs];
     h->next_rs = (h->next_rs + 1) % kRenderSlots;
-    int rc = stage_reserve(h, rs.st, c_off + sizeof(RenderCounters));
+    int rc = stage_reserve(h, rs.st, c_off + sizeof(RenderCounters));   // the slot is idle now
     if (rc) return rc;
+    if (part_floats * sizeof(float) > rs.part_cap) {
+        if (rs.part) HIPCHK(h, hipFree(rs.part));
+        rs.part = nullptr;
+        rs.part_cap = 0;
+        HIPCHK(h, hipMalloc(&rs.part, part_floats * sizeof(float)));
+        rs.part_cap = part_floats * sizeof(float);
+    }
+    for (int i : split_views) dvs[i].part = rs.part + (uintptr_t)dvs[i].part / sizeof(float);
     uint8_t *hp = (uint8_t *)rs.st.host;
     std::memcpy(hp, dvs.data(), v_bytes);
     std::memcpy(hp + i_off, items.data(), i_bytes);
+    std::memcpy(hp + sv_off, split_views.data(), sv_bytes);
     std::memset(hp + c_off, 0, sizeof(RenderCounters));
     HIPCHK(h, hipMemcpyAsync(rs.st.dev, hp, c_off + sizeof(RenderCounters), hipMemcpyHostToDevice, s));
     rc = wait_for(h, s, h->ev_upload);   // the node table and pool of the last upload
@@ -1095,6 +1134,8 @@ int render_views(oct_handle *h, int32_t n_views, const oct_view *views, float *c
                             (const WgItem *)(dp + i_off), (int)items.size(),
                             out ? (RenderCounters *)(dp + c_off) : nullptr,
                             h->capped ? h->flags : nullptr, s));
+    HIPCHK(h, launch_combine((const DevView *)dp, (const int32_t *)(dp + sv_off),
+                             (int)split_views.size(), max_split_pixels, s));
     if (out) {
         HIPCHK(h, hipMemcpyAsync(hp + c_off, dp + c_off, sizeof(RenderCounters), hipMemcpyDeviceToHost, s));
         HIPCHK(h, hipStreamSynchronize(s));

@@ -185,3 +185,21 @@ def test_early_ray_termination(orc, cfg1):
     assert (want[0][..., 3] >= 0.95).sum() > 100
     worst, amb = _compare(t.render([v]), want, margins=mg)
     assert amb <= 0.001 * 64 * 64 + 1
+
+
+def test_depth_segments_match_one_pass(orc, cfg1):
+    """Without early termination a ray is marched as depth segments by different waves and
+    composited afterwards; the same view rendered in one pass (a render that writes adjoint
+    checkpoints is never split) differs only by compositing rounding."""
+    import torch
+    dims, C, M, vol = cfg1
+    t = _build(dims, C, M, vol, 205)
+    views = [synth.make_view(dims, C, 1, az=az, el=el, width=72, height=56, lod=lod)
+             for az, el, lod in ((30.0, 20.0, 0), (250.0, -40.0, -1))]
+    split = t.render(views)
+    ck = torch.zeros(t.ckpt_bytes(views), dtype=torch.uint8, device="cuda")
+    whole = t.render(views, ckpt=ck)
+    for a, b in zip(split, whole):
+        assert float((a - b).abs().max()) <= 2e-6
+    ref = orc.Tree(vol, _full(C, dims), M, 0, 205)
+    _compare(split, ref.render(views))

@@ -62,9 +62,10 @@ def test_paged_upload_on_another_stream_reads_the_render_flags():
     def refine(bstream, rstream):
         from paper_1407_2074_amd.octree import Octree
         probe = Octree(DIMS, C, M, "u16", 0, 205)
-        bb = probe.brick_bytes
+        bb, n_all = probe.brick_bytes, probe.pool_slots
         probe.close()
-        t = Octree(DIMS, C, M, "u16", 0, 205, pool_bytes=60 * bb)
+        # one slot short of every brick: paging on request, and both views fit
+        t = Octree(DIMS, C, M, "u16", 0, 205, pool_bytes=(n_all - 1) * bb)
         t.insert_block(-1, (0, 0, 0), vol, stream=bstream)
         t.upload(stream=bstream)
         imgs = [torch.empty((v.height, v.width, 4), dtype=torch.float32, device="cuda")
