@@ -101,7 +101,13 @@ typedef struct {
     float tf_rgba[OCT_MAX_CHANNELS][OCT_TF_POINTS][4];
     float window[OCT_MAX_CHANNELS][2]; /* intensity (lo, hi) mapped to x = 0..1, hi > lo     */
     int32_t no_skip;            /* 1 disables empty-space skipping (same image, slower)    */
-    int32_t reserved[3];        /* must be 0                                               */
+    int32_t depth_segments;     /* rays of a view without early termination (and without
+                                   checkpoints) are marched as this many depth segments by
+                                   different waves and composited afterwards, which shortens
+                                   a launch's longest serial chain; 0 = library default (6),
+                                   1 = one pass, at most 16.  Only compositing rounding
+                                   differs between segment counts.                        */
+    int32_t reserved[2];        /* must be 0                                               */
 } oct_view;
 
 typedef struct {

@@ -71,6 +71,9 @@ struct DevView {
     // adjoint only: dL/dimage of this view, dL/dtable accumulator [C][256][4]
     const float *dimg;
     float *dlut;
+    // this view's transfer-function tables (value/slope and opacity prefix counts), built
+    // once per launch by k_view_tables and copied into LDS by every workgroup
+    const void *tables;
 };
 
 // One workgroup of a render launch: up to kRenderTilesPerWg consecutive tiles of one view,
@@ -143,6 +146,10 @@ constexpr int kCkptStride = 64;   // positions per transmittance checkpoint segm
 hipError_t launch_render(const VolGeom &g, const DevCell *table, const void *pool,
                          uint64_t brick_bytes, const DevView *views, const WgItem *items,
                          int n_items, RenderCounters *counters, uint8_t *flags, hipStream_t s);
+// Bytes of one view's tables for C channels, and the per-launch kernel that builds them for
+// every view (views[i].tables must point at a buffer of view_tables_bytes(C) bytes).
+size_t view_tables_bytes(int C);
+hipError_t launch_view_tables(const DevView *views, int n_views, int C, hipStream_t s);
 // Front-to-back composite of the depth segments of every split view into its image.
 hipError_t launch_combine(const DevView *views, const int32_t *split_views, int n_split,
                           int64_t max_pixels, hipStream_t s);

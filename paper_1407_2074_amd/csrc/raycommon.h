@@ -41,7 +41,7 @@ __device__ inline float4 tf_entry(const DevView &V, int c, int k)
 // [1] the RGBA slope to entry k+1 (0 for k = 255), so a lookup with fraction f is one fused
 // multiply-add per component; pref[c][k] counts the entries below k with non-zero opacity.
 template <int C>
-struct ViewTables {
+struct alignas(16) ViewTables {
     float4 lut[C][256][2];
     int pref[C][257];
     int wtot[C][4];
@@ -75,6 +75,19 @@ __device__ inline void build_tables(const DevView &V, ViewTables<C> &tb)
             tb.lut[c][tid][1] = make_float4(e1.x - e0.x, e1.y - e0.y, e1.z - e0.z, e1.w - e0.w);
         }
     }
+    __syncthreads();
+}
+
+// The tables of V, built by k_view_tables, copied into LDS by the whole workgroup (a
+// multiple of 16 bytes, 16-byte loads); ends with a barrier.
+template <int C, int kThreadsPerWg>
+__device__ inline void load_tables(const DevView &V, ViewTables<C> &tb)
+{
+    static_assert(sizeof(ViewTables<C>) % 16 == 0, "table copy in 16-byte words");
+    const uint4 *src = (const uint4 *)V.tables;
+    uint4 *dst = (uint4 *)&tb;
+    for (int i = threadIdx.x; i < (int)(sizeof(ViewTables<C>) / 16); i += kThreadsPerWg)
+        dst[i] = src[i];
     __syncthreads();
 }
 

@@ -34,7 +34,7 @@ render_body(const VolGeom &g, const DevCell *__restrict__ table, const uint8_t *
     const WgItem it = items[blockIdx.x];
     const DevView &V = views[it.view];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    build_tables<C>(V, tb);
+    load_tables<C, kThreads>(V, tb);
     if (wave >= it.ntiles) return;  // no barrier below this point
 
     // uniform per-view constants, held in registers for the whole march
@@ -360,6 +360,18 @@ k_combine(const DevView *__restrict__ views, const int32_t *__restrict__ split_v
     }
 }
 
+// One workgroup per view: the view's tables, built in LDS, written to V.tables.
+template <int C>
+__global__ void __launch_bounds__(256) k_view_tables(const DevView *__restrict__ views)
+{
+    __shared__ ViewTables<C> tb;
+    const DevView &V = views[blockIdx.x];
+    build_tables<C>(V, tb);   // ends with a barrier
+    const uint4 *src = (const uint4 *)&tb;
+    uint4 *dst = (uint4 *)V.tables;
+    for (int i = threadIdx.x; i < (int)(sizeof(ViewTables<C>) / 16); i += 256) dst[i] = src[i];
+}
+
 template <typename T, int C>
 void launch_c(const dim3 &grid, const dim3 &block, hipStream_t s, const VolGeom &g,
               const DevCell *table, const uint8_t *p, uint64_t brick_bytes, const DevView *views,
@@ -390,6 +402,29 @@ hipError_t launch_typed(const VolGeom &g, const DevCell *table, const void *pool
 }
 
 }  // namespace
+
+size_t view_tables_bytes(int C)
+{
+    switch (C) {
+    case 1: return sizeof(ViewTables<1>);
+    case 2: return sizeof(ViewTables<2>);
+    case 3: return sizeof(ViewTables<3>);
+    default: return sizeof(ViewTables<4>);
+    }
+}
+
+hipError_t launch_view_tables(const DevView *views, int n_views, int C, hipStream_t s)
+{
+    if (n_views <= 0) return hipSuccess;
+    const dim3 grid(n_views), block(256);
+    switch (C) {
+    case 1: hipLaunchKernelGGL(k_view_tables<1>, grid, block, 0, s, views); break;
+    case 2: hipLaunchKernelGGL(k_view_tables<2>, grid, block, 0, s, views); break;
+    case 3: hipLaunchKernelGGL(k_view_tables<3>, grid, block, 0, s, views); break;
+    default: hipLaunchKernelGGL(k_view_tables<4>, grid, block, 0, s, views); break;
+    }
+    return hipGetLastError();
+}
 
 hipError_t launch_combine(const DevView *views, const int32_t *split_views, int n_split,
                           int64_t max_pixels, hipStream_t s)

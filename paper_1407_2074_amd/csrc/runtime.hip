@@ -57,12 +57,15 @@ struct RenderSlot {
     Stage st;
     float *part = nullptr;   // depth-segment results of split views ([nsplit][pixel] float4)
     size_t part_cap = 0;
+    void *tables = nullptr;  // per-view transfer-function tables of the launch
+    size_t tables_cap = 0;
 };
 
-// Depth segments per ray for views without early termination or checkpoints: the longest
-// rays set a launch's duration, and splitting them across waves shortens that critical path.
+// Default depth segments per ray for views without early termination or checkpoints: the
+// longest rays set a launch's duration, and splitting them across waves shortens that
+// critical path (6 measured fastest for 1024x1024 views of a 512x512x256 octree).
 #ifndef OCTRC_SPLIT
-#define OCTRC_SPLIT 2
+#define OCTRC_SPLIT 6
 #endif
 constexpr int kSplit = OCTRC_SPLIT;
 
@@ -499,6 +502,7 @@ int octree_destroy(oct_handle *h)
     for (auto &r : h->rs) {
         stage_free(r.st);
         if (r.part) (void)hipFree(r.part);
+        if (r.tables) (void)hipFree(r.tables);
     }
     delete h;
     return OCT_OK;
@@ -994,7 +998,9 @@ static int build_view(oct_handle *h, const oct_view &v, float *image, DevView &d
     if (v.lod < -1) return fail(h, OCT_EINVAL, "lod must be >= -1");
     if (v.tile_begin < 0 || v.tile_count < -1) return fail(h, OCT_EINVAL, "bad tile range");
     if (!(v.ert_alpha > 0.0f)) return fail(h, OCT_EINVAL, "ert_alpha must be > 0");
-    for (int i = 0; i < 3; i++)
+    if (v.depth_segments < 0 || v.depth_segments > 16)
+        return fail(h, OCT_EINVAL, "depth_segments must be 0..16");
+    for (int i = 0; i < 2; i++)
         if (v.reserved[i]) return fail(h, OCT_EINVAL, "reserved fields must be 0");
     if (!image) return fail(h, OCT_EINVAL, "null image");
     for (int c = 0; c < g.C; c++) {
@@ -1083,7 +1089,8 @@ int render_views(oct_handle *h, int32_t n_views, const oct_view *views, float *c
         const int te = views[i].tile_count < 0 ? tiles : std::min(tiles, tb + views[i].tile_count);
         // early termination makes a later segment depend on the earlier ones; checkpoints
         // need the whole ray in one wave
-        const int nsplit = (!ckpt_ws && views[i].ert_alpha >= 1.0f && te > tb) ? kSplit : 1;
+        const int want = views[i].depth_segments > 0 ? views[i].depth_segments : kSplit;
+        const int nsplit = (!ckpt_ws && views[i].ert_alpha >= 1.0f && te > tb) ? want : 1;
         dvs[i].nsplit = nsplit;
         dvs[i].tile_begin = tb;
         dvs[i].tile_end = te;
@@ -1093,15 +1100,21 @@ int render_views(oct_handle *h, int32_t n_views, const oct_view *views, float *c
             split_views.push_back(i);
             max_split_pixels = std::max<int64_t>(max_split_pixels, (int64_t)npix);
         }
-        for (int t = tb; t < te; t += kRenderTilesPerWg)
-            for (int sg = 0; sg < nsplit; sg++) {
-                WgItem w{};
-                w.view = i;
-                w.tile0 = t;
-                w.ntiles = std::min(kRenderTilesPerWg, te - t);
-                w.seg = sg;
-                items.push_back(w);
-            }
+        // workgroups are dealt round-robin to the 8 XCDs: items go out in blocks of 8 tile
+        // groups, segment by segment, so all segments of group j land on XCD j like the
+        // unsplit launch (consecutive segments of one group would pin each segment to a
+        // fixed subset of XCDs whenever the segment count divides 8)
+        const int groups = (te - tb + kRenderTilesPerWg - 1) / kRenderTilesPerWg;
+        for (int g0 = 0; g0 < groups; g0 += 8)
+            for (int sg = 0; sg < nsplit; sg++)
+                for (int gi = g0; gi < std::min(g0 + 8, groups); gi++) {
+                    WgItem w{};
+                    w.view = i;
+                    w.tile0 = tb + gi * kRenderTilesPerWg;
+                    w.ntiles = std::min(kRenderTilesPerWg, te - w.tile0);
+                    w.seg = sg;
+                    items.push_back(w);
+                }
     }
     const size_t v_bytes = dvs.size() * sizeof(DevView);
     const size_t i_off = (v_bytes + 255) & ~(size_t)255;
@@ -1121,15 +1134,25 @@ int render_views(oct_handle *h, int32_t n_views, const oct_view *views, float *c
         rs.part_cap = part_floats * sizeof(float);
     }
     for (int i : split_views) dvs[i].part = rs.part + (uintptr_t)dvs[i].part / sizeof(float);
+    const size_t tbytes = view_tables_bytes(h->g.C);
+    if ((size_t)n_views * tbytes > rs.tables_cap) {
+        if (rs.tables) HIPCHK(h, hipFree(rs.tables));
+        rs.tables = nullptr;
+        rs.tables_cap = 0;
+        HIPCHK(h, hipMalloc(&rs.tables, (size_t)n_views * tbytes));
+        rs.tables_cap = (size_t)n_views * tbytes;
+    }
+    for (int i = 0; i < n_views; i++) dvs[i].tables = (const uint8_t *)rs.tables + (size_t)i * tbytes;
     uint8_t *hp = (uint8_t *)rs.st.host;
     std::memcpy(hp, dvs.data(), v_bytes);
     std::memcpy(hp + i_off, items.data(), i_bytes);
     std::memcpy(hp + sv_off, split_views.data(), sv_bytes);
     std::memset(hp + c_off, 0, sizeof(RenderCounters));
     HIPCHK(h, hipMemcpyAsync(rs.st.dev, hp, c_off + sizeof(RenderCounters), hipMemcpyHostToDevice, s));
+    uint8_t *dp = (uint8_t *)rs.st.dev;
+    HIPCHK(h, launch_view_tables((const DevView *)dp, n_views, h->g.C, s));
     rc = wait_for(h, s, h->ev_upload);   // the node table and pool of the last upload
     if (rc) return rc;
-    uint8_t *dp = (uint8_t *)rs.st.dev;
     HIPCHK(h, launch_render(h->g, h->table, h->pool, h->brick_bytes, (const DevView *)dp,
                             (const WgItem *)(dp + i_off), (int)items.size(),
                             out ? (RenderCounters *)(dp + c_off) : nullptr,

@@ -39,7 +39,8 @@ class OctView(ct.Structure):
                 ("ert_alpha", ct.c_float), ("lod", ct.c_int32), ("n_clip", ct.c_int32),
                 ("clip", (ct.c_float * 4) * 3), ("tf_pos", (ct.c_float * 8) * MAXC),
                 ("tf_rgba", ((ct.c_float * 4) * 8) * MAXC), ("window", (ct.c_float * 2) * MAXC),
-                ("no_skip", ct.c_int32), ("reserved", ct.c_int32 * 3)]
+                ("no_skip", ct.c_int32), ("depth_segments", ct.c_int32),
+                ("reserved", ct.c_int32 * 2)]
 
 
 class UploadStats(ct.Structure):
@@ -121,6 +122,7 @@ def to_oct_view(v) -> OctView:
                 o.tf_rgba[c][j][q] = float(rgba[c, j, q])
         o.window[c][0], o.window[c][1] = float(win[c, 0]), float(win[c, 1])
     o.no_skip = int(getattr(v, "no_skip", 0))
+    o.depth_segments = int(getattr(v, "depth_segments", 0))
     return o
 
 

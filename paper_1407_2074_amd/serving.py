@@ -65,7 +65,7 @@ class ServeStats:
 class Server:
     """Tile-level continuous batching on `streams` HIP streams.
 
-    tiles_per_launch: upper bound on the 8x8 tiles one launch carries (8 tiles per workgroup;
+    tiles_per_launch: upper bound on the 8x8 tiles one launch carries (4 tiles per workgroup;
     a full MI355X wants a few thousand workgroups); fb_cap_bytes: framebuffer memory cap for
     admitted requests; chunk_tiles: largest tile range of one request inside one launch."""
 
