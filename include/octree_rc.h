@@ -104,9 +104,10 @@ typedef struct {
     int32_t depth_segments;     /* rays of a view without early termination (and without
                                    checkpoints) are marched as this many depth segments by
                                    different waves and composited afterwards, which shortens
-                                   a launch's longest serial chain; 0 = library default (6),
-                                   1 = one pass, at most 16.  Only compositing rounding
-                                   differs between segment counts.                        */
+                                   a launch's longest serial chain; 0 = automatic (one per
+                                   256 positions of the volume diagonal, at most 6), 1 = one
+                                   pass, at most 16.  Only compositing rounding differs
+                                   between segment counts.                                */
     int32_t reserved[2];        /* must be 0                                               */
 } oct_view;
 

@@ -112,7 +112,11 @@ struct CellDelta {      // one change event applied to the node table
 };
 static_assert(sizeof(CellDelta) == 64, "CellDelta layout");
 
-struct RenderCounters {
+// Sample counters of a render launch, spread over kCounterSlots cache lines (a workgroup adds
+// into slot blockIdx % kCounterSlots; the host sums the slots): one shared line would
+// serialise the atomics of every wave of the launch.
+constexpr int kCounterSlots = 64;
+struct alignas(128) RenderCounters {
     unsigned long long rays, nominal, composited, trilinear;
 };
 

@@ -302,10 +302,11 @@ render_body(const VolGeom &g, const DevCell *__restrict__ table, const uint8_t *
             tt += __shfl_xor(tt, off, 64);
         }
         if (lane == 0) {
-            atomicAdd(&counters->rays, r);
-            atomicAdd(&counters->nominal, nn);
-            atomicAdd(&counters->composited, cc);
-            atomicAdd(&counters->trilinear, tt);
+            RenderCounters *cs = counters + (blockIdx.x & (kCounterSlots - 1));
+            atomicAdd(&cs->rays, r);
+            atomicAdd(&cs->nominal, nn);
+            atomicAdd(&cs->composited, cc);
+            atomicAdd(&cs->trilinear, tt);
         }
     }
 }

@@ -63,11 +63,22 @@ struct RenderSlot {
 
 // Default depth segments per ray for views without early termination or checkpoints: the
 // longest rays set a launch's duration, and splitting them across waves shortens that
-// critical path (6 measured fastest for 1024x1024 views of a 512x512x256 octree).
+// critical path.  One segment per kSplitPositions positions of the longest possible ray (the
+// volume diagonal over the step), at most kSplitMax (6 measured fastest for 1024x1024 views of
+// a 512x512x256 octree; short rays gain nothing and stay whole).
 #ifndef OCTRC_SPLIT
 #define OCTRC_SPLIT 6
 #endif
-constexpr int kSplit = OCTRC_SPLIT;
+constexpr int kSplitMax = OCTRC_SPLIT;
+constexpr double kSplitPositions = 256.0;
+
+int auto_segments(const VolGeom &g, const oct_view &v)
+{
+    const double diag = std::sqrt((double)g.dims[0] * g.dims[0] + (double)g.dims[1] * g.dims[1] +
+                                  (double)g.dims[2] * g.dims[2]);
+    const double n = std::ceil(diag / v.step / kSplitPositions);
+    return (int)std::max(1.0, std::min((double)kSplitMax, n));
+}
 
 constexpr int kRenderSlots = 8;
 
@@ -1089,7 +1100,8 @@ int render_views(oct_handle *h, int32_t n_views, const oct_view *views, float *c
         const int te = views[i].tile_count < 0 ? tiles : std::min(tiles, tb + views[i].tile_count);
         // early termination makes a later segment depend on the earlier ones; checkpoints
         // need the whole ray in one wave
-        const int want = views[i].depth_segments > 0 ? views[i].depth_segments : kSplit;
+        const int want = views[i].depth_segments > 0 ? views[i].depth_segments
+                                                     : auto_segments(h->g, views[i]);
         const int nsplit = (!ckpt_ws && views[i].ert_alpha >= 1.0f && te > tb) ? want : 1;
         dvs[i].nsplit = nsplit;
         dvs[i].tile_begin = tb;
@@ -1124,7 +1136,8 @@ int render_views(oct_handle *h, int32_t n_views, const oct_view *views, float *c
     const size_t c_off = (sv_off + sv_bytes + 255) & ~(size_t)255;
     RenderSlot &rs = h->rs[h->next_rs];
     h->next_rs = (h->next_rs + 1) % kRenderSlots;
-    int rc = stage_reserve(h, rs.st, c_off + sizeof(RenderCounters));   // the slot is idle now
+    const size_t c_bytes = kCounterSlots * sizeof(RenderCounters);
+    int rc = stage_reserve(h, rs.st, c_off + c_bytes);   // the slot is idle now
     if (rc) return rc;
     if (part_floats * sizeof(float) > rs.part_cap) {
         if (rs.part) HIPCHK(h, hipFree(rs.part));
@@ -1147,8 +1160,8 @@ int render_views(oct_handle *h, int32_t n_views, const oct_view *views, float *c
     std::memcpy(hp, dvs.data(), v_bytes);
     std::memcpy(hp + i_off, items.data(), i_bytes);
     std::memcpy(hp + sv_off, split_views.data(), sv_bytes);
-    std::memset(hp + c_off, 0, sizeof(RenderCounters));
-    HIPCHK(h, hipMemcpyAsync(rs.st.dev, hp, c_off + sizeof(RenderCounters), hipMemcpyHostToDevice, s));
+    std::memset(hp + c_off, 0, c_bytes);
+    HIPCHK(h, hipMemcpyAsync(rs.st.dev, hp, c_off + c_bytes, hipMemcpyHostToDevice, s));
     uint8_t *dp = (uint8_t *)rs.st.dev;
     HIPCHK(h, launch_view_tables((const DevView *)dp, n_views, h->g.C, s));
     rc = wait_for(h, s, h->ev_upload);   // the node table and pool of the last upload
@@ -1160,13 +1173,16 @@ int render_views(oct_handle *h, int32_t n_views, const oct_view *views, float *c
     HIPCHK(h, launch_combine((const DevView *)dp, (const int32_t *)(dp + sv_off),
                              (int)split_views.size(), max_split_pixels, s));
     if (out) {
-        HIPCHK(h, hipMemcpyAsync(hp + c_off, dp + c_off, sizeof(RenderCounters), hipMemcpyDeviceToHost, s));
+        HIPCHK(h, hipMemcpyAsync(hp + c_off, dp + c_off, c_bytes, hipMemcpyDeviceToHost, s));
         HIPCHK(h, hipStreamSynchronize(s));
         const RenderCounters *rcnt = (const RenderCounters *)(hp + c_off);
-        out->rays = rcnt->rays;
-        out->positions_nominal = rcnt->nominal;
-        out->positions_composited = rcnt->composited;
-        out->positions_trilinear = rcnt->trilinear;
+        *out = oct_render_stats{};
+        for (int i = 0; i < kCounterSlots; i++) {
+            out->rays += rcnt[i].rays;
+            out->positions_nominal += rcnt[i].nominal;
+            out->positions_composited += rcnt[i].composited;
+            out->positions_trilinear += rcnt[i].trilinear;
+        }
     }
     HIPCHK(h, hipEventRecord(rs.st.ev, s));
     return OCT_OK;

@@ -179,7 +179,7 @@ class View:
     clips: list = field(default_factory=list)   # up to 3 (nx, ny, nz, d): keep n.p >= d
     tile_begin: int = 0
     tile_count: int = -1          # -1 = all tiles from tile_begin
-    depth_segments: int = 0       # 0 = library default, 1 = one pass per ray
+    depth_segments: int = 0       # 0 = automatic (by ray length), 1 = one pass per ray
 
     @property
     def channels(self) -> int:

@@ -87,3 +87,27 @@ def test_oracle_is_separate_from_the_library():
                 assert "import oracle" not in txt and "orc_" not in txt, f
     txt = open(os.path.join(ROOT, "oracle", "oracle.c")).read()
     assert "octree_rc" not in txt and "internal.h" not in txt
+
+
+def test_vectorised_view_marshalling_matches_fieldwise(native):
+    """The numpy marshalling used by render() writes the same bytes as filling the ctypes
+    structure field by field (clips, TFs, windows, flags and tile ranges included)."""
+    from paper_1407_2074_amd import synth
+    vs = []
+    for i in range(6):
+        v = synth.make_view((64, 48, 40), 3, 2 + i, az=33.0 * i, el=10.0 - 7 * i,
+                            width=40 + i, height=24 + 3 * i, lod=i % 3 - 1,
+                            clips=[(1.0, 0.5 * i, 0.0, 3.0 + i)] * (i % 4),
+                            ert_alpha=1.0 if i % 2 else 0.9, tile_begin=i, tile_count=i - 1)
+        v.no_skip = i % 2
+        v.depth_segments = i
+        vs.append(v)
+    a = native.to_oct_views(vs)
+    b = (native.OctView * len(vs))(*[native.to_oct_view(v) for v in vs])
+    assert a.dtype.itemsize == ctypes_sizeof(native.OctView)
+    assert a.tobytes() == bytes(b)
+
+
+def ctypes_sizeof(t):
+    import ctypes as ct
+    return ct.sizeof(t)
