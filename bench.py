@@ -270,14 +270,22 @@ def bench_adjoint(args):
     def fwd():
         t.render([v], images=[img], ckpt=ck)
 
+    gI = [2 * (img - tgt)]
+
     def bwd():
-        t.render_backward([v], [2 * (img - tgt)], ck, dctrl, dvox)
+        t.render_backward([v], gI, ck, dctrl, dvox)
+
+    def bwd_tf_only():
+        t.render_backward([v], gI, ck, dctrl, None)
 
     for _ in range(max(args.warmup, 1)):
         fwd()
+        gI[0] = 2 * (img - tgt)
         bwd()
+        bwd_tf_only()
     tf = _sync_time(fwd, args.steps)
     tb = _sync_time(bwd, args.steps)
+    tb_tf = _sync_time(bwd_tf_only, args.steps)
     nom, comp = st["positions_nominal"], st["positions_composited"]
     out = {"metric": "adjoint Gsamples/s", "value": round(nom / (tf + tb) / 1e9, 3),
            "unit": "Gsamples/s (nominal positions per forward+adjoint)", "n_gpus": 1,
@@ -287,6 +295,7 @@ def bench_adjoint(args):
            "config": {"workload": "256^3x3 f32, 64^3 bricks, 512x512, LOD 0, L2 loss vs "
                                   "perturbed-TF target; forward with checkpoints + adjoint"},
            "forward_ms": round(tf * 1e3, 3), "adjoint_ms": round(tb * 1e3, 3),
+           "adjoint_tf_only_ms": round(tb_tf * 1e3, 3),
            "forward_gsamples_per_s": round(comp / tf / 1e9, 3),
            "adjoint_gsamples_per_s": round(nom / tb / 1e9, 3),
            "positions_nominal": nom, "positions_composited": comp,
