@@ -2,7 +2,10 @@
 // transfer-function control-point RGBA values and to the level-0 voxel values.
 //
 // The forward stored, per ray, the transmittance T before positions 0, 64, 128, ... and the
-// first position it did not evaluate.  Per 64-position segment, last to first, a lane
+// first position it did not evaluate (for a ray split into depth segments: T from the start
+// of the segment, plus each segment's composite, from which a wave walking one segment gets
+// the transmittance in front of it and the colour/opacity behind it).  Per 64-position block,
+// last to first, a lane
 //   1. replays the segment forward from its checkpoint, writing T before each position to a
 //      per-wave scratch area ([position][lane], coalesced), and
 //   2. walks the segment back to front.  With Bc / Ba the colour / opacity of everything
@@ -163,11 +166,34 @@ k_render_backward(VolGeom g, const DevCell *__restrict__ table, const uint8_t *_
         Marcher<T, C> mf(g, table, pool, brick_bytes, ray.L);
         Marcher<T, C> mb(g, table, pool, brick_bytes, ray.L);
         float Bc[3] = {0.0f, 0.0f, 0.0f}, Ba = 0.0f;
-        for (int sg = (n_end + kCkptStride - 1) / kCkptStride - 1; sg >= 0; sg--) {
+        // the checkpoint blocks this wave walks: all of the ray, or the blocks of its depth
+        // segment (the forward split the ray the same way); then T holds the transmittance in
+        // front of the segment and (Bc, Ba) start as the composite of the segments behind it
+        const int nb = (n_end + kCkptStride - 1) / kCkptStride;
+        int b_lo = 0, b_hi = nb;
+        float T_front = 1.0f;
+        if (V.nsplit > 1) {
+            b_lo = (int)(((int64_t)nb * it.seg) / V.nsplit);
+            b_hi = (int)(((int64_t)nb * (it.seg + 1)) / V.nsplit);
+            if (inside) {
+                const int64_t npix = (int64_t)V.width * V.height;
+                for (int j = 0; j < it.seg; j++) T_front *= V.part[((int64_t)j * npix + pix) * 4 + 3];
+                float Tb = 1.0f;
+                for (int j = V.nsplit - 1; j > it.seg; j--) {   // back to front
+                    const float4 q = *(const float4 *)(V.part + ((int64_t)j * npix + pix) * 4);
+                    Bc[0] = __builtin_fmaf(q.w, Bc[0], q.x);
+                    Bc[1] = __builtin_fmaf(q.w, Bc[1], q.y);
+                    Bc[2] = __builtin_fmaf(q.w, Bc[2], q.z);
+                    Tb = Tb * q.w;
+                }
+                Ba = 1.0f - Tb;
+            }
+        }
+        for (int sg = b_hi - 1; sg >= b_lo; sg--) {
             const int k0 = sg * kCkptStride;
             const int k1 = min(k0 + kCkptStride, n_end);
             // 1. forward replay: transmittance before each position of the segment
-            float Tr = V.ckpt[pix * V.nseg + sg];
+            float Tr = T_front * V.ckpt[pix * V.nseg + sg];
             for (int k = k0; k < k1; k++) {
                 const float tk = ray.t0 + (float)k * step;
                 if (!(tk < ray.t1)) break;

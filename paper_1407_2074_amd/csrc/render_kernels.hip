@@ -79,14 +79,22 @@ render_body(const VolGeom &g, const DevCell *__restrict__ table, const uint8_t *
         while (t0 + (float)kk * step < t1) kk++;
         nominal = kk;
     }
+    // segment s of a split ray: positions [n s / S, n (s+1) / S) of its n positions; when
+    // checkpoints are written the bounds are whole 64-position blocks instead, blocks
+    // [nb s / S, nb (s+1) / S) of nb = ceil(n / 64), as the adjoint walks them
     int k_begin = 0, k_end = 0x7fffffff;
-    if (split) {
+    if (split && ckpt) {
+        const int nb = (nominal + kCkptStride - 1) / kCkptStride;
+        k_begin = (int)(((int64_t)nb * it.seg) / V.nsplit) * kCkptStride;
+        k_end = min((int)(((int64_t)nb * (it.seg + 1)) / V.nsplit) * kCkptStride, nominal);
+    } else if (split) {
         k_begin = (int)(((int64_t)nominal * it.seg) / V.nsplit);
         k_end = (int)(((int64_t)nominal * (it.seg + 1)) / V.nsplit);
     }
 
+    // transmittance and colour from the segment's start (the whole ray when not split)
     float Tr = 1.0f, Cr = 0.0f, Cg = 0.0f, Cb = 0.0f;
-    int k = k_begin, composited = 0, trilinear = 0, next_ck = 0;
+    int k = k_begin, composited = 0, trilinear = 0, next_ck = k_begin;
     int blo[3] = {1, 1, 1}, bhi[3] = {0, 0, 0};  // cached cell, level-0 voxel box (inclusive)
     // positions k_lo..k_hi lie at least 1/64 voxel inside the cached cell (and one step away
     // from its faces), so their voxel test can only confirm the cell and is skipped
@@ -274,20 +282,22 @@ render_body(const VolGeom &g, const DevCell *__restrict__ table, const uint8_t *
         k++;
     }
 
-    if (inside && split) {
-        // this segment's premultiplied colour and transmittance, for the combine pass
-        const int64_t npix = (int64_t)V.width * V.height;
-        *(float4 *)(V.part + ((int64_t)it.seg * npix + pix) * 4) = make_float4(Cr, Cg, Cb, Tr);
-    } else if (inside) {
-        float4 out = make_float4(Cr, Cg, Cb, 1.0f - Tr);
-        *(float4 *)(V.image + pix * 4) = out;
+    if (inside) {
+        if (split) {
+            // this segment's premultiplied colour and transmittance, for the combine pass
+            const int64_t npix = (int64_t)V.width * V.height;
+            *(float4 *)(V.part + ((int64_t)it.seg * npix + pix) * 4) = make_float4(Cr, Cg, Cb, Tr);
+        } else {
+            *(float4 *)(V.image + pix * 4) = make_float4(Cr, Cg, Cb, 1.0f - Tr);
+        }
         // first position not evaluated: after early termination k, otherwise the end of the
-        // ray (a skip may have jumped past it)
+        // ray (a skip may have jumped past it); a split ray (no early termination) ends at n
         const int n_end = ray.hit ? (live ? nominal : k) : 0;
-        if (V.nend) V.nend[pix] = n_end;
-        // segments that began inside a final skipped run keep the transmittance of the jump
+        if (V.nend && it.seg == 0) V.nend[pix] = n_end;
+        // checkpoint blocks that begin inside a final skipped run keep the transmittance of
+        // the jump (split: up to the end of this segment's blocks)
         if (ckpt)
-            for (; next_ck < n_end; next_ck += kCkptStride)
+            for (; next_ck < min(n_end, k_end); next_ck += kCkptStride)
                 ckpt[pix * V.nseg + next_ck / kCkptStride] = Tr;
     }
     if (counters) {

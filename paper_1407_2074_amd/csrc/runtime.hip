@@ -980,10 +980,30 @@ static int view_nseg(const oct_handle *h, const oct_view &v)
     return (int)std::ceil(nmax / kCkptStride);
 }
 
+// Depth segments of a view's rays; the forward, the differentiable forward and the adjoint
+// agree on it: none with early termination, else the view's request or the automatic count.
+static int view_segments(const oct_handle *h, const oct_view &v)
+{
+    if (!(v.ert_alpha >= 1.0f)) return 1;
+    if (v.depth_segments > 0) return std::min(v.depth_segments, 16);
+    return auto_segments(h->g, v);
+}
+
+// Checkpoint workspace of one view: [pixel][nseg] float32 transmittance before each block of
+// 64 positions (from the start of the block's depth segment), [pixel] int32 end positions,
+// then for a split view [segment][pixel] float4 (C, T) of every depth segment.
+static size_t view_ckpt_part_offset(const oct_handle *h, const oct_view &v)
+{
+    const size_t npix = (size_t)v.width * v.height;
+    return (npix * (size_t)view_nseg(h, v) * 4 + npix * 4 + 15) & ~(size_t)15;
+}
+
 static size_t view_ckpt_bytes(const oct_handle *h, const oct_view &v)
 {
     const size_t npix = (size_t)v.width * v.height;
-    const size_t b = npix * (size_t)view_nseg(h, v) * 4 + npix * 4;
+    size_t b = view_ckpt_part_offset(h, v);
+    const int S = view_segments(h, v);
+    if (S > 1) b += npix * (size_t)S * 16;
     return (b + 255) & ~(size_t)255;
 }
 
@@ -1083,6 +1103,7 @@ int render_views(oct_handle *h, int32_t n_views, const oct_view *views, float *c
     std::vector<DevView> dvs((size_t)n_views);
     std::vector<WgItem> items;
     std::vector<int32_t> split_views;
+    std::vector<std::pair<int, size_t>> slot_part;   // (view, float offset) in the slot buffer
     size_t ck_off = 0, part_floats = 0;
     int64_t max_split_pixels = 0;
     for (int i = 0; i < n_views; i++) {
@@ -1098,17 +1119,20 @@ int render_views(oct_handle *h, int32_t n_views, const oct_view *views, float *c
         const int tiles = dvs[i].tiles_x * ((views[i].height + OCT_TILE - 1) / OCT_TILE);
         const int tb = std::min(views[i].tile_begin, tiles);
         const int te = views[i].tile_count < 0 ? tiles : std::min(tiles, tb + views[i].tile_count);
-        // early termination makes a later segment depend on the earlier ones; checkpoints
-        // need the whole ray in one wave
-        const int want = views[i].depth_segments > 0 ? views[i].depth_segments
-                                                     : auto_segments(h->g, views[i]);
-        const int nsplit = (!ckpt_ws && views[i].ert_alpha >= 1.0f && te > tb) ? want : 1;
+        // early termination makes a later segment depend on the earlier ones: unsplit then
+        const int nsplit = te > tb ? view_segments(h, views[i]) : 1;
         dvs[i].nsplit = nsplit;
         dvs[i].tile_begin = tb;
         dvs[i].tile_end = te;
         if (nsplit > 1) {
-            dvs[i].part = (float *)(uintptr_t)(part_floats * sizeof(float));   // offset for now
-            part_floats += (size_t)nsplit * npix * 4;
+            if (ckpt_ws) {
+                // the adjoint reads the segment partials back: they live in the workspace
+                dvs[i].part = (float *)((uint8_t *)ckpt_ws + ck_off - view_ckpt_bytes(h, views[i]) +
+                                        view_ckpt_part_offset(h, views[i]));
+            } else {
+                slot_part.push_back({i, part_floats});
+                part_floats += (size_t)nsplit * npix * 4;
+            }
             split_views.push_back(i);
             max_split_pixels = std::max<int64_t>(max_split_pixels, (int64_t)npix);
         }
@@ -1146,7 +1170,7 @@ int render_views(oct_handle *h, int32_t n_views, const oct_view *views, float *c
         HIPCHK(h, hipMalloc(&rs.part, part_floats * sizeof(float)));
         rs.part_cap = part_floats * sizeof(float);
     }
-    for (int i : split_views) dvs[i].part = rs.part + (uintptr_t)dvs[i].part / sizeof(float);
+    for (const auto &sp : slot_part) dvs[sp.first].part = rs.part + sp.second;
     const size_t tbytes = view_tables_bytes(h->g.C);
     if ((size_t)n_views * tbytes > rs.tables_cap) {
         if (rs.tables) HIPCHK(h, hipFree(rs.tables));
@@ -1230,13 +1254,23 @@ int render_views_backward(oct_handle *h, int32_t n_views, const oct_view *views,
         const int tiles = dvs[i].tiles_x * ((views[i].height + OCT_TILE - 1) / OCT_TILE);
         const int tb = std::min(views[i].tile_begin, tiles);
         const int te = views[i].tile_count < 0 ? tiles : std::min(tiles, tb + views[i].tile_count);
-        for (int t = tb; t < te; t += kRenderTilesPerWg) {
-            WgItem w{};
-            w.view = i;
-            w.tile0 = t;
-            w.ntiles = std::min(kRenderTilesPerWg, te - t);
-            items.push_back(w);
-        }
+        // the forward's depth segments: each (tile group, segment) is walked by its own waves
+        const int nsplit = te > tb ? view_segments(h, views[i]) : 1;
+        dvs[i].nsplit = nsplit;
+        if (nsplit > 1)
+            dvs[i].part = (float *)((uint8_t *)ckpt_ws + ck_off - view_ckpt_bytes(h, views[i]) +
+                                    view_ckpt_part_offset(h, views[i]));
+        const int groups = (te - tb + kRenderTilesPerWg - 1) / kRenderTilesPerWg;
+        for (int g0 = 0; g0 < groups; g0 += 8)   // segment order as in the forward
+            for (int sg = 0; sg < nsplit; sg++)
+                for (int gi = g0; gi < std::min(g0 + 8, groups); gi++) {
+                    WgItem w{};
+                    w.view = i;
+                    w.tile0 = tb + gi * kRenderTilesPerWg;
+                    w.ntiles = std::min(kRenderTilesPerWg, te - w.tile0);
+                    w.seg = sg;
+                    items.push_back(w);
+                }
     }
     // device temporaries: per-view table gradients, then the replay scratch
     const size_t dl_bytes = ((size_t)n_views * dlut_floats * 4 + 255) & ~(size_t)255;
