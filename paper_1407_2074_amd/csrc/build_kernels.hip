@@ -102,8 +102,8 @@ k_downsample(VolGeom g, T *master, int L, int lx, int ly, int lz, int hx, int hy
 }
 
 // ---------------------------------------------------------------------------------------
-// Block-wide reductions (4 waves of 64).
-template <typename V, typename Op>
+// Block-wide reductions over kWaves waves of 64 (scratch: kWaves values).
+template <typename V, typename Op, int kWaves = kThreads / 64>
 __device__ inline V block_reduce(V v, Op op, V *scratch)
 {
     for (int o = 32; o > 0; o >>= 1) v = op(v, __shfl_xor(v, o, 64));
@@ -112,7 +112,7 @@ __device__ inline V block_reduce(V v, Op op, V *scratch)
     if (lane == 0) scratch[w] = v;
     __syncthreads();
     V r = scratch[0];
-    for (int i = 1; i < kThreads / 64; i++) r = op(r, scratch[i]);
+    for (int i = 1; i < kWaves; i++) r = op(r, scratch[i]);
     return r;
 }
 
@@ -251,14 +251,20 @@ k_apply_deltas(DevCell *table, float *miss_range, const CellDelta *d, int n)
 // A job rebuilds the whole brick or only the sub-box its inserted data touched.  It also
 // reduces the per-channel min/max of what it wrote: the slot's skip range is replaced by a
 // whole-brick job and widened by a partial one (a superset stays a valid bound).
+// One 1024-thread workgroup per job; thread t owns (x, y) columns t, t + 1024, ... of the
+// job's sub-box and walks z, four slices per round so that several rows of loads are in
+// flight (the job's rows are short, 34 voxels for 32^3 bricks: a thread-per-row walk is
+// latency-bound).
+constexpr int kGatherThreads = 1024;
+
 template <typename T>
-__global__ void __launch_bounds__(kThreads)
+__global__ void __launch_bounds__(kGatherThreads)
 k_gather(VolGeom g, const T *master, const DevCell *table, uint8_t *pool, uint64_t brick_bytes,
          const BrickJob *jobs, float *slot_range, float background)
 {
     __shared__ int s_kind[27];
     __shared__ float s_avg[27][4];
-    __shared__ float sf[kThreads / 64];
+    __shared__ float sf[kGatherThreads / 64];
     const BrickJob job = jobs[blockIdx.x];
     const int L = job.level, M = g.M, S = M + 2, G = g.grid[L];
     const int b[3] = {job.bx, job.by, job.bz};
@@ -285,43 +291,43 @@ k_gather(VolGeom g, const T *master, const DevCell *table, uint8_t *pool, uint64
         mx[c] = -FLT_MAX;
     }
     T *dst = (T *)(pool + (uint64_t)job.slot * brick_bytes);
-    const int nx = job.hi[0] - job.lo[0] + 1;
-    const int rstep = kThreads / nx;
-    const int x = job.lo[0] + threadIdx.x % nx, r0 = threadIdx.x / nx;
-    if (r0 < rstep) {
+    const int nx = job.hi[0] - job.lo[0] + 1, ny = job.hi[1] - job.lo[1] + 1;
+    for (int j = threadIdx.x; j < nx * ny; j += kGatherThreads) {
+        const int x = job.lo[0] + j % nx, y = job.lo[1] + j / nx;
+        // bordered position -> clamped level index, and which of the 3x3x3 neighbours holds it
         const int gx = min(max(b[0] * M - 1 + x, 0), ex - 1);
         const int ox = gx < b[0] * M ? 0 : (gx >= b[0] * M + M ? 2 : 1);
+        const int gy = min(max(b[1] * M - 1 + y, 0), ey - 1);
+        const int oy = gy < b[1] * M ? 0 : (gy >= b[1] * M + M ? 2 : 1);
+        const int64_t row = (int64_t)gy * ex + gx;
+#pragma unroll 4
         for (int z = job.lo[2]; z <= job.hi[2]; z++) {
             const int gz = min(max(b[2] * M - 1 + z, 0), ez - 1);
             const int oz = gz < b[2] * M ? 0 : (gz >= b[2] * M + M ? 2 : 1);
-            for (int y = job.lo[1] + r0; y <= job.hi[1]; y += rstep) {
-                const int gy = min(max(b[1] * M - 1 + y, 0), ey - 1);
-                const int oy = gy < b[1] * M ? 0 : (gy >= b[1] * M + M ? 2 : 1);
-                const int nb = (oz * 3 + oy) * 3 + ox;
-                T v[4];
-                if (s_kind[nb] != kAvg) {
-                    const int64_t lin = ((int64_t)gz * ey + gy) * ex + gx;
-                    for (int c = 0; c < 4; c++) v[c] = c < g.C ? src[(int64_t)c * nlev + lin] : (T)0;
-                } else {
-                    for (int c = 0; c < 4; c++) v[c] = c < g.C ? (T)s_avg[nb][c] : (T)0;
+            const int nb = (oz * 3 + oy) * 3 + ox;
+            T v[4];
+            if (s_kind[nb] != kAvg) {
+                const int64_t lin = (int64_t)gz * ey * ex + row;
+                for (int c = 0; c < 4; c++) v[c] = c < g.C ? src[(int64_t)c * nlev + lin] : (T)0;
+            } else {
+                for (int c = 0; c < 4; c++) v[c] = c < g.C ? (T)s_avg[nb][c] : (T)0;
+            }
+            for (int c = 0; c < kMaxC; c++)
+                if (c < g.C) {
+                    mn[c] = fminf(mn[c], (float)v[c]);
+                    mx[c] = fmaxf(mx[c], (float)v[c]);
                 }
-                for (int c = 0; c < kMaxC; c++)
-                    if (c < g.C) {
-                        mn[c] = fminf(mn[c], (float)v[c]);
-                        mx[c] = fmaxf(mx[c], (float)v[c]);
-                    }
-                const int64_t i = ((int64_t)z * S + y) * S + x;
-                if constexpr (sizeof(T) == 2) {
-                    *(ushort4 *)(dst + i * 4) = make_ushort4(v[0], v[1], v[2], v[3]);
-                } else {
-                    *(float4 *)(dst + i * 4) = make_float4(v[0], v[1], v[2], v[3]);
-                }
+            const int64_t i = ((int64_t)z * S + y) * S + x;
+            if constexpr (sizeof(T) == 2) {
+                *(ushort4 *)(dst + i * 4) = make_ushort4(v[0], v[1], v[2], v[3]);
+            } else {
+                *(float4 *)(dst + i * 4) = make_float4(v[0], v[1], v[2], v[3]);
             }
         }
     }
     for (int c = 0; c < g.C; c++) {
-        const float lo = block_reduce(mn[c], MinF{}, sf);
-        const float hi = block_reduce(mx[c], MaxF{}, sf);
+        const float lo = block_reduce<float, MinF, kGatherThreads / 64>(mn[c], MinF{}, sf);
+        const float hi = block_reduce<float, MaxF, kGatherThreads / 64>(mx[c], MaxF{}, sf);
         if (threadIdx.x == 0) {
             float *r = slot_range + (int64_t)job.slot * 8;
             r[c] = job.full ? lo : fminf(r[c], lo);
@@ -454,11 +460,11 @@ hipError_t launch_gather(const VolGeom &g, const void *master, const DevCell *ta
 {
     if (n == 0) return hipSuccess;
     if (g.dtype == 0)
-        hipLaunchKernelGGL(k_gather<uint16_t>, dim3(n), dim3(kThreads), 0, s, g,
+        hipLaunchKernelGGL(k_gather<uint16_t>, dim3(n), dim3(kGatherThreads), 0, s, g,
                            (const uint16_t *)master, table, (uint8_t *)pool, brick_bytes, jobs,
                            slot_range, background);
     else
-        hipLaunchKernelGGL(k_gather<float>, dim3(n), dim3(kThreads), 0, s, g, (const float *)master,
+        hipLaunchKernelGGL(k_gather<float>, dim3(n), dim3(kGatherThreads), 0, s, g, (const float *)master,
                            table, (uint8_t *)pool, brick_bytes, jobs, slot_range, background);
     return hipGetLastError();
 }
