@@ -63,6 +63,7 @@ def lib():
         L.orc_build.argtypes = [ct.POINTER(_Params), ct.c_void_p, ct.c_void_p]
         L.orc_free.argtypes = [ct.c_void_p]
         L.orc_num_levels.argtypes = [ct.c_void_p]
+        L.orc_tree_depth.argtypes = [ct.POINTER(ct.c_int32), ct.c_int]
         L.orc_level_extent.argtypes = [ct.c_void_p, ct.c_int, ct.c_void_p]
         L.orc_read_level.argtypes = [ct.c_void_p, ct.c_int, ct.c_void_p]
         L.orc_dump.restype = ct.c_size_t
@@ -214,6 +215,12 @@ class Tree:
         lh = np.zeros((view.height, view.width, 2), np.int32)
         lib().orc_rays(self.h, ct.byref(ov), _ptr(out), _ptr(lh))
         return out, lh
+
+
+def tree_depth(dims, brick: int) -> int:
+    """N of Eq. 1 for these dimensions and brick size (no volume needed)."""
+    d = (ct.c_int32 * 3)(*[int(x) for x in dims])
+    return int(lib().orc_tree_depth(d, int(brick)))
 
 
 def apply_inserts(dims, channels: int, inserts, dtype="u16", background=0.0):

@@ -135,15 +135,23 @@ static int imax(int a, int b) { return a > b ? a : b; }
 
 void orc_free(orc_tree *t);
 
+/* Eq. 1: the octree has N+1 levels with N the smallest n for which M * 2^n covers the
+ * largest dimension (the volume is extended virtually to M * 2^N per axis). */
+int orc_tree_depth(const int32_t dims[3], int M)
+{
+    const int dmax = imax(dims[0], imax(dims[1], dims[2]));
+    int N = 0;
+    while ((int64_t)M << N < dmax) N++;
+    return N;
+}
+
 orc_tree *orc_build(const orc_params *p, const void *v0, const uint8_t *mask)
 {
     if (p->channels < 1 || p->channels > ORC_MAXC || p->brick < 2 || (p->brick & 1)) return NULL;
     orc_tree *t = (orc_tree *)calloc(1, sizeof(orc_tree));
     t->p = *p;
     const int C = p->channels, M = p->brick;
-    int dmax = imax(p->dims[0], imax(p->dims[1], p->dims[2]));
-    int N = 0;
-    while ((int64_t)M << N < dmax) N++;
+    const int N = orc_tree_depth(p->dims, M);
     t->N = N;
     for (int L = 0; L <= N; L++) {
         for (int a = 0; a < 3; a++)

@@ -110,15 +110,27 @@ def test_out_of_volume_voxels_do_not_enter_statistics(orc):
     assert st == orc.ST_HOMOG_LEAF and avg[0] == 10
 
 
+def _golden(name):
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", name)) as f:
+        return json.load(f)
+
+
 def test_fig3_incremental_example(orc):
-    """The paper's 1-D example: brick resolution 4, homogeneity threshold 1.
+    """The paper's 1-D example (tests/golden/fig3_incremental_1d.json): brick resolution 4,
+    homogeneity threshold 1, the printed blocks [1,5,2], [3,3,2,2], [4,3,3].
 
     Facts pinned from the narrative: data need not be coherent; a brick with min 3 and max 3 is
     homogeneous, deleted and represented by its AVG 3; a homogeneous parent keeps its subtree
     while a leaf below has min 1 and max 5; after the volume is complete the root is homogeneous
     but no subtree is deleted.  (Block positions are ours; the figure is not available.)"""
-    dims = (16, 1, 1)
-    blocks = [(0, [1, 5, 2]), (8, [3, 3, 2, 2]), (3, [4, 3, 3, 3, 3]), (12, [2, 4, 3, 3])]
+    gd = _golden("fig3_incremental_1d.json")
+    M, thr = gd["brick_resolution"], gd["homogeneity_threshold"]
+    pb, ours = gd["printed_blocks"], gd["ours"]
+    dims = (ours["volume_length"], 1, 1)
+    vals = [pb[0], pb[1], pb[2] + ours["block_3_padding"], ours["block_4"]]
+    blocks = list(zip(ours["block_starts"], vals))
     ins = []
     expect = [
         {(2, 0, 0, 0): orc.ST_BRICK, (1, 0, 0, 0): orc.ST_BRICK, (1, 1, 0, 0): orc.ST_EMPTY,
@@ -133,17 +145,63 @@ def test_fig3_incremental_example(orc):
     for step, (x0, vals) in enumerate(blocks):
         ins.append((-1, (x0, 0, 0), np.array(vals, np.uint16).reshape(1, 1, 1, -1)))
         v0, mask = orc.apply_inserts(dims, 1, ins)
-        t = orc.Tree(v0, mask, 4, background=0, threshold=1)
+        t = orc.Tree(v0, mask, M, background=0, threshold=thr)
         for key, st in expect[step].items():
             assert t.node(*key)[0] == st, (step, key)
         if step == 0:
             assert t.node(0, 2, 0, 0)[0] == orc.ST_NONE      # below an EMPTY leaf
+        if step == 2:
+            out = gd["printed_outcomes"]["after_block_3"]
+            _, recs, _ = orc.parse_dump(t.dump())
+            homog = [r for r in recs if r["head"][4] in (orc.ST_HOMOG_LEAF, orc.ST_HOMOG)]
+            assert len(homog) == out["homogeneous_bricks"]
+            for r in homog:
+                assert (r["bmin"][0], r["bmax"][0], r["avg"][0]) == \
+                    (out["their_min"], out["their_max"], out["their_avg"])
+            leaf = [r for r in recs if tuple(r["head"][:4]) == (0, 0, 0, 0)][0]
+            assert (leaf["bmin"][0], leaf["bmax"][0]) == (out["leftmost_leaf_min"],
+                                                        out["leftmost_leaf_max"])
+            assert bool(t.node(1, 0, 0, 0)[1] & orc.F_HAS_CHILDREN) == \
+                (not out["left_subtree_deleted"])
+    out = gd["printed_outcomes"]["after_block_4"]
     # homogeneous nodes carry AVG 3; the root's subtree survives
     assert t.node(0, 1, 0, 0)[2][0] == 3
     assert t.node(1, 0, 0, 0)[2][0] == 3
     assert t.node(2, 0, 0, 0)[2][0] == 3
     st, fl, _ = t.node(2, 0, 0, 0)
+    assert (st in (orc.ST_HOMOG, orc.ST_HOMOG_LEAF)) == out["root_homogeneous"]
     assert fl & orc.F_HAS_CHILDREN and fl & orc.F_COMPLETE
+    _, recs, _ = orc.parse_dump(t.dump())
+    deleted = [r for r in recs if r["head"][4] == orc.ST_HOMOG_LEAF and r["head"][0] > 0]
+    assert len(deleted) == out["subtrees_deleted"]
+
+
+def test_printed_overheads_and_virtual_extension(orc):
+    """Numbers the paper prints (tests/golden/paper_numbers.json): the brick pool is about 14%
+    larger than the volume; one voxel of border per side costs about 20% at 32^3; and
+    3865 x 1966 x 2893 with 32^3 bricks is extended virtually to 4096^3 (N = 7)."""
+    gd = _golden("paper_numbers.json")
+    # pool: the oracle's brick count for a dense volume over 7 levels, relative to level 0
+    M, N = 2, 6
+    D = M << N
+    rng = np.random.default_rng(5)
+    v0 = rng.integers(0, 65536, size=(1, D, D, D), dtype=np.uint16)
+    t = orc.Tree(v0, _full_mask(1, (D, D, D)), M, 0, 0)
+    hdr, _, bricks = orc.parse_dump(t.dump())
+    overhead = hdr["n_bricks"] * M ** 3 / D ** 3 - 1.0
+    assert abs(overhead - gd["brick_pool_overhead"]["fraction"]) < 0.005, overhead
+    # borders: bordered bricks in the oracle's dump are (M+2)^3
+    Mb = gd["border_overhead_32"]["brick"]
+    v1 = rng.integers(0, 65536, size=(1, Mb, Mb, Mb), dtype=np.uint16)
+    t1 = orc.Tree(v1, _full_mask(1, (Mb, Mb, Mb)), Mb, 0, 0)
+    hdr1, _, b1 = orc.parse_dump(t1.dump())
+    per_brick = len(b1) // (hdr1["n_bricks"] * 2)     # uint16 voxels of one bordered brick
+    assert per_brick == (Mb + 2) ** 3
+    assert abs(per_brick / Mb ** 3 - 1.0 - gd["border_overhead_32"]["fraction"]) < 0.005
+    # virtual extension
+    ve = gd["virtual_extension"]
+    n = orc.tree_depth(ve["dims"], ve["brick"])
+    assert ve["brick"] << n == ve["virtual_edge"] and n == 7
 
 
 def test_threshold_is_strict_and_per_channel(orc):
