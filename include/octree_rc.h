@@ -222,6 +222,14 @@ int octree_read_level(oct_handle *h, int32_t level, void *out, size_t cap, int32
 int octree_info(const oct_handle *h, int32_t *levels, uint64_t *brick_bytes,
                 uint64_t *pool_slots);
 
+/* Render-kernel timing, for measurement.  Each call waits for the renders recorded so far and
+ * returns in *total_ms / *launches (either may be NULL) their summed ray-casting kernel time
+ * and count; then enable = 1 clears the totals and (re)starts recording -- every later
+ * render_views records HIP events around its ray-casting kernel on the call's stream -- and
+ * enable = 0 stops recording.  The table and combine passes of a render are not included.
+ * Errors: OCT_EINVAL, OCT_EDEVICE. */
+int octree_render_timing(oct_handle *h, int32_t enable, double *total_ms, uint64_t *launches);
+
 /* Message describing the last failure on this handle (or of the last octree_create when h is
  * NULL); never NULL. */
 const char *oct_last_error(const oct_handle *h);

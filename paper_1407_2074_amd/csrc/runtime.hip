@@ -59,6 +59,8 @@ struct RenderSlot {
     size_t part_cap = 0;
     void *tables = nullptr;  // per-view transfer-function tables of the launch
     size_t tables_cap = 0;
+    hipEvent_t k0 = nullptr, k1 = nullptr;   // around the render kernel, when timing is on
+    bool k_pending = false;
 };
 
 // Default depth segments per ray for views without early termination or checkpoints: the
@@ -106,6 +108,9 @@ struct oct_handle {
     Stage up;                    // upload: cell list / stats / deltas / jobs
     RenderSlot rs[kRenderSlots];
     int next_rs = 0;
+    bool ktime = false;          // octree_render_timing: record the render kernels
+    double ktime_ms = 0.0;
+    uint64_t ktime_n = 0;
     void *bw_tmp = nullptr;      // adjoint: table-gradient accumulators + replay scratch
     size_t bw_tmp_cap = 0;
     // paging (capped pool): render flags per cell, missing-brick value bounds, LRU stamps
@@ -156,6 +161,19 @@ int64_t cell_index(const VolGeom &g, int L, int x, int y, int z)
 int wait_for(oct_handle *h, hipStream_t s, hipEvent_t ev)
 {
     if (ev) HIPCHK(h, hipStreamWaitEvent(s, ev, 0));
+    return OCT_OK;
+}
+
+// Adds a slot's recorded render-kernel time to the handle's totals (waits for it).
+int collect_kernel_time(oct_handle *h, RenderSlot &r)
+{
+    if (!r.k_pending) return OCT_OK;
+    HIPCHK(h, hipEventSynchronize(r.k1));
+    float ms = 0.0f;
+    HIPCHK(h, hipEventElapsedTime(&ms, r.k0, r.k1));
+    h->ktime_ms += ms;
+    h->ktime_n++;
+    r.k_pending = false;
     return OCT_OK;
 }
 
@@ -514,6 +532,8 @@ int octree_destroy(oct_handle *h)
         stage_free(r.st);
         if (r.part) (void)hipFree(r.part);
         if (r.tables) (void)hipFree(r.tables);
+        if (r.k0) (void)hipEventDestroy(r.k0);
+        if (r.k1) (void)hipEventDestroy(r.k1);
     }
     delete h;
     return OCT_OK;
@@ -1162,6 +1182,7 @@ int render_views(oct_handle *h, int32_t n_views, const oct_view *views, float *c
     h->next_rs = (h->next_rs + 1) % kRenderSlots;
     const size_t c_bytes = kCounterSlots * sizeof(RenderCounters);
     int rc = stage_reserve(h, rs.st, c_off + c_bytes);   // the slot is idle now
+    if (!rc) rc = collect_kernel_time(h, rs);
     if (rc) return rc;
     if (part_floats * sizeof(float) > rs.part_cap) {
         if (rs.part) HIPCHK(h, hipFree(rs.part));
@@ -1190,10 +1211,19 @@ int render_views(oct_handle *h, int32_t n_views, const oct_view *views, float *c
     HIPCHK(h, launch_view_tables((const DevView *)dp, n_views, h->g.C, s));
     rc = wait_for(h, s, h->ev_upload);   // the node table and pool of the last upload
     if (rc) return rc;
+    if (h->ktime) {
+        if (!rs.k0) HIPCHK(h, hipEventCreate(&rs.k0));
+        if (!rs.k1) HIPCHK(h, hipEventCreate(&rs.k1));
+        HIPCHK(h, hipEventRecord(rs.k0, s));
+    }
     HIPCHK(h, launch_render(h->g, h->table, h->pool, h->brick_bytes, (const DevView *)dp,
                             (const WgItem *)(dp + i_off), (int)items.size(),
                             out ? (RenderCounters *)(dp + c_off) : nullptr,
                             h->capped ? h->flags : nullptr, s));
+    if (h->ktime) {
+        HIPCHK(h, hipEventRecord(rs.k1, s));
+        rs.k_pending = true;
+    }
     HIPCHK(h, launch_combine((const DevView *)dp, (const int32_t *)(dp + sv_off),
                              (int)split_views.size(), max_split_pixels, s));
     if (out) {
@@ -1413,6 +1443,24 @@ int octree_read_level(oct_handle *h, int32_t level, void *out, size_t cap, int32
     HIPCHK(h, hipDeviceSynchronize());
     HIPCHK(h, hipMemcpy(out, (uint8_t *)h->master + (size_t)g.lvl_off[level] * h->esz, bytes,
                         hipMemcpyDeviceToHost));
+    return OCT_OK;
+}
+
+int octree_render_timing(oct_handle *h, int32_t enable, double *total_ms, uint64_t *launches)
+{
+    if (!h || (enable != 0 && enable != 1)) return h ? fail(h, OCT_EINVAL, "enable must be 0 or 1") : OCT_EINVAL;
+    HIPCHK(h, hipSetDevice(h->device));
+    for (auto &r : h->rs) {
+        int rc = collect_kernel_time(h, r);
+        if (rc) return rc;
+    }
+    if (total_ms) *total_ms = h->ktime_ms;
+    if (launches) *launches = h->ktime_n;
+    if (enable) {
+        h->ktime_ms = 0.0;
+        h->ktime_n = 0;
+    }
+    h->ktime = enable != 0;
     return OCT_OK;
 }
 

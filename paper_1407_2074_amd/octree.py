@@ -22,7 +22,7 @@ MAXC = 4
 EXPORTS = ["octree_create", "octree_destroy", "octree_clear", "octree_insert_block",
            "octree_insert_slices", "brick_pool_upload", "render_views", "render_ckpt_bytes",
            "render_views_backward", "octree_dump_canonical", "octree_read_level", "octree_info",
-           "oct_last_error"]
+           "octree_render_timing", "oct_last_error"]
 
 
 class CreateParams(ct.Structure):
@@ -79,6 +79,7 @@ def _load():
     L.octree_dump_canonical.argtypes = [vp, vp, sz, ct.POINTER(sz)]
     L.octree_read_level.argtypes = [vp, i32, vp, sz, ct.POINTER(i32)]
     L.octree_info.argtypes = [vp, ct.POINTER(i32), ct.POINTER(u64), ct.POINTER(u64)]
+    L.octree_render_timing.argtypes = [vp, i32, ct.POINTER(ct.c_double), ct.POINTER(u64)]
     L.oct_last_error.restype = ct.c_char_p
     L.oct_last_error.argtypes = [vp]
     return L
@@ -265,6 +266,13 @@ class Octree:
         self._check(lib.render_views_backward(
             self.h, len(views), ov, gp, ct.c_void_p(ckpt.data_ptr()), ct.c_void_p(dctrl.data_ptr()),
             ct.c_void_p(dvox.data_ptr()) if dvox is not None else None, _stream(stream)))
+
+    def render_timing(self, enable: bool):
+        """(total ms, launches) of the render kernels recorded so far (waits for them); then
+        enable=True restarts recording from zero, False stops it."""
+        ms, n = ct.c_double(), ct.c_uint64()
+        self._check(lib.octree_render_timing(self.h, 1 if enable else 0, ct.byref(ms), ct.byref(n)))
+        return ms.value, n.value
 
     def dump(self) -> bytes:
         need = ct.c_size_t()

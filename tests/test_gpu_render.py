@@ -211,3 +211,19 @@ def test_depth_segments_match_one_pass(orc, cfg1):
     with pytest.raises(OctError) as e:
         t.render([dataclasses.replace(views[0], depth_segments=17)])
     assert e.value.code == OCT_EINVAL
+
+
+def test_render_kernel_timing(cfg1):
+    """octree_render_timing counts exactly the render launches made while it is enabled."""
+    dims, C, M, vol = cfg1
+    t = _build(dims, C, M, vol, 205)
+    v = synth.make_view(dims, C, 1, az=40.0, el=25.0, width=64, height=48)
+    t.render([v])
+    ms, n = t.render_timing(True)            # totals before: nothing recorded
+    assert n == 0
+    for _ in range(3):
+        t.render([v, v])
+    ms, n = t.render_timing(False)
+    assert n == 3 and ms > 0.0
+    t.render([v])
+    assert t.render_timing(False) == (ms, n)  # stopped: nothing new recorded
