@@ -70,11 +70,11 @@ render_body(const VolGeom &g, const DevCell *__restrict__ table, const uint8_t *
                            d[1] != 0.0f ? 1.0f / d[1] : INFINITY,
                            d[2] != 0.0f ? 1.0f / d[2] : INFINITY};
 
-    // positions t_k < t1 (the nominal count): from the estimate, settled with the exact test;
-    // needed for the sample counters, the end positions and the depth-segment bounds
+    // positions t_k < t1 (the nominal count): from the estimate, settled with the exact test.
+    // t_k grows with k, so the march tests k against it instead of comparing t_k with t1
     const bool split = V.nsplit > 1;
     int nominal = 0;
-    if (ray.hit && (counters || V.nend || split)) {
+    if (ray.hit) {
         int kk = max((int)((t1 - t0) / step) - 2, 0);
         while (t0 + (float)kk * step < t1) kk++;
         nominal = kk;
@@ -82,7 +82,7 @@ render_body(const VolGeom &g, const DevCell *__restrict__ table, const uint8_t *
     // segment s of a split ray: positions [n s / S, n (s+1) / S) of its n positions; when
     // checkpoints are written the bounds are whole 64-position blocks instead, blocks
     // [nb s / S, nb (s+1) / S) of nb = ceil(n / 64), as the adjoint walks them
-    int k_begin = 0, k_end = 0x7fffffff;
+    int k_begin = 0, k_end = nominal;
     if (split && ckpt) {
         const int nb = (nominal + kCkptStride - 1) / kCkptStride;
         k_begin = (int)(((int64_t)nb * it.seg) / V.nsplit) * kCkptStride;
@@ -101,15 +101,18 @@ render_body(const VolGeom &g, const DevCell *__restrict__ table, const uint8_t *
     int k_lo = 1, k_hi = 0;
     bool brick = false;
     const uint8_t *base = nullptr;
-    float org[3] = {0.0f, 0.0f, 0.0f};
+    // brick coordinate of a position: p 2^-L - (cell origin - 1 border voxel + 1/2 voxel)
+    float bofs[3] = {0.0f, 0.0f, 0.0f};
+    const float imax = (float)(S - 2);                  // last corner-pair origin in the brick
+    const uint32_t row8 = (uint32_t)S * 8u, slice8 = (uint32_t)(S * S) * 8u;
     float avg[C];
 #pragma unroll
     for (int c = 0; c < C; c++) avg[c] = 0.0f;
 
     bool live = ray.hit;
     while (live) {
+        if (k >= k_end) break;
         const float tk = t0 + (float)k * step;
-        if (!(tk < t1) || k >= k_end) break;
         if (ckpt) {
             // transmittance before every 64th position (unchanged across skipped positions)
             for (; next_ck <= k; next_ck += kCkptStride)
@@ -181,9 +184,9 @@ render_body(const VolGeom &g, const DevCell *__restrict__ table, const uint8_t *
                 if (flags && ks.x != kAvg) flags[cidx] = brick ? 1 : 2;  // used / requested
                 if (brick) {
                     base = pool + (uint64_t)ks.y * brick_bytes;
-                    org[0] = (float)(cx * g.M - 1);
-                    org[1] = (float)(cy * g.M - 1);
-                    org[2] = (float)(cz * g.M - 1);
+                    bofs[0] = (float)(cx * g.M) - 0.5f;
+                    bofs[1] = (float)(cy * g.M) - 0.5f;
+                    bofs[2] = (float)(cz * g.M) - 0.5f;
                 } else {
                     const float4 av = *(const float4 *)cell.avg;
                     const float a4[4] = {av.x, av.y, av.z, av.w};
@@ -215,25 +218,29 @@ render_body(const VolGeom &g, const DevCell *__restrict__ table, const uint8_t *
             int ii[3];
 #pragma unroll
             for (int q = 0; q < 3; q++) {
-                const float qq = p[q] * scaleL - 0.5f;
-                const float lq = qq - org[q];
-                const float fl = floorf(lq);
-                f[q] = lq - fl;
+                // p 2^-L is exact (a power-of-two scale), so the fused form rounds once, like
+                // the unfused difference of exact terms
+                const float lq = __builtin_fmaf(p[q], scaleL, -bofs[q]);
+                f[q] = __builtin_amdgcn_fractf(lq);
                 // inside the node, lq lies in [0.5, M + 0.5); the clamp only guards the
-                // bordered brick against addressing outside itself
-                ii[q] = min(max((int)fl, 0), S - 2);
+                // bordered brick against addressing outside itself (truncation of a
+                // non-negative value is its floor)
+                ii[q] = (int)__builtin_amdgcn_fmed3f(lq, 0.0f, imax);
             }
+            // byte offset in the brick, 24-bit multiplies (a bordered brick is < 16 MiB)
+            const uint32_t off = __umul24((uint32_t)ii[2], slice8) +
+                                 __umul24((uint32_t)ii[1], row8) + ((uint32_t)ii[0] << 3);
             if constexpr (sizeof(T) == 2) {
-                const uint8_t *a0 = base + (uint64_t)(((ii[2] * S + ii[1]) * S + ii[0]) * 8);
-                const uint8_t *a1 = a0 + (uint64_t)S * S * 8;
+                const uint8_t *a0 = base + off;
+                const uint8_t *a1 = a0 + slice8;
                 const uint2 w000 = *(const uint2 *)(a0);
                 const uint2 w100 = *(const uint2 *)(a0 + 8);
-                const uint2 w010 = *(const uint2 *)(a0 + S * 8);
-                const uint2 w110 = *(const uint2 *)(a0 + S * 8 + 8);
+                const uint2 w010 = *(const uint2 *)(a0 + row8);
+                const uint2 w110 = *(const uint2 *)(a0 + row8 + 8);
                 const uint2 w001 = *(const uint2 *)(a1);
                 const uint2 w101 = *(const uint2 *)(a1 + 8);
-                const uint2 w011 = *(const uint2 *)(a1 + S * 8);
-                const uint2 w111 = *(const uint2 *)(a1 + S * 8 + 8);
+                const uint2 w011 = *(const uint2 *)(a1 + row8);
+                const uint2 w111 = *(const uint2 *)(a1 + row8 + 8);
 #pragma unroll
                 for (int c = 0; c < C; c++) {
                     auto ch = [&](const uint2 &w) -> float {
@@ -247,7 +254,7 @@ render_body(const VolGeom &g, const DevCell *__restrict__ table, const uint8_t *
                     s[c] = lerpf(lerpf(c00, c10, f[1]), lerpf(c01, c11, f[1]), f[2]);
                 }
             } else {
-                const float4 *a0 = (const float4 *)(base) + ((ii[2] * S + ii[1]) * S + ii[0]);
+                const float4 *a0 = (const float4 *)(base + 2u * off);   // 16-byte voxels
                 const float4 *a1 = a0 + S * S;
                 const float4 w000 = a0[0], w100 = a0[1], w010 = a0[S], w110 = a0[S + 1];
                 const float4 w001 = a1[0], w101 = a1[1], w011 = a1[S], w111 = a1[S + 1];
