@@ -17,12 +17,15 @@
 //      where (gC, gA) = dL/d(pixel RGBA).
 // The event gradient flows into the two table entries it interpolated (LDS accumulator per
 // workgroup, added to the view's table gradient at the end) and, through the table slope and
-// the trilinear weights, into the eight level-0 corner voxels (global float atomics).
+// the trilinear weights, into the eight level-0 corner voxels: summed per lane in registers
+// while the ray stays in one corner cube (a step to a face neighbour keeps the four shared
+// corners) and added to memory with float atomics when corners leave.
 // Every position is evaluated (no empty-space skipping): a zero-opacity sample still has a
 // non-zero gradient with respect to the table.
 #include "raycommon.h"
 
 #include <float.h>
+#include <limits.h>
 
 namespace octrc {
 
@@ -123,6 +126,95 @@ struct Marcher {
     }
 };
 
+// Voxel gradients of one lane's current corner cube (lower corner k, level-0 indices), summed in
+// registers while consecutive positions interpolate in the same cube; a step of one along an
+// axis keeps the four corners the two cubes share, the others are added to memory.
+template <int C>
+struct CubeAcc {
+    float v[C][8];
+    int kx = INT_MIN, ky = 0, kz = 0;
+    float *dvox;
+    int64_t nvox0;
+    int dims[3];
+
+    __device__ CubeAcc(float *d, int64_t n, const int32_t *dm) : dvox(d), nvox0(n)
+    {
+        dims[0] = dm[0];
+        dims[1] = dm[1];
+        dims[2] = dm[2];
+#pragma unroll
+        for (int c = 0; c < C; c++)
+#pragma unroll
+            for (int q = 0; q < 8; q++) v[c][q] = 0.0f;
+    }
+
+    template <int Q>
+    __device__ __forceinline__ void flush_corner()
+    {
+        const int gx = min(max(kx + (Q & 1), 0), dims[0] - 1);
+        const int gy = min(max(ky + ((Q >> 1) & 1), 0), dims[1] - 1);
+        const int gz = min(max(kz + (Q >> 2), 0), dims[2] - 1);
+        const int64_t vi = ((int64_t)gz * dims[1] + gy) * dims[0] + gx;
+#pragma unroll
+        for (int c = 0; c < C; c++) {
+            if (v[c][Q] != 0.0f) atomicAdd(dvox + c * nvox0 + vi, v[c][Q]);
+            v[c][Q] = 0.0f;
+        }
+    }
+
+    template <int Q = 0>
+    __device__ __forceinline__ void flush_all()
+    {
+        if constexpr (Q < 8) {
+            flush_corner<Q>();
+            flush_all<Q + 1>();
+        }
+    }
+
+    // a step of +1 (UP) or -1 along axis bit B: flush the face that leaves, move the other
+    template <int B, bool UP, int Q = 0>
+    __device__ __forceinline__ void shift_face()
+    {
+        if constexpr (Q < 8) {
+            constexpr bool leaves = UP ? !(Q & B) : (Q & B);
+            if constexpr (leaves) {
+                constexpr int P = Q ^ B;   // the corner of the other face on this edge
+                flush_corner<Q>();
+#pragma unroll
+                for (int c = 0; c < C; c++) {
+                    v[c][Q] = v[c][P];
+                    v[c][P] = 0.0f;
+                }
+            }
+            shift_face<B, UP, Q + 1>();
+        }
+    }
+
+    __device__ __forceinline__ void flush()
+    {
+        if (kx != INT_MIN) flush_all();
+        kx = INT_MIN;
+    }
+
+    __device__ __forceinline__ void move_to(int nx, int ny, int nz)
+    {
+        const int dx = nx - kx, dy = ny - ky, dz = nz - kz;
+        if (kx == INT_MIN || abs(dx) > 1 || abs(dy) > 1 || abs(dz) > 1) {
+            flush();
+        } else {
+            if (dx == 1) { shift_face<1, true>(); kx += 1; }
+            else if (dx == -1) { shift_face<1, false>(); kx -= 1; }
+            if (dy == 1) { shift_face<2, true>(); ky += 1; }
+            else if (dy == -1) { shift_face<2, false>(); ky -= 1; }
+            if (dz == 1) { shift_face<4, true>(); kz += 1; }
+            else if (dz == -1) { shift_face<4, false>(); kz -= 1; }
+        }
+        kx = nx;
+        ky = ny;
+        kz = nz;
+    }
+};
+
 template <typename T, int C>
 __global__ void __launch_bounds__(kThreads)
 k_render_backward(VolGeom g, const DevCell *__restrict__ table, const uint8_t *__restrict__ pool,
@@ -166,6 +258,7 @@ k_render_backward(VolGeom g, const DevCell *__restrict__ table, const uint8_t *_
         Marcher<T, C> mf(g, table, pool, brick_bytes, ray.L);
         Marcher<T, C> mb(g, table, pool, brick_bytes, ray.L);
         float Bc[3] = {0.0f, 0.0f, 0.0f}, Ba = 0.0f;
+        CubeAcc<C> acc(dvox, nvox0, g.dims);
         // the checkpoint blocks this wave walks: all of the ray, or the blocks of its depth
         // segment (the forward split the ray the same way); then T holds the transmittance in
         // front of the segment and (Bc, Ba) start as the composite of the segments behind it
@@ -224,6 +317,12 @@ k_render_backward(VolGeom g, const DevCell *__restrict__ table, const uint8_t *_
                 Classified cq[C];
                 float rgba[C][4], Tc[C];
                 float Tp = wscr[(k - k0) * 64 + lane];
+                if (dvox && sm.brick) {
+                    // the corner cube of this sample (level-0 index of its lower corner)
+                    const int kx = sm.org[0] + sm.ii[0], ky = sm.org[1] + sm.ii[1],
+                              kz = sm.org[2] + sm.ii[2];
+                    if (kx != acc.kx || ky != acc.ky || kz != acc.kz) acc.move_to(kx, ky, kz);
+                }
                 for (int c = 0; c < C; c++) {
                     cq[c] = classify(sm.s[c], ulo[c], usc[c], tb.lut[c]);
                     rgba[c][0] = __builtin_fmaf(cq[c].fr, cq[c].de.x, cq[c].e0.x);
@@ -233,6 +332,7 @@ k_render_backward(VolGeom g, const DevCell *__restrict__ table, const uint8_t *_
                     Tc[c] = Tp;
                     Tp = Tp - Tp * rgba[c][3];
                 }
+                #pragma unroll
                 for (int c = C - 1; c >= 0; c--) {
                     const float a = rgba[c][3];
                     float gq[4];
@@ -253,22 +353,20 @@ k_render_backward(VolGeom g, const DevCell *__restrict__ table, const uint8_t *_
                         const float gs = usc[c] * (gq[0] * de.x + gq[1] * de.y + gq[2] * de.z +
                                                    gq[3] * de.w);
                         if (gs != 0.0f) {
-                            float *dv = dvox + (int64_t)c * nvox0;
+#pragma unroll
                             for (int corner = 0; corner < 8; corner++) {
                                 const int dxx = corner & 1, dyy = (corner >> 1) & 1, dzz = corner >> 2;
                                 const float wgt = (dxx ? sm.f[0] : 1.0f - sm.f[0]) *
                                                   (dyy ? sm.f[1] : 1.0f - sm.f[1]) *
                                                   (dzz ? sm.f[2] : 1.0f - sm.f[2]);
-                                const int gx = min(max(sm.org[0] + sm.ii[0] + dxx, 0), g.dims[0] - 1);
-                                const int gy = min(max(sm.org[1] + sm.ii[1] + dyy, 0), g.dims[1] - 1);
-                                const int gz = min(max(sm.org[2] + sm.ii[2] + dzz, 0), g.dims[2] - 1);
-                                atomicAdd(dv + ((int64_t)gz * g.dims[1] + gy) * g.dims[0] + gx, gs * wgt);
+                                acc.v[c][corner] += gs * wgt;
                             }
                         }
                     }
                 }
             }
         }
+        if (dvox) acc.flush();
     }
     __syncthreads();
     for (int i = threadIdx.x; i < C * 256 * 4; i += kThreads) {

@@ -74,6 +74,9 @@ struct DevView {
     // this view's transfer-function tables (value/slope and opacity prefix counts), built
     // once per launch by k_view_tables and copied into LDS by every workgroup
     const void *tables;
+    // views with skipping: one bit per node-table cell, set when the cell is transparent for
+    // this view (built per launch by k_view_mask from the current table); NULL otherwise
+    uint32_t *tmask;
 };
 
 // One workgroup of a render launch: up to kRenderTilesPerWg consecutive tiles of one view,
@@ -154,6 +157,12 @@ hipError_t launch_render(const VolGeom &g, const DevCell *table, const void *poo
 // every view (views[i].tables must point at a buffer of view_tables_bytes(C) bytes).
 size_t view_tables_bytes(int C);
 hipError_t launch_view_tables(const DevView *views, int n_views, int C, hipStream_t s);
+// 32-bit words of one view's transparency mask over n_cells node-table cells (whole 64-cell
+// groups), and the per-launch kernel that fills the mask of every view with tmask != NULL
+// from the current node table (after the tables kernel, which it reads).
+inline int64_t view_mask_words(int64_t n_cells) { return (n_cells + 63) / 64 * 2; }
+hipError_t launch_view_mask(const DevView *views, int n_views, int C, const DevCell *table,
+                            int64_t n_cells, hipStream_t s);
 // Front-to-back composite of the depth segments of every split view into its image.
 hipError_t launch_combine(const DevView *views, const int32_t *split_views, int n_split,
                           int64_t max_pixels, hipStream_t s);

@@ -20,7 +20,14 @@ namespace {
 
 constexpr int kThreads = 64 * kRenderTilesPerWg;   // one wave per tile; the tiles share the tables
 
-template <typename T, int C>
+__device__ __forceinline__ bool mask_bit(const uint32_t *m, int i)
+{
+    return (m[i >> 5] >> (i & 31)) & 1u;
+}
+
+// kErt: the view may terminate rays early (otherwise the opacity test is left out of the
+// march); kCount: sample counters are requested.
+template <typename T, int C, bool kErt, bool kCount>
 __device__ __forceinline__ void
 render_body(const VolGeom &g, const DevCell *__restrict__ table, const uint8_t *__restrict__ pool,
             uint64_t brick_bytes, const DevView *__restrict__ views,
@@ -44,7 +51,11 @@ render_body(const VolGeom &g, const DevCell *__restrict__ table, const uint8_t *
         usc[c] = V.uscale[c];
         ulo[c] = -V.ulo[c] * usc[c];   // table coordinate u = s * usc + ulo
     }
+    const uint32_t *const tmask = V.tmask;
     const float step = V.step;
+    // 1/step for the position bounds of cells (each keeps a margin of a whole step, far above
+    // the relative error of a product with the rounded reciprocal)
+    const float rstep = 1.0f / step;
     const float ert_T = V.ert < 1.0f ? 1.0f - V.ert : -1.0f;
     const bool skip = V.skip != 0;
     float *const ckpt = V.ckpt;
@@ -145,15 +156,14 @@ render_body(const VolGeom &g, const DevCell *__restrict__ table, const uint8_t *
                     cz = v[2] / csz;
                 }
                 const int cidx = coff + (cz * G + cy) * G + cx;
-                const DevCell &cell = table[cidx];
-                if (skip && cell_transparent<C>(cell, ulo, usc, tb.pref)) {
+                if (skip && mask_bit(tmask, cidx)) {
                     // widen to the largest transparent ancestor, jump to just before its exit
                     int lev = L, ax = cx, ay = cy, az = cz;
                     while (lev < g.N) {
                         const int pg = g.grid[lev + 1];
-                        const DevCell &pc = table[g.cell_off[lev + 1] +
-                                                  ((az >> 1) * pg + (ay >> 1)) * pg + (ax >> 1)];
-                        if (!cell_transparent<C>(pc, ulo, usc, tb.pref)) break;
+                        if (!mask_bit(tmask, g.cell_off[lev + 1] +
+                                                 ((az >> 1) * pg + (ay >> 1)) * pg + (ax >> 1)))
+                            break;
                         lev++;
                         ax >>= 1;
                         ay >>= 1;
@@ -168,7 +178,7 @@ render_body(const VolGeom &g, const DevCell *__restrict__ table, const uint8_t *
                         if (d[q] != 0.0f) te = fminf(te, (plane - o[q]) * invd[q]);
                     }
                     // one whole step of margin: every skipped position lies inside the box
-                    const float kf = floorf((te - t0) / step) - 1.0f;
+                    const float kf = floorf((te - t0) * rstep) - 1.0f;
                     k = (kf > (float)(k + 1)) ? (int)fminf(kf, 2.0e9f) : k + 1;
                     blo[0] = 1;
                     bhi[0] = 0;
@@ -176,6 +186,7 @@ render_body(const VolGeom &g, const DevCell *__restrict__ table, const uint8_t *
                     k_hi = 0;
                     continue;
                 }
+                const DevCell &cell = table[cidx];
                 blo[0] = cx * csz; bhi[0] = blo[0] + csz - 1;
                 blo[1] = cy * csz; bhi[1] = blo[1] + csz - 1;
                 blo[2] = cz * csz; bhi[2] = blo[2] + csz - 1;
@@ -204,16 +215,16 @@ render_body(const VolGeom &g, const DevCell *__restrict__ table, const uint8_t *
                         tout = fminf(tout, fmaxf(pa, pb));
                     }
                 }
-                const float klo = ceilf((tin - t0) / step) + 1.0f;
-                const float khi = floorf((tout - t0) / step) - 1.0f;
+                const float klo = ceilf((tin - t0) * rstep) + 1.0f;
+                const float khi = floorf((tout - t0) * rstep) - 1.0f;
                 k_lo = klo > (float)k ? (int)fminf(klo, 2.0e9f) : k;
                 k_hi = khi > (float)k ? (int)fminf(khi, 2.0e9f) : -1;
             }
         }
-        composited++;
+        if constexpr (kCount) composited++;
         float s[C];
         if (brick) {
-            trilinear++;
+            if constexpr (kCount) trilinear++;
             float f[3];
             int ii[3];
 #pragma unroll
@@ -285,7 +296,8 @@ render_body(const VolGeom &g, const DevCell *__restrict__ table, const uint8_t *
             Cb = __builtin_fmaf(wgt, __builtin_fmaf(q.fr, q.de.z, q.e0.z), Cb);
             Tr = Tr - wgt;
         }
-        if (Tr <= ert_T) live = false;  // early ray termination after this position
+        if constexpr (kErt)
+            if (Tr <= ert_T) live = false;  // early ray termination after this position
         k++;
     }
 
@@ -307,7 +319,7 @@ render_body(const VolGeom &g, const DevCell *__restrict__ table, const uint8_t *
             for (; next_ck < min(n_end, k_end); next_ck += kCkptStride)
                 ckpt[pix * V.nseg + next_ck / kCkptStride] = Tr;
     }
-    if (counters) {
+    if (kCount && counters) {
         const bool first = it.seg == 0;   // rays and nominal positions counted once
         unsigned long long r = (ray.hit && first) ? 1ull : 0ull,
                            nn = first ? (unsigned long long)nominal : 0ull,
@@ -340,7 +352,16 @@ k_render_u16(VolGeom g, const DevCell *__restrict__ table, const uint8_t *__rest
              const WgItem *__restrict__ items, RenderCounters *counters, uint8_t *flags)
 {
     __shared__ ViewTables<C> tb;
-    render_body<uint16_t, C>(g, table, pool, brick_bytes, views, items, counters, flags, tb);
+    // uniform per workgroup: one view per work item
+    if (counters)
+        render_body<uint16_t, C, true, true>(g, table, pool, brick_bytes, views, items, counters,
+                                             flags, tb);
+    else if (views[items[blockIdx.x].view].ert < 1.0f)
+        render_body<uint16_t, C, true, false>(g, table, pool, brick_bytes, views, items, counters,
+                                              flags, tb);
+    else
+        render_body<uint16_t, C, false, false>(g, table, pool, brick_bytes, views, items, counters,
+                                               flags, tb);
 }
 
 template <int C>
@@ -350,7 +371,15 @@ k_render_f32(VolGeom g, const DevCell *__restrict__ table, const uint8_t *__rest
              const WgItem *__restrict__ items, RenderCounters *counters, uint8_t *flags)
 {
     __shared__ ViewTables<C> tb;
-    render_body<float, C>(g, table, pool, brick_bytes, views, items, counters, flags, tb);
+    if (counters)
+        render_body<float, C, true, true>(g, table, pool, brick_bytes, views, items, counters,
+                                          flags, tb);
+    else if (views[items[blockIdx.x].view].ert < 1.0f)
+        render_body<float, C, true, false>(g, table, pool, brick_bytes, views, items, counters,
+                                           flags, tb);
+    else
+        render_body<float, C, false, false>(g, table, pool, brick_bytes, views, items, counters,
+                                            flags, tb);
 }
 
 // Front-to-back composite of the depth segments: C = C_0 + T_0 (C_1 + T_1 (...)),
@@ -375,6 +404,35 @@ k_combine(const DevView *__restrict__ views, const int32_t *__restrict__ split_v
             T = T * q.w;
         }
         *(float4 *)(V.image + pix * 4) = make_float4(acc.x, acc.y, acc.z, 1.0f - T);
+    }
+}
+
+// Transparency of every node-table cell for every view that skips: bit i of V.tmask is set
+// when cell i's value range classifies to zero opacity in every channel (cell_transparent with
+// the view's opacity prefix counts).  Grid: (cells / 256, views); one 64-bit ballot per wave.
+template <int C>
+__global__ void __launch_bounds__(256)
+k_view_mask(const DevView *__restrict__ views, const DevCell *__restrict__ table, int64_t n_cells)
+{
+    const DevView &V = views[blockIdx.y];
+    if (!V.tmask) return;
+    __shared__ int pref[C][257];
+    const ViewTables<C> *tb = (const ViewTables<C> *)V.tables;
+    for (int i = threadIdx.x; i < C * 257; i += 256) (&pref[0][0])[i] = (&tb->pref[0][0])[i];
+    __syncthreads();
+    float ulo[C], usc[C];
+#pragma unroll
+    for (int c = 0; c < C; c++) {
+        usc[c] = V.uscale[c];
+        ulo[c] = -V.ulo[c] * usc[c];
+    }
+    const int64_t cell = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const bool t = cell < n_cells && cell_transparent<C>(table[cell], ulo, usc, pref);
+    const unsigned long long b = __ballot(t);
+    const int64_t first = cell & ~(int64_t)63;   // first cell of this wave
+    if ((threadIdx.x & 63) == 0 && first < n_cells) {
+        V.tmask[first >> 5] = (uint32_t)b;
+        V.tmask[(first >> 5) + 1] = (uint32_t)(b >> 32);
     }
 }
 
@@ -440,6 +498,20 @@ hipError_t launch_view_tables(const DevView *views, int n_views, int C, hipStrea
     case 2: hipLaunchKernelGGL(k_view_tables<2>, grid, block, 0, s, views); break;
     case 3: hipLaunchKernelGGL(k_view_tables<3>, grid, block, 0, s, views); break;
     default: hipLaunchKernelGGL(k_view_tables<4>, grid, block, 0, s, views); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_view_mask(const DevView *views, int n_views, int C, const DevCell *table,
+                            int64_t n_cells, hipStream_t s)
+{
+    if (n_views <= 0 || n_cells <= 0) return hipSuccess;
+    const dim3 grid((unsigned)((n_cells + 255) / 256), (unsigned)n_views), block(256);
+    switch (C) {
+    case 1: hipLaunchKernelGGL(k_view_mask<1>, grid, block, 0, s, views, table, n_cells); break;
+    case 2: hipLaunchKernelGGL(k_view_mask<2>, grid, block, 0, s, views, table, n_cells); break;
+    case 3: hipLaunchKernelGGL(k_view_mask<3>, grid, block, 0, s, views, table, n_cells); break;
+    default: hipLaunchKernelGGL(k_view_mask<4>, grid, block, 0, s, views, table, n_cells); break;
     }
     return hipGetLastError();
 }

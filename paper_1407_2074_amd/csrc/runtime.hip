@@ -59,6 +59,8 @@ struct RenderSlot {
     size_t part_cap = 0;
     void *tables = nullptr;  // per-view transfer-function tables of the launch
     size_t tables_cap = 0;
+    uint32_t *tmask = nullptr;  // per-view cell transparency masks of the launch
+    size_t tmask_cap = 0;
     hipEvent_t k0 = nullptr, k1 = nullptr;   // around the render kernel, when timing is on
     bool k_pending = false;
 };
@@ -532,6 +534,7 @@ int octree_destroy(oct_handle *h)
         stage_free(r.st);
         if (r.part) (void)hipFree(r.part);
         if (r.tables) (void)hipFree(r.tables);
+        if (r.tmask) (void)hipFree(r.tmask);
         if (r.k0) (void)hipEventDestroy(r.k0);
         if (r.k1) (void)hipEventDestroy(r.k1);
     }
@@ -1201,6 +1204,18 @@ int render_views(oct_handle *h, int32_t n_views, const oct_view *views, float *c
         rs.tables_cap = (size_t)n_views * tbytes;
     }
     for (int i = 0; i < n_views; i++) dvs[i].tables = (const uint8_t *)rs.tables + (size_t)i * tbytes;
+    const int64_t mwords = view_mask_words(h->n_cells);
+    int n_skip = 0;
+    for (int i = 0; i < n_views; i++) n_skip += dvs[i].skip ? 1 : 0;
+    if ((size_t)n_skip * mwords * 4 > rs.tmask_cap) {
+        if (rs.tmask) HIPCHK(h, hipFree(rs.tmask));
+        rs.tmask = nullptr;
+        rs.tmask_cap = 0;
+        HIPCHK(h, hipMalloc((void **)&rs.tmask, (size_t)n_skip * mwords * 4));
+        rs.tmask_cap = (size_t)n_skip * mwords * 4;
+    }
+    for (int i = 0, j = 0; i < n_views; i++)
+        dvs[i].tmask = dvs[i].skip ? rs.tmask + (size_t)(j++) * mwords : nullptr;
     uint8_t *hp = (uint8_t *)rs.st.host;
     std::memcpy(hp, dvs.data(), v_bytes);
     std::memcpy(hp + i_off, items.data(), i_bytes);
@@ -1211,6 +1226,7 @@ int render_views(oct_handle *h, int32_t n_views, const oct_view *views, float *c
     HIPCHK(h, launch_view_tables((const DevView *)dp, n_views, h->g.C, s));
     rc = wait_for(h, s, h->ev_upload);   // the node table and pool of the last upload
     if (rc) return rc;
+    if (n_skip) HIPCHK(h, launch_view_mask((const DevView *)dp, n_views, h->g.C, h->table, h->n_cells, s));
     if (h->ktime) {
         if (!rs.k0) HIPCHK(h, hipEventCreate(&rs.k0));
         if (!rs.k1) HIPCHK(h, hipEventCreate(&rs.k1));

@@ -180,6 +180,7 @@ class View:
     tile_begin: int = 0
     tile_count: int = -1          # -1 = all tiles from tile_begin
     depth_segments: int = 0       # 0 = automatic (by ray length), 1 = one pass per ray
+    no_skip: int = 0              # 1 = march every position (no empty-space skipping)
 
     @property
     def channels(self) -> int:

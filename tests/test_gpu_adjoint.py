@@ -75,6 +75,43 @@ def test_adjoint_matches_oracle_gradient(orc):
         assert _rel(dvox[c], rv[c]) <= 1e-3
 
 
+@pytest.mark.parametrize("step", [0.5, 1.0, 2.5])
+def test_voxel_gradient_along_axes_and_steps(orc, step):
+    """Rays close to each axis in both directions, at steps that move a sample's corner cube
+    by at most one voxel per axis (the shared corners' sums are kept) or jump further: voxel
+    by voxel against the oracle, volume faces included (clamped corner indices)."""
+    import dataclasses
+    dims, C, M = (34, 30, 28), 3, 8
+    vol = synth.gen_volume(dims, C, seed=9, n_blobs=10, dtype="f32")
+    t = _tree(dims, C, M, vol)
+    base = _views(dims, C, 1, 40, 36, seed=9)[0]
+    base.tf_rgba[:, 2:, 3] = 0.03      # semi-transparent: gradient reaches every depth
+    views = []
+    for az, el in ((0.0, 0.0), (90.0, 0.0), (180.0, 0.0), (270.0, 0.0), (30.0, 80.0),
+                   (210.0, -80.0)):
+        v = synth.make_view(dims, C, 9, az=az, el=el, width=40, height=36, dtype="f32")
+        views.append(dataclasses.replace(v, tf_pos=base.tf_pos, tf_rgba=base.tf_rgba, step=step))
+    rng = np.random.default_rng(2)
+    tgt = [rng.uniform(0, 0.3, size=(v.height, v.width, 4)) for v in views]
+
+    def dL(imgs):
+        return [2 * (im.cpu().numpy().astype(np.float64) - g) for im, g in zip(imgs, tgt)]
+
+    _, dctrl, dvox = _gpu_grads(t, views, dL)
+    ref = orc.Tree(vol, _full(C, dims), M, 0.0, 0.0)
+    gI = [2 * (w - g) for w, g in zip(ref.render(views), tgt)]
+    rc, rv = ref.render_grad(views, gI)
+    assert np.abs(rv).max() > 0
+    assert _rel(dctrl, rc) <= 1e-3
+    assert _rel(dvox, rv) <= 1e-3, _rel(dvox, rv)
+    err = np.abs(dvox - rv).max()
+    assert err <= 1e-3 * np.abs(rv).max(), (err, np.abs(rv).max())
+    # every face of the volume receives gradient (rays enter through each of them)
+    for sl in (np.s_[:, 0], np.s_[:, -1], np.s_[:, :, 0], np.s_[:, :, -1], np.s_[..., 0],
+               np.s_[..., -1]):
+        assert np.abs(rv[sl]).max() > 0
+
+
 def test_adjoint_matches_finite_differences(orc):
     """50 parameters: 25 control-point components and 25 voxels, central differences of the
     FP64 oracle forward with eps 1e-3; voxels are taken where the table is linear across the

@@ -105,6 +105,29 @@ def test_batched_views_equal_single_launches(orc, cfg1):
     _compare(batched, ref.render(views))
 
 
+def test_mixed_skip_views_in_one_launch(cfg1):
+    """Views with and without empty-space skipping and with different transfer functions in
+    one launch (each skipping view reads its own per-launch transparency mask): every image
+    equals the view rendered alone, and skipping does not change it."""
+    import dataclasses
+
+    import torch
+    dims, C, M, vol = cfg1
+    vol = vol.copy()
+    vol[:, :, :, 24:] = np.minimum(vol[:, :, :, 24:], 80)   # noise-level half: transparent
+    t = _build(dims, C, M, vol, 205)
+    views = []
+    for i, (az, el) in enumerate(((30.0, 20.0), (120.0, -30.0), (250.0, 50.0), (300.0, 5.0))):
+        v = synth.make_view(dims, C, 11 + i, az=az, el=el, width=40, height=36)
+        views.append(dataclasses.replace(v, no_skip=i % 2))
+    batched = t.render(views)
+    for v, b in zip(views, batched):
+        (alone,) = t.render([v])
+        assert torch.equal(alone, b)
+        (other,) = t.render([dataclasses.replace(v, no_skip=1 - v.no_skip)])
+        assert torch.equal(other, b)
+
+
 def test_tile_ranges_compose_the_image(cfg1):
     import torch
     dims, C, M, vol = cfg1
