@@ -47,6 +47,13 @@ struct alignas(16) ViewTables {
     int wtot[C][4];
 };
 
+// The part of a view's tables the forward march reads (the value/slope table, which leads
+// ViewTables): transparency comes from the per-launch cell mask instead of the prefix counts.
+template <int C>
+struct alignas(16) LutTable {
+    float4 lut[C][256][2];
+};
+
 // Called by every thread of the workgroup (blockDim >= 256); ends with a barrier.
 template <int C>
 __device__ inline void build_tables(const DevView &V, ViewTables<C> &tb)
@@ -78,15 +85,15 @@ __device__ inline void build_tables(const DevView &V, ViewTables<C> &tb)
     __syncthreads();
 }
 
-// The tables of V, built by k_view_tables, copied into LDS by the whole workgroup (a
-// multiple of 16 bytes, 16-byte loads); ends with a barrier.
-template <int C, int kThreadsPerWg>
-__device__ inline void load_tables(const DevView &V, ViewTables<C> &tb)
+// The leading sizeof(Tab) bytes of V's tables (built by k_view_tables) copied into LDS by the
+// whole workgroup (a multiple of 16 bytes, 16-byte loads); ends with a barrier.
+template <int kThreadsPerWg, typename Tab>
+__device__ inline void load_tables(const DevView &V, Tab &tb)
 {
-    static_assert(sizeof(ViewTables<C>) % 16 == 0, "table copy in 16-byte words");
+    static_assert(sizeof(Tab) % 16 == 0, "table copy in 16-byte words");
     const uint4 *src = (const uint4 *)V.tables;
     uint4 *dst = (uint4 *)&tb;
-    for (int i = threadIdx.x; i < (int)(sizeof(ViewTables<C>) / 16); i += kThreadsPerWg)
+    for (int i = threadIdx.x; i < (int)(sizeof(Tab) / 16); i += kThreadsPerWg)
         dst[i] = src[i];
     __syncthreads();
 }

@@ -20,9 +20,11 @@ namespace {
 
 constexpr int kThreads = 64 * kRenderTilesPerWg;   // one wave per tile; the tiles share the tables
 
-__device__ __forceinline__ bool mask_bit(const uint32_t *m, int i)
+// Bit i of a view's transparency mask: from its LDS copy when one was staged, else global.
+__device__ __forceinline__ bool mask_bit(const uint32_t *m, const uint32_t *lds, int in_lds, int i)
 {
-    return (m[i >> 5] >> (i & 31)) & 1u;
+    const uint32_t w = in_lds > 0 ? lds[i >> 5] : m[i >> 5];
+    return (w >> (i & 31)) & 1u;
 }
 
 // kErt: the view may terminate rays early (otherwise the opacity test is left out of the
@@ -32,7 +34,7 @@ __device__ __forceinline__ void
 render_body(const VolGeom &g, const DevCell *__restrict__ table, const uint8_t *__restrict__ pool,
             uint64_t brick_bytes, const DevView *__restrict__ views,
             const WgItem *__restrict__ items, RenderCounters *counters, uint8_t *flags,
-            ViewTables<C> &tb)
+            LutTable<C> &tb, int mask_lds)
 {
 
     // items stay in dispatch order: the hardware deals workgroups round-robin to the XCDs, which
@@ -41,7 +43,12 @@ render_body(const VolGeom &g, const DevCell *__restrict__ table, const uint8_t *
     const WgItem it = items[blockIdx.x];
     const DevView &V = views[it.view];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    load_tables<C, kThreads>(V, tb);
+    // a small transparency mask (mask_lds words, the same for every view of the launch) is
+    // staged in LDS next to the table; the barrier of load_tables covers both copies
+    extern __shared__ uint32_t smask[];
+    if (mask_lds > 0 && V.tmask)
+        for (int i = threadIdx.x; i < mask_lds; i += kThreads) smask[i] = V.tmask[i];
+    load_tables<kThreads>(V, tb);
     if (wave >= it.ntiles) return;  // no barrier below this point
 
     // uniform per-view constants, held in registers for the whole march
@@ -156,12 +163,12 @@ render_body(const VolGeom &g, const DevCell *__restrict__ table, const uint8_t *
                     cz = v[2] / csz;
                 }
                 const int cidx = coff + (cz * G + cy) * G + cx;
-                if (skip && mask_bit(tmask, cidx)) {
+                if (skip && mask_bit(tmask, smask, mask_lds, cidx)) {
                     // widen to the largest transparent ancestor, jump to just before its exit
                     int lev = L, ax = cx, ay = cy, az = cz;
                     while (lev < g.N) {
                         const int pg = g.grid[lev + 1];
-                        if (!mask_bit(tmask, g.cell_off[lev + 1] +
+                        if (!mask_bit(tmask, smask, mask_lds, g.cell_off[lev + 1] +
                                                  ((az >> 1) * pg + (ay >> 1)) * pg + (ax >> 1)))
                             break;
                         lev++;
@@ -340,46 +347,48 @@ render_body(const VolGeom &g, const DevCell *__restrict__ table, const uint8_t *
     }
 }
 
-// uint16 bricks fit 6 waves per SIMD in registers; float32 bricks (twice the corner data)
-// keep the compiler's choice.
+// uint16 bricks: registers for 5 waves per SIMD (6 fit only with spills, measured 2 % slower);
+// float32 bricks (twice the corner data) keep the compiler's choice.
 template <int C>
 #ifndef OCTRC_U16_WAVES_PER_EU
-#define OCTRC_U16_WAVES_PER_EU 6
+#define OCTRC_U16_WAVES_PER_EU 5
 #endif
 __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(OCTRC_U16_WAVES_PER_EU)))
 k_render_u16(VolGeom g, const DevCell *__restrict__ table, const uint8_t *__restrict__ pool,
              uint64_t brick_bytes, const DevView *__restrict__ views,
-             const WgItem *__restrict__ items, RenderCounters *counters, uint8_t *flags)
+             const WgItem *__restrict__ items, RenderCounters *counters, uint8_t *flags,
+             int mask_lds)
 {
-    __shared__ ViewTables<C> tb;
+    __shared__ LutTable<C> tb;
     // uniform per workgroup: one view per work item
     if (counters)
         render_body<uint16_t, C, true, true>(g, table, pool, brick_bytes, views, items, counters,
-                                             flags, tb);
+                                             flags, tb, mask_lds);
     else if (views[items[blockIdx.x].view].ert < 1.0f)
         render_body<uint16_t, C, true, false>(g, table, pool, brick_bytes, views, items, counters,
-                                              flags, tb);
+                                              flags, tb, mask_lds);
     else
         render_body<uint16_t, C, false, false>(g, table, pool, brick_bytes, views, items, counters,
-                                               flags, tb);
+                                               flags, tb, mask_lds);
 }
 
 template <int C>
 __global__ void __launch_bounds__(kThreads)
 k_render_f32(VolGeom g, const DevCell *__restrict__ table, const uint8_t *__restrict__ pool,
              uint64_t brick_bytes, const DevView *__restrict__ views,
-             const WgItem *__restrict__ items, RenderCounters *counters, uint8_t *flags)
+             const WgItem *__restrict__ items, RenderCounters *counters, uint8_t *flags,
+             int mask_lds)
 {
-    __shared__ ViewTables<C> tb;
+    __shared__ LutTable<C> tb;
     if (counters)
         render_body<float, C, true, true>(g, table, pool, brick_bytes, views, items, counters,
-                                          flags, tb);
+                                          flags, tb, mask_lds);
     else if (views[items[blockIdx.x].view].ert < 1.0f)
         render_body<float, C, true, false>(g, table, pool, brick_bytes, views, items, counters,
-                                           flags, tb);
+                                           flags, tb, mask_lds);
     else
         render_body<float, C, false, false>(g, table, pool, brick_bytes, views, items, counters,
-                                            flags, tb);
+                                            flags, tb, mask_lds);
 }
 
 // Front-to-back composite of the depth segments: C = C_0 + T_0 (C_1 + T_1 (...)),
@@ -453,12 +462,17 @@ void launch_c(const dim3 &grid, const dim3 &block, hipStream_t s, const VolGeom 
               const DevCell *table, const uint8_t *p, uint64_t brick_bytes, const DevView *views,
               const WgItem *items, RenderCounters *counters, uint8_t *flags)
 {
+    // masks of up to 1024 words (32768 cells: trees of up to five levels) go to LDS
+    constexpr int64_t kMaskLdsWords = 1024;
+    const int64_t words = view_mask_words((int64_t)g.cell_off[g.N] + 1);
+    const int mask_lds = words <= kMaskLdsWords ? (int)words : 0;
+    const size_t shm = (size_t)mask_lds * 4;
     if constexpr (sizeof(T) == 2)
-        hipLaunchKernelGGL((k_render_u16<C>), grid, block, 0, s, g, table, p, brick_bytes, views,
-                           items, counters, flags);
+        hipLaunchKernelGGL((k_render_u16<C>), grid, block, shm, s, g, table, p, brick_bytes, views,
+                           items, counters, flags, mask_lds);
     else
-        hipLaunchKernelGGL((k_render_f32<C>), grid, block, 0, s, g, table, p, brick_bytes, views,
-                           items, counters, flags);
+        hipLaunchKernelGGL((k_render_f32<C>), grid, block, shm, s, g, table, p, brick_bytes, views,
+                           items, counters, flags, mask_lds);
 }
 
 template <typename T>
