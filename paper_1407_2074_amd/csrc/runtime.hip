@@ -63,6 +63,7 @@ struct RenderSlot {
     size_t tmask_cap = 0;
     hipEvent_t k0 = nullptr, k1 = nullptr;   // around the render kernel, when timing is on
     bool k_pending = false;
+    int64_t version = -1;   // node-table version the slot's last launch read
 };
 
 // Default depth segments per ray for views without early termination or checkpoints: the
@@ -96,9 +97,18 @@ struct oct_handle {
     int64_t n_cells = 0;
     uint64_t brick_bytes = 0;
     int64_t n_slots = 0;
+    // Uncapped pools hold n_cow slots more, so that an upload can rebuild a brick that renders
+    // in flight still read into a fresh slot (copy on write) instead of waiting for them.
+    int64_t n_cow = 0;
     void *master = nullptr;
     uint8_t *mask = nullptr;
+    // Two node tables: renders read `table` (version `version`); an upload writes the other
+    // one (a copy of the current one plus its changes), then the two swap and the version
+    // grows.  Renders of older versions must end before a table or slot they read is reused.
     DevCell *table = nullptr;
+    DevCell *table_alt = nullptr;
+    int64_t version = 0;
+    std::vector<std::pair<int32_t, int64_t>> deferred;   // (slot, first version without it)
     uint8_t *pool = nullptr;
     float *slot_range = nullptr;
     void *ins_stage = nullptr;   // device staging for host-pointer inserts
@@ -186,6 +196,16 @@ int wait_for_renders(oct_handle *h, hipStream_t s)
     return OCT_OK;
 }
 
+// Device work on s after this call follows every render launch that read a node-table version
+// below v.  A slot's earlier launches ended before it was reused (stage_reserve), so its last
+// launch is the only one to wait for.
+int wait_for_renders_before(oct_handle *h, hipStream_t s, int64_t v)
+{
+    for (auto &r : h->rs)
+        if (r.st.ev && r.version < v) HIPCHK(h, hipStreamWaitEvent(s, r.st.ev, 0));
+    return OCT_OK;
+}
+
 int stage_reserve(oct_handle *h, Stage &s, size_t bytes)
 {
     if (s.ev) HIPCHK(h, hipEventSynchronize(s.ev));
@@ -268,7 +288,8 @@ void reset_host_state(oct_handle *h)
     h->cells[cell_index(g, g.N, 0, 0, 0)].exists = 1;
     h->cells[cell_index(g, g.N, 0, 0, 0)].state = kEmpty;
     h->free_slots.clear();
-    for (int64_t s = h->n_slots - 1; s >= 0; s--) h->free_slots.push_back((int32_t)s);
+    for (int64_t s = h->n_slots + h->n_cow - 1; s >= 0; s--) h->free_slots.push_back((int32_t)s);
+    h->deferred.clear();
     for (auto &d : h->dirty) d.clear();
 }
 
@@ -464,6 +485,17 @@ int octree_create(const oct_create_params *params, void *stream, oct_handle **ou
         h->err = "device_pool_bytes holds no brick";
         return bail(OCT_EINVAL);
     }
+    if (!h->capped) {
+        // copy-on-write headroom: the bricks of two brick layers across the largest face of
+        // every level (what one slab insert makes dirty)
+        int64_t cow = 8;
+        for (int L = 0; L <= N; L++) {
+            int64_t nb[3];
+            for (int a = 0; a < 3; a++) nb[a] = (g.ext[L][a] + g.M - 1) / g.M;
+            cow += 2 * std::max({nb[0] * nb[1], nb[0] * nb[2], nb[1] * nb[2]});
+        }
+        h->n_cow = std::min<int64_t>(cow, h->n_slots);
+    }
     h->master_host = params->master_on_host != 0;
     h->cells.assign((size_t)h->n_cells, HCell());
     h->dirty.assign((size_t)N + 1, std::vector<Box>());
@@ -491,10 +523,11 @@ int octree_create(const oct_create_params *params, void *stream, oct_handle **ou
     }
     if ((rc = dev_alloc((void **)&h->mask, (size_t)g.dims[0] * g.dims[1] * g.dims[2]))) return bail(rc);
     if ((rc = dev_alloc((void **)&h->table, sizeof(DevCell) * (size_t)h->n_cells))) return bail(rc);
+    if ((rc = dev_alloc((void **)&h->table_alt, sizeof(DevCell) * (size_t)h->n_cells))) return bail(rc);
     // one spare slot past the pool: canonical dumps gather non-resident bricks into it
-    if ((rc = dev_alloc((void **)&h->pool, (size_t)h->brick_bytes * (size_t)(h->n_slots + 1)))) return bail(rc);
-    if ((rc = dev_alloc((void **)&h->slot_range, sizeof(float) * 8 * (size_t)(h->n_slots + 1))))
-        return bail(rc);
+    const size_t pool_slots = (size_t)(h->n_slots + h->n_cow + 1);
+    if ((rc = dev_alloc((void **)&h->pool, (size_t)h->brick_bytes * pool_slots))) return bail(rc);
+    if ((rc = dev_alloc((void **)&h->slot_range, sizeof(float) * 8 * pool_slots))) return bail(rc);
     if ((rc = dev_alloc((void **)&h->flags, (size_t)h->n_cells))) return bail(rc);
     if ((rc = dev_alloc((void **)&h->miss_range, sizeof(float) * 8 * (size_t)h->n_cells))) return bail(rc);
     if (hipHostMalloc((void **)&h->flags_host, (size_t)h->n_cells, hipHostMallocDefault) != hipSuccess)
@@ -522,6 +555,7 @@ int octree_destroy(oct_handle *h)
     if (h->miss_range) (void)hipFree(h->miss_range);
     if (h->mask) (void)hipFree(h->mask);
     if (h->table) (void)hipFree(h->table);
+    if (h->table_alt) (void)hipFree(h->table_alt);
     if (h->pool) (void)hipFree(h->pool);
     if (h->slot_range) (void)hipFree(h->slot_range);
     if (h->ins_stage) (void)hipFree(h->ins_stage);
@@ -557,6 +591,7 @@ int octree_clear(oct_handle *h, void *stream)
     reset_host_state(h);
     std::fill(h->last_used.begin(), h->last_used.end(), 0);
     h->frame = 1;
+    h->version++;   // every earlier launch is now behind the version of the cleared table
     rc = upload_full_table(h, s);
     if (rc) return rc;
     HIPCHK(h, hipEventRecord(h->ev_insert, s));
@@ -641,6 +676,26 @@ int brick_pool_upload(oct_handle *h, uint64_t byte_budget, void *stream, oct_upl
         if (!rc && h->capped) rc = wait_for_renders(h, s);   // their flags are read first
         if (rc) return rc;
     }
+    // This call writes table version V + 1.  Renders below version V are waited for before
+    // its device writes (the other table held version V - 1), so slots that left the table at
+    // version V or earlier can be reused now; slots leaving it now wait for the next call.
+    const int64_t V = h->version;
+    if (!h->capped) {
+        size_t keep = 0;
+        for (const auto &d : h->deferred) {
+            if (d.second <= V) h->free_slots.push_back(d.first);
+            else h->deferred[keep++] = d;
+        }
+        h->deferred.resize(keep);
+    }
+    // a slot the current table points at is read by renders in flight: released later
+    auto release_slot = [&](const HCell &c) {
+        if (!h->capped && c.dev_valid && c.dev_kind == kBrick && c.dev_slot == c.slot)
+            h->deferred.push_back({c.slot, V + 1});
+        else
+            h->free_slots.push_back(c.slot);
+    };
+    bool in_place = false;   // a brick renders may read is rewritten in its slot
 
     // ---- 1. cells whose level data changed, and cells whose bordered region touches a change
     std::vector<int32_t> stat_cells;  // (L, x, y, z) quadruples
@@ -764,7 +819,7 @@ int brick_pool_upload(oct_handle *h, uint64_t byte_budget, void *stream, oct_upl
                     }
                     const bool brick = c.exists && c.state == kBrickState;
                     if (!brick && c.slot >= 0) {
-                        h->free_slots.push_back(c.slot);
+                        release_slot(c);
                         c.slot = -1;
                         c.needs_gather = false;
                     }
@@ -831,8 +886,23 @@ int brick_pool_upload(oct_handle *h, uint64_t byte_budget, void *stream, oct_upl
                     const int32_t *bb = &border_box[(size_t)ci * 6];
                     const bool part = !full && bb[3] >= 0 && bb[4] >= 0 && bb[5] >= 0;
                     if (full || part) {
-                        if (budget_left >= h->brick_bytes) push_job(c, L, x, y, z, full, bb);
-                        else c.needs_gather = true;   // stale until gathered: rendered with AVG
+                        if (budget_left >= h->brick_bytes) {
+                            if (!h->capped && c.dev_valid && c.dev_kind == kBrick &&
+                                c.dev_slot == c.slot) {
+                                if (!h->free_slots.empty()) {
+                                    // copy on write: the whole brick into a fresh slot
+                                    release_slot(c);
+                                    c.slot = h->free_slots.back();
+                                    h->free_slots.pop_back();
+                                    full = true;
+                                } else {
+                                    in_place = true;
+                                }
+                            }
+                            push_job(c, L, x, y, z, full, bb);
+                        } else {
+                            c.needs_gather = true;   // stale until gathered: rendered with AVG
+                        }
                     }
                     if (!c.needs_gather) new_kind[ci] = kBrick;
                 }
@@ -964,18 +1034,26 @@ int brick_pool_upload(oct_handle *h, uint64_t byte_budget, void *stream, oct_upl
     const size_t j_bytes = jobs.size() * sizeof(BrickJob);
     if (d_bytes + j_bytes) {
         int rc = stage_reserve(h, h->up, j_off + j_bytes);
-        if (!rc) rc = wait_for_renders(h, s);   // they read the node table and the pool
+        // renders read the node table and the pool: those of the other table's version (and
+        // older) end first, all of them when a brick they may read is rewritten in place
+        if (!rc) rc = (h->capped || in_place) ? wait_for_renders(h, s) : wait_for_renders_before(h, s, V);
         if (rc) return rc;
         if (d_bytes) std::memcpy(h->up.host, deltas.data(), d_bytes);
         if (j_bytes) std::memcpy((uint8_t *)h->up.host + j_off, jobs.data(), j_bytes);
         HIPCHK(h, hipMemcpyAsync(h->up.dev, h->up.host, j_off + j_bytes, hipMemcpyHostToDevice, s));
         HIPCHK(h, hipEventRecord(h->up.ev, s));
-        HIPCHK(h, launch_apply_deltas(h->table, h->miss_range, (const CellDelta *)h->up.dev,
+        DevCell *next = h->table_alt;
+        HIPCHK(h, hipMemcpyAsync(next, h->table, sizeof(DevCell) * (size_t)h->n_cells,
+                                 hipMemcpyDeviceToDevice, s));
+        HIPCHK(h, launch_apply_deltas(next, h->miss_range, (const CellDelta *)h->up.dev,
                                       (int)deltas.size(), s));
-        HIPCHK(h, launch_gather(g, h->master, h->table, h->pool, h->brick_bytes,
+        HIPCHK(h, launch_gather(g, h->master, next, h->pool, h->brick_bytes,
                                 (const BrickJob *)((uint8_t *)h->up.dev + j_off), (int)jobs.size(),
                                 h->slot_range, h->background_f, s));
-        HIPCHK(h, launch_ranges(g, h->table, h->slot_range, h->miss_range, s));
+        HIPCHK(h, launch_ranges(g, next, h->slot_range, h->miss_range, s));
+        h->table_alt = h->table;
+        h->table = next;
+        h->version++;
     }
     HIPCHK(h, hipEventRecord(h->ev_upload, s));
     if (out) {
@@ -1185,6 +1263,7 @@ int render_views(oct_handle *h, int32_t n_views, const oct_view *views, float *c
     h->next_rs = (h->next_rs + 1) % kRenderSlots;
     const size_t c_bytes = kCounterSlots * sizeof(RenderCounters);
     int rc = stage_reserve(h, rs.st, c_off + c_bytes);   // the slot is idle now
+    rs.version = h->version;
     if (!rc) rc = collect_kernel_time(h, rs);
     if (rc) return rc;
     if (part_floats * sizeof(float) > rs.part_cap) {
@@ -1340,6 +1419,7 @@ int render_views_backward(oct_handle *h, int32_t n_views, const oct_view *views,
     h->next_rs = (h->next_rs + 1) % kRenderSlots;
     int rc = stage_reserve(h, rs.st, i_off + i_bytes);
     if (rc) return rc;
+    rs.version = h->version;
     uint8_t *hp = (uint8_t *)rs.st.host;
     std::memcpy(hp, dvs.data(), v_bytes);
     std::memcpy(hp + i_off, items.data(), i_bytes);
@@ -1416,7 +1496,7 @@ int octree_dump_canonical(oct_handle *h, void *buf, size_t cap, size_t *needed)
                     int64_t slot = c.slot;
                     if (!resident) {
                         // gather the bordered brick into the spare slot past the pool
-                        slot = h->n_slots;
+                        slot = h->n_slots + h->n_cow;
                         int rc = stage_reserve(h, h->up, sizeof(BrickJob));
                         if (rc) return rc;
                         BrickJob j{};

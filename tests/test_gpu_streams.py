@@ -88,3 +88,48 @@ def test_paged_upload_on_another_stream_reads_the_render_flags():
     assert seq1[-1][0] == 0
     for a, w in zip(img2, img1):
         assert torch.equal(a, w)
+
+
+def test_upload_during_a_render_keeps_that_render_s_octree():
+    """A render issued before an upload reads the octree as it was when it was issued, even
+    while the upload runs on another stream: the upload rebuilds the bricks that render reads
+    into other pool slots and switches node tables, and the next render sees the new data."""
+    import dataclasses
+
+    import torch
+    from paper_1407_2074_amd.octree import Octree
+    vol = synth.gen_volume(DIMS, C, seed=12, n_blobs=14)
+    vol2 = vol.copy()
+    vol2[:, 8:24] = synth.gen_volume(DIMS, C, seed=13, n_blobs=14)[:, 8:24]
+    # slow render: 1024^2 rays, every position of the whole ray in one pass
+    v = dataclasses.replace(synth.make_view(DIMS, C, 7, az=35.0, el=25.0, width=1024,
+                                            height=1024), step=0.1, no_skip=1,
+                            depth_segments=1)
+
+    def tree(data):
+        t = Octree(DIMS, C, M, "u16", 0, 205)
+        t.insert_block(-1, (0, 0, 0), data)
+        t.upload()
+        return t
+
+    ref_old, ref_new = tree(vol), tree(vol2)
+    (want_old,) = ref_old.render([v])
+    (want_new,) = ref_new.render([v])
+    torch.cuda.synchronize()
+    assert not torch.equal(want_old, want_new)
+    t = tree(vol)
+    slab = torch.from_numpy(vol2[:, 8:24].view(np.int16)).cuda()
+    torch.cuda.synchronize()
+    r, b = torch.cuda.Stream(), torch.cuda.Stream()
+    img_old = torch.empty_like(want_old)
+    img_new = torch.empty_like(want_old)
+    t.render([v], images=[img_old], stream=r)           # in flight while the upload runs
+    t.insert_slices(-1, 8, slab, stream=b)
+    up = t.upload(stream=b)
+    t.render([v], images=[img_new], stream=r)
+    torch.cuda.synchronize()
+    assert up["bricks_gathered"] > 0
+    assert torch.equal(img_old, want_old)
+    assert torch.equal(img_new, want_new)
+    for x in (ref_old, ref_new, t):
+        x.close()
