@@ -251,11 +251,15 @@ k_apply_deltas(DevCell *table, float *miss_range, const CellDelta *d, int n)
 // A job rebuilds the whole brick or only the sub-box its inserted data touched.  It also
 // reduces the per-channel min/max of what it wrote: the slot's skip range is replaced by a
 // whole-brick job and widened by a partial one (a superset stays a valid bound).
-// One 1024-thread workgroup per job; thread t owns (x, y) columns t, t + 1024, ... of the
-// job's sub-box and walks z, four slices per round so that several rows of loads are in
-// flight (the job's rows are short, 34 voxels for 32^3 bricks: a thread-per-row walk is
-// latency-bound).
-constexpr int kGatherThreads = 1024;
+// One 256-thread workgroup per job; thread t owns (x, y) columns t, t + 256, ... of the job's
+// sub-box and walks z, four slices per round so that several rows of loads are in flight
+// (the job's rows are short, 34 voxels for 32^3 bricks: a thread-per-row walk is
+// latency-bound).  Uploads run while renders occupy most wave slots of every CU: 4-wave
+// workgroups fit beside them, 16-wave ones waited for whole CUs to drain.
+#ifndef OCTRC_GATHER_THREADS
+#define OCTRC_GATHER_THREADS 256
+#endif
+constexpr int kGatherThreads = OCTRC_GATHER_THREADS;
 
 template <typename T>
 __global__ void __launch_bounds__(kGatherThreads)
