@@ -20,16 +20,22 @@ namespace {
 
 constexpr int kThreads = 64 * kRenderTilesPerWg;   // one wave per tile; the tiles share the tables
 
-// Bit i of a view's transparency mask: from its LDS copy when one was staged, else global.
-__device__ __forceinline__ bool mask_bit(const uint32_t *m, const uint32_t *lds, int in_lds, int i)
+// Bit i of a view's transparency mask: from its LDS copy when one was staged (kLds), else
+// from global memory.  (The choice is a template parameter: a run-time select between the two
+// would make the compiler form generic pointers.)
+template <bool kLds>
+__device__ __forceinline__ bool mask_bit(const uint32_t *m, const uint32_t *lds, int i)
 {
-    const uint32_t w = in_lds > 0 ? lds[i >> 5] : m[i >> 5];
+    uint32_t w;
+    if constexpr (kLds) w = lds[i >> 5];
+    else w = m[i >> 5];
     return (w >> (i & 31)) & 1u;
 }
 
 // kErt: the view may terminate rays early (otherwise the opacity test is left out of the
-// march); kCount: sample counters are requested.
-template <typename T, int C, bool kErt, bool kCount>
+// march); kCount: sample counters are requested; kLdsMask: the transparency masks (mask_lds
+// words each) are staged in LDS.
+template <typename T, int C, bool kErt, bool kCount, bool kLdsMask>
 __device__ __forceinline__ void
 render_body(const VolGeom &g, const DevCell *__restrict__ table, const uint8_t *__restrict__ pool,
             uint64_t brick_bytes, const DevView *__restrict__ views,
@@ -46,7 +52,7 @@ render_body(const VolGeom &g, const DevCell *__restrict__ table, const uint8_t *
     // a small transparency mask (mask_lds words, the same for every view of the launch) is
     // staged in LDS next to the table; the barrier of load_tables covers both copies
     extern __shared__ uint32_t smask[];
-    if (mask_lds > 0 && V.tmask)
+    if (kLdsMask && V.tmask)
         for (int i = threadIdx.x; i < mask_lds; i += kThreads) smask[i] = V.tmask[i];
     load_tables<kThreads>(V, tb);
     if (wave >= it.ntiles) return;  // no barrier below this point
@@ -163,12 +169,12 @@ render_body(const VolGeom &g, const DevCell *__restrict__ table, const uint8_t *
                     cz = v[2] / csz;
                 }
                 const int cidx = coff + (cz * G + cy) * G + cx;
-                if (skip && mask_bit(tmask, smask, mask_lds, cidx)) {
+                if (skip && mask_bit<kLdsMask>(tmask, smask, cidx)) {
                     // widen to the largest transparent ancestor, jump to just before its exit
                     int lev = L, ax = cx, ay = cy, az = cz;
                     while (lev < g.N) {
                         const int pg = g.grid[lev + 1];
-                        if (!mask_bit(tmask, smask, mask_lds, g.cell_off[lev + 1] +
+                        if (!mask_bit<kLdsMask>(tmask, smask, g.cell_off[lev + 1] +
                                                  ((az >> 1) * pg + (ay >> 1)) * pg + (ax >> 1)))
                             break;
                         lev++;
@@ -347,12 +353,32 @@ render_body(const VolGeom &g, const DevCell *__restrict__ table, const uint8_t *
     }
 }
 
+// One render work item: the march specialised for the view's early termination and for
+// sample counters (both uniform over the workgroup).
+template <typename T, int C, bool kLdsMask>
+__device__ __forceinline__ void
+render_item(const VolGeom &g, const DevCell *__restrict__ table, const uint8_t *__restrict__ pool,
+            uint64_t brick_bytes, const DevView *__restrict__ views,
+            const WgItem *__restrict__ items, RenderCounters *counters, uint8_t *flags,
+            LutTable<C> &tb, int mask_lds)
+{
+    if (counters)
+        render_body<T, C, true, true, kLdsMask>(g, table, pool, brick_bytes, views, items, counters,
+                                                flags, tb, mask_lds);
+    else if (views[items[blockIdx.x].view].ert < 1.0f)
+        render_body<T, C, true, false, kLdsMask>(g, table, pool, brick_bytes, views, items,
+                                                 counters, flags, tb, mask_lds);
+    else
+        render_body<T, C, false, false, kLdsMask>(g, table, pool, brick_bytes, views, items,
+                                                  counters, flags, tb, mask_lds);
+}
+
 // uint16 bricks: registers for 5 waves per SIMD (6 fit only with spills, measured 2 % slower);
 // float32 bricks (twice the corner data) keep the compiler's choice.
-template <int C>
 #ifndef OCTRC_U16_WAVES_PER_EU
 #define OCTRC_U16_WAVES_PER_EU 5
 #endif
+template <int C, bool kLdsMask>
 __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(OCTRC_U16_WAVES_PER_EU)))
 k_render_u16(VolGeom g, const DevCell *__restrict__ table, const uint8_t *__restrict__ pool,
              uint64_t brick_bytes, const DevView *__restrict__ views,
@@ -360,19 +386,11 @@ k_render_u16(VolGeom g, const DevCell *__restrict__ table, const uint8_t *__rest
              int mask_lds)
 {
     __shared__ LutTable<C> tb;
-    // uniform per workgroup: one view per work item
-    if (counters)
-        render_body<uint16_t, C, true, true>(g, table, pool, brick_bytes, views, items, counters,
-                                             flags, tb, mask_lds);
-    else if (views[items[blockIdx.x].view].ert < 1.0f)
-        render_body<uint16_t, C, true, false>(g, table, pool, brick_bytes, views, items, counters,
-                                              flags, tb, mask_lds);
-    else
-        render_body<uint16_t, C, false, false>(g, table, pool, brick_bytes, views, items, counters,
-                                               flags, tb, mask_lds);
+    render_item<uint16_t, C, kLdsMask>(g, table, pool, brick_bytes, views, items, counters, flags,
+                                       tb, mask_lds);
 }
 
-template <int C>
+template <int C, bool kLdsMask>
 __global__ void __launch_bounds__(kThreads)
 k_render_f32(VolGeom g, const DevCell *__restrict__ table, const uint8_t *__restrict__ pool,
              uint64_t brick_bytes, const DevView *__restrict__ views,
@@ -380,15 +398,8 @@ k_render_f32(VolGeom g, const DevCell *__restrict__ table, const uint8_t *__rest
              int mask_lds)
 {
     __shared__ LutTable<C> tb;
-    if (counters)
-        render_body<float, C, true, true>(g, table, pool, brick_bytes, views, items, counters,
-                                          flags, tb, mask_lds);
-    else if (views[items[blockIdx.x].view].ert < 1.0f)
-        render_body<float, C, true, false>(g, table, pool, brick_bytes, views, items, counters,
-                                           flags, tb, mask_lds);
-    else
-        render_body<float, C, false, false>(g, table, pool, brick_bytes, views, items, counters,
-                                            flags, tb, mask_lds);
+    render_item<float, C, kLdsMask>(g, table, pool, brick_bytes, views, items, counters, flags,
+                                    tb, mask_lds);
 }
 
 // Front-to-back composite of the depth segments: C = C_0 + T_0 (C_1 + T_1 (...)),
@@ -467,12 +478,21 @@ void launch_c(const dim3 &grid, const dim3 &block, hipStream_t s, const VolGeom 
     const int64_t words = view_mask_words((int64_t)g.cell_off[g.N] + 1);
     const int mask_lds = words <= kMaskLdsWords ? (int)words : 0;
     const size_t shm = (size_t)mask_lds * 4;
-    if constexpr (sizeof(T) == 2)
-        hipLaunchKernelGGL((k_render_u16<C>), grid, block, shm, s, g, table, p, brick_bytes, views,
-                           items, counters, flags, mask_lds);
-    else
-        hipLaunchKernelGGL((k_render_f32<C>), grid, block, shm, s, g, table, p, brick_bytes, views,
-                           items, counters, flags, mask_lds);
+    if constexpr (sizeof(T) == 2) {
+        if (mask_lds)
+            hipLaunchKernelGGL((k_render_u16<C, true>), grid, block, shm, s, g, table, p,
+                               brick_bytes, views, items, counters, flags, mask_lds);
+        else
+            hipLaunchKernelGGL((k_render_u16<C, false>), grid, block, 0, s, g, table, p,
+                               brick_bytes, views, items, counters, flags, 0);
+    } else {
+        if (mask_lds)
+            hipLaunchKernelGGL((k_render_f32<C, true>), grid, block, shm, s, g, table, p,
+                               brick_bytes, views, items, counters, flags, mask_lds);
+        else
+            hipLaunchKernelGGL((k_render_f32<C, false>), grid, block, 0, s, g, table, p,
+                               brick_bytes, views, items, counters, flags, 0);
+    }
 }
 
 template <typename T>
