@@ -8,6 +8,7 @@ namespace octrc {
 
 constexpr int kMaxLevels = 16;
 constexpr int kMaxC = 4;
+constexpr int kMaxSplit = 16;   // depth segments per ray at most
 
 // Kinds of a resolved node-table cell.  Every cell of the virtual complete tree has an entry:
 // a cell whose node does not exist carries the AVG of its deepest existing ancestor, so a
@@ -68,14 +69,17 @@ struct DevView {
     int32_t nsplit;
     float *part;
     int32_t tile_begin, tile_end;   // tiles rendered by this launch (the combine pass's range)
+    // forward launches: this view's work items are item_begin ... item_begin + groups * nsplit
+    // - 1 of the grid (groups of kRenderTilesPerWg tiles; order in item_of)
+    int32_t item_begin, groups;
     // adjoint only: dL/dimage of this view, dL/dtable accumulator [C][256][4]
     const float *dimg;
     float *dlut;
     // this view's transfer-function tables (value/slope and opacity prefix counts), built
-    // once per launch by k_view_tables and copied into LDS by every workgroup
+    // once per launch by k_view_setup and copied into LDS by every workgroup
     const void *tables;
     // views with skipping: one bit per node-table cell, set when the cell is transparent for
-    // this view (built per launch by k_view_mask from the current table); NULL otherwise
+    // this view (built per launch by k_view_setup from the current table); NULL otherwise
     uint32_t *tmask;
 };
 
@@ -151,18 +155,16 @@ constexpr int kCkptStride = 64;   // positions per transmittance checkpoint segm
 // flags (may be NULL): per node-table cell, set to 1 when a render interpolated the cell's
 // resident brick and to 2 when it needed the cell's brick but found it missing.
 hipError_t launch_render(const VolGeom &g, const DevCell *table, const void *pool,
-                         uint64_t brick_bytes, const DevView *views, const WgItem *items,
-                         int n_items, RenderCounters *counters, uint8_t *flags, hipStream_t s);
-// Bytes of one view's tables for C channels, and the per-launch kernel that builds them for
-// every view (views[i].tables must point at a buffer of view_tables_bytes(C) bytes).
-size_t view_tables_bytes(int C);
-hipError_t launch_view_tables(const DevView *views, int n_views, int C, hipStream_t s);
+                         uint64_t brick_bytes, const DevView *views, int n_views, int n_items,
+                         RenderCounters *counters, uint8_t *flags, hipStream_t s);
+// Bytes of one view's tables for C channels (views[i].tables points at that many bytes) and
 // 32-bit words of one view's transparency mask over n_cells node-table cells (whole 64-cell
-// groups), and the per-launch kernel that fills the mask of every view with tmask != NULL
-// from the current node table (after the tables kernel, which it reads).
+// groups).  The per-launch set-up kernel builds every view's tables and, over mask_cells cells
+// (0: none), the mask of every view with tmask != NULL from the node table `table`.
+size_t view_tables_bytes(int C);
 inline int64_t view_mask_words(int64_t n_cells) { return (n_cells + 63) / 64 * 2; }
-hipError_t launch_view_mask(const DevView *views, int n_views, int C, const DevCell *table,
-                            int64_t n_cells, hipStream_t s);
+hipError_t launch_view_setup(const DevView *views, int n_views, int C, const DevCell *table,
+                             int64_t mask_cells, hipStream_t s);
 // Front-to-back composite of the depth segments of every split view into its image.
 hipError_t launch_combine(const DevView *views, const int32_t *split_views, int n_split,
                           int64_t max_pixels, hipStream_t s);

@@ -54,6 +54,29 @@ struct alignas(16) LutTable {
     float4 lut[C][256][2];
 };
 
+// Only the opacity prefix counts of build_tables (same entries, same counts); called by every
+// thread of a 256-thread workgroup, ends with a barrier.
+template <int C>
+__device__ inline void build_prefix(const DevView &V, int (*pref)[257], int (*wtot)[4])
+{
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+#pragma unroll
+    for (int c = 0; c < C; c++) {
+        const unsigned long long m = __ballot(tf_entry(V, c, tid).w != 0.0f);
+        if (lane == 63) wtot[c][wave] = __popcll(m);
+        pref[c][tid] = __popcll(m & ((1ull << lane) - 1ull));
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < C; c++) {
+        int base = 0;
+        for (int w = 0; w < wave; w++) base += wtot[c][w];
+        pref[c][tid] += base;
+        if (tid == 255) pref[c][256] = base + wtot[c][3];
+    }
+    __syncthreads();
+}
+
 // Called by every thread of the workgroup (blockDim >= 256); ends with a barrier.
 template <int C>
 __device__ inline void build_tables(const DevView &V, ViewTables<C> &tb)
@@ -85,7 +108,7 @@ __device__ inline void build_tables(const DevView &V, ViewTables<C> &tb)
     __syncthreads();
 }
 
-// The leading sizeof(Tab) bytes of V's tables (built by k_view_tables) copied into LDS by the
+// The leading sizeof(Tab) bytes of V's tables (built by k_view_setup) copied into LDS by the
 // whole workgroup (a multiple of 16 bytes, 16-byte loads); ends with a barrier.
 template <int kThreadsPerWg, typename Tab>
 __device__ inline void load_tables(const DevView &V, Tab &tb)

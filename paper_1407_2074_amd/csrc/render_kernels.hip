@@ -32,21 +32,45 @@ __device__ __forceinline__ bool mask_bit(const uint32_t *m, const uint32_t *lds,
     return (w >> (i & 31)) & 1u;
 }
 
+// Work item b of a forward launch.  The views' items are consecutive (item_begin); inside a
+// view, items go out in blocks of 8 tile groups, segment by segment, so that all segments of
+// tile group j land on XCD j mod 8 (workgroups are dealt round-robin to the 8 XCDs; emitting
+// a group's segments back to back would pin each segment to a fixed subset of XCDs whenever
+// the segment count divides 8).
+__device__ inline WgItem item_of(const DevView *__restrict__ views, int n_views, int b)
+{
+    int lo = 0, hi = n_views - 1;
+    while (lo < hi) {   // last view with item_begin <= b
+        const int mid = (lo + hi + 1) >> 1;
+        if (views[mid].item_begin <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    const DevView &V = views[lo];
+    const int S = V.nsplit, j = b - V.item_begin;
+    const int blk = j / (8 * S), r = j - blk * 8 * S;
+    const int gcount = min(8, V.groups - 8 * blk);
+    const int gi = 8 * blk + r % gcount;
+    WgItem it;
+    it.view = lo;
+    it.seg = r / gcount;
+    it.tile0 = V.tile_begin + gi * kRenderTilesPerWg;
+    it.ntiles = min(kRenderTilesPerWg, V.tile_end - it.tile0);
+    return it;
+}
+
 // kErt: the view may terminate rays early (otherwise the opacity test is left out of the
 // march); kCount: sample counters are requested; kLdsMask: the transparency masks (mask_lds
 // words each) are staged in LDS.
 template <typename T, int C, bool kErt, bool kCount, bool kLdsMask>
 __device__ __forceinline__ void
 render_body(const VolGeom &g, const DevCell *__restrict__ table, const uint8_t *__restrict__ pool,
-            uint64_t brick_bytes, const DevView *__restrict__ views,
-            const WgItem *__restrict__ items, RenderCounters *counters, uint8_t *flags,
-            LutTable<C> &tb, int mask_lds)
+            uint64_t brick_bytes, const DevView *__restrict__ views, const WgItem &it,
+            RenderCounters *counters, uint8_t *flags, LutTable<C> &tb, int mask_lds)
 {
 
     // items stay in dispatch order: the hardware deals workgroups round-robin to the XCDs, which
     // spreads every part of the image over all of them (giving each XCD one contiguous band
     // measured 2x slower: the volume covers the bands unevenly)
-    const WgItem it = items[blockIdx.x];
     const DevView &V = views[it.view];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     // a small transparency mask (mask_lds words, the same for every view of the launch) is
@@ -358,18 +382,18 @@ render_body(const VolGeom &g, const DevCell *__restrict__ table, const uint8_t *
 template <typename T, int C, bool kLdsMask>
 __device__ __forceinline__ void
 render_item(const VolGeom &g, const DevCell *__restrict__ table, const uint8_t *__restrict__ pool,
-            uint64_t brick_bytes, const DevView *__restrict__ views,
-            const WgItem *__restrict__ items, RenderCounters *counters, uint8_t *flags,
-            LutTable<C> &tb, int mask_lds)
+            uint64_t brick_bytes, const DevView *__restrict__ views, int n_views,
+            RenderCounters *counters, uint8_t *flags, LutTable<C> &tb, int mask_lds)
 {
+    const WgItem it = item_of(views, n_views, blockIdx.x);
     if (counters)
-        render_body<T, C, true, true, kLdsMask>(g, table, pool, brick_bytes, views, items, counters,
+        render_body<T, C, true, true, kLdsMask>(g, table, pool, brick_bytes, views, it, counters,
                                                 flags, tb, mask_lds);
-    else if (views[items[blockIdx.x].view].ert < 1.0f)
-        render_body<T, C, true, false, kLdsMask>(g, table, pool, brick_bytes, views, items,
-                                                 counters, flags, tb, mask_lds);
+    else if (views[it.view].ert < 1.0f)
+        render_body<T, C, true, false, kLdsMask>(g, table, pool, brick_bytes, views, it, counters,
+                                                 flags, tb, mask_lds);
     else
-        render_body<T, C, false, false, kLdsMask>(g, table, pool, brick_bytes, views, items,
+        render_body<T, C, false, false, kLdsMask>(g, table, pool, brick_bytes, views, it,
                                                   counters, flags, tb, mask_lds);
 }
 
@@ -382,23 +406,21 @@ template <int C, bool kLdsMask>
 __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(OCTRC_U16_WAVES_PER_EU)))
 k_render_u16(VolGeom g, const DevCell *__restrict__ table, const uint8_t *__restrict__ pool,
              uint64_t brick_bytes, const DevView *__restrict__ views,
-             const WgItem *__restrict__ items, RenderCounters *counters, uint8_t *flags,
-             int mask_lds)
+             int n_views, RenderCounters *counters, uint8_t *flags, int mask_lds)
 {
     __shared__ LutTable<C> tb;
-    render_item<uint16_t, C, kLdsMask>(g, table, pool, brick_bytes, views, items, counters, flags,
-                                       tb, mask_lds);
+    render_item<uint16_t, C, kLdsMask>(g, table, pool, brick_bytes, views, n_views, counters,
+                                       flags, tb, mask_lds);
 }
 
 template <int C, bool kLdsMask>
 __global__ void __launch_bounds__(kThreads)
 k_render_f32(VolGeom g, const DevCell *__restrict__ table, const uint8_t *__restrict__ pool,
              uint64_t brick_bytes, const DevView *__restrict__ views,
-             const WgItem *__restrict__ items, RenderCounters *counters, uint8_t *flags,
-             int mask_lds)
+             int n_views, RenderCounters *counters, uint8_t *flags, int mask_lds)
 {
     __shared__ LutTable<C> tb;
-    render_item<float, C, kLdsMask>(g, table, pool, brick_bytes, views, items, counters, flags,
+    render_item<float, C, kLdsMask>(g, table, pool, brick_bytes, views, n_views, counters, flags,
                                     tb, mask_lds);
 }
 
@@ -414,40 +436,55 @@ k_combine(const DevView *__restrict__ views, const int32_t *__restrict__ split_v
         const int px = (int)(pix % V.width), py = (int)(pix / V.width);
         const int tile = (py >> 3) * V.tiles_x + (px >> 3);
         if (tile < V.tile_begin || tile >= V.tile_end) continue;
-        float4 acc = *(const float4 *)(V.part + pix * 4);
+        // every segment's loads are issued before the first is used (at most kMaxSplit)
+        float4 q[kMaxSplit];
+#pragma unroll
+        for (int sg = 0; sg < kMaxSplit; sg++)
+            if (sg < V.nsplit) q[sg] = *(const float4 *)(V.part + ((int64_t)sg * npix + pix) * 4);
+        float4 acc = q[0];
         float T = acc.w;
-        for (int sg = 1; sg < V.nsplit; sg++) {
-            const float4 q = *(const float4 *)(V.part + ((int64_t)sg * npix + pix) * 4);
-            acc.x = __builtin_fmaf(T, q.x, acc.x);
-            acc.y = __builtin_fmaf(T, q.y, acc.y);
-            acc.z = __builtin_fmaf(T, q.z, acc.z);
-            T = T * q.w;
+#pragma unroll
+        for (int sg = 1; sg < kMaxSplit; sg++) {
+            if (sg < V.nsplit) {
+                acc.x = __builtin_fmaf(T, q[sg].x, acc.x);
+                acc.y = __builtin_fmaf(T, q[sg].y, acc.y);
+                acc.z = __builtin_fmaf(T, q[sg].z, acc.z);
+                T = T * q[sg].w;
+            }
         }
         *(float4 *)(V.image + pix * 4) = make_float4(acc.x, acc.y, acc.z, 1.0f - T);
     }
 }
 
-// Transparency of every node-table cell for every view that skips: bit i of V.tmask is set
-// when cell i's value range classifies to zero opacity in every channel (cell_transparent with
-// the view's opacity prefix counts).  Grid: (cells / 256, views); one 64-bit ballot per wave.
+// Per-launch view set-up in one grid (views along y).  Workgroup 0 of a view tabulates its
+// transfer functions (value/slope table and opacity prefix counts) into V.tables.  For a view
+// that skips, workgroup 1 + b sets bits 256 b ... 256 b + 255 of V.tmask: bit i when cell i's
+// value range classifies to zero opacity in every channel (cell_transparent with the view's
+// prefix counts, rebuilt locally), one 64-bit ballot per wave.  The mask reads the current
+// node table, so the launch follows the last upload.
 template <int C>
 __global__ void __launch_bounds__(256)
-k_view_mask(const DevView *__restrict__ views, const DevCell *__restrict__ table, int64_t n_cells)
+k_view_setup(const DevView *__restrict__ views, const DevCell *__restrict__ table, int64_t n_cells)
 {
+    __shared__ ViewTables<C> tb;
     const DevView &V = views[blockIdx.y];
+    if (blockIdx.x == 0) {
+        build_tables<C>(V, tb);   // ends with a barrier
+        const uint4 *src = (const uint4 *)&tb;
+        uint4 *dst = (uint4 *)V.tables;
+        for (int i = threadIdx.x; i < (int)(sizeof(ViewTables<C>) / 16); i += 256) dst[i] = src[i];
+        return;
+    }
     if (!V.tmask) return;
-    __shared__ int pref[C][257];
-    const ViewTables<C> *tb = (const ViewTables<C> *)V.tables;
-    for (int i = threadIdx.x; i < C * 257; i += 256) (&pref[0][0])[i] = (&tb->pref[0][0])[i];
-    __syncthreads();
+    build_prefix<C>(V, tb.pref, tb.wtot);
     float ulo[C], usc[C];
 #pragma unroll
     for (int c = 0; c < C; c++) {
         usc[c] = V.uscale[c];
         ulo[c] = -V.ulo[c] * usc[c];
     }
-    const int64_t cell = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const bool t = cell < n_cells && cell_transparent<C>(table[cell], ulo, usc, pref);
+    const int64_t cell = (int64_t)(blockIdx.x - 1) * 256 + threadIdx.x;
+    const bool t = cell < n_cells && cell_transparent<C>(table[cell], ulo, usc, tb.pref);
     const unsigned long long b = __ballot(t);
     const int64_t first = cell & ~(int64_t)63;   // first cell of this wave
     if ((threadIdx.x & 63) == 0 && first < n_cells) {
@@ -456,22 +493,10 @@ k_view_mask(const DevView *__restrict__ views, const DevCell *__restrict__ table
     }
 }
 
-// One workgroup per view: the view's tables, built in LDS, written to V.tables.
-template <int C>
-__global__ void __launch_bounds__(256) k_view_tables(const DevView *__restrict__ views)
-{
-    __shared__ ViewTables<C> tb;
-    const DevView &V = views[blockIdx.x];
-    build_tables<C>(V, tb);   // ends with a barrier
-    const uint4 *src = (const uint4 *)&tb;
-    uint4 *dst = (uint4 *)V.tables;
-    for (int i = threadIdx.x; i < (int)(sizeof(ViewTables<C>) / 16); i += 256) dst[i] = src[i];
-}
-
 template <typename T, int C>
 void launch_c(const dim3 &grid, const dim3 &block, hipStream_t s, const VolGeom &g,
               const DevCell *table, const uint8_t *p, uint64_t brick_bytes, const DevView *views,
-              const WgItem *items, RenderCounters *counters, uint8_t *flags)
+              int n_views, RenderCounters *counters, uint8_t *flags)
 {
     // masks of up to 1024 words (32768 cells: trees of up to five levels) go to LDS
     constexpr int64_t kMaskLdsWords = 1024;
@@ -481,32 +506,32 @@ void launch_c(const dim3 &grid, const dim3 &block, hipStream_t s, const VolGeom 
     if constexpr (sizeof(T) == 2) {
         if (mask_lds)
             hipLaunchKernelGGL((k_render_u16<C, true>), grid, block, shm, s, g, table, p,
-                               brick_bytes, views, items, counters, flags, mask_lds);
+                               brick_bytes, views, n_views, counters, flags, mask_lds);
         else
             hipLaunchKernelGGL((k_render_u16<C, false>), grid, block, 0, s, g, table, p,
-                               brick_bytes, views, items, counters, flags, 0);
+                               brick_bytes, views, n_views, counters, flags, 0);
     } else {
         if (mask_lds)
             hipLaunchKernelGGL((k_render_f32<C, true>), grid, block, shm, s, g, table, p,
-                               brick_bytes, views, items, counters, flags, mask_lds);
+                               brick_bytes, views, n_views, counters, flags, mask_lds);
         else
             hipLaunchKernelGGL((k_render_f32<C, false>), grid, block, 0, s, g, table, p,
-                               brick_bytes, views, items, counters, flags, 0);
+                               brick_bytes, views, n_views, counters, flags, 0);
     }
 }
 
 template <typename T>
 hipError_t launch_typed(const VolGeom &g, const DevCell *table, const void *pool,
-                        uint64_t brick_bytes, const DevView *views, const WgItem *items,
-                        int n_items, RenderCounters *counters, uint8_t *flags, hipStream_t s)
+                        uint64_t brick_bytes, const DevView *views, int n_views, int n_items,
+                        RenderCounters *counters, uint8_t *flags, hipStream_t s)
 {
     const dim3 grid(n_items), block(kThreads);
     const uint8_t *p = (const uint8_t *)pool;
     switch (g.C) {
-    case 1: launch_c<T, 1>(grid, block, s, g, table, p, brick_bytes, views, items, counters, flags); break;
-    case 2: launch_c<T, 2>(grid, block, s, g, table, p, brick_bytes, views, items, counters, flags); break;
-    case 3: launch_c<T, 3>(grid, block, s, g, table, p, brick_bytes, views, items, counters, flags); break;
-    default: launch_c<T, 4>(grid, block, s, g, table, p, brick_bytes, views, items, counters, flags); break;
+    case 1: launch_c<T, 1>(grid, block, s, g, table, p, brick_bytes, views, n_views, counters, flags); break;
+    case 2: launch_c<T, 2>(grid, block, s, g, table, p, brick_bytes, views, n_views, counters, flags); break;
+    case 3: launch_c<T, 3>(grid, block, s, g, table, p, brick_bytes, views, n_views, counters, flags); break;
+    default: launch_c<T, 4>(grid, block, s, g, table, p, brick_bytes, views, n_views, counters, flags); break;
     }
     return hipGetLastError();
 }
@@ -523,29 +548,16 @@ size_t view_tables_bytes(int C)
     }
 }
 
-hipError_t launch_view_tables(const DevView *views, int n_views, int C, hipStream_t s)
+hipError_t launch_view_setup(const DevView *views, int n_views, int C, const DevCell *table,
+                             int64_t mask_cells, hipStream_t s)
 {
     if (n_views <= 0) return hipSuccess;
-    const dim3 grid(n_views), block(256);
+    const dim3 grid((unsigned)(1 + (mask_cells + 255) / 256), (unsigned)n_views), block(256);
     switch (C) {
-    case 1: hipLaunchKernelGGL(k_view_tables<1>, grid, block, 0, s, views); break;
-    case 2: hipLaunchKernelGGL(k_view_tables<2>, grid, block, 0, s, views); break;
-    case 3: hipLaunchKernelGGL(k_view_tables<3>, grid, block, 0, s, views); break;
-    default: hipLaunchKernelGGL(k_view_tables<4>, grid, block, 0, s, views); break;
-    }
-    return hipGetLastError();
-}
-
-hipError_t launch_view_mask(const DevView *views, int n_views, int C, const DevCell *table,
-                            int64_t n_cells, hipStream_t s)
-{
-    if (n_views <= 0 || n_cells <= 0) return hipSuccess;
-    const dim3 grid((unsigned)((n_cells + 255) / 256), (unsigned)n_views), block(256);
-    switch (C) {
-    case 1: hipLaunchKernelGGL(k_view_mask<1>, grid, block, 0, s, views, table, n_cells); break;
-    case 2: hipLaunchKernelGGL(k_view_mask<2>, grid, block, 0, s, views, table, n_cells); break;
-    case 3: hipLaunchKernelGGL(k_view_mask<3>, grid, block, 0, s, views, table, n_cells); break;
-    default: hipLaunchKernelGGL(k_view_mask<4>, grid, block, 0, s, views, table, n_cells); break;
+    case 1: hipLaunchKernelGGL(k_view_setup<1>, grid, block, 0, s, views, table, mask_cells); break;
+    case 2: hipLaunchKernelGGL(k_view_setup<2>, grid, block, 0, s, views, table, mask_cells); break;
+    case 3: hipLaunchKernelGGL(k_view_setup<3>, grid, block, 0, s, views, table, mask_cells); break;
+    default: hipLaunchKernelGGL(k_view_setup<4>, grid, block, 0, s, views, table, mask_cells); break;
     }
     return hipGetLastError();
 }
@@ -561,15 +573,15 @@ hipError_t launch_combine(const DevView *views, const int32_t *split_views, int 
 }
 
 hipError_t launch_render(const VolGeom &g, const DevCell *table, const void *pool,
-                         uint64_t brick_bytes, const DevView *views, const WgItem *items,
-                         int n_items, RenderCounters *counters, uint8_t *flags, hipStream_t s)
+                         uint64_t brick_bytes, const DevView *views, int n_views, int n_items,
+                         RenderCounters *counters, uint8_t *flags, hipStream_t s)
 {
     if (n_items == 0) return hipSuccess;
     if (g.dtype == 0)
-        return launch_typed<uint16_t>(g, table, pool, brick_bytes, views, items, n_items, counters,
-                                      flags, s);
-    return launch_typed<float>(g, table, pool, brick_bytes, views, items, n_items, counters, flags,
-                               s);
+        return launch_typed<uint16_t>(g, table, pool, brick_bytes, views, n_views, n_items,
+                                      counters, flags, s);
+    return launch_typed<float>(g, table, pool, brick_bytes, views, n_views, n_items, counters,
+                               flags, s);
 }
 
 }  // namespace octrc

@@ -1086,7 +1086,7 @@ static int view_nseg(const oct_handle *h, const oct_view &v)
 static int view_segments(const oct_handle *h, const oct_view &v)
 {
     if (!(v.ert_alpha >= 1.0f)) return 1;
-    if (v.depth_segments > 0) return std::min(v.depth_segments, 16);
+    if (v.depth_segments > 0) return std::min(v.depth_segments, kMaxSplit);
     return auto_segments(h->g, v);
 }
 
@@ -1130,7 +1130,7 @@ static int build_view(oct_handle *h, const oct_view &v, float *image, DevView &d
     if (v.lod < -1) return fail(h, OCT_EINVAL, "lod must be >= -1");
     if (v.tile_begin < 0 || v.tile_count < -1) return fail(h, OCT_EINVAL, "bad tile range");
     if (!(v.ert_alpha > 0.0f)) return fail(h, OCT_EINVAL, "ert_alpha must be > 0");
-    if (v.depth_segments < 0 || v.depth_segments > 16)
+    if (v.depth_segments < 0 || v.depth_segments > kMaxSplit)
         return fail(h, OCT_EINVAL, "depth_segments must be 0..16");
     for (int i = 0; i < 2; i++)
         if (v.reserved[i]) return fail(h, OCT_EINVAL, "reserved fields must be 0");
@@ -1202,7 +1202,7 @@ int render_views(oct_handle *h, int32_t n_views, const oct_view *views, float *c
     HIPCHK(h, hipSetDevice(h->device));
     hipStream_t s = (hipStream_t)stream;
     std::vector<DevView> dvs((size_t)n_views);
-    std::vector<WgItem> items;
+    int64_t n_items = 0;
     std::vector<int32_t> split_views;
     std::vector<std::pair<int, size_t>> slot_part;   // (view, float offset) in the slot buffer
     size_t ck_off = 0, part_floats = 0;
@@ -1237,26 +1237,15 @@ int render_views(oct_handle *h, int32_t n_views, const oct_view *views, float *c
             split_views.push_back(i);
             max_split_pixels = std::max<int64_t>(max_split_pixels, (int64_t)npix);
         }
-        // workgroups are dealt round-robin to the 8 XCDs: items go out in blocks of 8 tile
-        // groups, segment by segment, so all segments of group j land on XCD j like the
-        // unsplit launch (consecutive segments of one group would pin each segment to a
-        // fixed subset of XCDs whenever the segment count divides 8)
+        // the view's work items (the kernel derives each one from its index, item_of)
         const int groups = (te - tb + kRenderTilesPerWg - 1) / kRenderTilesPerWg;
-        for (int g0 = 0; g0 < groups; g0 += 8)
-            for (int sg = 0; sg < nsplit; sg++)
-                for (int gi = g0; gi < std::min(g0 + 8, groups); gi++) {
-                    WgItem w{};
-                    w.view = i;
-                    w.tile0 = tb + gi * kRenderTilesPerWg;
-                    w.ntiles = std::min(kRenderTilesPerWg, te - w.tile0);
-                    w.seg = sg;
-                    items.push_back(w);
-                }
+        dvs[i].item_begin = (int32_t)n_items;
+        dvs[i].groups = groups;
+        n_items += (int64_t)groups * nsplit;
     }
+    if (n_items > INT32_MAX) return fail(h, OCT_EINVAL, "too many tiles in one launch");
     const size_t v_bytes = dvs.size() * sizeof(DevView);
-    const size_t i_off = (v_bytes + 255) & ~(size_t)255;
-    const size_t i_bytes = items.size() * sizeof(WgItem);
-    const size_t sv_off = (i_off + i_bytes + 255) & ~(size_t)255;
+    const size_t sv_off = (v_bytes + 255) & ~(size_t)255;
     const size_t sv_bytes = split_views.size() * sizeof(int32_t);
     const size_t c_off = (sv_off + sv_bytes + 255) & ~(size_t)255;
     RenderSlot &rs = h->rs[h->next_rs];
@@ -1297,23 +1286,23 @@ int render_views(oct_handle *h, int32_t n_views, const oct_view *views, float *c
         dvs[i].tmask = dvs[i].skip ? rs.tmask + (size_t)(j++) * mwords : nullptr;
     uint8_t *hp = (uint8_t *)rs.st.host;
     std::memcpy(hp, dvs.data(), v_bytes);
-    std::memcpy(hp + i_off, items.data(), i_bytes);
     std::memcpy(hp + sv_off, split_views.data(), sv_bytes);
     std::memset(hp + c_off, 0, c_bytes);
-    HIPCHK(h, hipMemcpyAsync(rs.st.dev, hp, c_off + c_bytes, hipMemcpyHostToDevice, s));
+    // views and split list, plus the zeroed sample counters when they are asked for
+    HIPCHK(h, hipMemcpyAsync(rs.st.dev, hp, out ? c_off + c_bytes : sv_off + sv_bytes,
+                             hipMemcpyHostToDevice, s));
     uint8_t *dp = (uint8_t *)rs.st.dev;
-    HIPCHK(h, launch_view_tables((const DevView *)dp, n_views, h->g.C, s));
     rc = wait_for(h, s, h->ev_upload);   // the node table and pool of the last upload
     if (rc) return rc;
-    if (n_skip) HIPCHK(h, launch_view_mask((const DevView *)dp, n_views, h->g.C, h->table, h->n_cells, s));
+    HIPCHK(h, launch_view_setup((const DevView *)dp, n_views, h->g.C, h->table,
+                                n_skip ? h->n_cells : 0, s));
     if (h->ktime) {
         if (!rs.k0) HIPCHK(h, hipEventCreate(&rs.k0));
         if (!rs.k1) HIPCHK(h, hipEventCreate(&rs.k1));
         HIPCHK(h, hipEventRecord(rs.k0, s));
     }
     HIPCHK(h, launch_render(h->g, h->table, h->pool, h->brick_bytes, (const DevView *)dp,
-                            (const WgItem *)(dp + i_off), (int)items.size(),
-                            out ? (RenderCounters *)(dp + c_off) : nullptr,
+                            n_views, (int)n_items, out ? (RenderCounters *)(dp + c_off) : nullptr,
                             h->capped ? h->flags : nullptr, s));
     if (h->ktime) {
         HIPCHK(h, hipEventRecord(rs.k1, s));
