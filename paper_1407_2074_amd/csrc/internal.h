@@ -72,14 +72,17 @@ struct DevView {
     // forward launches: this view's work items are item_begin ... item_begin + groups * nsplit
     // - 1 of the grid (groups of kRenderTilesPerWg tiles; order in item_of)
     int32_t item_begin, groups;
+    // [groups] the view's tile groups in dispatch order (longest estimated rays first), then
+    // [groups] scratch; written by k_view_prep each launch.  NULL: index order
+    int32_t *group_order;
     // adjoint only: dL/dimage of this view, dL/dtable accumulator [C][256][4]
     const float *dimg;
     float *dlut;
     // this view's transfer-function tables (value/slope and opacity prefix counts), built
-    // once per launch by k_view_setup and copied into LDS by every workgroup
+    // once per launch by k_view_prep and copied into LDS by every workgroup
     const void *tables;
     // views with skipping: one bit per node-table cell, set when the cell is transparent for
-    // this view (built per launch by k_view_setup from the current table); NULL otherwise
+    // this view (built per launch by k_view_mask from the current table); NULL otherwise
     uint32_t *tmask;
 };
 
@@ -159,12 +162,14 @@ hipError_t launch_render(const VolGeom &g, const DevCell *table, const void *poo
                          RenderCounters *counters, uint8_t *flags, hipStream_t s);
 // Bytes of one view's tables for C channels (views[i].tables points at that many bytes) and
 // 32-bit words of one view's transparency mask over n_cells node-table cells (whole 64-cell
-// groups).  The per-launch set-up kernel builds every view's tables and, over mask_cells cells
-// (0: none), the mask of every view with tmask != NULL from the node table `table`.
+// groups).  Per launch, the preparation kernel builds every view's tables and tile-group
+// dispatch order (it reads only the views); the mask kernel, after it and after the last
+// upload, fills the mask of every view with tmask != NULL from the node table `table`.
 size_t view_tables_bytes(int C);
 inline int64_t view_mask_words(int64_t n_cells) { return (n_cells + 63) / 64 * 2; }
-hipError_t launch_view_setup(const DevView *views, int n_views, int C, const DevCell *table,
-                             int64_t mask_cells, hipStream_t s);
+hipError_t launch_view_prep(const VolGeom &g, const DevView *views, int n_views, hipStream_t s);
+hipError_t launch_view_mask(const DevView *views, int n_views, int C, const DevCell *table,
+                            int64_t n_cells, hipStream_t s);
 // Front-to-back composite of the depth segments of every split view into its image.
 hipError_t launch_combine(const DevView *views, const int32_t *split_views, int n_split,
                           int64_t max_pixels, hipStream_t s);

@@ -108,7 +108,7 @@ __device__ inline void build_tables(const DevView &V, ViewTables<C> &tb)
     __syncthreads();
 }
 
-// The leading sizeof(Tab) bytes of V's tables (built by k_view_setup) copied into LDS by the
+// The leading sizeof(Tab) bytes of V's tables (built by k_view_prep) copied into LDS by the
 // whole workgroup (a multiple of 16 bytes, 16-byte loads); ends with a barrier.
 template <int kThreadsPerWg, typename Tab>
 __device__ inline void load_tables(const DevView &V, Tab &tb)

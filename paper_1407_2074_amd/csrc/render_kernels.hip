@@ -33,10 +33,11 @@ __device__ __forceinline__ bool mask_bit(const uint32_t *m, const uint32_t *lds,
 }
 
 // Work item b of a forward launch.  The views' items are consecutive (item_begin); inside a
-// view, items go out in blocks of 8 tile groups, segment by segment, so that all segments of
-// tile group j land on XCD j mod 8 (workgroups are dealt round-robin to the 8 XCDs; emitting
-// a group's segments back to back would pin each segment to a fixed subset of XCDs whenever
-// the segment count divides 8).
+// view, tile groups go out in V.group_order (longest estimated rays first, so that the
+// longest chains start early and short work fills the end of the launch), in blocks of 8
+// groups, segment by segment, so that all segments of the j-th group land on XCD j mod 8
+// (workgroups are dealt round-robin to the 8 XCDs; emitting a group's segments back to back
+// would pin each segment to a fixed subset of XCDs whenever the segment count divides 8).
 __device__ inline WgItem item_of(const DevView *__restrict__ views, int n_views, int b)
 {
     int lo = 0, hi = n_views - 1;
@@ -49,7 +50,12 @@ __device__ inline WgItem item_of(const DevView *__restrict__ views, int n_views,
     const int S = V.nsplit, j = b - V.item_begin;
     const int blk = j / (8 * S), r = j - blk * 8 * S;
     const int gcount = min(8, V.groups - 8 * blk);
-    const int gi = 8 * blk + r % gcount;
+    const int gs = 8 * blk + r % gcount;   // position in dispatch order
+#ifdef OCTRC_NO_GROUP_ORDER
+    const int gi = gs;
+#else
+    const int gi = V.group_order ? V.group_order[gs] : gs;
+#endif
     WgItem it;
     it.view = lo;
     it.seg = r / gcount;
@@ -456,35 +462,142 @@ k_combine(const DevView *__restrict__ views, const int32_t *__restrict__ split_v
     }
 }
 
-// Per-launch view set-up in one grid (views along y).  Workgroup 0 of a view tabulates its
-// transfer functions (value/slope table and opacity prefix counts) into V.tables.  For a view
-// that skips, workgroup 1 + b sets bits 256 b ... 256 b + 255 of V.tmask: bit i when cell i's
-// value range classifies to zero opacity in every channel (cell_transparent with the view's
-// prefix counts, rebuilt locally), one 64-bit ballot per wave.  The mask reads the current
-// node table, so the launch follows the last upload.
+// Dispatch order of a view's tile groups (item_of): groups sorted by the length inside the
+// volume box and the clip half-spaces of their longest tile-centre ray (one ray per group when
+// the view has more than 4096 groups), longest first, in 32 length classes.  Each thread owns a
+// contiguous run of groups, and a counting sort with per-thread class counts (scanned class by
+// class over the threads) keeps index order inside a class, so neighbouring groups of one
+// class stay neighbours in the dispatch.  One 256-thread workgroup; group_order[G ... 2G) is
+// scratch.  Precision does not matter here (the order changes no result), hence the
+// approximate reciprocals.
+__device__ inline void view_group_order(const VolGeom &g, const DevView &V)
+{
+    constexpr int kCls = 32;
+    __shared__ int cnt[kCls][256];
+    __shared__ int base[kCls];
+    __shared__ float red[4];
+    const int G = V.groups, tid = threadIdx.x;
+    int32_t *order = V.group_order, *cls = V.group_order + G;
+    const int chunk = (G + 255) / 256, lo = min(tid * chunk, G), hi = min(lo + chunk, G);
+    const int rays = G > 4096 ? 1 : kRenderTilesPerWg;
+    const float rw = __builtin_amdgcn_rcpf((float)V.width), rh = __builtin_amdgcn_rcpf((float)V.height);
+    float lmax = 0.0f;
+    for (int gi = lo; gi < hi; gi++) {
+        float best = 0.0f;
+        for (int q = 0; q < rays; q++) {
+            const int t = min(V.tile_begin + gi * kRenderTilesPerWg + (rays == 1 ? 1 : q),
+                              V.tile_end - 1);
+            const int px = min((t % V.tiles_x) * 8 + 4, V.width - 1);
+            const int py = min((t / V.tiles_x) * 8 + 4, V.height - 1);
+            const float sx = ((float)(2 * px + 1) * rw - 1.0f) * V.kx;
+            const float sy = (1.0f - (float)(2 * py + 1) * rh) * V.ky;
+            float d[3];
+            for (int k = 0; k < 3; k++) d[k] = V.f[k] + sx * V.r[k] + sy * V.u[k];
+            const float inv = rsqrtf(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+            float t0 = 0.0f, t1 = INFINITY;
+            for (int k = 0; k < 3; k++) {
+                d[k] *= inv;
+                const float o = V.eye[k];
+                if (d[k] == 0.0f) {
+                    if (o < 0.0f || o > (float)g.dims[k]) t1 = -1.0f;
+                    continue;
+                }
+                const float rk = __builtin_amdgcn_rcpf(d[k]);
+                const float ta = -o * rk, tb = ((float)g.dims[k] - o) * rk;
+                t0 = fmaxf(t0, fminf(ta, tb));
+                t1 = fminf(t1, fmaxf(ta, tb));
+            }
+            for (int c = 0; c < V.n_clip; c++) {
+                const float *pl = V.clip[c];
+                const float nd = pl[0] * d[0] + pl[1] * d[1] + pl[2] * d[2];
+                const float no = pl[0] * V.eye[0] + pl[1] * V.eye[1] + pl[2] * V.eye[2];
+                if (nd > 0.0f) t0 = fmaxf(t0, (pl[3] - no) * __builtin_amdgcn_rcpf(nd));
+                else if (nd < 0.0f) t1 = fminf(t1, (pl[3] - no) * __builtin_amdgcn_rcpf(nd));
+                else if (no < pl[3]) t1 = -1.0f;
+            }
+            best = fmaxf(best, t1 - t0);
+        }
+        cls[gi] = __float_as_int(best);
+        lmax = fmaxf(lmax, best);
+    }
+    for (int c = 0; c < kCls; c++) cnt[c][tid] = 0;
+    for (int o = 32; o > 0; o >>= 1) lmax = fmaxf(lmax, __shfl_xor(lmax, o, 64));
+    if ((tid & 63) == 0) red[tid >> 6] = lmax;
+    __syncthreads();
+    lmax = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+    const float scale = lmax > 0.0f ? (float)kCls / lmax : 0.0f;
+    for (int gi = lo; gi < hi; gi++) {
+        const int c = kCls - 1 - min(max((int)(__int_as_float(cls[gi]) * scale), 0), kCls - 1);
+        cls[gi] = c;   // class 0: the longest rays
+        cnt[c][tid]++;
+    }
+    __syncthreads();
+    if (tid < kCls) {   // exclusive prefix over the threads, per class
+        int run = 0;
+        for (int t = 0; t < 256; t++) {
+            const int n = cnt[tid][t];
+            cnt[tid][t] = run;
+            run += n;
+        }
+        base[tid] = run;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        int run = 0;
+        for (int c = 0; c < kCls; c++) {
+            const int n = base[c];
+            base[c] = run;
+            run += n;
+        }
+    }
+    __syncthreads();
+    for (int gi = lo; gi < hi; gi++) {
+        const int c = cls[gi];
+        order[base[c] + cnt[c][tid]++] = gi;
+    }
+}
+
+// Per-launch view preparation in one grid (views along y): workgroup 0 of a view tabulates
+// its transfer functions (value/slope table and opacity prefix counts) into V.tables,
+// workgroup 1 sorts its tile groups into dispatch order.  Reads only the views.
 template <int C>
-__global__ void __launch_bounds__(256)
-k_view_setup(const DevView *__restrict__ views, const DevCell *__restrict__ table, int64_t n_cells)
+__global__ void __launch_bounds__(256) k_view_prep(VolGeom g, const DevView *__restrict__ views)
 {
     __shared__ ViewTables<C> tb;
     const DevView &V = views[blockIdx.y];
-    if (blockIdx.x == 0) {
-        build_tables<C>(V, tb);   // ends with a barrier
-        const uint4 *src = (const uint4 *)&tb;
-        uint4 *dst = (uint4 *)V.tables;
-        for (int i = threadIdx.x; i < (int)(sizeof(ViewTables<C>) / 16); i += 256) dst[i] = src[i];
+    if (blockIdx.x == 1) {
+        if (V.group_order) view_group_order(g, V);
         return;
     }
+    build_tables<C>(V, tb);   // ends with a barrier
+    const uint4 *src = (const uint4 *)&tb;
+    uint4 *dst = (uint4 *)V.tables;
+    for (int i = threadIdx.x; i < (int)(sizeof(ViewTables<C>) / 16); i += 256) dst[i] = src[i];
+}
+
+// Transparency of every node-table cell for every view that skips: workgroup b of a view sets
+// bits 256 b ... 256 b + 255 of V.tmask, bit i when cell i's value range classifies to zero
+// opacity in every channel (cell_transparent with the view's opacity prefix counts from
+// V.tables), one 64-bit ballot per wave.  Reads the current node table: after the last upload
+// and after k_view_prep.
+template <int C>
+__global__ void __launch_bounds__(256)
+k_view_mask(const DevView *__restrict__ views, const DevCell *__restrict__ table, int64_t n_cells)
+{
+    const DevView &V = views[blockIdx.y];
     if (!V.tmask) return;
-    build_prefix<C>(V, tb.pref, tb.wtot);
+    __shared__ int pref[C][257];
+    const ViewTables<C> *tb = (const ViewTables<C> *)V.tables;
+    for (int i = threadIdx.x; i < C * 257; i += 256) (&pref[0][0])[i] = (&tb->pref[0][0])[i];
+    __syncthreads();
     float ulo[C], usc[C];
 #pragma unroll
     for (int c = 0; c < C; c++) {
         usc[c] = V.uscale[c];
         ulo[c] = -V.ulo[c] * usc[c];
     }
-    const int64_t cell = (int64_t)(blockIdx.x - 1) * 256 + threadIdx.x;
-    const bool t = cell < n_cells && cell_transparent<C>(table[cell], ulo, usc, tb.pref);
+    const int64_t cell = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const bool t = cell < n_cells && cell_transparent<C>(table[cell], ulo, usc, pref);
     const unsigned long long b = __ballot(t);
     const int64_t first = cell & ~(int64_t)63;   // first cell of this wave
     if ((threadIdx.x & 63) == 0 && first < n_cells) {
@@ -548,16 +661,29 @@ size_t view_tables_bytes(int C)
     }
 }
 
-hipError_t launch_view_setup(const DevView *views, int n_views, int C, const DevCell *table,
-                             int64_t mask_cells, hipStream_t s)
+hipError_t launch_view_prep(const VolGeom &g, const DevView *views, int n_views, hipStream_t s)
 {
     if (n_views <= 0) return hipSuccess;
-    const dim3 grid((unsigned)(1 + (mask_cells + 255) / 256), (unsigned)n_views), block(256);
+    const dim3 grid(2, (unsigned)n_views), block(256);
+    switch (g.C) {
+    case 1: hipLaunchKernelGGL(k_view_prep<1>, grid, block, 0, s, g, views); break;
+    case 2: hipLaunchKernelGGL(k_view_prep<2>, grid, block, 0, s, g, views); break;
+    case 3: hipLaunchKernelGGL(k_view_prep<3>, grid, block, 0, s, g, views); break;
+    default: hipLaunchKernelGGL(k_view_prep<4>, grid, block, 0, s, g, views); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_view_mask(const DevView *views, int n_views, int C, const DevCell *table,
+                            int64_t n_cells, hipStream_t s)
+{
+    if (n_views <= 0 || n_cells <= 0) return hipSuccess;
+    const dim3 grid((unsigned)((n_cells + 255) / 256), (unsigned)n_views), block(256);
     switch (C) {
-    case 1: hipLaunchKernelGGL(k_view_setup<1>, grid, block, 0, s, views, table, mask_cells); break;
-    case 2: hipLaunchKernelGGL(k_view_setup<2>, grid, block, 0, s, views, table, mask_cells); break;
-    case 3: hipLaunchKernelGGL(k_view_setup<3>, grid, block, 0, s, views, table, mask_cells); break;
-    default: hipLaunchKernelGGL(k_view_setup<4>, grid, block, 0, s, views, table, mask_cells); break;
+    case 1: hipLaunchKernelGGL(k_view_mask<1>, grid, block, 0, s, views, table, n_cells); break;
+    case 2: hipLaunchKernelGGL(k_view_mask<2>, grid, block, 0, s, views, table, n_cells); break;
+    case 3: hipLaunchKernelGGL(k_view_mask<3>, grid, block, 0, s, views, table, n_cells); break;
+    default: hipLaunchKernelGGL(k_view_mask<4>, grid, block, 0, s, views, table, n_cells); break;
     }
     return hipGetLastError();
 }

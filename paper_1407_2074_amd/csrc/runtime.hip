@@ -61,9 +61,12 @@ struct RenderSlot {
     size_t tables_cap = 0;
     uint32_t *tmask = nullptr;  // per-view cell transparency masks of the launch
     size_t tmask_cap = 0;
+    int32_t *gorder = nullptr;  // per-view tile-group dispatch orders (+ length classes)
+    size_t gorder_cap = 0;
     hipEvent_t k0 = nullptr, k1 = nullptr;   // around the render kernel, when timing is on
     bool k_pending = false;
     int64_t version = -1;   // node-table version the slot's last launch read
+    hipEvent_t prep = nullptr;   // end of the launch's preparation on the handle's prep stream
 };
 
 // Default depth segments per ray for views without early termination or checkpoints: the
@@ -117,6 +120,9 @@ struct oct_handle {
     // cross-stream order: end of the last insert's kernels / of the last upload's device work
     hipEvent_t ev_insert = nullptr;
     hipEvent_t ev_upload = nullptr;
+    // a render's view upload, tables and tile-group order run on this internal stream (default
+    // priority), so they overlap the previous render; the render waits for their event
+    hipStream_t prep = nullptr;
     Stage up;                    // upload: cell list / stats / deltas / jobs
     RenderSlot rs[kRenderSlots];
     int next_rs = 0;
@@ -533,6 +539,7 @@ int octree_create(const oct_create_params *params, void *stream, oct_handle **ou
     if (hipHostMalloc((void **)&h->flags_host, (size_t)h->n_cells, hipHostMallocDefault) != hipSuccess)
         return bail(OCT_ENOMEM);
     h->last_used.assign((size_t)h->n_cells, 0);
+    if (hipStreamCreateWithFlags(&h->prep, hipStreamNonBlocking) != hipSuccess) return bail(OCT_EDEVICE);
     if (hipEventCreateWithFlags(&h->ins_ev, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&h->ev_insert, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&h->ev_upload, hipEventDisableTiming) != hipSuccess)
@@ -563,12 +570,15 @@ int octree_destroy(oct_handle *h)
     if (h->ins_ev) (void)hipEventDestroy(h->ins_ev);
     if (h->ev_insert) (void)hipEventDestroy(h->ev_insert);
     if (h->ev_upload) (void)hipEventDestroy(h->ev_upload);
+    if (h->prep) (void)hipStreamDestroy(h->prep);
     stage_free(h->up);
     for (auto &r : h->rs) {
         stage_free(r.st);
         if (r.part) (void)hipFree(r.part);
         if (r.tables) (void)hipFree(r.tables);
         if (r.tmask) (void)hipFree(r.tmask);
+        if (r.gorder) (void)hipFree(r.gorder);
+        if (r.prep) (void)hipEventDestroy(r.prep);
         if (r.k0) (void)hipEventDestroy(r.k0);
         if (r.k1) (void)hipEventDestroy(r.k1);
     }
@@ -1203,6 +1213,7 @@ int render_views(oct_handle *h, int32_t n_views, const oct_view *views, float *c
     hipStream_t s = (hipStream_t)stream;
     std::vector<DevView> dvs((size_t)n_views);
     int64_t n_items = 0;
+    int64_t order_ints = 0;           // every view's tile-group order and length classes
     std::vector<int32_t> split_views;
     std::vector<std::pair<int, size_t>> slot_part;   // (view, float offset) in the slot buffer
     size_t ck_off = 0, part_floats = 0;
@@ -1242,6 +1253,7 @@ int render_views(oct_handle *h, int32_t n_views, const oct_view *views, float *c
         dvs[i].item_begin = (int32_t)n_items;
         dvs[i].groups = groups;
         n_items += (int64_t)groups * nsplit;
+        order_ints += 2 * (int64_t)groups;
     }
     if (n_items > INT32_MAX) return fail(h, OCT_EINVAL, "too many tiles in one launch");
     const size_t v_bytes = dvs.size() * sizeof(DevView);
@@ -1285,17 +1297,32 @@ int render_views(oct_handle *h, int32_t n_views, const oct_view *views, float *c
     for (int i = 0, j = 0; i < n_views; i++)
         dvs[i].tmask = dvs[i].skip ? rs.tmask + (size_t)(j++) * mwords : nullptr;
     uint8_t *hp = (uint8_t *)rs.st.host;
+    if ((size_t)order_ints * 4 > rs.gorder_cap) {
+        if (rs.gorder) HIPCHK(h, hipFree(rs.gorder));
+        rs.gorder = nullptr;
+        rs.gorder_cap = 0;
+        HIPCHK(h, hipMalloc((void **)&rs.gorder, (size_t)order_ints * 4));
+        rs.gorder_cap = (size_t)order_ints * 4;
+    }
+    for (int i = 0, at = 0; i < n_views; i++) {
+        dvs[i].group_order = rs.gorder + at;   // written by the set-up kernel
+        at += 2 * dvs[i].groups;
+    }
     std::memcpy(hp, dvs.data(), v_bytes);
     std::memcpy(hp + sv_off, split_views.data(), sv_bytes);
     std::memset(hp + c_off, 0, c_bytes);
-    // views and split list, plus the zeroed sample counters when they are asked for
-    HIPCHK(h, hipMemcpyAsync(rs.st.dev, hp, out ? c_off + c_bytes : sv_off + sv_bytes,
-                             hipMemcpyHostToDevice, s));
+    // preparation on the prep stream (it overlaps the renders issued before this one): views
+    // and split list (plus the zeroed sample counters when asked for), tables, group order
     uint8_t *dp = (uint8_t *)rs.st.dev;
-    rc = wait_for(h, s, h->ev_upload);   // the node table and pool of the last upload
+    if (!rs.prep) HIPCHK(h, hipEventCreateWithFlags(&rs.prep, hipEventDisableTiming));
+    HIPCHK(h, hipMemcpyAsync(rs.st.dev, hp, out ? c_off + c_bytes : sv_off + sv_bytes,
+                             hipMemcpyHostToDevice, h->prep));
+    HIPCHK(h, launch_view_prep(h->g, (const DevView *)dp, n_views, h->prep));
+    HIPCHK(h, hipEventRecord(rs.prep, h->prep));
+    rc = wait_for(h, s, rs.prep);
+    if (!rc) rc = wait_for(h, s, h->ev_upload);   // the node table and pool of the last upload
     if (rc) return rc;
-    HIPCHK(h, launch_view_setup((const DevView *)dp, n_views, h->g.C, h->table,
-                                n_skip ? h->n_cells : 0, s));
+    if (n_skip) HIPCHK(h, launch_view_mask((const DevView *)dp, n_views, h->g.C, h->table, h->n_cells, s));
     if (h->ktime) {
         if (!rs.k0) HIPCHK(h, hipEventCreate(&rs.k0));
         if (!rs.k1) HIPCHK(h, hipEventCreate(&rs.k1));

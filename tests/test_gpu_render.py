@@ -142,6 +142,27 @@ def test_tile_ranges_compose_the_image(cfg1):
     assert torch.equal(img, full)
 
 
+def test_large_view_equals_its_tile_ranges(cfg1):
+    """A view of more than 4096 tile groups (one estimated ray per group when the launch
+    orders its groups, longest first) equals the same view rendered as four tile ranges of
+    fewer groups (four rays per group) -- the dispatch order changes no pixel."""
+    import torch
+    dims, C, M, vol = cfg1
+    t = _build(dims, C, M, vol, 205)
+    v = synth.make_view(dims, C, 1, az=130.0, el=-25.0, width=1040, height=1032, lod=-1,
+                        dist_scale=0.7)
+    (full,) = t.render([v])
+    tiles = ((1040 + 7) // 8) * ((1032 + 7) // 8)
+    assert tiles > 4 * 4096
+    img = torch.full_like(full, -1.0)
+    step = (tiles + 3) // 4
+    for tb in range(0, tiles, step):
+        v.tile_begin, v.tile_count = tb, step
+        t.render([v], images=[img])
+    assert torch.equal(img, full)
+    assert full[..., 3].max() > 0.1
+
+
 def test_render_during_construction(orc):
     """Renders after each streamed batch match the oracle for the partial octree (EMPTY
     background nodes, incomplete bricks, per-ray LOD)."""
