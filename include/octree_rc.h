@@ -105,7 +105,7 @@ typedef struct {
                                    checkpoints) are marched as this many depth segments by
                                    different waves and composited afterwards, which shortens
                                    a launch's longest serial chain; 0 = automatic (one per
-                                   256 positions of the volume diagonal, at most 6), 1 = one
+                                   256 positions of the volume diagonal, at most 5), 1 = one
                                    pass, at most 16.  Only compositing rounding differs
                                    between segment counts.                                */
     int32_t reserved[2];        /* must be 0                                               */

@@ -58,7 +58,10 @@ __device__ inline WgItem item_of(const DevView *__restrict__ views, int n_views,
 #endif
     WgItem it;
     it.view = lo;
-    it.seg = r / gcount;
+    // inside an XCD, consecutive workgroups go to its shader engines in turn: with an even
+    // segment count the same segment of every group would land on the same engines (segments
+    // differ in cost), so even counts rotate the segment order from block to block
+    it.seg = (S & 1) ? r / gcount : (r / gcount + blk) % S;
     it.tile0 = V.tile_begin + gi * kRenderTilesPerWg;
     it.ntiles = min(kRenderTilesPerWg, V.tile_end - it.tile0);
     return it;

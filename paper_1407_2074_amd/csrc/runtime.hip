@@ -72,13 +72,17 @@ struct RenderSlot {
 // Default depth segments per ray for views without early termination or checkpoints: the
 // longest rays set a launch's duration, and splitting them across waves shortens that
 // critical path.  One segment per kSplitPositions positions of the longest possible ray (the
-// volume diagonal over the step), at most kSplitMax (6 measured fastest for 1024x1024 views of
-// a 512x512x256 octree; short rays gain nothing and stay whole).
+// volume diagonal over the step), at most kSplitMax (5 measured fastest for 1024x1024 views of
+// a 512x512x256 octree with the longest tile groups dispatched first; short rays gain nothing
+// and stay whole).
 #ifndef OCTRC_SPLIT
-#define OCTRC_SPLIT 6
+#define OCTRC_SPLIT 5
 #endif
 constexpr int kSplitMax = OCTRC_SPLIT;
-constexpr double kSplitPositions = 256.0;
+#ifndef OCTRC_SPLIT_POSITIONS
+#define OCTRC_SPLIT_POSITIONS 256.0
+#endif
+constexpr double kSplitPositions = OCTRC_SPLIT_POSITIONS;
 
 int auto_segments(const VolGeom &g, const oct_view &v)
 {
