@@ -166,6 +166,12 @@ render_body(const VolGeom &g, const DevCell *__restrict__ table, const uint8_t *
 #pragma unroll
     for (int c = 0; c < C; c++) avg[c] = 0.0f;
 
+    // the 8 corners of the last trilinear sample (bordered-brick byte offset last_off):
+    // consecutive positions often fall between the same 8 voxels, and the loads are what the
+    // texture data path is busiest with
+    uint32_t last_off = 0xffffffffu;
+    uint2 c000 = {0, 0}, c100 = {0, 0}, c010 = {0, 0}, c110 = {0, 0};
+    uint2 c001 = {0, 0}, c101 = {0, 0}, c011 = {0, 0}, c111 = {0, 0};
     bool live = ray.hit;
     while (live) {
         if (k >= k_end) break;
@@ -240,6 +246,7 @@ render_body(const VolGeom &g, const DevCell *__restrict__ table, const uint8_t *
                 brick = ks.x == kBrick;
                 if (flags && ks.x != kAvg) flags[cidx] = brick ? 1 : 2;  // used / requested
                 if (brick) {
+                    last_off = 0xffffffffu;   // another brick: reload
                     base = pool + (uint64_t)ks.y * brick_bytes;
                     bofs[0] = (float)(cx * g.M) - 0.5f;
                     bofs[1] = (float)(cy * g.M) - 0.5f;
@@ -288,16 +295,21 @@ render_body(const VolGeom &g, const DevCell *__restrict__ table, const uint8_t *
             const uint32_t off = __umul24((uint32_t)ii[2], slice8) +
                                  __umul24((uint32_t)ii[1], row8) + ((uint32_t)ii[0] << 3);
             if constexpr (sizeof(T) == 2) {
-                const uint8_t *a0 = base + off;
-                const uint8_t *a1 = a0 + slice8;
-                const uint2 w000 = *(const uint2 *)(a0);
-                const uint2 w100 = *(const uint2 *)(a0 + 8);
-                const uint2 w010 = *(const uint2 *)(a0 + row8);
-                const uint2 w110 = *(const uint2 *)(a0 + row8 + 8);
-                const uint2 w001 = *(const uint2 *)(a1);
-                const uint2 w101 = *(const uint2 *)(a1 + 8);
-                const uint2 w011 = *(const uint2 *)(a1 + row8);
-                const uint2 w111 = *(const uint2 *)(a1 + row8 + 8);
+                if (off != last_off) {
+                    const uint8_t *a0 = base + off;
+                    const uint8_t *a1 = a0 + slice8;
+                    c000 = *(const uint2 *)(a0);
+                    c100 = *(const uint2 *)(a0 + 8);
+                    c010 = *(const uint2 *)(a0 + row8);
+                    c110 = *(const uint2 *)(a0 + row8 + 8);
+                    c001 = *(const uint2 *)(a1);
+                    c101 = *(const uint2 *)(a1 + 8);
+                    c011 = *(const uint2 *)(a1 + row8);
+                    c111 = *(const uint2 *)(a1 + row8 + 8);
+                    last_off = off;
+                }
+                const uint2 w000 = c000, w100 = c100, w010 = c010, w110 = c110;
+                const uint2 w001 = c001, w101 = c101, w011 = c011, w111 = c111;
 #pragma unroll
                 for (int c = 0; c < C; c++) {
                     auto ch = [&](const uint2 &w) -> float {
@@ -475,7 +487,10 @@ k_combine(const DevView *__restrict__ views, const int32_t *__restrict__ split_v
 // approximate reciprocals.
 __device__ inline void view_group_order(const VolGeom &g, const DevView &V)
 {
-    constexpr int kCls = 32;
+#ifndef OCTRC_ORDER_CLASSES
+#define OCTRC_ORDER_CLASSES 32
+#endif
+    constexpr int kCls = OCTRC_ORDER_CLASSES;
     __shared__ int cnt[kCls][256];
     __shared__ int base[kCls];
     __shared__ float red[4];
