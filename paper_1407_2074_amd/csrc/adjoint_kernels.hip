@@ -15,11 +15,12 @@
 //          dL/da_e   = T_e * (gC . (rgb_e - Bc) + gA * (1 - Ba))
 //      and then Bc <- a_e rgb_e + (1 - a_e) Bc, Ba <- a_e + (1 - a_e) Ba,
 //      where (gC, gA) = dL/d(pixel RGBA).
-// The event gradient flows into the two table entries it interpolated (LDS accumulator per
-// workgroup, added to the view's table gradient at the end) and, through the table slope and
-// the trilinear weights, into the eight level-0 corner voxels: summed per lane in registers
-// while the ray stays in one corner cube (a step to a face neighbour keeps the four shared
-// corners) and added to memory with float atomics when corners leave.
+// The event gradient flows into the two table entries it interpolated (summed per lane in
+// registers while consecutive positions use the same entry pair, then added to an LDS
+// accumulator per workgroup, which goes to the view's table gradient at the end) and, through
+// the table slope and the trilinear weights, into the eight level-0 corner voxels: summed per
+// lane in registers while the ray stays in one corner cube (a step to a face neighbour keeps
+// the four shared corners) and added to memory with float atomics when corners leave.
 // Every position is evaluated (no empty-space skipping): a zero-opacity sample still has a
 // non-zero gradient with respect to the table.
 #include "raycommon.h"
@@ -259,6 +260,16 @@ k_render_backward(VolGeom g, const DevCell *__restrict__ table, const uint8_t *_
         Marcher<T, C> mb(g, table, pool, brick_bytes, ray.L);
         float Bc[3] = {0.0f, 0.0f, 0.0f}, Ba = 0.0f;
         CubeAcc<C> acc(dvox, nvox0, g.dims);
+        // table gradients of the entry pair (li, li + 1) each channel last interpolated in,
+        // summed in registers while consecutive positions keep using that pair
+        int li[C];
+        float ga[C][4], gb[C][4];
+#pragma unroll
+        for (int c = 0; c < C; c++) {
+            li[c] = -1;
+#pragma unroll
+            for (int q = 0; q < 4; q++) ga[c][q] = gb[c][q] = 0.0f;
+        }
         // the checkpoint blocks this wave walks: all of the ray, or the blocks of its depth
         // segment (the forward split the ray the same way); then T holds the transmittance in
         // front of the segment and (Bc, Ba) start as the composite of the segments behind it
@@ -342,11 +353,21 @@ k_render_backward(VolGeom g, const DevCell *__restrict__ table, const uint8_t *_
                     for (int q = 0; q < 3; q++) Bc[q] = a * rgba[c][q] + (1.0f - a) * Bc[q];
                     Ba = a + (1.0f - a) * Ba;
                     const float fr = cq[c].fr;
-                    for (int q = 0; q < 4; q++) {
-                        if (gq[q] != 0.0f) {
-                            atomicAdd(&s_dlut[c][cq[c].i][q], (1.0f - fr) * gq[q]);
-                            atomicAdd(&s_dlut[c][cq[c].i + 1][q], fr * gq[q]);
+                    if (cq[c].i != li[c]) {
+                        if (li[c] >= 0) {
+#pragma unroll
+                            for (int q = 0; q < 4; q++) {
+                                if (ga[c][q] != 0.0f) atomicAdd(&s_dlut[c][li[c]][q], ga[c][q]);
+                                if (gb[c][q] != 0.0f) atomicAdd(&s_dlut[c][li[c] + 1][q], gb[c][q]);
+                                ga[c][q] = gb[c][q] = 0.0f;
+                            }
                         }
+                        li[c] = cq[c].i;
+                    }
+#pragma unroll
+                    for (int q = 0; q < 4; q++) {
+                        ga[c][q] += (1.0f - fr) * gq[q];
+                        gb[c][q] += fr * gq[q];
                     }
                     if (dvox && sm.brick && cq[c].inside) {
                         const float4 de = cq[c].de;
@@ -367,6 +388,14 @@ k_render_backward(VolGeom g, const DevCell *__restrict__ table, const uint8_t *_
             }
         }
         if (dvox) acc.flush();
+#pragma unroll
+        for (int c = 0; c < C; c++)
+            if (li[c] >= 0)
+#pragma unroll
+                for (int q = 0; q < 4; q++) {
+                    if (ga[c][q] != 0.0f) atomicAdd(&s_dlut[c][li[c]][q], ga[c][q]);
+                    if (gb[c][q] != 0.0f) atomicAdd(&s_dlut[c][li[c] + 1][q], gb[c][q]);
+                }
     }
     __syncthreads();
     for (int i = threadIdx.x; i < C * 256 * 4; i += kThreads) {
