@@ -1,10 +1,13 @@
-// Forward ray casting (Algorithm 1, "Basic Ray-Casting"), one 64-lane wave per 8x8 pixel tile,
-// several tiles of one view per workgroup (kRenderTilesPerWg waves).
+// Forward ray casting (Algorithm 1, "Basic Ray-Casting"), one 64-lane wave per 8x8 pixel tile
+// (or per depth segment of a tile's rays), several tiles of one view per workgroup
+// (kRenderTilesPerWg waves).
 //
-// Per workgroup the view's transfer functions are tabulated into LDS (256 RGBA value/slope
-// pairs per channel) together with a prefix count of the entries with non-zero opacity; the
-// latter turns "is every sample in this node transparent?" into two LDS reads per channel,
-// which drives the exact empty-space skipping (skipped positions would add exactly zero).
+// Per launch, k_view_prep tabulates each view's transfer functions (256 RGBA value/slope pairs
+// per channel, plus a prefix count of the entries with non-zero opacity) and orders its tile
+// groups, and k_view_mask turns the prefix counts into one bit per node-table cell: set when
+// every value the cell can produce classifies to zero opacity in every channel.  Every render
+// workgroup copies the value/slope table (and a small mask) into LDS; the mask drives the exact
+// empty-space skipping (skipped positions would add exactly zero).
 //
 // Geometry follows the float32 operation sequence written in raycommon.h; this file is
 // compiled without floating-point contraction.
