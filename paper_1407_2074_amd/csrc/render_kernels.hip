@@ -54,11 +54,7 @@ __device__ inline WgItem item_of(const DevView *__restrict__ views, int n_views,
     const int blk = j / (8 * S), r = j - blk * 8 * S;
     const int gcount = min(8, V.groups - 8 * blk);
     const int gs = 8 * blk + r % gcount;   // position in dispatch order
-#ifdef OCTRC_NO_GROUP_ORDER
-    const int gi = gs;
-#else
     const int gi = V.group_order ? V.group_order[gs] : gs;
-#endif
     WgItem it;
     it.view = lo;
     // inside an XCD, consecutive workgroups go to its shader engines in turn: with an even
@@ -190,10 +186,6 @@ render_body(const VolGeom &g, const DevCell *__restrict__ table, const uint8_t *
             const float m = tk * d[q];
             p[q] = o[q] + m;
         }
-#ifdef OCTRC_NO_COUNTDOWN
-        k_lo = 1;
-        k_hi = 0;
-#endif
         if (k < k_lo || k > k_hi) {
             int v[3];
 #pragma unroll
