@@ -98,8 +98,8 @@ render_body(const VolGeom &g, const DevCell *__restrict__ table, const uint8_t *
     }
     const uint32_t *const tmask = V.tmask;
     const float step = V.step;
-    // 1/step for the position bounds of cells (each keeps a margin of a whole step, far above
-    // the relative error of a product with the rounded reciprocal)
+    // 1/step for the exit position of a skipped box (which keeps a margin of a whole step, far
+    // above the relative error of a product with the rounded reciprocal)
     const float rstep = 1.0f / step;
     const float ert_T = V.ert < 1.0f ? 1.0f - V.ert : -1.0f;
     const bool skip = V.skip != 0;
@@ -151,14 +151,12 @@ render_body(const VolGeom &g, const DevCell *__restrict__ table, const uint8_t *
     // transmittance and colour from the segment's start (the whole ray when not split)
     float Tr = 1.0f, Cr = 0.0f, Cg = 0.0f, Cb = 0.0f;
     int k = k_begin, composited = 0, trilinear = 0, next_ck = k_begin;
-    int blo[3] = {1, 1, 1}, bhi[3] = {0, 0, 0};  // cached cell, level-0 voxel box (inclusive)
-    // positions k_lo..k_hi lie at least 1/64 voxel inside the cached cell (and one step away
-    // from its faces), so their voxel test can only confirm the cell and is skipped
-    int k_lo = 1, k_hi = 0;
     bool brick = false;
     const uint8_t *base = nullptr;
-    // brick coordinate of a position: p 2^-L - (cell origin - 1 border voxel + 1/2 voxel)
-    float bofs[3] = {0.0f, 0.0f, 0.0f};
+    // brick coordinate of a position in the cached cell: p 2^-L - (cell origin - 1 border voxel
+    // + 1/2 voxel); infinite while no cell is cached
+    float bofs[3] = {INFINITY, INFINITY, INFINITY};
+    const float lq_end = (float)g.M + 0.5f;
     const float imax = (float)(S - 2);                  // last corner-pair origin in the brick
     const uint32_t row8 = (uint32_t)S * 8u, slice8 = (uint32_t)(S * S) * 8u;
     float avg[C];
@@ -186,88 +184,78 @@ render_body(const VolGeom &g, const DevCell *__restrict__ table, const uint8_t *
             const float m = tk * d[q];
             p[q] = o[q] + m;
         }
-        if (k < k_lo || k > k_hi) {
+        // brick coordinates of the position in the cached cell (also those of the sample). The
+        // cell holds the position's clamped voxel whenever all three lie in [1/2, M + 1/2):
+        // the single rounding of p 2^-L - bofs is monotone and both bounds are floats, so a
+        // coordinate can pass only if its exact value passes, or, just below 1/2, where the
+        // position lies just below the volume's low face and its voxel is clamped into this
+        // cell anyway. A position that fails (a new cell, or one clamped back into the same
+        // cell from outside the volume) looks its cell up again, which gives the same sample.
+        float lq[3];
+#pragma unroll
+        for (int q = 0; q < 3; q++) lq[q] = __builtin_fmaf(p[q], scaleL, -bofs[q]);
+        if (!(fminf(fminf(lq[0], lq[1]), lq[2]) >= 0.5f &&
+              fmaxf(fmaxf(lq[0], lq[1]), lq[2]) < lq_end)) {
+            // the clamped voxel of the position and its cell at level L
             int v[3];
 #pragma unroll
             for (int q = 0; q < 3; q++) v[q] = min(max((int)floorf(p[q]), 0), g.dims[q] - 1);
-            if (v[0] < blo[0] || v[0] > bhi[0] || v[1] < blo[1] || v[1] > bhi[1] ||
-                v[2] < blo[2] || v[2] > bhi[2]) {
-                int cx, cy, cz;
-                if (csh >= 0) {
-                    cx = v[0] >> csh;
-                    cy = v[1] >> csh;
-                    cz = v[2] >> csh;
-                } else {
-                    cx = v[0] / csz;
-                    cy = v[1] / csz;
-                    cz = v[2] / csz;
+            int cx, cy, cz;
+            if (csh >= 0) {
+                cx = v[0] >> csh;
+                cy = v[1] >> csh;
+                cz = v[2] >> csh;
+            } else {
+                cx = v[0] / csz;
+                cy = v[1] / csz;
+                cz = v[2] / csz;
+            }
+            const int cidx = coff + (cz * G + cy) * G + cx;
+            if (skip && mask_bit<kLdsMask>(tmask, smask, cidx)) {
+                // widen to the largest transparent ancestor, jump to just before its exit
+                int lev = L, ax = cx, ay = cy, az = cz;
+                while (lev < g.N) {
+                    const int pg = g.grid[lev + 1];
+                    if (!mask_bit<kLdsMask>(tmask, smask, g.cell_off[lev + 1] +
+                                             ((az >> 1) * pg + (ay >> 1)) * pg + (ax >> 1)))
+                        break;
+                    lev++;
+                    ax >>= 1;
+                    ay >>= 1;
+                    az >>= 1;
                 }
-                const int cidx = coff + (cz * G + cy) * G + cx;
-                if (skip && mask_bit<kLdsMask>(tmask, smask, cidx)) {
-                    // widen to the largest transparent ancestor, jump to just before its exit
-                    int lev = L, ax = cx, ay = cy, az = cz;
-                    while (lev < g.N) {
-                        const int pg = g.grid[lev + 1];
-                        if (!mask_bit<kLdsMask>(tmask, smask, g.cell_off[lev + 1] +
-                                                 ((az >> 1) * pg + (ay >> 1)) * pg + (ax >> 1)))
-                            break;
-                        lev++;
-                        ax >>= 1;
-                        ay >>= 1;
-                        az >>= 1;
-                    }
-                    const int e = g.M << lev;
-                    const int bl[3] = {ax * e, ay * e, az * e};
-                    float te = INFINITY;
-#pragma unroll
-                    for (int q = 0; q < 3; q++) {
-                        const float plane = d[q] > 0.0f ? (float)(bl[q] + e) : (float)bl[q];
-                        if (d[q] != 0.0f) te = fminf(te, (plane - o[q]) * invd[q]);
-                    }
-                    // one whole step of margin: every skipped position lies inside the box
-                    const float kf = floorf((te - t0) * rstep) - 1.0f;
-                    k = (kf > (float)(k + 1)) ? (int)fminf(kf, 2.0e9f) : k + 1;
-                    blo[0] = 1;
-                    bhi[0] = 0;
-                    k_lo = 1;
-                    k_hi = 0;
-                    continue;
-                }
-                const DevCell &cell = table[cidx];
-                blo[0] = cx * csz; bhi[0] = blo[0] + csz - 1;
-                blo[1] = cy * csz; bhi[1] = blo[1] + csz - 1;
-                blo[2] = cz * csz; bhi[2] = blo[2] + csz - 1;
-                const int2 ks = *(const int2 *)&cell.kind;
-                brick = ks.x == kBrick;
-                if (flags && ks.x != kAvg) flags[cidx] = brick ? 1 : 2;  // used / requested
-                if (brick) {
-                    last_off = 0xffffffffu;   // another brick: reload
-                    base = pool + (uint64_t)ks.y * brick_bytes;
-                    bofs[0] = (float)(cx * g.M) - 0.5f;
-                    bofs[1] = (float)(cy * g.M) - 0.5f;
-                    bofs[2] = (float)(cz * g.M) - 0.5f;
-                } else {
-                    const float4 av = *(const float4 *)cell.avg;
-                    const float a4[4] = {av.x, av.y, av.z, av.w};
-#pragma unroll
-                    for (int c = 0; c < C; c++) avg[c] = a4[c];
-                }
-                // positions safely inside the cell: the box shrunk by 1/64 voxel per face
-                float tin = -INFINITY, tout = INFINITY;
+                const int e = g.M << lev;
+                const int bl[3] = {ax * e, ay * e, az * e};
+                float te = INFINITY;
 #pragma unroll
                 for (int q = 0; q < 3; q++) {
-                    if (d[q] != 0.0f) {
-                        const float pa = ((float)blo[q] + 0.015625f - o[q]) * invd[q];
-                        const float pb = ((float)(bhi[q] + 1) - 0.015625f - o[q]) * invd[q];
-                        tin = fmaxf(tin, fminf(pa, pb));
-                        tout = fminf(tout, fmaxf(pa, pb));
-                    }
+                    const float plane = d[q] > 0.0f ? (float)(bl[q] + e) : (float)bl[q];
+                    if (d[q] != 0.0f) te = fminf(te, (plane - o[q]) * invd[q]);
                 }
-                const float klo = ceilf((tin - t0) * rstep) + 1.0f;
-                const float khi = floorf((tout - t0) * rstep) - 1.0f;
-                k_lo = klo > (float)k ? (int)fminf(klo, 2.0e9f) : k;
-                k_hi = khi > (float)k ? (int)fminf(khi, 2.0e9f) : -1;
+                // one whole step of margin: every skipped position lies inside the box
+                const float kf = floorf((te - t0) * rstep) - 1.0f;
+                k = (kf > (float)(k + 1)) ? (int)fminf(kf, 2.0e9f) : k + 1;
+                bofs[0] = INFINITY;   // no cell cached: the next position looks its cell up
+                continue;
             }
+            const DevCell &cell = table[cidx];
+            bofs[0] = (float)(cx * g.M) - 0.5f;
+            bofs[1] = (float)(cy * g.M) - 0.5f;
+            bofs[2] = (float)(cz * g.M) - 0.5f;
+            const int2 ks = *(const int2 *)&cell.kind;
+            brick = ks.x == kBrick;
+            if (flags && ks.x != kAvg) flags[cidx] = brick ? 1 : 2;  // used / requested
+            if (brick) {
+                last_off = 0xffffffffu;   // another brick: reload
+                base = pool + (uint64_t)ks.y * brick_bytes;
+            } else {
+                const float4 av = *(const float4 *)cell.avg;
+                const float a4[4] = {av.x, av.y, av.z, av.w};
+#pragma unroll
+                for (int c = 0; c < C; c++) avg[c] = a4[c];
+            }
+#pragma unroll
+            for (int q = 0; q < 3; q++) lq[q] = __builtin_fmaf(p[q], scaleL, -bofs[q]);
         }
         if constexpr (kCount) composited++;
         float s[C];
@@ -277,14 +265,11 @@ render_body(const VolGeom &g, const DevCell *__restrict__ table, const uint8_t *
             int ii[3];
 #pragma unroll
             for (int q = 0; q < 3; q++) {
-                // p 2^-L is exact (a power-of-two scale), so the fused form rounds once, like
-                // the unfused difference of exact terms
-                const float lq = __builtin_fmaf(p[q], scaleL, -bofs[q]);
-                f[q] = __builtin_amdgcn_fractf(lq);
+                f[q] = __builtin_amdgcn_fractf(lq[q]);
                 // inside the node, lq lies in [0.5, M + 0.5); the clamp only guards the
                 // bordered brick against addressing outside itself (truncation of a
                 // non-negative value is its floor)
-                ii[q] = (int)__builtin_amdgcn_fmed3f(lq, 0.0f, imax);
+                ii[q] = (int)__builtin_amdgcn_fmed3f(lq[q], 0.0f, imax);
             }
             // byte offset in the brick, 24-bit multiplies (a bordered brick is < 16 MiB)
             const uint32_t off = __umul24((uint32_t)ii[2], slice8) +
