@@ -67,6 +67,23 @@ def test_cfg1_render_parity(orc, cfg1, thr, lod):
     print(f"thr={thr} lod={lod} max|err|={worst:.2e}")
 
 
+
+@pytest.mark.parametrize("lod", [0, 1])
+def test_axis_aligned_views_parity(orc, cfg1, lod):
+    """Face-on views of odd size: the centre column and row of rays run exactly along the cell
+    faces y = 32 / z = 32 (or x = 32) with zero direction components, and rays near the
+    silhouette graze the volume's faces, where positions can round to just outside it."""
+    dims, C, M, vol = cfg1
+    t = _build(dims, C, M, vol, 205)
+    ref = orc.Tree(vol, _full(C, dims), M, 0, 205)
+    views = [synth.make_view(dims, C, 1, az=az, el=el, width=65, height=63, lod=lod)
+             for az, el in [(0.0, 0.0), (90.0, 0.0), (180.0, 0.0), (270.0, 0.0), (45.0, 0.0)]]
+    imgs = t.render(views)
+    want = ref.render(views)
+    worst, _ = _compare(imgs, want)
+    assert min(w[..., 3].max() for w in want) > 0.1
+    print(f"lod={lod} max|err|={worst:.2e}")
+
 def test_skip_on_off_bit_identical(cfg1):
     import torch
     dims, C, M, vol = cfg1
