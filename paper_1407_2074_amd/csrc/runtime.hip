@@ -857,8 +857,21 @@ int brick_pool_upload(oct_handle *h, uint64_t byte_budget, void *stream, oct_upl
                 if (c.dev_avg[k] != new_avg[(size_t)ci * 4 + k]) return true;
         return false;
     };
-    std::vector<uint8_t> changed((size_t)h->n_cells, 0);
-    for (int64_t i = 0; i < h->n_cells; i++) changed[i] = rep_changed(i);
+    // near_change: the cell or one of its 26 neighbours (same level) changed kind or AVG.
+    // Marked from the changed cells, usually few, instead of testing 27 cells per brick.
+    std::vector<uint8_t> near_change((size_t)h->n_cells, 0);
+    for (int L = 0; L <= g.N; L++) {
+        const int G = g.grid[L];
+        for (int z = 0; z < G; z++)
+            for (int y = 0; y < G; y++)
+                for (int x = 0; x < G; x++) {
+                    if (!rep_changed(cell_index(g, L, x, y, z))) continue;
+                    for (int nz = std::max(z - 1, 0); nz <= std::min(z + 1, G - 1); nz++)
+                        for (int ny = std::max(y - 1, 0); ny <= std::min(y + 1, G - 1); ny++)
+                            for (int nx = std::max(x - 1, 0); nx <= std::min(x + 1, G - 1); nx++)
+                                near_change[cell_index(g, L, nx, ny, nz)] = 1;
+                }
+    }
     std::vector<BrickJob> jobs;
     uint64_t budget_left = byte_budget ? byte_budget : UINT64_MAX;
     uint64_t bricks_total = 0;
@@ -889,14 +902,7 @@ int brick_pool_upload(oct_handle *h, uint64_t byte_budget, void *stream, oct_upl
                     bricks_total++;
                     if (c.slot < 0) continue;
                     // whole brick: new slot, deferred earlier, or a neighbour changed kind/AVG
-                    bool full = c.needs_gather;
-                    for (int dz = -1; dz <= 1 && !full; dz++)
-                        for (int dy = -1; dy <= 1 && !full; dy++)
-                            for (int dx = -1; dx <= 1 && !full; dx++) {
-                                const int nx = x + dx, ny = y + dy, nz = z + dz;
-                                if (nx < 0 || ny < 0 || nz < 0 || nx >= G || ny >= G || nz >= G) continue;
-                                if (changed[cell_index(g, L, nx, ny, nz)]) full = true;
-                            }
+                    bool full = c.needs_gather || near_change[ci];
                     const int32_t *bb = &border_box[(size_t)ci * 6];
                     const bool part = !full && bb[3] >= 0 && bb[4] >= 0 && bb[5] >= 0;
                     if (full || part) {
