@@ -107,8 +107,11 @@ render_body(const VolGeom &g, const DevCell *__restrict__ table, const uint8_t *
     float *const ckpt = V.ckpt;
 
     const int tile = it.tile0 + wave;
-    const int px_i = (tile % V.tiles_x) * 8 + (lane & 7);
-    const int px_j = (tile / V.tiles_x) * 8 + (lane >> 3);
+    // lanes in Morton order over the 8x8 tile: each 16-lane quarter covers a 4x4 block
+    const int mx = (lane & 1) | ((lane >> 1) & 2) | ((lane >> 2) & 4);
+    const int my = ((lane >> 1) & 1) | ((lane >> 2) & 2) | ((lane >> 3) & 4);
+    const int px_i = (tile % V.tiles_x) * 8 + mx;
+    const int px_j = (tile / V.tiles_x) * 8 + my;
     const bool inside = px_i < V.width && px_j < V.height;
     const int64_t pix = (int64_t)px_j * V.width + px_i;
     const Ray ray = setup_ray(V, g, px_i, px_j, inside);
