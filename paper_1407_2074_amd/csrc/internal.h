@@ -86,7 +86,7 @@ struct DevView {
     uint32_t *tmask;
 };
 
-// One workgroup of a render launch: up to kRenderTilesPerWg consecutive tiles of one view,
+// One workgroup of a render launch: up to kRenderTilesPerWg tiles of one view (group_tile),
 // one wave each.
 #ifndef OCTRC_RENDER_WAVES
 #define OCTRC_RENDER_WAVES 4

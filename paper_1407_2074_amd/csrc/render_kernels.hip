@@ -41,6 +41,21 @@ __device__ __forceinline__ bool mask_bit(const uint32_t *m, const uint32_t *lds,
 // groups, segment by segment, so that all segments of the j-th group land on XCD j mod 8
 // (workgroups are dealt round-robin to the 8 XCDs; emitting a group's segments back to back
 // would pin each segment to a fixed subset of XCDs whenever the segment count divides 8).
+
+// Tile q of tile group gi. A whole image with an even number of tile rows and columns is
+// grouped in 2x2 blocks of tiles (the four waves of a workgroup share L1); otherwise a group is
+// four consecutive tiles of the view's row-major tile range.
+__device__ inline int group_tile(const DevView &V, int gi, int q)
+{
+    const int ty = (V.height + 7) >> 3;
+    if (kRenderTilesPerWg == 4 && V.tile_begin == 0 && V.tile_end == V.tiles_x * ty &&
+        !(V.tiles_x & 1) && !(ty & 1)) {
+        const int hx = V.tiles_x >> 1, gx = gi % hx, gy = gi / hx;
+        return (2 * gy + (q >> 1)) * V.tiles_x + 2 * gx + (q & 1);
+    }
+    return V.tile_begin + gi * kRenderTilesPerWg + q;
+}
+
 __device__ inline WgItem item_of(const DevView *__restrict__ views, int n_views, int b)
 {
     int lo = 0, hi = n_views - 1;
@@ -106,7 +121,7 @@ render_body(const VolGeom &g, const DevCell *__restrict__ table, const uint8_t *
     const bool skip = V.skip != 0;
     float *const ckpt = V.ckpt;
 
-    const int tile = it.tile0 + wave;
+    const int tile = group_tile(V, (it.tile0 - V.tile_begin) / kRenderTilesPerWg, wave);
     // lanes in Morton order over the 8x8 tile: each 16-lane quarter covers a 4x4 block
     const int mx = (lane & 1) | ((lane >> 1) & 2) | ((lane >> 2) & 4);
     const int my = ((lane >> 1) & 1) | ((lane >> 2) & 2) | ((lane >> 3) & 4);
@@ -534,8 +549,7 @@ __device__ inline void view_group_order(const VolGeom &g, const DevView &V)
     for (int gi = lo; gi < hi; gi++) {
         float best = 0.0f;
         for (int q = 0; q < rays; q++) {
-            const int t = min(V.tile_begin + gi * kRenderTilesPerWg + (rays == 1 ? 1 : q),
-                              V.tile_end - 1);
+            const int t = min(group_tile(V, gi, rays == 1 ? 1 : q), V.tile_end - 1);
             const int px = min((t % V.tiles_x) * 8 + 4, V.width - 1);
             const int py = min((t / V.tiles_x) * 8 + 4, V.height - 1);
             const float sx = ((float)(2 * px + 1) * rw - 1.0f) * V.kx;
