@@ -159,6 +159,22 @@ def test_tile_ranges_compose_the_image(cfg1):
     assert torch.equal(img, full)
 
 
+
+def test_whole_even_image_equals_its_tile_ranges(cfg1):
+    """A whole image with even tile counts is rendered in 2x2 tile groups, a tile range in
+    groups of consecutive tiles: both cover every tile once, with identical results."""
+    import torch
+    dims, C, M, vol = cfg1
+    t = _build(dims, C, M, vol, 205)
+    v = synth.make_view(dims, C, 1, az=55.0, el=-15.0, width=96, height=80)   # 12 x 10 tiles
+    (full,) = t.render([v])
+    img = torch.full_like(full, -1.0)
+    for tb, tc in ((0, 37), (37, 120 - 37)):
+        v.tile_begin, v.tile_count = tb, tc
+        t.render([v], images=[img])
+    assert torch.equal(img, full)
+    assert float(full[..., 3].max()) > 0.1
+
 def test_large_view_equals_its_tile_ranges(cfg1):
     """A view of more than 4096 tile groups (one estimated ray per group when the launch
     orders its groups, longest first) equals the same view rendered as four tile ranges of
