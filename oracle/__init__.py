@@ -75,6 +75,10 @@ def lib():
         L.orc_rays.argtypes = [ct.c_void_p, ct.POINTER(OrcView), ct.c_void_p, ct.c_void_p]
         L.orc_render_rows.argtypes = [ct.c_void_p, ct.POINTER(OrcView), ct.c_void_p,
                                       ct.c_void_p, ct.c_int, ct.c_int]
+        L.orc_render_window.argtypes = [ct.c_void_p, ct.POINTER(OrcView), ct.c_void_p, ct.c_int,
+                                        ct.c_int, ct.c_int, ct.c_int]
+        L.orc_poke_level0.argtypes = [ct.c_void_p, ct.c_int, ct.c_int, ct.c_int, ct.c_int,
+                                      ct.c_double]
         L.orc_num_threads.restype = ct.c_int
         L.orc_node_info.argtypes = [ct.c_void_p, ct.c_int, ct.c_int, ct.c_int, ct.c_int,
                                     ct.c_void_p, ct.c_void_p, ct.c_void_p]
@@ -156,6 +160,8 @@ class Tree:
 
     def dump(self) -> bytes:
         need = lib().orc_dump(self.h, None, 0)
+        if need == 0:
+            raise ValueError("no dump after an in-place level-0 replacement")
         buf = np.empty(need, np.uint8)
         lib().orc_dump(self.h, _ptr(buf), need)
         return buf.tobytes()
@@ -208,6 +214,21 @@ class Tree:
                                  row_step) != 0:
             raise ValueError("oracle render rejected the view")
         return img, ns
+
+    def poke_level0(self, c: int, x: int, y: int, z: int, value: float):
+        """Replace one level-0 value in place (threshold 0, brick node): for finite differences
+        of LOD-0 renders; afterwards only LOD-0 renders and gradients are allowed."""
+        if lib().orc_poke_level0(self.h, int(c), int(x), int(y), int(z), float(value)) != 0:
+            raise ValueError("oracle refused the level-0 replacement")
+
+    def render_window(self, view, x0: int, y0: int, x1: int, y1: int):
+        """Render only the pixels x0 <= i < x1, y0 <= j < y1 (others zero)."""
+        ov = to_orc_view(view)
+        img = np.zeros((view.height, view.width, 4), np.float64)
+        if lib().orc_render_window(self.h, ct.byref(ov), _ptr(img), int(x0), int(y0), int(x1),
+                                   int(y1)) != 0:
+            raise ValueError("oracle render rejected the window")
+        return img
 
     def rays(self, view):
         ov = to_orc_view(view)

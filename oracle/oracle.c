@@ -94,6 +94,7 @@ typedef struct {
     double *V[ORC_MAXL];   /* level values, planar [C][ez][ey][ex] (exact in the data type) */
     double *R[ORC_MAXL];   /* represented field, same layout */
     orc_node *nodes[ORC_MAXL];
+    int poked;             /* a level-0 value was replaced in place (orc_poke_level0) */
 } orc_tree;
 
 /* ------------------------------------------------------------------ helpers */
@@ -172,6 +173,7 @@ orc_tree *orc_build(const orc_params *p, const void *v0, const uint8_t *mask)
     for (int L = 0; L < N; L++) {
         const int *e = t->ext[L], *e1 = t->ext[L + 1];
         for (int c = 0; c < C; c++)
+#pragma omp parallel for schedule(static)
             for (int z = 0; z < e1[2]; z++)
                 for (int y = 0; y < e1[1]; y++)
                     for (int x = 0; x < e1[0]; x++) {
@@ -189,9 +191,10 @@ orc_tree *orc_build(const orc_params *p, const void *v0, const uint8_t *mask)
                     }
     }
 
-    /* Per-node statistics straight from the definitions. */
+    /* Per-node statistics straight from the definitions (nodes are independent). */
     for (int L = 0; L <= N; L++) {
         int g = t->G[L];
+#pragma omp parallel for collapse(3) schedule(dynamic, 1)
         for (int bz = 0; bz < g; bz++)
             for (int by = 0; by < g; by++)
                 for (int bx = 0; bx < g; bx++) {
@@ -285,9 +288,10 @@ orc_tree *orc_build(const orc_params *p, const void *v0, const uint8_t *mask)
                 }
     }
 
-    /* Represented field R_L. */
+    /* Represented field R_L (voxels are independent). */
     for (int L = 0; L <= N; L++) {
         const int *e = t->ext[L];
+#pragma omp parallel for schedule(static)
         for (int z = 0; z < e[2]; z++)
             for (int y = 0; y < e[1]; y++)
                 for (int x = 0; x < e[0]; x++) {
@@ -329,7 +333,7 @@ void orc_level_extent(const orc_tree *t, int L, int32_t *ext3)
 /* Copy level L of the mipmap (planar [C][ez][ey][ex]) into out, in the data type. */
 int orc_read_level(const orc_tree *t, int L, void *out)
 {
-    if (L < 0 || L > t->N) return -1;
+    if (L < 0 || L > t->N || (t->poked && L > 0)) return -1;
     int64_t n = t->p.channels * lvl_voxels(t, L);
     for (int64_t i = 0; i < n; i++) {
         if (t->p.dtype == 0) ((uint16_t *)out)[i] = (uint16_t)t->V[L][i];
@@ -353,6 +357,7 @@ int orc_read_level(const orc_tree *t, int L, void *out)
 
 size_t orc_dump(const orc_tree *t, void *buf, size_t cap)
 {
+    if (t->poked) return 0;
     const int C = t->p.channels, M = t->p.brick, S = M + 2;
     const size_t esz = t->p.dtype == 0 ? 2 : 4;
     int64_t n_nodes = 0, n_bricks = 0;
@@ -674,12 +679,12 @@ static void classify(const orc_luts *lu, const orc_view *v, int c, double s, dou
  */
 static int render_rows(const orc_tree *t, int n_views, const orc_view *views,
                        double *const *images, int32_t *const *nsamp, double *const *ert_margin,
-                       int row_begin, int row_step);
+                       int row_begin, int row_end, int row_step, int col_begin, int col_end);
 
 int orc_render(const orc_tree *t, int n_views, const orc_view *views, double *const *images,
                int32_t *const *nsamp, double *const *ert_margin)
 {
-    return render_rows(t, n_views, views, images, nsamp, ert_margin, 0, 1);
+    return render_rows(t, n_views, views, images, nsamp, ert_margin, 0, 1 << 30, 1, 0, 1 << 30);
 }
 
 /* Same as orc_render for the rows row_begin, row_begin + row_step, ... only (other rows are
@@ -688,7 +693,16 @@ int orc_render_rows(const orc_tree *t, const orc_view *view, double *image, int3
                     int row_begin, int row_step)
 {
     if (row_begin < 0 || row_step < 1) return -1;
-    return render_rows(t, 1, view, &image, &nsamp, NULL, row_begin, row_step);
+    return render_rows(t, 1, view, &image, &nsamp, NULL, row_begin, 1 << 30, row_step, 0, 1 << 30);
+}
+
+/* Same as orc_render for the pixels x0 <= i < x1, y0 <= j < y1 of the [H][W] image only (the
+ * others are left untouched): the rays a local change of the volume can reach. */
+int orc_render_window(const orc_tree *t, const orc_view *view, double *image, int x0, int y0,
+                      int x1, int y1)
+{
+    if (x0 < 0 || y0 < 0 || x1 < x0 || y1 < y0) return -1;
+    return render_rows(t, 1, view, &image, NULL, NULL, y0, y1, 1, x0, x1);
 }
 
 int orc_num_threads(void)
@@ -702,20 +716,22 @@ int orc_num_threads(void)
 
 static int render_rows(const orc_tree *t, int n_views, const orc_view *views,
                        double *const *images, int32_t *const *nsamp, double *const *ert_margin,
-                       int row_begin, int row_step)
+                       int row_begin, int row_end, int row_step, int col_begin, int col_end)
 {
     const int C = t->p.channels;
     for (int vi = 0; vi < n_views; vi++) {
         const orc_view *v = &views[vi];
         if (v->width <= 0 || v->height <= 0) return -1;
+        if (t->poked && v->lod != 0) return -1;
         orc_luts *lu = (orc_luts *)malloc(sizeof(orc_luts));
         build_luts(v, C, lu);
         orc_cam cm;
         cam_setup(v, &cm);
         const int W = v->width, H = v->height;
+        const int j_end = row_end < H ? row_end : H, i_end = col_end < W ? col_end : W;
 #pragma omp parallel for schedule(dynamic, 1)
-        for (int j = row_begin; j < H; j += row_step)
-            for (int i = 0; i < W; i++) {
+        for (int j = row_begin; j < j_end; j += row_step)
+            for (int i = col_begin; i < i_end; i++) {
                 double *px = images[vi] + ((int64_t)j * W + i) * 4;
                 orc_ray ry;
                 ray_setup(t, v, &cm, i, j, &ry);
@@ -786,6 +802,8 @@ int orc_render_grad(const orc_tree *t, int n_views, const orc_view *views,
 {
     const int C = t->p.channels;
     const int64_t nv0 = lvl_voxels(t, 0);
+    for (int vi = 0; vi < n_views; vi++)
+        if (t->poked && views[vi].lod != 0) return -1;
     for (int vi = 0; vi < n_views; vi++) {
         const orc_view *v = &views[vi];
         orc_luts *lu = (orc_luts *)malloc(sizeof(orc_luts));
@@ -794,8 +812,14 @@ int orc_render_grad(const orc_tree *t, int n_views, const orc_view *views,
         cam_setup(v, &cm);
         const int W = v->width, H = v->height;
         double *dlut = (double *)calloc((size_t)C * 256 * 4, sizeof(double));
+        /* rays are independent; their contributions are added with atomic updates (only the
+         * order of the FP64 sums depends on the threads) */
+#pragma omp parallel
+        {
         size_t cap = 1024;
         orc_event *ev = (orc_event *)malloc(cap * sizeof(orc_event));
+        double *tl = (double *)calloc((size_t)C * 256 * 4, sizeof(double));  /* this thread's */
+#pragma omp for schedule(dynamic, 1)
         for (int j = 0; j < H; j++)
             for (int i = 0; i < W; i++) {
                 const double *gI = dL_dI[vi] + ((int64_t)j * W + i) * 4;
@@ -844,7 +868,7 @@ int orc_render_grad(const orc_tree *t, int n_views, const orc_view *views,
                     g_rgba[3] = gcr * T + gA * T;
                     gA = gA * (1.0 - a) - a * gcr;
                     /* into the table cell */
-                    double *d0 = dlut + ((int64_t)e->c * 256 + e->slot_i) * 4;
+                    double *d0 = tl + ((int64_t)e->c * 256 + e->slot_i) * 4;
                     double *d1 = d0 + 4;
                     double gs = 0.0;
                     const double *l0 = lu->lut[e->c][e->slot_i], *l1 = lu->lut[e->c][e->slot_i + 1];
@@ -856,10 +880,19 @@ int orc_render_grad(const orc_tree *t, int n_views, const orc_view *views,
                     gs *= e->duds;
                     if (dvox && e->L == 0 && e->brick) {
                         double *dv = dvox + (int64_t)e->c * nv0;
-                        for (int k = 0; k < 8; k++) dv[e->idx[k]] += gs * e->w[k];
+                        for (int k = 0; k < 8; k++) {
+                            const double add = gs * e->w[k];
+#pragma omp atomic
+                            dv[e->idx[k]] += add;
+                        }
                     }
                 }
             }
+        free(ev);
+#pragma omp critical
+        for (int k = 0; k < C * 256 * 4; k++) dlut[k] += tl[k];
+        free(tl);
+        }
         /* table entries -> control points */
         for (int c = 0; c < C; c++)
             for (int k = 0; k < 256; k++) {
@@ -872,7 +905,6 @@ int orc_render_grad(const orc_tree *t, int n_views, const orc_view *views,
                     dctrl[(((int64_t)vi * C + c) * 8 + jj + 1) * 4 + q] += w1 * g;
                 }
             }
-        free(ev);
         free(dlut);
         free(lu);
     }
@@ -925,5 +957,25 @@ int orc_node_info(const orc_tree *t, int L, int bx, int by, int bz, int32_t *sta
     *state = nd->exists ? nd->state : ST_NONE;
     *flags = (nd->has_children ? 1 : 0) | (nd->complete ? 2 : 0) | (nd->populated ? 4 : 0);
     for (int c = 0; c < t->p.channels; c++) avg[c] = nd->avg[c];
+    return 0;
+}
+
+/* Replaces the level-0 value of voxel (x, y, z), channel c, in place, for finite differences
+ * with respect to a voxel: valid only where level 0 is sampled as the data itself, i.e. when
+ * the homogeneity threshold is 0 and the level-0 node holding the voxel is a brick.  Then
+ * R_0 = V_0 there and a view at LOD 0 reads nothing else that depends on the voxel.  Upper
+ * levels, node statistics and the dump keep describing the built volume, so afterwards the
+ * tree refuses everything but LOD-0 renders and gradients (they return -1). */
+int orc_poke_level0(orc_tree *t, int c, int x, int y, int z, double value)
+{
+    if (c < 0 || c >= t->p.channels || t->p.threshold != 0.0) return -1;
+    if (x < 0 || y < 0 || z < 0 || x >= t->ext[0][0] || y >= t->ext[0][1] || z >= t->ext[0][2])
+        return -1;
+    const int M = t->p.brick;
+    const orc_node *nd = node_at(t, 0, x / M, y / M, z / M);
+    if (!nd->exists || nd->state != ST_BRICK) return -1;
+    *lvl_at(t->V[0], t, 0, c, z, y, x) = value;
+    *lvl_at(t->R[0], t, 0, c, z, y, x) = value;
+    t->poked = 1;
     return 0;
 }

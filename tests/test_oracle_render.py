@@ -296,3 +296,47 @@ def test_nonresident_bricks_render_their_avg(orc):
             ref[j, i, :3], ref[j, i, 3] = col, A
     assert img[..., 3].max() > 0.01
     assert np.abs(img - ref).max() < 1e-12
+
+
+def test_window_render_is_the_full_render_cut_out(orc):
+    """The oracle's pixel-window render equals those pixels of the full render and leaves the
+    others untouched."""
+    dims, M, C = (24, 20, 16), 4, 3
+    vol = _random_case(dims, C, blobs=5)
+    t = orc.Tree(vol, _full(C, dims), M, 0, 0)
+    v = synth.make_view(dims, C, 1, az=35.0, el=15.0, width=30, height=22, lod=-1)
+    (full,) = t.render([v])
+    win = t.render_window(v, 7, 3, 19, 15)
+    assert np.array_equal(win[3:15, 7:19], full[3:15, 7:19])
+    win[3:15, 7:19] = 0
+    assert not win.any()
+
+
+def test_level0_poke_equals_rebuilt_tree(orc):
+    """Replacing one level-0 voxel in place gives the LOD-0 images and gradients of a tree
+    built from scratch on the changed volume; everything that reads other levels is refused."""
+    dims, M, C = (20, 18, 14), 4, 2
+    vol = _random_case(dims, C, blobs=6).astype(np.float32) * np.float32(2.0 ** -16)
+    t = orc.Tree(vol, _full(C, dims), M, 0.0, 0.0)
+    v = synth.make_view(dims, C, 1, az=60.0, el=25.0, width=24, height=20, lod=0, dtype="f32")
+    v.tf_pos[:, 1] = 0.005
+    changed = vol.copy()
+    for (c, x, y, z, val) in ((1, 9, 8, 7, 0.03), (0, 0, 17, 13, 0.01), (1, 19, 0, 0, 0.02)):
+        changed[c, z, y, x] = np.float32(val)
+        t.poke_level0(c, x, y, z, float(np.float32(val)))
+    fresh = orc.Tree(changed, _full(C, dims), M, 0.0, 0.0)
+    (a,) = t.render([v])
+    (b,) = fresh.render([v])
+    assert np.array_equal(a, b)
+    g = [np.ones_like(a)]
+    ca, va = t.render_grad([v], g)
+    cb, vb = fresh.render_grad([v], g)
+    assert np.allclose(ca, cb, rtol=1e-12, atol=0) and np.allclose(va, vb, rtol=1e-12, atol=0)
+    with pytest.raises(ValueError):
+        t.dump()
+    v.lod = 1
+    with pytest.raises(ValueError):
+        t.render([v])
+    hom = orc.Tree(vol, _full(C, dims), M, 0.0, 1.0)       # threshold > 0: refused
+    with pytest.raises(ValueError):
+        hom.poke_level0(0, 1, 1, 1, 0.5)
