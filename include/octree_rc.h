@@ -197,7 +197,13 @@ size_t render_ckpt_bytes(const oct_handle *h, int32_t n_views, const oct_view *v
  *   dL_dvoxels device [C][Dz][Dy][Dx] float32 or NULL: gradient w.r.t. the level-0 voxel
  *              values, defined for views with lod 0 on an octree whose level-0 nodes all hold
  *              bricks (threshold 0, everything inserted)
- * Errors: OCT_EINVAL (e.g. voxel gradients requested where not defined), OCT_EDEVICE. */
+ * The workspace must have been filled by the last render_views call that used it, with the
+ * same views, and no upload or clear that changed the octree may come between the two.
+ * Ordering: the backward follows every render and backward issued earlier on this handle, on
+ * any stream (they share its table-gradient accumulators and replay scratch).
+ * Errors: OCT_EINVAL (e.g. voxel gradients requested where not defined, a workspace not filled
+ * by a render of this handle, views that differ from the forward's, an octree changed since
+ * the forward), OCT_EDEVICE. */
 int render_views_backward(oct_handle *h, int32_t n_views, const oct_view *views,
                           const float *const *dL_dimages, const void *ckpt_ws, float *dL_dctrl,
                           float *dL_dvoxels, void *stream);

@@ -94,7 +94,18 @@ int auto_segments(const VolGeom &g, const oct_view &v)
 
 constexpr int kRenderSlots = 8;
 
+// Forward renders that filled a checkpoint workspace: the backward checks that the octree and
+// the views are still those of the forward (ring of the last kCkptLog workspaces).
+constexpr int kCkptLog = 64;
+struct CkptRec {
+    const void *ws = nullptr;
+    int64_t version = -1;
+    uint64_t views_hash = 0;
+    int32_t n_views = 0;
+};
+
 }  // namespace
+
 
 struct oct_handle {
     oct_create_params p{};
@@ -130,6 +141,8 @@ struct oct_handle {
     Stage up;                    // upload: cell list / stats / deltas / jobs
     RenderSlot rs[kRenderSlots];
     int next_rs = 0;
+    CkptRec ckpt_log[kCkptLog];
+    int ckpt_next = 0;
     bool ktime = false;          // octree_render_timing: record the render kernels
     double ktime_ms = 0.0;
     uint64_t ktime_n = 0;
@@ -214,6 +227,31 @@ int wait_for_renders_before(oct_handle *h, hipStream_t s, int64_t v)
     for (auto &r : h->rs)
         if (r.st.ev && r.version < v) HIPCHK(h, hipStreamWaitEvent(s, r.st.ev, 0));
     return OCT_OK;
+}
+
+// FNV-1a over the bytes of a view list (oct_view has no padding: 4-byte fields only).
+uint64_t views_hash(int32_t n_views, const oct_view *views)
+{
+    uint64_t x = 1469598103934665603ull;
+    const uint8_t *b = (const uint8_t *)views;
+    for (size_t i = 0; i < (size_t)n_views * sizeof(oct_view); i++) x = (x ^ b[i]) * 1099511628211ull;
+    return x;
+}
+
+// Records that `ws` now holds the checkpoints of these views at the current table version.
+void ckpt_log_put(oct_handle *h, const void *ws, int32_t n_views, const oct_view *views)
+{
+    CkptRec *r = nullptr;
+    for (auto &e : h->ckpt_log)
+        if (e.ws == ws) r = &e;
+    if (!r) {
+        r = &h->ckpt_log[h->ckpt_next];
+        h->ckpt_next = (h->ckpt_next + 1) % kCkptLog;
+    }
+    r->ws = ws;
+    r->version = h->version;
+    r->views_hash = views_hash(n_views, views);
+    r->n_views = n_views;
 }
 
 int stage_reserve(oct_handle *h, Stage &s, size_t bytes)
@@ -1214,20 +1252,25 @@ static int build_view(oct_handle *h, const oct_view &v, float *image, DevView &d
     return OCT_OK;
 }
 
-int render_views(oct_handle *h, int32_t n_views, const oct_view *views, float *const *images,
-                 void *ckpt_ws, void *stream, oct_render_stats *out)
-{
-    if (!h) return OCT_EINVAL;
-    if (n_views < 0 || (n_views > 0 && (!views || !images))) return fail(h, OCT_EINVAL, "bad view list");
-    HIPCHK(h, hipSetDevice(h->device));
-    hipStream_t s = (hipStream_t)stream;
-    std::vector<DevView> dvs((size_t)n_views);
+// Per-launch plan of a view list: the view records, their work items and depth segments.
+struct LaunchPlan {
     int64_t n_items = 0;
-    int64_t order_ints = 0;           // every view's tile-group order and length classes
-    std::vector<int32_t> split_views;
-    std::vector<std::pair<int, size_t>> slot_part;   // (view, float offset) in the slot buffer
-    size_t ck_off = 0, part_floats = 0;
+    int64_t order_ints = 0;          // every view's tile-group order and length classes
     int64_t max_split_pixels = 0;
+    int n_split = 0;
+    int n_skip = 0;
+    size_t part_floats = 0;          // segment results of split views without checkpoints
+};
+
+// Fills dvs[0 .. n_views) and split[0 .. n_split) for one forward launch.  Views without
+// checkpoints are split into depth segments only when `split_ok`; their segment results go
+// at float offset part_at[i] of a buffer the caller assigns afterwards (dvs[i].part is left
+// NULL for them).  With checkpoints the segment results live in the workspace.
+static int plan_launch(oct_handle *h, int32_t n_views, const oct_view *views,
+                       float *const *images, void *ckpt_ws, bool split_ok, DevView *dvs,
+                       int32_t *split, size_t *part_at, LaunchPlan &pl)
+{
+    size_t ck_off = 0;
     for (int i = 0; i < n_views; i++) {
         int rc = build_view(h, views[i], images[i], dvs[i]);
         if (rc) return rc;
@@ -1242,7 +1285,7 @@ int render_views(oct_handle *h, int32_t n_views, const oct_view *views, float *c
         const int tb = std::min(views[i].tile_begin, tiles);
         const int te = views[i].tile_count < 0 ? tiles : std::min(tiles, tb + views[i].tile_count);
         // early termination makes a later segment depend on the earlier ones: unsplit then
-        const int nsplit = te > tb ? view_segments(h, views[i]) : 1;
+        const int nsplit = te > tb && (ckpt_ws || split_ok) ? view_segments(h, views[i]) : 1;
         dvs[i].nsplit = nsplit;
         dvs[i].tile_begin = tb;
         dvs[i].tile_end = te;
@@ -1252,20 +1295,44 @@ int render_views(oct_handle *h, int32_t n_views, const oct_view *views, float *c
                 dvs[i].part = (float *)((uint8_t *)ckpt_ws + ck_off - view_ckpt_bytes(h, views[i]) +
                                         view_ckpt_part_offset(h, views[i]));
             } else {
-                slot_part.push_back({i, part_floats});
-                part_floats += (size_t)nsplit * npix * 4;
+                part_at[i] = pl.part_floats;
+                pl.part_floats += (size_t)nsplit * npix * 4;
             }
-            split_views.push_back(i);
-            max_split_pixels = std::max<int64_t>(max_split_pixels, (int64_t)npix);
+            split[pl.n_split++] = i;
+            pl.max_split_pixels = std::max<int64_t>(pl.max_split_pixels, (int64_t)npix);
         }
         // the view's work items (the kernel derives each one from its index, item_of)
         const int groups = (te - tb + kRenderTilesPerWg - 1) / kRenderTilesPerWg;
-        dvs[i].item_begin = (int32_t)n_items;
+        dvs[i].item_begin = (int32_t)pl.n_items;
         dvs[i].groups = groups;
-        n_items += (int64_t)groups * nsplit;
-        order_ints += 2 * (int64_t)groups;
+        pl.n_items += (int64_t)groups * nsplit;
+        pl.order_ints += 2 * (int64_t)groups;
+        pl.n_skip += dvs[i].skip ? 1 : 0;
     }
-    if (n_items > INT32_MAX) return fail(h, OCT_EINVAL, "too many tiles in one launch");
+    if (pl.n_items > INT32_MAX) return fail(h, OCT_EINVAL, "too many tiles in one launch");
+    return OCT_OK;
+}
+
+int render_views(oct_handle *h, int32_t n_views, const oct_view *views, float *const *images,
+                 void *ckpt_ws, void *stream, oct_render_stats *out)
+{
+    if (!h) return OCT_EINVAL;
+    if (n_views < 0 || (n_views > 0 && (!views || !images))) return fail(h, OCT_EINVAL, "bad view list");
+    HIPCHK(h, hipSetDevice(h->device));
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<DevView> dvs((size_t)n_views);
+    std::vector<int32_t> split_views((size_t)n_views);
+    std::vector<size_t> part_at((size_t)n_views, 0);
+    LaunchPlan pl;
+    {
+        int rc = plan_launch(h, n_views, views, images, ckpt_ws, true, dvs.data(), split_views.data(),
+                             part_at.data(), pl);
+        if (rc) return rc;
+    }
+    split_views.resize((size_t)pl.n_split);
+    const int64_t n_items = pl.n_items, order_ints = pl.order_ints;
+    const int64_t max_split_pixels = pl.max_split_pixels;
+    const size_t part_floats = pl.part_floats;
     const size_t v_bytes = dvs.size() * sizeof(DevView);
     const size_t sv_off = (v_bytes + 255) & ~(size_t)255;
     const size_t sv_bytes = split_views.size() * sizeof(int32_t);
@@ -1284,7 +1351,8 @@ int render_views(oct_handle *h, int32_t n_views, const oct_view *views, float *c
         HIPCHK(h, hipMalloc(&rs.part, part_floats * sizeof(float)));
         rs.part_cap = part_floats * sizeof(float);
     }
-    for (const auto &sp : slot_part) dvs[sp.first].part = rs.part + sp.second;
+    for (int32_t i : split_views)
+        if (!dvs[i].part) dvs[i].part = rs.part + part_at[i];
     const size_t tbytes = view_tables_bytes(h->g.C);
     if ((size_t)n_views * tbytes > rs.tables_cap) {
         if (rs.tables) HIPCHK(h, hipFree(rs.tables));
@@ -1295,8 +1363,7 @@ int render_views(oct_handle *h, int32_t n_views, const oct_view *views, float *c
     }
     for (int i = 0; i < n_views; i++) dvs[i].tables = (const uint8_t *)rs.tables + (size_t)i * tbytes;
     const int64_t mwords = view_mask_words(h->n_cells);
-    int n_skip = 0;
-    for (int i = 0; i < n_views; i++) n_skip += dvs[i].skip ? 1 : 0;
+    const int n_skip = pl.n_skip;
     if ((size_t)n_skip * mwords * 4 > rs.tmask_cap) {
         if (rs.tmask) HIPCHK(h, hipFree(rs.tmask));
         rs.tmask = nullptr;
@@ -1360,6 +1427,7 @@ int render_views(oct_handle *h, int32_t n_views, const oct_view *views, float *c
         }
     }
     HIPCHK(h, hipEventRecord(rs.st.ev, s));
+    if (ckpt_ws) ckpt_log_put(h, ckpt_ws, n_views, views);
     return OCT_OK;
 }
 
@@ -1371,6 +1439,19 @@ int render_views_backward(oct_handle *h, int32_t n_views, const oct_view *views,
     if (n_views < 1 || !views || !dL_dimages || !ckpt_ws || !dL_dctrl)
         return fail(h, OCT_EINVAL, "backward needs views, dL/dimages, the forward workspace and dL/dctrl");
     const VolGeom &g = h->g;
+    {
+        // the replay must see the octree and the views that the forward's checkpoints came from
+        const CkptRec *r = nullptr;
+        for (const auto &e : h->ckpt_log)
+            if (e.ws == ckpt_ws) r = &e;
+        if (!r)
+            return fail(h, OCT_EINVAL, "the workspace was not filled by a render of this octree");
+        if (r->version != h->version)
+            return fail(h, OCT_EINVAL, "the octree changed (an upload or clear) since the forward "
+                                       "render that filled the workspace");
+        if (r->n_views != n_views || r->views_hash != views_hash(n_views, views))
+            return fail(h, OCT_EINVAL, "the views differ from those of the forward render");
+    }
     if (dL_dvoxels) {
         // voxel gradients flow through trilinear weights of level-0 bricks only
         for (int i = 0; i < n_views; i++)
@@ -1427,6 +1508,9 @@ int render_views_backward(oct_handle *h, int32_t n_views, const oct_view *views,
     const size_t dl_bytes = ((size_t)n_views * dlut_floats * 4 + 255) & ~(size_t)255;
     const size_t scr_bytes = items.size() * (size_t)kRenderTilesPerWg * 64 * kCkptStride * 4;
     if (dl_bytes + scr_bytes > h->bw_tmp_cap) {
+        // an earlier backward on any stream may still use the temporaries
+        for (auto &r : h->rs)
+            if (r.st.ev) HIPCHK(h, hipEventSynchronize(r.st.ev));
         HIPCHK(h, hipStreamSynchronize(s));
         if (h->bw_tmp) HIPCHK(h, hipFree(h->bw_tmp));
         h->bw_tmp = nullptr;
@@ -1436,7 +1520,6 @@ int render_views_backward(oct_handle *h, int32_t n_views, const oct_view *views,
     }
     float *dlut = (float *)h->bw_tmp;
     for (int i = 0; i < n_views; i++) dvs[i].dlut = dlut + (size_t)i * dlut_floats;
-    HIPCHK(h, launch_fill_f32(dlut, (int64_t)n_views * dlut_floats, 0.0f, s));
 
     const size_t v_bytes = dvs.size() * sizeof(DevView);
     const size_t i_off = (v_bytes + 255) & ~(size_t)255;
@@ -1450,8 +1533,13 @@ int render_views_backward(oct_handle *h, int32_t n_views, const oct_view *views,
     std::memcpy(hp, dvs.data(), v_bytes);
     std::memcpy(hp + i_off, items.data(), i_bytes);
     HIPCHK(h, hipMemcpyAsync(rs.st.dev, hp, i_off + i_bytes, hipMemcpyHostToDevice, s));
+    // the forward that wrote the checkpoints and every earlier backward (which shared the
+    // table-gradient accumulators and the replay scratch) may run on other streams: wait for
+    // the last launch of every render slot (a slot's older launches ended before its reuse)
     rc = wait_for(h, s, h->ev_upload);
+    if (!rc) rc = wait_for_renders(h, s);
     if (rc) return rc;
+    HIPCHK(h, launch_fill_f32(dlut, (int64_t)n_views * dlut_floats, 0.0f, s));
     uint8_t *dp = (uint8_t *)rs.st.dev;
     HIPCHK(h, launch_render_backward(g, h->table, h->pool, h->brick_bytes, (const DevView *)dp,
                                      (const WgItem *)(dp + i_off), (int)items.size(),

@@ -234,19 +234,39 @@ class Octree:
         d["complete"] = rc == OCT_OK
         return d
 
+    @staticmethod
+    def _check_buffer(t, what: str, dtype, shape=None, min_bytes=None):
+        """The C ABI takes raw device pointers without sizes: check every buffer here."""
+        import torch
+        if not isinstance(t, torch.Tensor) or not t.is_cuda or not t.is_contiguous():
+            raise TypeError(f"{what} must be a contiguous CUDA tensor")
+        if dtype is not None and t.dtype != dtype:
+            raise TypeError(f"{what} must be {dtype}, got {t.dtype}")
+        if shape is not None and tuple(t.shape) != tuple(shape):
+            raise ValueError(f"{what} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+        if min_bytes is not None and t.numel() * t.element_size() < min_bytes:
+            raise ValueError(f"{what} holds {t.numel() * t.element_size()} bytes, "
+                             f"needs {min_bytes}")
+
     def render(self, views, images=None, stats: bool = False, stream=None, ckpt=None):
         """Render views into torch CUDA images [H][W][4] float32 (allocated when not given)."""
         import torch
         if images is None:
             images = [torch.zeros((v.height, v.width, 4), dtype=torch.float32, device="cuda")
                       for v in views]
+        if len(images) != len(views):
+            raise ValueError("one image per view")
+        for k, (v, im) in enumerate(zip(views, images)):
+            self._check_buffer(im, f"images[{k}]", torch.float32, (v.height, v.width, 4))
         ova = to_oct_views(views)
         ov = ova.ctypes.data_as(ct.POINTER(OctView))
+        if ckpt is not None:
+            self._check_buffer(ckpt, "ckpt", None, min_bytes=self.ckpt_bytes(views))
         ptrs = (ct.c_void_p * len(views))(*[im.data_ptr() for im in images])
         rs = RenderStats()
         self._check(lib.render_views(self.h, len(views), ov, ptrs,
-                                     ct.c_void_p(ckpt.data_ptr()) if ckpt is not None else None,
-                                     _stream(stream), ct.byref(rs) if stats else None))
+                       ct.c_void_p(ckpt.data_ptr()) if ckpt is not None else None,
+                       _stream(stream), ct.byref(rs) if stats else None))
         if stats:
             return images, {k: getattr(rs, k) for k, _ in RenderStats._fields_}
         return images
@@ -260,6 +280,15 @@ class Octree:
     def render_backward(self, views, dL_dimages, ckpt, dctrl, dvox=None, stream=None):
         """Accumulate dL/dctrl [n][C][8][4] (and dL/dvoxel [C][Dz][Dy][Dx]) for the loss whose
         image gradients are dL_dimages, using the workspace of the forward render."""
+        import torch
+        if len(dL_dimages) != len(views):
+            raise ValueError("one image gradient per view")
+        for k, (v, g) in enumerate(zip(views, dL_dimages)):
+            self._check_buffer(g, f"dL_dimages[{k}]", torch.float32, (v.height, v.width, 4))
+        self._check_buffer(ckpt, "ckpt", None, min_bytes=self.ckpt_bytes(views))
+        self._check_buffer(dctrl, "dctrl", torch.float32, min_bytes=len(views) * self.C * 8 * 4 * 4)
+        if dvox is not None:
+            self._check_buffer(dvox, "dvox", torch.float32, (self.C,) + tuple(self.dims[::-1]))
         ova = to_oct_views(views)
         ov = ova.ctypes.data_as(ct.POINTER(OctView))
         gp = (ct.c_void_p * len(views))(*[g.data_ptr() for g in dL_dimages])

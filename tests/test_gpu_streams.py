@@ -133,3 +133,76 @@ def test_upload_during_a_render_keeps_that_render_s_octree():
     assert torch.equal(img_new, want_new)
     for x in (ref_old, ref_new, t):
         x.close()
+
+
+def _grad_tree():
+    import torch
+    from paper_1407_2074_amd.octree import Octree
+    dims = (24, 20, 16)
+    vol = synth.gen_volume(dims, C, seed=9, n_blobs=6).astype(np.float32) / 65536.0
+    t = Octree(dims, C, 8, "f32", 0, 0)
+    t.insert_slices(-1, 0, torch.from_numpy(vol).cuda())
+    t.upload()
+    views = [synth.make_view(dims, C, 9, az=30.0, el=20.0, width=24, height=16, lod=0,
+                             dtype="f32")]
+    return t, views, vol
+
+
+def _backward(t, views, ck, imgs, stream=None):
+    import torch
+    g = [im * 2.0 - 0.25 for im in imgs]
+    dctrl = torch.zeros((len(views), C, 8, 4), dtype=torch.float32, device="cuda")
+    dvox = torch.zeros((C,) + tuple(t.dims[::-1]), dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()
+    t.render_backward(views, g, ck, dctrl, dvox, stream=stream)
+    torch.cuda.synchronize()
+    return dctrl.cpu(), dvox.cpu()
+
+
+def test_forward_and_backward_on_two_streams_match_one_stream():
+    """A backward on another stream than its forward waits for the forward's checkpoints, and two
+    backwards on two streams do not share their temporaries while running."""
+    import torch
+    t, views, _ = _grad_tree()
+    ck = torch.zeros(t.ckpt_bytes(views), dtype=torch.uint8, device="cuda")
+    imgs = t.render(views, ckpt=ck)
+    ref = _backward(t, views, ck, imgs)
+    a, b = torch.cuda.Stream(), torch.cuda.Stream()
+    for _ in range(3):
+        ck2 = torch.zeros_like(ck)
+        imgs2 = t.render(views, ckpt=ck2, stream=a)     # no host synchronisation in between
+        g = [im * 2.0 - 0.25 for im in imgs]
+        d1 = torch.zeros((1, C, 8, 4), dtype=torch.float32, device="cuda")
+        d2 = torch.zeros_like(d1)
+        torch.cuda.synchronize()
+        t.render_backward(views, g, ck2, d1, None, stream=b)
+        t.render_backward(views, g, ck2, d2, None, stream=a)
+        torch.cuda.synchronize()
+        for im, w in zip(imgs2, imgs):
+            assert torch.equal(im, w)
+        for d in (d1, d2):
+            assert float((d.cpu() - ref[0]).abs().max()) <= 1e-5 * float(ref[0].abs().max())
+    t.close()
+
+
+def test_backward_refuses_a_changed_octree_or_other_views():
+    import torch
+    from paper_1407_2074_amd.octree import OCT_EINVAL, OctError
+    t, views, vol = _grad_tree()
+    ck = torch.zeros(t.ckpt_bytes(views), dtype=torch.uint8, device="cuda")
+    imgs = t.render(views, ckpt=ck)
+    other = [synth.make_view(t.dims, C, 9, az=50.0, el=20.0, width=24, height=16, lod=0,
+                             dtype="f32")]
+    with pytest.raises(OctError) as e:
+        _backward(t, other, ck, imgs)
+    assert e.value.code == OCT_EINVAL
+    _backward(t, views, ck, imgs)                       # the matching views are accepted
+    # an upload that changes the octree invalidates the checkpoints
+    t.insert_block(-1, (0, 0, 0), torch.from_numpy(vol[:, :4, :4, :4] * 0.5).cuda())
+    t.upload()
+    with pytest.raises(OctError) as e:
+        _backward(t, views, ck, imgs)
+    assert e.value.code == OCT_EINVAL
+    imgs = t.render(views, ckpt=ck)                     # a new forward makes it valid again
+    _backward(t, views, ck, imgs)
+    t.close()
