@@ -187,6 +187,25 @@ int brick_pool_upload(oct_handle *h, uint64_t byte_budget, void *stream, oct_upl
 int render_views(oct_handle *h, int32_t n_views, const oct_view *views, float *const *images,
                  void *ckpt_ws, void *stream, oct_render_stats *out);
 
+/* render_views for callers that cannot allocate memory: code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation.  Same arguments, images and errors as
+ * render_views, with these differences:
+ *  - No allocation of any kind: the view records, sample counters, transfer-function tables,
+ *    transparency masks and tile-group orders of the launch live in a fixed 16 MiB device
+ *    scratch array that every GPU the library runs on holds until the process ends, and the
+ *    host records in pinned memory that octree_create set aside.
+ *  - At most 64 views per call; a launch whose tables, masks and orders do not fit the scratch
+ *    returns OCT_ERANGE (before anything is enqueued) with the size it needed.
+ *  - Views without a checkpoint workspace are marched in one pass (depth_segments is taken as
+ *    1): the images equal render_views' images for the same views with depth_segments = 1 bit
+ *    for bit, and other depth-segment counts within compositing rounding.  With ckpt_ws the
+ *    call behaves as render_views (segment results live in the workspace).
+ *  - All preparation runs on `stream` (no internal stream).  Successive calls on one handle are
+ *    ordered by the library; calls on two handles of one GPU share that GPU's scratch, so
+ *    calls that overlap in time on one GPU race and their results are undefined. */
+int render_views_noalloc(oct_handle *h, int32_t n_views, const oct_view *views,
+                         float *const *images, void *ckpt_ws, void *stream, oct_render_stats *out);
+
 /* Bytes of checkpoint workspace render_views needs for these views (0 on bad arguments). */
 size_t render_ckpt_bytes(const oct_handle *h, int32_t n_views, const oct_view *views);
 

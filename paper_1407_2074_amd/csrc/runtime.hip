@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -94,6 +95,10 @@ int auto_segments(const VolGeom &g, const oct_view &v)
 
 constexpr int kRenderSlots = 8;
 
+// Views per render_views_noalloc call and bytes of its device scratch (per GPU).
+constexpr int kNoAllocMaxViews = 64;
+constexpr size_t kScratchBytes = (size_t)16 << 20;
+
 // Forward renders that filled a checkpoint workspace: the backward checks that the octree and
 // the views are still those of the forward (ring of the last kCkptLog workspaces).
 constexpr int kCkptLog = 64;
@@ -106,6 +111,11 @@ struct CkptRec {
 
 }  // namespace
 
+// Device scratch of render_views_noalloc: the view records, sample counters, transfer-function
+// tables, transparency masks and tile-group orders of one launch.  Every GPU holds its own
+// copy at its own address, which set-up looks up once per device (scratch_for_device); host
+// code uses only that address, never this name.
+static __device__ __align__(256) uint8_t scratch[kScratchBytes];
 
 struct oct_handle {
     oct_create_params p{};
@@ -139,8 +149,12 @@ struct oct_handle {
     // priority), so they overlap the previous render; the render waits for their event
     hipStream_t prep = nullptr;
     Stage up;                    // upload: cell list / stats / deltas / jobs
-    RenderSlot rs[kRenderSlots];
+    // rs[0 .. kRenderSlots) serve render_views and render_views_backward in turn;
+    // rs[kRenderSlots] is render_views_noalloc's (host records allocated at creation)
+    RenderSlot rs[kRenderSlots + 1];
     int next_rs = 0;
+    void *scratch_dev = nullptr;     // this device's copy of `scratch`
+    hipEvent_t na_copy = nullptr;    // end of the last noalloc call's record copy
     CkptRec ckpt_log[kCkptLog];
     int ckpt_next = 0;
     bool ktime = false;          // octree_render_timing: record the render kernels
@@ -226,6 +240,44 @@ int wait_for_renders_before(oct_handle *h, hipStream_t s, int64_t v)
 {
     for (auto &r : h->rs)
         if (r.st.ev && r.version < v) HIPCHK(h, hipStreamWaitEvent(s, r.st.ev, 0));
+    return OCT_OK;
+}
+
+// Bytes of render_views_noalloc's host records (and of the same prefix of its scratch) for
+// n views: the DevView records, the list of split views, the sample counters.
+struct RecordLayout {
+    size_t v_bytes, sv_off, sv_bytes, c_off, c_bytes;
+};
+RecordLayout record_layout(size_t n_views, size_t n_split)
+{
+    RecordLayout l;
+    l.v_bytes = n_views * sizeof(DevView);
+    l.sv_off = (l.v_bytes + 255) & ~(size_t)255;
+    l.sv_bytes = n_split * sizeof(int32_t);
+    l.c_off = (l.sv_off + l.sv_bytes + 255) & ~(size_t)255;
+    l.c_bytes = kCounterSlots * sizeof(RenderCounters);
+    return l;
+}
+
+size_t noalloc_record_bytes()
+{
+    const RecordLayout l = record_layout(kNoAllocMaxViews, kNoAllocMaxViews);
+    return l.c_off + l.c_bytes;
+}
+
+// Address of `scratch` on device `dev` (the current device), looked up once per device.
+int scratch_for_device(int dev, void **out)
+{
+    static std::mutex mu;
+    static void *addr[64] = {};
+    if (dev < 0 || dev >= 64) return OCT_EDEVICE;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return OCT_EDEVICE;
+        addr[dev] = p;
+    }
+    *out = addr[dev];
     return OCT_OK;
 }
 
@@ -586,6 +638,21 @@ int octree_create(const oct_create_params *params, void *stream, oct_handle **ou
         hipEventCreateWithFlags(&h->ev_insert, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&h->ev_upload, hipEventDisableTiming) != hipSuccess)
         return bail(OCT_EDEVICE);
+    // render_views_noalloc: this device's scratch address, pinned host records for the largest
+    // call, and its events -- everything it needs, so that the call itself allocates nothing
+    if (scratch_for_device(h->device, &h->scratch_dev) != OCT_OK) {
+        h->err = "hipGetSymbolAddress(scratch) failed";
+        return bail(OCT_EDEVICE);
+    }
+    {
+        RenderSlot &na = h->rs[kRenderSlots];
+        na.st.cap = noalloc_record_bytes();
+        if (hipHostMalloc(&na.st.host, na.st.cap, hipHostMallocDefault) != hipSuccess)
+            return bail(OCT_ENOMEM);
+        if (hipEventCreateWithFlags(&na.st.ev, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&h->na_copy, hipEventDisableTiming) != hipSuccess)
+            return bail(OCT_EDEVICE);
+    }
     if (octree_clear(h, stream) != OCT_OK) return bail(OCT_EDEVICE);
     (void)s;
     *out = h;
@@ -612,6 +679,7 @@ int octree_destroy(oct_handle *h)
     if (h->ins_ev) (void)hipEventDestroy(h->ins_ev);
     if (h->ev_insert) (void)hipEventDestroy(h->ev_insert);
     if (h->ev_upload) (void)hipEventDestroy(h->ev_upload);
+    if (h->na_copy) (void)hipEventDestroy(h->na_copy);
     if (h->prep) (void)hipStreamDestroy(h->prep);
     stage_free(h->up);
     for (auto &r : h->rs) {
@@ -1418,6 +1486,84 @@ int render_views(oct_handle *h, int32_t n_views, const oct_view *views, float *c
         HIPCHK(h, hipMemcpyAsync(hp + c_off, dp + c_off, c_bytes, hipMemcpyDeviceToHost, s));
         HIPCHK(h, hipStreamSynchronize(s));
         const RenderCounters *rcnt = (const RenderCounters *)(hp + c_off);
+        *out = oct_render_stats{};
+        for (int i = 0; i < kCounterSlots; i++) {
+            out->rays += rcnt[i].rays;
+            out->positions_nominal += rcnt[i].nominal;
+            out->positions_composited += rcnt[i].composited;
+            out->positions_trilinear += rcnt[i].trilinear;
+        }
+    }
+    HIPCHK(h, hipEventRecord(rs.st.ev, s));
+    if (ckpt_ws) ckpt_log_put(h, ckpt_ws, n_views, views);
+    return OCT_OK;
+}
+
+int render_views_noalloc(oct_handle *h, int32_t n_views, const oct_view *views,
+                         float *const *images, void *ckpt_ws, void *stream, oct_render_stats *out)
+{
+    if (!h) return OCT_EINVAL;
+    if (n_views < 0 || (n_views > 0 && (!views || !images))) return fail(h, OCT_EINVAL, "bad view list");
+    if (n_views > kNoAllocMaxViews)
+        return fail(h, OCT_ERANGE, "render_views_noalloc takes at most 64 views per call");
+    if (!h->scratch_dev) return fail(h, OCT_EDEVICE, "no device scratch");
+    HIPCHK(h, hipSetDevice(h->device));
+    hipStream_t s = (hipStream_t)stream;
+    RenderSlot &rs = h->rs[kRenderSlots];
+    // the host records are reused: the previous call's copy of them must have finished
+    HIPCHK(h, hipEventSynchronize(h->na_copy));
+    uint8_t *hp = (uint8_t *)rs.st.host;
+    const RecordLayout cap = record_layout(kNoAllocMaxViews, kNoAllocMaxViews);
+    DevView *dvs = (DevView *)hp;
+    int32_t *split = (int32_t *)(hp + cap.sv_off);   // moved behind the records below
+    LaunchPlan pl;
+    int rc = plan_launch(h, n_views, views, images, ckpt_ws, false, dvs, split, nullptr, pl);
+    if (rc) return rc;
+    const RecordLayout l = record_layout((size_t)n_views, (size_t)pl.n_split);
+    // scratch: records | tables | masks | tile-group orders
+    const size_t tbytes = view_tables_bytes(h->g.C);
+    const int64_t mwords = view_mask_words(h->n_cells);
+    const size_t t_off = (l.c_off + l.c_bytes + 255) & ~(size_t)255;
+    const size_t m_off = (t_off + (size_t)n_views * tbytes + 255) & ~(size_t)255;
+    const size_t g_off = (m_off + (size_t)pl.n_skip * mwords * 4 + 255) & ~(size_t)255;
+    const size_t need = g_off + (size_t)pl.order_ints * 4;
+    if (need > kScratchBytes)
+        return fail(h, OCT_ERANGE,
+                    "render_views_noalloc: this launch needs " + std::to_string(need) +
+                        " bytes of device scratch, the limit is " + std::to_string(kScratchBytes) +
+                        " (fewer or smaller views per call, or render_views)");
+    uint8_t *dp = (uint8_t *)h->scratch_dev;
+    for (int i = 0, j = 0, at = 0; i < n_views; i++) {
+        dvs[i].tables = dp + t_off + (size_t)i * tbytes;
+        dvs[i].tmask = dvs[i].skip ? (uint32_t *)(dp + m_off) + (size_t)(j++) * mwords : nullptr;
+        dvs[i].group_order = (int32_t *)(dp + g_off) + at;   // written by the set-up kernel
+        at += 2 * dvs[i].groups;
+    }
+    if (pl.n_split) std::memmove(hp + l.sv_off, split, l.sv_bytes);
+    std::memset(hp + l.c_off, 0, l.c_bytes);
+    // the scratch is reused: this call's writes follow the previous call's launch; the node
+    // table and pool are the last upload's
+    rc = wait_for(h, s, rs.st.ev);
+    if (!rc) rc = wait_for(h, s, h->ev_upload);
+    if (rc) return rc;
+    // an upload that rewrites what renders of an older table read waits for this slot's event,
+    // which follows the previous launch too: keep the older version while that one may run
+    rs.version = hipEventQuery(rs.st.ev) == hipSuccess ? h->version : std::min(rs.version, h->version);
+    HIPCHK(h, hipMemcpyAsync(dp, hp, out ? l.c_off + l.c_bytes : l.sv_off + l.sv_bytes,
+                             hipMemcpyHostToDevice, s));
+    HIPCHK(h, hipEventRecord(h->na_copy, s));
+    HIPCHK(h, launch_view_prep(h->g, (const DevView *)dp, n_views, s));
+    if (pl.n_skip)
+        HIPCHK(h, launch_view_mask((const DevView *)dp, n_views, h->g.C, h->table, h->n_cells, s));
+    HIPCHK(h, launch_render(h->g, h->table, h->pool, h->brick_bytes, (const DevView *)dp, n_views,
+                            (int)pl.n_items, out ? (RenderCounters *)(dp + l.c_off) : nullptr,
+                            h->capped ? h->flags : nullptr, s));
+    HIPCHK(h, launch_combine((const DevView *)dp, (const int32_t *)(dp + l.sv_off), pl.n_split,
+                             pl.max_split_pixels, s));
+    if (out) {
+        HIPCHK(h, hipMemcpyAsync(hp + l.c_off, dp + l.c_off, l.c_bytes, hipMemcpyDeviceToHost, s));
+        HIPCHK(h, hipStreamSynchronize(s));
+        const RenderCounters *rcnt = (const RenderCounters *)(hp + l.c_off);
         *out = oct_render_stats{};
         for (int i = 0; i < kCounterSlots; i++) {
             out->rays += rcnt[i].rays;

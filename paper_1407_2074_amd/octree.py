@@ -20,7 +20,8 @@ OCT_U16, OCT_F32 = 0, 1
 MAXC = 4
 
 EXPORTS = ["octree_create", "octree_destroy", "octree_clear", "octree_insert_block",
-           "octree_insert_slices", "brick_pool_upload", "render_views", "render_ckpt_bytes",
+           "octree_insert_slices", "brick_pool_upload", "render_views", "render_views_noalloc",
+           "render_ckpt_bytes",
            "render_views_backward", "octree_dump_canonical", "octree_read_level", "octree_info",
            "octree_render_timing", "oct_last_error"]
 
@@ -72,6 +73,7 @@ def _load():
     L.brick_pool_upload.argtypes = [vp, u64, vp, ct.POINTER(UploadStats)]
     L.render_views.argtypes = [vp, i32, ct.POINTER(OctView), ct.POINTER(vp), vp, vp,
                                ct.POINTER(RenderStats)]
+    L.render_views_noalloc.argtypes = L.render_views.argtypes
     L.render_ckpt_bytes.restype = sz
     L.render_ckpt_bytes.argtypes = [vp, i32, ct.POINTER(OctView)]
     L.render_views_backward.argtypes = [vp, i32, ct.POINTER(OctView), ct.POINTER(vp), vp, vp, vp,
@@ -248,8 +250,10 @@ class Octree:
             raise ValueError(f"{what} holds {t.numel() * t.element_size()} bytes, "
                              f"needs {min_bytes}")
 
-    def render(self, views, images=None, stats: bool = False, stream=None, ckpt=None):
-        """Render views into torch CUDA images [H][W][4] float32 (allocated when not given)."""
+    def render(self, views, images=None, stats: bool = False, stream=None, ckpt=None,
+               noalloc: bool = False):
+        """Render views into torch CUDA images [H][W][4] float32 (allocated when not given).
+        noalloc=True calls render_views_noalloc (no allocation inside the library)."""
         import torch
         if images is None:
             images = [torch.zeros((v.height, v.width, 4), dtype=torch.float32, device="cuda")
@@ -264,7 +268,8 @@ class Octree:
             self._check_buffer(ckpt, "ckpt", None, min_bytes=self.ckpt_bytes(views))
         ptrs = (ct.c_void_p * len(views))(*[im.data_ptr() for im in images])
         rs = RenderStats()
-        self._check(lib.render_views(self.h, len(views), ov, ptrs,
+        fn = lib.render_views_noalloc if noalloc else lib.render_views
+        self._check(fn(self.h, len(views), ov, ptrs,
                        ct.c_void_p(ckpt.data_ptr()) if ckpt is not None else None,
                        _stream(stream), ct.byref(rs) if stats else None))
         if stats:
