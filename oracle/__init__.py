@@ -47,7 +47,9 @@ class OrcView(ct.Structure):
                 ("step", ct.c_float), ("ert_alpha", ct.c_float), ("lod", ct.c_int32),
                 ("n_clip", ct.c_int32), ("clip", (ct.c_float * 4) * 3),
                 ("tf_pos", (ct.c_float * 8) * MAXC), ("tf_rgba", ((ct.c_float * 4) * 8) * MAXC),
-                ("window", (ct.c_float * 2) * MAXC)]
+                ("window", (ct.c_float * 2) * MAXC), ("mode", ct.c_int32),
+                ("fullframe", ct.c_int32), ("n_xform", ct.c_int32),
+                ("xform", ((ct.c_float * 4) * 3) * MAXC)]
 
 
 _lib = None
@@ -73,6 +75,10 @@ def lib():
         L.orc_render_grad.argtypes = [ct.c_void_p, ct.c_int, ct.POINTER(OrcView), ct.c_void_p,
                                       ct.c_void_p, ct.c_void_p]
         L.orc_rays.argtypes = [ct.c_void_p, ct.POINTER(OrcView), ct.c_void_p, ct.c_void_p]
+        L.orc_render_aux.argtypes = [ct.c_void_p, ct.POINTER(OrcView), ct.c_void_p, ct.c_void_p,
+                                     ct.c_void_p, ct.c_void_p]
+        L.orc_render_pixels.argtypes = [ct.c_void_p, ct.POINTER(OrcView), ct.c_void_p,
+                                        ct.c_int64, ct.c_void_p]
         L.orc_render_rows.argtypes = [ct.c_void_p, ct.POINTER(OrcView), ct.c_void_p,
                                       ct.c_void_p, ct.c_int, ct.c_int]
         L.orc_render_window.argtypes = [ct.c_void_p, ct.POINTER(OrcView), ct.c_void_p, ct.c_int,
@@ -107,6 +113,17 @@ def to_orc_view(v) -> OrcView:
             for q in range(4):
                 o.tf_rgba[c][j][q] = float(v.tf_rgba[c][j][q])
         o.window[c][0], o.window[c][1] = float(v.window[c][0]), float(v.window[c][1])
+    o.mode = int(getattr(v, "mode", 0))
+    o.fullframe = 1 if int(getattr(v, "missing", 0)) == 1 else 0
+    xf = getattr(v, "xform", None)
+    if xf is not None:
+        xf = np.asarray(xf, np.float32)
+        assert xf.shape == (C, 3, 4)
+        o.n_xform = C
+        for c in range(C):
+            for a in range(3):
+                for k in range(4):
+                    o.xform[c][a][k] = float(xf[c, a, k])
     return o
 
 
@@ -192,6 +209,28 @@ class Tree:
             raise ValueError("oracle render rejected the views")
         return (imgs, ns, mg) if want_info else imgs
 
+    def render_aux(self, view):
+        """One view: image, nominal counts, margins (ERT / MIP arg-max ambiguity) and the
+        number of channel samples that approximated a non-resident brick by its AVG."""
+        ov = to_orc_view(view)
+        img = np.zeros((view.height, view.width, 4), np.float64)
+        ns = np.zeros((view.height, view.width), np.int32)
+        mg = np.zeros((view.height, view.width), np.float64)
+        na = np.zeros((view.height, view.width), np.int32)
+        if lib().orc_render_aux(self.h, ct.byref(ov), _ptr(img), _ptr(ns), _ptr(mg),
+                                _ptr(na)) != 0:
+            raise ValueError("oracle render rejected the view")
+        return img, ns, mg, na
+
+    def render_pixels(self, view, px):
+        """RGBA of the listed pixels (px: [n][2] column, row) of one view."""
+        ov = to_orc_view(view)
+        px = np.ascontiguousarray(px, np.int32)
+        out = np.zeros((len(px), 4), np.float64)
+        if lib().orc_render_pixels(self.h, ct.byref(ov), _ptr(px), len(px), _ptr(out)) != 0:
+            raise ValueError("oracle render rejected the pixels")
+        return out
+
     def render_grad(self, views, dL_dI, want_voxels: bool = True):
         """Gradient of a loss with image adjoints dL_dI w.r.t. control RGBA and level-0 voxels."""
         ov = (OrcView * len(views))(*[to_orc_view(v) for v in views])
@@ -200,8 +239,9 @@ class Tree:
         Dx, Dy, Dz = self.dims
         dvox = np.zeros((self.C, Dz, Dy, Dx), np.float64) if want_voxels else None
         P = ct.c_void_p * len(views)
-        lib().orc_render_grad(self.h, len(views), ov, P(*[g.ctypes.data for g in gI]),
-                              _ptr(dctrl), _ptr(dvox) if dvox is not None else None)
+        if lib().orc_render_grad(self.h, len(views), ov, P(*[g.ctypes.data for g in gI]),
+                                 _ptr(dctrl), _ptr(dvox) if dvox is not None else None) != 0:
+            raise ValueError("oracle gradient rejected the views")
         return dctrl, dvox
 
     def render_rows(self, view, row_begin: int, row_step: int):

@@ -34,6 +34,20 @@
  *     trilinear (brick) or AVG; per channel, in channel order, the sample is classified by a
  *     256-entry piecewise-linear RGBA table and composited ("accumulation level intermixing"),
  *     then early termination is tested once per position.
+ *   - Maximum intensity projection ("Basic Ray-Casting": the traversal serves other compositing
+ *     modes; Fig. 6, Table 1): per channel the largest sample along the ray is classified once,
+ *     and the C classified values are composited in channel order like one DVR position.
+ *     Early termination does not apply.
+ *   - Missing bricks ("Basic Ray-Casting", "Full-Frame Ray-Casting"): a brick node whose brick
+ *     is not resident is sampled with its AVG; under the full-frame fallback the resident brick
+ *     of the first of the two coarser levels on the sample's path is interpolated instead, and
+ *     only when neither is resident the AVG.
+ *   - Chromatic-aberration correction ("Correction of Chromatic Aberration"): optionally each
+ *     channel samples the volume at its own affine image of the ray position.
+ *
+ * Storage: level values are kept in the volume's data type (uint16 or float32), which holds
+ * every value of the mipmap exactly (integer means for uint16, float32-rounded means for
+ * float32), and R_L is evaluated at each lookup from the node states; nothing is stored twice.
  *
  * Precision: values, classification and compositing are FP64.  The geometric decisions (ray
  * direction, entry/exit parameter, clip planes, LOD, sample positions and the voxel/node a
@@ -74,6 +88,10 @@ typedef struct {
     float tf_pos[ORC_MAXC][8];
     float tf_rgba[ORC_MAXC][8][4];
     float window[ORC_MAXC][2];
+    int32_t mode;          /* 0: emission-absorption (DVR), 1: maximum intensity projection */
+    int32_t fullframe;     /* 1: missing bricks fall back to the two coarser levels */
+    int32_t n_xform;       /* 0, or C: channel c samples at xform[c] applied to the position */
+    float xform[ORC_MAXC][3][4];   /* rows (m_a0, m_a1, m_a2, b_a) of p' = M p + b */
 } orc_view;
 
 enum { ST_NONE = -1, ST_EMPTY = 0, ST_HOMOG_LEAF = 1, ST_HOMOG = 2, ST_BRICK = 3 };
@@ -91,8 +109,7 @@ typedef struct {
     int N;
     int ext[ORC_MAXL][3];
     int G[ORC_MAXL];
-    double *V[ORC_MAXL];   /* level values, planar [C][ez][ey][ex] (exact in the data type) */
-    double *R[ORC_MAXL];   /* represented field, same layout */
+    void *V[ORC_MAXL];     /* level values, planar [C][ez][ey][ex], in the data type */
     orc_node *nodes[ORC_MAXL];
     int poked;             /* a level-0 value was replaced in place (orc_poke_level0) */
 } orc_tree;
@@ -104,9 +121,28 @@ static int64_t lvl_voxels(const orc_tree *t, int L)
     return (int64_t)t->ext[L][0] * t->ext[L][1] * t->ext[L][2];
 }
 
-static double *lvl_at(double *a, const orc_tree *t, int L, int c, int z, int y, int x)
+static int64_t lvl_index(const orc_tree *t, int L, int c, int z, int y, int x)
 {
-    return a + (((int64_t)c * t->ext[L][2] + z) * t->ext[L][1] + y) * t->ext[L][0] + x;
+    return (((int64_t)c * t->ext[L][2] + z) * t->ext[L][1] + y) * t->ext[L][0] + x;
+}
+
+/* Level-L value at planar index i (channel included), exact in FP64. */
+static double vget(const orc_tree *t, int L, int64_t i)
+{
+    return t->p.dtype == 0 ? (double)((const uint16_t *)t->V[L])[i]
+                           : (double)((const float *)t->V[L])[i];
+}
+
+/* Stores a value that the data type holds exactly (a mean of the mipmap or a replacement). */
+static void vset(orc_tree *t, int L, int64_t i, double v)
+{
+    if (t->p.dtype == 0) ((uint16_t *)t->V[L])[i] = (uint16_t)v;
+    else ((float *)t->V[L])[i] = (float)v;
+}
+
+static double lvl_get(const orc_tree *t, int L, int c, int z, int y, int x)
+{
+    return vget(t, L, lvl_index(t, L, c, z, y, x));
 }
 
 static orc_node *node_at(const orc_tree *t, int L, int bx, int by, int bz)
@@ -135,6 +171,7 @@ static int imax(int a, int b) { return a > b ? a : b; }
 /* ------------------------------------------------------------------ build */
 
 void orc_free(orc_tree *t);
+int orc_num_threads(void);
 
 /* Eq. 1: the octree has N+1 levels with N the smallest n for which M * 2^n covers the
  * largest dimension (the volume is extended virtually to M * 2^N per axis). */
@@ -146,28 +183,111 @@ int orc_tree_depth(const int32_t dims[3], int M)
     return N;
 }
 
+/* Subtree minimum / maximum over the level-0 region [l0, h0) of channel c and whether any /
+ * every voxel of it was inserted in that channel.  Minimum, maximum, "any" and "all" do not
+ * depend on the order of evaluation, so large regions (few nodes per level) are split over
+ * threads; small ones run in the caller's thread. */
+static void region_stats(const orc_tree *t, const uint8_t *mask, int c, const int64_t l0[3],
+                         const int64_t h0[3], int split, double *mn_out, double *mx_out,
+                         int *any_out, int *all_out)
+{
+    const orc_params *p = &t->p;
+    double mn = INFINITY, mx = -INFINITY;
+    int any = 0, all = 1;
+#pragma omp parallel for if (split) schedule(static) reduction(min : mn) reduction(max : mx) \
+    reduction(| : any) reduction(& : all)
+    for (int64_t z = l0[2]; z < h0[2]; z++)
+        for (int64_t y = l0[1]; y < h0[1]; y++)
+            for (int64_t x = l0[0]; x < h0[0]; x++) {
+                double v = lvl_get(t, 0, c, (int)z, (int)y, (int)x);
+                mn = fmin(mn, v);
+                mx = fmax(mx, v);
+                int ins = (mask[(z * p->dims[1] + y) * p->dims[0] + x] >> c) & 1;
+                any |= ins;
+                all &= ins;
+            }
+    *mn_out = mn;
+    *mx_out = mx;
+    *any_out = any;
+    *all_out = all;
+}
+
+/* Statistics of node (L, b) straight from the definitions. */
+static void node_stats(orc_tree *t, const uint8_t *mask, int L, const int b[3], int split)
+{
+    const orc_params *p = &t->p;
+    const int C = p->channels, M = p->brick;
+    orc_node *nd = node_at(t, L, b[0], b[1], b[2]);
+    /* own brick at level L */
+    int lo[3], hi[3];
+    for (int a = 0; a < 3; a++) {
+        lo[a] = b[a] * M;
+        hi[a] = imin((b[a] + 1) * M, t->ext[L][a]);
+    }
+    int64_t cnt = 0;
+    for (int c = 0; c < C; c++) {
+        double mn = INFINITY, mx = -INFINITY, sm = 0.0;
+        cnt = 0;
+        for (int z = lo[2]; z < hi[2]; z++)
+            for (int y = lo[1]; y < hi[1]; y++)
+                for (int x = lo[0]; x < hi[0]; x++) {
+                    double v = lvl_get(t, L, c, z, y, x);
+                    mn = fmin(mn, v);
+                    mx = fmax(mx, v);
+                    sm += v;
+                    cnt++;
+                }
+        nd->bmin[c] = cnt ? mn : 0.0;
+        nd->bmax[c] = cnt ? mx : 0.0;
+        nd->bsum[c] = sm;
+    }
+    nd->count = cnt;
+    /* level-0 region: subtree min/max and insertion coverage */
+    int64_t span = (int64_t)M << L;
+    int64_t l0[3], h0[3], nvox = 1;
+    for (int a = 0; a < 3; a++) {
+        l0[a] = b[a] * span;
+        h0[a] = b[a] * span + span;
+        if (h0[a] > p->dims[a]) h0[a] = p->dims[a];
+        nvox *= h0[a] > l0[a] ? h0[a] - l0[a] : 0;
+    }
+    int any = 0, all = 1;
+    for (int c = 0; c < C; c++) {
+        double mn, mx;
+        int a1, a2;
+        region_stats(t, mask, c, l0, h0, split && nvox > 0, &mn, &mx, &a1, &a2);
+        any |= a1;
+        all &= a2;
+        nd->smin[c] = nvox ? mn : 0.0;
+        nd->smax[c] = nvox ? mx : 0.0;
+    }
+    nd->populated = (int8_t)(nvox > 0 && any);
+    nd->complete = (int8_t)(nvox > 0 && all);
+}
+
 orc_tree *orc_build(const orc_params *p, const void *v0, const uint8_t *mask)
 {
     if (p->channels < 1 || p->channels > ORC_MAXC || p->brick < 2 || (p->brick & 1)) return NULL;
     orc_tree *t = (orc_tree *)calloc(1, sizeof(orc_tree));
     t->p = *p;
-    const int C = p->channels, M = p->brick;
-    const int N = orc_tree_depth(p->dims, M);
+    const int C = p->channels;
+    const int N = orc_tree_depth(p->dims, p->brick);
+    const size_t esz = p->dtype == 0 ? 2 : 4;
     t->N = N;
     for (int L = 0; L <= N; L++) {
         for (int a = 0; a < 3; a++)
             t->ext[L][a] = (int)(((int64_t)p->dims[a] + ((int64_t)1 << L) - 1) >> L);
         t->G[L] = 1 << (N - L);
-        t->V[L] = (double *)malloc(sizeof(double) * C * lvl_voxels(t, L));
-        t->R[L] = (double *)malloc(sizeof(double) * C * lvl_voxels(t, L));
+        t->V[L] = malloc(esz * C * lvl_voxels(t, L));
         t->nodes[L] = (orc_node *)calloc((size_t)t->G[L] * t->G[L] * t->G[L], sizeof(orc_node));
+        if (!t->V[L] || !t->nodes[L]) {
+            orc_free(t);
+            return NULL;
+        }
     }
 
     /* Level 0: the inserted data (background where nothing was inserted is already in v0). */
-    int64_t n0 = lvl_voxels(t, 0);
-    for (int64_t i = 0; i < C * n0; i++)
-        t->V[0][i] = p->dtype == 0 ? (double)((const uint16_t *)v0)[i]
-                                   : (double)((const float *)v0)[i];
+    memcpy(t->V[0], v0, esz * C * lvl_voxels(t, 0));
 
     /* Levels 1..N: half-sampling of the valid children. */
     for (int L = 0; L < N; L++) {
@@ -184,75 +304,31 @@ orc_tree *orc_build(const orc_params *p, const void *v0, const uint8_t *mask)
                                 for (int dx = 0; dx < 2; dx++) {
                                     int cz = 2 * z + dz, cy = 2 * y + dy, cx = 2 * x + dx;
                                     if (cz >= e[2] || cy >= e[1] || cx >= e[0]) continue;
-                                    s += *lvl_at(t->V[L], t, L, c, cz, cy, cx);
+                                    s += lvl_get(t, L, c, cz, cy, cx);
                                     n++;
                                 }
-                        *lvl_at(t->V[L + 1], t, L + 1, c, z, y, x) = type_mean(t, s, n);
+                        vset(t, L + 1, lvl_index(t, L + 1, c, z, y, x), type_mean(t, s, n));
                     }
     }
 
-    /* Per-node statistics straight from the definitions (nodes are independent). */
+    /* Per-node statistics (nodes are independent; levels with fewer nodes than threads split
+     * each node's level-0 region instead). */
+    const int nthr = orc_num_threads();
     for (int L = 0; L <= N; L++) {
-        int g = t->G[L];
-#pragma omp parallel for collapse(3) schedule(dynamic, 1)
-        for (int bz = 0; bz < g; bz++)
-            for (int by = 0; by < g; by++)
-                for (int bx = 0; bx < g; bx++) {
-                    orc_node *nd = node_at(t, L, bx, by, bz);
-                    int b[3] = {bx, by, bz};
-                    /* own brick at level L */
-                    int lo[3], hi[3];
-                    for (int a = 0; a < 3; a++) {
-                        lo[a] = b[a] * M;
-                        hi[a] = imin((b[a] + 1) * M, t->ext[L][a]);
-                    }
-                    int64_t cnt = 0;
-                    for (int c = 0; c < C; c++) {
-                        double mn = INFINITY, mx = -INFINITY, sm = 0.0;
-                        cnt = 0;
-                        for (int z = lo[2]; z < hi[2]; z++)
-                            for (int y = lo[1]; y < hi[1]; y++)
-                                for (int x = lo[0]; x < hi[0]; x++) {
-                                    double v = *lvl_at(t->V[L], t, L, c, z, y, x);
-                                    mn = fmin(mn, v);
-                                    mx = fmax(mx, v);
-                                    sm += v;
-                                    cnt++;
-                                }
-                        nd->bmin[c] = cnt ? mn : 0.0;
-                        nd->bmax[c] = cnt ? mx : 0.0;
-                        nd->bsum[c] = sm;
-                    }
-                    nd->count = cnt;
-                    /* level-0 region: subtree min/max and insertion coverage */
-                    int64_t span = (int64_t)M << L;
-                    int64_t l0[3], h0[3];
-                    for (int a = 0; a < 3; a++) {
-                        l0[a] = b[a] * span;
-                        h0[a] = b[a] * span + span;
-                        if (h0[a] > p->dims[a]) h0[a] = p->dims[a];
-                    }
-                    int any = 0, all = 1;
-                    int64_t nvox = 0;
-                    for (int c = 0; c < C; c++) {
-                        double mn = INFINITY, mx = -INFINITY;
-                        for (int64_t z = l0[2]; z < h0[2]; z++)
-                            for (int64_t y = l0[1]; y < h0[1]; y++)
-                                for (int64_t x = l0[0]; x < h0[0]; x++) {
-                                    double v = *lvl_at(t->V[0], t, 0, c, (int)z, (int)y, (int)x);
-                                    mn = fmin(mn, v);
-                                    mx = fmax(mx, v);
-                                    int ins = (mask[(z * p->dims[1] + y) * p->dims[0] + x] >> c) & 1;
-                                    any |= ins;
-                                    all &= ins;
-                                    nvox++;
-                                }
-                        nd->smin[c] = nvox ? mn : 0.0;
-                        nd->smax[c] = nvox ? mx : 0.0;
-                    }
-                    nd->populated = (int8_t)(nvox > 0 && any);
-                    nd->complete = (int8_t)(nvox > 0 && all);
-                }
+        const int g = t->G[L];
+        const int64_t g3 = (int64_t)g * g * g;
+        if (g3 >= 4 * nthr) {
+#pragma omp parallel for schedule(dynamic, 1)
+            for (int64_t i = 0; i < g3; i++) {
+                int b[3] = {(int)(i % g), (int)((i / g) % g), (int)(i / ((int64_t)g * g))};
+                node_stats(t, mask, L, b, 0);
+            }
+        } else {
+            for (int64_t i = 0; i < g3; i++) {
+                int b[3] = {(int)(i % g), (int)((i / g) % g), (int)(i / ((int64_t)g * g))};
+                node_stats(t, mask, L, b, 1);
+            }
+        }
     }
 
     /* States, top-down from the root (the root always exists). */
@@ -287,29 +363,23 @@ orc_tree *orc_build(const orc_params *p, const void *v0, const uint8_t *mask)
                     }
                 }
     }
-
-    /* Represented field R_L (voxels are independent). */
-    for (int L = 0; L <= N; L++) {
-        const int *e = t->ext[L];
-#pragma omp parallel for schedule(static)
-        for (int z = 0; z < e[2]; z++)
-            for (int y = 0; y < e[1]; y++)
-                for (int x = 0; x < e[0]; x++) {
-                    int bx = x / M, by = y / M, bz = z / M;
-                    orc_node *nd = node_at(t, L, bx, by, bz);
-                    int l = L;
-                    while (!nd->exists) {
-                        l++;
-                        bx >>= 1; by >>= 1; bz >>= 1;
-                        nd = node_at(t, l, bx, by, bz);
-                    }
-                    for (int c = 0; c < C; c++)
-                        *lvl_at(t->R[L], t, L, c, z, y, x) =
-                            (l == L && nd->state == ST_BRICK) ? *lvl_at(t->V[L], t, L, c, z, y, x)
-                                                              : nd->avg[c];
-                }
-    }
     return t;
+}
+
+/* Represented field R_L at voxel (x, y, z) of level L: V_L where the level-L node holding the
+ * voxel is a brick, else the AVG of the deepest existing node at level >= L containing it.
+ * Returns that node when the value is its AVG, NULL when it is V_L. */
+static const orc_node *r_source(const orc_tree *t, int L, int x, int y, int z)
+{
+    const int M = t->p.brick;
+    int bx = x / M, by = y / M, bz = z / M, l = L;
+    const orc_node *nd = node_at(t, L, bx, by, bz);
+    while (!nd->exists) {
+        l++;
+        bx >>= 1; by >>= 1; bz >>= 1;
+        nd = node_at(t, l, bx, by, bz);
+    }
+    return (l == L && nd->state == ST_BRICK) ? NULL : nd;
 }
 
 void orc_free(orc_tree *t)
@@ -317,7 +387,6 @@ void orc_free(orc_tree *t)
     if (!t) return;
     for (int L = 0; L <= t->N; L++) {
         free(t->V[L]);
-        free(t->R[L]);
         free(t->nodes[L]);
     }
     free(t);
@@ -334,11 +403,7 @@ void orc_level_extent(const orc_tree *t, int L, int32_t *ext3)
 int orc_read_level(const orc_tree *t, int L, void *out)
 {
     if (L < 0 || L > t->N || (t->poked && L > 0)) return -1;
-    int64_t n = t->p.channels * lvl_voxels(t, L);
-    for (int64_t i = 0; i < n; i++) {
-        if (t->p.dtype == 0) ((uint16_t *)out)[i] = (uint16_t)t->V[L][i];
-        else ((float *)out)[i] = (float)t->V[L][i];
-    }
+    memcpy(out, t->V[L], (t->p.dtype == 0 ? 2 : 4) * t->p.channels * lvl_voxels(t, L));
     return 0;
 }
 
@@ -412,8 +477,9 @@ size_t orc_dump(const orc_tree *t, void *buf, size_t cap)
                                 int gz = imin(imax(bz * M - 1 + z, 0), e[2] - 1);
                                 int gy = imin(imax(by * M - 1 + y, 0), e[1] - 1);
                                 int gx = imin(imax(bx * M - 1 + x, 0), e[0] - 1);
+                                const orc_node *src = r_source(t, L, gx, gy, gz);
                                 for (int c = 0; c < C; c++) {
-                                    double v = *lvl_at(t->R[L], t, L, c, gz, gy, gx);
+                                    double v = src ? src->avg[c] : lvl_get(t, L, c, gz, gy, gx);
                                     if (esz == 2) {
                                         uint16_t u = (uint16_t)v;
                                         memcpy(bricks, &u, 2);
@@ -593,34 +659,24 @@ static void ray_setup(const orc_tree *t, const orc_view *v, const orc_cam *cm, i
 
 /* ------------------------------------------------------------------ sampling */
 
-/* Sample of channel c at float32 position p on level L (R_L semantics above). */
+/* What channel samples at a float32 position read: trilinear interpolation in R at level Ls
+ * (the ray's LOD, or a coarser level under the full-frame fallback), or one node's AVG. */
 typedef struct {
-    int brick;                 /* 1: trilinear, 0: constant (AVG) */
-    int64_t idx[8];            /* corner voxel linear indices within one channel of R_L */
+    int trilinear;             /* 1: trilinear in R_Ls, 0: constant */
+    int Ls;                    /* level of the interpolated field */
+    int64_t idx[8];            /* corner voxel indices within one channel of level Ls */
     double w[8];               /* trilinear weights */
-    int64_t cidx;              /* constant case: voxel index */
-    const double *avg;         /* constant case of a non-resident brick node: its AVG */
+    const orc_node *src[8];    /* corner value: NULL = V_Ls at idx, else that node's AVG */
+    const orc_node *cnode;     /* constant case: the node whose AVG is the value */
+    int avg_fallback;          /* a non-resident brick node approximated by its AVG */
 } orc_sample_geo;
 
-static void sample_geo(const orc_tree *t, int L, const float p[3], orc_sample_geo *g)
+/* Trilinear set-up in R at level Ls: q = p 2^-Ls - 1/2 (exact), corner i0 = floor(q), weight
+ * f = q - i0 (float32), corner indices clamped to the valid extent. */
+static void trilinear_geo(const orc_tree *t, int Ls, const float p[3], orc_sample_geo *g)
 {
-    const int M = t->p.brick;
-    const int *e = t->ext[L];
-    int v[3], b[3];
-    for (int a = 0; a < 3; a++) {
-        int vi = (int)floorf(p[a]);
-        vi = imax(0, imin(vi, t->p.dims[a] - 1));
-        v[a] = vi;
-        b[a] = (vi >> L) / M;
-    }
-    const orc_node *nd = node_at(t, L, b[0], b[1], b[2]);
-    g->brick = nd->exists && nd->state == ST_BRICK && !nd->nonresident;
-    g->avg = (nd->exists && nd->state == ST_BRICK && nd->nonresident) ? nd->avg : NULL;
-    if (!g->brick) {
-        g->cidx = ((int64_t)(v[2] >> L) * e[1] + (v[1] >> L)) * e[0] + (v[0] >> L);
-        return;
-    }
-    float scale = ldexpf(1.0f, -L);
+    const int *e = t->ext[Ls];
+    float scale = ldexpf(1.0f, -Ls);
     int i0[3];
     double f[3];
     for (int a = 0; a < 3; a++) {
@@ -629,6 +685,8 @@ static void sample_geo(const orc_tree *t, int L, const float p[3], orc_sample_ge
         i0[a] = (int)fl;
         f[a] = (double)(q - fl);
     }
+    g->trilinear = 1;
+    g->Ls = Ls;
     int k = 0;
     for (int dz = 0; dz < 2; dz++)
         for (int dy = 0; dy < 2; dy++)
@@ -637,17 +695,106 @@ static void sample_geo(const orc_tree *t, int L, const float p[3], orc_sample_ge
                 int y = imax(0, imin(i0[1] + dy, e[1] - 1));
                 int z = imax(0, imin(i0[2] + dz, e[2] - 1));
                 g->idx[k] = ((int64_t)z * e[1] + y) * e[0] + x;
+                g->src[k] = r_source(t, Ls, x, y, z);
                 g->w[k] = (dx ? f[0] : 1.0 - f[0]) * (dy ? f[1] : 1.0 - f[1]) * (dz ? f[2] : 1.0 - f[2]);
             }
 }
 
-static double sample_value(const orc_tree *t, int L, int c, const orc_sample_geo *g)
+/* The node at the ray's LOD L holding the position's clamped voxel decides: a resident brick
+ * is interpolated; a brick that is not resident is approximated by its AVG ("Basic
+ * Ray-Casting"), or, under the full-frame fallback, by the resident brick of level L+1, else
+ * of level L+2, on the position's path ("Full-Frame Ray-Casting"); any other node (and any
+ * cell whose node does not exist) contributes the AVG of the deepest existing node. */
+static void sample_geo(const orc_tree *t, int L, const float p[3], int fullframe,
+                       orc_sample_geo *g)
 {
-    const double *R = t->R[L] + (int64_t)c * lvl_voxels(t, L);
-    if (!g->brick) return g->avg ? g->avg[c] : R[g->cidx];
+    const int M = t->p.brick;
+    int v[3], b[3];
+    for (int a = 0; a < 3; a++) {
+        int vi = (int)floorf(p[a]);
+        vi = imax(0, imin(vi, t->p.dims[a] - 1));
+        v[a] = vi;
+        b[a] = (vi >> L) / M;
+    }
+    g->avg_fallback = 0;
+    const orc_node *nd = node_at(t, L, b[0], b[1], b[2]);
+    if (nd->exists && nd->state == ST_BRICK) {
+        if (!nd->nonresident) {
+            trilinear_geo(t, L, p, g);
+            return;
+        }
+        if (fullframe)
+            for (int l = L + 1; l <= L + 2 && l <= t->N; l++) {
+                const orc_node *up = node_at(t, l, (v[0] >> l) / M, (v[1] >> l) / M, (v[2] >> l) / M);
+                if (up->state == ST_BRICK && !up->nonresident) {
+                    trilinear_geo(t, l, p, g);
+                    return;
+                }
+            }
+        g->trilinear = 0;
+        g->cnode = nd;
+        g->avg_fallback = 1;
+        return;
+    }
+    int l = L;
+    while (!nd->exists) {
+        l++;
+        b[0] >>= 1; b[1] >>= 1; b[2] >>= 1;
+        nd = node_at(t, l, b[0], b[1], b[2]);
+    }
+    g->trilinear = 0;
+    g->cnode = nd;
+}
+
+static double sample_value(const orc_tree *t, int c, const orc_sample_geo *g)
+{
+    if (!g->trilinear) return g->cnode->avg[c];
+    const int64_t off = (int64_t)c * lvl_voxels(t, g->Ls);
     double s = 0.0;
-    for (int k = 0; k < 8; k++) s += g->w[k] * R[g->idx[k]];
+    for (int k = 0; k < 8; k++)
+        s += g->w[k] * (g->src[k] ? g->src[k]->avg[c] : vget(t, g->Ls, off + g->idx[k]));
     return s;
+}
+
+/* Position at which channel c is sampled ("Correction of Chromatic Aberration"): the ray
+ * position itself, or its image under the channel's affine map, each row as float32
+ * ((m0 p0 + m1 p1) + m2 p2) + b, every operation rounded once, no fused multiply-add. */
+static void channel_position(const orc_view *v, int c, const float p[3], float pc[3])
+{
+    if (v->n_xform == 0) {
+        for (int a = 0; a < 3; a++) pc[a] = p[a];
+        return;
+    }
+    for (int a = 0; a < 3; a++) {
+        const float *m = v->xform[c][a];
+        float s0 = m[0] * p[0];
+        float s1 = m[1] * p[1];
+        float s2 = m[2] * p[2];
+        float u = s0 + s1;
+        float w = u + s2;
+        pc[a] = w + m[3];
+    }
+}
+
+/* The per-channel sample geometry of one ray position (shared by all channels when the view
+ * has no channel transforms).  Returns the number of AVG fallbacks among the C samples. */
+static int position_geo(const orc_tree *t, const orc_view *v, int L, const float p[3],
+                        orc_sample_geo *g /* [C] */)
+{
+    const int C = t->p.channels;
+    int nfb = 0;
+    if (v->n_xform == 0) {
+        sample_geo(t, L, p, v->fullframe, &g[0]);
+        for (int c = 1; c < C; c++) g[c] = g[0];
+        return g[0].avg_fallback ? C : 0;
+    }
+    for (int c = 0; c < C; c++) {
+        float pc[3];
+        channel_position(v, c, p, pc);
+        sample_geo(t, L, pc, v->fullframe, &g[c]);
+        nfb += g[c].avg_fallback;
+    }
+    return nfb;
 }
 
 /* Classification: returns rgba; *slot_i / *slot_f give the table cell, *dudx the slope
@@ -673,18 +820,39 @@ static void classify(const orc_luts *lu, const orc_view *v, int c, double s, dou
 
 /* ------------------------------------------------------------------ render
  * images: [n_views] pointers to [H][W][4] double (premultiplied RGBA, row 0 at the top).
- * nsamp (optional): per view [H][W] int32 count of positions t_k < t1 (nominal samples).
- * ert_margin (optional): per view [H][W] double, the smallest |A - ert| over the early
- * termination tests evaluated on the ray (+inf when ERT is off), for ambiguity detection.
+ * Optional per-view [H][W] outputs:
+ *   nsamp   int32: positions t_k < t1 (nominal samples);
+ *   margin  double: DVR with early termination: the smallest |A - ert| over the termination
+ *           tests of the ray; MIP: the smallest gap, over the channels, between the largest
+ *           sample and the largest sample at any other position (0 = a tie); +inf otherwise.
+ *           Both detect rays whose discrete outcome floating point could decide differently;
+ *   navg    int32: channel samples that approximated a non-resident brick by its AVG.
  */
 static int render_rows(const orc_tree *t, int n_views, const orc_view *views,
-                       double *const *images, int32_t *const *nsamp, double *const *ert_margin,
-                       int row_begin, int row_end, int row_step, int col_begin, int col_end);
+                       double *const *images, int32_t *const *nsamp, double *const *margin,
+                       int32_t *const *navg, int row_begin, int row_end, int row_step,
+                       int col_begin, int col_end);
+
+static int view_ok(const orc_tree *t, const orc_view *v)
+{
+    if (v->width <= 0 || v->height <= 0) return 0;
+    if (v->mode != 0 && v->mode != 1) return 0;
+    if (v->n_xform != 0 && v->n_xform != t->p.channels) return 0;
+    if (t->poked && v->lod != 0) return 0;
+    return 1;
+}
 
 int orc_render(const orc_tree *t, int n_views, const orc_view *views, double *const *images,
-               int32_t *const *nsamp, double *const *ert_margin)
+               int32_t *const *nsamp, double *const *margin)
 {
-    return render_rows(t, n_views, views, images, nsamp, ert_margin, 0, 1 << 30, 1, 0, 1 << 30);
+    return render_rows(t, n_views, views, images, nsamp, margin, NULL, 0, 1 << 30, 1, 0, 1 << 30);
+}
+
+/* One view with every optional output (any of them may be NULL). */
+int orc_render_aux(const orc_tree *t, const orc_view *view, double *image, int32_t *nsamp,
+                   double *margin, int32_t *navg)
+{
+    return render_rows(t, 1, view, &image, &nsamp, &margin, &navg, 0, 1 << 30, 1, 0, 1 << 30);
 }
 
 /* Same as orc_render for the rows row_begin, row_begin + row_step, ... only (other rows are
@@ -693,7 +861,8 @@ int orc_render_rows(const orc_tree *t, const orc_view *view, double *image, int3
                     int row_begin, int row_step)
 {
     if (row_begin < 0 || row_step < 1) return -1;
-    return render_rows(t, 1, view, &image, &nsamp, NULL, row_begin, 1 << 30, row_step, 0, 1 << 30);
+    return render_rows(t, 1, view, &image, &nsamp, NULL, NULL, row_begin, 1 << 30, row_step, 0,
+                       1 << 30);
 }
 
 /* Same as orc_render for the pixels x0 <= i < x1, y0 <= j < y1 of the [H][W] image only (the
@@ -702,8 +871,13 @@ int orc_render_window(const orc_tree *t, const orc_view *view, double *image, in
                       int x1, int y1)
 {
     if (x0 < 0 || y0 < 0 || x1 < x0 || y1 < y0) return -1;
-    return render_rows(t, 1, view, &image, NULL, NULL, y0, y1, 1, x0, x1);
+    return render_rows(t, 1, view, &image, NULL, NULL, NULL, y0, y1, 1, x0, x1);
 }
+
+/* The pixels listed in px ([n][2] = column, row) of one view, written to out[n][4] (a sparse
+ * sample of a large frame). */
+int orc_render_pixels(const orc_tree *t, const orc_view *view, const int32_t *px, int64_t n,
+                      double *out);
 
 int orc_num_threads(void)
 {
@@ -714,15 +888,87 @@ int orc_num_threads(void)
 #endif
 }
 
-static int render_rows(const orc_tree *t, int n_views, const orc_view *views,
-                       double *const *images, int32_t *const *nsamp, double *const *ert_margin,
-                       int row_begin, int row_end, int row_step, int col_begin, int col_end)
+/* One ray: its premultiplied RGBA, nominal count, margin and AVG-fallback count. */
+static void cast_ray(const orc_tree *t, const orc_view *v, const orc_cam *cm,
+                     const orc_luts *lu, int i, int j, double px[4], int32_t *ns_out,
+                     double *margin_out, int32_t *navg_out)
 {
     const int C = t->p.channels;
+    orc_ray ry;
+    ray_setup(t, v, cm, i, j, &ry);
+    double Cr = 0, Cg = 0, Cb = 0, A = 0, margin = INFINITY;
+    int32_t ns = 0, nfb = 0;
+    double mx1[ORC_MAXC], mx2[ORC_MAXC];   /* MIP: largest sample, largest at another position */
+    for (int c = 0; c < C; c++) mx1[c] = mx2[c] = -INFINITY;
+    const int mip = v->mode == 1;
+    const int ert = !mip && v->ert_alpha < 1.0f;
+    if (ry.hit) {
+        for (int k = 0;; k++) {
+            float tk = ry.t0 + (float)k * v->step;
+            if (!(tk < ry.t1)) break;
+            ns++;
+            if (ert && A >= (double)v->ert_alpha) continue;
+            float p[3];
+            for (int a = 0; a < 3; a++) {
+                float m = tk * ry.d[a];
+                p[a] = ry.o[a] + m;
+            }
+            orc_sample_geo g[ORC_MAXC];
+            nfb += position_geo(t, v, ry.L, p, g);
+            for (int c = 0; c < C; c++) {
+                double s = sample_value(t, c, &g[c]);
+                if (mip) {
+                    if (s > mx1[c]) {
+                        mx2[c] = mx1[c];
+                        mx1[c] = s;
+                    } else if (s > mx2[c]) {
+                        mx2[c] = s;
+                    }
+                    continue;
+                }
+                double rgba[4];
+                classify(lu, v, c, s, rgba, NULL, NULL, NULL);
+                double wgt = (1.0 - A) * rgba[3];
+                Cr += wgt * rgba[0];
+                Cg += wgt * rgba[1];
+                Cb += wgt * rgba[2];
+                A += wgt;
+            }
+            if (ert) {
+                double m = fabs(A - (double)v->ert_alpha);
+                if (m < margin) margin = m;
+            }
+        }
+        if (mip && ns > 0) {
+            for (int c = 0; c < C; c++) {
+                double rgba[4];
+                classify(lu, v, c, mx1[c], rgba, NULL, NULL, NULL);
+                double wgt = (1.0 - A) * rgba[3];
+                Cr += wgt * rgba[0];
+                Cg += wgt * rgba[1];
+                Cb += wgt * rgba[2];
+                A += wgt;
+                double gap = mx1[c] - mx2[c];
+                if (gap < margin) margin = gap;
+            }
+        }
+    }
+    px[0] = Cr; px[1] = Cg; px[2] = Cb; px[3] = A;
+    if (ns_out) *ns_out = ns;
+    if (margin_out) *margin_out = margin;
+    if (navg_out) *navg_out = nfb;
+}
+
+static int render_rows(const orc_tree *t, int n_views, const orc_view *views,
+                       double *const *images, int32_t *const *nsamp, double *const *margin,
+                       int32_t *const *navg, int row_begin, int row_end, int row_step,
+                       int col_begin, int col_end)
+{
+    const int C = t->p.channels;
+    for (int vi = 0; vi < n_views; vi++)
+        if (!view_ok(t, &views[vi])) return -1;
     for (int vi = 0; vi < n_views; vi++) {
         const orc_view *v = &views[vi];
-        if (v->width <= 0 || v->height <= 0) return -1;
-        if (t->poked && v->lod != 0) return -1;
         orc_luts *lu = (orc_luts *)malloc(sizeof(orc_luts));
         build_luts(v, C, lu);
         orc_cam cm;
@@ -732,45 +978,31 @@ static int render_rows(const orc_tree *t, int n_views, const orc_view *views,
 #pragma omp parallel for schedule(dynamic, 1)
         for (int j = row_begin; j < j_end; j += row_step)
             for (int i = col_begin; i < i_end; i++) {
-                double *px = images[vi] + ((int64_t)j * W + i) * 4;
-                orc_ray ry;
-                ray_setup(t, v, &cm, i, j, &ry);
-                double Cr = 0, Cg = 0, Cb = 0, A = 0, margin = INFINITY;
-                int32_t ns = 0;
-                if (ry.hit) {
-                    for (int k = 0;; k++) {
-                        float tk = ry.t0 + (float)k * v->step;
-                        if (!(tk < ry.t1)) break;
-                        ns++;
-                        if (v->ert_alpha < 1.0f && A >= (double)v->ert_alpha) continue;
-                        float p[3];
-                        for (int a = 0; a < 3; a++) {
-                            float m = tk * ry.d[a];
-                            p[a] = ry.o[a] + m;
-                        }
-                        orc_sample_geo g;
-                        sample_geo(t, ry.L, p, &g);
-                        for (int c = 0; c < C; c++) {
-                            double s = sample_value(t, ry.L, c, &g), rgba[4];
-                            classify(lu, v, c, s, rgba, NULL, NULL, NULL);
-                            double wgt = (1.0 - A) * rgba[3];
-                            Cr += wgt * rgba[0];
-                            Cg += wgt * rgba[1];
-                            Cb += wgt * rgba[2];
-                            A += wgt;
-                        }
-                        if (v->ert_alpha < 1.0f) {
-                            double m = fabs(A - (double)v->ert_alpha);
-                            if (m < margin) margin = m;
-                        }
-                    }
-                }
-                px[0] = Cr; px[1] = Cg; px[2] = Cb; px[3] = A;
-                if (nsamp) nsamp[vi][(int64_t)j * W + i] = ns;
-                if (ert_margin) ert_margin[vi][(int64_t)j * W + i] = margin;
+                const int64_t q = (int64_t)j * W + i;
+                cast_ray(t, v, &cm, lu, i, j, images[vi] + q * 4, nsamp ? &nsamp[vi][q] : NULL,
+                         margin ? &margin[vi][q] : NULL, navg ? &navg[vi][q] : NULL);
             }
         free(lu);
     }
+    return 0;
+}
+
+int orc_render_pixels(const orc_tree *t, const orc_view *view, const int32_t *px, int64_t n,
+                      double *out)
+{
+    if (!view_ok(t, view)) return -1;
+    for (int64_t q = 0; q < n; q++)
+        if (px[2 * q] < 0 || px[2 * q] >= view->width || px[2 * q + 1] < 0 ||
+            px[2 * q + 1] >= view->height)
+            return -1;
+    orc_luts *lu = (orc_luts *)malloc(sizeof(orc_luts));
+    build_luts(view, t->p.channels, lu);
+    orc_cam cm;
+    cam_setup(view, &cm);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t q = 0; q < n; q++)
+        cast_ray(t, view, &cm, lu, px[2 * q], px[2 * q + 1], out + q * 4, NULL, NULL, NULL);
+    free(lu);
     return 0;
 }
 
@@ -785,27 +1017,67 @@ static int render_rows(const orc_tree *t, int n_views, const orc_view *views,
  *   C_{e+1} = C_e + T_e a_e rgb_e,  A_{e+1} = A_e + T_e a_e.
  * Walking back: g_rgb_e = gC T_e a_e, g_a_e = gC.rgb_e T_e + gA_{e+1} T_e,
  *   gA_e = gA_{e+1} (1 - a_e) - a_e gC.rgb_e.
+ * MIP: the events are the C classified maxima; the maximum of channel c is the sample at the
+ * first position where it is reached (the gradient of a maximum is taken at its arg max), so
+ * its value gradient flows through that sample's trilinear weights.
  */
 typedef struct {
     double A;              /* alpha before the event */
     double rgba[4];
     int slot_i;
     double slot_f, duds;
-    int L, brick;
-    int64_t idx[8];
-    double w[8];
+    orc_sample_geo g;      /* the sample's geometry (its channel's) */
     int c;
 } orc_event;
+
+/* Adds the gradient of one ray's events (in compositing order) into the thread's table
+ * accumulator tl and into dvox. */
+static void backprop_events(const orc_tree *t, const orc_luts *lu, const orc_event *ev, size_t ne,
+                            const double gI[4], double *tl, double *dvox)
+{
+    const int64_t nv0 = lvl_voxels(t, 0);
+    double gC[3] = {gI[0], gI[1], gI[2]}, gA = gI[3];
+    for (size_t n = ne; n-- > 0;) {
+        const orc_event *e = &ev[n];
+        double T = 1.0 - e->A, a = e->rgba[3];
+        double gcr = gC[0] * e->rgba[0] + gC[1] * e->rgba[1] + gC[2] * e->rgba[2];
+        double g_rgba[4];
+        for (int q = 0; q < 3; q++) g_rgba[q] = gC[q] * T * a;
+        g_rgba[3] = gcr * T + gA * T;
+        gA = gA * (1.0 - a) - a * gcr;
+        /* into the table cell */
+        double *d0 = tl + ((int64_t)e->c * 256 + e->slot_i) * 4;
+        double *d1 = d0 + 4;
+        double gs = 0.0;
+        const double *l0 = lu->lut[e->c][e->slot_i], *l1 = lu->lut[e->c][e->slot_i + 1];
+        for (int q = 0; q < 4; q++) {
+            d0[q] += (1.0 - e->slot_f) * g_rgba[q];
+            d1[q] += e->slot_f * g_rgba[q];
+            gs += g_rgba[q] * (l1[q] - l0[q]);
+        }
+        gs *= e->duds;
+        if (dvox && e->g.trilinear && e->g.Ls == 0) {
+            double *dv = dvox + (int64_t)e->c * nv0;
+            for (int k = 0; k < 8; k++) {
+                if (e->g.src[k]) continue;   /* an AVG, not a voxel value */
+                const double add = gs * e->g.w[k];
+#pragma omp atomic
+                dv[e->g.idx[k]] += add;
+            }
+        }
+    }
+}
 
 int orc_render_grad(const orc_tree *t, int n_views, const orc_view *views,
                     const double *const *dL_dI, double *dctrl, double *dvox)
 {
     const int C = t->p.channels;
-    const int64_t nv0 = lvl_voxels(t, 0);
     for (int vi = 0; vi < n_views; vi++)
-        if (t->poked && views[vi].lod != 0) return -1;
+        if (!view_ok(t, &views[vi])) return -1;
     for (int vi = 0; vi < n_views; vi++) {
         const orc_view *v = &views[vi];
+        const int mip = v->mode == 1;
+        const int ert = !mip && v->ert_alpha < 1.0f;
         orc_luts *lu = (orc_luts *)malloc(sizeof(orc_luts));
         build_luts(v, C, lu);
         orc_cam cm;
@@ -830,63 +1102,51 @@ int orc_render_grad(const orc_tree *t, int n_views, const orc_view *views,
                 if (!ry.hit) continue;
                 size_t ne = 0;
                 double A = 0.0;
+                double mx[ORC_MAXC];
+                orc_sample_geo amax[ORC_MAXC];
+                for (int c = 0; c < C; c++) mx[c] = -INFINITY;
                 for (int k = 0;; k++) {
                     float tk = ry.t0 + (float)k * v->step;
                     if (!(tk < ry.t1)) break;
-                    if (v->ert_alpha < 1.0f && A >= (double)v->ert_alpha) break;
+                    if (ert && A >= (double)v->ert_alpha) break;
                     float p[3];
                     for (int a = 0; a < 3; a++) {
                         float m = tk * ry.d[a];
                         p[a] = ry.o[a] + m;
                     }
-                    orc_sample_geo g;
-                    sample_geo(t, ry.L, p, &g);
+                    orc_sample_geo g[ORC_MAXC];
+                    position_geo(t, v, ry.L, p, g);
                     for (int c = 0; c < C; c++) {
+                        double s = sample_value(t, c, &g[c]);
+                        if (mip) {
+                            if (s > mx[c]) {   /* the first position reaching the maximum */
+                                mx[c] = s;
+                                amax[c] = g[c];
+                            }
+                            continue;
+                        }
                         if (ne == cap) {
                             cap *= 2;
                             ev = (orc_event *)realloc(ev, cap * sizeof(orc_event));
                         }
                         orc_event *e = &ev[ne++];
-                        double s = sample_value(t, ry.L, c, &g);
                         classify(lu, v, c, s, e->rgba, &e->slot_i, &e->slot_f, &e->duds);
                         e->A = A;
                         e->c = c;
-                        e->L = ry.L;
-                        e->brick = g.brick;
-                        memcpy(e->idx, g.idx, sizeof g.idx);
-                        memcpy(e->w, g.w, sizeof g.w);
+                        e->g = g[c];
                         A += (1.0 - A) * e->rgba[3];
                     }
                 }
-                double gC[3] = {gI[0], gI[1], gI[2]}, gA = gI[3];
-                for (size_t n = ne; n-- > 0;) {
-                    orc_event *e = &ev[n];
-                    double T = 1.0 - e->A, a = e->rgba[3];
-                    double gcr = gC[0] * e->rgba[0] + gC[1] * e->rgba[1] + gC[2] * e->rgba[2];
-                    double g_rgba[4];
-                    for (int q = 0; q < 3; q++) g_rgba[q] = gC[q] * T * a;
-                    g_rgba[3] = gcr * T + gA * T;
-                    gA = gA * (1.0 - a) - a * gcr;
-                    /* into the table cell */
-                    double *d0 = tl + ((int64_t)e->c * 256 + e->slot_i) * 4;
-                    double *d1 = d0 + 4;
-                    double gs = 0.0;
-                    const double *l0 = lu->lut[e->c][e->slot_i], *l1 = lu->lut[e->c][e->slot_i + 1];
-                    for (int q = 0; q < 4; q++) {
-                        d0[q] += (1.0 - e->slot_f) * g_rgba[q];
-                        d1[q] += e->slot_f * g_rgba[q];
-                        gs += g_rgba[q] * (l1[q] - l0[q]);
+                if (mip)
+                    for (int c = 0; c < C; c++) {
+                        orc_event *e = &ev[ne++];
+                        classify(lu, v, c, mx[c], e->rgba, &e->slot_i, &e->slot_f, &e->duds);
+                        e->A = A;
+                        e->c = c;
+                        e->g = amax[c];
+                        A += (1.0 - A) * e->rgba[3];
                     }
-                    gs *= e->duds;
-                    if (dvox && e->L == 0 && e->brick) {
-                        double *dv = dvox + (int64_t)e->c * nv0;
-                        for (int k = 0; k < 8; k++) {
-                            const double add = gs * e->w[k];
-#pragma omp atomic
-                            dv[e->idx[k]] += add;
-                        }
-                    }
-                }
+                backprop_events(t, lu, ev, ne, gI, tl, dvox);
             }
         free(ev);
 #pragma omp critical
@@ -974,8 +1234,10 @@ int orc_poke_level0(orc_tree *t, int c, int x, int y, int z, double value)
     const int M = t->p.brick;
     const orc_node *nd = node_at(t, 0, x / M, y / M, z / M);
     if (!nd->exists || nd->state != ST_BRICK) return -1;
-    *lvl_at(t->V[0], t, 0, c, z, y, x) = value;
-    *lvl_at(t->R[0], t, 0, c, z, y, x) = value;
+    if (t->p.dtype == 0 ? !(value >= 0.0 && value <= 65535.0 && value == floor(value))
+                        : (double)(float)value != value)
+        return -1;   /* the data type must hold the replacement exactly */
+    vset(t, 0, lvl_index(t, 0, c, z, y, x), value);
     t->poked = 1;
     return 0;
 }

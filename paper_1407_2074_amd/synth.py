@@ -181,6 +181,10 @@ class View:
     tile_count: int = -1          # -1 = all tiles from tile_begin
     depth_segments: int = 0       # 0 = automatic (by ray length), 1 = one pass per ray
     no_skip: int = 0              # 1 = march every position (no empty-space skipping)
+    mode: int = 0                 # 0 = emission-absorption (DVR), 1 = maximum intensity projection
+    missing: int = 0              # non-resident bricks: 0 = AVG, 1 = full-frame fallback to the
+                                  # two coarser levels, 2 = refinement (rays wait for the brick)
+    xform: np.ndarray = None      # None, or [C][3][4] float32: channel c samples at M p + b
 
     @property
     def channels(self) -> int:
