@@ -53,6 +53,23 @@ extern "C" {
 #define OCT_TF_POINTS 8
 #define OCT_TILE 8
 
+/* oct_view.mode: how the samples of a ray are combined ("Basic Ray-Casting"). */
+#define OCT_MODE_DVR 0   /* front-to-back emission-absorption (direct volume rendering)    */
+#define OCT_MODE_MIP 1   /* maximum intensity projection: per channel the largest sample of
+                            the ray is classified once; the C classified values are
+                            composited in channel order; ert_alpha does not apply          */
+
+/* oct_view.missing: how a sample is drawn whose brick is not in the device pool (capped
+ * pools, "Brick Upload from RAM to GPU"). */
+#define OCT_MISSING_AVG 0       /* the node's AVG ("Basic Ray-Casting")                     */
+#define OCT_MISSING_FALLBACK 1  /* the resident brick of the first of the two coarser levels
+                                   on the sample's path, else the AVG; all three bricks are
+                                   requested ("Full-Frame Ray-Casting")                     */
+#define OCT_MISSING_REFINE 2    /* the ray stops before the sample and waits in
+                                   oct_view.refine_state; the next render_views of the same
+                                   view resumes it; the image is written only by the pass in
+                                   which no ray had to wait ("Refinement Ray-Casting")      */
+
 typedef struct oct_handle oct_handle;
 
 /* Volume description (section "CPU Data Structure", Eq. 1, and "Handling Volumes of Arbitrary
@@ -108,7 +125,18 @@ typedef struct {
                                    256 positions of the volume diagonal, at most 5), 1 = one
                                    pass, at most 16.  Only compositing rounding differs
                                    between segment counts.                                */
-    int32_t reserved[2];        /* must be 0                                               */
+    int32_t mode;               /* OCT_MODE_DVR or OCT_MODE_MIP                            */
+    int32_t missing;            /* OCT_MISSING_AVG, _FALLBACK or _REFINE                   */
+    int32_t n_xform;            /* 0, or C: channel c samples the volume at
+                                   xform[c] (p) = M p + b instead of the ray position p
+                                   ("Correction of Chromatic Aberration"); each row is
+                                   evaluated as ((m0 p0 + m1 p1) + m2 p2) + b in float32   */
+    int32_t reserved;           /* must be 0                                               */
+    float xform[OCT_MAX_CHANNELS][3][4]; /* rows (m0, m1, m2, b) of each channel's map     */
+    void *refine_state;         /* OCT_MISSING_REFINE only: device buffer of
+                                   render_refine_bytes() bytes owned by the caller, zero-
+                                   filled before the first pass of a new image and kept
+                                   unchanged between the passes of one view               */
 } oct_view;
 
 typedef struct {
@@ -126,6 +154,8 @@ typedef struct {
     uint64_t positions_nominal; /* sample positions t_k < t1 over all rays                 */
     uint64_t positions_composited; /* positions actually sampled (not skipped, before ERT)  */
     uint64_t positions_trilinear;  /* of those, positions interpolated inside a brick       */
+    uint64_t rays_waiting;      /* OCT_MISSING_REFINE views: rays stopped at a missing brick
+                                   in this pass (their images were not written)            */
 } oct_render_stats;
 
 /* Creates the octree: the root node exists from the start and holds only the background
@@ -181,9 +211,13 @@ int brick_pool_upload(oct_handle *h, uint64_t byte_budget, void *stream, oct_upl
 /* Renders n_views views in one launch (Algorithm 1 with accumulation-level intermixing of the
  * channels): each 8x8 tile of each view is one 64-lane wave.  images[i] is a device pointer
  * to [height][width][4] float32 for view i; only the tiles [tile_begin, tile_begin+count)
- * are written.  ckpt_ws: NULL, or a device workspace of render_ckpt_bytes() bytes that
- * receives the transmittance checkpoints render_views_backward needs.  `out` (may be NULL)
- * returns sample counts; passing it synchronises the stream.  Errors: OCT_EINVAL, OCT_EDEVICE. */
+ * are written (for OCT_MISSING_REFINE views only by the pass in which no ray waited).
+ * ckpt_ws: NULL, or a device workspace of render_ckpt_bytes() bytes that receives what
+ * render_views_backward needs (transmittance checkpoints; for MIP views the position of each
+ * channel's maximum).  `out` (may be NULL) returns sample counts; passing it synchronises the
+ * stream.  Views of any mode, missing-brick rule and transform may share a launch.
+ * Errors: OCT_EINVAL (e.g. a refinement view without refine_state, n_xform other than 0 or
+ * C, a refinement view with checkpoints), OCT_EDEVICE. */
 int render_views(oct_handle *h, int32_t n_views, const oct_view *views, float *const *images,
                  void *ckpt_ws, void *stream, oct_render_stats *out);
 
@@ -209,6 +243,11 @@ int render_views_noalloc(oct_handle *h, int32_t n_views, const oct_view *views,
 /* Bytes of checkpoint workspace render_views needs for these views (0 on bad arguments). */
 size_t render_ckpt_bytes(const oct_handle *h, int32_t n_views, const oct_view *views);
 
+/* Bytes of refinement state for one view (32 per pixel; 0 on bad arguments).  The state holds
+ * each ray's next position and its colour and opacity (or, for MIP, its running maxima) so far;
+ * zero-filled memory starts every ray from its entry point. */
+size_t render_refine_bytes(const oct_handle *h, const oct_view *view);
+
 /* Adjoint of render_views for a scalar loss L(images): given dL/dimage per view (device,
  * [height][width][4] float32) and the workspace filled by the forward with the same views,
  * accumulates (adds) into
@@ -216,6 +255,10 @@ size_t render_ckpt_bytes(const oct_handle *h, int32_t n_views, const oct_view *v
  *   dL_dvoxels device [C][Dz][Dy][Dx] float32 or NULL: gradient w.r.t. the level-0 voxel
  *              values, defined for views with lod 0 on an octree whose level-0 nodes all hold
  *              bricks (threshold 0, everything inserted)
+ * DVR views are differentiated through every position (transmittance checkpoints replayed back
+ * to front); MIP views through the sample at which each channel first reaches its maximum
+ * (with or without channel transforms).  DVR views with channel transforms and views whose
+ * missing-brick rule is not OCT_MISSING_AVG are not differentiable here (OCT_EINVAL).
  * The workspace must have been filled by the last render_views call that used it, with the
  * same views, and no upload or clear that changed the octree may come between the two.
  * Ordering: the backward follows every render and backward issued earlier on this handle, on

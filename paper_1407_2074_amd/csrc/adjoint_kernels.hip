@@ -404,6 +404,173 @@ k_render_backward(VolGeom g, const DevCell *__restrict__ table, const uint8_t *_
     }
 }
 
+// Adjoint of a MIP view: a pixel is the channel-order composite of the classified maxima m_c,
+// and m_c is the sample at the recorded position amax[c] (the first position reaching it; -1:
+// no sample exceeded the window's low end, m_c = lo_c).  Per pixel the image gradient goes back
+// through the compositing chain of the C events (as for one DVR position), into the two table
+// entries each event interpolated (per-workgroup LDS accumulator), and, through the table slope
+// and the trilinear weights of that one sample, into its eight level-0 corner voxels.  The
+// sample is recomputed with the forward's operations (same cell, brick coordinates and
+// interpolation order), so it equals the forward's maximum.
+template <typename T, int C, bool kXf>
+__device__ __forceinline__ void
+mip_backward_body(const VolGeom &g, const DevCell *__restrict__ table,
+                  const uint8_t *__restrict__ pool, uint64_t brick_bytes, const DevView &V,
+                  const WgItem &it, const ViewTables<C> &tb, float (*s_dlut)[256][4], float *dvox)
+{
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (wave >= it.ntiles) return;
+    const int tile = it.tile0 + wave;
+    const int px_i = (tile % V.tiles_x) * 8 + (lane & 7);
+    const int px_j = (tile / V.tiles_x) * 8 + (lane >> 3);
+    const bool inside = px_i < V.width && px_j < V.height;
+    if (!inside) return;
+    const int64_t pix = (int64_t)px_j * V.width + px_i;
+    const Ray ray = setup_ray(V, g, px_i, px_j, inside);
+    if (!ray.hit) return;
+    const float4 gi = *(const float4 *)(V.dimg + pix * 4);
+    const int4 am4 = *(const int4 *)(V.amax + pix * 4);
+    const int am[4] = {am4.x, am4.y, am4.z, am4.w};
+    const int L = ray.L;
+    const float scaleL = __builtin_ldexpf(1.0f, -L);
+    const int S = g.M + 2;
+    const float imax = (float)(S - 2);
+    const int csz = g.M << L, G = g.grid[L];
+    const int64_t nvox0 = (int64_t)g.dims[0] * g.dims[1] * g.dims[2];
+    float sv[C], f[C][3], usc[C], ub[C];
+    int org[C][3], ii[C][3];
+    bool vox[C];
+#pragma unroll
+    for (int c = 0; c < C; c++) {
+        usc[c] = V.uscale[c];
+        ub[c] = -V.ulo[c] * usc[c];
+        sv[c] = V.ulo[c];
+        vox[c] = false;
+        if (am[c] < 0) continue;
+        const float tk = ray.t0 + (float)am[c] * V.step;
+        float p[3];
+        for (int q = 0; q < 3; q++) {
+            const float m = tk * ray.d[q];
+            p[q] = ray.o[q] + m;
+        }
+        if constexpr (kXf) {
+            float pc[3];
+            for (int a = 0; a < 3; a++) {
+                const float *m = V.xform[c][a];
+                const float s0 = m[0] * p[0];
+                const float s1 = m[1] * p[1];
+                const float s2 = m[2] * p[2];
+                const float u = s0 + s1;
+                const float w = u + s2;
+                pc[a] = w + m[3];
+            }
+            for (int a = 0; a < 3; a++) p[a] = pc[a];
+        }
+        int v[3], cc[3];
+        for (int q = 0; q < 3; q++) {
+            v[q] = min(max((int)floorf(p[q]), 0), g.dims[q] - 1);
+            cc[q] = v[q] / csz;
+        }
+        const DevCell &cell = table[g.cell_off[L] + (cc[2] * G + cc[1]) * G + cc[0]];
+        if (cell.kind != kBrick) {
+            sv[c] = cell.avg[c];
+            continue;
+        }
+        const T *b0 = (const T *)(pool + (uint64_t)cell.slot * brick_bytes);
+        for (int q = 0; q < 3; q++) {
+            const float lq = __builtin_fmaf(p[q], scaleL, -((float)(cc[q] * g.M) - 0.5f));
+            f[c][q] = __builtin_amdgcn_fractf(lq);
+            ii[c][q] = (int)__builtin_amdgcn_fmed3f(lq, 0.0f, imax);
+            org[c][q] = cc[q] * g.M - 1;
+        }
+        const int64_t v0 = ((int64_t)(ii[c][2] * S + ii[c][1]) * S + ii[c][0]) * 4 + c;
+        const int64_t dy = (int64_t)S * 4, dz = (int64_t)S * S * 4;
+        const float w000 = (float)b0[v0], w100 = (float)b0[v0 + 4];
+        const float w010 = (float)b0[v0 + dy], w110 = (float)b0[v0 + dy + 4];
+        const float w001 = (float)b0[v0 + dz], w101 = (float)b0[v0 + dz + 4];
+        const float w011 = (float)b0[v0 + dz + dy], w111 = (float)b0[v0 + dz + dy + 4];
+        const float c00 = lerpf(w000, w100, f[c][0]);
+        const float c10 = lerpf(w010, w110, f[c][0]);
+        const float c01 = lerpf(w001, w101, f[c][0]);
+        const float c11 = lerpf(w011, w111, f[c][0]);
+        sv[c] = lerpf(lerpf(c00, c10, f[c][1]), lerpf(c01, c11, f[c][1]), f[c][2]);
+        vox[c] = dvox != nullptr && L == 0;
+    }
+    // forward chain over the C events, then back
+    Classified cq[C];
+    float rgba[C][4], Tc[C];
+    float Tp = 1.0f;
+#pragma unroll
+    for (int c = 0; c < C; c++) {
+        cq[c] = classify(sv[c], ub[c], usc[c], tb.lut[c]);
+        rgba[c][0] = __builtin_fmaf(cq[c].fr, cq[c].de.x, cq[c].e0.x);
+        rgba[c][1] = __builtin_fmaf(cq[c].fr, cq[c].de.y, cq[c].e0.y);
+        rgba[c][2] = __builtin_fmaf(cq[c].fr, cq[c].de.z, cq[c].e0.z);
+        rgba[c][3] = __builtin_fmaf(cq[c].fr, cq[c].de.w, cq[c].e0.w);
+        Tc[c] = Tp;
+        Tp = Tp - Tp * rgba[c][3];
+    }
+    const float gC[3] = {gi.x, gi.y, gi.z}, gA = gi.w;
+    float Bc[3] = {0.0f, 0.0f, 0.0f}, Ba = 0.0f;
+#pragma unroll
+    for (int c = C - 1; c >= 0; c--) {
+        const float a = rgba[c][3];
+        float gq[4];
+        for (int q = 0; q < 3; q++) gq[q] = gC[q] * Tc[c] * a;
+        gq[3] = Tc[c] * (gC[0] * (rgba[c][0] - Bc[0]) + gC[1] * (rgba[c][1] - Bc[1]) +
+                         gC[2] * (rgba[c][2] - Bc[2]) + gA * (1.0f - Ba));
+        for (int q = 0; q < 3; q++) Bc[q] = a * rgba[c][q] + (1.0f - a) * Bc[q];
+        Ba = a + (1.0f - a) * Ba;
+        const float fr = cq[c].fr;
+        for (int q = 0; q < 4; q++) {
+            const float ga = (1.0f - fr) * gq[q], gb = fr * gq[q];
+            if (ga != 0.0f) atomicAdd(&s_dlut[c][cq[c].i][q], ga);
+            if (gb != 0.0f) atomicAdd(&s_dlut[c][cq[c].i + 1][q], gb);
+        }
+        if (vox[c] && cq[c].inside) {
+            const float4 de = cq[c].de;
+            const float gs = usc[c] * (gq[0] * de.x + gq[1] * de.y + gq[2] * de.z + gq[3] * de.w);
+            if (gs != 0.0f) {
+                for (int corner = 0; corner < 8; corner++) {
+                    const int dxx = corner & 1, dyy = (corner >> 1) & 1, dzz = corner >> 2;
+                    const float wgt = (dxx ? f[c][0] : 1.0f - f[c][0]) *
+                                      (dyy ? f[c][1] : 1.0f - f[c][1]) *
+                                      (dzz ? f[c][2] : 1.0f - f[c][2]);
+                    const int gx = min(max(org[c][0] + ii[c][0] + dxx, 0), g.dims[0] - 1);
+                    const int gy = min(max(org[c][1] + ii[c][1] + dyy, 0), g.dims[1] - 1);
+                    const int gz = min(max(org[c][2] + ii[c][2] + dzz, 0), g.dims[2] - 1);
+                    atomicAdd(dvox + c * nvox0 + ((int64_t)gz * g.dims[1] + gy) * g.dims[0] + gx,
+                              gs * wgt);
+                }
+            }
+        }
+    }
+}
+
+template <typename T, int C>
+__global__ void __launch_bounds__(kThreads)
+k_render_backward_mip(VolGeom g, const DevCell *__restrict__ table,
+                      const uint8_t *__restrict__ pool, uint64_t brick_bytes,
+                      const DevView *__restrict__ views, const WgItem *__restrict__ items,
+                      float *dvox)
+{
+    __shared__ ViewTables<C> tb;
+    __shared__ float s_dlut[C][256][4];
+    const WgItem it = items[blockIdx.x];
+    const DevView &V = views[it.view];
+    for (int i = threadIdx.x; i < C * 256 * 4; i += kThreads) (&s_dlut[0][0][0])[i] = 0.0f;
+    build_tables<C>(V, tb);   // ends with a barrier
+    if (V.xform_on)
+        mip_backward_body<T, C, true>(g, table, pool, brick_bytes, V, it, tb, s_dlut, dvox);
+    else
+        mip_backward_body<T, C, false>(g, table, pool, brick_bytes, V, it, tb, s_dlut, dvox);
+    __syncthreads();
+    for (int i = threadIdx.x; i < C * 256 * 4; i += kThreads) {
+        const float v = (&s_dlut[0][0][0])[i];
+        if (v != 0.0f) atomicAdd(V.dlut + i, v);
+    }
+}
+
 // dL/dctrl[v][c][j][q] += sum over table entries k of (weight of control point j in entry k)
 // * dL/dtable[v][c][k][q]; the weights are those of the table construction.
 __global__ void k_lut_to_ctrl(const DevView *views, int n_views, int C, float *dctrl)
@@ -421,7 +588,7 @@ __global__ void k_lut_to_ctrl(const DevView *views, int n_views, int C, float *d
         if (js == j) acc += (1.0f - f) * gk;
         if (js + 1 == j) acc += f * gk;
     }
-    dctrl[(((int64_t)v * C + c) * 8 + j) * 4 + q] += acc;
+    dctrl[(((int64_t)V.user_index * C + c) * 8 + j) * 4 + q] += acc;
 }
 
 template <typename T>
@@ -452,6 +619,34 @@ hipError_t launch_render_backward(const VolGeom &g, const DevCell *table, const 
                                          dvox, s);
     return launch_bw_typed<float>(g, table, pool, brick_bytes, views, items, n_items, scratch, dvox,
                                   s);
+}
+
+hipError_t launch_render_backward_mip(const VolGeom &g, const DevCell *table, const void *pool,
+                                      uint64_t brick_bytes, const DevView *views,
+                                      const WgItem *items, int n_items, float *dvox, hipStream_t s)
+{
+    if (n_items == 0) return hipSuccess;
+    const dim3 grid(n_items), block(kThreads);
+    const uint8_t *p = (const uint8_t *)pool;
+#define OCTRC_MIPBW(T, CC) hipLaunchKernelGGL((k_render_backward_mip<T, CC>), grid, block, 0, s, g, \
+                                              table, p, brick_bytes, views, items, dvox)
+    if (g.dtype == 0) {
+        switch (g.C) {
+        case 1: OCTRC_MIPBW(uint16_t, 1); break;
+        case 2: OCTRC_MIPBW(uint16_t, 2); break;
+        case 3: OCTRC_MIPBW(uint16_t, 3); break;
+        default: OCTRC_MIPBW(uint16_t, 4); break;
+        }
+    } else {
+        switch (g.C) {
+        case 1: OCTRC_MIPBW(float, 1); break;
+        case 2: OCTRC_MIPBW(float, 2); break;
+        case 3: OCTRC_MIPBW(float, 3); break;
+        default: OCTRC_MIPBW(float, 4); break;
+        }
+    }
+#undef OCTRC_MIPBW
+    return hipGetLastError();
 }
 
 hipError_t launch_lut_to_ctrl(const DevView *views, int n_views, int C, float *dctrl, hipStream_t s)

@@ -40,6 +40,27 @@ struct VolGeom {
     int32_t cell_off[kMaxLevels];  // offset of level L in the node table
 };
 
+// Per-ray state of a refinement view (OCT_MISSING_REFINE), kept between passes: status 0 =
+// not started (zero-filled memory), 1 = finished (acc is the result), 2 = waiting before
+// position k for a missing brick.  acc = premultiplied colour and opacity (DVR) or the running
+// per-channel maxima (MIP).
+struct alignas(16) RefineState {
+    float acc[4];
+    int32_t k;
+    int32_t status;
+    int32_t pad[2];
+};
+static_assert(sizeof(RefineState) == 32, "RefineState layout");
+
+// Render kernel classes: views are grouped by class in a launch (consecutive work items), and
+// each class runs its own kernel, so the variants do not share one register allocation.
+enum ViewClass : int32_t {
+    kClassDvr = 0,      // emission-absorption, missing bricks drawn with AVG, no transforms
+    kClassMip = 1,      // maximum intensity projection, otherwise as kClassDvr
+    kClassGeneral = 2,  // channel transforms, full-frame fallback or refinement (either mode)
+    kNumClasses = 3
+};
+
 // Per-view constants of one render launch (built on the host, read by every lane).
 struct DevView {
     float eye[3];
@@ -84,6 +105,17 @@ struct DevView {
     // views with skipping: one bit per node-table cell, set when the cell is transparent for
     // this view (built per launch by k_view_mask from the current table); NULL otherwise
     uint32_t *tmask;
+    int32_t mode;        // OCT_MODE_DVR (0) or OCT_MODE_MIP (1)
+    int32_t missing;     // OCT_MISSING_AVG (0), _FALLBACK (1) or _REFINE (2)
+    int32_t xform_on;    // channel c samples at xform[c] applied to the position
+    int32_t vclass;      // ViewClass
+    int32_t user_index;  // position of the view in the caller's list
+    float xform[kMaxC][3][4];
+    RefineState *rstate; // refinement: [pixel] state kept between passes
+    int32_t *rwait;      // refinement: rays of this view that waited in this launch
+    // MIP with a checkpoint workspace: per pixel, per channel, the first position at which the
+    // channel's maximum was reached (-1: no sample above the window's low end)
+    int32_t *amax;
 };
 
 // One workgroup of a render launch: up to kRenderTilesPerWg tiles of one view (group_tile),
@@ -157,9 +189,16 @@ constexpr int kCkptStride = 64;   // positions per transmittance checkpoint segm
 
 // flags (may be NULL): per node-table cell, set to 1 when a render interpolated the cell's
 // resident brick and to 2 when it needed the cell's brick but found it missing.
+// Views are ordered by class; class_items[k] .. class_items[k + 1] are the work items of class
+// k (class_items[kNumClasses] = all items).
 hipError_t launch_render(const VolGeom &g, const DevCell *table, const void *pool,
-                         uint64_t brick_bytes, const DevView *views, int n_views, int n_items,
-                         RenderCounters *counters, uint8_t *flags, hipStream_t s);
+                         uint64_t brick_bytes, const DevView *views, int n_views,
+                         const int32_t *class_items, RenderCounters *counters, uint8_t *flags,
+                         hipStream_t s);
+// Refinement views: when no ray of the view waited in this launch, write the states' results
+// (DVR: the premultiplied colour; MIP: the classified, composited maxima) to the image.
+hipError_t launch_refine_finish(const DevView *views, const int32_t *refine_views, int n_refine,
+                                int C, int64_t max_pixels, hipStream_t s);
 // Bytes of one view's tables for C channels (views[i].tables points at that many bytes) and
 // 32-bit words of one view's transparency mask over n_cells node-table cells (whole 64-cell
 // groups).  Per launch, the preparation kernel builds every view's tables and tile-group
@@ -168,15 +207,20 @@ hipError_t launch_render(const VolGeom &g, const DevCell *table, const void *poo
 size_t view_tables_bytes(int C);
 inline int64_t view_mask_words(int64_t n_cells) { return (n_cells + 63) / 64 * 2; }
 hipError_t launch_view_prep(const VolGeom &g, const DevView *views, int n_views, hipStream_t s);
-hipError_t launch_view_mask(const DevView *views, int n_views, int C, const DevCell *table,
-                            int64_t n_cells, hipStream_t s);
+hipError_t launch_view_mask(const VolGeom &g, const DevView *views, int n_views,
+                            const DevCell *table, int64_t n_cells, hipStream_t s);
 // Front-to-back composite of the depth segments of every split view into its image.
 hipError_t launch_combine(const DevView *views, const int32_t *split_views, int n_split,
-                          int64_t max_pixels, hipStream_t s);
+                          int C, int64_t max_pixels, hipStream_t s);
 // Adjoint: scratch holds kCkptStride floats per lane of the launch (n_items * 512 lanes).
 hipError_t launch_render_backward(const VolGeom &g, const DevCell *table, const void *pool,
                                   uint64_t brick_bytes, const DevView *views, const WgItem *items,
                                   int n_items, float *scratch, float *dvox, hipStream_t s);
+// Adjoint of MIP views: one lane per pixel, through the samples at the recorded maxima.
+hipError_t launch_render_backward_mip(const VolGeom &g, const DevCell *table, const void *pool,
+                                      uint64_t brick_bytes, const DevView *views,
+                                      const WgItem *items, int n_items, float *dvox,
+                                      hipStream_t s);
 hipError_t launch_lut_to_ctrl(const DevView *views, int n_views, int C, float *dctrl,
                               hipStream_t s);
 

@@ -83,8 +83,16 @@ __device__ inline WgItem item_of(const DevView *__restrict__ views, int n_views,
 
 // kErt: the view may terminate rays early (otherwise the opacity test is left out of the
 // march); kCount: sample counters are requested; kLdsMask: the transparency masks (mask_lds
-// words each) are staged in LDS.
-template <typename T, int C, bool kErt, bool kCount, bool kLdsMask>
+// words each) are staged in LDS; kMip: maximum intensity projection instead of
+// emission-absorption compositing.
+//
+// MIP keeps per channel the running maximum m_c, started at the window's low end lo_c (values
+// at or below lo_c classify like lo_c, so max(lo_c, samples) gives the same image as the
+// maximum of the samples), and the first position that raised it.  A cell whose upper value
+// bound is at most m_c in every channel cannot change either, so its positions are skipped
+// (the per-launch mask marks the cells bounded by lo_c; cells looked up are tested against the
+// current m_c).  The result is the same with skipping on or off, bit for bit.
+template <typename T, int C, bool kErt, bool kCount, bool kLdsMask, bool kMip = false>
 __device__ __forceinline__ void
 render_body(const VolGeom &g, const DevCell *__restrict__ table, const uint8_t *__restrict__ pool,
             uint64_t brick_bytes, const DevView *__restrict__ views, const WgItem &it,
@@ -189,6 +197,34 @@ render_body(const VolGeom &g, const DevCell *__restrict__ table, const uint8_t *
     float avg[C];
 #pragma unroll
     for (int c = 0; c < C; c++) avg[c] = 0.0f;
+    float mxv[C];    // MIP: running maxima (from the window's low end) and their positions
+    int kmv[C];
+#pragma unroll
+    for (int c = 0; c < C; c++) {
+        mxv[c] = V.ulo[c];
+        kmv[c] = -1;
+    }
+
+    // skip the positions inside the box of cell (ax, ay, az) at level lev: jump to just before
+    // its exit (one whole step of margin: every skipped position lies inside the box) and
+    // forget the cached cell
+    auto jump_box = [&](int lev, int ax, int ay, int az) {
+        const int e = g.M << lev;
+        const int bl[3] = {ax * e, ay * e, az * e};
+        float te = INFINITY;
+#pragma unroll
+        for (int q = 0; q < 3; q++) {
+            const float plane = d[q] > 0.0f ? (float)(bl[q] + e) : (float)bl[q];
+            if (d[q] != 0.0f) te = fminf(te, (plane - o[q]) * invd[q]);
+        }
+        const float kf = floorf((te - t0) * rstep) - 1.0f;
+        k = (kf > (float)(k + 1)) ? (int)fminf(kf, 2.0e9f) : k + 1;
+        bofs[0] = INFINITY;   // no cell cached: the next position looks its cell up
+        blo[0] = 1;
+        bhi[0] = 0;
+        k_lo = 1;
+        k_hi = 0;
+    };
 
     // the 8 corners of the last trilinear sample (bordered-brick byte offset last_off):
     // consecutive positions often fall between the same 8 voxels, and the loads are what the
@@ -262,25 +298,24 @@ render_body(const VolGeom &g, const DevCell *__restrict__ table, const uint8_t *
                     ay >>= 1;
                     az >>= 1;
                 }
-                const int e = g.M << lev;
-                const int bl[3] = {ax * e, ay * e, az * e};
-                float te = INFINITY;
-#pragma unroll
-                for (int q = 0; q < 3; q++) {
-                    const float plane = d[q] > 0.0f ? (float)(bl[q] + e) : (float)bl[q];
-                    if (d[q] != 0.0f) te = fminf(te, (plane - o[q]) * invd[q]);
-                }
-                // one whole step of margin: every skipped position lies inside the box
-                const float kf = floorf((te - t0) * rstep) - 1.0f;
-                k = (kf > (float)(k + 1)) ? (int)fminf(kf, 2.0e9f) : k + 1;
-                bofs[0] = INFINITY;   // no cell cached: the next position looks its cell up
-                blo[0] = 1;
-                bhi[0] = 0;
-                k_lo = 1;
-                k_hi = 0;
+                jump_box(lev, ax, ay, az);
                 continue;
             }
             const DevCell &cell = table[cidx];
+            if constexpr (kMip) {
+                if (skip) {
+                    // no sample of this cell can raise a running maximum
+                    const float4 ch4 = *(const float4 *)cell.hi;
+                    const float chi[4] = {ch4.x, ch4.y, ch4.z, ch4.w};
+                    bool below = true;
+#pragma unroll
+                    for (int c = 0; c < C; c++) below = below && chi[c] <= mxv[c];
+                    if (below) {
+                        jump_box(L, cx, cy, cz);
+                        continue;
+                    }
+                }
+            }
             bofs[0] = (float)(cx * g.M) - 0.5f;
             bofs[1] = (float)(cy * g.M) - 0.5f;
             bofs[2] = (float)(cz * g.M) - 0.5f;
@@ -389,23 +424,63 @@ render_body(const VolGeom &g, const DevCell *__restrict__ table, const uint8_t *
 #pragma unroll
             for (int c = 0; c < C; c++) s[c] = avg[c];
         }
-        // classification and front-to-back compositing, channels in order
+        if constexpr (kMip) {
 #pragma unroll
-        for (int c = 0; c < C; c++) {
-            const Classified q = classify(s[c], ulo[c], usc[c], tb.lut[c]);
-            const float al = __builtin_fmaf(q.fr, q.de.w, q.e0.w);
-            const float wgt = Tr * al;
-            Cr = __builtin_fmaf(wgt, __builtin_fmaf(q.fr, q.de.x, q.e0.x), Cr);
-            Cg = __builtin_fmaf(wgt, __builtin_fmaf(q.fr, q.de.y, q.e0.y), Cg);
-            Cb = __builtin_fmaf(wgt, __builtin_fmaf(q.fr, q.de.z, q.e0.z), Cb);
-            Tr = Tr - wgt;
+            for (int c = 0; c < C; c++)
+                if (s[c] > mxv[c]) {
+                    mxv[c] = s[c];
+                    kmv[c] = k;
+                }
+        } else {
+            // classification and front-to-back compositing, channels in order
+#pragma unroll
+            for (int c = 0; c < C; c++) {
+                const Classified q = classify(s[c], ulo[c], usc[c], tb.lut[c]);
+                const float al = __builtin_fmaf(q.fr, q.de.w, q.e0.w);
+                const float wgt = Tr * al;
+                Cr = __builtin_fmaf(wgt, __builtin_fmaf(q.fr, q.de.x, q.e0.x), Cr);
+                Cg = __builtin_fmaf(wgt, __builtin_fmaf(q.fr, q.de.y, q.e0.y), Cg);
+                Cb = __builtin_fmaf(wgt, __builtin_fmaf(q.fr, q.de.z, q.e0.z), Cb);
+                Tr = Tr - wgt;
+            }
         }
         if constexpr (kErt)
             if (Tr <= ert_T) live = false;  // early ray termination after this position
         k++;
     }
 
-    if (inside) {
+    if (kMip && inside) {
+        if (split) {
+            // this segment's maxima for the combine pass (-inf: the ray misses the volume)
+            float m4[4] = {-INFINITY, -INFINITY, -INFINITY, -INFINITY};
+            if (ray.hit)
+#pragma unroll
+                for (int c = 0; c < C; c++) m4[c] = mxv[c];
+            const int64_t npix = (int64_t)V.width * V.height;
+            *(float4 *)(V.part + ((int64_t)it.seg * npix + pix) * 4) =
+                make_float4(m4[0], m4[1], m4[2], m4[3]);
+        } else {
+            if (ray.hit) {
+                // the classified maxima, composited in channel order
+#pragma unroll
+                for (int c = 0; c < C; c++) {
+                    const Classified q = classify(mxv[c], ulo[c], usc[c], tb.lut[c]);
+                    const float wgt = Tr * __builtin_fmaf(q.fr, q.de.w, q.e0.w);
+                    Cr = __builtin_fmaf(wgt, __builtin_fmaf(q.fr, q.de.x, q.e0.x), Cr);
+                    Cg = __builtin_fmaf(wgt, __builtin_fmaf(q.fr, q.de.y, q.e0.y), Cg);
+                    Cb = __builtin_fmaf(wgt, __builtin_fmaf(q.fr, q.de.z, q.e0.z), Cb);
+                    Tr = Tr - wgt;
+                }
+            }
+            *(float4 *)(V.image + pix * 4) = make_float4(Cr, Cg, Cb, 1.0f - Tr);
+            if (V.amax) {
+                int a4[4] = {-1, -1, -1, -1};
+#pragma unroll
+                for (int c = 0; c < C; c++) a4[c] = kmv[c];
+                *(int4 *)(V.amax + pix * 4) = make_int4(a4[0], a4[1], a4[2], a4[3]);
+            }
+        }
+    } else if (inside) {
         if (split) {
             // this segment's premultiplied colour and transmittance, for the combine pass
             const int64_t npix = (int64_t)V.width * V.height;
@@ -445,59 +520,510 @@ render_body(const VolGeom &g, const DevCell *__restrict__ table, const uint8_t *
 }
 
 // One render work item: the march specialised for the view's early termination and for
-// sample counters (both uniform over the workgroup).
-template <typename T, int C, bool kLdsMask>
+// sample counters (both uniform over the workgroup); kMip: the MIP class (no termination).
+template <typename T, int C, bool kLdsMask, bool kMip>
 __device__ __forceinline__ void
 render_item(const VolGeom &g, const DevCell *__restrict__ table, const uint8_t *__restrict__ pool,
-            uint64_t brick_bytes, const DevView *__restrict__ views, int n_views,
+            uint64_t brick_bytes, const DevView *__restrict__ views, int n_views, int item,
             RenderCounters *counters, uint8_t *flags, LutTable<C> &tb, int mask_lds)
 {
-    const WgItem it = item_of(views, n_views, blockIdx.x);
-    if (counters)
-        render_body<T, C, true, true, kLdsMask>(g, table, pool, brick_bytes, views, it, counters,
-                                                flags, tb, mask_lds);
-    else if (views[it.view].ert < 1.0f)
-        render_body<T, C, true, false, kLdsMask>(g, table, pool, brick_bytes, views, it, counters,
-                                                 flags, tb, mask_lds);
-    else
-        render_body<T, C, false, false, kLdsMask>(g, table, pool, brick_bytes, views, it,
-                                                  counters, flags, tb, mask_lds);
+    const WgItem it = item_of(views, n_views, item);
+    if constexpr (kMip) {
+        if (counters)
+            render_body<T, C, false, true, kLdsMask, true>(g, table, pool, brick_bytes, views, it,
+                                                           counters, flags, tb, mask_lds);
+        else
+            render_body<T, C, false, false, kLdsMask, true>(g, table, pool, brick_bytes, views,
+                                                            it, counters, flags, tb, mask_lds);
+    } else {
+        if (counters)
+            render_body<T, C, true, true, kLdsMask>(g, table, pool, brick_bytes, views, it,
+                                                    counters, flags, tb, mask_lds);
+        else if (views[it.view].ert < 1.0f)
+            render_body<T, C, true, false, kLdsMask>(g, table, pool, brick_bytes, views, it,
+                                                     counters, flags, tb, mask_lds);
+        else
+            render_body<T, C, false, false, kLdsMask>(g, table, pool, brick_bytes, views, it,
+                                                      counters, flags, tb, mask_lds);
+    }
 }
 
 // uint16 bricks: registers for 5 waves per SIMD (6 fit only with spills, measured 2 % slower);
-// float32 bricks (twice the corner data) keep the compiler's choice.
+// float32 bricks (twice the corner data) keep the compiler's choice.  item_base: the first
+// work item of this kernel's view class.
 #ifndef OCTRC_U16_WAVES_PER_EU
 #define OCTRC_U16_WAVES_PER_EU 5
 #endif
-template <int C, bool kLdsMask>
+template <int C, bool kLdsMask, bool kMip>
 __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(OCTRC_U16_WAVES_PER_EU)))
 k_render_u16(VolGeom g, const DevCell *__restrict__ table, const uint8_t *__restrict__ pool,
              uint64_t brick_bytes, const DevView *__restrict__ views,
-             int n_views, RenderCounters *counters, uint8_t *flags, int mask_lds)
+             int n_views, int item_base, RenderCounters *counters, uint8_t *flags, int mask_lds)
 {
     __shared__ LutTable<C> tb;
-    render_item<uint16_t, C, kLdsMask>(g, table, pool, brick_bytes, views, n_views, counters,
-                                       flags, tb, mask_lds);
+    render_item<uint16_t, C, kLdsMask, kMip>(g, table, pool, brick_bytes, views, n_views,
+                                             item_base + (int)blockIdx.x, counters, flags, tb,
+                                             mask_lds);
 }
 
-template <int C, bool kLdsMask>
+template <int C, bool kLdsMask, bool kMip>
 __global__ void __launch_bounds__(kThreads)
 k_render_f32(VolGeom g, const DevCell *__restrict__ table, const uint8_t *__restrict__ pool,
              uint64_t brick_bytes, const DevView *__restrict__ views,
-             int n_views, RenderCounters *counters, uint8_t *flags, int mask_lds)
+             int n_views, int item_base, RenderCounters *counters, uint8_t *flags, int mask_lds)
 {
     __shared__ LutTable<C> tb;
-    render_item<float, C, kLdsMask>(g, table, pool, brick_bytes, views, n_views, counters, flags,
-                                    tb, mask_lds);
+    render_item<float, C, kLdsMask, kMip>(g, table, pool, brick_bytes, views, n_views,
+                                          item_base + (int)blockIdx.x, counters, flags, tb,
+                                          mask_lds);
+}
+
+// ---------------------------------------------------------------------------------------
+// General march (class kClassGeneral): per-channel sample transforms ("Correction of
+// Chromatic Aberration"), the full-frame fallback ("Full-Frame Ray-Casting") and refinement
+// ("Refinement Ray-Casting"), in either compositing mode, one pass per ray.  A lookup group
+// -- all channels at the ray position, or (kXf) each channel at its own transformed position
+// -- caches the node-table cell of its last sample and how that cell is drawn.
+enum : int { kDrawAvg = 0, kDrawBrick = 1, kDrawNone = 2, kDrawWait = 3 };
+
+template <int C>
+struct LookupGroup {
+    int cidx = -1;               // cached cell at the ray's level
+    int draw = kDrawAvg;
+    float sscale = 1.0f;         // sampling level Ls: 2^-Ls
+    float sb[3] = {0.0f, 0.0f, 0.0f};  // brick coordinate = p 2^-Ls - sb
+    const uint8_t *base = nullptr;
+    float avg[C];
+};
+
+template <typename T, int C, bool kXf, bool kLdsMask, bool kCount>
+__device__ __forceinline__ void
+render_general_body(const VolGeom &g, const DevCell *__restrict__ table,
+                    const uint8_t *__restrict__ pool, uint64_t brick_bytes,
+                    const DevView *__restrict__ views, const WgItem &it, RenderCounters *counters,
+                    uint8_t *flags, LutTable<C> &tb, int mask_lds)
+{
+    const DevView &V = views[it.view];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    extern __shared__ uint32_t smask[];
+    if (kLdsMask && V.tmask)
+        for (int i = threadIdx.x; i < mask_lds; i += kThreads) smask[i] = V.tmask[i];
+    load_tables<kThreads>(V, tb);
+    if (wave >= it.ntiles) return;  // no barrier below this point
+
+    float ulo[C], usc[C];
+#pragma unroll
+    for (int c = 0; c < C; c++) {
+        usc[c] = V.uscale[c];
+        ulo[c] = -V.ulo[c] * usc[c];
+    }
+    const uint32_t *const tmask = V.tmask;
+    const float step = V.step, rstep = 1.0f / step;
+    const bool mip = V.mode == 1;
+    const int missing = V.missing;
+    const float ert_T = (!mip && V.ert < 1.0f) ? 1.0f - V.ert : -1.0f;
+    const bool skip = V.skip != 0;
+
+    const int tile = group_tile(V, (it.tile0 - V.tile_begin) / kRenderTilesPerWg, wave);
+    const int mx_ = (lane & 1) | ((lane >> 1) & 2) | ((lane >> 2) & 4);
+    const int my_ = ((lane >> 1) & 1) | ((lane >> 2) & 2) | ((lane >> 3) & 4);
+    const int px_i = (tile % V.tiles_x) * 8 + mx_;
+    const int px_j = (tile / V.tiles_x) * 8 + my_;
+    const bool inside = px_i < V.width && px_j < V.height;
+    const int64_t pix = (int64_t)px_j * V.width + px_i;
+    const Ray ray = setup_ray(V, g, px_i, px_j, inside);
+    const float *o = ray.o, *d = ray.d;
+    const float t0 = ray.t0, t1 = ray.t1;
+    const int L = ray.L;
+    const float scaleL = __builtin_ldexpf(1.0f, -L);
+    const int S = g.M + 2;
+    const float imax = (float)(S - 2);
+    const float invd[3] = {d[0] != 0.0f ? 1.0f / d[0] : INFINITY,
+                           d[1] != 0.0f ? 1.0f / d[1] : INFINITY,
+                           d[2] != 0.0f ? 1.0f / d[2] : INFINITY};
+    int nominal = 0;
+    if (ray.hit) {
+        int kk = max((int)((t1 - t0) / step) - 2, 0);
+        while (t0 + (float)kk * step < t1) kk++;
+        nominal = kk;
+    }
+
+    // accumulated state: DVR colour and transmittance, MIP running maxima (from the window's
+    // low end) and the positions that set them
+    float Tr = 1.0f, Cr = 0.0f, Cg = 0.0f, Cb = 0.0f;
+    float mx[C];
+    int kmx[C];
+#pragma unroll
+    for (int c = 0; c < C; c++) {
+        mx[c] = V.ulo[c];
+        kmx[c] = -1;
+    }
+    int k = 0;
+    bool live = ray.hit && inside;
+    RefineState *const rst = (missing == 2 && inside) ? V.rstate + pix : nullptr;
+    int st_status = 0;   // refinement: the ray's state at the start of this pass
+    if (rst) {
+        const RefineState st = *rst;
+        st_status = st.status;
+        if (st.status == 1 || st.status == 3) {
+            live = false;   // finished in an earlier pass: its result is kept in the state
+        } else if (st.status == 2) {
+            k = st.k;
+            if (mip) {
+#pragma unroll
+                for (int c = 0; c < C; c++) mx[c] = st.acc[c];
+            } else {
+                Cr = st.acc[0];
+                Cg = st.acc[1];
+                Cb = st.acc[2];
+                Tr = st.acc[3];
+            }
+        }
+    }
+    const bool done_before = st_status == 1 || st_status == 3;
+    const bool first_pass = st_status == 0;   // rays and nominal positions counted once
+
+    constexpr int NG = kXf ? C : 1;
+    LookupGroup<C> grp[NG];
+    bool waited = false;
+    int composited = 0, trilinear = 0;
+
+    auto cell_index = [&](int lev, const int v[3]) -> int {
+        const int sh = g.mlog2 >= 0 ? g.mlog2 + lev : -1;
+        const int e = g.M << lev;
+        int cx, cy, cz;
+        if (sh >= 0) {
+            cx = v[0] >> sh;
+            cy = v[1] >> sh;
+            cz = v[2] >> sh;
+        } else {
+            cx = v[0] / e;
+            cy = v[1] / e;
+            cz = v[2] / e;
+        }
+        const int G = g.grid[lev];
+        return g.cell_off[lev] + (cz * G + cy) * G + cx;
+    };
+
+    while (live && k < nominal) {
+        const float tk = t0 + (float)k * step;
+        float p[3];
+#pragma unroll
+        for (int q = 0; q < 3; q++) {
+            const float m = tk * d[q];
+            p[q] = o[q] + m;
+        }
+        bool jumped = false;
+        bool any_brick = false;
+#pragma unroll
+        for (int gi = 0; gi < NG; gi++) {
+            float pg[3];
+            if constexpr (kXf) {
+#pragma unroll
+                for (int a = 0; a < 3; a++) {
+                    const float *m = V.xform[gi][a];
+                    const float s0 = m[0] * p[0];
+                    const float s1 = m[1] * p[1];
+                    const float s2 = m[2] * p[2];
+                    const float u = s0 + s1;
+                    const float w = u + s2;
+                    pg[a] = w + m[3];
+                }
+            } else {
+#pragma unroll
+                for (int a = 0; a < 3; a++) pg[a] = p[a];
+            }
+            int v[3];
+#pragma unroll
+            for (int q = 0; q < 3; q++) v[q] = min(max((int)floorf(pg[q]), 0), g.dims[q] - 1);
+            const int cidx = cell_index(L, v);
+            LookupGroup<C> &G = grp[gi];
+            if (cidx != G.cidx) {
+                G.cidx = cidx;
+                if (skip && mask_bit<kLdsMask>(tmask, smask, cidx)) {
+                    G.draw = kDrawNone;
+                    if constexpr (!kXf) {
+                        // widen to the largest transparent ancestor, jump to just before its exit
+                        int lev = L;
+                        int a3[3];
+                        const int e0 = g.M << L;
+                        for (int q = 0; q < 3; q++) a3[q] = v[q] / e0;
+                        while (lev < g.N) {
+                            const int pg_ = g.grid[lev + 1];
+                            if (!mask_bit<kLdsMask>(tmask, smask, g.cell_off[lev + 1] +
+                                                     ((a3[2] >> 1) * pg_ + (a3[1] >> 1)) * pg_ +
+                                                     (a3[0] >> 1)))
+                                break;
+                            lev++;
+                            for (int q = 0; q < 3; q++) a3[q] >>= 1;
+                        }
+                        const int e = g.M << lev;
+                        float te = INFINITY;
+                        for (int q = 0; q < 3; q++) {
+                            const float plane = d[q] > 0.0f ? (float)(a3[q] * e + e) : (float)(a3[q] * e);
+                            if (d[q] != 0.0f) te = fminf(te, (plane - o[q]) * invd[q]);
+                        }
+                        const float kf = floorf((te - t0) * rstep) - 1.0f;
+                        k = (kf > (float)(k + 1)) ? (int)fminf(kf, 2.0e9f) : k + 1;
+                        G.cidx = -1;
+                        jumped = true;
+                    }
+                    continue;
+                }
+                const DevCell &cell = table[cidx];
+                const int kind = cell.kind;
+                if (mip && skip && (kind != kBrickMissing || missing == 0)) {
+                    // no sample of this cell can raise the group's running maxima
+                    bool below = true;
+#pragma unroll
+                    for (int c = 0; c < C; c++)
+                        if (!kXf || c == gi) below = below && cell.hi[c] <= mx[c];
+                    if (below) {
+                        G.draw = kDrawNone;
+                        continue;
+                    }
+                }
+                G.sscale = scaleL;
+                G.base = nullptr;
+                if (kind == kBrick) {
+                    if (flags) flags[cidx] = 1;
+                    G.draw = kDrawBrick;
+                } else {
+                    G.draw = kDrawAvg;
+                    if (kind == kBrickMissing) {
+                        if (flags) flags[cidx] = 2;
+                        if (missing == 2) {
+                            G.draw = kDrawWait;
+                        } else if (missing == 1) {
+                            // the resident brick of the first of the two coarser levels;
+                            // missing ones among them are requested as well
+                            for (int l = L + 1; l <= min(L + 2, g.N); l++) {
+                                const int ci = cell_index(l, v);
+                                const int2 ks = *(const int2 *)&table[ci].kind;
+                                if (ks.x == kBrick && G.draw == kDrawAvg) {
+                                    if (flags) flags[ci] = 1;
+                                    G.draw = kDrawBrick;
+                                    G.sscale = __builtin_ldexpf(1.0f, -l);
+                                    const int e = g.M << l;
+                                    for (int q = 0; q < 3; q++)
+                                        G.sb[q] = (float)((v[q] / e) * g.M) - 0.5f;
+                                    G.base = pool + (uint64_t)ks.y * brick_bytes;
+                                } else if (ks.x == kBrickMissing && flags) {
+                                    flags[ci] = 2;
+                                }
+                            }
+                        }
+                    }
+                    if (G.draw == kDrawAvg)
+#pragma unroll
+                        for (int c = 0; c < C; c++) G.avg[c] = cell.avg[c];
+                }
+                if (G.draw == kDrawBrick && !G.base) {
+                    const int e = g.M << L;
+                    for (int q = 0; q < 3; q++) G.sb[q] = (float)((v[q] / e) * g.M) - 0.5f;
+                    G.base = pool + (uint64_t)cell.slot * brick_bytes;
+                }
+            }
+        }
+        if (jumped) continue;
+        bool wait = false;
+#pragma unroll
+        for (int gi = 0; gi < NG; gi++) wait = wait || grp[gi].draw == kDrawWait;
+        if (wait) {
+            waited = true;
+            break;
+        }
+        // samples, one group at a time
+        float s[C];
+        bool on[C];
+#pragma unroll
+        for (int gi = 0; gi < NG; gi++) {
+            const LookupGroup<C> &G = grp[gi];
+            const int c_lo = kXf ? gi : 0, c_hi = kXf ? gi + 1 : C;
+            for (int c = c_lo; c < c_hi; c++) on[c] = G.draw != kDrawNone;
+            if (G.draw == kDrawAvg) {
+                for (int c = c_lo; c < c_hi; c++) s[c] = G.avg[c];
+            } else if (G.draw == kDrawBrick) {
+                any_brick = true;
+                float pg[3];
+                if constexpr (kXf) {
+#pragma unroll
+                    for (int a = 0; a < 3; a++) {
+                        const float *m = V.xform[gi][a];
+                        const float s0 = m[0] * p[0];
+                        const float s1 = m[1] * p[1];
+                        const float s2 = m[2] * p[2];
+                        const float u = s0 + s1;
+                        const float w = u + s2;
+                        pg[a] = w + m[3];
+                    }
+                } else {
+#pragma unroll
+                    for (int a = 0; a < 3; a++) pg[a] = p[a];
+                }
+                float f[3];
+                int ii[3];
+#pragma unroll
+                for (int q = 0; q < 3; q++) {
+                    const float lq = __builtin_fmaf(pg[q], G.sscale, -G.sb[q]);
+                    f[q] = __builtin_amdgcn_fractf(lq);
+                    ii[q] = (int)__builtin_amdgcn_fmed3f(lq, 0.0f, imax);
+                }
+                const int64_t v0 = ((int64_t)(ii[2] * S + ii[1]) * S + ii[0]) * 4;
+                const int64_t dy = (int64_t)S * 4, dz = (int64_t)S * S * 4;
+                const T *b0 = (const T *)G.base;
+                const int64_t off[8] = {v0, v0 + 4, v0 + dy, v0 + dy + 4,
+                                        v0 + dz, v0 + dz + 4, v0 + dz + dy, v0 + dz + dy + 4};
+                for (int c = c_lo; c < c_hi; c++) {
+                    float w[8];
+#pragma unroll
+                    for (int q = 0; q < 8; q++) w[q] = (float)b0[off[q] + c];
+                    const float c00 = lerpf(w[0], w[1], f[0]);
+                    const float c10 = lerpf(w[2], w[3], f[0]);
+                    const float c01 = lerpf(w[4], w[5], f[0]);
+                    const float c11 = lerpf(w[6], w[7], f[0]);
+                    s[c] = lerpf(lerpf(c00, c10, f[1]), lerpf(c01, c11, f[1]), f[2]);
+                }
+            }
+        }
+        if constexpr (kCount) {
+            composited++;
+            if (any_brick) trilinear++;
+        }
+        if (mip) {
+#pragma unroll
+            for (int c = 0; c < C; c++)
+                if (on[c] && s[c] > mx[c]) {
+                    mx[c] = s[c];
+                    kmx[c] = k;
+                }
+        } else {
+#pragma unroll
+            for (int c = 0; c < C; c++) {
+                if (!on[c]) continue;   // zero opacity: compositing would change nothing
+                const Classified q = classify(s[c], ulo[c], usc[c], tb.lut[c]);
+                const float wgt = Tr * __builtin_fmaf(q.fr, q.de.w, q.e0.w);
+                Cr = __builtin_fmaf(wgt, __builtin_fmaf(q.fr, q.de.x, q.e0.x), Cr);
+                Cg = __builtin_fmaf(wgt, __builtin_fmaf(q.fr, q.de.y, q.e0.y), Cg);
+                Cb = __builtin_fmaf(wgt, __builtin_fmaf(q.fr, q.de.z, q.e0.z), Cb);
+                Tr = Tr - wgt;
+            }
+            if (Tr <= ert_T) {
+                k++;
+                break;   // early ray termination after this position
+            }
+        }
+        k++;
+    }
+
+    if (inside && !done_before) {
+        float res[4];
+        if (mip) {
+            float a4[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int c = 0; c < C; c++) a4[c] = mx[c];
+            for (int q = 0; q < 4; q++) res[q] = a4[q];
+        } else {
+            res[0] = Cr;
+            res[1] = Cg;
+            res[2] = Cb;
+            res[3] = waited ? Tr : 1.0f - Tr;   // a waiting ray keeps its transmittance exactly
+        }
+        if (rst) {
+            RefineState st;
+            for (int q = 0; q < 4; q++) st.acc[q] = res[q];
+            st.k = k;
+            st.status = waited ? 2 : (ray.hit ? 1 : 3);
+            st.pad[0] = st.pad[1] = 0;
+            *rst = st;
+        } else {
+            if (mip && ray.hit) {
+                Tr = 1.0f;
+#pragma unroll
+                for (int c = 0; c < C; c++) {
+                    const Classified q = classify(mx[c], ulo[c], usc[c], tb.lut[c]);
+                    const float wgt = Tr * __builtin_fmaf(q.fr, q.de.w, q.e0.w);
+                    Cr = __builtin_fmaf(wgt, __builtin_fmaf(q.fr, q.de.x, q.e0.x), Cr);
+                    Cg = __builtin_fmaf(wgt, __builtin_fmaf(q.fr, q.de.y, q.e0.y), Cg);
+                    Cb = __builtin_fmaf(wgt, __builtin_fmaf(q.fr, q.de.z, q.e0.z), Cb);
+                    Tr = Tr - wgt;
+                }
+                *(float4 *)(V.image + pix * 4) = make_float4(Cr, Cg, Cb, 1.0f - Tr);
+            } else if (mip) {
+                *(float4 *)(V.image + pix * 4) = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            } else {
+                *(float4 *)(V.image + pix * 4) = make_float4(Cr, Cg, Cb, 1.0f - Tr);
+            }
+            if (mip && V.amax) {
+                int a4[4] = {-1, -1, -1, -1};
+#pragma unroll
+                for (int c = 0; c < C; c++) a4[c] = kmx[c];
+                *(int4 *)(V.amax + pix * 4) = make_int4(a4[0], a4[1], a4[2], a4[3]);
+            }
+        }
+    }
+    if (missing == 2) {
+        const unsigned long long b = __ballot(waited);
+        if (lane == 0 && b) atomicAdd(V.rwait, (int)__popcll(b));
+    }
+    if (kCount && counters) {
+        unsigned long long r = (ray.hit && inside && first_pass) ? 1ull : 0ull,
+                           nn = (inside && first_pass) ? (unsigned long long)nominal : 0ull,
+                           cc = (unsigned long long)composited, tt = (unsigned long long)trilinear;
+        for (int off = 32; off > 0; off >>= 1) {
+            r += __shfl_xor(r, off, 64);
+            nn += __shfl_xor(nn, off, 64);
+            cc += __shfl_xor(cc, off, 64);
+            tt += __shfl_xor(tt, off, 64);
+        }
+        if (lane == 0) {
+            RenderCounters *cs = counters + (blockIdx.x & (kCounterSlots - 1));
+            atomicAdd(&cs->rays, r);
+            atomicAdd(&cs->nominal, nn);
+            atomicAdd(&cs->composited, cc);
+            atomicAdd(&cs->trilinear, tt);
+        }
+    }
+}
+
+template <typename T, int C, bool kLdsMask>
+__global__ void __launch_bounds__(kThreads)
+k_render_general(VolGeom g, const DevCell *__restrict__ table, const uint8_t *__restrict__ pool,
+                 uint64_t brick_bytes, const DevView *__restrict__ views, int n_views,
+                 int item_base, RenderCounters *counters, uint8_t *flags, int mask_lds)
+{
+    __shared__ LutTable<C> tb;
+    const WgItem it = item_of(views, n_views, item_base + (int)blockIdx.x);
+    const bool xf = views[it.view].xform_on != 0;
+    if (counters) {
+        if (xf)
+            render_general_body<T, C, true, kLdsMask, true>(g, table, pool, brick_bytes, views, it,
+                                                            counters, flags, tb, mask_lds);
+        else
+            render_general_body<T, C, false, kLdsMask, true>(g, table, pool, brick_bytes, views,
+                                                             it, counters, flags, tb, mask_lds);
+    } else {
+        if (xf)
+            render_general_body<T, C, true, kLdsMask, false>(g, table, pool, brick_bytes, views,
+                                                             it, counters, flags, tb, mask_lds);
+        else
+            render_general_body<T, C, false, kLdsMask, false>(g, table, pool, brick_bytes, views,
+                                                              it, counters, flags, tb, mask_lds);
+    }
 }
 
 // Front-to-back composite of the depth segments: C = C_0 + T_0 (C_1 + T_1 (...)),
 // T = T_0 T_1 ..., written as premultiplied (C, 1 - T) to the pixels of the rendered tiles.
+// MIP views: the segments' per-channel maxima are combined by max and then classified and
+// composited in channel order (-inf marks a ray that misses the volume: the pixel is 0).
+template <int C>
 __global__ void __launch_bounds__(256)
 k_combine(const DevView *__restrict__ views, const int32_t *__restrict__ split_views)
 {
     const DevView &V = views[split_views[blockIdx.y]];
     const int64_t npix = (int64_t)V.width * V.height;
+    const bool mip = V.mode == 1;
+    const LutTable<C> *tab = (const LutTable<C> *)V.tables;
     for (int64_t pix = (int64_t)blockIdx.x * 256 + threadIdx.x; pix < npix;
          pix += (int64_t)gridDim.x * 256) {
         const int px = (int)(pix % V.width), py = (int)(pix / V.width);
@@ -509,6 +1035,33 @@ k_combine(const DevView *__restrict__ views, const int32_t *__restrict__ split_v
         for (int sg = 0; sg < kMaxSplit; sg++)
             if (sg < V.nsplit) q[sg] = *(const float4 *)(V.part + ((int64_t)sg * npix + pix) * 4);
         float4 acc = q[0];
+        if (mip) {
+#pragma unroll
+            for (int sg = 1; sg < kMaxSplit; sg++) {
+                if (sg < V.nsplit) {
+                    acc.x = fmaxf(acc.x, q[sg].x);
+                    acc.y = fmaxf(acc.y, q[sg].y);
+                    acc.z = fmaxf(acc.z, q[sg].z);
+                    acc.w = fmaxf(acc.w, q[sg].w);
+                }
+            }
+            float Cr = 0.0f, Cg = 0.0f, Cb = 0.0f, Tr = 1.0f;
+            if (acc.x > -INFINITY) {
+                const float m4[4] = {acc.x, acc.y, acc.z, acc.w};
+#pragma unroll
+                for (int c = 0; c < C; c++) {
+                    const float usc = V.uscale[c], ub = -V.ulo[c] * usc;
+                    const Classified cq = classify(m4[c], ub, usc, tab->lut[c]);
+                    const float wgt = Tr * __builtin_fmaf(cq.fr, cq.de.w, cq.e0.w);
+                    Cr = __builtin_fmaf(wgt, __builtin_fmaf(cq.fr, cq.de.x, cq.e0.x), Cr);
+                    Cg = __builtin_fmaf(wgt, __builtin_fmaf(cq.fr, cq.de.y, cq.e0.y), Cg);
+                    Cb = __builtin_fmaf(wgt, __builtin_fmaf(cq.fr, cq.de.z, cq.e0.z), Cb);
+                    Tr = Tr - wgt;
+                }
+            }
+            *(float4 *)(V.image + pix * 4) = make_float4(Cr, Cg, Cb, 1.0f - Tr);
+            continue;
+        }
         float T = acc.w;
 #pragma unroll
         for (int sg = 1; sg < kMaxSplit; sg++) {
@@ -520,6 +1073,46 @@ k_combine(const DevView *__restrict__ views, const int32_t *__restrict__ split_v
             }
         }
         *(float4 *)(V.image + pix * 4) = make_float4(acc.x, acc.y, acc.z, 1.0f - T);
+    }
+}
+
+// Refinement views whose rays all finished in this launch (no ray waited): the image takes
+// the states' results -- DVR the premultiplied colour and opacity, MIP the classified maxima
+// composited in channel order; rays that miss the volume give 0.
+template <int C>
+__global__ void __launch_bounds__(256)
+k_refine_finish(const DevView *__restrict__ views, const int32_t *__restrict__ refine_views)
+{
+    const DevView &V = views[refine_views[blockIdx.y]];
+    if (*V.rwait != 0) return;   // the previous image stays until every ray has finished
+    const int64_t npix = (int64_t)V.width * V.height;
+    const LutTable<C> *tab = (const LutTable<C> *)V.tables;
+    for (int64_t pix = (int64_t)blockIdx.x * 256 + threadIdx.x; pix < npix;
+         pix += (int64_t)gridDim.x * 256) {
+        const int px = (int)(pix % V.width), py = (int)(pix / V.width);
+        const int tile = (py >> 3) * V.tiles_x + (px >> 3);
+        if (tile < V.tile_begin || tile >= V.tile_end) continue;
+        const RefineState st = V.rstate[pix];
+        float4 out = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        if (st.status == 1) {
+            if (V.mode == 1) {
+                float Cr = 0.0f, Cg = 0.0f, Cb = 0.0f, Tr = 1.0f;
+#pragma unroll
+                for (int c = 0; c < C; c++) {
+                    const float usc = V.uscale[c], ub = -V.ulo[c] * usc;
+                    const Classified cq = classify(st.acc[c], ub, usc, tab->lut[c]);
+                    const float wgt = Tr * __builtin_fmaf(cq.fr, cq.de.w, cq.e0.w);
+                    Cr = __builtin_fmaf(wgt, __builtin_fmaf(cq.fr, cq.de.x, cq.e0.x), Cr);
+                    Cg = __builtin_fmaf(wgt, __builtin_fmaf(cq.fr, cq.de.y, cq.e0.y), Cg);
+                    Cb = __builtin_fmaf(wgt, __builtin_fmaf(cq.fr, cq.de.z, cq.e0.z), Cb);
+                    Tr = Tr - wgt;
+                }
+                out = make_float4(Cr, Cg, Cb, 1.0f - Tr);
+            } else {
+                out = make_float4(st.acc[0], st.acc[1], st.acc[2], st.acc[3]);
+            }
+        }
+        *(float4 *)(V.image + pix * 4) = out;
     }
 }
 
@@ -639,13 +1232,20 @@ __global__ void __launch_bounds__(256) k_view_prep(VolGeom g, const DevView *__r
 }
 
 // Transparency of every node-table cell for every view that skips: workgroup b of a view sets
-// bits 256 b ... 256 b + 255 of V.tmask, bit i when cell i's value range classifies to zero
-// opacity in every channel (cell_transparent with the view's opacity prefix counts from
-// V.tables), one 64-bit ballot per wave.  Reads the current node table: after the last upload
-// and after k_view_prep.
+// bits 256 b ... 256 b + 255 of V.tmask, one 64-bit ballot per wave.  Bit i is set when no
+// sample drawn inside cell i can contribute:
+//  - DVR: the cell's value range classifies to zero opacity in every channel (cell_transparent
+//    with the view's opacity prefix counts from V.tables);
+//  - MIP: the cell's upper bound is at most the window's low end in every channel (no sample
+//    can raise a running maximum, which starts there);
+//  - full-frame fallback views take the range of the cell's ancestor two levels up (or the
+//    root): a missing brick is drawn from a coarser brick whose values that ancestor's range
+//    covers, while its own range need not.
+// Reads the current node table: after the last upload and after k_view_prep.
 template <int C>
 __global__ void __launch_bounds__(256)
-k_view_mask(const DevView *__restrict__ views, const DevCell *__restrict__ table, int64_t n_cells)
+k_view_mask(VolGeom g, const DevView *__restrict__ views, const DevCell *__restrict__ table,
+            int64_t n_cells)
 {
     const DevView &V = views[blockIdx.y];
     if (!V.tmask) return;
@@ -660,7 +1260,31 @@ k_view_mask(const DevView *__restrict__ views, const DevCell *__restrict__ table
         ulo[c] = -V.ulo[c] * usc[c];
     }
     const int64_t cell = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const bool t = cell < n_cells && cell_transparent<C>(table[cell], ulo, usc, pref);
+    bool t = false;
+    if (cell < n_cells) {
+        int64_t src = cell;
+        if (V.missing == 1) {
+            int lev = 0;
+            while (lev < g.N && cell >= g.cell_off[lev + 1]) lev++;
+            const int G = g.grid[lev];
+            const int64_t li = cell - g.cell_off[lev];
+            int x = (int)(li % G), y = (int)((li / G) % G), z = (int)(li / ((int64_t)G * G));
+            const int up = min(lev + 2, g.N);
+            x >>= (up - lev);
+            y >>= (up - lev);
+            z >>= (up - lev);
+            const int Gu = g.grid[up];
+            src = g.cell_off[up] + ((int64_t)z * Gu + y) * Gu + x;
+        }
+        const DevCell &dc = table[src];
+        if (V.mode == 1) {
+            t = true;
+#pragma unroll
+            for (int c = 0; c < C; c++) t = t && dc.hi[c] <= V.ulo[c];
+        } else {
+            t = cell_transparent<C>(dc, ulo, usc, pref);
+        }
+    }
     const unsigned long long b = __ballot(t);
     const int64_t first = cell & ~(int64_t)63;   // first cell of this wave
     if ((threadIdx.x & 63) == 0 && first < n_cells) {
@@ -670,44 +1294,59 @@ k_view_mask(const DevView *__restrict__ views, const DevCell *__restrict__ table
 }
 
 template <typename T, int C>
-void launch_c(const dim3 &grid, const dim3 &block, hipStream_t s, const VolGeom &g,
-              const DevCell *table, const uint8_t *p, uint64_t brick_bytes, const DevView *views,
-              int n_views, RenderCounters *counters, uint8_t *flags)
+void launch_c(hipStream_t s, const VolGeom &g, const DevCell *table, const uint8_t *p,
+              uint64_t brick_bytes, const DevView *views, int n_views, const int32_t *class_items,
+              RenderCounters *counters, uint8_t *flags)
 {
     // masks of up to 1024 words (32768 cells: trees of up to five levels) go to LDS
     constexpr int64_t kMaskLdsWords = 1024;
     const int64_t words = view_mask_words((int64_t)g.cell_off[g.N] + 1);
     const int mask_lds = words <= kMaskLdsWords ? (int)words : 0;
     const size_t shm = (size_t)mask_lds * 4;
-    if constexpr (sizeof(T) == 2) {
-        if (mask_lds)
-            hipLaunchKernelGGL((k_render_u16<C, true>), grid, block, shm, s, g, table, p,
-                               brick_bytes, views, n_views, counters, flags, mask_lds);
-        else
-            hipLaunchKernelGGL((k_render_u16<C, false>), grid, block, 0, s, g, table, p,
-                               brick_bytes, views, n_views, counters, flags, 0);
-    } else {
-        if (mask_lds)
-            hipLaunchKernelGGL((k_render_f32<C, true>), grid, block, shm, s, g, table, p,
-                               brick_bytes, views, n_views, counters, flags, mask_lds);
-        else
-            hipLaunchKernelGGL((k_render_f32<C, false>), grid, block, 0, s, g, table, p,
-                               brick_bytes, views, n_views, counters, flags, 0);
+    const dim3 block(kThreads);
+    for (int cls = 0; cls < kNumClasses; cls++) {
+        const int base = class_items[cls], n = class_items[cls + 1] - base;
+        if (n <= 0) continue;
+        const dim3 grid((unsigned)n);
+#define OCTRC_LAUNCH(KERNEL, LDS)                                                              \
+    hipLaunchKernelGGL(KERNEL, grid, block, (LDS) ? shm : 0, s, g, table, p, brick_bytes, views, \
+                       n_views, base, counters, flags, (LDS) ? mask_lds : 0)
+        if (cls == kClassGeneral) {
+            if (mask_lds) OCTRC_LAUNCH((k_render_general<T, C, true>), true);
+            else OCTRC_LAUNCH((k_render_general<T, C, false>), false);
+        } else if constexpr (sizeof(T) == 2) {
+            if (cls == kClassMip) {
+                if (mask_lds) OCTRC_LAUNCH((k_render_u16<C, true, true>), true);
+                else OCTRC_LAUNCH((k_render_u16<C, false, true>), false);
+            } else {
+                if (mask_lds) OCTRC_LAUNCH((k_render_u16<C, true, false>), true);
+                else OCTRC_LAUNCH((k_render_u16<C, false, false>), false);
+            }
+        } else {
+            if (cls == kClassMip) {
+                if (mask_lds) OCTRC_LAUNCH((k_render_f32<C, true, true>), true);
+                else OCTRC_LAUNCH((k_render_f32<C, false, true>), false);
+            } else {
+                if (mask_lds) OCTRC_LAUNCH((k_render_f32<C, true, false>), true);
+                else OCTRC_LAUNCH((k_render_f32<C, false, false>), false);
+            }
+        }
+#undef OCTRC_LAUNCH
     }
 }
 
 template <typename T>
 hipError_t launch_typed(const VolGeom &g, const DevCell *table, const void *pool,
-                        uint64_t brick_bytes, const DevView *views, int n_views, int n_items,
-                        RenderCounters *counters, uint8_t *flags, hipStream_t s)
+                        uint64_t brick_bytes, const DevView *views, int n_views,
+                        const int32_t *class_items, RenderCounters *counters, uint8_t *flags,
+                        hipStream_t s)
 {
-    const dim3 grid(n_items), block(kThreads);
     const uint8_t *p = (const uint8_t *)pool;
     switch (g.C) {
-    case 1: launch_c<T, 1>(grid, block, s, g, table, p, brick_bytes, views, n_views, counters, flags); break;
-    case 2: launch_c<T, 2>(grid, block, s, g, table, p, brick_bytes, views, n_views, counters, flags); break;
-    case 3: launch_c<T, 3>(grid, block, s, g, table, p, brick_bytes, views, n_views, counters, flags); break;
-    default: launch_c<T, 4>(grid, block, s, g, table, p, brick_bytes, views, n_views, counters, flags); break;
+    case 1: launch_c<T, 1>(s, g, table, p, brick_bytes, views, n_views, class_items, counters, flags); break;
+    case 2: launch_c<T, 2>(s, g, table, p, brick_bytes, views, n_views, class_items, counters, flags); break;
+    case 3: launch_c<T, 3>(s, g, table, p, brick_bytes, views, n_views, class_items, counters, flags); break;
+    default: launch_c<T, 4>(s, g, table, p, brick_bytes, views, n_views, class_items, counters, flags); break;
     }
     return hipGetLastError();
 }
@@ -737,39 +1376,60 @@ hipError_t launch_view_prep(const VolGeom &g, const DevView *views, int n_views,
     return hipGetLastError();
 }
 
-hipError_t launch_view_mask(const DevView *views, int n_views, int C, const DevCell *table,
-                            int64_t n_cells, hipStream_t s)
+hipError_t launch_view_mask(const VolGeom &g, const DevView *views, int n_views,
+                            const DevCell *table, int64_t n_cells, hipStream_t s)
 {
     if (n_views <= 0 || n_cells <= 0) return hipSuccess;
     const dim3 grid((unsigned)((n_cells + 255) / 256), (unsigned)n_views), block(256);
-    switch (C) {
-    case 1: hipLaunchKernelGGL(k_view_mask<1>, grid, block, 0, s, views, table, n_cells); break;
-    case 2: hipLaunchKernelGGL(k_view_mask<2>, grid, block, 0, s, views, table, n_cells); break;
-    case 3: hipLaunchKernelGGL(k_view_mask<3>, grid, block, 0, s, views, table, n_cells); break;
-    default: hipLaunchKernelGGL(k_view_mask<4>, grid, block, 0, s, views, table, n_cells); break;
+    switch (g.C) {
+    case 1: hipLaunchKernelGGL(k_view_mask<1>, grid, block, 0, s, g, views, table, n_cells); break;
+    case 2: hipLaunchKernelGGL(k_view_mask<2>, grid, block, 0, s, g, views, table, n_cells); break;
+    case 3: hipLaunchKernelGGL(k_view_mask<3>, grid, block, 0, s, g, views, table, n_cells); break;
+    default: hipLaunchKernelGGL(k_view_mask<4>, grid, block, 0, s, g, views, table, n_cells); break;
     }
     return hipGetLastError();
 }
 
-hipError_t launch_combine(const DevView *views, const int32_t *split_views, int n_split,
+hipError_t launch_combine(const DevView *views, const int32_t *split_views, int n_split, int C,
                           int64_t max_pixels, hipStream_t s)
 {
     if (n_split <= 0 || max_pixels <= 0) return hipSuccess;
     const unsigned gx = (unsigned)std::min<int64_t>((max_pixels + 255) / 256, 4096);
-    hipLaunchKernelGGL(k_combine, dim3(gx, (unsigned)n_split), dim3(256), 0, s, views,
-                       split_views);
+    const dim3 grid(gx, (unsigned)n_split), block(256);
+    switch (C) {
+    case 1: hipLaunchKernelGGL(k_combine<1>, grid, block, 0, s, views, split_views); break;
+    case 2: hipLaunchKernelGGL(k_combine<2>, grid, block, 0, s, views, split_views); break;
+    case 3: hipLaunchKernelGGL(k_combine<3>, grid, block, 0, s, views, split_views); break;
+    default: hipLaunchKernelGGL(k_combine<4>, grid, block, 0, s, views, split_views); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_refine_finish(const DevView *views, const int32_t *refine_views, int n_refine,
+                                int C, int64_t max_pixels, hipStream_t s)
+{
+    if (n_refine <= 0 || max_pixels <= 0) return hipSuccess;
+    const unsigned gx = (unsigned)std::min<int64_t>((max_pixels + 255) / 256, 4096);
+    const dim3 grid(gx, (unsigned)n_refine), block(256);
+    switch (C) {
+    case 1: hipLaunchKernelGGL(k_refine_finish<1>, grid, block, 0, s, views, refine_views); break;
+    case 2: hipLaunchKernelGGL(k_refine_finish<2>, grid, block, 0, s, views, refine_views); break;
+    case 3: hipLaunchKernelGGL(k_refine_finish<3>, grid, block, 0, s, views, refine_views); break;
+    default: hipLaunchKernelGGL(k_refine_finish<4>, grid, block, 0, s, views, refine_views); break;
+    }
     return hipGetLastError();
 }
 
 hipError_t launch_render(const VolGeom &g, const DevCell *table, const void *pool,
-                         uint64_t brick_bytes, const DevView *views, int n_views, int n_items,
-                         RenderCounters *counters, uint8_t *flags, hipStream_t s)
+                         uint64_t brick_bytes, const DevView *views, int n_views,
+                         const int32_t *class_items, RenderCounters *counters, uint8_t *flags,
+                         hipStream_t s)
 {
-    if (n_items == 0) return hipSuccess;
+    if (class_items[kNumClasses] == 0) return hipSuccess;
     if (g.dtype == 0)
-        return launch_typed<uint16_t>(g, table, pool, brick_bytes, views, n_views, n_items,
+        return launch_typed<uint16_t>(g, table, pool, brick_bytes, views, n_views, class_items,
                                       counters, flags, s);
-    return launch_typed<float>(g, table, pool, brick_bytes, views, n_views, n_items, counters,
+    return launch_typed<float>(g, table, pool, brick_bytes, views, n_views, class_items, counters,
                                flags, s);
 }
 

@@ -245,15 +245,20 @@ int wait_for_renders_before(oct_handle *h, hipStream_t s, int64_t v)
 
 // Bytes of render_views_noalloc's host records (and of the same prefix of its scratch) for
 // n views: the DevView records, the list of split views, the sample counters.
+// Host records of a launch: views | split list, refinement list, per-view refinement wait
+// counters | sample counters.
 struct RecordLayout {
     size_t v_bytes, sv_off, sv_bytes, c_off, c_bytes;
+    size_t rf_off, rw_off;   // offsets of the refinement list and wait counters
 };
-RecordLayout record_layout(size_t n_views, size_t n_split)
+RecordLayout record_layout(size_t n_views, size_t n_split, size_t n_refine)
 {
     RecordLayout l;
     l.v_bytes = n_views * sizeof(DevView);
     l.sv_off = (l.v_bytes + 255) & ~(size_t)255;
-    l.sv_bytes = n_split * sizeof(int32_t);
+    l.rf_off = l.sv_off + n_split * sizeof(int32_t);
+    l.rw_off = l.rf_off + n_refine * sizeof(int32_t);
+    l.sv_bytes = (n_split + n_refine + n_views) * sizeof(int32_t);
     l.c_off = (l.sv_off + l.sv_bytes + 255) & ~(size_t)255;
     l.c_bytes = kCounterSlots * sizeof(RenderCounters);
     return l;
@@ -261,7 +266,7 @@ RecordLayout record_layout(size_t n_views, size_t n_split)
 
 size_t noalloc_record_bytes()
 {
-    const RecordLayout l = record_layout(kNoAllocMaxViews, kNoAllocMaxViews);
+    const RecordLayout l = record_layout(kNoAllocMaxViews, kNoAllocMaxViews, kNoAllocMaxViews);
     return l.c_off + l.c_bytes;
 }
 
@@ -1195,9 +1200,25 @@ int brick_pool_upload(oct_handle *h, uint64_t byte_budget, void *stream, oct_upl
     return resident < bricks_total ? OCT_INCOMPLETE : OCT_OK;
 }
 
+// The render kernel a view runs in (views of one launch are grouped by class).
+static int32_t view_class(const oct_view &v)
+{
+    if (v.n_xform > 0 || v.missing != OCT_MISSING_AVG) return kClassGeneral;
+    return v.mode == OCT_MODE_MIP ? kClassMip : kClassDvr;
+}
+
+// Views whose adjoint render_views_backward computes (and whose forward may therefore fill a
+// checkpoint workspace): DVR without channel transforms, MIP with or without them, both with
+// missing bricks drawn as AVG.
+static bool view_differentiable(const oct_view &v)
+{
+    if (v.missing != OCT_MISSING_AVG) return false;
+    return v.mode == OCT_MODE_MIP || v.n_xform == 0;
+}
+
 // Checkpoint workspace: per view, [pixel][nseg] float32 transmittances then [pixel] int32
 // end positions; nseg covers the longest possible ray (the box diagonal) in 64-position
-// segments.
+// segments.  MIP views hold [pixel][4] int32 positions of the channel maxima instead.
 static int view_nseg(const oct_handle *h, const oct_view &v)
 {
     const double diag = std::sqrt((double)h->g.dims[0] * h->g.dims[0] +
@@ -1211,6 +1232,12 @@ static int view_nseg(const oct_handle *h, const oct_view &v)
 // agree on it: none with early termination, else the view's request or the automatic count.
 static int view_segments(const oct_handle *h, const oct_view &v)
 {
+    if (view_class(v) == kClassGeneral) return 1;
+    if (v.mode == OCT_MODE_MIP) {
+        // maxima combine by max; no early termination applies
+        if (v.depth_segments > 0) return std::min(v.depth_segments, kMaxSplit);
+        return auto_segments(h->g, v);
+    }
     if (!(v.ert_alpha >= 1.0f)) return 1;
     if (v.depth_segments > 0) return std::min(v.depth_segments, kMaxSplit);
     return auto_segments(h->g, v);
@@ -1228,10 +1255,17 @@ static size_t view_ckpt_part_offset(const oct_handle *h, const oct_view &v)
 static size_t view_ckpt_bytes(const oct_handle *h, const oct_view &v)
 {
     const size_t npix = (size_t)v.width * v.height;
+    if (v.mode == OCT_MODE_MIP) return (npix * 16 + 255) & ~(size_t)255;
     size_t b = view_ckpt_part_offset(h, v);
     const int S = view_segments(h, v);
     if (S > 1) b += npix * (size_t)S * 16;
     return (b + 255) & ~(size_t)255;
+}
+
+size_t render_refine_bytes(const oct_handle *h, const oct_view *view)
+{
+    if (!h || !view || view->width < 1 || view->height < 1) return 0;
+    return (size_t)view->width * view->height * sizeof(RefineState);
 }
 
 size_t render_ckpt_bytes(const oct_handle *h, int32_t n_views, const oct_view *views)
@@ -1258,8 +1292,20 @@ static int build_view(oct_handle *h, const oct_view &v, float *image, DevView &d
     if (!(v.ert_alpha > 0.0f)) return fail(h, OCT_EINVAL, "ert_alpha must be > 0");
     if (v.depth_segments < 0 || v.depth_segments > kMaxSplit)
         return fail(h, OCT_EINVAL, "depth_segments must be 0..16");
-    for (int i = 0; i < 2; i++)
-        if (v.reserved[i]) return fail(h, OCT_EINVAL, "reserved fields must be 0");
+    if (v.reserved) return fail(h, OCT_EINVAL, "reserved fields must be 0");
+    if (v.mode != OCT_MODE_DVR && v.mode != OCT_MODE_MIP)
+        return fail(h, OCT_EINVAL, "mode must be OCT_MODE_DVR or OCT_MODE_MIP");
+    if (v.missing < OCT_MISSING_AVG || v.missing > OCT_MISSING_REFINE)
+        return fail(h, OCT_EINVAL, "missing must be OCT_MISSING_AVG, _FALLBACK or _REFINE");
+    if ((v.missing == OCT_MISSING_REFINE) != (v.refine_state != nullptr))
+        return fail(h, OCT_EINVAL, "refine_state is required by, and only by, refinement views");
+    if (v.n_xform != 0 && v.n_xform != g.C)
+        return fail(h, OCT_EINVAL, "n_xform must be 0 or the channel count");
+    for (int c = 0; c < v.n_xform; c++)
+        for (int a = 0; a < 3; a++)
+            for (int q = 0; q < 4; q++)
+                if (!std::isfinite(v.xform[c][a][q]))
+                    return fail(h, OCT_EINVAL, "channel transforms must be finite");
     if (!image) return fail(h, OCT_EINVAL, "null image");
     for (int c = 0; c < g.C; c++) {
         if (!(v.window[c][1] > v.window[c][0])) return fail(h, OCT_EINVAL, "window hi must exceed lo");
@@ -1317,6 +1363,12 @@ static int build_view(oct_handle *h, const oct_view &v, float *image, DevView &d
     std::memcpy(dv.tf_pos, v.tf_pos, sizeof dv.tf_pos);
     std::memcpy(dv.tf_rgba, v.tf_rgba, sizeof dv.tf_rgba);
     dv.image = image;
+    dv.mode = v.mode;
+    dv.missing = v.missing;
+    dv.xform_on = v.n_xform > 0 ? 1 : 0;
+    if (dv.xform_on) std::memcpy(dv.xform, v.xform, sizeof dv.xform);
+    dv.rstate = (RefineState *)v.refine_state;
+    dv.vclass = view_class(v);
     return OCT_OK;
 }
 
@@ -1325,60 +1377,114 @@ struct LaunchPlan {
     int64_t n_items = 0;
     int64_t order_ints = 0;          // every view's tile-group order and length classes
     int64_t max_split_pixels = 0;
+    int64_t max_refine_pixels = 0;
     int n_split = 0;
+    int n_refine = 0;
     int n_skip = 0;
     size_t part_floats = 0;          // segment results of split views without checkpoints
+    int32_t class_items[kNumClasses + 1] = {0, 0, 0, 0};
 };
 
-// Fills dvs[0 .. n_views) and split[0 .. n_split) for one forward launch.  Views without
-// checkpoints are split into depth segments only when `split_ok`; their segment results go
-// at float offset part_at[i] of a buffer the caller assigns afterwards (dvs[i].part is left
-// NULL for them).  With checkpoints the segment results live in the workspace.
+// Fills dvs[0 .. n_views) -- the views grouped by kernel class, in the caller's order inside a
+// class (dvs[j].user_index is the caller's index) -- plus split[0 .. n_split) and
+// refine[0 .. n_refine) (record indices of split and refinement views) for one forward launch.
+// Views without checkpoints are split into depth segments only when `split_ok`; their segment
+// results go at float offset part_at[j] of a buffer the caller assigns afterwards (dvs[j].part
+// is left NULL for them).  With checkpoints the segment results live in the workspace, laid
+// out in the caller's view order.
 static int plan_launch(oct_handle *h, int32_t n_views, const oct_view *views,
                        float *const *images, void *ckpt_ws, bool split_ok, DevView *dvs,
-                       int32_t *split, size_t *part_at, LaunchPlan &pl)
+                       int32_t *split, int32_t *refine, size_t *part_at, LaunchPlan &pl)
 {
-    size_t ck_off = 0;
-    for (int i = 0; i < n_views; i++) {
-        int rc = build_view(h, views[i], images[i], dvs[i]);
-        if (rc) return rc;
-        const size_t npix = (size_t)views[i].width * views[i].height;
-        if (ckpt_ws) {
-            dvs[i].nseg = view_nseg(h, views[i]);
-            dvs[i].ckpt = (float *)((uint8_t *)ckpt_ws + ck_off);
-            dvs[i].nend = (int32_t *)((uint8_t *)ckpt_ws + ck_off + npix * dvs[i].nseg * 4);
-            ck_off += view_ckpt_bytes(h, views[i]);
-        }
-        const int tiles = dvs[i].tiles_x * ((views[i].height + OCT_TILE - 1) / OCT_TILE);
-        const int tb = std::min(views[i].tile_begin, tiles);
-        const int te = views[i].tile_count < 0 ? tiles : std::min(tiles, tb + views[i].tile_count);
-        // early termination makes a later segment depend on the earlier ones: unsplit then
-        const int nsplit = te > tb && (ckpt_ws || split_ok) ? view_segments(h, views[i]) : 1;
-        dvs[i].nsplit = nsplit;
-        dvs[i].tile_begin = tb;
-        dvs[i].tile_end = te;
-        if (nsplit > 1) {
+    // workspace offsets in the caller's order
+    std::vector<size_t> ck_at((size_t)n_views, 0);
+    {
+        size_t ck_off = 0;
+        for (int i = 0; i < n_views; i++) {
+            ck_at[i] = ck_off;
             if (ckpt_ws) {
-                // the adjoint reads the segment partials back: they live in the workspace
-                dvs[i].part = (float *)((uint8_t *)ckpt_ws + ck_off - view_ckpt_bytes(h, views[i]) +
-                                        view_ckpt_part_offset(h, views[i]));
-            } else {
-                part_at[i] = pl.part_floats;
-                pl.part_floats += (size_t)nsplit * npix * 4;
+                if (!view_differentiable(views[i]))
+                    return fail(h, OCT_EINVAL, "a checkpoint workspace needs views the adjoint "
+                                               "supports (no refinement or full-frame fallback, "
+                                               "no channel transforms in DVR)");
+                if (views[i].width < 1 || views[i].height < 1 || !(views[i].step > 0.0f))
+                    return fail(h, OCT_EINVAL, "view size out of range");
+                ck_off += view_ckpt_bytes(h, views[i]);
             }
-            split[pl.n_split++] = i;
-            pl.max_split_pixels = std::max<int64_t>(pl.max_split_pixels, (int64_t)npix);
         }
-        // the view's work items (the kernel derives each one from its index, item_of)
-        const int groups = (te - tb + kRenderTilesPerWg - 1) / kRenderTilesPerWg;
-        dvs[i].item_begin = (int32_t)pl.n_items;
-        dvs[i].groups = groups;
-        pl.n_items += (int64_t)groups * nsplit;
-        pl.order_ints += 2 * (int64_t)groups;
-        pl.n_skip += dvs[i].skip ? 1 : 0;
     }
+    int j = 0;
+    for (int cls = 0; cls < kNumClasses; cls++) {
+        pl.class_items[cls] = (int32_t)pl.n_items;
+        for (int i = 0; i < n_views; i++) {
+            if (view_class(views[i]) != cls) continue;
+            DevView &dv = dvs[j];
+            int rc = build_view(h, views[i], images[i], dv);
+            if (rc) return rc;
+            dv.user_index = i;
+            const size_t npix = (size_t)views[i].width * views[i].height;
+            uint8_t *ws = ckpt_ws ? (uint8_t *)ckpt_ws + ck_at[i] : nullptr;
+            if (ws && views[i].mode == OCT_MODE_MIP) {
+                dv.amax = (int32_t *)ws;
+            } else if (ws) {
+                dv.nseg = view_nseg(h, views[i]);
+                dv.ckpt = (float *)ws;
+                dv.nend = (int32_t *)(ws + npix * dv.nseg * 4);
+            }
+            const int tiles = dv.tiles_x * ((views[i].height + OCT_TILE - 1) / OCT_TILE);
+            const int tb = std::min(views[i].tile_begin, tiles);
+            const int te = views[i].tile_count < 0 ? tiles : std::min(tiles, tb + views[i].tile_count);
+            // early termination makes a later segment depend on the earlier ones: unsplit then;
+            // a MIP adjoint needs each ray's positions of the maxima from one pass
+            const bool mip_ck = ws && views[i].mode == OCT_MODE_MIP;
+            const int nsplit = te > tb && !mip_ck && (ws || split_ok) ? view_segments(h, views[i]) : 1;
+            dv.nsplit = nsplit;
+            dv.tile_begin = tb;
+            dv.tile_end = te;
+            if (nsplit > 1) {
+                if (ws) {
+                    // the adjoint reads the segment partials back: they live in the workspace
+                    dv.part = (float *)(ws + view_ckpt_part_offset(h, views[i]));
+                } else {
+                    part_at[j] = pl.part_floats;
+                    pl.part_floats += (size_t)nsplit * npix * 4;
+                }
+                split[pl.n_split++] = j;
+                pl.max_split_pixels = std::max<int64_t>(pl.max_split_pixels, (int64_t)npix);
+            }
+            if (views[i].missing == OCT_MISSING_REFINE) {
+                refine[pl.n_refine++] = j;
+                pl.max_refine_pixels = std::max<int64_t>(pl.max_refine_pixels, (int64_t)npix);
+            }
+            // the view's work items (the kernel derives each one from its index, item_of)
+            const int groups = (te - tb + kRenderTilesPerWg - 1) / kRenderTilesPerWg;
+            dv.item_begin = (int32_t)pl.n_items;
+            dv.groups = groups;
+            pl.n_items += (int64_t)groups * nsplit;
+            pl.order_ints += 2 * (int64_t)groups;
+            pl.n_skip += dv.skip ? 1 : 0;
+            j++;
+        }
+    }
+    pl.class_items[kNumClasses] = (int32_t)pl.n_items;
     if (pl.n_items > INT32_MAX) return fail(h, OCT_EINVAL, "too many tiles in one launch");
     return OCT_OK;
+}
+
+// Sums the sample counters (and the refinement views' waiting rays) read back to the host.
+static void collect_stats(const uint8_t *hp, const RecordLayout &l, int n_views,
+                          oct_render_stats *out)
+{
+    const RenderCounters *rcnt = (const RenderCounters *)(hp + l.c_off);
+    *out = oct_render_stats{};
+    for (int i = 0; i < kCounterSlots; i++) {
+        out->rays += rcnt[i].rays;
+        out->positions_nominal += rcnt[i].nominal;
+        out->positions_composited += rcnt[i].composited;
+        out->positions_trilinear += rcnt[i].trilinear;
+    }
+    const int32_t *rw = (const int32_t *)(hp + l.rw_off);
+    for (int i = 0; i < n_views; i++) out->rays_waiting += (uint64_t)rw[i];
 }
 
 int render_views(oct_handle *h, int32_t n_views, const oct_view *views, float *const *images,
@@ -1389,29 +1495,22 @@ int render_views(oct_handle *h, int32_t n_views, const oct_view *views, float *c
     HIPCHK(h, hipSetDevice(h->device));
     hipStream_t s = (hipStream_t)stream;
     std::vector<DevView> dvs((size_t)n_views);
-    std::vector<int32_t> split_views((size_t)n_views);
+    std::vector<int32_t> split_views((size_t)n_views), refine_views((size_t)n_views);
     std::vector<size_t> part_at((size_t)n_views, 0);
     LaunchPlan pl;
     {
         int rc = plan_launch(h, n_views, views, images, ckpt_ws, true, dvs.data(), split_views.data(),
-                             part_at.data(), pl);
+                             refine_views.data(), part_at.data(), pl);
         if (rc) return rc;
     }
-    split_views.resize((size_t)pl.n_split);
-    const int64_t n_items = pl.n_items, order_ints = pl.order_ints;
-    const int64_t max_split_pixels = pl.max_split_pixels;
-    const size_t part_floats = pl.part_floats;
-    const size_t v_bytes = dvs.size() * sizeof(DevView);
-    const size_t sv_off = (v_bytes + 255) & ~(size_t)255;
-    const size_t sv_bytes = split_views.size() * sizeof(int32_t);
-    const size_t c_off = (sv_off + sv_bytes + 255) & ~(size_t)255;
+    const RecordLayout l = record_layout((size_t)n_views, (size_t)pl.n_split, (size_t)pl.n_refine);
     RenderSlot &rs = h->rs[h->next_rs];
     h->next_rs = (h->next_rs + 1) % kRenderSlots;
-    const size_t c_bytes = kCounterSlots * sizeof(RenderCounters);
-    int rc = stage_reserve(h, rs.st, c_off + c_bytes);   // the slot is idle now
+    int rc = stage_reserve(h, rs.st, l.c_off + l.c_bytes);   // the slot is idle now
     rs.version = h->version;
     if (!rc) rc = collect_kernel_time(h, rs);
     if (rc) return rc;
+    const size_t part_floats = pl.part_floats;
     if (part_floats * sizeof(float) > rs.part_cap) {
         if (rs.part) HIPCHK(h, hipFree(rs.part));
         rs.part = nullptr;
@@ -1419,8 +1518,10 @@ int render_views(oct_handle *h, int32_t n_views, const oct_view *views, float *c
         HIPCHK(h, hipMalloc(&rs.part, part_floats * sizeof(float)));
         rs.part_cap = part_floats * sizeof(float);
     }
-    for (int32_t i : split_views)
-        if (!dvs[i].part) dvs[i].part = rs.part + part_at[i];
+    for (int k = 0; k < pl.n_split; k++) {
+        const int32_t j = split_views[k];
+        if (!dvs[j].part) dvs[j].part = rs.part + part_at[j];
+    }
     const size_t tbytes = view_tables_bytes(h->g.C);
     if ((size_t)n_views * tbytes > rs.tables_cap) {
         if (rs.tables) HIPCHK(h, hipFree(rs.tables));
@@ -1442,57 +1543,57 @@ int render_views(oct_handle *h, int32_t n_views, const oct_view *views, float *c
     for (int i = 0, j = 0; i < n_views; i++)
         dvs[i].tmask = dvs[i].skip ? rs.tmask + (size_t)(j++) * mwords : nullptr;
     uint8_t *hp = (uint8_t *)rs.st.host;
-    if ((size_t)order_ints * 4 > rs.gorder_cap) {
+    uint8_t *dp = (uint8_t *)rs.st.dev;
+    if ((size_t)pl.order_ints * 4 > rs.gorder_cap) {
         if (rs.gorder) HIPCHK(h, hipFree(rs.gorder));
         rs.gorder = nullptr;
         rs.gorder_cap = 0;
-        HIPCHK(h, hipMalloc((void **)&rs.gorder, (size_t)order_ints * 4));
-        rs.gorder_cap = (size_t)order_ints * 4;
+        HIPCHK(h, hipMalloc((void **)&rs.gorder, (size_t)pl.order_ints * 4));
+        rs.gorder_cap = (size_t)pl.order_ints * 4;
     }
     for (int i = 0, at = 0; i < n_views; i++) {
         dvs[i].group_order = rs.gorder + at;   // written by the set-up kernel
         at += 2 * dvs[i].groups;
+        dvs[i].rwait = (int32_t *)(dp + l.rw_off) + i;
     }
-    std::memcpy(hp, dvs.data(), v_bytes);
-    std::memcpy(hp + sv_off, split_views.data(), sv_bytes);
-    std::memset(hp + c_off, 0, c_bytes);
-    // preparation on the prep stream (it overlaps the renders issued before this one): views
-    // and split list (plus the zeroed sample counters when asked for), tables, group order
-    uint8_t *dp = (uint8_t *)rs.st.dev;
+    std::memcpy(hp, dvs.data(), l.v_bytes);
+    std::memcpy(hp + l.sv_off, split_views.data(), (size_t)pl.n_split * 4);
+    std::memcpy(hp + l.rf_off, refine_views.data(), (size_t)pl.n_refine * 4);
+    std::memset(hp + l.rw_off, 0, (size_t)n_views * 4);
+    std::memset(hp + l.c_off, 0, l.c_bytes);
+    // preparation on the prep stream (it overlaps the renders issued before this one): views,
+    // lists and zeroed wait counters (plus the zeroed sample counters when asked for), tables,
+    // group order
     if (!rs.prep) HIPCHK(h, hipEventCreateWithFlags(&rs.prep, hipEventDisableTiming));
-    HIPCHK(h, hipMemcpyAsync(rs.st.dev, hp, out ? c_off + c_bytes : sv_off + sv_bytes,
+    HIPCHK(h, hipMemcpyAsync(rs.st.dev, hp, out ? l.c_off + l.c_bytes : l.sv_off + l.sv_bytes,
                              hipMemcpyHostToDevice, h->prep));
     HIPCHK(h, launch_view_prep(h->g, (const DevView *)dp, n_views, h->prep));
     HIPCHK(h, hipEventRecord(rs.prep, h->prep));
     rc = wait_for(h, s, rs.prep);
     if (!rc) rc = wait_for(h, s, h->ev_upload);   // the node table and pool of the last upload
     if (rc) return rc;
-    if (n_skip) HIPCHK(h, launch_view_mask((const DevView *)dp, n_views, h->g.C, h->table, h->n_cells, s));
+    if (n_skip) HIPCHK(h, launch_view_mask(h->g, (const DevView *)dp, n_views, h->table, h->n_cells, s));
     if (h->ktime) {
         if (!rs.k0) HIPCHK(h, hipEventCreate(&rs.k0));
         if (!rs.k1) HIPCHK(h, hipEventCreate(&rs.k1));
         HIPCHK(h, hipEventRecord(rs.k0, s));
     }
     HIPCHK(h, launch_render(h->g, h->table, h->pool, h->brick_bytes, (const DevView *)dp,
-                            n_views, (int)n_items, out ? (RenderCounters *)(dp + c_off) : nullptr,
+                            n_views, pl.class_items, out ? (RenderCounters *)(dp + l.c_off) : nullptr,
                             h->capped ? h->flags : nullptr, s));
     if (h->ktime) {
         HIPCHK(h, hipEventRecord(rs.k1, s));
         rs.k_pending = true;
     }
-    HIPCHK(h, launch_combine((const DevView *)dp, (const int32_t *)(dp + sv_off),
-                             (int)split_views.size(), max_split_pixels, s));
+    HIPCHK(h, launch_combine((const DevView *)dp, (const int32_t *)(dp + l.sv_off), pl.n_split,
+                             h->g.C, pl.max_split_pixels, s));
+    HIPCHK(h, launch_refine_finish((const DevView *)dp, (const int32_t *)(dp + l.rf_off),
+                                   pl.n_refine, h->g.C, pl.max_refine_pixels, s));
     if (out) {
-        HIPCHK(h, hipMemcpyAsync(hp + c_off, dp + c_off, c_bytes, hipMemcpyDeviceToHost, s));
+        HIPCHK(h, hipMemcpyAsync(hp + l.sv_off, dp + l.sv_off, l.c_off + l.c_bytes - l.sv_off,
+                                 hipMemcpyDeviceToHost, s));
         HIPCHK(h, hipStreamSynchronize(s));
-        const RenderCounters *rcnt = (const RenderCounters *)(hp + c_off);
-        *out = oct_render_stats{};
-        for (int i = 0; i < kCounterSlots; i++) {
-            out->rays += rcnt[i].rays;
-            out->positions_nominal += rcnt[i].nominal;
-            out->positions_composited += rcnt[i].composited;
-            out->positions_trilinear += rcnt[i].trilinear;
-        }
+        collect_stats(hp, l, n_views, out);
     }
     HIPCHK(h, hipEventRecord(rs.st.ev, s));
     if (ckpt_ws) ckpt_log_put(h, ckpt_ws, n_views, views);
@@ -1513,13 +1614,12 @@ int render_views_noalloc(oct_handle *h, int32_t n_views, const oct_view *views,
     // the host records are reused: the previous call's copy of them must have finished
     HIPCHK(h, hipEventSynchronize(h->na_copy));
     uint8_t *hp = (uint8_t *)rs.st.host;
-    const RecordLayout cap = record_layout(kNoAllocMaxViews, kNoAllocMaxViews);
     DevView *dvs = (DevView *)hp;
-    int32_t *split = (int32_t *)(hp + cap.sv_off);   // moved behind the records below
+    int32_t split[kNoAllocMaxViews], refine[kNoAllocMaxViews];
     LaunchPlan pl;
-    int rc = plan_launch(h, n_views, views, images, ckpt_ws, false, dvs, split, nullptr, pl);
+    int rc = plan_launch(h, n_views, views, images, ckpt_ws, false, dvs, split, refine, nullptr, pl);
     if (rc) return rc;
-    const RecordLayout l = record_layout((size_t)n_views, (size_t)pl.n_split);
+    const RecordLayout l = record_layout((size_t)n_views, (size_t)pl.n_split, (size_t)pl.n_refine);
     // scratch: records | tables | masks | tile-group orders
     const size_t tbytes = view_tables_bytes(h->g.C);
     const int64_t mwords = view_mask_words(h->n_cells);
@@ -1537,9 +1637,12 @@ int render_views_noalloc(oct_handle *h, int32_t n_views, const oct_view *views,
         dvs[i].tables = dp + t_off + (size_t)i * tbytes;
         dvs[i].tmask = dvs[i].skip ? (uint32_t *)(dp + m_off) + (size_t)(j++) * mwords : nullptr;
         dvs[i].group_order = (int32_t *)(dp + g_off) + at;   // written by the set-up kernel
+        dvs[i].rwait = (int32_t *)(dp + l.rw_off) + i;
         at += 2 * dvs[i].groups;
     }
-    if (pl.n_split) std::memmove(hp + l.sv_off, split, l.sv_bytes);
+    std::memcpy(hp + l.sv_off, split, (size_t)pl.n_split * 4);
+    std::memcpy(hp + l.rf_off, refine, (size_t)pl.n_refine * 4);
+    std::memset(hp + l.rw_off, 0, (size_t)n_views * 4);
     std::memset(hp + l.c_off, 0, l.c_bytes);
     // the scratch is reused: this call's writes follow the previous call's launch; the node
     // table and pool are the last upload's
@@ -1554,23 +1657,19 @@ int render_views_noalloc(oct_handle *h, int32_t n_views, const oct_view *views,
     HIPCHK(h, hipEventRecord(h->na_copy, s));
     HIPCHK(h, launch_view_prep(h->g, (const DevView *)dp, n_views, s));
     if (pl.n_skip)
-        HIPCHK(h, launch_view_mask((const DevView *)dp, n_views, h->g.C, h->table, h->n_cells, s));
+        HIPCHK(h, launch_view_mask(h->g, (const DevView *)dp, n_views, h->table, h->n_cells, s));
     HIPCHK(h, launch_render(h->g, h->table, h->pool, h->brick_bytes, (const DevView *)dp, n_views,
-                            (int)pl.n_items, out ? (RenderCounters *)(dp + l.c_off) : nullptr,
+                            pl.class_items, out ? (RenderCounters *)(dp + l.c_off) : nullptr,
                             h->capped ? h->flags : nullptr, s));
     HIPCHK(h, launch_combine((const DevView *)dp, (const int32_t *)(dp + l.sv_off), pl.n_split,
-                             pl.max_split_pixels, s));
+                             h->g.C, pl.max_split_pixels, s));
+    HIPCHK(h, launch_refine_finish((const DevView *)dp, (const int32_t *)(dp + l.rf_off),
+                                   pl.n_refine, h->g.C, pl.max_refine_pixels, s));
     if (out) {
-        HIPCHK(h, hipMemcpyAsync(hp + l.c_off, dp + l.c_off, l.c_bytes, hipMemcpyDeviceToHost, s));
+        HIPCHK(h, hipMemcpyAsync(hp + l.sv_off, dp + l.sv_off, l.c_off + l.c_bytes - l.sv_off,
+                                 hipMemcpyDeviceToHost, s));
         HIPCHK(h, hipStreamSynchronize(s));
-        const RenderCounters *rcnt = (const RenderCounters *)(hp + l.c_off);
-        *out = oct_render_stats{};
-        for (int i = 0; i < kCounterSlots; i++) {
-            out->rays += rcnt[i].rays;
-            out->positions_nominal += rcnt[i].nominal;
-            out->positions_composited += rcnt[i].composited;
-            out->positions_trilinear += rcnt[i].trilinear;
-        }
+        collect_stats(hp, l, n_views, out);
     }
     HIPCHK(h, hipEventRecord(rs.st.ev, s));
     if (ckpt_ws) ckpt_log_put(h, ckpt_ws, n_views, views);
@@ -1598,6 +1697,10 @@ int render_views_backward(oct_handle *h, int32_t n_views, const oct_view *views,
         if (r->n_views != n_views || r->views_hash != views_hash(n_views, views))
             return fail(h, OCT_EINVAL, "the views differ from those of the forward render");
     }
+    for (int i = 0; i < n_views; i++)
+        if (!view_differentiable(views[i]))
+            return fail(h, OCT_EINVAL, "the adjoint covers DVR without channel transforms and MIP, "
+                                       "with missing bricks drawn as AVG");
     if (dL_dvoxels) {
         // voxel gradients flow through trilinear weights of level-0 bricks only
         for (int i = 0; i < n_views; i++)
@@ -1616,7 +1719,7 @@ int render_views_backward(oct_handle *h, int32_t n_views, const oct_view *views,
     HIPCHK(h, hipSetDevice(h->device));
     hipStream_t s = (hipStream_t)stream;
     std::vector<DevView> dvs((size_t)n_views);
-    std::vector<WgItem> items;
+    std::vector<WgItem> items, mip_items;
     size_t ck_off = 0;
     const size_t dlut_floats = (size_t)g.C * 256 * 4;
     for (int i = 0; i < n_views; i++) {
@@ -1625,6 +1728,23 @@ int render_views_backward(oct_handle *h, int32_t n_views, const oct_view *views,
         const size_t npix = (size_t)views[i].width * views[i].height;
         dvs[i].image = nullptr;
         dvs[i].dimg = dL_dimages[i];
+        dvs[i].user_index = i;
+        if (views[i].mode == OCT_MODE_MIP) {
+            // one lane per pixel through the samples at the recorded maxima
+            dvs[i].amax = (int32_t *)((uint8_t *)ckpt_ws + ck_off);
+            ck_off += view_ckpt_bytes(h, views[i]);
+            const int tiles = dvs[i].tiles_x * ((views[i].height + OCT_TILE - 1) / OCT_TILE);
+            const int tb = std::min(views[i].tile_begin, tiles);
+            const int te = views[i].tile_count < 0 ? tiles : std::min(tiles, tb + views[i].tile_count);
+            for (int t = tb; t < te; t += kRenderTilesPerWg) {
+                WgItem w{};
+                w.view = i;
+                w.tile0 = t;
+                w.ntiles = std::min(kRenderTilesPerWg, te - t);
+                mip_items.push_back(w);
+            }
+            continue;
+        }
         dvs[i].nseg = view_nseg(h, views[i]);
         dvs[i].ckpt = (float *)((uint8_t *)ckpt_ws + ck_off);
         dvs[i].nend = (int32_t *)((uint8_t *)ckpt_ws + ck_off + npix * dvs[i].nseg * 4);
@@ -1667,6 +1787,8 @@ int render_views_backward(oct_handle *h, int32_t n_views, const oct_view *views,
     float *dlut = (float *)h->bw_tmp;
     for (int i = 0; i < n_views; i++) dvs[i].dlut = dlut + (size_t)i * dlut_floats;
 
+    const size_t n_dvr_items = items.size();
+    items.insert(items.end(), mip_items.begin(), mip_items.end());
     const size_t v_bytes = dvs.size() * sizeof(DevView);
     const size_t i_off = (v_bytes + 255) & ~(size_t)255;
     const size_t i_bytes = items.size() * sizeof(WgItem);
@@ -1688,8 +1810,11 @@ int render_views_backward(oct_handle *h, int32_t n_views, const oct_view *views,
     HIPCHK(h, launch_fill_f32(dlut, (int64_t)n_views * dlut_floats, 0.0f, s));
     uint8_t *dp = (uint8_t *)rs.st.dev;
     HIPCHK(h, launch_render_backward(g, h->table, h->pool, h->brick_bytes, (const DevView *)dp,
-                                     (const WgItem *)(dp + i_off), (int)items.size(),
+                                     (const WgItem *)(dp + i_off), (int)n_dvr_items,
                                      (float *)((uint8_t *)h->bw_tmp + dl_bytes), dL_dvoxels, s));
+    HIPCHK(h, launch_render_backward_mip(g, h->table, h->pool, h->brick_bytes, (const DevView *)dp,
+                                         (const WgItem *)(dp + i_off) + n_dvr_items,
+                                         (int)mip_items.size(), dL_dvoxels, s));
     HIPCHK(h, launch_lut_to_ctrl((const DevView *)dp, n_views, g.C, dL_dctrl, s));
     HIPCHK(h, hipEventRecord(rs.st.ev, s));
     return OCT_OK;

@@ -17,11 +17,13 @@ LIB_PATH = os.path.join(_HERE, "liboctree_rc.so")
 OCT_OK, OCT_INCOMPLETE = 0, 1
 OCT_EINVAL, OCT_ENOMEM, OCT_ERANGE, OCT_EDEVICE, OCT_EBUSY = -1, -2, -3, -4, -5
 OCT_U16, OCT_F32 = 0, 1
+OCT_MODE_DVR, OCT_MODE_MIP = 0, 1
+OCT_MISSING_AVG, OCT_MISSING_FALLBACK, OCT_MISSING_REFINE = 0, 1, 2
 MAXC = 4
 
 EXPORTS = ["octree_create", "octree_destroy", "octree_clear", "octree_insert_block",
            "octree_insert_slices", "brick_pool_upload", "render_views", "render_views_noalloc",
-           "render_ckpt_bytes",
+           "render_ckpt_bytes", "render_refine_bytes",
            "render_views_backward", "octree_dump_canonical", "octree_read_level", "octree_info",
            "octree_render_timing", "oct_last_error"]
 
@@ -41,7 +43,9 @@ class OctView(ct.Structure):
                 ("clip", (ct.c_float * 4) * 3), ("tf_pos", (ct.c_float * 8) * MAXC),
                 ("tf_rgba", ((ct.c_float * 4) * 8) * MAXC), ("window", (ct.c_float * 2) * MAXC),
                 ("no_skip", ct.c_int32), ("depth_segments", ct.c_int32),
-                ("reserved", ct.c_int32 * 2)]
+                ("mode", ct.c_int32), ("missing", ct.c_int32), ("n_xform", ct.c_int32),
+                ("reserved", ct.c_int32), ("xform", ((ct.c_float * 4) * 3) * MAXC),
+                ("refine_state", ct.c_void_p)]
 
 
 class UploadStats(ct.Structure):
@@ -53,7 +57,8 @@ class UploadStats(ct.Structure):
 
 class RenderStats(ct.Structure):
     _fields_ = [("rays", ct.c_uint64), ("positions_nominal", ct.c_uint64),
-                ("positions_composited", ct.c_uint64), ("positions_trilinear", ct.c_uint64)]
+                ("positions_composited", ct.c_uint64), ("positions_trilinear", ct.c_uint64),
+                ("rays_waiting", ct.c_uint64)]
 
 
 def _load():
@@ -76,6 +81,8 @@ def _load():
     L.render_views_noalloc.argtypes = L.render_views.argtypes
     L.render_ckpt_bytes.restype = sz
     L.render_ckpt_bytes.argtypes = [vp, i32, ct.POINTER(OctView)]
+    L.render_refine_bytes.restype = sz
+    L.render_refine_bytes.argtypes = [vp, ct.POINTER(OctView)]
     L.render_views_backward.argtypes = [vp, i32, ct.POINTER(OctView), ct.POINTER(vp), vp, vp, vp,
                                         vp]
     L.octree_dump_canonical.argtypes = [vp, vp, sz, ct.POINTER(sz)]
@@ -136,6 +143,14 @@ def to_oct_views(views) -> np.ndarray:
         a["window"][k, :C] = v.window
     a["no_skip"] = [getattr(v, "no_skip", 0) for v in views]
     a["depth_segments"] = [getattr(v, "depth_segments", 0) for v in views]
+    a["mode"] = [getattr(v, "mode", 0) for v in views]
+    a["missing"] = [getattr(v, "missing", 0) for v in views]
+    for k, v in enumerate(views):
+        xf = getattr(v, "xform", None)
+        if xf is not None:
+            xf = np.asarray(xf, f32)
+            a["n_xform"][k] = xf.shape[0]
+            a["xform"][k, :xf.shape[0]] = xf
     return a
 
 
@@ -161,6 +176,15 @@ def to_oct_view(v) -> OctView:
         o.window[c][0], o.window[c][1] = float(win[c, 0]), float(win[c, 1])
     o.no_skip = int(getattr(v, "no_skip", 0))
     o.depth_segments = int(getattr(v, "depth_segments", 0))
+    o.mode, o.missing = int(getattr(v, "mode", 0)), int(getattr(v, "missing", 0))
+    xf = getattr(v, "xform", None)
+    if xf is not None:
+        xf = np.asarray(xf, np.float32)
+        o.n_xform = xf.shape[0]
+        for c in range(xf.shape[0]):
+            for a in range(3):
+                for k in range(4):
+                    o.xform[c][a][k] = float(xf[c, a, k])
     return o
 
 
@@ -251,9 +275,11 @@ class Octree:
                              f"needs {min_bytes}")
 
     def render(self, views, images=None, stats: bool = False, stream=None, ckpt=None,
-               noalloc: bool = False):
+               noalloc: bool = False, refine=None):
         """Render views into torch CUDA images [H][W][4] float32 (allocated when not given).
-        noalloc=True calls render_views_noalloc (no allocation inside the library)."""
+        noalloc=True calls render_views_noalloc (no allocation inside the library).
+        refine: per view None or the refinement-state tensor of a refinement view (see
+        refine_state())."""
         import torch
         if images is None:
             images = [torch.zeros((v.height, v.width, 4), dtype=torch.float32, device="cuda")
@@ -263,6 +289,14 @@ class Octree:
         for k, (v, im) in enumerate(zip(views, images)):
             self._check_buffer(im, f"images[{k}]", torch.float32, (v.height, v.width, 4))
         ova = to_oct_views(views)
+        if refine is not None:
+            if len(refine) != len(views):
+                raise ValueError("one refinement state (or None) per view")
+            for k, (v, r) in enumerate(zip(views, refine)):
+                if r is None:
+                    continue
+                self._check_buffer(r, f"refine[{k}]", None, min_bytes=self.refine_bytes(v))
+                ova["refine_state"][k] = r.data_ptr()
         ov = ova.ctypes.data_as(ct.POINTER(OctView))
         if ckpt is not None:
             self._check_buffer(ckpt, "ckpt", None, min_bytes=self.ckpt_bytes(views))
@@ -275,6 +309,16 @@ class Octree:
         if stats:
             return images, {k: getattr(rs, k) for k, _ in RenderStats._fields_}
         return images
+
+    def refine_bytes(self, view) -> int:
+        """Bytes of refinement state one refinement view needs."""
+        o = to_oct_view(view)
+        return int(lib.render_refine_bytes(self.h, ct.byref(o)))
+
+    def refine_state(self, view):
+        """A zero-filled refinement state for `view` (every ray starts from its entry)."""
+        import torch
+        return torch.zeros(self.refine_bytes(view), dtype=torch.uint8, device="cuda")
 
     def ckpt_bytes(self, views) -> int:
         """Bytes of the checkpoint workspace a differentiable render of these views needs."""
