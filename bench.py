@@ -4,13 +4,16 @@ One step is the whole streamed workload: the octree is cleared, then 32 batches 
 (already resident in HBM) are inserted; after each batch brick_pool_upload applies the changes
 and one 1024x1024 view (orbit az 45 el 30, step 0.5, per-ray footprint LOD) is rendered.
 Insertion and uploads run on a stream of their own (the library orders it against the render
-stream), so the next batch is inserted and analysed while the current one renders.  32^3 bricks, homogeneity threshold 205, seeded synthetic blob + Poisson data (stand-in for the
-paper's SPIM scans).
+stream), so the next batch is inserted and analysed while the current one renders.  32^3 bricks,
+homogeneity threshold 205, seeded synthetic blob + Poisson data (stand-in for the paper's SPIM
+scans).
 
 Prints one JSON line.  `value` is composited sample positions per second over the whole step
 (build time included); render-only, nominal and frame rates are reported beside it, with the
-render kernel's roofline (VALU-bound: algorithmic FP32 flops per second vs the non-packed FP32
-peak) and the CPU oracle timed on a bounded sample.
+render kernel's roofline (VALU-bound: algorithmic FP32 flops per second against the published
+FP32 peak), the CPU oracle timed on a bounded sample, and further legs: the build kernels'
+algorithmic GB/s (streamed and whole-volume), MIP on the final octree, the adjoint at 256^3
+f32, and the out-of-core 2048x2048x1024 orbit-and-dolly path with its own oracle sample.
 """
 from __future__ import annotations
 
@@ -28,14 +31,20 @@ sys.path.insert(0, ROOT)
 # trilinear 3x21 and classification 3x15.
 FLOPS_ANY = 8 + 24
 FLOPS_TRILINEAR = 12 + 63 + 45
-# 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz x 2 (FMA) -- FP32 without packed math
-PEAK_FP32_TFLOPS = 78.6
+# MI355X's published FP32 vector peak (it counts packed two-wide FMAs) -- the roofline's peak
+PEAK_FP32_TFLOPS = 157.3
+# 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz x 2 (FMA): the ceiling of FP32 without packed math,
+# which this build never emits (reported beside the published peak)
+NONPACKED_FP32_TFLOPS = 78.6
+PEAK_HBM_GBPS = 8000.0
 
 # HBM bytes per render launch of the default workload, from FETCH_SIZE / WRITE_SIZE counter
 # runs scaled by the same counters over a plain 1 GiB copy; valid only for the kernel code
 # they were taken on (its sources are hashed without comments, with the compile flags)
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_render_u16_hbm_traffic_stream_512x512x256.md")
 RENDER_SOURCES = ("render_kernels.hip", "raycommon.h", "internal.h")
+# the workload those counters were taken on (the default streamed configuration)
+TRAFFIC_WORKLOAD = "stream 512x512x256x3 u16 M32 1024x1024"
 
 
 def render_code_hash() -> str:
@@ -51,7 +60,9 @@ def render_code_hash() -> str:
     return h.hexdigest()
 
 
-def measured_traffic():
+def measured_traffic(workload: str):
+    """HBM bytes per render launch from the committed counter profile, when it was taken on
+    this workload and on the current kernel code; else None."""
     import re
     try:
         txt = open(TRAFFIC_PROFILE).read()
@@ -59,7 +70,10 @@ def measured_traffic():
         return None
     b = re.search(r"traffic_bytes_per_launch:\s*(\d+)", txt)
     h = re.search(r"kernel_code_sha256:\s*([0-9a-f]{64})", txt)
-    if not b or not h or h.group(1) != render_code_hash():
+    w = re.search(r"workload_key:\s*(.+)", txt)
+    if not b or not h or not w or h.group(1) != render_code_hash():
+        return None
+    if w.group(1).strip() != workload:
         return None
     return int(b.group(1))
 
@@ -79,18 +93,25 @@ def main():
     ap.add_argument("--config", type=int, default=2, choices=sorted(CFG))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true",
-                    help="stream workload: skip the adjoint summary (256^3 f32, 512x512)")
+                    help="stream workload: skip the adjoint leg (256^3 f32, 512x512)")
+    ap.add_argument("--no-paging", action="store_true",
+                    help="stream workload: skip the out-of-core leg (2048x2048x1024)")
+    ap.add_argument("--no-build", action="store_true",
+                    help="stream workload: skip the whole-volume build and MIP legs")
     ap.add_argument("--streams", type=int, default=2, choices=[1, 2],
                     help="stream workload: 2 = build and render on separate streams")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run a plain device copy of this size (counter calibration)")
     ap.add_argument("--scale", type=int, default=1, choices=[1, 2, 4],
-                    help="paging workload: 1 = 2048x2048x1024, 2 = half and 4 = quarter size")
+                    help="paging workload / leg: 1 = 2048x2048x1024, 2 = half and 4 = quarter "
+                         "size per axis")
     ap.add_argument("--workload", default="stream",
-                    choices=["stream", "adjoint", "serve", "views", "paging"],
+                    choices=["stream", "adjoint", "serve", "views", "paging", "build", "mip"],
                     help="stream: streamed build+render (default); adjoint: 256^3 f32 forward + "
                          "adjoint at 512x512; serve: Poisson request mix; views: 64 views of "
-                         "the 64^3 volume in one launch vs one launch per view")
+                         "the 64^3 volume in one launch vs one launch per view; paging: the "
+                         "out-of-core path alone; build: whole-volume build of the 512x512x256 "
+                         "volume; mip: MIP renders of the 512x512x256 octree")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
@@ -103,7 +124,7 @@ def main():
     from paper_1407_2074_amd import synth
     from paper_1407_2074_amd.octree import Octree
 
-    if args.workload != "stream":
+    if args.workload not in ("stream", "build", "mip"):
         {"adjoint": bench_adjoint, "serve": bench_serve, "views": bench_views,
          "paging": bench_paging}[args.workload](args)
         return
@@ -116,9 +137,17 @@ def main():
     print(f"[bench] generated {dims} x{C} in {time.perf_counter() - t_gen:.1f}s", file=sys.stderr,
           flush=True)
     dev = torch.from_numpy(vol.view(np.int16)).cuda()
+    if args.workload == "build":
+        print(json.dumps(measure_build(dev, cfg, args)), flush=True)
+        return
+    if args.workload == "mip":
+        t = Octree(dims, C, M, "u16", background=0, threshold=cfg["thr"])
+        t.insert_block(-1, (0, 0, 0), dev)
+        t.upload()
+        print(json.dumps(measure_mip(t, cfg, args)), flush=True)
+        return
     nb = dims[2] // cfg["batch"]
     slabs = [dev[:, b * cfg["batch"]:(b + 1) * cfg["batch"]].contiguous() for b in range(nb)]
-    del dev
     tree = Octree(dims, C, M, "u16", background=0, threshold=cfg["thr"])
     view = synth.make_view(dims, C, cfg["seed"], az=cfg["az"], el=cfg["el"], width=cfg["width"],
                            height=cfg["height"], lod=cfg["lod"])
@@ -167,12 +196,14 @@ def main():
             for _ in range(nb)] for _ in range(args.steps)]
     torch.cuda.synchronize()
     tree.render_timing(True)   # HIP events around each ray-casting kernel, on its stream
+    tree.build_timing(True)    # and around the build kernels, on theirs
     t0 = time.perf_counter()
     for k in range(args.steps):
         step(events=evs[k])
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     kernel_ms, kernel_n = tree.render_timing(False)
+    build_ms, build_bytes = tree.build_timing(False)
     render_ms = sum(e[0].elapsed_time(e[1]) for ev in evs for e in ev)   # whole render calls
     n_launch = args.steps * nb
     assert kernel_n == n_launch, (kernel_n, n_launch)
@@ -181,7 +212,9 @@ def main():
 
     value = composited * args.steps / elapsed / 1e9
     achieved_tflops = flops_step * args.steps / (kernel_ms / 1e3) / 1e12
-    traffic = measured_traffic()
+    workload_key = (f"stream {dims[0]}x{dims[1]}x{dims[2]}x{C} u16 M{M} "
+                    f"{cfg['width']}x{cfg['height']}")
+    traffic = measured_traffic(workload_key) if args.streams == 2 else None
     out = {
         "metric": "Gsamples/s + frames/s, 3-ch octree raycast fwd & adjoint, % HBM peak",
         "value": round(value, 3),
@@ -210,13 +243,16 @@ def main():
         "render_kernel_ms_per_launch": round(kernel_ms / n_launch, 4),
         "streams": args.streams,
         "non_render_ms_per_step": round(ms_per_step - render_ms / args.steps, 3),
-        "hbm_pct_of_peak": (round(100.0 * traffic / (kernel_ms / n_launch / 1e3) / 8e12, 2)
-                            if traffic else None),
+        "hbm_pct_of_peak": (round(100.0 * traffic / (kernel_ms / n_launch / 1e3) /
+                                  (PEAK_HBM_GBPS * 1e9), 2) if traffic else None),
         "roofline": {"bound": "alu", "achieved": round(achieved_tflops, 3),
                      "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(achieved_tflops / PEAK_FP32_TFLOPS, 4), "traffic": traffic,
-                     "kernel": "k_render<u16,3>",
-                     "flops_per_launch": flops_step // nb},
+                     "kernel": "k_render_u16<3, true, false>",
+                     "flops_per_launch": flops_step // nb,
+                     "nonpacked_fp32_ceiling": NONPACKED_FP32_TFLOPS,
+                     "frac_of_nonpacked_ceiling": round(achieved_tflops / NONPACKED_FP32_TFLOPS, 4)},
+        "build_streamed": build_summary(build_ms, build_bytes, args.steps),
     }
 
     if not args.no_cpu_baseline:
@@ -248,11 +284,89 @@ def main():
                       f"excluded from the value, bring the sample to "
                       f"{time.perf_counter() - t_all:.1f} s)"}
         out["final_frame_max_abs_err_vs_oracle"] = err
+    if not args.no_build:
+        out["mip"] = measure_mip(tree, cfg, args)
+        tree.close()
+        out["build_whole_volume"] = measure_build(dev, cfg, args)
+    tree.close()
+    del slabs, dev
     if not args.no_adjoint:
         out["adjoint"] = {k: v for k, v in measure_adjoint(args).items()
                           if k in ("value", "unit", "forward_ms", "adjoint_ms", "adjoint_tf_only_ms",
                                    "config")}
+    if not args.no_paging:
+        torch.cuda.empty_cache()
+        out["out_of_core"] = measure_paging(args)
     print(json.dumps(out), flush=True)
+
+
+def build_summary(ms, by, steps: int = 1) -> dict:
+    """Per build phase: kernel ms (per step), algorithmic GB, GB/s and % of HBM peak."""
+    names = ("insert", "downsample", "stats", "gather")
+    out = {}
+    for k, n in enumerate(names):
+        gbps = by[k] / (ms[k] / 1e3) / 1e9 if ms[k] > 0 else 0.0
+        out[n] = {"ms": round(ms[k] / steps, 3), "gb": round(by[k] / steps / 1e9, 4),
+                  "gb_per_s": round(gbps, 1), "hbm_pct": round(100.0 * gbps / PEAK_HBM_GBPS, 2)}
+    tot_ms, tot_b = sum(ms), sum(by)
+    g = tot_b / (tot_ms / 1e3) / 1e9 if tot_ms > 0 else 0.0
+    out["all"] = {"ms": round(tot_ms / steps, 3), "gb": round(tot_b / steps / 1e9, 4),
+                  "gb_per_s": round(g, 1), "hbm_pct": round(100.0 * g / PEAK_HBM_GBPS, 2)}
+    return out
+
+
+def measure_build(dev, cfg, args) -> dict:
+    """Whole-volume build from HBM: one insert of the full volume (level 0 + every level above)
+    and one brick_pool_upload (statistics of every cell, every bordered brick gathered); build
+    kernel time and algorithmic bytes per phase, median of the timed repetitions."""
+    import torch
+
+    from paper_1407_2074_amd.octree import Octree
+    dims, C, M = cfg["dims"], cfg["C"], cfg["M"]
+    t = Octree(dims, C, M, "u16", background=0, threshold=cfg["thr"])
+    runs = []
+    reps = max(args.steps, 3)
+    for r in range(reps + 1):
+        t.clear()
+        torch.cuda.synchronize()
+        t.build_timing(True)
+        t.insert_block(-1, (0, 0, 0), dev)
+        t.upload()
+        torch.cuda.synchronize()
+        ms, by = t.build_timing(False)
+        if r:
+            runs.append((ms, by))
+    t.close()
+    runs.sort(key=lambda x: sum(x[0]))
+    ms, by = runs[len(runs) // 2]
+    res = build_summary(ms, by)
+    res["config"] = (f"{dims[0]}x{dims[1]}x{dims[2]}x{C} u16 from HBM, {M}^3 bricks, "
+                     f"threshold {cfg['thr']}: one insert + one upload, median of {reps}")
+    return res
+
+
+def measure_mip(tree, cfg, args) -> dict:
+    """MIP of the complete octree: one 1024x1024 view (same camera as the streamed frames)."""
+    import torch
+
+    from paper_1407_2074_amd import synth
+    dims, C = cfg["dims"], cfg["C"]
+    v = synth.make_view(dims, C, cfg["seed"], az=cfg["az"], el=cfg["el"], width=cfg["width"],
+                        height=cfg["height"], lod=cfg["lod"], mode=1)
+    d = synth.make_view(dims, C, cfg["seed"], az=cfg["az"], el=cfg["el"], width=cfg["width"],
+                        height=cfg["height"], lod=cfg["lod"])
+    img = torch.empty((v.height, v.width, 4), dtype=torch.float32, device="cuda")
+    _, st = tree.render([v], images=[img], stats=True)
+    _, sd = tree.render([d], images=[img], stats=True)
+    reps = max(10, args.steps)
+    tm = _sync_time(lambda: tree.render([v], images=[img]), reps)
+    td = _sync_time(lambda: tree.render([d], images=[img]), reps)
+    return {"config": f"MIP, {cfg['width']}x{cfg['height']}, final octree of the stream",
+            "ms_per_frame": round(tm * 1e3, 4), "frames_per_s": round(1.0 / tm, 1),
+            "gsamples_per_s": round(st["positions_composited"] / tm / 1e9, 3),
+            "positions_composited": st["positions_composited"],
+            "dvr_ms_per_frame": round(td * 1e3, 4),
+            "dvr_positions_composited": sd["positions_composited"]}
 
 
 def _sync_time(fn, reps):
@@ -416,18 +530,43 @@ def bench_views(args):
 
 
 def bench_paging(args):
+    """The out-of-core path alone (see measure_paging)."""
+    print(json.dumps(measure_paging(args)), flush=True)
+
+
+def h2d_peak_gb_per_s(nbytes: int = 1 << 30, reps: int = 5) -> float:
+    """Plain pinned-host to device copy rate (hipMemcpyAsync through torch), median of reps."""
+    import torch
+    h = torch.empty(nbytes, dtype=torch.uint8, pin_memory=True)
+    d = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    d.copy_(h, non_blocking=True)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        d.copy_(h, non_blocking=True)
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1) / 1e3)
+    del h, d
+    return nbytes / sorted(ts)[len(ts) // 2] / 1e9
+
+
+def measure_paging(args) -> dict:
     """Out-of-core: 3-channel u16 2048x2048x1024 (100k blobs) at --scale 1, 32^3 bricks, the
-    full-resolution mipmap in pinned host memory, device brick pool capped (16 GB at scale 1,
+    full-resolution mipmap in pinned host memory, device brick pool capped (16 GiB at scale 1,
     divided by scale^3), 1920x1080 views along a 64-frame orbit that dollies from 1.0 to 0.5 of
     the fitting distance (per-ray LOD, step 0.5, ERT 0.99).  At --scale s the image shrinks by s
     too, so per-ray LODs and the working set relative to the pool match the full-size case.
     Each frame = render + one brick_pool_upload with a byte budget (bricks are paged in on
-    request).  The last frame is then refined until no brick is missing (compared with an
-    in-core render) or until the pool cannot take more (over-subscribed: coarser requests
-    have kept their slots, the rest are drawn with AVG)."""
+    request).  Afterwards four frames of the path (the last one among them) are refined until
+    no brick is missing, and 4096 random pixels of each converged image are compared with the
+    FP64 oracle, whose time on those rays is the CPU baseline."""
     import numpy as np
     import torch
 
+    import oracle
     from paper_1407_2074_amd import synth
     from paper_1407_2074_amd.octree import Octree
     sc = args.scale
@@ -437,6 +576,9 @@ def bench_paging(args):
     t_gen = time.perf_counter()
     vol = synth.gen_volume(dims, C, seed=3, n_blobs=blobs, workers=workers)
     t_gen = time.perf_counter() - t_gen
+    print(f"[bench] out-of-core volume {dims} x{C} generated in {t_gen:.1f}s", file=sys.stderr,
+          flush=True)
+    h2d = h2d_peak_gb_per_s()
     pool_bytes = (16 << 30) // (sc ** 3)
     tree = Octree(dims, C, M, "u16", 0, 205, pool_bytes=pool_bytes, master_on_host=True)
     t_ins = time.perf_counter()
@@ -446,6 +588,7 @@ def bench_paging(args):
     tree.upload()
     torch.cuda.synchronize()
     t_ins = time.perf_counter() - t_ins
+    print(f"[bench] out-of-core octree built in {t_ins:.1f}s", file=sys.stderr, flush=True)
     n_frames = 64
     W, H = 1920 // sc, 1080 // sc
     budget = (1 << 30) // sc
@@ -479,41 +622,77 @@ def bench_paging(args):
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     render_s = sum(a.elapsed_time(b) for a, b in ev) / 1e3
-    # refine the last view to convergence, compare with the in-core render of the same view
-    last = views[-1]
-    passes, unserved, resident = 0, 0, 0
-    for passes in range(1, 400):
-        (img,) = tree.render([last], images=[img])
-        up = tree.upload()
-        unserved, resident = up["requests_seen"], up["bricks_resident"]
-        if unserved == 0 or (up["bricks_gathered"] == 0 and up["evictions"] == 0):
-            break       # converged, or the pool holds what it can
-    (img,) = tree.render([last], images=[img])
-    paged = img.cpu()
-    incore_slots = tree.pool_slots
-    del tree
-    incore = Octree(dims, C, M, "u16", 0, 205)
-    for z0 in range(0, dims[2], zc):
-        incore.insert_slices(-1, z0, np.ascontiguousarray(vol[:, z0:z0 + zc]))
-    incore.upload()
-    (ref,) = incore.render([last])
-    same = bool(torch.equal(paged, ref.cpu())) if unserved == 0 else None
-    out = {"metric": "out-of-core frames/s over a 64-frame orbit-and-dolly path", "value":
-           round(n_frames / elapsed, 2), "unit": "frames/s", "n_gpus": 1, "higher_is_better": True,
-           "data": "synthetic", "config": {"workload": f"{dims[0]}x{dims[1]}x{dims[2]}x3 u16, "
-           f"{blobs} blobs, 32^3 bricks, master in pinned host memory, device pool "
-           f"{pool_bytes >> 20} MiB, {W}x{H}, ERT 0.99, per-ray LOD, {budget >> 20} MiB "
-           "upload budget per frame"},
-           "render_only_gsamples_per_s": round(comp / render_s / 1e9, 3),
-           "render_ms_per_frame": round(render_s / n_frames * 1e3, 3),
-           "upload_ms_per_frame": round(up_s / n_frames * 1e3, 3),
-           "paged_bricks": gathered, "paged_gb_per_s": round(gathered * incore.brick_bytes / up_s / 1e9, 2),
-           "requests": requests, "evictions": evictions,
-           "refine_passes_last_frame": passes, "last_frame_resident_bricks": resident,
-           "last_frame_unserved_requests": unserved, "pool_slots": incore_slots,
-           "converged_equals_in_core": same,
-           "generation_s": round(t_gen, 1), "insert_s": round(t_ins, 2)}
-    print(json.dumps(out), flush=True)
+    # host-link bytes per gathered brick: the bordered brick's source voxels, all channels
+    src_bytes = (M + 2) ** 3 * C * 2
+    # refine four frames of the path to convergence (untimed), keep their images
+    checks = sorted({0, n_frames // 3, 2 * n_frames // 3, n_frames - 1})
+    converged, passes_last, unserved_last, resident_last = {}, 0, 0, 0
+    for k in checks:
+        v = views[k]
+        for passes in range(1, 400):
+            _, st = tree.render([v], images=[img], stats=True)
+            up = tree.upload()
+            unserved, resident = up["requests_seen"], up["bricks_resident"]
+            if unserved == 0 or (up["bricks_gathered"] == 0 and up["evictions"] == 0):
+                break       # converged, or the pool holds what it can
+        (img,) = tree.render([v], images=[img])
+        converged[k] = (img.cpu().numpy().astype(np.float64), unserved)
+        passes_last, unserved_last, resident_last = passes, unserved, resident
+    slots = tree.pool_slots
+    tree.close()
+    torch.cuda.empty_cache()
+    # oracle: the same volume, everything inserted; 4096 random pixels per converged frame
+    t_orc = time.perf_counter()
+    mask = np.full((dims[2], dims[1], dims[0]), (1 << C) - 1, np.uint8)
+    ref = oracle.Tree(vol, mask, M, background=0, threshold=205)
+    del mask
+    t_orc = time.perf_counter() - t_orc
+    rng = np.random.default_rng(3)
+    worst, n_px, n_amb, pos, dt = 0.0, 0, 0, 0, 0.0
+    for k in checks:
+        gimg, unserved = converged[k]
+        if unserved:
+            continue    # not converged (over-subscribed pool): no in-core image to compare
+        px = np.stack([rng.integers(0, W, 4096), rng.integers(0, H, 4096)], -1)
+        tc = time.perf_counter()
+        want, ns, mg = ref.render_pixels(views[k], px, want_info=True)
+        dt += time.perf_counter() - tc
+        pos += int(ns.sum())
+        ok = mg >= 1e-5          # early-termination decisions FP32 and FP64 may take apart
+        got = gimg[px[:, 1], px[:, 0]]
+        worst = max(worst, float(np.abs(got - want)[ok].max()))
+        n_px += int(ok.sum())
+        n_amb += int((~ok).sum())
+    del ref
+    paged_gbps = gathered * src_bytes / up_s / 1e9 if up_s > 0 else 0.0
+    return {"metric": "out-of-core frames/s over a 64-frame orbit-and-dolly path",
+            "value": round(n_frames / elapsed, 2), "unit": "frames/s", "n_gpus": 1,
+            "higher_is_better": True, "data": "synthetic",
+            "config": {"workload": f"{dims[0]}x{dims[1]}x{dims[2]}x3 u16, {blobs} blobs, 32^3 "
+                       f"bricks, master in pinned host memory, device pool {pool_bytes >> 20} "
+                       f"MiB, {W}x{H}, ERT 0.99, per-ray LOD, {budget >> 20} MiB upload budget "
+                       "per frame"},
+            "render_only_gsamples_per_s": round(comp / render_s / 1e9, 3),
+            "render_ms_per_frame": round(render_s / n_frames * 1e3, 3),
+            "upload_ms_per_frame": round(up_s / n_frames * 1e3, 3),
+            "paged_bricks": gathered,
+            "paged_gb_per_s": round(paged_gbps, 2),
+            "h2d_peak_gb_per_s": round(h2d, 2),
+            "paged_frac_of_h2d_peak": round(paged_gbps / h2d, 3) if h2d > 0 else None,
+            "requests": requests, "evictions": evictions, "pool_slots": slots,
+            "refined_frames": checks, "refine_passes_last_frame": passes_last,
+            "last_frame_resident_bricks": resident_last,
+            "last_frame_unserved_requests": unserved_last,
+            "sampled_parity": {"pixels": n_px, "excluded_near_ert": n_amb,
+                               "max_abs_err_vs_oracle": worst, "tolerance": 1e-4,
+                               "pass": bool(n_px > 0 and worst <= 1e-4)},
+            "cpu_baseline": {"value": round(pos / dt / 1e9, 5) if dt > 0 else None,
+                             "unit": "Gsamples/s", "cores": oracle.num_threads(),
+                             "kind": "oracle",
+                             "sample": f"FP64 oracle on 4096 random rays of each converged frame "
+                                       f"{checks} ({pos} positions in {dt:.1f} s; its octree "
+                                       f"build took {t_orc:.1f} s, not counted)"},
+            "generation_s": round(t_gen, 1), "insert_s": round(t_ins, 2)}
 
 
 if __name__ == "__main__":

@@ -298,6 +298,16 @@ int octree_info(const oct_handle *h, int32_t *levels, uint64_t *brick_bytes,
  * Errors: OCT_EINVAL, OCT_EDEVICE. */
 int octree_render_timing(oct_handle *h, int32_t enable, double *total_ms, uint64_t *launches);
 
+/* Build-kernel timing, for measurement.  Each call waits for the build work recorded so far and
+ * returns in ms[4] its summed kernel time and in bytes[4] its algorithmic bytes, per phase:
+ * [0] insertion into level 0 (block read, level-0 write, mask read and write), [1] half-sampling
+ * of the levels above (children read, parents written), [2] statistics of the changed cells
+ * (their valid voxels read, plus the mask at level 0), [3] bordered-brick gathers (the padded
+ * pool voxels written and the source voxels read); either pointer may be NULL.  Then
+ * enable = 1 clears the totals and (re)starts recording -- HIP events around those launches
+ * on the calls' streams -- and enable = 0 stops it.  Errors: OCT_EINVAL, OCT_EDEVICE. */
+int octree_build_timing(oct_handle *h, int32_t enable, double *ms, double *bytes);
+
 /* Message describing the last failure on this handle (or of the last octree_create when h is
  * NULL); never NULL. */
 const char *oct_last_error(const oct_handle *h);

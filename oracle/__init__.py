@@ -78,7 +78,7 @@ def lib():
         L.orc_render_aux.argtypes = [ct.c_void_p, ct.POINTER(OrcView), ct.c_void_p, ct.c_void_p,
                                      ct.c_void_p, ct.c_void_p]
         L.orc_render_pixels.argtypes = [ct.c_void_p, ct.POINTER(OrcView), ct.c_void_p,
-                                        ct.c_int64, ct.c_void_p]
+                                        ct.c_int64, ct.c_void_p, ct.c_void_p, ct.c_void_p]
         L.orc_render_rows.argtypes = [ct.c_void_p, ct.POINTER(OrcView), ct.c_void_p,
                                       ct.c_void_p, ct.c_int, ct.c_int]
         L.orc_render_window.argtypes = [ct.c_void_p, ct.POINTER(OrcView), ct.c_void_p, ct.c_int,
@@ -222,14 +222,18 @@ class Tree:
             raise ValueError("oracle render rejected the view")
         return img, ns, mg, na
 
-    def render_pixels(self, view, px):
-        """RGBA of the listed pixels (px: [n][2] column, row) of one view."""
+    def render_pixels(self, view, px, want_info: bool = False):
+        """RGBA of the listed pixels (px: [n][2] column, row) of one view (plus their nominal
+        counts and margins)."""
         ov = to_orc_view(view)
         px = np.ascontiguousarray(px, np.int32)
         out = np.zeros((len(px), 4), np.float64)
-        if lib().orc_render_pixels(self.h, ct.byref(ov), _ptr(px), len(px), _ptr(out)) != 0:
+        ns = np.zeros(len(px), np.int32)
+        mg = np.zeros(len(px), np.float64)
+        if lib().orc_render_pixels(self.h, ct.byref(ov), _ptr(px), len(px), _ptr(out), _ptr(ns),
+                                   _ptr(mg)) != 0:
             raise ValueError("oracle render rejected the pixels")
-        return out
+        return (out, ns, mg) if want_info else out
 
     def render_grad(self, views, dL_dI, want_voxels: bool = True):
         """Gradient of a loss with image adjoints dL_dI w.r.t. control RGBA and level-0 voxels."""

@@ -183,37 +183,16 @@ int orc_tree_depth(const int32_t dims[3], int M)
     return N;
 }
 
-/* Subtree minimum / maximum over the level-0 region [l0, h0) of channel c and whether any /
- * every voxel of it was inserted in that channel.  Minimum, maximum, "any" and "all" do not
- * depend on the order of evaluation, so large regions (few nodes per level) are split over
- * threads; small ones run in the caller's thread. */
-static void region_stats(const orc_tree *t, const uint8_t *mask, int c, const int64_t l0[3],
-                         const int64_t h0[3], int split, double *mn_out, double *mx_out,
-                         int *any_out, int *all_out)
-{
-    const orc_params *p = &t->p;
-    double mn = INFINITY, mx = -INFINITY;
-    int any = 0, all = 1;
-#pragma omp parallel for if (split) schedule(static) reduction(min : mn) reduction(max : mx) \
-    reduction(| : any) reduction(& : all)
-    for (int64_t z = l0[2]; z < h0[2]; z++)
-        for (int64_t y = l0[1]; y < h0[1]; y++)
-            for (int64_t x = l0[0]; x < h0[0]; x++) {
-                double v = lvl_get(t, 0, c, (int)z, (int)y, (int)x);
-                mn = fmin(mn, v);
-                mx = fmax(mx, v);
-                int ins = (mask[(z * p->dims[1] + y) * p->dims[0] + x] >> c) & 1;
-                any |= ins;
-                all &= ins;
-            }
-    *mn_out = mn;
-    *mx_out = mx;
-    *any_out = any;
-    *all_out = all;
-}
-
-/* Statistics of node (L, b) straight from the definitions. */
-static void node_stats(orc_tree *t, const uint8_t *mask, int L, const int b[3], int split)
+/* Statistics of node (L, b) from the definitions ("CPU Data Structure"):
+ *   own brick:  min, max and sum over the node's valid level-L voxels (AVG follows from them);
+ *   subtree:    min and max over every value stored in the subtree -- the node's own brick and
+ *               the subtrees of its children; at level 0 the subtree is the brick itself --
+ *               and which of the region's valid level-0 voxels were inserted (any / all),
+ *               which at level 0 is read from the mask and above is the union of the
+ *               children's regions.  (Coarser values are means of finer ones, so this is also
+ *               the minimum / maximum over the node's level-0 region.)
+ * Children are computed before their parents (levels bottom-up). */
+static void node_stats(orc_tree *t, const uint8_t *mask, int L, const int b[3])
 {
     const orc_params *p = &t->p;
     const int C = p->channels, M = p->brick;
@@ -242,27 +221,47 @@ static void node_stats(orc_tree *t, const uint8_t *mask, int L, const int b[3], 
         nd->bsum[c] = sm;
     }
     nd->count = cnt;
-    /* level-0 region: subtree min/max and insertion coverage */
-    int64_t span = (int64_t)M << L;
-    int64_t l0[3], h0[3], nvox = 1;
-    for (int a = 0; a < 3; a++) {
-        l0[a] = b[a] * span;
-        h0[a] = b[a] * span + span;
-        if (h0[a] > p->dims[a]) h0[a] = p->dims[a];
-        nvox *= h0[a] > l0[a] ? h0[a] - l0[a] : 0;
+    if (cnt == 0) {          /* outside the volume (virtual extension): no voxels */
+        nd->populated = nd->complete = 0;
+        for (int c = 0; c < C; c++) nd->smin[c] = nd->smax[c] = 0.0;
+        return;
     }
     int any = 0, all = 1;
+    double smin[ORC_MAXC], smax[ORC_MAXC];
     for (int c = 0; c < C; c++) {
-        double mn, mx;
-        int a1, a2;
-        region_stats(t, mask, c, l0, h0, split && nvox > 0, &mn, &mx, &a1, &a2);
-        any |= a1;
-        all &= a2;
-        nd->smin[c] = nvox ? mn : 0.0;
-        nd->smax[c] = nvox ? mx : 0.0;
+        smin[c] = nd->bmin[c];
+        smax[c] = nd->bmax[c];
     }
-    nd->populated = (int8_t)(nvox > 0 && any);
-    nd->complete = (int8_t)(nvox > 0 && all);
+    if (L == 0) {
+        for (int z = lo[2]; z < hi[2]; z++)
+            for (int y = lo[1]; y < hi[1]; y++)
+                for (int x = lo[0]; x < hi[0]; x++) {
+                    const uint8_t m = mask[((int64_t)z * p->dims[1] + y) * p->dims[0] + x];
+                    for (int c = 0; c < C; c++) {
+                        int ins = (m >> c) & 1;
+                        any |= ins;
+                        all &= ins;
+                    }
+                }
+    } else {
+        for (int k = 0; k < 8; k++) {
+            const orc_node *ch = node_at(t, L - 1, 2 * b[0] + (k & 1), 2 * b[1] + ((k >> 1) & 1),
+                                         2 * b[2] + (k >> 2));
+            if (ch->count == 0) continue;   /* a child outside the volume */
+            any |= ch->populated;
+            all &= ch->complete;
+            for (int c = 0; c < C; c++) {
+                smin[c] = fmin(smin[c], ch->smin[c]);
+                smax[c] = fmax(smax[c], ch->smax[c]);
+            }
+        }
+    }
+    for (int c = 0; c < C; c++) {
+        nd->smin[c] = smin[c];
+        nd->smax[c] = smax[c];
+    }
+    nd->populated = (int8_t)any;
+    nd->complete = (int8_t)all;
 }
 
 orc_tree *orc_build(const orc_params *p, const void *v0, const uint8_t *mask)
@@ -311,23 +310,15 @@ orc_tree *orc_build(const orc_params *p, const void *v0, const uint8_t *mask)
                     }
     }
 
-    /* Per-node statistics (nodes are independent; levels with fewer nodes than threads split
-     * each node's level-0 region instead). */
-    const int nthr = orc_num_threads();
+    /* Per-node statistics, level by level from the finest (nodes of one level are
+     * independent). */
     for (int L = 0; L <= N; L++) {
         const int g = t->G[L];
         const int64_t g3 = (int64_t)g * g * g;
-        if (g3 >= 4 * nthr) {
 #pragma omp parallel for schedule(dynamic, 1)
-            for (int64_t i = 0; i < g3; i++) {
-                int b[3] = {(int)(i % g), (int)((i / g) % g), (int)(i / ((int64_t)g * g))};
-                node_stats(t, mask, L, b, 0);
-            }
-        } else {
-            for (int64_t i = 0; i < g3; i++) {
-                int b[3] = {(int)(i % g), (int)((i / g) % g), (int)(i / ((int64_t)g * g))};
-                node_stats(t, mask, L, b, 1);
-            }
+        for (int64_t i = 0; i < g3; i++) {
+            int b[3] = {(int)(i % g), (int)((i / g) % g), (int)(i / ((int64_t)g * g))};
+            node_stats(t, mask, L, b);
         }
     }
 
@@ -875,9 +866,9 @@ int orc_render_window(const orc_tree *t, const orc_view *view, double *image, in
 }
 
 /* The pixels listed in px ([n][2] = column, row) of one view, written to out[n][4] (a sparse
- * sample of a large frame). */
+ * sample of a large frame), with their nominal counts and margins when asked for. */
 int orc_render_pixels(const orc_tree *t, const orc_view *view, const int32_t *px, int64_t n,
-                      double *out);
+                      double *out, int32_t *nsamp, double *margin);
 
 int orc_num_threads(void)
 {
@@ -988,7 +979,7 @@ static int render_rows(const orc_tree *t, int n_views, const orc_view *views,
 }
 
 int orc_render_pixels(const orc_tree *t, const orc_view *view, const int32_t *px, int64_t n,
-                      double *out)
+                      double *out, int32_t *nsamp, double *margin)
 {
     if (!view_ok(t, view)) return -1;
     for (int64_t q = 0; q < n; q++)
@@ -1001,7 +992,8 @@ int orc_render_pixels(const orc_tree *t, const orc_view *view, const int32_t *px
     cam_setup(view, &cm);
 #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t q = 0; q < n; q++)
-        cast_ray(t, view, &cm, lu, px[2 * q], px[2 * q + 1], out + q * 4, NULL, NULL, NULL);
+        cast_ray(t, view, &cm, lu, px[2 * q], px[2 * q + 1], out + q * 4,
+                 nsamp ? nsamp + q : NULL, margin ? margin + q : NULL, NULL);
     free(lu);
     return 0;
 }

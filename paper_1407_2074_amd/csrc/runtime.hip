@@ -160,6 +160,17 @@ struct oct_handle {
     bool ktime = false;          // octree_render_timing: record the render kernels
     double ktime_ms = 0.0;
     uint64_t ktime_n = 0;
+    // octree_build_timing: HIP events around the build kernels of each phase (insert,
+    // downsample, statistics, gather) with the algorithmic bytes of each timed launch group
+    bool btime = false;
+    struct BuildTimed {
+        int phase;
+        hipEvent_t e0, e1;
+        double bytes;
+    };
+    std::vector<BuildTimed> btimed;
+    std::vector<hipEvent_t> bt_free;
+    double bt_ms[4] = {0, 0, 0, 0}, bt_bytes[4] = {0, 0, 0, 0};
     void *bw_tmp = nullptr;      // adjoint: table-gradient accumulators + replay scratch
     size_t bw_tmp_cap = 0;
     // paging (capped pool): render flags per cell, missing-brick value bounds, LRU stamps
@@ -207,6 +218,35 @@ int64_t cell_index(const VolGeom &g, int L, int x, int y, int z)
 // on one stream in call order, with one relaxation: an upload's statistics pass (which reads
 // only the mipmap) does not wait for renders issued before it, only its node-table and
 // brick-pool writes do -- so the next batch's insertion and analysis overlap a render.
+// Build timing: an event before a launch group (when enabled) and one after it, with the
+// group's algorithmic bytes; summed when octree_build_timing is called.
+hipEvent_t bt_event(oct_handle *h)
+{
+    if (!h->bt_free.empty()) {
+        hipEvent_t e = h->bt_free.back();
+        h->bt_free.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    return hipEventCreate(&e) == hipSuccess ? e : nullptr;
+}
+
+hipEvent_t bt_begin(oct_handle *h, hipStream_t s)
+{
+    if (!h->btime) return nullptr;
+    hipEvent_t e = bt_event(h);
+    if (e && hipEventRecord(e, s) != hipSuccess) return nullptr;
+    return e;
+}
+
+void bt_end(oct_handle *h, hipEvent_t e0, hipStream_t s, int phase, double bytes)
+{
+    if (!e0) return;
+    hipEvent_t e1 = bt_event(h);
+    if (!e1 || hipEventRecord(e1, s) != hipSuccess) return;
+    h->btimed.push_back({phase, e0, e1, bytes});
+}
+
 int wait_for(oct_handle *h, hipStream_t s, hipEvent_t ev)
 {
     if (ev) HIPCHK(h, hipStreamWaitEvent(s, ev, 0));
@@ -681,6 +721,11 @@ int octree_destroy(oct_handle *h)
     if (h->slot_range) (void)hipFree(h->slot_range);
     if (h->ins_stage) (void)hipFree(h->ins_stage);
     if (h->bw_tmp) (void)hipFree(h->bw_tmp);
+    for (const auto &r : h->btimed) {
+        (void)hipEventDestroy(r.e0);
+        (void)hipEventDestroy(r.e1);
+    }
+    for (hipEvent_t e : h->bt_free) (void)hipEventDestroy(e);
     if (h->ins_ev) (void)hipEventDestroy(h->ins_ev);
     if (h->ev_insert) (void)hipEventDestroy(h->ev_insert);
     if (h->ev_upload) (void)hipEventDestroy(h->ev_upload);
@@ -757,7 +802,15 @@ int octree_insert_block(oct_handle *h, int32_t channel, const int32_t origin[3],
     int rc = wait_for(h, s, h->ev_insert);     // overlapping inserts, and the last upload's
     if (!rc) rc = wait_for(h, s, h->ev_upload);  // gathers (they read the mipmap)
     if (rc) return rc;
-    HIPCHK(h, launch_insert(g, h->master, h->mask, src, channel, origin, size, s));
+    {
+        const double nvox = (double)size[0] * size[1] * size[2];
+        hipEvent_t e0 = bt_begin(h, s);
+        HIPCHK(h, launch_insert(g, h->master, h->mask, src, channel, origin, size, s));
+        // block read + level-0 write per channel, inserted-channel mask read and written
+        bt_end(h, e0, s, 0, nvox * (2.0 * cb * (double)h->esz + 2.0));
+    }
+    hipEvent_t e_ds = bt_begin(h, s);
+    double ds_bytes = 0.0;
     Box b;
     for (int a = 0; a < 3; a++) {
         b.lo[a] = origin[a];
@@ -771,9 +824,16 @@ int octree_insert_block(oct_handle *h, int32_t channel, const int32_t origin[3],
             p.hi[a] = b.hi[a] >> 1;
         }
         HIPCHK(h, launch_downsample(g, h->master, L, p.lo, p.hi, s));
+        double parents = 1.0, children = 1.0;
+        for (int a = 0; a < 3; a++) {
+            parents *= (double)(p.hi[a] - p.lo[a] + 1);
+            children *= (double)(std::min(2 * p.hi[a] + 1, g.ext[L][a] - 1) - 2 * p.lo[a] + 1);
+        }
+        ds_bytes += (double)g.C * (double)h->esz * (parents + children);
         h->dirty[L + 1].push_back(p);
         b = p;
     }
+    bt_end(h, e_ds, s, 1, ds_bytes);
     if (!data_is_device) HIPCHK(h, hipEventRecord(h->ins_ev, s));
     HIPCHK(h, hipEventRecord(h->ev_insert, s));
     return OCT_OK;
@@ -899,9 +959,24 @@ int brick_pool_upload(oct_handle *h, uint64_t byte_budget, void *stream, oct_upl
         if (rc) return rc;
         std::memcpy(h->up.host, stat_cells.data(), cl_bytes);
         HIPCHK(h, hipMemcpyAsync(h->up.dev, h->up.host, cl_bytes, hipMemcpyHostToDevice, s));
+        hipEvent_t e0 = bt_begin(h, s);
         HIPCHK(h, launch_stats(g, h->master, h->mask, (const int32_t *)h->up.dev, n_stat,
                                (uint8_t *)h->up.dev + sc_off,
                                (CellStat *)((uint8_t *)h->up.dev + st_off), s));
+        if (e0) {
+            // every valid voxel of each changed cell, all channels (plus the mask at level 0)
+            double bytes = 0.0;
+            for (int i = 0; i < n_stat; i++) {
+                const int L = stat_cells[4 * i];
+                double nv = 1.0;
+                for (int a = 0; a < 3; a++) {
+                    const int lo = stat_cells[4 * i + 1 + a] * M;
+                    nv *= (double)std::max(0, std::min(lo + M, g.ext[L][a]) - lo);
+                }
+                bytes += nv * ((double)C * (double)h->esz + (L == 0 ? 1.0 : 0.0));
+            }
+            bt_end(h, e0, s, 2, bytes);
+        }
         HIPCHK(h, hipMemcpyAsync((uint8_t *)h->up.host + st_off, (uint8_t *)h->up.dev + st_off, st_bytes,
                                  hipMemcpyDeviceToHost, s));
         HIPCHK(h, hipStreamSynchronize(s));
@@ -1178,9 +1253,21 @@ int brick_pool_upload(oct_handle *h, uint64_t byte_budget, void *stream, oct_upl
                                  hipMemcpyDeviceToDevice, s));
         HIPCHK(h, launch_apply_deltas(next, h->miss_range, (const CellDelta *)h->up.dev,
                                       (int)deltas.size(), s));
+        hipEvent_t e0 = bt_begin(h, s);
         HIPCHK(h, launch_gather(g, h->master, next, h->pool, h->brick_bytes,
                                 (const BrickJob *)((uint8_t *)h->up.dev + j_off), (int)jobs.size(),
                                 h->slot_range, h->background_f, s));
+        if (e0) {
+            // per bordered voxel of each job's sub-box: the padded pool voxel written and the
+            // source level's C values read
+            double bytes = 0.0;
+            for (const BrickJob &jb : jobs) {
+                double nv = 1.0;
+                for (int a = 0; a < 3; a++) nv *= (double)(jb.hi[a] - jb.lo[a] + 1);
+                bytes += nv * (4.0 + (double)C) * (double)h->esz;
+            }
+            bt_end(h, e0, s, 3, bytes);
+        }
         HIPCHK(h, launch_ranges(g, next, h->slot_range, h->miss_range, s));
         h->table_alt = h->table;
         h->table = next;
@@ -1942,6 +2029,29 @@ int octree_render_timing(oct_handle *h, int32_t enable, double *total_ms, uint64
         h->ktime_n = 0;
     }
     h->ktime = enable != 0;
+    return OCT_OK;
+}
+
+int octree_build_timing(oct_handle *h, int32_t enable, double *ms, double *bytes)
+{
+    if (!h) return OCT_EINVAL;
+    HIPCHK(h, hipSetDevice(h->device));
+    for (const auto &r : h->btimed) {
+        HIPCHK(h, hipEventSynchronize(r.e1));
+        float t = 0.0f;
+        HIPCHK(h, hipEventElapsedTime(&t, r.e0, r.e1));
+        h->bt_ms[r.phase] += (double)t;
+        h->bt_bytes[r.phase] += r.bytes;
+        h->bt_free.push_back(r.e0);
+        h->bt_free.push_back(r.e1);
+    }
+    h->btimed.clear();
+    for (int k = 0; k < 4; k++) {
+        if (ms) ms[k] = h->bt_ms[k];
+        if (bytes) bytes[k] = h->bt_bytes[k];
+    }
+    h->btime = enable != 0;
+    for (int k = 0; k < 4; k++) h->bt_ms[k] = h->bt_bytes[k] = 0.0;
     return OCT_OK;
 }
 

@@ -25,7 +25,7 @@ EXPORTS = ["octree_create", "octree_destroy", "octree_clear", "octree_insert_blo
            "octree_insert_slices", "brick_pool_upload", "render_views", "render_views_noalloc",
            "render_ckpt_bytes", "render_refine_bytes",
            "render_views_backward", "octree_dump_canonical", "octree_read_level", "octree_info",
-           "octree_render_timing", "oct_last_error"]
+           "octree_render_timing", "octree_build_timing", "oct_last_error"]
 
 
 class CreateParams(ct.Structure):
@@ -89,6 +89,7 @@ def _load():
     L.octree_read_level.argtypes = [vp, i32, vp, sz, ct.POINTER(i32)]
     L.octree_info.argtypes = [vp, ct.POINTER(i32), ct.POINTER(u64), ct.POINTER(u64)]
     L.octree_render_timing.argtypes = [vp, i32, ct.POINTER(ct.c_double), ct.POINTER(u64)]
+    L.octree_build_timing.argtypes = [vp, i32, ct.POINTER(ct.c_double), ct.POINTER(ct.c_double)]
     L.oct_last_error.restype = ct.c_char_p
     L.oct_last_error.argtypes = [vp]
     return L
@@ -351,6 +352,14 @@ class Octree:
         ms, n = ct.c_double(), ct.c_uint64()
         self._check(lib.octree_render_timing(self.h, 1 if enable else 0, ct.byref(ms), ct.byref(n)))
         return ms.value, n.value
+
+    def build_timing(self, enable: bool):
+        """Per phase (insert, downsample, stats, gather): summed kernel ms and algorithmic
+        bytes of the build work recorded so far (waits for it); then enable=True restarts
+        recording from zero, False stops it."""
+        ms, by = (ct.c_double * 4)(), (ct.c_double * 4)()
+        self._check(lib.octree_build_timing(self.h, 1 if enable else 0, ms, by))
+        return list(ms), list(by)
 
     def dump(self) -> bytes:
         need = ct.c_size_t()
