@@ -137,6 +137,13 @@ def main():
     print(f"[bench] generated {dims} x{C} in {time.perf_counter() - t_gen:.1f}s", file=sys.stderr,
           flush=True)
     dev = torch.from_numpy(vol.view(np.int16)).cuda()
+    if args.copy_probe_mib:
+        # a plain device copy of known size: calibrates the FETCH_SIZE / WRITE_SIZE counters
+        a = torch.empty(args.copy_probe_mib << 20, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     if args.workload == "build":
         print(json.dumps(measure_build(dev, cfg, args)), flush=True)
         return
@@ -153,12 +160,6 @@ def main():
                            height=cfg["height"], lod=cfg["lod"])
     img = torch.zeros((view.height, view.width, 4), dtype=torch.float32, device="cuda")
     stream = torch.cuda.current_stream()
-
-    if args.copy_probe_mib:
-        a = torch.empty(args.copy_probe_mib << 20, dtype=torch.uint8, device="cuda")
-        b = torch.empty_like(a)
-        b.copy_(a)
-        torch.cuda.synchronize()
 
     # insertion and uploads on their own stream: the library orders the two streams, and the
     # next batch's insertion and statistics run while the current batch renders
@@ -284,16 +285,16 @@ def main():
                       f"excluded from the value, bring the sample to "
                       f"{time.perf_counter() - t_all:.1f} s)"}
         out["final_frame_max_abs_err_vs_oracle"] = err
+    if not args.no_adjoint:
+        out["adjoint"] = {k: v for k, v in measure_adjoint(args).items()
+                          if k in ("value", "unit", "forward_ms", "adjoint_ms", "adjoint_tf_only_ms",
+                                   "config")}
     if not args.no_build:
         out["mip"] = measure_mip(tree, cfg, args)
         tree.close()
         out["build_whole_volume"] = measure_build(dev, cfg, args)
     tree.close()
     del slabs, dev
-    if not args.no_adjoint:
-        out["adjoint"] = {k: v for k, v in measure_adjoint(args).items()
-                          if k in ("value", "unit", "forward_ms", "adjoint_ms", "adjoint_tf_only_ms",
-                                   "config")}
     if not args.no_paging:
         torch.cuda.empty_cache()
         out["out_of_core"] = measure_paging(args)
