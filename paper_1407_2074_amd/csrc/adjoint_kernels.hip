@@ -15,9 +15,10 @@
 //          dL/da_e   = T_e * (gC . (rgb_e - Bc) + gA * (1 - Ba))
 //      and then Bc <- a_e rgb_e + (1 - a_e) Bc, Ba <- a_e + (1 - a_e) Ba,
 //      where (gC, gA) = dL/d(pixel RGBA).
-// The event gradient flows into the two table entries it interpolated (summed per lane in
-// registers while consecutive positions use the same entry pair, then added to an LDS
-// accumulator per workgroup, which goes to the view's table gradient at the end) and, through
+// The event gradient flows into the two table entries it interpolated and through them into at
+// most three consecutive transfer-function control points (summed per lane in registers over a
+// window of three control points, added to an LDS accumulator per workgroup when an event leaves
+// the window, which goes to dL/dctrl at the end) and, through
 // the table slope and the trilinear weights, into the eight level-0 corner voxels: summed per
 // lane in registers while the ray stays in one corner cube (a step to a face neighbour keeps
 // the four shared corners) and added to memory with float atomics when corners leave.
@@ -57,7 +58,6 @@ struct Marcher {
     const uint8_t *base = nullptr;
     int org[3] = {0, 0, 0};
     float avg[C];
-
     __device__ Marcher(const VolGeom &g_, const DevCell *t, const uint8_t *p, uint64_t bb, int L_)
         : g(g_), table(t), pool(p), brick_bytes(bb), L(L_)
     {
@@ -69,7 +69,9 @@ struct Marcher {
     }
 
     // Same decisions as the forward: the voxel holding p selects the level-L node; a brick
-    // node is interpolated in its bordered brick, any other node gives its AVG.
+    // node is interpolated in its bordered brick (channels interleaved and padded to four: one
+    // 8-byte (u16) or 16-byte (f32) load per corner, the eight issued together), any other node
+    // gives its AVG.
     __device__ void sample(const float p[3], Sample<C> &out)
     {
         int v[3];
@@ -107,15 +109,35 @@ struct Marcher {
             out.ii[q] = min(max((int)fl, 0), S - 2);
             out.org[q] = org[q];
         }
-        const int64_t i0 = ((int64_t)(out.ii[2] * S + out.ii[1]) * S + out.ii[0]) * 4;
-        const int64_t dy = (int64_t)S * 4, dz = (int64_t)S * S * 4;
-        const T *b0 = (const T *)base;
-        float w[8][kMaxC];
-        const int64_t off[8] = {i0, i0 + 4, i0 + dy, i0 + dy + 4,
-                                i0 + dz, i0 + dz + 4, i0 + dz + dy, i0 + dz + dy + 4};
+        const uint32_t off = (uint32_t)((out.ii[2] * S + out.ii[1]) * S + out.ii[0]);
+        const uint32_t dy = (uint32_t)S, dz = (uint32_t)(S * S);
+        const uint32_t o8[8] = {off, off + 1, off + dy, off + dy + 1,
+                                off + dz, off + dz + 1, off + dz + dy, off + dz + dy + 1};
+        float w[8][C];
+        if constexpr (sizeof(T) == 2) {
+            const uint2 *b2 = (const uint2 *)base;
+            uint2 q[8];
 #pragma unroll
-        for (int k = 0; k < 8; k++)
-            for (int c = 0; c < C; c++) w[k][c] = (float)b0[off[k] + c];
+            for (int k = 0; k < 8; k++) q[k] = b2[o8[k]];   // all loads in flight first
+#pragma unroll
+            for (int k = 0; k < 8; k++)
+#pragma unroll
+                for (int c = 0; c < C; c++) {
+                    const uint32_t word = (c < 2) ? q[k].x : q[k].y;
+                    w[k][c] = (float)((c & 1) ? (word >> 16) : (word & 0xffffu));
+                }
+        } else {
+            const float4 *b4 = (const float4 *)base;
+            float4 q[8];
+#pragma unroll
+            for (int k = 0; k < 8; k++) q[k] = b4[o8[k]];
+#pragma unroll
+            for (int k = 0; k < 8; k++) {
+                const float qv[4] = {q[k].x, q[k].y, q[k].z, q[k].w};
+#pragma unroll
+                for (int c = 0; c < C; c++) w[k][c] = qv[c];
+            }
+        }
 #pragma unroll
         for (int c = 0; c < C; c++) {
             const float c00 = lerpf(w[0][c], w[1][c], out.f[0]);
@@ -216,19 +238,30 @@ struct CubeAcc {
     }
 };
 
-template <typename T, int C>
+// kVox: voxel gradients are requested (otherwise their accumulators are not allocated).
+template <typename T, int C, bool kVox>
 __global__ void __launch_bounds__(kThreads)
 k_render_backward(VolGeom g, const DevCell *__restrict__ table, const uint8_t *__restrict__ pool,
                   uint64_t brick_bytes, const DevView *__restrict__ views,
-                  const WgItem *__restrict__ items, float *__restrict__ scratch, float *dvox)
+                  const WgItem *__restrict__ items, float *__restrict__ scratch, float *dvox,
+                  float *dctrl)
 {
     __shared__ ViewTables<C> tb;
-    __shared__ float s_dlut[C][256][4];
+    __shared__ float s_dctrl[C][8][4];
+    __shared__ int s_segj[C][256];     // table entry k = (1 - f) ctrl[j] + f ctrl[j + 1]
+    __shared__ float s_segf[C][256];
 
     const WgItem it = items[blockIdx.x];
     const DevView &V = views[it.view];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    for (int i = threadIdx.x; i < C * 256 * 4; i += kThreads) (&s_dlut[0][0][0])[i] = 0.0f;
+    for (int i = threadIdx.x; i < C * 8 * 4; i += kThreads) (&s_dctrl[0][0][0])[i] = 0.0f;
+    for (int i = threadIdx.x; i < C * 256; i += kThreads) {
+        int j;
+        float f;
+        tf_segment(V.tf_pos[i >> 8], i & 255, j, f);
+        s_segj[i >> 8][i & 255] = j;
+        s_segf[i >> 8][i & 255] = f;
+    }
     build_tables<C>(V, tb);   // ends with a barrier
 
     float ulo[C], usc[C];
@@ -256,20 +289,36 @@ k_render_backward(VolGeom g, const DevCell *__restrict__ table, const uint8_t *_
             gA = gi.w;
         }
         const int64_t nvox0 = (int64_t)g.dims[0] * g.dims[1] * g.dims[2];
+        // one cell cache for both walks: the back walk starts where the replay ended
         Marcher<T, C> mf(g, table, pool, brick_bytes, ray.L);
-        Marcher<T, C> mb(g, table, pool, brick_bytes, ray.L);
+        Marcher<T, C> &mb = mf;
         float Bc[3] = {0.0f, 0.0f, 0.0f}, Ba = 0.0f;
         CubeAcc<C> acc(dvox, nvox0, g.dims);
-        // table gradients of the entry pair (li, li + 1) each channel last interpolated in,
-        // summed in registers while consecutive positions keep using that pair
-        int li[C];
-        float ga[C][4], gb[C][4];
+        // control-point gradients, through the table construction: an event interpolating
+        // entries (i, i + 1) with weights (1 - fr, fr) reaches the control points of those two
+        // entries (table entry k = (1 - f_k) ctrl[j_k] + f_k ctrl[j_k + 1]), i.e. at most three
+        // consecutive control points.  Each lane sums them in registers over a window of three
+        // control points (jb .. jb + 2) per channel and adds the window to the workgroup's LDS
+        // accumulator only when an event falls outside it (a segment spans ~36 table entries)
+        int jb[C];
+        float wacc[C][3][4];
 #pragma unroll
         for (int c = 0; c < C; c++) {
-            li[c] = -1;
+            jb[c] = -1;
 #pragma unroll
-            for (int q = 0; q < 4; q++) ga[c][q] = gb[c][q] = 0.0f;
+            for (int j = 0; j < 3; j++)
+#pragma unroll
+                for (int q = 0; q < 4; q++) wacc[c][j][q] = 0.0f;
         }
+        auto flush_window = [&](int c) {
+#pragma unroll
+            for (int j = 0; j < 3; j++)
+#pragma unroll
+                for (int q = 0; q < 4; q++) {
+                    if (wacc[c][j][q] != 0.0f) atomicAdd(&s_dctrl[c][jb[c] + j][q], wacc[c][j][q]);
+                    wacc[c][j][q] = 0.0f;
+                }
+        };
         // the checkpoint blocks this wave walks: all of the ray, or the blocks of its depth
         // segment (the forward split the ray the same way); then T holds the transmittance in
         // front of the segment and (Bc, Ba) start as the composite of the segments behind it
@@ -328,7 +377,7 @@ k_render_backward(VolGeom g, const DevCell *__restrict__ table, const uint8_t *_
                 Classified cq[C];
                 float rgba[C][4], Tc[C];
                 float Tp = wscr[(k - k0) * 64 + lane];
-                if (dvox && sm.brick) {
+                if (kVox && sm.brick) {
                     // the corner cube of this sample (level-0 index of its lower corner)
                     const int kx = sm.org[0] + sm.ii[0], ky = sm.org[1] + sm.ii[1],
                               kz = sm.org[2] + sm.ii[2];
@@ -353,23 +402,26 @@ k_render_backward(VolGeom g, const DevCell *__restrict__ table, const uint8_t *_
                     for (int q = 0; q < 3; q++) Bc[q] = a * rgba[c][q] + (1.0f - a) * Bc[q];
                     Ba = a + (1.0f - a) * Ba;
                     const float fr = cq[c].fr;
-                    if (cq[c].i != li[c]) {
-                        if (li[c] >= 0) {
-#pragma unroll
-                            for (int q = 0; q < 4; q++) {
-                                if (ga[c][q] != 0.0f) atomicAdd(&s_dlut[c][li[c]][q], ga[c][q]);
-                                if (gb[c][q] != 0.0f) atomicAdd(&s_dlut[c][li[c] + 1][q], gb[c][q]);
-                                ga[c][q] = gb[c][q] = 0.0f;
-                            }
-                        }
-                        li[c] = cq[c].i;
+                    const int ja = s_segj[c][cq[c].i], jn = s_segj[c][cq[c].i + 1];
+                    const float fa = s_segf[c][cq[c].i], fn = s_segf[c][cq[c].i + 1];
+                    if (jb[c] < 0 || ja < jb[c] || jn + 1 > jb[c] + 2) {
+                        if (jb[c] >= 0) flush_window(c);
+                        jb[c] = min(ja, 5);
                     }
+                    // weights of the window's three control points in this event
+                    const float w0 = 1.0f - fr;
+                    const int sa = ja - jb[c], sn = jn - jb[c];
+                    float ws[3];
 #pragma unroll
-                    for (int q = 0; q < 4; q++) {
-                        ga[c][q] += (1.0f - fr) * gq[q];
-                        gb[c][q] += fr * gq[q];
-                    }
-                    if (dvox && sm.brick && cq[c].inside) {
+                    for (int j = 0; j < 3; j++)
+                        ws[j] = (sa == j ? w0 * (1.0f - fa) : 0.0f) + (sa + 1 == j ? w0 * fa : 0.0f) +
+                                (sn == j ? fr * (1.0f - fn) : 0.0f) + (sn + 1 == j ? fr * fn : 0.0f);
+#pragma unroll
+                    for (int j = 0; j < 3; j++)
+#pragma unroll
+                        for (int q = 0; q < 4; q++)
+                            wacc[c][j][q] = __builtin_fmaf(ws[j], gq[q], wacc[c][j][q]);
+                    if (kVox && sm.brick && cq[c].inside) {
                         const float4 de = cq[c].de;
                         const float gs = usc[c] * (gq[0] * de.x + gq[1] * de.y + gq[2] * de.z +
                                                    gq[3] * de.w);
@@ -387,20 +439,16 @@ k_render_backward(VolGeom g, const DevCell *__restrict__ table, const uint8_t *_
                 }
             }
         }
-        if (dvox) acc.flush();
+        if (kVox) acc.flush();
 #pragma unroll
         for (int c = 0; c < C; c++)
-            if (li[c] >= 0)
-#pragma unroll
-                for (int q = 0; q < 4; q++) {
-                    if (ga[c][q] != 0.0f) atomicAdd(&s_dlut[c][li[c]][q], ga[c][q]);
-                    if (gb[c][q] != 0.0f) atomicAdd(&s_dlut[c][li[c] + 1][q], gb[c][q]);
-                }
+            if (jb[c] >= 0) flush_window(c);
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < C * 256 * 4; i += kThreads) {
-        const float v = (&s_dlut[0][0][0])[i];
-        if (v != 0.0f) atomicAdd(V.dlut + i, v);
+    float *out = dctrl + (int64_t)V.user_index * C * 32;
+    for (int i = threadIdx.x; i < C * 8 * 4; i += kThreads) {
+        const float v = (&s_dctrl[0][0][0])[i];
+        if (v != 0.0f) atomicAdd(out + i, v);
     }
 }
 
@@ -594,16 +642,26 @@ __global__ void k_lut_to_ctrl(const DevView *views, int n_views, int C, float *d
 template <typename T>
 hipError_t launch_bw_typed(const VolGeom &g, const DevCell *table, const void *pool,
                            uint64_t brick_bytes, const DevView *views, const WgItem *items,
-                           int n_items, float *scratch, float *dvox, hipStream_t s)
+                           int n_items, float *scratch, float *dvox, float *dctrl, hipStream_t s)
 {
     const dim3 grid(n_items), block(kThreads);
     const uint8_t *p = (const uint8_t *)pool;
+#define OCTRC_BW(TT, CC)                                                                          \
+    do {                                                                                          \
+        if (dvox)                                                                                 \
+            hipLaunchKernelGGL((k_render_backward<TT, CC, true>), grid, block, 0, s, g, table, p,  \
+                               brick_bytes, views, items, scratch, dvox, dctrl);                  \
+        else                                                                                      \
+            hipLaunchKernelGGL((k_render_backward<TT, CC, false>), grid, block, 0, s, g, table, p, \
+                               brick_bytes, views, items, scratch, dvox, dctrl);                  \
+    } while (0)
     switch (g.C) {
-    case 1: hipLaunchKernelGGL((k_render_backward<T, 1>), grid, block, 0, s, g, table, p, brick_bytes, views, items, scratch, dvox); break;
-    case 2: hipLaunchKernelGGL((k_render_backward<T, 2>), grid, block, 0, s, g, table, p, brick_bytes, views, items, scratch, dvox); break;
-    case 3: hipLaunchKernelGGL((k_render_backward<T, 3>), grid, block, 0, s, g, table, p, brick_bytes, views, items, scratch, dvox); break;
-    default: hipLaunchKernelGGL((k_render_backward<T, 4>), grid, block, 0, s, g, table, p, brick_bytes, views, items, scratch, dvox); break;
+    case 1: OCTRC_BW(T, 1); break;
+    case 2: OCTRC_BW(T, 2); break;
+    case 3: OCTRC_BW(T, 3); break;
+    default: OCTRC_BW(T, 4); break;
     }
+#undef OCTRC_BW
     return hipGetLastError();
 }
 
@@ -611,14 +669,15 @@ hipError_t launch_bw_typed(const VolGeom &g, const DevCell *table, const void *p
 
 hipError_t launch_render_backward(const VolGeom &g, const DevCell *table, const void *pool,
                                   uint64_t brick_bytes, const DevView *views, const WgItem *items,
-                                  int n_items, float *scratch, float *dvox, hipStream_t s)
+                                  int n_items, float *scratch, float *dvox, float *dctrl,
+                                  hipStream_t s)
 {
     if (n_items == 0) return hipSuccess;
     if (g.dtype == 0)
         return launch_bw_typed<uint16_t>(g, table, pool, brick_bytes, views, items, n_items, scratch,
-                                         dvox, s);
+                                         dvox, dctrl, s);
     return launch_bw_typed<float>(g, table, pool, brick_bytes, views, items, n_items, scratch, dvox,
-                                  s);
+                                  dctrl, s);
 }
 
 hipError_t launch_render_backward_mip(const VolGeom &g, const DevCell *table, const void *pool,

@@ -212,10 +212,12 @@ hipError_t launch_view_mask(const VolGeom &g, const DevView *views, int n_views,
 // Front-to-back composite of the depth segments of every split view into its image.
 hipError_t launch_combine(const DevView *views, const int32_t *split_views, int n_split,
                           int C, int64_t max_pixels, hipStream_t s);
-// Adjoint: scratch holds kCkptStride floats per lane of the launch (n_items * 512 lanes).
+// Adjoint of DVR views: scratch holds kCkptStride floats per lane of the launch (n_items * 512
+// lanes); control-point gradients are added to dctrl [view][C][8][4] (views' user_index).
 hipError_t launch_render_backward(const VolGeom &g, const DevCell *table, const void *pool,
                                   uint64_t brick_bytes, const DevView *views, const WgItem *items,
-                                  int n_items, float *scratch, float *dvox, hipStream_t s);
+                                  int n_items, float *scratch, float *dvox, float *dctrl,
+                                  hipStream_t s);
 // Adjoint of MIP views: one lane per pixel, through the samples at the recorded maxima.
 hipError_t launch_render_backward_mip(const VolGeom &g, const DevCell *table, const void *pool,
                                       uint64_t brick_bytes, const DevView *views,

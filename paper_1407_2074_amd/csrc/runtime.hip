@@ -1894,15 +1894,17 @@ int render_views_backward(oct_handle *h, int32_t n_views, const oct_view *views,
     rc = wait_for(h, s, h->ev_upload);
     if (!rc) rc = wait_for_renders(h, s);
     if (rc) return rc;
-    HIPCHK(h, launch_fill_f32(dlut, (int64_t)n_views * dlut_floats, 0.0f, s));
+    if (!mip_items.empty()) HIPCHK(h, launch_fill_f32(dlut, (int64_t)n_views * dlut_floats, 0.0f, s));
     uint8_t *dp = (uint8_t *)rs.st.dev;
     HIPCHK(h, launch_render_backward(g, h->table, h->pool, h->brick_bytes, (const DevView *)dp,
                                      (const WgItem *)(dp + i_off), (int)n_dvr_items,
-                                     (float *)((uint8_t *)h->bw_tmp + dl_bytes), dL_dvoxels, s));
+                                     (float *)((uint8_t *)h->bw_tmp + dl_bytes), dL_dvoxels,
+                                     dL_dctrl, s));
     HIPCHK(h, launch_render_backward_mip(g, h->table, h->pool, h->brick_bytes, (const DevView *)dp,
                                          (const WgItem *)(dp + i_off) + n_dvr_items,
                                          (int)mip_items.size(), dL_dvoxels, s));
-    HIPCHK(h, launch_lut_to_ctrl((const DevView *)dp, n_views, g.C, dL_dctrl, s));
+    // MIP views accumulate table gradients (V.dlut); DVR views add to dL/dctrl directly
+    if (!mip_items.empty()) HIPCHK(h, launch_lut_to_ctrl((const DevView *)dp, n_views, g.C, dL_dctrl, s));
     HIPCHK(h, hipEventRecord(rs.st.ev, s));
     return OCT_OK;
 }
