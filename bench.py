@@ -98,6 +98,10 @@ def main():
                     help="stream workload: skip the out-of-core leg (2048x2048x1024)")
     ap.add_argument("--no-build", action="store_true",
                     help="stream workload: skip the whole-volume build and MIP legs")
+    ap.add_argument("--no-serve", action="store_true",
+                    help="stream workload: skip the serving leg (2000 Poisson requests)")
+    ap.add_argument("--serve-only", action="store_true",
+                    help="serve workload: skip the one-view-per-launch comparison loop")
     ap.add_argument("--streams", type=int, default=2, choices=[1, 2],
                     help="stream workload: 2 = build and render on separate streams")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -295,6 +299,10 @@ def main():
         out["build_whole_volume"] = measure_build(dev, cfg, args)
     tree.close()
     del slabs, dev
+    if not args.no_serve:
+        torch.cuda.empty_cache()
+        out["serving"] = {k: v for k, v in measure_serve(args).items()
+                          if k not in ("metric", "n_gpus", "higher_is_better", "data")}
     if not args.no_paging:
         torch.cuda.empty_cache()
         out["out_of_core"] = measure_paging(args)
@@ -446,12 +454,20 @@ def measure_adjoint(args) -> dict:
 
 
 def bench_serve(args):
-    """Serving: the 512x512x256 streamed-config octree resident; Poisson requests (200/s) with
-    image sizes uniform in {256, 512, 1024, 2048}^2, random orbits, per-request TFs and 0-3
-    clipping planes; framebuffer cap 2 GB."""
+    """Serving alone (see measure_serve)."""
+    print(json.dumps(measure_serve(args)), flush=True)
+
+
+def measure_serve(args, n: int = 2000) -> dict:
+    """Serving: the 512x512x256 streamed-config octree resident; 2000 Poisson requests (200/s)
+    with image sizes uniform in {256, 512, 1024, 2048}^2, random orbits, per-request TFs and 0-3
+    clipping planes; admission by framebuffer (2 GB cap) and brick-pool memory.  Reported:
+    requests/s, p50/p99 latency (arrival -> completion), the closed-loop rate, the same views
+    one launch per view, and 1024 random pixels of 8 served images against the FP64 oracle."""
     import numpy as np
     import torch
 
+    import oracle
     from paper_1407_2074_amd import synth
     from paper_1407_2074_amd.octree import Octree
     from paper_1407_2074_amd.serving import Server, poisson_requests
@@ -460,37 +476,64 @@ def bench_serve(args):
     t = Octree(dims, C, M, "u16", 0, 205)
     t.insert_block(-1, (0, 0, 0), torch.from_numpy(vol.view(np.int16)).cuda())
     t.upload()
-    n = max(args.steps, 1) * 40
     reqs = poisson_requests(dims, C, n, rate=200.0, seed=5)
     # positions per request, counted once (deterministic), not part of the timed run
     pos = 0
-    for r in reqs:
-        _, st = t.render([r.view], stats=True)
+    for k in range(0, len(reqs), 16):
+        _, st = t.render([r.view for r in reqs[k:k + 16]], stats=True)
         pos += st["positions_composited"]
     warm = poisson_requests(dims, C, 8, rate=1e6, seed=55)
     Server(t).run(warm, realtime=False)
-    st = Server(t).run(reqs, realtime=True)
+    keep = {r.rid for r in reqs[:: max(1, n // 8)][:8]}
+    kept = {}
+
+    def grab(r):
+        if r.rid in keep:
+            kept[r.rid] = r.image.cpu()
+    st = Server(t).run(reqs, realtime=True, on_complete=grab)
     closed = Server(t).run(poisson_requests(dims, C, n, rate=1e9, seed=5), realtime=False)
-    alone = 0.0
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
+    alone = None
+    if not getattr(args, "serve_only", False):
+        t0 = time.perf_counter()
+        for r in reqs:
+            t.render([r.view])
+        torch.cuda.synchronize()
+        alone = time.perf_counter() - t0
+    t.close()
+    # the oracle on 1024 random pixels of each kept image
+    ref = oracle.Tree(vol, np.full((dims[2], dims[1], dims[0]), (1 << C) - 1, np.uint8), M,
+                      background=0, threshold=205)
+    rng = np.random.default_rng(5)
+    worst = 0.0
     for r in reqs:
-        t.render([r.view])
-    torch.cuda.synchronize()
-    alone = time.perf_counter() - t0
-    out = {"metric": "serving requests/s, p50/p99 latency", "value": round(st.requests_per_s, 2),
-           "unit": "requests/s", "n_gpus": 1, "higher_is_better": True, "data": "synthetic",
-           "config": {"workload": f"{n} Poisson requests at 200/s, sizes {{256..2048}}^2, "
-                                  "512x512x256x3 octree resident"},
-           "offered_rate": 200.0, "latency_p50_ms": round(st.latency_p50_ms, 2),
-           "latency_p99_ms": round(st.latency_p99_ms, 2),
-           "gsamples_per_s": round(pos / st.makespan_s / 1e9, 3),
-           "closed_loop_requests_per_s": round(closed.requests_per_s, 2),
-           "closed_loop_gsamples_per_s": round(pos / closed.makespan_s / 1e9, 3),
-           "one_view_per_launch_gsamples_per_s": round(pos / alone / 1e9, 3),
-           "launches": st.launches, "max_in_flight": st.max_in_flight,
-           "max_fb_bytes": st.max_fb_bytes_in_use}
-    print(json.dumps(out), flush=True)
+        if r.rid not in kept:
+            continue
+        v = r.view
+        px = np.stack([rng.integers(0, v.width, 1024), rng.integers(0, v.height, 1024)], -1)
+        want = ref.render_pixels(v, px)
+        got = kept[r.rid].numpy().astype(np.float64)[px[:, 1], px[:, 0]]
+        worst = max(worst, float(np.abs(got - want).max()))
+    return {"metric": "serving requests/s, p50/p99 latency", "value": round(st.requests_per_s, 2),
+            "unit": "requests/s", "n_gpus": 1, "higher_is_better": True, "data": "synthetic",
+            "config": {"workload": f"{n} Poisson requests at 200/s, sizes {{256..2048}}^2, "
+                                   "0-3 clip planes, per-request TFs, 512x512x256x3 octree "
+                                   "resident, admission by framebuffer (2 GB) and brick-pool "
+                                   "memory"},
+            "offered_rate": 200.0, "completed": st.completed,
+            "latency_p50_ms": round(st.latency_p50_ms, 2),
+            "latency_p99_ms": round(st.latency_p99_ms, 2),
+            "gsamples_per_s": round(pos / st.makespan_s / 1e9, 3),
+            "closed_loop_requests_per_s": round(closed.requests_per_s, 2),
+            "closed_loop_gsamples_per_s": round(pos / closed.makespan_s / 1e9, 3),
+            "closed_loop_latency_p50_ms": round(closed.latency_p50_ms, 2),
+            "closed_loop_latency_p99_ms": round(closed.latency_p99_ms, 2),
+            "one_view_per_launch_gsamples_per_s": round(pos / alone / 1e9, 3) if alone else None,
+            "launches": st.launches, "max_in_flight": st.max_in_flight,
+            "max_fb_bytes": st.max_fb_bytes_in_use,
+            "sampled_parity": {"images": len(kept), "pixels_each": 1024,
+                               "max_abs_err_vs_oracle": worst, "tolerance": 1e-4,
+                               "pass": bool(kept and worst <= 1e-4)}}
 
 
 def bench_views(args):

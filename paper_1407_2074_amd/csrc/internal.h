@@ -199,19 +199,21 @@ hipError_t launch_render(const VolGeom &g, const DevCell *table, const void *poo
 // (DVR: the premultiplied colour; MIP: the classified, composited maxima) to the image.
 hipError_t launch_refine_finish(const DevView *views, const int32_t *refine_views, int n_refine,
                                 int C, int64_t max_pixels, hipStream_t s);
-// Bytes of one view's tables for C channels (views[i].tables points at that many bytes) and
-// 32-bit words of one view's transparency mask over n_cells node-table cells (whole 64-cell
-// groups).  Per launch, the preparation kernel builds every view's tables and tile-group
-// dispatch order (it reads only the views); the mask kernel, after it and after the last
-// upload, fills the mask of every view with tmask != NULL from the node table `table`.
+// Bytes of one view's tables for C channels (views[i].tables points at that many bytes, built
+// on the host) and 32-bit words of one view's transparency mask over n_cells node-table cells
+// (whole 64-cell groups).  Per launch, the preparation kernel builds the tile-group dispatch
+// order of every view with group_order != NULL (it reads only the views); the mask kernel,
+// after the last upload, fills the mask of every view with tmask != NULL from the node table
+// `table`.
 size_t view_tables_bytes(int C);
 inline int64_t view_mask_words(int64_t n_cells) { return (n_cells + 63) / 64 * 2; }
 hipError_t launch_view_prep(const VolGeom &g, const DevView *views, int n_views, hipStream_t s);
 hipError_t launch_view_mask(const VolGeom &g, const DevView *views, int n_views,
                             const DevCell *table, int64_t n_cells, hipStream_t s);
 // Front-to-back composite of the depth segments of every split view into its image.
+// modes: bit 0 = some split view is DVR, bit 1 = some split view is MIP.
 hipError_t launch_combine(const DevView *views, const int32_t *split_views, int n_split,
-                          int C, int64_t max_pixels, hipStream_t s);
+                          int C, int modes, int64_t max_pixels, hipStream_t s);
 // Adjoint of DVR views: scratch holds kCkptStride floats per lane of the launch (n_items * 512
 // lanes); control-point gradients are added to dctrl [view][C][8][4] (views' user_index).
 hipError_t launch_render_backward(const VolGeom &g, const DevCell *table, const void *pool,

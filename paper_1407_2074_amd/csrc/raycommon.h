@@ -15,8 +15,9 @@ __device__ inline float lerpf(float a, float b, float t) { return __builtin_fmaf
 
 // Control-point segment and weight of table entry k (x = k/255): the entry is
 // (1-f) * rgba[j] + f * rgba[j+1]; outside the first / last control point the end value is
-// held (j = 0, f = 0 / j = 6, f = 1).
-__device__ inline void tf_segment(const float *p, int k, int &j, float &f)
+// held (j = 0, f = 0 / j = 6, f = 1).  Host and device evaluate the same IEEE float32
+// operations (no contraction), so tables built on either side are identical.
+__host__ __device__ inline void tf_segment(const float *p, int k, int &j, float &f)
 {
     const float x = (float)k / 255.0f;
     if (x <= p[0]) { j = 0; f = 0.0f; return; }
@@ -26,7 +27,7 @@ __device__ inline void tf_segment(const float *p, int k, int &j, float &f)
     f = (x - p[j]) / (p[j + 1] - p[j]);
 }
 
-__device__ inline float4 tf_entry(const DevView &V, int c, int k)
+__host__ __device__ inline float4 tf_entry(const DevView &V, int c, int k)
 {
     int j;
     float f;
@@ -108,7 +109,31 @@ __device__ inline void build_tables(const DevView &V, ViewTables<C> &tb)
     __syncthreads();
 }
 
-// The leading sizeof(Tab) bytes of V's tables (built by k_view_prep) copied into LDS by the
+// A view's tables built on the host (the same entries, slopes and opacity prefix counts as
+// build_tables), to be copied to the device with the launch's view records.
+template <int C>
+__host__ inline void host_build_tables(const DevView &V, ViewTables<C> &tb)
+{
+    for (int c = 0; c < C; c++) {
+        int run = 0;
+        for (int k = 0; k < 256; k++) {
+            const float4 e0 = tf_entry(V, c, k);
+            const float4 e1 = k < 255 ? tf_entry(V, c, k + 1) : e0;
+            tb.lut[c][k][0] = e0;
+            tb.lut[c][k][1] = make_float4(e1.x - e0.x, e1.y - e0.y, e1.z - e0.z, e1.w - e0.w);
+            tb.pref[c][k] = run;
+            run += e0.w != 0.0f ? 1 : 0;
+        }
+        tb.pref[c][256] = run;
+        for (int w = 0; w < 4; w++) {
+            int n = 0;
+            for (int k = 64 * w; k < 64 * w + 64; k++) n += tf_entry(V, c, k).w != 0.0f ? 1 : 0;
+            tb.wtot[c][w] = n;
+        }
+    }
+}
+
+// The leading sizeof(Tab) bytes of V's tables (built on the host) copied into LDS by the
 // whole workgroup (a multiple of 16 bytes, 16-byte loads); ends with a barrier.
 template <int kThreadsPerWg, typename Tab>
 __device__ inline void load_tables(const DevView &V, Tab &tb)

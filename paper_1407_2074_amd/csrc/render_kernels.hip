@@ -1016,34 +1016,40 @@ k_render_general(VolGeom g, const DevCell *__restrict__ table, const uint8_t *__
 // T = T_0 T_1 ..., written as premultiplied (C, 1 - T) to the pixels of the rendered tiles.
 // MIP views: the segments' per-channel maxima are combined by max and then classified and
 // composited in channel order (-inf marks a ray that misses the volume: the pixel is 0).
-template <int C>
-__global__ void __launch_bounds__(256)
+// Segments are loaded two at a time and the kernel is held to 32 registers, so that it starts
+// beside render waves of other launches (they leave 32 of a SIMD's 512).
+// One instantiation per mode (kMip), each skipping the other mode's views, so that the DVR one
+// keeps its few registers.
+template <int C, bool kMip>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_num_vgpr(32)))
 k_combine(const DevView *__restrict__ views, const int32_t *__restrict__ split_views)
 {
     const DevView &V = views[split_views[blockIdx.y]];
+    if ((V.mode == 1) != kMip) return;
     const int64_t npix = (int64_t)V.width * V.height;
-    const bool mip = V.mode == 1;
+    constexpr bool mip = kMip;
     const LutTable<C> *tab = (const LutTable<C> *)V.tables;
     for (int64_t pix = (int64_t)blockIdx.x * 256 + threadIdx.x; pix < npix;
          pix += (int64_t)gridDim.x * 256) {
         const int px = (int)(pix % V.width), py = (int)(pix / V.width);
         const int tile = (py >> 3) * V.tiles_x + (px >> 3);
         if (tile < V.tile_begin || tile >= V.tile_end) continue;
-        // every segment's loads are issued before the first is used (at most kMaxSplit)
-        float4 q[kMaxSplit];
+        const float4 *part = (const float4 *)V.part + pix;
+        float4 acc = part[0];
+        if constexpr (mip) {
+            for (int s0 = 1; s0 < V.nsplit; s0 += 2) {
+                float4 q[2];
 #pragma unroll
-        for (int sg = 0; sg < kMaxSplit; sg++)
-            if (sg < V.nsplit) q[sg] = *(const float4 *)(V.part + ((int64_t)sg * npix + pix) * 4);
-        float4 acc = q[0];
-        if (mip) {
+                for (int k = 0; k < 2; k++)   // two segments' loads in flight
+                    if (s0 + k < V.nsplit) q[k] = part[(int64_t)(s0 + k) * npix];
 #pragma unroll
-            for (int sg = 1; sg < kMaxSplit; sg++) {
-                if (sg < V.nsplit) {
-                    acc.x = fmaxf(acc.x, q[sg].x);
-                    acc.y = fmaxf(acc.y, q[sg].y);
-                    acc.z = fmaxf(acc.z, q[sg].z);
-                    acc.w = fmaxf(acc.w, q[sg].w);
-                }
+                for (int k = 0; k < 2; k++)
+                    if (s0 + k < V.nsplit) {
+                        acc.x = fmaxf(acc.x, q[k].x);
+                        acc.y = fmaxf(acc.y, q[k].y);
+                        acc.z = fmaxf(acc.z, q[k].z);
+                        acc.w = fmaxf(acc.w, q[k].w);
+                    }
             }
             float Cr = 0.0f, Cg = 0.0f, Cb = 0.0f, Tr = 1.0f;
             if (acc.x > -INFINITY) {
@@ -1063,14 +1069,19 @@ k_combine(const DevView *__restrict__ views, const int32_t *__restrict__ split_v
             continue;
         }
         float T = acc.w;
+        for (int s0 = 1; s0 < V.nsplit; s0 += 2) {
+            float4 q[2];
 #pragma unroll
-        for (int sg = 1; sg < kMaxSplit; sg++) {
-            if (sg < V.nsplit) {
-                acc.x = __builtin_fmaf(T, q[sg].x, acc.x);
-                acc.y = __builtin_fmaf(T, q[sg].y, acc.y);
-                acc.z = __builtin_fmaf(T, q[sg].z, acc.z);
-                T = T * q[sg].w;
-            }
+            for (int k = 0; k < 2; k++)   // two segments' loads in flight
+                if (s0 + k < V.nsplit) q[k] = part[(int64_t)(s0 + k) * npix];
+#pragma unroll
+            for (int k = 0; k < 2; k++)
+                if (s0 + k < V.nsplit) {
+                    acc.x = __builtin_fmaf(T, q[k].x, acc.x);
+                    acc.y = __builtin_fmaf(T, q[k].y, acc.y);
+                    acc.z = __builtin_fmaf(T, q[k].z, acc.z);
+                    T = T * q[k].w;
+                }
         }
         *(float4 *)(V.image + pix * 4) = make_float4(acc.x, acc.y, acc.z, 1.0f - T);
     }
@@ -1119,21 +1130,22 @@ k_refine_finish(const DevView *__restrict__ views, const int32_t *__restrict__ r
 // Dispatch order of a view's tile groups (item_of): groups sorted by the length inside the
 // volume box and the clip half-spaces of their longest tile-centre ray (one ray per group when
 // the view has more than 4096 groups), longest first, in 32 length classes.  Each thread owns a
-// contiguous run of groups, and a counting sort with per-thread class counts (scanned class by
-// class over the threads) keeps index order inside a class, so neighbouring groups of one
-// class stay neighbours in the dispatch.  One 256-thread workgroup; group_order[G ... 2G) is
-// scratch.  Precision does not matter here (the order changes no result), hence the
-// approximate reciprocals.
+// contiguous run of groups; a counting sort keeps index order inside a class, so neighbouring
+// groups of one class stay neighbours in the dispatch.  Per class (an unrolled loop, so the
+// per-thread counts stay in registers) a wave scan of the threads' counts gives each thread its
+// offset, and the thread writes its groups of that class.  One 256-thread workgroup, under 1 KB
+// of LDS (it runs on the preparation stream beside render workgroups, which leave little LDS
+// free); group_order[G ... 2G) holds the classes.  Precision does not matter here (the order
+// changes no result), hence the approximate reciprocals.
 __device__ inline void view_group_order(const VolGeom &g, const DevView &V)
 {
 #ifndef OCTRC_ORDER_CLASSES
 #define OCTRC_ORDER_CLASSES 32
 #endif
     constexpr int kCls = OCTRC_ORDER_CLASSES;
-    __shared__ int cnt[kCls][256];
-    __shared__ int base[kCls];
+    __shared__ int wsum[kCls][4];
     __shared__ float red[4];
-    const int G = V.groups, tid = threadIdx.x;
+    const int G = V.groups, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     int32_t *order = V.group_order, *cls = V.group_order + G;
     const int chunk = (G + 255) / 256, lo = min(tid * chunk, G), hi = min(lo + chunk, G);
     const int rays = G > 4096 ? 1 : kRenderTilesPerWg;
@@ -1176,59 +1188,51 @@ __device__ inline void view_group_order(const VolGeom &g, const DevView &V)
         cls[gi] = __float_as_int(best);
         lmax = fmaxf(lmax, best);
     }
-    for (int c = 0; c < kCls; c++) cnt[c][tid] = 0;
     for (int o = 32; o > 0; o >>= 1) lmax = fmaxf(lmax, __shfl_xor(lmax, o, 64));
-    if ((tid & 63) == 0) red[tid >> 6] = lmax;
+    if (lane == 0) red[wave] = lmax;
     __syncthreads();
     lmax = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
     const float scale = lmax > 0.0f ? (float)kCls / lmax : 0.0f;
-    for (int gi = lo; gi < hi; gi++) {
-        const int c = kCls - 1 - min(max((int)(__int_as_float(cls[gi]) * scale), 0), kCls - 1);
-        cls[gi] = c;   // class 0: the longest rays
-        cnt[c][tid]++;
-    }
-    __syncthreads();
-    if (tid < kCls) {   // exclusive prefix over the threads, per class
-        int run = 0;
-        for (int t = 0; t < 256; t++) {
-            const int n = cnt[tid][t];
-            cnt[tid][t] = run;
-            run += n;
+    for (int gi = lo; gi < hi; gi++)   // class 0: the longest rays
+        cls[gi] = kCls - 1 - min(max((int)(__int_as_float(cls[gi]) * scale), 0), kCls - 1);
+    // per class: this thread's count and its exclusive scan over the wave (recomputed in the
+    // second pass rather than kept, so the kernel stays within a few registers), the wave totals
+    auto wave_scan = [&](int c, int &n) -> int {
+        n = 0;
+        for (int gi = lo; gi < hi; gi++) n += cls[gi] == c ? 1 : 0;
+        int x = n;
+        for (int o = 1; o < 64; o <<= 1) {
+            const int y = __shfl_up(x, o, 64);
+            if (lane >= o) x += y;
         }
-        base[tid] = run;
+        return x;   // inclusive
+    };
+    for (int c = 0; c < kCls; c++) {
+        int n;
+        const int x = wave_scan(c, n);
+        if (lane == 63) wsum[c][wave] = x;
     }
     __syncthreads();
-    if (tid == 0) {
-        int run = 0;
-        for (int c = 0; c < kCls; c++) {
-            const int n = base[c];
-            base[c] = run;
-            run += n;
-        }
-    }
-    __syncthreads();
-    for (int gi = lo; gi < hi; gi++) {
-        const int c = cls[gi];
-        order[base[c] + cnt[c][tid]++] = gi;
+    int base = 0;   // groups of the classes before c, then of the waves before this one
+    for (int c = 0; c < kCls; c++) {
+        int n;
+        int at = base + wave_scan(c, n) - n;
+        for (int w = 0; w < wave; w++) at += wsum[c][w];
+        for (int gi = lo; gi < hi; gi++)
+            if (cls[gi] == c) order[at++] = gi;
+        base += wsum[c][0] + wsum[c][1] + wsum[c][2] + wsum[c][3];
     }
 }
 
-// Per-launch view preparation in one grid (views along y): workgroup 0 of a view tabulates
-// its transfer functions (value/slope table and opacity prefix counts) into V.tables,
-// workgroup 1 sorts its tile groups into dispatch order.  Reads only the views.
-template <int C>
-__global__ void __launch_bounds__(256) k_view_prep(VolGeom g, const DevView *__restrict__ views)
+// Per-launch view preparation (views along y): one workgroup per view with a dispatch order
+// sorts its tile groups (the tables come from the host).  Reads only the views.  It runs on the
+// preparation stream while renders hold the CUs: render waves take 480 of a SIMD's 512
+// registers, so this kernel is held to 32 (and little LDS) to start beside them.
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_num_vgpr(32)))
+k_view_prep(VolGeom g, const DevView *__restrict__ views)
 {
-    __shared__ ViewTables<C> tb;
     const DevView &V = views[blockIdx.y];
-    if (blockIdx.x == 1) {
-        if (V.group_order) view_group_order(g, V);
-        return;
-    }
-    build_tables<C>(V, tb);   // ends with a barrier
-    const uint4 *src = (const uint4 *)&tb;
-    uint4 *dst = (uint4 *)V.tables;
-    for (int i = threadIdx.x; i < (int)(sizeof(ViewTables<C>) / 16); i += 256) dst[i] = src[i];
+    if (V.group_order) view_group_order(g, V);
 }
 
 // Transparency of every node-table cell for every view that skips: workgroup b of a view sets
@@ -1366,13 +1370,7 @@ size_t view_tables_bytes(int C)
 hipError_t launch_view_prep(const VolGeom &g, const DevView *views, int n_views, hipStream_t s)
 {
     if (n_views <= 0) return hipSuccess;
-    const dim3 grid(2, (unsigned)n_views), block(256);
-    switch (g.C) {
-    case 1: hipLaunchKernelGGL(k_view_prep<1>, grid, block, 0, s, g, views); break;
-    case 2: hipLaunchKernelGGL(k_view_prep<2>, grid, block, 0, s, g, views); break;
-    case 3: hipLaunchKernelGGL(k_view_prep<3>, grid, block, 0, s, g, views); break;
-    default: hipLaunchKernelGGL(k_view_prep<4>, grid, block, 0, s, g, views); break;
-    }
+    hipLaunchKernelGGL(k_view_prep, dim3(1, (unsigned)n_views), dim3(256), 0, s, g, views);
     return hipGetLastError();
 }
 
@@ -1391,16 +1389,23 @@ hipError_t launch_view_mask(const VolGeom &g, const DevView *views, int n_views,
 }
 
 hipError_t launch_combine(const DevView *views, const int32_t *split_views, int n_split, int C,
-                          int64_t max_pixels, hipStream_t s)
+                          int modes, int64_t max_pixels, hipStream_t s)
 {
     if (n_split <= 0 || max_pixels <= 0) return hipSuccess;
     const unsigned gx = (unsigned)std::min<int64_t>((max_pixels + 255) / 256, 4096);
     const dim3 grid(gx, (unsigned)n_split), block(256);
-    switch (C) {
-    case 1: hipLaunchKernelGGL(k_combine<1>, grid, block, 0, s, views, split_views); break;
-    case 2: hipLaunchKernelGGL(k_combine<2>, grid, block, 0, s, views, split_views); break;
-    case 3: hipLaunchKernelGGL(k_combine<3>, grid, block, 0, s, views, split_views); break;
-    default: hipLaunchKernelGGL(k_combine<4>, grid, block, 0, s, views, split_views); break;
+    for (int m = 0; m < 2; m++) {   // DVR views, then MIP views (each kernel skips the others)
+        if (!(modes & (1 << m))) continue;
+        switch (C * 2 + m) {
+        case 2: hipLaunchKernelGGL((k_combine<1, false>), grid, block, 0, s, views, split_views); break;
+        case 3: hipLaunchKernelGGL((k_combine<1, true>), grid, block, 0, s, views, split_views); break;
+        case 4: hipLaunchKernelGGL((k_combine<2, false>), grid, block, 0, s, views, split_views); break;
+        case 5: hipLaunchKernelGGL((k_combine<2, true>), grid, block, 0, s, views, split_views); break;
+        case 6: hipLaunchKernelGGL((k_combine<3, false>), grid, block, 0, s, views, split_views); break;
+        case 7: hipLaunchKernelGGL((k_combine<3, true>), grid, block, 0, s, views, split_views); break;
+        case 8: hipLaunchKernelGGL((k_combine<4, false>), grid, block, 0, s, views, split_views); break;
+        default: hipLaunchKernelGGL((k_combine<4, true>), grid, block, 0, s, views, split_views); break;
+        }
     }
     return hipGetLastError();
 }

@@ -3,6 +3,7 @@
 // and render_kernels.hip; this file only decides what to launch.
 #include "../../include/octree_rc.h"
 #include "internal.h"
+#include "raycommon.h"
 
 #include <algorithm>
 #include <cmath>
@@ -58,8 +59,6 @@ struct RenderSlot {
     Stage st;
     float *part = nullptr;   // depth-segment results of split views ([nsplit][pixel] float4)
     size_t part_cap = 0;
-    void *tables = nullptr;  // per-view transfer-function tables of the launch
-    size_t tables_cap = 0;
     uint32_t *tmask = nullptr;  // per-view cell transparency masks of the launch
     size_t tmask_cap = 0;
     int32_t *gorder = nullptr;  // per-view tile-group dispatch orders (+ length classes)
@@ -304,10 +303,40 @@ RecordLayout record_layout(size_t n_views, size_t n_split, size_t n_refine)
     return l;
 }
 
+// Offset of the view tables behind a launch's host records (they are copied together).
+size_t tables_offset(const RecordLayout &l) { return (l.c_off + l.c_bytes + 255) & ~(size_t)255; }
+
 size_t noalloc_record_bytes()
 {
     const RecordLayout l = record_layout(kNoAllocMaxViews, kNoAllocMaxViews, kNoAllocMaxViews);
-    return l.c_off + l.c_bytes;
+    return tables_offset(l) + (size_t)kNoAllocMaxViews * view_tables_bytes(kMaxC);
+}
+
+// Every view's transfer-function tables, built on the host into the launch's records.
+void fill_tables(int C, const DevView *dvs, int n_views, uint8_t *dst, size_t tbytes)
+{
+    for (int i = 0; i < n_views; i++) {
+        uint8_t *t = dst + (size_t)i * tbytes;
+        switch (C) {
+        case 1: host_build_tables<1>(dvs[i], *(ViewTables<1> *)t); break;
+        case 2: host_build_tables<2>(dvs[i], *(ViewTables<2> *)t); break;
+        case 3: host_build_tables<3>(dvs[i], *(ViewTables<3> *)t); break;
+        default: host_build_tables<4>(dvs[i], *(ViewTables<4> *)t); break;
+        }
+    }
+}
+
+// Views whose tile groups are dispatched longest first (the order is built on the device per
+// launch, on the preparation stream): the whole image of a launch's only view, when it has
+// more than 1024 groups (above 512x512 pixels) -- there the longest rays set the launch's
+// duration; smaller launches end soon either way.  Launches of several
+// views or tile ranges (a serving mix) keep index order: they overlap other launches, which
+// fill their tails, and an order kernel would have to wait for execution slots behind those
+// launches' renders before this one could start.
+bool view_ordered(const DevView &v, int n_views)
+{
+    const int tiles = v.tiles_x * ((v.height + OCT_TILE - 1) / OCT_TILE);
+    return n_views == 1 && v.tile_begin == 0 && v.tile_end == tiles && v.groups > 1024;
 }
 
 // Address of `scratch` on device `dev` (the current device), looked up once per device.
@@ -735,7 +764,6 @@ int octree_destroy(oct_handle *h)
     for (auto &r : h->rs) {
         stage_free(r.st);
         if (r.part) (void)hipFree(r.part);
-        if (r.tables) (void)hipFree(r.tables);
         if (r.tmask) (void)hipFree(r.tmask);
         if (r.gorder) (void)hipFree(r.gorder);
         if (r.prep) (void)hipEventDestroy(r.prep);
@@ -1466,6 +1494,7 @@ struct LaunchPlan {
     int64_t max_split_pixels = 0;
     int64_t max_refine_pixels = 0;
     int n_split = 0;
+    int split_modes = 0;             // bit 0: a split DVR view, bit 1: a split MIP view
     int n_refine = 0;
     int n_skip = 0;
     size_t part_floats = 0;          // segment results of split views without checkpoints
@@ -1537,6 +1566,7 @@ static int plan_launch(oct_handle *h, int32_t n_views, const oct_view *views,
                     pl.part_floats += (size_t)nsplit * npix * 4;
                 }
                 split[pl.n_split++] = j;
+                pl.split_modes |= views[i].mode == OCT_MODE_MIP ? 2 : 1;
                 pl.max_split_pixels = std::max<int64_t>(pl.max_split_pixels, (int64_t)npix);
             }
             if (views[i].missing == OCT_MISSING_REFINE) {
@@ -1591,9 +1621,11 @@ int render_views(oct_handle *h, int32_t n_views, const oct_view *views, float *c
         if (rc) return rc;
     }
     const RecordLayout l = record_layout((size_t)n_views, (size_t)pl.n_split, (size_t)pl.n_refine);
+    const size_t tbytes = view_tables_bytes(h->g.C);
+    const size_t t_off = tables_offset(l), rec_bytes = t_off + (size_t)n_views * tbytes;
     RenderSlot &rs = h->rs[h->next_rs];
     h->next_rs = (h->next_rs + 1) % kRenderSlots;
-    int rc = stage_reserve(h, rs.st, l.c_off + l.c_bytes);   // the slot is idle now
+    int rc = stage_reserve(h, rs.st, rec_bytes);   // the slot is idle now
     rs.version = h->version;
     if (!rc) rc = collect_kernel_time(h, rs);
     if (rc) return rc;
@@ -1609,15 +1641,6 @@ int render_views(oct_handle *h, int32_t n_views, const oct_view *views, float *c
         const int32_t j = split_views[k];
         if (!dvs[j].part) dvs[j].part = rs.part + part_at[j];
     }
-    const size_t tbytes = view_tables_bytes(h->g.C);
-    if ((size_t)n_views * tbytes > rs.tables_cap) {
-        if (rs.tables) HIPCHK(h, hipFree(rs.tables));
-        rs.tables = nullptr;
-        rs.tables_cap = 0;
-        HIPCHK(h, hipMalloc(&rs.tables, (size_t)n_views * tbytes));
-        rs.tables_cap = (size_t)n_views * tbytes;
-    }
-    for (int i = 0; i < n_views; i++) dvs[i].tables = (const uint8_t *)rs.tables + (size_t)i * tbytes;
     const int64_t mwords = view_mask_words(h->n_cells);
     const int n_skip = pl.n_skip;
     if ((size_t)n_skip * mwords * 4 > rs.tmask_cap) {
@@ -1638,23 +1661,26 @@ int render_views(oct_handle *h, int32_t n_views, const oct_view *views, float *c
         HIPCHK(h, hipMalloc((void **)&rs.gorder, (size_t)pl.order_ints * 4));
         rs.gorder_cap = (size_t)pl.order_ints * 4;
     }
+    int n_ordered = 0;
     for (int i = 0, at = 0; i < n_views; i++) {
-        dvs[i].group_order = rs.gorder + at;   // written by the set-up kernel
+        const bool ord = view_ordered(dvs[i], n_views);
+        dvs[i].group_order = ord ? rs.gorder + at : nullptr;   // written by the order kernel
+        n_ordered += ord ? 1 : 0;
         at += 2 * dvs[i].groups;
         dvs[i].rwait = (int32_t *)(dp + l.rw_off) + i;
+        dvs[i].tables = dp + t_off + (size_t)i * tbytes;
     }
+    fill_tables(h->g.C, dvs.data(), n_views, hp + t_off, tbytes);
     std::memcpy(hp, dvs.data(), l.v_bytes);
     std::memcpy(hp + l.sv_off, split_views.data(), (size_t)pl.n_split * 4);
     std::memcpy(hp + l.rf_off, refine_views.data(), (size_t)pl.n_refine * 4);
     std::memset(hp + l.rw_off, 0, (size_t)n_views * 4);
     std::memset(hp + l.c_off, 0, l.c_bytes);
     // preparation on the prep stream (it overlaps the renders issued before this one): views,
-    // lists and zeroed wait counters (plus the zeroed sample counters when asked for), tables,
-    // group order
+    // lists, zeroed counters and the tables in one copy, then the tile-group orders
     if (!rs.prep) HIPCHK(h, hipEventCreateWithFlags(&rs.prep, hipEventDisableTiming));
-    HIPCHK(h, hipMemcpyAsync(rs.st.dev, hp, out ? l.c_off + l.c_bytes : l.sv_off + l.sv_bytes,
-                             hipMemcpyHostToDevice, h->prep));
-    HIPCHK(h, launch_view_prep(h->g, (const DevView *)dp, n_views, h->prep));
+    HIPCHK(h, hipMemcpyAsync(rs.st.dev, hp, rec_bytes, hipMemcpyHostToDevice, h->prep));
+    if (n_ordered) HIPCHK(h, launch_view_prep(h->g, (const DevView *)dp, n_views, h->prep));
     HIPCHK(h, hipEventRecord(rs.prep, h->prep));
     rc = wait_for(h, s, rs.prep);
     if (!rc) rc = wait_for(h, s, h->ev_upload);   // the node table and pool of the last upload
@@ -1673,7 +1699,7 @@ int render_views(oct_handle *h, int32_t n_views, const oct_view *views, float *c
         rs.k_pending = true;
     }
     HIPCHK(h, launch_combine((const DevView *)dp, (const int32_t *)(dp + l.sv_off), pl.n_split,
-                             h->g.C, pl.max_split_pixels, s));
+                             h->g.C, pl.split_modes, pl.max_split_pixels, s));
     HIPCHK(h, launch_refine_finish((const DevView *)dp, (const int32_t *)(dp + l.rf_off),
                                    pl.n_refine, h->g.C, pl.max_refine_pixels, s));
     if (out) {
@@ -1707,11 +1733,11 @@ int render_views_noalloc(oct_handle *h, int32_t n_views, const oct_view *views,
     int rc = plan_launch(h, n_views, views, images, ckpt_ws, false, dvs, split, refine, nullptr, pl);
     if (rc) return rc;
     const RecordLayout l = record_layout((size_t)n_views, (size_t)pl.n_split, (size_t)pl.n_refine);
-    // scratch: records | tables | masks | tile-group orders
+    // scratch: records and tables (one copy) | masks | tile-group orders
     const size_t tbytes = view_tables_bytes(h->g.C);
     const int64_t mwords = view_mask_words(h->n_cells);
-    const size_t t_off = (l.c_off + l.c_bytes + 255) & ~(size_t)255;
-    const size_t m_off = (t_off + (size_t)n_views * tbytes + 255) & ~(size_t)255;
+    const size_t t_off = tables_offset(l), rec_bytes = t_off + (size_t)n_views * tbytes;
+    const size_t m_off = (rec_bytes + 255) & ~(size_t)255;
     const size_t g_off = (m_off + (size_t)pl.n_skip * mwords * 4 + 255) & ~(size_t)255;
     const size_t need = g_off + (size_t)pl.order_ints * 4;
     if (need > kScratchBytes)
@@ -1720,13 +1746,17 @@ int render_views_noalloc(oct_handle *h, int32_t n_views, const oct_view *views,
                         " bytes of device scratch, the limit is " + std::to_string(kScratchBytes) +
                         " (fewer or smaller views per call, or render_views)");
     uint8_t *dp = (uint8_t *)h->scratch_dev;
+    int n_ordered = 0;
     for (int i = 0, j = 0, at = 0; i < n_views; i++) {
+        const bool ord = view_ordered(dvs[i], n_views);
         dvs[i].tables = dp + t_off + (size_t)i * tbytes;
         dvs[i].tmask = dvs[i].skip ? (uint32_t *)(dp + m_off) + (size_t)(j++) * mwords : nullptr;
-        dvs[i].group_order = (int32_t *)(dp + g_off) + at;   // written by the set-up kernel
+        dvs[i].group_order = ord ? (int32_t *)(dp + g_off) + at : nullptr;   // order kernel
+        n_ordered += ord ? 1 : 0;
         dvs[i].rwait = (int32_t *)(dp + l.rw_off) + i;
         at += 2 * dvs[i].groups;
     }
+    fill_tables(h->g.C, dvs, n_views, hp + t_off, tbytes);
     std::memcpy(hp + l.sv_off, split, (size_t)pl.n_split * 4);
     std::memcpy(hp + l.rf_off, refine, (size_t)pl.n_refine * 4);
     std::memset(hp + l.rw_off, 0, (size_t)n_views * 4);
@@ -1739,17 +1769,16 @@ int render_views_noalloc(oct_handle *h, int32_t n_views, const oct_view *views,
     // an upload that rewrites what renders of an older table read waits for this slot's event,
     // which follows the previous launch too: keep the older version while that one may run
     rs.version = hipEventQuery(rs.st.ev) == hipSuccess ? h->version : std::min(rs.version, h->version);
-    HIPCHK(h, hipMemcpyAsync(dp, hp, out ? l.c_off + l.c_bytes : l.sv_off + l.sv_bytes,
-                             hipMemcpyHostToDevice, s));
+    HIPCHK(h, hipMemcpyAsync(dp, hp, rec_bytes, hipMemcpyHostToDevice, s));
     HIPCHK(h, hipEventRecord(h->na_copy, s));
-    HIPCHK(h, launch_view_prep(h->g, (const DevView *)dp, n_views, s));
+    if (n_ordered) HIPCHK(h, launch_view_prep(h->g, (const DevView *)dp, n_views, s));
     if (pl.n_skip)
         HIPCHK(h, launch_view_mask(h->g, (const DevView *)dp, n_views, h->table, h->n_cells, s));
     HIPCHK(h, launch_render(h->g, h->table, h->pool, h->brick_bytes, (const DevView *)dp, n_views,
                             pl.class_items, out ? (RenderCounters *)(dp + l.c_off) : nullptr,
                             h->capped ? h->flags : nullptr, s));
     HIPCHK(h, launch_combine((const DevView *)dp, (const int32_t *)(dp + l.sv_off), pl.n_split,
-                             h->g.C, pl.max_split_pixels, s));
+                             h->g.C, pl.split_modes, pl.max_split_pixels, s));
     HIPCHK(h, launch_refine_finish((const DevView *)dp, (const int32_t *)(dp + l.rf_off),
                                    pl.n_refine, h->g.C, pl.max_refine_pixels, s));
     if (out) {

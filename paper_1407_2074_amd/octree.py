@@ -209,6 +209,7 @@ class Octree:
             raise OctError(rc, lib.oct_last_error(None).decode())
         self.h = h
         self.dims, self.C, self.M, self.dtype = tuple(int(d) for d in dims), channels, brick, dtype
+        self.pool_bytes = int(pool_bytes)          # 0: uncapped (every brick resident)
         lv, bb, ns = ct.c_int32(), ct.c_uint64(), ct.c_uint64()
         lib.octree_info(self.h, ct.byref(lv), ct.byref(bb), ct.byref(ns))
         self.levels, self.brick_bytes, self.pool_slots = lv.value, bb.value, ns.value

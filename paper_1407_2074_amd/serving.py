@@ -4,10 +4,19 @@ Requests (camera, image size, transfer functions, clipping planes) arrive over t
 split into 8x8-pixel tiles; every scheduler tick builds ONE render_views launch from the tile
 chunks of all admitted requests (oldest first, round-robin over requests within the tick's
 tile budget) and enqueues it on the next of K HIP streams, so launches of different ticks run
-concurrently and a small request is never stuck behind a large one.  A request is admitted
-when its framebuffer fits under the memory cap (and the octree's brick pool is resident);
-it completes when the event of the last launch holding one of its tiles has fired.  Latency
-is arrival -> completion.
+concurrently and a small request is never stuck behind a large one.  A request completes when
+the event of the last launch holding one of its tiles has fired.  Latency is arrival ->
+completion.
+
+Admission is by device memory:
+  * framebuffer: the images of the admitted requests stay under `fb_cap_bytes`;
+  * brick pool: the bricks the admitted requests sample stay under `pool_cap_bytes` (default:
+    the octree's pool cap; none for an uncapped, fully resident octree).  Requests at the same level of detail share bricks, so the demand of a
+    set of requests is the sum, over the distinct levels they render at, of the level's brick
+    nodes (the cells of that level inside the volume -- an upper bound) times the brick size.
+    A request's level is its fixed LOD, or for the per-ray footprint LOD the level whose voxel
+    projects to about one pixel at the distance from its eye to the volume centre.
+A request that alone exceeds a cap is admitted when nothing else is in flight.
 
 Each pixel depends only on its own ray, so a request's image is the same whether it is
 rendered alone or inside any mix (bit-identical).
@@ -36,6 +45,7 @@ class Request:
     pending: int = 0        # launches in flight that hold tiles of this request
     admitted: float = -1.0
     done: float = -1.0
+    lod_level: int = 0      # level of detail it renders at (set on admission)
 
     @property
     def n_tiles(self) -> int:
@@ -44,6 +54,16 @@ class Request:
     @property
     def fb_bytes(self) -> int:
         return self.view.width * self.view.height * 16
+
+    def level(self, N: int, dims) -> int:
+        """The level of detail the request renders at (see the module docstring)."""
+        v = self.view
+        if v.lod >= 0:
+            return min(int(v.lod), N)
+        centre = np.array(dims, np.float64) / 2
+        dist = float(np.linalg.norm(np.asarray(v.eye, np.float64) - centre))
+        w = 2.0 * dist * math.tan(math.radians(v.fov_y_deg) / 2) / v.height
+        return int(min(max(math.floor(math.log2(w)), 0), N)) if w > 0 else 0
 
 
 @dataclasses.dataclass
@@ -57,6 +77,7 @@ class ServeStats:
     launches: int
     max_fb_bytes_in_use: int
     max_in_flight: int
+    max_pool_bytes_in_use: int = 0
 
     def as_dict(self):
         return dataclasses.asdict(self)
@@ -70,7 +91,8 @@ class Server:
     admitted requests; chunk_tiles: largest tile range of one request inside one launch."""
 
     def __init__(self, tree: Octree, streams: int = 3, tiles_per_launch: int = 16384,
-                 chunk_tiles: int = 4096, fb_cap_bytes: int = 2 << 30, max_in_flight: int = 3):
+                 chunk_tiles: int = 4096, fb_cap_bytes: int = 2 << 30, max_in_flight: int = 3,
+                 pool_cap_bytes: int | None = None):
         import torch
         self.torch = torch
         self.tree = tree
@@ -79,6 +101,25 @@ class Server:
         self.chunk_tiles = chunk_tiles
         self.fb_cap = fb_cap_bytes
         self.max_in_flight = min(max_in_flight, streams)
+        # default: the octree's capped pool; an uncapped octree holds every brick, so no set
+        # of requests can exceed it
+        if pool_cap_bytes is None:
+            pool_cap_bytes = tree.pool_bytes if tree.pool_bytes > 0 else float("inf")
+        self.pool_cap = pool_cap_bytes
+        # brick nodes per level at most: the level's cells inside the volume
+        M, N = tree.M, tree.levels - 1
+        self.N = N
+        self.level_bytes = []
+        for L in range(N + 1):
+            cells = 1
+            for d in tree.dims:
+                ext = -(-d // (1 << L))          # valid extent of level L along this axis
+                cells *= -(-ext // M)            # its cells, rounded up
+            self.level_bytes.append(cells * tree.brick_bytes)
+
+    def pool_demand(self, levels) -> int:
+        """Brick-pool bytes of requests rendering at these levels (each level's bricks once)."""
+        return sum(self.level_bytes[L] for L in set(levels))
 
     def run(self, requests, realtime: bool = True, on_complete=None) -> ServeStats:
         """Serve `requests` (sorted by arrival).  With realtime=False arrivals are taken as
@@ -88,8 +129,9 @@ class Server:
         queue = collections.deque(sorted(requests, key=lambda r: r.arrival))
         active: list[Request] = []
         inflight = collections.deque()        # (event, [requests], stream)
-        fb_used = max_fb = 0
+        fb_used = max_fb = max_pool = 0
         launches = max_inflight = 0
+        level_use = collections.Counter()     # admitted requests per level of detail
         done: list[Request] = []
         si = 0
         t_start = time.perf_counter()
@@ -113,16 +155,23 @@ class Server:
                         r.done = now()
                         active.remove(r)
                         fb_used -= r.fb_bytes
+                        level_use[r.lod_level] -= 1
+                        if level_use[r.lod_level] == 0:
+                            del level_use[r.lod_level]
                         done.append(r)
                         if on_complete:
                             on_complete(r)
-            # admit arrivals while framebuffer memory allows
+            # admit arrivals while framebuffer and brick-pool memory allow
             t = now()
             while queue and (not realtime or queue[0].arrival <= t):
                 r = queue[0]
-                if fb_used + r.fb_bytes > self.fb_cap and active:
+                r.lod_level = r.level(self.N, self.tree.dims)
+                pool = self.pool_demand(list(level_use) + [r.lod_level])
+                if active and (fb_used + r.fb_bytes > self.fb_cap or pool > self.pool_cap):
                     break
                 queue.popleft()
+                level_use[r.lod_level] += 1
+                max_pool = max(max_pool, pool)
                 r.image = torch.empty((r.view.height, r.view.width, 4), dtype=torch.float32,
                                       device="cuda")
                 r.admitted = t
@@ -176,7 +225,8 @@ class Server:
                           latency_p50_ms=float(np.percentile(lat, 50)),
                           latency_p99_ms=float(np.percentile(lat, 99)),
                           latency_mean_ms=float(lat.mean()), launches=launches,
-                          max_fb_bytes_in_use=max_fb, max_in_flight=max_inflight)
+                          max_fb_bytes_in_use=max_fb, max_in_flight=max_inflight,
+                          max_pool_bytes_in_use=max_pool)
 
 
 def poisson_requests(dims, channels: int, n: int, rate: float, seed: int = 5,
