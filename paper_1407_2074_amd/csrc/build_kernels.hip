@@ -15,6 +15,7 @@ namespace octrc {
 namespace {
 
 constexpr int kThreads = 256;
+constexpr int kXcds = 8;        // MI355X: 8 XCDs of 32 CUs, one L2 each
 
 template <typename T>
 __device__ inline T *level_ptr(T *master, const VolGeom &g, int L, int c)
@@ -23,9 +24,73 @@ __device__ inline T *level_ptr(T *master, const VolGeom &g, int L, int c)
     return master + g.lvl_off[L] + (int64_t)c * n;
 }
 
+// Eight consecutive elements moved as 16-byte words (one for uint16, two for float32).
+template <typename T> struct Pack8;
+template <> struct Pack8<uint16_t> {
+    uint4 w;
+    __device__ static Pack8 load(const uint16_t *p) { return {*(const uint4 *)p}; }
+    __device__ void store(uint16_t *p) const { *(uint4 *)p = w; }
+    __device__ uint32_t at(int i) const
+    {
+        const uint32_t d = i < 2 ? w.x : i < 4 ? w.y : i < 6 ? w.z : w.w;
+        return (i & 1) ? d >> 16 : d & 0xffffu;
+    }
+};
+template <> struct Pack8<float> {
+    float4 a, b;
+    __device__ static Pack8 load(const float *p) { return {((const float4 *)p)[0], ((const float4 *)p)[1]}; }
+    __device__ void store(float *p) const
+    {
+        ((float4 *)p)[0] = a;
+        ((float4 *)p)[1] = b;
+    }
+    __device__ float at(int i) const
+    {
+        const float4 &q = i < 4 ? a : b;
+        const int j = i & 3;
+        return j == 0 ? q.x : j == 1 ? q.y : j == 2 ? q.z : q.w;
+    }
+};
+
 // ---------------------------------------------------------------------------------------
 // Step 1 of incremental construction: copy a block into level 0 and record which channels
-// of each voxel have been inserted (completeness tracking).
+// of each voxel have been inserted (completeness tracking).  Two forms: k_insert8 moves eight
+// voxels per thread with 16-byte accesses (block origin, width and volume width multiples of
+// eight, 16-byte-aligned source); k_insert takes any block, one voxel per thread.
+template <typename T>
+__global__ void __launch_bounds__(kThreads)
+k_insert8(VolGeom g, T *__restrict__ master, uint8_t *__restrict__ mask,
+          const T *__restrict__ src, int channel, int x0, int y0, int z0, int nx, int ny, int nz)
+{
+    const int nq = nx >> 3;
+    const int64_t items = (int64_t)nq * ny * nz;
+    const int cb = channel < 0 ? g.C : 1;
+    const int64_t nvox0 = (int64_t)g.dims[0] * g.dims[1] * g.dims[2];
+    const int64_t nblk = (int64_t)nx * ny * nz;
+    uint32_t bits = 0;
+    for (int c = 0; c < cb; c++) bits |= 1u << (channel < 0 ? c : channel);
+    const uint32_t bits4 = bits * 0x01010101u;
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < items;
+         i += (int64_t)gridDim.x * kThreads) {
+        const int q = (int)(i % nq);
+        const int64_t row = i / nq;
+        const int y = (int)(row % ny), z = (int)(row / ny);
+        const int64_t lin = ((int64_t)(z0 + z) * g.dims[1] + (y0 + y)) * g.dims[0] + x0 + 8 * q;
+        const int64_t sl = row * nx + 8 * q;
+        Pack8<T> v[kMaxC];
+#pragma unroll
+        for (int c = 0; c < kMaxC; c++)
+            if (c < cb) v[c] = Pack8<T>::load(src + c * nblk + sl);
+        uint2 m = *(const uint2 *)(mask + lin);
+#pragma unroll
+        for (int c = 0; c < kMaxC; c++)
+            if (c < cb) v[c].store(master + g.lvl_off[0] + (int64_t)(channel < 0 ? c : channel) * nvox0 + lin);
+        m.x |= bits4;
+        m.y |= bits4;
+        *(uint2 *)(mask + lin) = m;
+    }
+}
+
 template <typename T>
 __global__ void __launch_bounds__(kThreads)
 k_insert(VolGeom g, T *master, uint8_t *mask, const T *src, int channel, int x0, int y0, int z0,
@@ -58,6 +123,67 @@ __device__ inline uint32_t mean_rhu(uint32_t s, uint32_t n)
 {
     const uint32_t sh = n == 8 ? 4u : n == 4 ? 3u : n == 2 ? 2u : 1u;  // log2(2n)
     return (2u * s + n) >> sh;
+}
+
+// Four parents along x per thread from 16-byte child loads.  Needs level L's rows and both
+// levels' channel planes aligned to eight (L) and four (L + 1) elements; the host checks.
+// The x range is widened to whole groups of four: a parent outside the requested range is
+// recomputed from unchanged children, which rewrites the value it already holds.
+template <typename T>
+__global__ void __launch_bounds__(kThreads)
+k_downsample4(VolGeom g, T *__restrict__ master, int L, int qx0, int nq, int ly, int lz, int ny,
+              int nz)
+{
+    const int ex = g.ext[L][0], ey = g.ext[L][1], ez = g.ext[L][2];
+    const int px = g.ext[L + 1][0], py = g.ext[L + 1][1];
+    const int64_t items = (int64_t)nq * ny * nz;
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < items;
+         i += (int64_t)gridDim.x * kThreads) {
+        const int x4 = 4 * (qx0 + (int)(i % nq));
+        const int64_t row = i / nq;
+        const int y = ly + (int)(row % ny), z = lz + (int)(row / ny);
+        const int nyv = (2 * y + 1 < ey) ? 2 : 1, nzv = (2 * z + 1 < ez) ? 2 : 1;
+        const uint32_t sh = 2u + (nyv == 2) + (nzv == 2);        // log2(2n), n = 2 nyv nzv
+        const uint32_t n = 2u * nyv * nzv;
+        for (int c = 0; c < g.C; c++) {
+            const T *src = level_ptr(master, g, L, c);
+            T *dst = level_ptr(master, g, L + 1, c) + ((int64_t)z * py + y) * px + x4;
+            Pack8<T> r[4];
+#pragma unroll
+            for (int k = 0; k < 4; k++) {
+                const int dz = k >> 1, dy = k & 1;
+                if (dz < nzv && dy < nyv)
+                    r[k] = Pack8<T>::load(src + ((int64_t)(2 * z + dz) * ey + (2 * y + dy)) * ex + 2 * x4);
+            }
+            if constexpr (sizeof(T) == 2) {
+                uint32_t s[4] = {0, 0, 0, 0};
+#pragma unroll
+                for (int k = 0; k < 4; k++) {
+                    const int dz = k >> 1, dy = k & 1;
+                    if (dz < nzv && dy < nyv)
+#pragma unroll
+                        for (int j = 0; j < 4; j++) s[j] += r[k].at(2 * j) + r[k].at(2 * j + 1);
+                }
+                uint2 o;
+                o.x = ((2u * s[0] + n) >> sh) | (((2u * s[1] + n) >> sh) << 16);
+                o.y = ((2u * s[2] + n) >> sh) | (((2u * s[3] + n) >> sh) << 16);
+                *(uint2 *)dst = o;
+            } else {
+                double s[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int k = 0; k < 4; k++) {
+                    const int dz = k >> 1, dy = k & 1;
+                    if (dz < nzv && dy < nyv)
+#pragma unroll
+                        for (int j = 0; j < 4; j++)
+                            s[j] += (double)r[k].at(2 * j) + (double)r[k].at(2 * j + 1);
+                }
+                const double inv = 1.0 / (double)n;
+                *(float4 *)dst = make_float4((float)(s[0] * inv), (float)(s[1] * inv),
+                                             (float)(s[2] * inv), (float)(s[3] * inv));
+            }
+        }
+    }
 }
 
 template <typename T>
@@ -135,14 +261,20 @@ struct StatPart {
 struct MinF { __device__ float operator()(float a, float b) const { return fminf(a, b); } };
 struct MaxF { __device__ float operator()(float a, float b) const { return fmaxf(a, b); } };
 
+// Cells of levels whose rows and channel planes are aligned to eight elements, with M a
+// multiple of eight (a cell row is whole 8-element words; bit L of `vec_levels`), are read a
+// 16-byte word per thread and step, every channel at once; other levels' cells one element per
+// thread.  The block folds every statistic in one pass through LDS.
 template <typename T>
 __global__ void __launch_bounds__(kThreads)
-k_stats_part(VolGeom g, const T *master, const uint8_t *mask, const int4 *cells, int nsub,
-             StatPart *part)
+k_stats_part(VolGeom g, const T *__restrict__ master, const uint8_t *__restrict__ mask,
+              const int4 *cells, int nsub, uint32_t vec_levels, StatPart *part)
 {
-    __shared__ float sf[kThreads / 64];
-    __shared__ double sd[kThreads / 64];
-    __shared__ unsigned long long su[kThreads / 64];
+    constexpr int kW = kThreads / 64;
+    __shared__ float s_mn[kW][kMaxC], s_mx[kW][kMaxC];
+    __shared__ unsigned long long s_su[kW][kMaxC];
+    __shared__ double s_sd[kW][kMaxC];
+    __shared__ uint32_t s_in[kW][kMaxC];
     const int4 cl = cells[blockIdx.x / nsub];
     const int sub = blockIdx.x % nsub;
     const int L = cl.x;
@@ -154,48 +286,113 @@ k_stats_part(VolGeom g, const T *master, const uint8_t *mask, const int4 *cells,
     }
     const int zc = (n[2] + nsub - 1) / nsub;
     const int zs = min(sub * zc, n[2]), ze = min(zs + zc, n[2]);
-    const int rstep = kThreads / n[0];            // rows per pass (n[0] <= 128)
-    const int x = threadIdx.x % n[0], r0 = threadIdx.x / n[0];
-    const bool on = r0 < rstep;
     const int ex = g.ext[L][0], ey = g.ext[L][1];
-    StatPart *o = part + blockIdx.x;
-    for (int c = 0; c < g.C; c++) {
-        const T *src = level_ptr(master, g, L, c);
-        float mn = FLT_MAX, mx = -FLT_MAX;
-        double sm = 0.0;
-        uint32_t su_local = 0;
-        if (on)
+    const int64_t nlev = (int64_t)ex * ey * g.ext[L][2];
+    const bool wide = (vec_levels >> L) & 1u;
+    const int C = g.C;
+    float mn[kMaxC], mx[kMaxC];
+    uint32_t su[kMaxC], cnt[kMaxC];
+    double sd[kMaxC];
+    for (int c = 0; c < kMaxC; c++) {
+        mn[c] = FLT_MAX;
+        mx[c] = -FLT_MAX;
+        su[c] = cnt[c] = 0;
+        sd[c] = 0.0;
+    }
+    const T *src = master + g.lvl_off[L];
+    if (wide) {
+        const int nq = n[0] >> 3;                    // 8-element words per cell row
+        const int rows = (ze - zs) * n[1];
+        for (int j = threadIdx.x; j < rows * nq; j += kThreads) {
+            const int q = j % nq, r = j / nq;
+            const int y = lo[1] + r % n[1], z = lo[2] + zs + r / n[1];
+            const int64_t lin = ((int64_t)z * ey + y) * ex + lo[0] + 8 * q;
+            Pack8<T> v[kMaxC];
+#pragma unroll
+            for (int c = 0; c < kMaxC; c++)
+                if (c < C) v[c] = Pack8<T>::load(src + c * nlev + lin);
+#pragma unroll
+            for (int c = 0; c < kMaxC; c++)
+                if (c < C)
+#pragma unroll
+                    for (int e = 0; e < 8; e++) {
+                        const auto x = v[c].at(e);
+                        mn[c] = fminf(mn[c], (float)x);
+                        mx[c] = fmaxf(mx[c], (float)x);
+                        if constexpr (sizeof(T) == 2) su[c] += x;
+                        else sd[c] += (double)x;
+                    }
+            if (L == 0) {
+                const uint2 m = *(const uint2 *)(mask + lin);
+#pragma unroll
+                for (int c = 0; c < kMaxC; c++) {
+                    // bit c of each of the eight mask bytes, summed
+                    const uint32_t a = (m.x >> c) & 0x01010101u, bb = (m.y >> c) & 0x01010101u;
+                    cnt[c] += (uint32_t)__popc(a) + (uint32_t)__popc(bb);
+                }
+            }
+        }
+    } else {
+        const int rstep = kThreads / n[0];            // rows per pass (n[0] <= 128)
+        const int x = threadIdx.x % n[0], r0 = threadIdx.x / n[0];
+        if (r0 < rstep)
             for (int z = zs; z < ze; z++)
                 for (int y = r0; y < n[1]; y += rstep) {
-                    const T v = src[((int64_t)(lo[2] + z) * ey + (lo[1] + y)) * ex + (lo[0] + x)];
-                    mn = fminf(mn, (float)v);
-                    mx = fmaxf(mx, (float)v);
-                    if constexpr (sizeof(T) == 2) su_local += v;
-                    else sm += (double)v;
+                    const int64_t lin = ((int64_t)(lo[2] + z) * ey + (lo[1] + y)) * ex + (lo[0] + x);
+                    for (int c = 0; c < C; c++) {
+                        const T v = src[c * nlev + lin];
+                        mn[c] = fminf(mn[c], (float)v);
+                        mx[c] = fmaxf(mx[c], (float)v);
+                        if constexpr (sizeof(T) == 2) su[c] += v;
+                        else sd[c] += (double)v;
+                    }
+                    if (L == 0) {
+                        const uint32_t bits = mask[lin];
+                        for (int c = 0; c < kMaxC; c++) cnt[c] += (bits >> c) & 1u;
+                    }
                 }
-        mn = block_reduce(mn, MinF{}, sf);
-        mx = block_reduce(mx, MaxF{}, sf);
-        if constexpr (sizeof(T) == 2)
-            sm = (double)block_reduce((unsigned long long)su_local, AddU{}, su);
-        else
-            sm = block_reduce(sm, AddD{}, sd);
-        if (threadIdx.x == 0) {
-            o->mn[c] = mn;
-            o->mx[c] = mx;
-            o->sum[c] = sm;
-        }
     }
-    uint32_t cnt[kMaxC] = {0, 0, 0, 0};
-    if (L == 0 && on)
-        for (int z = zs; z < ze; z++)
-            for (int y = r0; y < n[1]; y += rstep) {
-                const uint32_t bits = mask[((int64_t)(lo[2] + z) * g.dims[1] + (lo[1] + y)) *
-                                               g.dims[0] + (lo[0] + x)];
-                for (int c = 0; c < kMaxC; c++) cnt[c] += (bits >> c) & 1u;
-            }
-    for (int c = 0; c < g.C; c++) {
-        const unsigned long long t = block_reduce((unsigned long long)cnt[c], AddU{}, su);
-        if (threadIdx.x == 0) o->ins[c] = (uint32_t)t;
+    // wave folds, then one LDS exchange for every statistic
+    unsigned long long sul[kMaxC];
+    for (int c = 0; c < kMaxC; c++) sul[c] = su[c];
+    for (int o = 32; o > 0; o >>= 1)
+        for (int c = 0; c < kMaxC; c++) {
+            mn[c] = fminf(mn[c], __shfl_xor(mn[c], o, 64));
+            mx[c] = fmaxf(mx[c], __shfl_xor(mx[c], o, 64));
+            if constexpr (sizeof(T) == 2) sul[c] += __shfl_xor(sul[c], o, 64);
+            else sd[c] += __shfl_xor(sd[c], o, 64);
+            cnt[c] += __shfl_xor(cnt[c], o, 64);
+        }
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0)
+        for (int c = 0; c < kMaxC; c++) {
+            s_mn[w][c] = mn[c];
+            s_mx[w][c] = mx[c];
+            s_su[w][c] = sul[c];
+            s_sd[w][c] = sd[c];
+            s_in[w][c] = cnt[c];
+        }
+    __syncthreads();
+    if (threadIdx.x < kMaxC) {
+        const int c = threadIdx.x;
+        float a = s_mn[0][c], z = s_mx[0][c];
+        unsigned long long u = s_su[0][c];
+        double d = s_sd[0][c];
+        uint32_t k = s_in[0][c];
+        for (int i = 1; i < kW; i++) {
+            a = fminf(a, s_mn[i][c]);
+            z = fmaxf(z, s_mx[i][c]);
+            u += s_su[i][c];
+            d += s_sd[i][c];
+            k += s_in[i][c];
+        }
+        StatPart *o = part + blockIdx.x;
+        if (c < C) {
+            o->mn[c] = a;
+            o->mx[c] = z;
+            o->sum[c] = sizeof(T) == 2 ? (double)u : d;
+        }
+        o->ins[c] = k;
     }
 }
 
@@ -256,6 +453,10 @@ k_apply_deltas(DevCell *table, float *miss_range, const CellDelta *d, int n)
 // (the job's rows are short, 34 voxels for 32^3 bricks: a thread-per-row walk is
 // latency-bound).  Uploads run while renders occupy most wave slots of every CU: 4-wave
 // workgroups fit beside them, 16-wave ones waited for whole CUs to drain.
+// Jobs are listed x-fastest, and x-neighbours read the same 64-byte segments of each other's
+// border rows.  Workgroups are dealt to the eight XCDs (each with its own L2) round robin, so
+// workgroup w takes job (w % 8) * per + w / 8 (per = jobs per XCD): an XCD works through a
+// contiguous run of jobs and neighbours find the shared segments in its L2.
 #ifndef OCTRC_GATHER_THREADS
 #define OCTRC_GATHER_THREADS 256
 #endif
@@ -264,12 +465,15 @@ constexpr int kGatherThreads = OCTRC_GATHER_THREADS;
 template <typename T>
 __global__ void __launch_bounds__(kGatherThreads)
 k_gather(VolGeom g, const T *master, const DevCell *table, uint8_t *pool, uint64_t brick_bytes,
-         const BrickJob *jobs, float *slot_range, float background)
+         const BrickJob *jobs, int n_jobs, float *slot_range, float background)
 {
     __shared__ int s_kind[27];
     __shared__ float s_avg[27][4];
     __shared__ float sf[kGatherThreads / 64];
-    const BrickJob job = jobs[blockIdx.x];
+    const int per = (int)(gridDim.x / kXcds);
+    const int jid = (int)(blockIdx.x % kXcds) * per + (int)(blockIdx.x / kXcds);
+    if (jid >= n_jobs) return;
+    const BrickJob job = jobs[jid];
     const int L = job.level, M = g.M, S = M + 2, G = g.grid[L];
     const int b[3] = {job.bx, job.by, job.bz};
     if (threadIdx.x < 27) {
@@ -401,6 +605,21 @@ inline unsigned ceil_div(int64_t a, int64_t b) { return (unsigned)((a + b - 1) /
 hipError_t launch_insert(const VolGeom &g, void *master, uint8_t *mask, const void *src,
                          int channel, const int32_t o[3], const int32_t n[3], hipStream_t s)
 {
+    if ((int64_t)n[0] * n[1] * n[2] == 0) return hipSuccess;
+    const bool wide = o[0] % 8 == 0 && n[0] % 8 == 0 && g.dims[0] % 8 == 0 && g.lvl_off[0] % 8 == 0 &&
+                      ((uintptr_t)src & 15) == 0 && ((uintptr_t)master & 15) == 0 &&
+                      ((uintptr_t)mask & 15) == 0;
+    if (wide) {
+        const int64_t items = (int64_t)(n[0] / 8) * n[1] * n[2];
+        const dim3 grid((unsigned)std::min<int64_t>(ceil_div(items, kThreads), 1 << 20));
+        if (g.dtype == 0)
+            hipLaunchKernelGGL(k_insert8<uint16_t>, grid, dim3(kThreads), 0, s, g, (uint16_t *)master,
+                               mask, (const uint16_t *)src, channel, o[0], o[1], o[2], n[0], n[1], n[2]);
+        else
+            hipLaunchKernelGGL(k_insert8<float>, grid, dim3(kThreads), 0, s, g, (float *)master, mask,
+                               (const float *)src, channel, o[0], o[1], o[2], n[0], n[1], n[2]);
+        return hipGetLastError();
+    }
     dim3 grid(ceil_div(n[0], kThreads), (unsigned)std::min<int64_t>((int64_t)n[1] * n[2], 65535));
     if (g.dtype == 0)
         hipLaunchKernelGGL(k_insert<uint16_t>, grid, dim3(kThreads), 0, s, g, (uint16_t *)master,
@@ -411,10 +630,32 @@ hipError_t launch_insert(const VolGeom &g, void *master, uint8_t *mask, const vo
     return hipGetLastError();
 }
 
+// Level L's channel planes start on multiples of `a` elements and its rows are multiples of
+// `a` elements long.
+static bool level_aligned(const VolGeom &g, int L, int a)
+{
+    const int64_t plane = (int64_t)g.ext[L][0] * g.ext[L][1] * g.ext[L][2];
+    return g.ext[L][0] % a == 0 && g.lvl_off[L] % a == 0 && plane % a == 0;
+}
+
 hipError_t launch_downsample(const VolGeom &g, void *master, int L, const int32_t lo[3],
                              const int32_t hi[3], hipStream_t s)
 {
-    const int64_t rows = (int64_t)(hi[1] - lo[1] + 1) * (hi[2] - lo[2] + 1);
+    const int ny = hi[1] - lo[1] + 1, nz = hi[2] - lo[2] + 1;
+    if (hi[0] < lo[0] || ny <= 0 || nz <= 0) return hipSuccess;
+    if (level_aligned(g, L, 8) && level_aligned(g, L + 1, 4) && ((uintptr_t)master & 15) == 0) {
+        const int q0 = lo[0] / 4, nq = hi[0] / 4 - q0 + 1;
+        const int64_t items = (int64_t)nq * ny * nz;
+        const dim3 grid((unsigned)std::min<int64_t>(ceil_div(items, kThreads), 1 << 20));
+        if (g.dtype == 0)
+            hipLaunchKernelGGL(k_downsample4<uint16_t>, grid, dim3(kThreads), 0, s, g,
+                               (uint16_t *)master, L, q0, nq, lo[1], lo[2], ny, nz);
+        else
+            hipLaunchKernelGGL(k_downsample4<float>, grid, dim3(kThreads), 0, s, g, (float *)master,
+                               L, q0, nq, lo[1], lo[2], ny, nz);
+        return hipGetLastError();
+    }
+    const int64_t rows = (int64_t)ny * nz;
     dim3 grid(ceil_div(hi[0] - lo[0] + 1, kThreads), (unsigned)std::min<int64_t>(rows, 65535));
     if (g.dtype == 0)
         hipLaunchKernelGGL(k_downsample<uint16_t>, grid, dim3(kThreads), 0, s, g,
@@ -425,23 +666,30 @@ hipError_t launch_downsample(const VolGeom &g, void *master, int L, const int32_
     return hipGetLastError();
 }
 
+static int stats_nsub(const VolGeom &g) { return std::max(1, g.M / 8); }
+
 size_t stats_scratch_bytes(const VolGeom &g, int n)
 {
-    return (size_t)n * (size_t)std::max(1, g.M / 4) * sizeof(StatPart);
+    return (size_t)n * (size_t)stats_nsub(g) * sizeof(StatPart);
 }
 
 hipError_t launch_stats(const VolGeom &g, const void *master, const uint8_t *mask,
                         const int32_t *cells, int n, void *scratch, CellStat *out, hipStream_t s)
 {
     if (n == 0) return hipSuccess;
-    const int nsub = std::max(1, g.M / 4);
+    const int nsub = stats_nsub(g);
+    uint32_t vec_levels = 0;
+    if (g.M % 8 == 0 && ((uintptr_t)master & 15) == 0 && ((uintptr_t)mask & 15) == 0)
+        for (int L = 0; L <= g.N; L++)
+            if (level_aligned(g, L, 8)) vec_levels |= 1u << L;
     StatPart *part = (StatPart *)scratch;
     if (g.dtype == 0)
         hipLaunchKernelGGL(k_stats_part<uint16_t>, dim3(n * nsub), dim3(kThreads), 0, s, g,
-                           (const uint16_t *)master, mask, (const int4 *)cells, nsub, part);
+                           (const uint16_t *)master, mask, (const int4 *)cells, nsub, vec_levels,
+                           part);
     else
         hipLaunchKernelGGL(k_stats_part<float>, dim3(n * nsub), dim3(kThreads), 0, s, g,
-                           (const float *)master, mask, (const int4 *)cells, nsub, part);
+                           (const float *)master, mask, (const int4 *)cells, nsub, vec_levels, part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_stats_fold, dim3(ceil_div(n, kThreads)), dim3(kThreads), 0, s, n, nsub,
@@ -463,13 +711,14 @@ hipError_t launch_gather(const VolGeom &g, const void *master, const DevCell *ta
                          float background, hipStream_t s)
 {
     if (n == 0) return hipSuccess;
+    const dim3 grid((unsigned)(ceil_div(n, kXcds) * kXcds));
     if (g.dtype == 0)
-        hipLaunchKernelGGL(k_gather<uint16_t>, dim3(n), dim3(kGatherThreads), 0, s, g,
-                           (const uint16_t *)master, table, (uint8_t *)pool, brick_bytes, jobs,
+        hipLaunchKernelGGL(k_gather<uint16_t>, grid, dim3(kGatherThreads), 0, s, g,
+                           (const uint16_t *)master, table, (uint8_t *)pool, brick_bytes, jobs, n,
                            slot_range, background);
     else
-        hipLaunchKernelGGL(k_gather<float>, dim3(n), dim3(kGatherThreads), 0, s, g, (const float *)master,
-                           table, (uint8_t *)pool, brick_bytes, jobs, slot_range, background);
+        hipLaunchKernelGGL(k_gather<float>, grid, dim3(kGatherThreads), 0, s, g, (const float *)master,
+                           table, (uint8_t *)pool, brick_bytes, jobs, n, slot_range, background);
     return hipGetLastError();
 }
 
