@@ -93,14 +93,14 @@ struct DevView {
     // forward launches: this view's work items are item_begin ... item_begin + groups * nsplit
     // - 1 of the grid (groups of kRenderTilesPerWg tiles; order in item_of)
     int32_t item_begin, groups;
-    // [groups] the view's tile groups in dispatch order (longest estimated rays first), then
-    // [groups] scratch; written by k_view_prep each launch.  NULL: index order
+    // [groups] the view's tile groups in dispatch order (longest estimated rays first), built
+    // on the host and copied with the launch records.  NULL: index order
     int32_t *group_order;
     // adjoint only: dL/dimage of this view, dL/dtable accumulator [C][256][4]
     const float *dimg;
     float *dlut;
     // this view's transfer-function tables (value/slope and opacity prefix counts), built
-    // once per launch by k_view_prep and copied into LDS by every workgroup
+    // on the host per launch and copied into LDS by every workgroup
     const void *tables;
     // views with skipping: one bit per node-table cell, set when the cell is transparent for
     // this view (built per launch by k_view_mask from the current table); NULL otherwise
@@ -201,13 +201,10 @@ hipError_t launch_refine_finish(const DevView *views, const int32_t *refine_view
                                 int C, int64_t max_pixels, hipStream_t s);
 // Bytes of one view's tables for C channels (views[i].tables points at that many bytes, built
 // on the host) and 32-bit words of one view's transparency mask over n_cells node-table cells
-// (whole 64-cell groups).  Per launch, the preparation kernel builds the tile-group dispatch
-// order of every view with group_order != NULL (it reads only the views); the mask kernel,
-// after the last upload, fills the mask of every view with tmask != NULL from the node table
-// `table`.
+// (whole 64-cell groups).  Per launch, the mask kernel, after the last upload, fills the mask
+// of every view with tmask != NULL from the node table `table`.
 size_t view_tables_bytes(int C);
 inline int64_t view_mask_words(int64_t n_cells) { return (n_cells + 63) / 64 * 2; }
-hipError_t launch_view_prep(const VolGeom &g, const DevView *views, int n_views, hipStream_t s);
 hipError_t launch_view_mask(const VolGeom &g, const DevView *views, int n_views,
                             const DevCell *table, int64_t n_cells, hipStream_t s);
 // Front-to-back composite of the depth segments of every split view into its image.

@@ -11,6 +11,20 @@
 
 namespace octrc {
 
+// Tile q of tile group gi. A whole image with an even number of tile rows and columns is
+// grouped in 2x2 blocks of tiles (the four waves of a workgroup share L1); otherwise a group is
+// four consecutive tiles of the view's row-major tile range.
+__host__ __device__ inline int group_tile(const DevView &V, int gi, int q)
+{
+    const int ty = (V.height + 7) >> 3;
+    if (kRenderTilesPerWg == 4 && V.tile_begin == 0 && V.tile_end == V.tiles_x * ty &&
+        !(V.tiles_x & 1) && !(ty & 1)) {
+        const int hx = V.tiles_x >> 1, gx = gi % hx, gy = gi / hx;
+        return (2 * gy + (q >> 1)) * V.tiles_x + 2 * gx + (q & 1);
+    }
+    return V.tile_begin + gi * kRenderTilesPerWg + q;
+}
+
 __device__ inline float lerpf(float a, float b, float t) { return __builtin_fmaf(t, b - a, a); }
 
 // Control-point segment and weight of table entry k (x = k/255): the entry is

@@ -2,9 +2,9 @@
 // (or per depth segment of a tile's rays), several tiles of one view per workgroup
 // (kRenderTilesPerWg waves).
 //
-// Per launch, k_view_prep tabulates each view's transfer functions (256 RGBA value/slope pairs
-// per channel, plus a prefix count of the entries with non-zero opacity) and orders its tile
-// groups, and k_view_mask turns the prefix counts into one bit per node-table cell: set when
+// Per launch, the host tabulates each view's transfer functions (256 RGBA value/slope pairs
+// per channel, plus a prefix count of the entries with non-zero opacity) and the dispatch order
+// of its tile groups, and k_view_mask turns the prefix counts into one bit per node-table cell: set when
 // every value the cell can produce classifies to zero opacity in every channel.  Every render
 // workgroup copies the value/slope table (and a small mask) into LDS; the mask drives the exact
 // empty-space skipping (skipped positions would add exactly zero).
@@ -41,20 +41,6 @@ __device__ __forceinline__ bool mask_bit(const uint32_t *m, const uint32_t *lds,
 // groups, segment by segment, so that all segments of the j-th group land on XCD j mod 8
 // (workgroups are dealt round-robin to the 8 XCDs; emitting a group's segments back to back
 // would pin each segment to a fixed subset of XCDs whenever the segment count divides 8).
-
-// Tile q of tile group gi. A whole image with an even number of tile rows and columns is
-// grouped in 2x2 blocks of tiles (the four waves of a workgroup share L1); otherwise a group is
-// four consecutive tiles of the view's row-major tile range.
-__device__ inline int group_tile(const DevView &V, int gi, int q)
-{
-    const int ty = (V.height + 7) >> 3;
-    if (kRenderTilesPerWg == 4 && V.tile_begin == 0 && V.tile_end == V.tiles_x * ty &&
-        !(V.tiles_x & 1) && !(ty & 1)) {
-        const int hx = V.tiles_x >> 1, gx = gi % hx, gy = gi / hx;
-        return (2 * gy + (q >> 1)) * V.tiles_x + 2 * gx + (q & 1);
-    }
-    return V.tile_begin + gi * kRenderTilesPerWg + q;
-}
 
 __device__ inline WgItem item_of(const DevView *__restrict__ views, int n_views, int b)
 {
@@ -1127,114 +1113,6 @@ k_refine_finish(const DevView *__restrict__ views, const int32_t *__restrict__ r
     }
 }
 
-// Dispatch order of a view's tile groups (item_of): groups sorted by the length inside the
-// volume box and the clip half-spaces of their longest tile-centre ray (one ray per group when
-// the view has more than 4096 groups), longest first, in 32 length classes.  Each thread owns a
-// contiguous run of groups; a counting sort keeps index order inside a class, so neighbouring
-// groups of one class stay neighbours in the dispatch.  Per class (an unrolled loop, so the
-// per-thread counts stay in registers) a wave scan of the threads' counts gives each thread its
-// offset, and the thread writes its groups of that class.  One 256-thread workgroup, under 1 KB
-// of LDS (it runs on the preparation stream beside render workgroups, which leave little LDS
-// free); group_order[G ... 2G) holds the classes.  Precision does not matter here (the order
-// changes no result), hence the approximate reciprocals.
-__device__ inline void view_group_order(const VolGeom &g, const DevView &V)
-{
-#ifndef OCTRC_ORDER_CLASSES
-#define OCTRC_ORDER_CLASSES 32
-#endif
-    constexpr int kCls = OCTRC_ORDER_CLASSES;
-    __shared__ int wsum[kCls][4];
-    __shared__ float red[4];
-    const int G = V.groups, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    int32_t *order = V.group_order, *cls = V.group_order + G;
-    const int chunk = (G + 255) / 256, lo = min(tid * chunk, G), hi = min(lo + chunk, G);
-    const int rays = G > 4096 ? 1 : kRenderTilesPerWg;
-    const float rw = __builtin_amdgcn_rcpf((float)V.width), rh = __builtin_amdgcn_rcpf((float)V.height);
-    float lmax = 0.0f;
-    for (int gi = lo; gi < hi; gi++) {
-        float best = 0.0f;
-        for (int q = 0; q < rays; q++) {
-            const int t = min(group_tile(V, gi, rays == 1 ? 1 : q), V.tile_end - 1);
-            const int px = min((t % V.tiles_x) * 8 + 4, V.width - 1);
-            const int py = min((t / V.tiles_x) * 8 + 4, V.height - 1);
-            const float sx = ((float)(2 * px + 1) * rw - 1.0f) * V.kx;
-            const float sy = (1.0f - (float)(2 * py + 1) * rh) * V.ky;
-            float d[3];
-            for (int k = 0; k < 3; k++) d[k] = V.f[k] + sx * V.r[k] + sy * V.u[k];
-            const float inv = rsqrtf(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-            float t0 = 0.0f, t1 = INFINITY;
-            for (int k = 0; k < 3; k++) {
-                d[k] *= inv;
-                const float o = V.eye[k];
-                if (d[k] == 0.0f) {
-                    if (o < 0.0f || o > (float)g.dims[k]) t1 = -1.0f;
-                    continue;
-                }
-                const float rk = __builtin_amdgcn_rcpf(d[k]);
-                const float ta = -o * rk, tb = ((float)g.dims[k] - o) * rk;
-                t0 = fmaxf(t0, fminf(ta, tb));
-                t1 = fminf(t1, fmaxf(ta, tb));
-            }
-            for (int c = 0; c < V.n_clip; c++) {
-                const float *pl = V.clip[c];
-                const float nd = pl[0] * d[0] + pl[1] * d[1] + pl[2] * d[2];
-                const float no = pl[0] * V.eye[0] + pl[1] * V.eye[1] + pl[2] * V.eye[2];
-                if (nd > 0.0f) t0 = fmaxf(t0, (pl[3] - no) * __builtin_amdgcn_rcpf(nd));
-                else if (nd < 0.0f) t1 = fminf(t1, (pl[3] - no) * __builtin_amdgcn_rcpf(nd));
-                else if (no < pl[3]) t1 = -1.0f;
-            }
-            best = fmaxf(best, t1 - t0);
-        }
-        cls[gi] = __float_as_int(best);
-        lmax = fmaxf(lmax, best);
-    }
-    for (int o = 32; o > 0; o >>= 1) lmax = fmaxf(lmax, __shfl_xor(lmax, o, 64));
-    if (lane == 0) red[wave] = lmax;
-    __syncthreads();
-    lmax = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
-    const float scale = lmax > 0.0f ? (float)kCls / lmax : 0.0f;
-    for (int gi = lo; gi < hi; gi++)   // class 0: the longest rays
-        cls[gi] = kCls - 1 - min(max((int)(__int_as_float(cls[gi]) * scale), 0), kCls - 1);
-    // per class: this thread's count and its exclusive scan over the wave (recomputed in the
-    // second pass rather than kept, so the kernel stays within a few registers), the wave totals
-    auto wave_scan = [&](int c, int &n) -> int {
-        n = 0;
-        for (int gi = lo; gi < hi; gi++) n += cls[gi] == c ? 1 : 0;
-        int x = n;
-        for (int o = 1; o < 64; o <<= 1) {
-            const int y = __shfl_up(x, o, 64);
-            if (lane >= o) x += y;
-        }
-        return x;   // inclusive
-    };
-    for (int c = 0; c < kCls; c++) {
-        int n;
-        const int x = wave_scan(c, n);
-        if (lane == 63) wsum[c][wave] = x;
-    }
-    __syncthreads();
-    int base = 0;   // groups of the classes before c, then of the waves before this one
-    for (int c = 0; c < kCls; c++) {
-        int n;
-        int at = base + wave_scan(c, n) - n;
-        for (int w = 0; w < wave; w++) at += wsum[c][w];
-        for (int gi = lo; gi < hi; gi++)
-            if (cls[gi] == c) order[at++] = gi;
-        base += wsum[c][0] + wsum[c][1] + wsum[c][2] + wsum[c][3];
-    }
-}
-
-// Per-launch view preparation (views along y): one workgroup per view with a dispatch order
-// sorts its tile groups (the tables come from the host).  Reads only the views.  It runs on the
-// preparation stream while renders hold the CUs: render waves take 480 of a SIMD's 512
-// registers, so this kernel is held to 32 (and little LDS) to start beside them.
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_num_vgpr(32)))
-k_view_prep(VolGeom g, const DevView *__restrict__ views)
-{
-    const DevView &V = views[blockIdx.y];
-    if (V.group_order) view_group_order(g, V);
-}
-
 // Transparency of every node-table cell for every view that skips: workgroup b of a view sets
 // bits 256 b ... 256 b + 255 of V.tmask, one 64-bit ballot per wave.  Bit i is set when no
 // sample drawn inside cell i can contribute:
@@ -1245,7 +1123,7 @@ k_view_prep(VolGeom g, const DevView *__restrict__ views)
 //  - full-frame fallback views take the range of the cell's ancestor two levels up (or the
 //    root): a missing brick is drawn from a coarser brick whose values that ancestor's range
 //    covers, while its own range need not.
-// Reads the current node table: after the last upload and after k_view_prep.
+// Reads the current node table: after the last upload and after the launch records' copy.
 template <int C>
 __global__ void __launch_bounds__(256)
 k_view_mask(VolGeom g, const DevView *__restrict__ views, const DevCell *__restrict__ table,
@@ -1365,13 +1243,6 @@ size_t view_tables_bytes(int C)
     case 3: return sizeof(ViewTables<3>);
     default: return sizeof(ViewTables<4>);
     }
-}
-
-hipError_t launch_view_prep(const VolGeom &g, const DevView *views, int n_views, hipStream_t s)
-{
-    if (n_views <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_view_prep, dim3(1, (unsigned)n_views), dim3(256), 0, s, g, views);
-    return hipGetLastError();
 }
 
 hipError_t launch_view_mask(const VolGeom &g, const DevView *views, int n_views,

@@ -61,8 +61,6 @@ struct RenderSlot {
     size_t part_cap = 0;
     uint32_t *tmask = nullptr;  // per-view cell transparency masks of the launch
     size_t tmask_cap = 0;
-    int32_t *gorder = nullptr;  // per-view tile-group dispatch orders (+ length classes)
-    size_t gorder_cap = 0;
     hipEvent_t k0 = nullptr, k1 = nullptr;   // around the render kernel, when timing is on
     bool k_pending = false;
     int64_t version = -1;   // node-table version the slot's last launch read
@@ -96,6 +94,7 @@ constexpr int kRenderSlots = 8;
 
 // Views per render_views_noalloc call and bytes of its device scratch (per GPU).
 constexpr int kNoAllocMaxViews = 64;
+constexpr int kNoAllocMaxOrder = 65536;   // tile groups of an ordered view (a 2048x2048 image)
 constexpr size_t kScratchBytes = (size_t)16 << 20;
 
 // Forward renders that filled a checkpoint workspace: the backward checks that the octree and
@@ -184,6 +183,8 @@ struct oct_handle {
     std::vector<HCell> cells;
     std::vector<int32_t> free_slots;
     std::vector<std::vector<Box>> dirty;  // per level
+    // tile-group dispatch orders of the last few ordered views (geometry key bytes -> order)
+    std::vector<std::pair<std::vector<uint8_t>, std::vector<int32_t>>> order_cache;
     std::string err;
     float background_f = 0.0f;
 };
@@ -309,7 +310,8 @@ size_t tables_offset(const RecordLayout &l) { return (l.c_off + l.c_bytes + 255)
 size_t noalloc_record_bytes()
 {
     const RecordLayout l = record_layout(kNoAllocMaxViews, kNoAllocMaxViews, kNoAllocMaxViews);
-    return tables_offset(l) + (size_t)kNoAllocMaxViews * view_tables_bytes(kMaxC);
+    return ((tables_offset(l) + (size_t)kNoAllocMaxViews * view_tables_bytes(kMaxC) + 255) &
+            ~(size_t)255) + (size_t)kNoAllocMaxOrder * 8;   // the order and its scratch
 }
 
 // Every view's transfer-function tables, built on the host into the launch's records.
@@ -326,17 +328,128 @@ void fill_tables(int C, const DevView *dvs, int n_views, uint8_t *dst, size_t tb
     }
 }
 
-// Views whose tile groups are dispatched longest first (the order is built on the device per
-// launch, on the preparation stream): the whole image of a launch's only view, when it has
-// more than 1024 groups (above 512x512 pixels) -- there the longest rays set the launch's
-// duration; smaller launches end soon either way.  Launches of several
-// views or tile ranges (a serving mix) keep index order: they overlap other launches, which
-// fill their tails, and an order kernel would have to wait for execution slots behind those
-// launches' renders before this one could start.
+// Views whose tile groups are dispatched longest first: the whole image of a launch's only
+// view, when it has more than 1024 groups (above 512x512 pixels) -- there the longest rays set
+// the launch's duration; smaller launches end soon either way.  Launches of several views or
+// tile ranges (a serving mix) keep index order: they overlap other launches, which fill their
+// tails.
 bool view_ordered(const DevView &v, int n_views)
 {
     const int tiles = v.tiles_x * ((v.height + OCT_TILE - 1) / OCT_TILE);
     return n_views == 1 && v.tile_begin == 0 && v.tile_end == tiles && v.groups > 1024;
+}
+
+// Dispatch order of a view's tile groups (read by item_of): groups sorted by the length, inside
+// the volume box and the clip half-spaces, of the longest of their tile-centre rays (one ray
+// per group above 4096 groups), longest first, in 32 length classes.  A stable counting sort
+// keeps index order inside a class, so neighbouring groups of one class stay neighbours in the
+// dispatch.  The order changes no result: every pixel depends only on its own ray.  `work`
+// holds V.groups ints of scratch (lengths, then classes).
+void build_group_order(const VolGeom &g, const DevView &V, int32_t *order, int32_t *work)
+{
+    constexpr int kCls = 32;
+    const int G = V.groups;
+    const int rays = G > 4096 ? 1 : kRenderTilesPerWg;
+    float *len = (float *)work;
+    float lmax = 0.0f;
+    for (int gi = 0; gi < G; gi++) {
+        float best = 0.0f;
+        for (int q = 0; q < rays; q++) {
+            const int t = std::min(group_tile(V, gi, rays == 1 ? 1 : q), V.tile_end - 1);
+            const int px = std::min((t % V.tiles_x) * 8 + 4, V.width - 1);
+            const int py = std::min((t / V.tiles_x) * 8 + 4, V.height - 1);
+            const float sx = ((float)(2 * px + 1) / (float)V.width - 1.0f) * V.kx;
+            const float sy = (1.0f - (float)(2 * py + 1) / (float)V.height) * V.ky;
+            float d[3];
+            for (int k = 0; k < 3; k++) d[k] = V.f[k] + sx * V.r[k] + sy * V.u[k];
+            const float inv = 1.0f / std::sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+            float t0 = 0.0f, t1 = INFINITY;
+            for (int k = 0; k < 3; k++) {
+                d[k] *= inv;
+                const float o = V.eye[k];
+                if (d[k] == 0.0f) {
+                    if (o < 0.0f || o > (float)g.dims[k]) t1 = -1.0f;
+                    continue;
+                }
+                const float ta = -o / d[k], tb = ((float)g.dims[k] - o) / d[k];
+                t0 = std::max(t0, std::min(ta, tb));
+                t1 = std::min(t1, std::max(ta, tb));
+            }
+            for (int c = 0; c < V.n_clip; c++) {
+                const float *pl = V.clip[c];
+                const float nd = pl[0] * d[0] + pl[1] * d[1] + pl[2] * d[2];
+                const float no = pl[0] * V.eye[0] + pl[1] * V.eye[1] + pl[2] * V.eye[2];
+                if (nd > 0.0f) t0 = std::max(t0, (pl[3] - no) / nd);
+                else if (nd < 0.0f) t1 = std::min(t1, (pl[3] - no) / nd);
+                else if (no < pl[3]) t1 = -1.0f;
+            }
+            best = std::max(best, t1 - t0);
+        }
+        len[gi] = best;
+        lmax = std::max(lmax, best);
+    }
+    const float scale = lmax > 0.0f ? (float)kCls / lmax : 0.0f;
+    int32_t *cls = work;   // replaces the lengths, entry by entry
+    int start[kCls + 1] = {0};
+    for (int gi = 0; gi < G; gi++) {   // class 0: the longest rays
+        const int k = std::min(std::max((int)(len[gi] * scale), 0), kCls - 1);
+        cls[gi] = kCls - 1 - k;
+        start[cls[gi] + 1]++;
+    }
+    for (int c = 0; c < kCls; c++) start[c + 1] += start[c];
+    for (int gi = 0; gi < G; gi++) order[start[cls[gi]]++] = gi;
+}
+
+// The geometry a group order depends on: a view repeated across launches (a stream of frames
+// of one camera) reuses its order.
+struct OrderKey {
+    float eye[3], f[3], r[3], u[3], kx, ky;
+    int32_t width, height, tiles_x, tile_begin, tile_end, groups, n_clip;
+    float clip[3][4];
+    int32_t dims[3];
+};
+
+OrderKey order_key(const VolGeom &g, const DevView &v)
+{
+    OrderKey k;
+    std::memset(&k, 0, sizeof(k));
+    for (int a = 0; a < 3; a++) {
+        k.eye[a] = v.eye[a];
+        k.f[a] = v.f[a];
+        k.r[a] = v.r[a];
+        k.u[a] = v.u[a];
+        k.dims[a] = g.dims[a];
+    }
+    k.kx = v.kx;
+    k.ky = v.ky;
+    k.width = v.width;
+    k.height = v.height;
+    k.tiles_x = v.tiles_x;
+    k.tile_begin = v.tile_begin;
+    k.tile_end = v.tile_end;
+    k.groups = v.groups;
+    k.n_clip = v.n_clip;
+    for (int c = 0; c < v.n_clip; c++)
+        for (int q = 0; q < 4; q++) k.clip[c][q] = v.clip[c][q];
+    return k;
+}
+
+// The group order of view v (from the cache when its geometry was ordered recently).
+const std::vector<int32_t> &cached_group_order(oct_handle *h, const DevView &v)
+{
+    const OrderKey k = order_key(h->g, v);
+    const uint8_t *kb = (const uint8_t *)&k;
+    auto &cache = h->order_cache;
+    for (size_t i = 0; i < cache.size(); i++)
+        if (cache[i].first.size() == sizeof(k) && !std::memcmp(cache[i].first.data(), kb, sizeof(k))) {
+            if (i) std::rotate(cache.begin(), cache.begin() + (std::ptrdiff_t)i, cache.begin() + (std::ptrdiff_t)i + 1);
+            return cache[0].second;
+        }
+    std::vector<int32_t> ord((size_t)v.groups), work((size_t)v.groups);
+    build_group_order(h->g, v, ord.data(), work.data());
+    cache.insert(cache.begin(), {std::vector<uint8_t>(kb, kb + sizeof(k)), std::move(ord)});
+    if (cache.size() > 4) cache.pop_back();
+    return cache[0].second;
 }
 
 // Address of `scratch` on device `dev` (the current device), looked up once per device.
@@ -765,7 +878,6 @@ int octree_destroy(oct_handle *h)
         stage_free(r.st);
         if (r.part) (void)hipFree(r.part);
         if (r.tmask) (void)hipFree(r.tmask);
-        if (r.gorder) (void)hipFree(r.gorder);
         if (r.prep) (void)hipEventDestroy(r.prep);
         if (r.k0) (void)hipEventDestroy(r.k0);
         if (r.k1) (void)hipEventDestroy(r.k1);
@@ -1490,7 +1602,6 @@ static int build_view(oct_handle *h, const oct_view &v, float *image, DevView &d
 // Per-launch plan of a view list: the view records, their work items and depth segments.
 struct LaunchPlan {
     int64_t n_items = 0;
-    int64_t order_ints = 0;          // every view's tile-group order and length classes
     int64_t max_split_pixels = 0;
     int64_t max_refine_pixels = 0;
     int n_split = 0;
@@ -1578,7 +1689,6 @@ static int plan_launch(oct_handle *h, int32_t n_views, const oct_view *views,
             dv.item_begin = (int32_t)pl.n_items;
             dv.groups = groups;
             pl.n_items += (int64_t)groups * nsplit;
-            pl.order_ints += 2 * (int64_t)groups;
             pl.n_skip += dv.skip ? 1 : 0;
             j++;
         }
@@ -1622,7 +1732,13 @@ int render_views(oct_handle *h, int32_t n_views, const oct_view *views, float *c
     }
     const RecordLayout l = record_layout((size_t)n_views, (size_t)pl.n_split, (size_t)pl.n_refine);
     const size_t tbytes = view_tables_bytes(h->g.C);
-    const size_t t_off = tables_offset(l), rec_bytes = t_off + (size_t)n_views * tbytes;
+    const size_t t_off = tables_offset(l);
+    // tile-group orders behind the tables (one copy with the records)
+    const size_t o_off = (t_off + (size_t)n_views * tbytes + 255) & ~(size_t)255;
+    size_t order_ints = 0;
+    for (int i = 0; i < n_views; i++)
+        if (view_ordered(dvs[i], n_views)) order_ints += (size_t)dvs[i].groups;
+    const size_t rec_bytes = o_off + order_ints * 4;
     RenderSlot &rs = h->rs[h->next_rs];
     h->next_rs = (h->next_rs + 1) % kRenderSlots;
     int rc = stage_reserve(h, rs.st, rec_bytes);   // the slot is idle now
@@ -1654,19 +1770,14 @@ int render_views(oct_handle *h, int32_t n_views, const oct_view *views, float *c
         dvs[i].tmask = dvs[i].skip ? rs.tmask + (size_t)(j++) * mwords : nullptr;
     uint8_t *hp = (uint8_t *)rs.st.host;
     uint8_t *dp = (uint8_t *)rs.st.dev;
-    if ((size_t)pl.order_ints * 4 > rs.gorder_cap) {
-        if (rs.gorder) HIPCHK(h, hipFree(rs.gorder));
-        rs.gorder = nullptr;
-        rs.gorder_cap = 0;
-        HIPCHK(h, hipMalloc((void **)&rs.gorder, (size_t)pl.order_ints * 4));
-        rs.gorder_cap = (size_t)pl.order_ints * 4;
-    }
-    int n_ordered = 0;
     for (int i = 0, at = 0; i < n_views; i++) {
-        const bool ord = view_ordered(dvs[i], n_views);
-        dvs[i].group_order = ord ? rs.gorder + at : nullptr;   // written by the order kernel
-        n_ordered += ord ? 1 : 0;
-        at += 2 * dvs[i].groups;
+        dvs[i].group_order = nullptr;
+        if (view_ordered(dvs[i], n_views)) {
+            const std::vector<int32_t> &ord = cached_group_order(h, dvs[i]);
+            std::memcpy(hp + o_off + (size_t)at * 4, ord.data(), ord.size() * 4);
+            dvs[i].group_order = (int32_t *)(dp + o_off) + at;
+            at += dvs[i].groups;
+        }
         dvs[i].rwait = (int32_t *)(dp + l.rw_off) + i;
         dvs[i].tables = dp + t_off + (size_t)i * tbytes;
     }
@@ -1676,11 +1787,10 @@ int render_views(oct_handle *h, int32_t n_views, const oct_view *views, float *c
     std::memcpy(hp + l.rf_off, refine_views.data(), (size_t)pl.n_refine * 4);
     std::memset(hp + l.rw_off, 0, (size_t)n_views * 4);
     std::memset(hp + l.c_off, 0, l.c_bytes);
-    // preparation on the prep stream (it overlaps the renders issued before this one): views,
-    // lists, zeroed counters and the tables in one copy, then the tile-group orders
+    // the copy runs on the prep stream (it overlaps the renders issued before this one): views,
+    // lists, zeroed counters, tables and tile-group orders in one copy
     if (!rs.prep) HIPCHK(h, hipEventCreateWithFlags(&rs.prep, hipEventDisableTiming));
     HIPCHK(h, hipMemcpyAsync(rs.st.dev, hp, rec_bytes, hipMemcpyHostToDevice, h->prep));
-    if (n_ordered) HIPCHK(h, launch_view_prep(h->g, (const DevView *)dp, n_views, h->prep));
     HIPCHK(h, hipEventRecord(rs.prep, h->prep));
     rc = wait_for(h, s, rs.prep);
     if (!rc) rc = wait_for(h, s, h->ev_upload);   // the node table and pool of the last upload
@@ -1733,28 +1843,37 @@ int render_views_noalloc(oct_handle *h, int32_t n_views, const oct_view *views,
     int rc = plan_launch(h, n_views, views, images, ckpt_ws, false, dvs, split, refine, nullptr, pl);
     if (rc) return rc;
     const RecordLayout l = record_layout((size_t)n_views, (size_t)pl.n_split, (size_t)pl.n_refine);
-    // scratch: records and tables (one copy) | masks | tile-group orders
+    // scratch: records, tables and the tile-group order (one copy) | masks.  The order needs
+    // room in the host records allotted at creation: a view of more groups keeps index order.
     const size_t tbytes = view_tables_bytes(h->g.C);
     const int64_t mwords = view_mask_words(h->n_cells);
-    const size_t t_off = tables_offset(l), rec_bytes = t_off + (size_t)n_views * tbytes;
+    const size_t t_off = tables_offset(l);
+    const size_t o_off = (t_off + (size_t)n_views * tbytes + 255) & ~(size_t)255;
+    size_t order_ints = 0;
+    for (int i = 0; i < n_views; i++)
+        if (view_ordered(dvs[i], n_views) && dvs[i].groups <= kNoAllocMaxOrder)
+            order_ints += (size_t)dvs[i].groups;
+    const size_t rec_bytes = o_off + order_ints * 4;
     const size_t m_off = (rec_bytes + 255) & ~(size_t)255;
-    const size_t g_off = (m_off + (size_t)pl.n_skip * mwords * 4 + 255) & ~(size_t)255;
-    const size_t need = g_off + (size_t)pl.order_ints * 4;
+    const size_t need = m_off + (size_t)pl.n_skip * mwords * 4;
     if (need > kScratchBytes)
         return fail(h, OCT_ERANGE,
                     "render_views_noalloc: this launch needs " + std::to_string(need) +
                         " bytes of device scratch, the limit is " + std::to_string(kScratchBytes) +
                         " (fewer or smaller views per call, or render_views)");
     uint8_t *dp = (uint8_t *)h->scratch_dev;
-    int n_ordered = 0;
     for (int i = 0, j = 0, at = 0; i < n_views; i++) {
-        const bool ord = view_ordered(dvs[i], n_views);
         dvs[i].tables = dp + t_off + (size_t)i * tbytes;
         dvs[i].tmask = dvs[i].skip ? (uint32_t *)(dp + m_off) + (size_t)(j++) * mwords : nullptr;
-        dvs[i].group_order = ord ? (int32_t *)(dp + g_off) + at : nullptr;   // order kernel
-        n_ordered += ord ? 1 : 0;
+        dvs[i].group_order = nullptr;
+        if (view_ordered(dvs[i], n_views) && dvs[i].groups <= kNoAllocMaxOrder) {
+            // built in the host records (no host allocation), its scratch behind it
+            int32_t *ord = (int32_t *)(hp + o_off) + at;
+            build_group_order(h->g, dvs[i], ord, ord + dvs[i].groups);
+            dvs[i].group_order = (int32_t *)(dp + o_off) + at;
+            at += dvs[i].groups;
+        }
         dvs[i].rwait = (int32_t *)(dp + l.rw_off) + i;
-        at += 2 * dvs[i].groups;
     }
     fill_tables(h->g.C, dvs, n_views, hp + t_off, tbytes);
     std::memcpy(hp + l.sv_off, split, (size_t)pl.n_split * 4);
@@ -1771,7 +1890,6 @@ int render_views_noalloc(oct_handle *h, int32_t n_views, const oct_view *views,
     rs.version = hipEventQuery(rs.st.ev) == hipSuccess ? h->version : std::min(rs.version, h->version);
     HIPCHK(h, hipMemcpyAsync(dp, hp, rec_bytes, hipMemcpyHostToDevice, s));
     HIPCHK(h, hipEventRecord(h->na_copy, s));
-    if (n_ordered) HIPCHK(h, launch_view_prep(h->g, (const DevView *)dp, n_views, s));
     if (pl.n_skip)
         HIPCHK(h, launch_view_mask(h->g, (const DevView *)dp, n_views, h->table, h->n_cells, s));
     HIPCHK(h, launch_render(h->g, h->table, h->pool, h->brick_bytes, (const DevView *)dp, n_views,
