@@ -98,6 +98,8 @@ def main():
                     help="stream workload: skip the out-of-core leg (2048x2048x1024)")
     ap.add_argument("--no-build", action="store_true",
                     help="stream workload: skip the whole-volume build and MIP legs")
+    ap.add_argument("--no-disk", action="store_true",
+                    help="leave out the disk-tier leg (streamed build through a page file)")
     ap.add_argument("--no-serve", action="store_true",
                     help="stream workload: skip the serving leg (2000 Poisson requests)")
     ap.add_argument("--serve-only", action="store_true",
@@ -110,13 +112,19 @@ def main():
                     help="paging workload / leg: 1 = 2048x2048x1024, 2 = half and 4 = quarter "
                          "size per axis")
     ap.add_argument("--workload", default="stream",
-                    choices=["stream", "adjoint", "serve", "views", "paging", "build", "mip"],
+                    choices=["stream", "adjoint", "serve", "views", "paging", "build", "mip",
+                             "disk"],
                     help="stream: streamed build+render (default); adjoint: 256^3 f32 forward + "
                          "adjoint at 512x512; serve: Poisson request mix; views: 64 views of "
                          "the 64^3 volume in one launch vs one launch per view; paging: the "
                          "out-of-core path alone; build: whole-volume build of the 512x512x256 "
-                         "volume; mip: MIP renders of the 512x512x256 octree")
+                         "volume; mip: MIP renders of the 512x512x256 octree; disk: the streamed "
+                         "step, then the same step with the mipmap in the disk tier")
     args = ap.parse_args()
+    if args.workload == "disk":   # the streamed step and the disk-tier leg only
+        args.workload = "stream"
+        args.no_cpu_baseline = args.no_adjoint = args.no_build = True
+        args.no_serve = args.no_paging = True
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
               "(the multi-GPU design is described but not built)", file=sys.stderr)
@@ -293,11 +301,15 @@ def main():
         out["adjoint"] = {k: v for k, v in measure_adjoint(args).items()
                           if k in ("value", "unit", "forward_ms", "adjoint_ms", "adjoint_tf_only_ms",
                                    "config")}
+    final_img = img.clone()
     if not args.no_build:
         out["mip"] = measure_mip(tree, cfg, args)
         tree.close()
         out["build_whole_volume"] = measure_build(dev, cfg, args)
     tree.close()
+    if not args.no_disk:
+        torch.cuda.empty_cache()
+        out["disk_tier"] = measure_disk(slabs, cfg, args, final_img, composited, ms_per_step)
     del slabs, dev
     if not args.no_serve:
         torch.cuda.empty_cache()
@@ -352,6 +364,89 @@ def measure_build(dev, cfg, args) -> dict:
     res["config"] = (f"{dims[0]}x{dims[1]}x{dims[2]}x{C} u16 from HBM, {M}^3 bricks, "
                      f"threshold {cfg['thr']}: one insert + one upload, median of {reps}")
     return res
+
+
+def _fs_type(path: str) -> str:
+    """File system of `path` (the longest mount point above it in /proc/mounts)."""
+    best, kind = "", "unknown"
+    try:
+        for line in open("/proc/mounts"):
+            f = line.split()
+            if len(f) >= 3 and path.startswith(f[1]) and len(f[1]) > len(best):
+                best, kind = f[1], f[2]
+    except OSError:
+        pass
+    return kind
+
+
+def measure_disk(slabs, cfg, args, want, composited, hbm_ms_per_step) -> dict:
+    """Disk tier: the streamed build + render step of the headline configuration with the
+    mipmap kept in pages in a file (pages of 2x2x2 cells = 64^3 voxels, all channels) and RAM
+    frames for a third of the pages; one warm-up step, then one timed step.  Reports the
+    step's rate, the page traffic of the timed step, and the final image against the in-HBM
+    run's (the octree is the same, so the image must be equal)."""
+    import shutil
+    import tempfile
+
+    import numpy as np
+    import torch
+
+    from paper_1407_2074_amd import synth
+    from paper_1407_2074_amd.octree import Octree
+    dims, C, M = cfg["dims"], cfg["C"], cfg["M"]
+    P, page_cells = 2 * M, 2
+    N = 0
+    while (M << N) < max(dims):
+        N += 1
+    n_pages = 0
+    for L in range(N + 1):
+        ext = [-(-d // (1 << L)) for d in dims]
+        n_pages += int(np.prod([-(-e // P) for e in ext]))
+    page_bytes = P ** 3 * C * 2
+    frames = max(16, n_pages // 3)
+    tmp = tempfile.mkdtemp(prefix="octree_pages_")
+    path = os.path.join(tmp, "pages.bin")
+    try:
+        t = Octree(dims, C, M, "u16", background=0, threshold=cfg["thr"], disk_path=path,
+                   host_cache_bytes=frames * page_bytes, page_cells=page_cells)
+        view = synth.make_view(dims, C, cfg["seed"], az=cfg["az"], el=cfg["el"],
+                               width=cfg["width"], height=cfg["height"], lod=cfg["lod"])
+        img = torch.zeros((view.height, view.width, 4), dtype=torch.float32, device="cuda")
+
+        def step():
+            t.clear()
+            for b, slab in enumerate(slabs):
+                t.insert_slices(-1, b * cfg["batch"], slab)
+                t.upload()
+                t.render([view], images=[img])
+
+        step()
+        torch.cuda.synchronize()
+        s0 = t.disk_stats()
+        t0 = time.perf_counter()
+        step()
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        s1 = t.disk_stats()
+        err = float((img - want).abs().max().item())
+        t.close()
+    finally:
+        shutil.rmtree(tmp, ignore_errors=True)
+    d = {k: s1[k] - s0[k] for k in ("hits", "loads", "fills", "writebacks", "evictions", "waits",
+                                   "bytes_read", "bytes_written")}
+    return {
+        "config": (f"streamed build+render {dims[0]}x{dims[1]}x{dims[2]}x{C} u16, {M}^3 bricks, "
+                   f"{len(slabs)} batches of {cfg['batch']} slices, one {cfg['width']}x"
+                   f"{cfg['height']} view per batch; mipmap in {n_pages} pages of {P}^3 voxels "
+                   f"({page_bytes >> 20} MiB) in a file on {_fs_type(tmp)}, {frames} RAM frames"),
+        "ms_per_step": round(el * 1e3, 2),
+        "gsamples_per_s": round(composited / el / 1e9, 3),
+        "hbm_master_ms_per_step": round(hbm_ms_per_step, 2),
+        "page_traffic": d,
+        "file_read_gb_per_s": round(d["bytes_read"] / el / 1e9, 3),
+        "file_write_gb_per_s": round(d["bytes_written"] / el / 1e9, 3),
+        "final_image_max_abs_diff_vs_hbm_master": err,
+    }
 
 
 def measure_mip(tree, cfg, args) -> dict:

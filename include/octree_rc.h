@@ -91,11 +91,46 @@ typedef struct {
                                    their AVG meanwhile); brick_pool_upload reads the flags
                                    and replaces least-recently-used slots, coarser levels
                                    first                                                  */
-    int32_t master_on_host;     /* 1: the full-resolution mipmap lives in pinned host
-                                   memory (read by the kernels over the host link) instead
-                                   of HBM                                                 */
-    int32_t reserved[3];        /* must be 0                                              */
+    int32_t master_on_host;     /* where the full-resolution mipmap lives:
+                                   OCT_MASTER_HBM (0): device memory;
+                                   OCT_MASTER_HOST (1): pinned host memory, read and
+                                   written by the kernels over the host link;
+                                   OCT_MASTER_DISK (2): the disk tier ("Brick Upload from
+                                   Disk to RAM", Fig. 5): the levels are cut into pages of
+                                   page_cells^3 cells, stored in the file disk_path; RAM
+                                   holds an LRU set of host_cache_bytes of them (pinned,
+                                   accessed by the kernels over the host link).  A page
+                                   modified by insertion is written back before its RAM
+                                   frame is reused; a page that device work in flight still
+                                   uses is not removed (the call waits for that work).
+                                   Needs M a power of two.                                 */
+    int32_t page_cells;         /* disk tier: cells per page edge, a power of two >= 2
+                                   (0: 2); a page holds M*page_cells voxels per edge, all
+                                   channels                                               */
+    int32_t reserved[2];        /* must be 0                                              */
+    uint64_t host_cache_bytes;  /* disk tier: RAM for pages; must hold at least 16 pages
+                                   (or every page)                                        */
+    const char *disk_path;      /* disk tier: the page file, created (truncated) by
+                                   octree_create and removed by octree_destroy            */
 } oct_create_params;
+
+#define OCT_MASTER_HBM 0
+#define OCT_MASTER_HOST 1
+#define OCT_MASTER_DISK 2
+
+/* Counters of the disk tier since octree_create (octree_disk_stats). */
+typedef struct {
+    uint64_t pages;             /* pages of the mipmap                                     */
+    uint64_t frames;            /* RAM frames (pages held at once)                         */
+    uint64_t hits;              /* page uses that found the page in RAM                    */
+    uint64_t loads;             /* pages read from the file                                */
+    uint64_t fills;             /* pages never written, set to the background in RAM       */
+    uint64_t writebacks;        /* modified pages written to the file before eviction      */
+    uint64_t evictions;         /* pages removed from RAM                                  */
+    uint64_t waits;             /* evictions that waited for device work on the page       */
+    uint64_t bytes_read;        /* file bytes read                                         */
+    uint64_t bytes_written;     /* file bytes written                                      */
+} oct_disk_stats;
 
 /* One render request (Algorithm 1 and "Basic Ray-Casting").  Pinhole camera with square
  * pixels through pixel centres, row 0 at the top.  The image is premultiplied RGBA float32,
@@ -281,6 +316,11 @@ int render_views_backward(oct_handle *h, int32_t n_views, const oct_view *views,
  * sampled with its AVG).  Bricks that are not resident are gathered into a spare slot for
  * the dump.  With buf == NULL or cap too small only *needed is set and OCT_ERANGE returned. */
 int octree_dump_canonical(oct_handle *h, void *buf, size_t cap, size_t *needed);
+
+/* Counters of the disk tier ("Brick Upload from Disk to RAM"): page hits, loads from the
+ * file, background fills, write-backs of modified pages, evictions and evictions that waited
+ * for device work.  Errors: OCT_EINVAL for a null argument or a handle without the disk tier. */
+int octree_disk_stats(oct_handle *h, oct_disk_stats *out);
 
 /* Copies mipmap level `level` (planar [C][ez][ey][ex], dtype) to host memory `out` of `cap`
  * bytes; ext receives (ex, ey, ez).  Applies pending inserts first (synchronises). */

@@ -1,7 +1,7 @@
 // Construction kernels: block insertion, 2x2x2 half-sampling, per-cell statistics, node-table
 // change events, bordered-brick gather and skip-range propagation.
 //
-// The master mipmap lives in HBM as dense planar levels ([C][ez][ey][ex] per level, level L
+// The master mipmap lives in HBM (or pinned host memory) as dense planar levels ([C][ez][ey][ex] per level, level L
 // valid extent ceil(D/2^L)), which makes insertion a coalesced copy and half-sampling a
 // streaming pass; the renderer reads a separate pool of bordered, channel-interleaved bricks.
 #include "internal.h"
@@ -9,6 +9,7 @@
 #include <float.h>
 
 #include <algorithm>
+#include <type_traits>
 
 namespace octrc {
 
@@ -16,13 +17,6 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kXcds = 8;        // MI355X: 8 XCDs of 32 CUs, one L2 each
-
-template <typename T>
-__device__ inline T *level_ptr(T *master, const VolGeom &g, int L, int c)
-{
-    const int64_t n = (int64_t)g.ext[L][0] * g.ext[L][1] * g.ext[L][2];
-    return master + g.lvl_off[L] + (int64_t)c * n;
-}
 
 // Eight consecutive elements moved as 16-byte words (one for uint16, two for float32).
 template <typename T> struct Pack8;
@@ -55,18 +49,18 @@ template <> struct Pack8<float> {
 // ---------------------------------------------------------------------------------------
 // Step 1 of incremental construction: copy a block into level 0 and record which channels
 // of each voxel have been inserted (completeness tracking).  Two forms: k_insert8 moves eight
-// voxels per thread with 16-byte accesses (block origin, width and volume width multiples of
-// eight, 16-byte-aligned source); k_insert takes any block, one voxel per thread.
-template <typename T>
+// voxels per thread with 16-byte accesses (block origin, width and row pitches multiples of
+// eight, 16-byte-aligned source and rows); k_insert takes any block, one voxel per thread.
+// The source block has row / slice / channel pitches sp_y / sp_z / sp_c (elements).
+template <typename T, bool kPaged>
 __global__ void __launch_bounds__(kThreads)
-k_insert8(VolGeom g, T *__restrict__ master, uint8_t *__restrict__ mask,
-          const T *__restrict__ src, int channel, int x0, int y0, int z0, int nx, int ny, int nz)
+k_insert8(VolGeom g, MasterRef<T> mr, uint8_t *__restrict__ mask, const T *__restrict__ src,
+          int64_t sp_y, int64_t sp_z, int64_t sp_c, int channel, int x0, int y0, int z0, int nx,
+          int ny, int nz)
 {
     const int nq = nx >> 3;
     const int64_t items = (int64_t)nq * ny * nz;
     const int cb = channel < 0 ? g.C : 1;
-    const int64_t nvox0 = (int64_t)g.dims[0] * g.dims[1] * g.dims[2];
-    const int64_t nblk = (int64_t)nx * ny * nz;
     uint32_t bits = 0;
     for (int c = 0; c < cb; c++) bits |= 1u << (channel < 0 ? c : channel);
     const uint32_t bits4 = bits * 0x01010101u;
@@ -76,38 +70,38 @@ k_insert8(VolGeom g, T *__restrict__ master, uint8_t *__restrict__ mask,
         const int64_t row = i / nq;
         const int y = (int)(row % ny), z = (int)(row / ny);
         const int64_t lin = ((int64_t)(z0 + z) * g.dims[1] + (y0 + y)) * g.dims[0] + x0 + 8 * q;
-        const int64_t sl = row * nx + 8 * q;
+        const int64_t sl = (int64_t)z * sp_z + (int64_t)y * sp_y + 8 * q;
         Pack8<T> v[kMaxC];
 #pragma unroll
         for (int c = 0; c < kMaxC; c++)
-            if (c < cb) v[c] = Pack8<T>::load(src + c * nblk + sl);
+            if (c < cb) v[c] = Pack8<T>::load(src + c * sp_c + sl);
         uint2 m = *(const uint2 *)(mask + lin);
 #pragma unroll
         for (int c = 0; c < kMaxC; c++)
-            if (c < cb) v[c].store(master + g.lvl_off[0] + (int64_t)(channel < 0 ? c : channel) * nvox0 + lin);
+            if (c < cb)
+                v[c].store(melem<kPaged>(g, mr, 0, channel < 0 ? c : channel, x0 + 8 * q, y0 + y, z0 + z));
         m.x |= bits4;
         m.y |= bits4;
         *(uint2 *)(mask + lin) = m;
     }
 }
 
-template <typename T>
+template <typename T, bool kPaged>
 __global__ void __launch_bounds__(kThreads)
-k_insert(VolGeom g, T *master, uint8_t *mask, const T *src, int channel, int x0, int y0, int z0,
-         int nx, int ny, int nz)
+k_insert(VolGeom g, MasterRef<T> mr, uint8_t *mask, const T *src, int64_t sp_y, int64_t sp_z,
+         int64_t sp_c, int channel, int x0, int y0, int z0, int nx, int ny, int nz)
 {
     const int x = blockIdx.x * kThreads + threadIdx.x;
     if (x >= nx) return;
     const int cb = channel < 0 ? g.C : 1;
-    const int64_t nvox0 = (int64_t)g.dims[0] * g.dims[1] * g.dims[2];
     for (int row = blockIdx.y; row < ny * nz; row += gridDim.y) {
         const int y = row % ny, z = row / ny;
         const int64_t lin = ((int64_t)(z0 + z) * g.dims[1] + (y0 + y)) * g.dims[0] + (x0 + x);
         uint32_t bits = 0;
         for (int c = 0; c < cb; c++) {
             const int ch = channel < 0 ? c : channel;
-            master[g.lvl_off[0] + (int64_t)ch * nvox0 + lin] =
-                src[(((int64_t)c * nz + z) * ny + y) * nx + x];
+            *melem<kPaged>(g, mr, 0, ch, x0 + x, y0 + y, z0 + z) =
+                src[c * sp_c + (int64_t)z * sp_z + (int64_t)y * sp_y + x];
             bits |= 1u << ch;
         }
         mask[lin] = (uint8_t)(mask[lin] | bits);
@@ -129,13 +123,11 @@ __device__ inline uint32_t mean_rhu(uint32_t s, uint32_t n)
 // levels' channel planes aligned to eight (L) and four (L + 1) elements; the host checks.
 // The x range is widened to whole groups of four: a parent outside the requested range is
 // recomputed from unchanged children, which rewrites the value it already holds.
-template <typename T>
+template <typename T, bool kPaged>
 __global__ void __launch_bounds__(kThreads)
-k_downsample4(VolGeom g, T *__restrict__ master, int L, int qx0, int nq, int ly, int lz, int ny,
-              int nz)
+k_downsample4(VolGeom g, MasterRef<T> mr, int L, int qx0, int nq, int ly, int lz, int ny, int nz)
 {
-    const int ex = g.ext[L][0], ey = g.ext[L][1], ez = g.ext[L][2];
-    const int px = g.ext[L + 1][0], py = g.ext[L + 1][1];
+    const int ey = g.ext[L][1], ez = g.ext[L][2];
     const int64_t items = (int64_t)nq * ny * nz;
     for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < items;
          i += (int64_t)gridDim.x * kThreads) {
@@ -146,14 +138,13 @@ k_downsample4(VolGeom g, T *__restrict__ master, int L, int qx0, int nq, int ly,
         const uint32_t sh = 2u + (nyv == 2) + (nzv == 2);        // log2(2n), n = 2 nyv nzv
         const uint32_t n = 2u * nyv * nzv;
         for (int c = 0; c < g.C; c++) {
-            const T *src = level_ptr(master, g, L, c);
-            T *dst = level_ptr(master, g, L + 1, c) + ((int64_t)z * py + y) * px + x4;
+            T *dst = melem<kPaged>(g, mr, L + 1, c, x4, y, z);
             Pack8<T> r[4];
 #pragma unroll
             for (int k = 0; k < 4; k++) {
                 const int dz = k >> 1, dy = k & 1;
                 if (dz < nzv && dy < nyv)
-                    r[k] = Pack8<T>::load(src + ((int64_t)(2 * z + dz) * ey + (2 * y + dy)) * ex + 2 * x4);
+                    r[k] = Pack8<T>::load(melem<kPaged>(g, mr, L, c, 2 * x4, 2 * y + dy, 2 * z + dz));
             }
             if constexpr (sizeof(T) == 2) {
                 uint32_t s[4] = {0, 0, 0, 0};
@@ -186,14 +177,13 @@ k_downsample4(VolGeom g, T *__restrict__ master, int L, int qx0, int nq, int ly,
     }
 }
 
-template <typename T>
+template <typename T, bool kPaged>
 __global__ void __launch_bounds__(kThreads)
-k_downsample(VolGeom g, T *master, int L, int lx, int ly, int lz, int hx, int hy, int hz)
+k_downsample(VolGeom g, MasterRef<T> mr, int L, int lx, int ly, int lz, int hx, int hy, int hz)
 {
     const int x = lx + blockIdx.x * kThreads + threadIdx.x;
     if (x > hx) return;
     const int ex = g.ext[L][0], ey = g.ext[L][1], ez = g.ext[L][2];
-    const int px = g.ext[L + 1][0], py = g.ext[L + 1][1];
     const int ny = hy - ly + 1, nz = hz - lz + 1;
     const int cx0 = 2 * x, cx1 = min(2 * x + 1, ex - 1);
     const uint32_t nxv = (2 * x + 1 < ex) ? 2u : 1u;
@@ -202,26 +192,24 @@ k_downsample(VolGeom g, T *master, int L, int lx, int ly, int lz, int hx, int hy
         const uint32_t nyv = (2 * y + 1 < ey) ? 2u : 1u, nzv = (2 * z + 1 < ez) ? 2u : 1u;
         const uint32_t n = nxv * nyv * nzv;
         for (int c = 0; c < g.C; c++) {
-            const T *src = level_ptr(master, g, L, c);
-            T *dst = level_ptr(master, g, L + 1, c);
+            T *dst = melem<kPaged>(g, mr, L + 1, c, x, y, z);
             if constexpr (sizeof(T) == 2) {
                 uint32_t s = 0;
                 for (uint32_t dz = 0; dz < nzv; dz++)
                     for (uint32_t dy = 0; dy < nyv; dy++) {
-                        const T *r = src + ((int64_t)(2 * z + dz) * ey + (2 * y + dy)) * ex;
-                        s += r[cx0];
-                        if (nxv == 2) s += r[cx1];
+                        s += *melem<kPaged>(g, mr, L, c, cx0, 2 * y + dy, 2 * z + dz);
+                        if (nxv == 2) s += *melem<kPaged>(g, mr, L, c, cx1, 2 * y + dy, 2 * z + dz);
                     }
-                dst[((int64_t)z * py + y) * px + x] = (T)mean_rhu(s, n);
+                *dst = (T)mean_rhu(s, n);
             } else {
                 double s = 0.0;
                 for (uint32_t dz = 0; dz < nzv; dz++)
                     for (uint32_t dy = 0; dy < nyv; dy++) {
-                        const T *r = src + ((int64_t)(2 * z + dz) * ey + (2 * y + dy)) * ex;
-                        s += (double)r[cx0];
-                        if (nxv == 2) s += (double)r[cx1];
+                        s += (double)*melem<kPaged>(g, mr, L, c, cx0, 2 * y + dy, 2 * z + dz);
+                        if (nxv == 2)
+                            s += (double)*melem<kPaged>(g, mr, L, c, cx1, 2 * y + dy, 2 * z + dz);
                     }
-                dst[((int64_t)z * py + y) * px + x] = (float)(s * (1.0 / (double)n));
+                *dst = (float)(s * (1.0 / (double)n));
             }
         }
     }
@@ -265,18 +253,24 @@ struct MaxF { __device__ float operator()(float a, float b) const { return fmaxf
 // multiple of eight (a cell row is whole 8-element words; bit L of `vec_levels`), are read a
 // 16-byte word per thread and step, every channel at once; other levels' cells one element per
 // thread.  The block folds every statistic in one pass through LDS.
-template <typename T>
+template <typename T, bool kPaged>
 __global__ void __launch_bounds__(kThreads)
-k_stats_part(VolGeom g, const T *__restrict__ master, const uint8_t *__restrict__ mask,
-              const int4 *cells, int nsub, uint32_t vec_levels, StatPart *part)
+k_stats_part(VolGeom g, MasterRef<const T> mr, const uint8_t *__restrict__ mask,
+             const int4 *cells, int nsub, int n_items, uint32_t vec_levels, StatPart *part)
 {
     constexpr int kW = kThreads / 64;
     __shared__ float s_mn[kW][kMaxC], s_mx[kW][kMaxC];
     __shared__ unsigned long long s_su[kW][kMaxC];
     __shared__ double s_sd[kW][kMaxC];
     __shared__ uint32_t s_in[kW][kMaxC];
-    const int4 cl = cells[blockIdx.x / nsub];
-    const int sub = blockIdx.x % nsub;
+    // work item = cell * nsub + slab; workgroup b takes item (b % 8) * per + b / 8, so an XCD
+    // works through a contiguous run of cells and x-neighbours, whose rows share 128-byte
+    // lines, meet in its L2 (workgroups are dealt to the eight XCDs round robin)
+    const int per = (int)(gridDim.x / kXcds);
+    const int item = (int)(blockIdx.x % kXcds) * per + (int)(blockIdx.x / kXcds);
+    if (item >= n_items) return;
+    const int4 cl = cells[item / nsub];
+    const int sub = item % nsub;
     const int L = cl.x;
     const int b[3] = {cl.y, cl.z, cl.w};
     int lo[3], n[3];
@@ -286,8 +280,6 @@ k_stats_part(VolGeom g, const T *__restrict__ master, const uint8_t *__restrict_
     }
     const int zc = (n[2] + nsub - 1) / nsub;
     const int zs = min(sub * zc, n[2]), ze = min(zs + zc, n[2]);
-    const int ex = g.ext[L][0], ey = g.ext[L][1];
-    const int64_t nlev = (int64_t)ex * ey * g.ext[L][2];
     const bool wide = (vec_levels >> L) & 1u;
     const int C = g.C;
     float mn[kMaxC], mx[kMaxC];
@@ -299,18 +291,17 @@ k_stats_part(VolGeom g, const T *__restrict__ master, const uint8_t *__restrict_
         su[c] = cnt[c] = 0;
         sd[c] = 0.0;
     }
-    const T *src = master + g.lvl_off[L];
     if (wide) {
         const int nq = n[0] >> 3;                    // 8-element words per cell row
         const int rows = (ze - zs) * n[1];
         for (int j = threadIdx.x; j < rows * nq; j += kThreads) {
             const int q = j % nq, r = j / nq;
             const int y = lo[1] + r % n[1], z = lo[2] + zs + r / n[1];
-            const int64_t lin = ((int64_t)z * ey + y) * ex + lo[0] + 8 * q;
+            const int64_t lin = ((int64_t)z * g.dims[1] + y) * g.dims[0] + lo[0] + 8 * q;   // mask (level 0)
             Pack8<T> v[kMaxC];
 #pragma unroll
             for (int c = 0; c < kMaxC; c++)
-                if (c < C) v[c] = Pack8<T>::load(src + c * nlev + lin);
+                if (c < C) v[c] = Pack8<T>::load(melem<kPaged>(g, mr, L, c, lo[0] + 8 * q, y, z));
 #pragma unroll
             for (int c = 0; c < kMaxC; c++)
                 if (c < C)
@@ -338,9 +329,9 @@ k_stats_part(VolGeom g, const T *__restrict__ master, const uint8_t *__restrict_
         if (r0 < rstep)
             for (int z = zs; z < ze; z++)
                 for (int y = r0; y < n[1]; y += rstep) {
-                    const int64_t lin = ((int64_t)(lo[2] + z) * ey + (lo[1] + y)) * ex + (lo[0] + x);
+                    const int64_t lin = ((int64_t)(lo[2] + z) * g.dims[1] + (lo[1] + y)) * g.dims[0] + (lo[0] + x);
                     for (int c = 0; c < C; c++) {
-                        const T v = src[c * nlev + lin];
+                        const T v = *melem<kPaged>(g, mr, L, c, lo[0] + x, lo[1] + y, lo[2] + z);
                         mn[c] = fminf(mn[c], (float)v);
                         mx[c] = fmaxf(mx[c], (float)v);
                         if constexpr (sizeof(T) == 2) su[c] += v;
@@ -386,7 +377,7 @@ k_stats_part(VolGeom g, const T *__restrict__ master, const uint8_t *__restrict_
             d += s_sd[i][c];
             k += s_in[i][c];
         }
-        StatPart *o = part + blockIdx.x;
+        StatPart *o = part + item;
         if (c < C) {
             o->mn[c] = a;
             o->mx[c] = z;
@@ -462,9 +453,9 @@ k_apply_deltas(DevCell *table, float *miss_range, const CellDelta *d, int n)
 #endif
 constexpr int kGatherThreads = OCTRC_GATHER_THREADS;
 
-template <typename T>
+template <typename T, bool kPaged>
 __global__ void __launch_bounds__(kGatherThreads)
-k_gather(VolGeom g, const T *master, const DevCell *table, uint8_t *pool, uint64_t brick_bytes,
+k_gather(VolGeom g, MasterRef<const T> mr, const DevCell *table, uint8_t *pool, uint64_t brick_bytes,
          const BrickJob *jobs, int n_jobs, float *slot_range, float background)
 {
     __shared__ int s_kind[27];
@@ -491,8 +482,7 @@ k_gather(VolGeom g, const T *master, const DevCell *table, uint8_t *pool, uint64
     }
     __syncthreads();
     const int ex = g.ext[L][0], ey = g.ext[L][1], ez = g.ext[L][2];
-    const int64_t nlev = (int64_t)ex * ey * ez;
-    const T *src = master + g.lvl_off[L];
+    const int64_t slice = (int64_t)ex * ey, plane = slice * ez;   // dense master strides
     float mn[kMaxC], mx[kMaxC];
     for (int c = 0; c < kMaxC; c++) {
         mn[c] = FLT_MAX;
@@ -507,7 +497,7 @@ k_gather(VolGeom g, const T *master, const DevCell *table, uint8_t *pool, uint64
         const int ox = gx < b[0] * M ? 0 : (gx >= b[0] * M + M ? 2 : 1);
         const int gy = min(max(b[1] * M - 1 + y, 0), ey - 1);
         const int oy = gy < b[1] * M ? 0 : (gy >= b[1] * M + M ? 2 : 1);
-        const int64_t row = (int64_t)gy * ex + gx;
+        const T *col = kPaged ? nullptr : melem<false>(g, mr, L, 0, gx, gy, 0);   // dense: column base
 #pragma unroll 4
         for (int z = job.lo[2]; z <= job.hi[2]; z++) {
             const int gz = min(max(b[2] * M - 1 + z, 0), ez - 1);
@@ -515,8 +505,12 @@ k_gather(VolGeom g, const T *master, const DevCell *table, uint8_t *pool, uint64
             const int nb = (oz * 3 + oy) * 3 + ox;
             T v[4];
             if (s_kind[nb] != kAvg) {
-                const int64_t lin = (int64_t)gz * ey * ex + row;
-                for (int c = 0; c < 4; c++) v[c] = c < g.C ? src[(int64_t)c * nlev + lin] : (T)0;
+                if constexpr (kPaged) {
+                    for (int c = 0; c < 4; c++) v[c] = c < g.C ? *melem<true>(g, mr, L, c, gx, gy, gz) : (T)0;
+                } else {
+                    const T *p = col + (int64_t)gz * slice;
+                    for (int c = 0; c < 4; c++) v[c] = c < g.C ? p[(int64_t)c * plane] : (T)0;
+                }
             } else {
                 for (int c = 0; c < 4; c++) v[c] = c < g.C ? (T)s_avg[nb][c] : (T)0;
             }
@@ -602,38 +596,66 @@ inline unsigned ceil_div(int64_t a, int64_t b) { return (unsigned)((a + b - 1) /
 
 }  // namespace
 
+// The master as the kernels see it: dense levels, or the device page table of the disk tier.
+template <typename T>
+static MasterRef<T> master_ref(const VolGeom &g, void *master)
+{
+    if (g.plog > 0) return MasterRef<T>{nullptr, (T *const *)master};
+    return MasterRef<T>{(T *)master, nullptr};
+}
+
+// Calls f(T{}, std::bool_constant<paged>{}) for the master's element type and layout.
+template <typename F>
+static void by_type(const VolGeom &g, F &&f)
+{
+    if (g.dtype == 0) {
+        if (g.plog > 0) f(uint16_t{}, std::true_type{});
+        else f(uint16_t{}, std::false_type{});
+    } else {
+        if (g.plog > 0) f(float{}, std::true_type{});
+        else f(float{}, std::false_type{});
+    }
+}
+
 hipError_t launch_insert(const VolGeom &g, void *master, uint8_t *mask, const void *src,
-                         int channel, const int32_t o[3], const int32_t n[3], hipStream_t s)
+                         const int64_t sp[3], int channel, const int32_t o[3], const int32_t n[3],
+                         hipStream_t s)
 {
     if ((int64_t)n[0] * n[1] * n[2] == 0) return hipSuccess;
-    const bool wide = o[0] % 8 == 0 && n[0] % 8 == 0 && g.dims[0] % 8 == 0 && g.lvl_off[0] % 8 == 0 &&
-                      ((uintptr_t)src & 15) == 0 && ((uintptr_t)master & 15) == 0 &&
-                      ((uintptr_t)mask & 15) == 0;
-    if (wide) {
-        const int64_t items = (int64_t)(n[0] / 8) * n[1] * n[2];
-        const dim3 grid((unsigned)std::min<int64_t>(ceil_div(items, kThreads), 1 << 20));
-        if (g.dtype == 0)
-            hipLaunchKernelGGL(k_insert8<uint16_t>, grid, dim3(kThreads), 0, s, g, (uint16_t *)master,
-                               mask, (const uint16_t *)src, channel, o[0], o[1], o[2], n[0], n[1], n[2]);
-        else
-            hipLaunchKernelGGL(k_insert8<float>, grid, dim3(kThreads), 0, s, g, (float *)master, mask,
-                               (const float *)src, channel, o[0], o[1], o[2], n[0], n[1], n[2]);
-        return hipGetLastError();
-    }
-    dim3 grid(ceil_div(n[0], kThreads), (unsigned)std::min<int64_t>((int64_t)n[1] * n[2], 65535));
-    if (g.dtype == 0)
-        hipLaunchKernelGGL(k_insert<uint16_t>, grid, dim3(kThreads), 0, s, g, (uint16_t *)master,
-                           mask, (const uint16_t *)src, channel, o[0], o[1], o[2], n[0], n[1], n[2]);
-    else
-        hipLaunchKernelGGL(k_insert<float>, grid, dim3(kThreads), 0, s, g, (float *)master, mask,
-                           (const float *)src, channel, o[0], o[1], o[2], n[0], n[1], n[2]);
+    // 16-byte words: rows of the block, of the level-0 mask and of the master (or its pages)
+    // start on multiples of eight elements
+    const bool layout = g.plog > 0 ? g.plog >= 3
+                                   : (g.lvl_off[0] % 8 == 0 && ((uintptr_t)master & 15) == 0);
+    const bool wide = layout && o[0] % 8 == 0 && n[0] % 8 == 0 && g.dims[0] % 8 == 0 &&
+                      sp[0] % 8 == 0 && sp[1] % 8 == 0 && sp[2] % 8 == 0 &&
+                      ((uintptr_t)src & 15) == 0 && ((uintptr_t)mask & 15) == 0;
+    by_type(g, [&](auto tv, auto paged) {
+        using T = decltype(tv);
+        constexpr bool kP = decltype(paged)::value;
+        const MasterRef<T> mr = master_ref<T>(g, master);
+        if (wide) {
+            const int64_t items = (int64_t)(n[0] / 8) * n[1] * n[2];
+            const dim3 grid((unsigned)std::min<int64_t>(ceil_div(items, kThreads), 1 << 20));
+            hipLaunchKernelGGL((k_insert8<T, kP>), grid, dim3(kThreads), 0, s, g, mr, mask,
+                               (const T *)src, sp[0], sp[1], sp[2], channel, o[0], o[1], o[2],
+                               n[0], n[1], n[2]);
+        } else {
+            const dim3 grid(ceil_div(n[0], kThreads),
+                            (unsigned)std::min<int64_t>((int64_t)n[1] * n[2], 65535));
+            hipLaunchKernelGGL((k_insert<T, kP>), grid, dim3(kThreads), 0, s, g, mr, mask,
+                               (const T *)src, sp[0], sp[1], sp[2], channel, o[0], o[1], o[2],
+                               n[0], n[1], n[2]);
+        }
+    });
     return hipGetLastError();
 }
 
 // Level L's channel planes start on multiples of `a` elements and its rows are multiples of
-// `a` elements long.
+// `a` elements long (dense master); with pages, rows of `a` elements stay inside a page row
+// and only the extent matters.
 static bool level_aligned(const VolGeom &g, int L, int a)
 {
+    if (g.plog > 0) return g.ext[L][0] % a == 0 && (1 << g.plog) % 8 == 0;
     const int64_t plane = (int64_t)g.ext[L][0] * g.ext[L][1] * g.ext[L][2];
     return g.ext[L][0] % a == 0 && g.lvl_off[L] % a == 0 && plane % a == 0;
 }
@@ -643,26 +665,26 @@ hipError_t launch_downsample(const VolGeom &g, void *master, int L, const int32_
 {
     const int ny = hi[1] - lo[1] + 1, nz = hi[2] - lo[2] + 1;
     if (hi[0] < lo[0] || ny <= 0 || nz <= 0) return hipSuccess;
-    if (level_aligned(g, L, 8) && level_aligned(g, L + 1, 4) && ((uintptr_t)master & 15) == 0) {
-        const int q0 = lo[0] / 4, nq = hi[0] / 4 - q0 + 1;
-        const int64_t items = (int64_t)nq * ny * nz;
-        const dim3 grid((unsigned)std::min<int64_t>(ceil_div(items, kThreads), 1 << 20));
-        if (g.dtype == 0)
-            hipLaunchKernelGGL(k_downsample4<uint16_t>, grid, dim3(kThreads), 0, s, g,
-                               (uint16_t *)master, L, q0, nq, lo[1], lo[2], ny, nz);
-        else
-            hipLaunchKernelGGL(k_downsample4<float>, grid, dim3(kThreads), 0, s, g, (float *)master,
-                               L, q0, nq, lo[1], lo[2], ny, nz);
-        return hipGetLastError();
-    }
-    const int64_t rows = (int64_t)ny * nz;
-    dim3 grid(ceil_div(hi[0] - lo[0] + 1, kThreads), (unsigned)std::min<int64_t>(rows, 65535));
-    if (g.dtype == 0)
-        hipLaunchKernelGGL(k_downsample<uint16_t>, grid, dim3(kThreads), 0, s, g,
-                           (uint16_t *)master, L, lo[0], lo[1], lo[2], hi[0], hi[1], hi[2]);
-    else
-        hipLaunchKernelGGL(k_downsample<float>, grid, dim3(kThreads), 0, s, g, (float *)master, L,
-                           lo[0], lo[1], lo[2], hi[0], hi[1], hi[2]);
+    const bool wide = level_aligned(g, L, 8) && level_aligned(g, L + 1, 4) &&
+                      (g.plog > 0 || ((uintptr_t)master & 15) == 0);
+    by_type(g, [&](auto tv, auto paged) {
+        using T = decltype(tv);
+        constexpr bool kP = decltype(paged)::value;
+        const MasterRef<T> mr = master_ref<T>(g, master);
+        if (wide) {
+            const int q0 = lo[0] / 4, nq = hi[0] / 4 - q0 + 1;
+            const int64_t items = (int64_t)nq * ny * nz;
+            const dim3 grid((unsigned)std::min<int64_t>(ceil_div(items, kThreads), 1 << 20));
+            hipLaunchKernelGGL((k_downsample4<T, kP>), grid, dim3(kThreads), 0, s, g, mr, L, q0,
+                               nq, lo[1], lo[2], ny, nz);
+        } else {
+            const int64_t rows = (int64_t)ny * nz;
+            const dim3 grid(ceil_div(hi[0] - lo[0] + 1, kThreads),
+                            (unsigned)std::min<int64_t>(rows, 65535));
+            hipLaunchKernelGGL((k_downsample<T, kP>), grid, dim3(kThreads), 0, s, g, mr, L, lo[0],
+                               lo[1], lo[2], hi[0], hi[1], hi[2]);
+        }
+    });
     return hipGetLastError();
 }
 
@@ -679,17 +701,20 @@ hipError_t launch_stats(const VolGeom &g, const void *master, const uint8_t *mas
     if (n == 0) return hipSuccess;
     const int nsub = stats_nsub(g);
     uint32_t vec_levels = 0;
-    if (g.M % 8 == 0 && ((uintptr_t)master & 15) == 0 && ((uintptr_t)mask & 15) == 0)
+    if (g.M % 8 == 0 && (g.plog > 0 || ((uintptr_t)master & 15) == 0) && ((uintptr_t)mask & 15) == 0)
         for (int L = 0; L <= g.N; L++)
             if (level_aligned(g, L, 8)) vec_levels |= 1u << L;
     StatPart *part = (StatPart *)scratch;
-    if (g.dtype == 0)
-        hipLaunchKernelGGL(k_stats_part<uint16_t>, dim3(n * nsub), dim3(kThreads), 0, s, g,
-                           (const uint16_t *)master, mask, (const int4 *)cells, nsub, vec_levels,
-                           part);
-    else
-        hipLaunchKernelGGL(k_stats_part<float>, dim3(n * nsub), dim3(kThreads), 0, s, g,
-                           (const float *)master, mask, (const int4 *)cells, nsub, vec_levels, part);
+    by_type(g, [&](auto tv, auto paged) {
+        using T = decltype(tv);
+        constexpr bool kP = decltype(paged)::value;
+        const MasterRef<T> m0 = master_ref<T>(g, (void *)master);
+        const MasterRef<const T> mr{m0.base, m0.pages};
+        const int items = n * nsub;
+        hipLaunchKernelGGL((k_stats_part<T, kP>), dim3((unsigned)(ceil_div(items, kXcds) * kXcds)),
+                           dim3(kThreads), 0, s, g, mr, mask, (const int4 *)cells, nsub, items,
+                           vec_levels, part);
+    });
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_stats_fold, dim3(ceil_div(n, kThreads)), dim3(kThreads), 0, s, n, nsub,
@@ -712,13 +737,14 @@ hipError_t launch_gather(const VolGeom &g, const void *master, const DevCell *ta
 {
     if (n == 0) return hipSuccess;
     const dim3 grid((unsigned)(ceil_div(n, kXcds) * kXcds));
-    if (g.dtype == 0)
-        hipLaunchKernelGGL(k_gather<uint16_t>, grid, dim3(kGatherThreads), 0, s, g,
-                           (const uint16_t *)master, table, (uint8_t *)pool, brick_bytes, jobs, n,
-                           slot_range, background);
-    else
-        hipLaunchKernelGGL(k_gather<float>, grid, dim3(kGatherThreads), 0, s, g, (const float *)master,
-                           table, (uint8_t *)pool, brick_bytes, jobs, n, slot_range, background);
+    by_type(g, [&](auto tv, auto paged) {
+        using T = decltype(tv);
+        constexpr bool kP = decltype(paged)::value;
+        const MasterRef<T> m0 = master_ref<T>(g, (void *)master);
+        const MasterRef<const T> mr{m0.base, m0.pages};
+        hipLaunchKernelGGL((k_gather<T, kP>), grid, dim3(kGatherThreads), 0, s, g, mr, table,
+                           (uint8_t *)pool, brick_bytes, jobs, n, slot_range, background);
+    });
     return hipGetLastError();
 }
 
@@ -754,16 +780,19 @@ hipError_t launch_fill_f32(float *p, int64_t n, float v, hipStream_t s)
 hipError_t launch_clear(const VolGeom &g, void *master, uint8_t *mask, double background,
                         hipStream_t s)
 {
-    const int64_t n = g.lvl_off[g.N + 1];
-    const unsigned blocks = (unsigned)std::min<int64_t>(ceil_div(n, kThreads), 65536);
-    if (g.dtype == 0)
-        hipLaunchKernelGGL(k_fill<uint16_t>, dim3(blocks), dim3(kThreads), 0, s, (uint16_t *)master,
-                           n, (uint16_t)background);
-    else
-        hipLaunchKernelGGL(k_fill<float>, dim3(blocks), dim3(kThreads), 0, s, (float *)master, n,
-                           (float)background);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    // a paged master is reset on the host (every page back to the background)
+    if (g.plog == 0) {
+        const int64_t n = g.lvl_off[g.N + 1];
+        const unsigned blocks = (unsigned)std::min<int64_t>(ceil_div(n, kThreads), 65536);
+        if (g.dtype == 0)
+            hipLaunchKernelGGL(k_fill<uint16_t>, dim3(blocks), dim3(kThreads), 0, s,
+                               (uint16_t *)master, n, (uint16_t)background);
+        else
+            hipLaunchKernelGGL(k_fill<float>, dim3(blocks), dim3(kThreads), 0, s, (float *)master,
+                               n, (float)background);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
     const int64_t nm = (int64_t)g.dims[0] * g.dims[1] * g.dims[2];
     hipLaunchKernelGGL(k_fill<uint8_t>, dim3((unsigned)std::min<int64_t>(ceil_div(nm, kThreads), 65536)),
                        dim3(kThreads), 0, s, mask, nm, (uint8_t)0);

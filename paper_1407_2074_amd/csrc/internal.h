@@ -38,7 +38,41 @@ struct VolGeom {
     int64_t lvl_off[kMaxLevels];   // element offset of level L in the master buffer
     int32_t grid[kMaxLevels];      // cells per axis at level L = 2^(N-L)
     int32_t cell_off[kMaxLevels];  // offset of level L in the node table
+    // disk tier (paged master): level L is cut into pages of P^3 voxels (P = 2^plog, a multiple
+    // of M), pgrid[L] pages along x and y, page ids from page_off[L]; within a page the voxels
+    // are planar per channel, [c][z][y][x].  plog = 0: the master is dense (lvl_off).
+    int32_t plog;
+    int32_t pgrid[kMaxLevels][2];
+    int64_t page_off[kMaxLevels + 1];
 };
+
+// Where the build kernels find the master: dense levels, or the frame of each page (device
+// addresses of the pinned RAM frames of the disk tier; only the pages of the current batch are
+// valid).
+template <typename T>
+struct MasterRef {
+    T *base;
+    T *const *pages;
+};
+
+// Element (x, y, z) of channel c at level L; with kPaged, elements x .. x + k of a row stay in
+// one page while x + k < the next multiple of P.
+template <bool kPaged, typename T>
+__host__ __device__ inline T *melem(const VolGeom &g, const MasterRef<T> &m, int L, int c, int x,
+                                    int y, int z)
+{
+    if constexpr (kPaged) {
+        const int pl = g.plog, pm = (1 << pl) - 1;
+        const int64_t pid = g.page_off[L] +
+                            ((int64_t)(z >> pl) * g.pgrid[L][1] + (y >> pl)) * g.pgrid[L][0] + (x >> pl);
+        return m.pages[pid] + ((((int64_t)c << pl) + (z & pm)) << (2 * pl)) +
+               ((int64_t)(y & pm) << pl) + (x & pm);
+    } else {
+        const int64_t plane = (int64_t)g.ext[L][0] * g.ext[L][1] * g.ext[L][2];
+        return m.base + g.lvl_off[L] + (int64_t)c * plane +
+               ((int64_t)z * g.ext[L][1] + y) * g.ext[L][0] + x;
+    }
+}
 
 // Per-ray state of a refinement view (OCT_MISSING_REFINE), kept between passes: status 0 =
 // not started (zero-filled memory), 1 = finished (acc is the result), 2 = waiting before
@@ -163,9 +197,13 @@ struct alignas(128) RenderCounters {
 };
 
 // ---- launchers (build path) ----
+// `master` is the dense master (g.plog == 0) or, for the disk tier, the device page table
+// (void *[pages], the frame of every page the launch touches).
+// Insert: the block's voxels in [C or 1][z][y][x] with row / slice / channel pitches
+// src_pitch (elements); the region written is origin .. origin + size - 1.
 hipError_t launch_insert(const VolGeom &g, void *master, uint8_t *mask, const void *src,
-                         int channel, const int32_t origin[3], const int32_t size[3],
-                         hipStream_t s);
+                         const int64_t src_pitch[3], int channel, const int32_t origin[3],
+                         const int32_t size[3], hipStream_t s);
 hipError_t launch_downsample(const VolGeom &g, void *master, int L, const int32_t lo[3],
                              const int32_t hi[3], hipStream_t s);
 size_t stats_scratch_bytes(const VolGeom &g, int n);

@@ -3,12 +3,14 @@
 // and render_kernels.hip; this file only decides what to launch.
 #include "../../include/octree_rc.h"
 #include "internal.h"
+#include "page_cache.h"
 #include "raycommon.h"
 
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <deque>
 #include <mutex>
 #include <new>
 #include <string>
@@ -174,7 +176,17 @@ struct oct_handle {
     // paging (capped pool): render flags per cell, missing-brick value bounds, LRU stamps
     bool capped = false;
     bool master_host = false;
-    void *master_alloc = nullptr;  // host allocation when the master lives in pinned memory
+    void *master_alloc = nullptr;  // host allocation when the master (or its RAM frames) lives in pinned memory
+    // disk tier: page file with its RAM frames (master_alloc), the device page table (master)
+    // and its pinned mirror, and the build-kernel batches in flight (sequence number, end
+    // event) that the frames' pinning waits for
+    PageCache *pc = nullptr;
+    uint8_t *frames_dev = nullptr;
+    void **ptab_host = nullptr;
+    hipEvent_t ptab_ev = nullptr;
+    uint64_t pg_seq = 0;
+    std::deque<std::pair<uint64_t, hipEvent_t>> pg_batches;
+    std::vector<hipEvent_t> pg_free;
     uint8_t *flags = nullptr;
     uint8_t *flags_host = nullptr;
     float *miss_range = nullptr;
@@ -538,8 +550,30 @@ bool valid_params(const oct_create_params *p, std::string &why)
         why = "u16 background must be an integer in [0, 65535]";
         return false;
     }
-    for (int i = 0; i < 3; i++)
+    for (int i = 0; i < 2; i++)
         if (p->reserved[i]) { why = "reserved fields must be 0"; return false; }
+    if (p->master_on_host < OCT_MASTER_HBM || p->master_on_host > OCT_MASTER_DISK) {
+        why = "master_on_host must be OCT_MASTER_HBM, _HOST or _DISK";
+        return false;
+    }
+    if (p->master_on_host == OCT_MASTER_DISK) {
+        const int pc = p->page_cells ? p->page_cells : 2;
+        if (p->brick_size & (p->brick_size - 1)) {
+            why = "the disk tier needs brick_size a power of two";
+            return false;
+        }
+        if (pc < 2 || (pc & (pc - 1)) || (int64_t)pc * p->brick_size > 1024) {
+            why = "page_cells must be a power of two >= 2 (at most 1024 voxels per page edge)";
+            return false;
+        }
+        if (!p->disk_path || !p->disk_path[0]) {
+            why = "the disk tier needs disk_path";
+            return false;
+        }
+    } else if (p->page_cells || p->host_cache_bytes || p->disk_path) {
+        why = "page_cells, host_cache_bytes and disk_path belong to the disk tier";
+        return false;
+    }
     return true;
 }
 
@@ -700,6 +734,192 @@ bool box_intersects(const Box &b, const int lo[3], const int hi[3])
     return true;
 }
 
+// ------------------------------------------------------------------- disk tier
+// Build kernels of the disk tier run in batches: a batch's pages are made resident (loaded,
+// filled, or already in RAM), written into the device page table, and pinned until the batch's
+// end event, which later evictions of their frames wait for.
+
+// End of every batch up to `seq` (blocking) / without blocking, whether they have ended.
+void pg_wait(oct_handle *h, uint64_t seq)
+{
+    while (!h->pg_batches.empty() && h->pg_batches.front().first <= seq) {
+        (void)hipEventSynchronize(h->pg_batches.front().second);
+        h->pg_free.push_back(h->pg_batches.front().second);
+        h->pg_batches.pop_front();
+    }
+}
+
+bool pg_done(oct_handle *h, uint64_t seq)
+{
+    while (!h->pg_batches.empty() && h->pg_batches.front().first <= seq &&
+           hipEventQuery(h->pg_batches.front().second) == hipSuccess) {
+        h->pg_free.push_back(h->pg_batches.front().second);
+        h->pg_batches.pop_front();
+    }
+    return h->pg_batches.empty() || h->pg_batches.front().first > seq;
+}
+
+// Pages a batch may hold: half the frames, so that a batch finds frames whose previous batch
+// has ended while the one before it still runs (at least the 9 of one downsample step).
+int64_t pg_budget(const oct_handle *h) { return std::max<int64_t>(9, h->pc->n_frames() / 2); }
+
+// Page range along each axis of level L's voxel box lo..hi (clamped to the level); false when
+// the box is empty.
+bool page_range(const VolGeom &g, int L, const int lo[3], const int hi[3], int a0[3], int a1[3])
+{
+    for (int a = 0; a < 3; a++) {
+        const int l = std::max(lo[a], 0), u = std::min(hi[a], g.ext[L][a] - 1);
+        if (u < l) return false;
+        a0[a] = l >> g.plog;
+        a1[a] = u >> g.plog;
+    }
+    return true;
+}
+
+int64_t count_box_pages(const VolGeom &g, int L, const int lo[3], const int hi[3])
+{
+    int a0[3], a1[3];
+    if (!page_range(g, L, lo, hi, a0, a1)) return 0;
+    return (int64_t)(a1[0] - a0[0] + 1) * (a1[1] - a0[1] + 1) * (a1[2] - a0[2] + 1);
+}
+
+void add_box_pages(const VolGeom &g, int L, const int lo[3], const int hi[3], uint8_t write,
+                   std::vector<int64_t> &pages, std::vector<uint8_t> &writes)
+{
+    int a0[3], a1[3];
+    if (!page_range(g, L, lo, hi, a0, a1)) return;
+    for (int z = a0[2]; z <= a1[2]; z++)
+        for (int y = a0[1]; y <= a1[1]; y++)
+            for (int x = a0[0]; x <= a1[0]; x++) {
+                pages.push_back(g.page_off[L] + ((int64_t)z * g.pgrid[L][1] + y) * g.pgrid[L][0] + x);
+                writes.push_back(write);
+            }
+}
+
+// Runs launch() as one batch on stream s with `pages` resident and mapped (writes[i]: the
+// batch modifies pages[i]).
+template <typename F>
+int paged_batch(oct_handle *h, std::vector<int64_t> &pages, std::vector<uint8_t> &writes,
+                hipStream_t s, F &&launch)
+{
+    if (pages.empty()) return launch();
+    // distinct pages, a page written if any of its entries is
+    std::vector<std::pair<int64_t, uint8_t>> pw(pages.size());
+    for (size_t i = 0; i < pages.size(); i++) pw[i] = {pages[i], writes[i]};
+    std::sort(pw.begin(), pw.end());
+    pages.clear();
+    writes.clear();
+    for (const auto &e : pw) {
+        if (!pages.empty() && pages.back() == e.first) writes.back() |= e.second;
+        else {
+            pages.push_back(e.first);
+            writes.push_back(e.second);
+        }
+    }
+    const uint64_t seq = ++h->pg_seq;
+    std::string err;
+    const int r = h->pc->acquire(pages.data(), (int)pages.size(), writes.data(), seq,
+                                 [h](uint64_t q) { pg_wait(h, q); },
+                                 [h](uint64_t q) { return pg_done(h, q); }, err);
+    if (r == -1) return fail(h, OCT_ENOMEM, err);
+    if (r < 0) return fail(h, OCT_EDEVICE, err);
+    // the page table's entries for this batch; the mirror's previous copy must have been read
+    HIPCHK(h, hipEventSynchronize(h->ptab_ev));
+    for (int64_t p : pages)
+        h->ptab_host[p] = h->frames_dev + (size_t)h->pc->frame_of(p) * h->pc->page_bytes();
+    const int64_t lo = pages.front(), n = pages.back() - pages.front() + 1;
+    HIPCHK(h, hipMemcpyAsync((void **)h->master + lo, h->ptab_host + lo, (size_t)n * sizeof(void *),
+                             hipMemcpyHostToDevice, s));
+    HIPCHK(h, hipEventRecord(h->ptab_ev, s));
+    const int rc = launch();
+    if (rc) return rc;
+    hipEvent_t ev;
+    if (!h->pg_free.empty()) {
+        ev = h->pg_free.back();
+        h->pg_free.pop_back();
+    } else {
+        HIPCHK(h, hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    }
+    HIPCHK(h, hipEventRecord(ev, s));
+    h->pg_batches.push_back({seq, ev});
+    return OCT_OK;
+}
+
+// Bordered-brick gathers of jobs[j0 .. j1) (jobs_dev: the same jobs on the device) in runs
+// whose source pages fit a batch.
+int gather_paged(oct_handle *h, const std::vector<BrickJob> &jobs, int j0, int j1,
+                 const BrickJob *jobs_dev, const DevCell *table, hipStream_t s)
+{
+    const VolGeom &g = h->g;
+    const int M = g.M;
+    const int64_t budget = pg_budget(h);
+    for (int i0 = j0; i0 < j1;) {
+        std::vector<int64_t> pages;
+        std::vector<uint8_t> wr;
+        int i1 = i0;
+        for (; i1 < j1; i1++) {
+            const BrickJob &jb = jobs[(size_t)i1];
+            const int b[3] = {jb.bx, jb.by, jb.bz};
+            int lo[3], hi[3];
+            for (int a = 0; a < 3; a++) {
+                lo[a] = b[a] * M - 1 + jb.lo[a];
+                hi[a] = b[a] * M - 1 + jb.hi[a];
+            }
+            std::vector<int64_t> cp;
+            std::vector<uint8_t> cw;
+            add_box_pages(g, jb.level, lo, hi, 0, cp, cw);
+            int fresh = 0;
+            for (int64_t q : cp) fresh += std::find(pages.begin(), pages.end(), q) == pages.end();
+            if (i1 > i0 && (int64_t)pages.size() + fresh > budget) break;
+            for (int64_t q : cp)
+                if (std::find(pages.begin(), pages.end(), q) == pages.end()) {
+                    pages.push_back(q);
+                    wr.push_back(0);
+                }
+        }
+        const int a0 = i0, n = i1 - i0;
+        const int rc = paged_batch(h, pages, wr, s, [&]() -> int {
+            HIPCHK(h, launch_gather(g, h->master, table, h->pool, h->brick_bytes, jobs_dev + a0, n,
+                                    h->slot_range, h->background_f, s));
+            return OCT_OK;
+        });
+        if (rc) return rc;
+        i0 = i1;
+    }
+    return OCT_OK;
+}
+
+// Splits the box lo..hi of level Lt into sub-boxes along whole pages of Lt (z rows, then y
+// rows, then x columns) such that pages_of(sub-box) <= budget where possible (a single page
+// column is taken as it is), and calls f(sub_lo, sub_hi) for each, in order.
+template <typename Count, typename F>
+int split_by_pages(const VolGeom &g, const int lo[3], const int hi[3], int64_t budget,
+                   Count &&pages_of, F &&f)
+{
+    const int P = 1 << g.plog;
+    auto rec = [&](auto &&self, int axis, const int *blo, const int *bhi) -> int {
+        if (axis < 0 || pages_of(blo, bhi) <= budget) return f(blo, bhi);
+        // greedy runs of whole page rows along `axis`
+        int r = blo[axis];
+        while (r <= bhi[axis]) {
+            int sl[3] = {blo[0], blo[1], blo[2]}, sh[3] = {bhi[0], bhi[1], bhi[2]};
+            sl[axis] = r;
+            sh[axis] = std::min(bhi[axis], (r / P) * P + P - 1);   // one page row
+            while (sh[axis] < bhi[axis]) {
+                int th[3] = {sh[0], sh[1], sh[2]};
+                th[axis] = std::min(bhi[axis], sh[axis] + P);
+                if (pages_of(sl, th) > budget) break;
+                sh[axis] = th[axis];
+            }
+            const int rc = pages_of(sl, sh) <= budget ? f(sl, sh) : self(self, axis - 1, sl, sh);
+            if (rc) return rc;
+            r = sh[axis] + 1;
+        }
+        return OCT_OK;
+    };
+    return rec(rec, 2, lo, hi);
+}
+
 }  // namespace
 
 // =================================================================== C ABI
@@ -783,7 +1003,7 @@ int octree_create(const oct_create_params *params, void *stream, oct_handle **ou
         }
         h->n_cow = std::min<int64_t>(cow, h->n_slots);
     }
-    h->master_host = params->master_on_host != 0;
+    h->master_host = params->master_on_host == OCT_MASTER_HOST;
     h->cells.assign((size_t)h->n_cells, HCell());
     h->dirty.assign((size_t)N + 1, std::vector<Box>());
 
@@ -796,7 +1016,55 @@ int octree_create(const oct_create_params *params, void *stream, oct_handle **ou
         return OCT_OK;
     };
     int rc;
-    if (h->master_host) {
+    if (params->master_on_host == OCT_MASTER_DISK) {
+        // pages of P^3 voxels (P = M * page_cells) per level, all channels
+        const int P = g.M * (params->page_cells ? params->page_cells : 2);
+        while ((1 << g.plog) < P) g.plog++;
+        int64_t np = 0;
+        for (int L = 0; L <= N; L++) {
+            int64_t n3[3];
+            for (int a = 0; a < 3; a++) n3[a] = (g.ext[L][a] + P - 1) / P;
+            g.pgrid[L][0] = (int32_t)n3[0];
+            g.pgrid[L][1] = (int32_t)n3[1];
+            g.page_off[L] = np;
+            np += n3[0] * n3[1] * n3[2];
+        }
+        g.page_off[N + 1] = np;
+        const size_t page_bytes = (size_t)P * P * P * (size_t)g.C * h->esz;
+        const int64_t n_frames = std::min<int64_t>((int64_t)(params->host_cache_bytes / page_bytes), np);
+        if (n_frames < std::min<int64_t>(16, np) || n_frames > INT32_MAX) {
+            h->err = "host_cache_bytes must hold at least 16 pages of " + std::to_string(page_bytes) +
+                     " bytes (or every page)";
+            return bail(OCT_EINVAL);
+        }
+        // RAM frames (pinned, mapped for the kernels), the device page table and its mirror
+        hipError_t e = hipHostMalloc(&h->master_alloc, (size_t)n_frames * page_bytes, hipHostMallocMapped);
+        if (e == hipSuccess) e = hipHostGetDevicePointer((void **)&h->frames_dev, h->master_alloc, 0);
+        if (e == hipSuccess) e = hipHostMalloc((void **)&h->ptab_host, (size_t)np * sizeof(void *), hipHostMallocDefault);
+        if (e != hipSuccess) {
+            h->err = std::string("disk tier frames: ") + hipGetErrorString(e);
+            return bail(e == hipErrorOutOfMemory ? OCT_ENOMEM : OCT_EDEVICE);
+        }
+        std::memset(h->ptab_host, 0, (size_t)np * sizeof(void *));
+        if ((rc = dev_alloc(&h->master, (size_t)np * sizeof(void *)))) return bail(rc);
+        if (hipMemcpy(h->master, h->ptab_host, (size_t)np * sizeof(void *), hipMemcpyHostToDevice) != hipSuccess ||
+            hipEventCreateWithFlags(&h->ptab_ev, hipEventDisableTiming) != hipSuccess)
+            return bail(OCT_EDEVICE);
+        const bool u16 = params->dtype == OCT_U16;
+        const double bg = params->background;
+        h->pc = new (std::nothrow) PageCache();
+        if (!h->pc) return bail(OCT_ENOMEM);
+        std::string perr;
+        if (!h->pc->open(params->disk_path, np, page_bytes, (uint8_t *)h->master_alloc, (int)n_frames,
+                         [u16, bg, page_bytes](uint8_t *f) {
+                             if (u16) std::fill_n((uint16_t *)f, page_bytes / 2, (uint16_t)bg);
+                             else std::fill_n((float *)f, page_bytes / 4, (float)bg);
+                         },
+                         perr)) {
+            h->err = perr;
+            return bail(OCT_EINVAL);
+        }
+    } else if (h->master_host) {
         // pinned host memory, mapped for the kernels (they read and write it over the link)
         hipError_t e = hipHostMalloc(&h->master_alloc, std::max<size_t>((size_t)off * h->esz, 256),
                                      hipHostMallocMapped);
@@ -851,8 +1119,19 @@ int octree_destroy(oct_handle *h)
     if (!h) return OCT_EINVAL;
     (void)hipSetDevice(h->device);
     (void)hipDeviceSynchronize();
-    if (h->master_alloc) (void)hipHostFree(h->master_alloc);
-    else if (h->master) (void)hipFree(h->master);
+    if (h->pc) {
+        pg_wait(h, UINT64_MAX);
+        delete h->pc;   // removes the page file
+        for (hipEvent_t e : h->pg_free) (void)hipEventDestroy(e);
+        if (h->ptab_ev) (void)hipEventDestroy(h->ptab_ev);
+        if (h->ptab_host) (void)hipHostFree(h->ptab_host);
+        if (h->master) (void)hipFree(h->master);   // the device page table
+        if (h->master_alloc) (void)hipHostFree(h->master_alloc);
+    } else if (h->master_alloc) {
+        (void)hipHostFree(h->master_alloc);
+    } else if (h->master) {
+        (void)hipFree(h->master);
+    }
     if (h->flags) (void)hipFree(h->flags);
     if (h->flags_host) (void)hipHostFree(h->flags_host);
     if (h->miss_range) (void)hipFree(h->miss_range);
@@ -895,6 +1174,12 @@ int octree_clear(oct_handle *h, void *stream)
     if (!rc) rc = wait_for(h, s, h->ev_upload);
     if (!rc) rc = wait_for_renders(h, s);
     if (rc) return rc;
+    if (h->pc) {
+        // every page back to the background: the frames are dropped once the batches using
+        // them have ended (the renders never read the master)
+        pg_wait(h, UINT64_MAX);
+        h->pc->reset([h](uint64_t q) { pg_wait(h, q); });
+    }
     HIPCHK(h, launch_clear(h->g, h->master, h->mask, h->p.background, s));
     HIPCHK(h, launch_fill_u8(h->flags, h->n_cells, 0, s));
     HIPCHK(h, launch_fill_f32(h->miss_range, h->n_cells * 8, h->background_f, s));
@@ -945,7 +1230,33 @@ int octree_insert_block(oct_handle *h, int32_t channel, const int32_t origin[3],
     {
         const double nvox = (double)size[0] * size[1] * size[2];
         hipEvent_t e0 = bt_begin(h, s);
-        HIPCHK(h, launch_insert(g, h->master, h->mask, src, channel, origin, size, s));
+        const int64_t sp[3] = {size[0], (int64_t)size[0] * size[1], (int64_t)size[0] * size[1] * size[2]};
+        if (h->pc) {
+            // disk tier: level-0 page rows of the block, a batch each (as many as fit)
+            const int lo[3] = {origin[0], origin[1], origin[2]};
+            const int hi[3] = {origin[0] + size[0] - 1, origin[1] + size[1] - 1, origin[2] + size[2] - 1};
+            rc = split_by_pages(
+                g, lo, hi, pg_budget(h),
+                [&](const int *a, const int *b) { return count_box_pages(g, 0, a, b); },
+                [&](const int *a, const int *b) -> int {
+                    std::vector<int64_t> pages;
+                    std::vector<uint8_t> wr;
+                    add_box_pages(g, 0, a, b, 1, pages, wr);
+                    return paged_batch(h, pages, wr, s, [&]() -> int {
+                        const int32_t o2[3] = {a[0], a[1], a[2]};
+                        const int32_t n2[3] = {b[0] - a[0] + 1, b[1] - a[1] + 1, b[2] - a[2] + 1};
+                        const int64_t off = (a[2] - origin[2]) * sp[1] + (a[1] - origin[1]) * sp[0] +
+                                            (a[0] - origin[0]);
+                        HIPCHK(h, launch_insert(g, h->master, h->mask,
+                                                (const uint8_t *)src + off * (int64_t)h->esz, sp,
+                                                channel, o2, n2, s));
+                        return OCT_OK;
+                    });
+                });
+            if (rc) return rc;
+        } else {
+            HIPCHK(h, launch_insert(g, h->master, h->mask, src, sp, channel, origin, size, s));
+        }
         // block read + level-0 write per channel, inserted-channel mask read and written
         bt_end(h, e0, s, 0, nvox * (2.0 * cb * (double)h->esz + 2.0));
     }
@@ -963,7 +1274,48 @@ int octree_insert_block(oct_handle *h, int32_t channel, const int32_t origin[3],
             p.lo[a] = b.lo[a] >> 1;
             p.hi[a] = b.hi[a] >> 1;
         }
-        HIPCHK(h, launch_downsample(g, h->master, L, p.lo, p.hi, s));
+        if (h->pc) {
+            // disk tier: parent page rows with their children's pages, a batch each.  The
+            // pages are taken for the x range widened to groups of four parents (the unit of
+            // the four-parent kernel; page edges are multiples of four, so a widened sub-box
+            // stays in its pages).
+            auto widen = [&](const int *a, const int *b, int wl[3], int wh[3], int cl[3], int ch[3]) {
+                for (int q = 0; q < 3; q++) {
+                    wl[q] = a[q];
+                    wh[q] = b[q];
+                }
+                wl[0] &= ~3;
+                wh[0] = std::min(wh[0] | 3, g.ext[L + 1][0] - 1);
+                for (int q = 0; q < 3; q++) {
+                    cl[q] = 2 * wl[q];
+                    ch[q] = 2 * wh[q] + 1;
+                }
+            };
+            const int lo[3] = {p.lo[0], p.lo[1], p.lo[2]}, hi[3] = {p.hi[0], p.hi[1], p.hi[2]};
+            int rc2 = split_by_pages(
+                g, lo, hi, pg_budget(h),
+                [&](const int *a, const int *b) {
+                    int wl[3], wh[3], cl[3], ch[3];
+                    widen(a, b, wl, wh, cl, ch);
+                    return count_box_pages(g, L + 1, wl, wh) + count_box_pages(g, L, cl, ch);
+                },
+                [&](const int *a, const int *b) -> int {
+                    int wl[3], wh[3], cl[3], ch[3];
+                    widen(a, b, wl, wh, cl, ch);
+                    std::vector<int64_t> pages;
+                    std::vector<uint8_t> wr;
+                    add_box_pages(g, L + 1, wl, wh, 1, pages, wr);
+                    add_box_pages(g, L, cl, ch, 0, pages, wr);
+                    return paged_batch(h, pages, wr, s, [&]() -> int {
+                        const int32_t sl[3] = {a[0], a[1], a[2]}, sh[3] = {b[0], b[1], b[2]};
+                        HIPCHK(h, launch_downsample(g, h->master, L, sl, sh, s));
+                        return OCT_OK;
+                    });
+                });
+            if (rc2) return rc2;
+        } else {
+            HIPCHK(h, launch_downsample(g, h->master, L, p.lo, p.hi, s));
+        }
         double parents = 1.0, children = 1.0;
         for (int a = 0; a < 3; a++) {
             parents *= (double)(p.hi[a] - p.lo[a] + 1);
@@ -1100,9 +1452,47 @@ int brick_pool_upload(oct_handle *h, uint64_t byte_budget, void *stream, oct_upl
         std::memcpy(h->up.host, stat_cells.data(), cl_bytes);
         HIPCHK(h, hipMemcpyAsync(h->up.dev, h->up.host, cl_bytes, hipMemcpyHostToDevice, s));
         hipEvent_t e0 = bt_begin(h, s);
-        HIPCHK(h, launch_stats(g, h->master, h->mask, (const int32_t *)h->up.dev, n_stat,
-                               (uint8_t *)h->up.dev + sc_off,
-                               (CellStat *)((uint8_t *)h->up.dev + st_off), s));
+        const int32_t *cells_dev = (const int32_t *)h->up.dev;
+        CellStat *stats_dev = (CellStat *)((uint8_t *)h->up.dev + st_off);
+        if (h->pc) {
+            // disk tier: runs of cells whose pages fit a batch (a cell lies in one page)
+            const int64_t budget = pg_budget(h);
+            for (int i0 = 0; i0 < n_stat;) {
+                std::vector<int64_t> pages;
+                std::vector<uint8_t> wr;
+                int i1 = i0;
+                for (; i1 < n_stat; i1++) {
+                    const int L = stat_cells[4 * i1];
+                    int lo[3], hi[3];
+                    for (int a = 0; a < 3; a++) {
+                        lo[a] = stat_cells[4 * i1 + 1 + a] * M;
+                        hi[a] = lo[a] + M - 1;
+                    }
+                    std::vector<int64_t> cp;
+                    std::vector<uint8_t> cw;
+                    add_box_pages(g, L, lo, hi, 0, cp, cw);
+                    bool fresh = false;
+                    for (int64_t q : cp) fresh |= std::find(pages.begin(), pages.end(), q) == pages.end();
+                    if (fresh && (int64_t)pages.size() + (int64_t)cp.size() > budget && i1 > i0) break;
+                    for (size_t k = 0; k < cp.size(); k++)
+                        if (std::find(pages.begin(), pages.end(), cp[k]) == pages.end()) {
+                            pages.push_back(cp[k]);
+                            wr.push_back(0);
+                        }
+                }
+                const int a0 = i0, n = i1 - i0;
+                rc = paged_batch(h, pages, wr, s, [&]() -> int {
+                    HIPCHK(h, launch_stats(g, h->master, h->mask, cells_dev + 4 * a0, n,
+                                           (uint8_t *)h->up.dev + sc_off, stats_dev + a0, s));
+                    return OCT_OK;
+                });
+                if (rc) return rc;
+                i0 = i1;
+            }
+        } else {
+            HIPCHK(h, launch_stats(g, h->master, h->mask, cells_dev, n_stat,
+                                   (uint8_t *)h->up.dev + sc_off, stats_dev, s));
+        }
         if (e0) {
             // every valid voxel of each changed cell, all channels (plus the mask at level 0)
             double bytes = 0.0;
@@ -1394,9 +1784,14 @@ int brick_pool_upload(oct_handle *h, uint64_t byte_budget, void *stream, oct_upl
         HIPCHK(h, launch_apply_deltas(next, h->miss_range, (const CellDelta *)h->up.dev,
                                       (int)deltas.size(), s));
         hipEvent_t e0 = bt_begin(h, s);
-        HIPCHK(h, launch_gather(g, h->master, next, h->pool, h->brick_bytes,
-                                (const BrickJob *)((uint8_t *)h->up.dev + j_off), (int)jobs.size(),
-                                h->slot_range, h->background_f, s));
+        const BrickJob *jobs_dev = (const BrickJob *)((uint8_t *)h->up.dev + j_off);
+        if (h->pc) {
+            int rc2 = gather_paged(h, jobs, 0, (int)jobs.size(), jobs_dev, next, s);
+            if (rc2) return rc2;
+        } else {
+            HIPCHK(h, launch_gather(g, h->master, next, h->pool, h->brick_bytes, jobs_dev,
+                                    (int)jobs.size(), h->slot_range, h->background_f, s));
+        }
         if (e0) {
             // per bordered voxel of each job's sub-box: the padded pool voxel written and the
             // source level's C values read
@@ -2130,9 +2525,16 @@ int octree_dump_canonical(oct_handle *h, void *buf, size_t cap, size_t *needed)
                         for (int a = 0; a < 3; a++) j.hi[a] = S - 1;
                         std::memcpy(h->up.host, &j, sizeof j);
                         HIPCHK(h, hipMemcpy(h->up.dev, h->up.host, sizeof j, hipMemcpyHostToDevice));
-                        HIPCHK(h, launch_gather(g, h->master, h->table, h->pool, h->brick_bytes,
-                                                (const BrickJob *)h->up.dev, 1, h->slot_range,
-                                                h->background_f, nullptr));
+                        if (h->pc) {
+                            const std::vector<BrickJob> one(1, j);
+                            int rc2 = gather_paged(h, one, 0, 1, (const BrickJob *)h->up.dev,
+                                                   h->table, nullptr);
+                            if (rc2) return rc2;
+                        } else {
+                            HIPCHK(h, launch_gather(g, h->master, h->table, h->pool, h->brick_bytes,
+                                                    (const BrickJob *)h->up.dev, 1, h->slot_range,
+                                                    h->background_f, nullptr));
+                        }
                         HIPCHK(h, hipDeviceSynchronize());
                     }
                     HIPCHK(h, hipMemcpy(slotbuf.data(), h->pool + (uint64_t)slot * h->brick_bytes,
@@ -2158,8 +2560,52 @@ int octree_read_level(oct_handle *h, int32_t level, void *out, size_t cap, int32
         for (int a = 0; a < 3; a++) ext[a] = g.ext[level][a];
     if (cap < bytes) return fail(h, OCT_ERANGE, "buffer too small");
     HIPCHK(h, hipDeviceSynchronize());
+    if (h->pc) {
+        // disk tier: the level assembled page by page (RAM frame, file or background)
+        const int P = 1 << g.plog, L = level;
+        const int64_t ex = g.ext[L][0], ey = g.ext[L][1], ez = g.ext[L][2];
+        std::vector<uint8_t> page(h->pc->page_bytes());
+        const int64_t npz = (ez + P - 1) / P;
+        for (int64_t pz = 0; pz < npz; pz++)
+            for (int64_t py = 0; py < g.pgrid[L][1]; py++)
+                for (int64_t px = 0; px < g.pgrid[L][0]; px++) {
+                    const int64_t id = g.page_off[L] + (pz * g.pgrid[L][1] + py) * g.pgrid[L][0] + px;
+                    std::string err;
+                    if (!h->pc->read_page(id, page.data(), [h](uint64_t q) { pg_wait(h, q); }, err))
+                        return fail(h, OCT_EDEVICE, err);
+                    const int64_t nx = std::min<int64_t>(P, ex - px * P);
+                    for (int c = 0; c < g.C; c++)
+                        for (int64_t z = pz * P; z < std::min<int64_t>(ez, pz * P + P); z++)
+                            for (int64_t y = py * P; y < std::min<int64_t>(ey, py * P + P); y++) {
+                                const uint8_t *src = page.data() +
+                                    ((((int64_t)c * P + (z - pz * P)) * P + (y - py * P)) * P) * (int64_t)h->esz;
+                                uint8_t *dst = (uint8_t *)out +
+                                    ((((int64_t)c * ez + z) * ey + y) * ex + px * P) * (int64_t)h->esz;
+                                std::memcpy(dst, src, (size_t)nx * h->esz);
+                            }
+                }
+        return OCT_OK;
+    }
     HIPCHK(h, hipMemcpy(out, (uint8_t *)h->master + (size_t)g.lvl_off[level] * h->esz, bytes,
                         hipMemcpyDeviceToHost));
+    return OCT_OK;
+}
+
+int octree_disk_stats(oct_handle *h, oct_disk_stats *out)
+{
+    if (!h || !out) return OCT_EINVAL;
+    if (!h->pc) return fail(h, OCT_EINVAL, "the octree has no disk tier");
+    const PageCache::Stats &st = h->pc->stats;
+    out->pages = (uint64_t)h->pc->n_pages();
+    out->frames = (uint64_t)h->pc->n_frames();
+    out->hits = st.hits;
+    out->loads = st.loads;
+    out->fills = st.fills;
+    out->writebacks = st.writebacks;
+    out->evictions = st.evictions;
+    out->waits = st.waits;
+    out->bytes_read = st.bytes_read;
+    out->bytes_written = st.bytes_written;
     return OCT_OK;
 }
 

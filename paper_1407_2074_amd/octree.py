@@ -25,14 +25,17 @@ EXPORTS = ["octree_create", "octree_destroy", "octree_clear", "octree_insert_blo
            "octree_insert_slices", "brick_pool_upload", "render_views", "render_views_noalloc",
            "render_ckpt_bytes", "render_refine_bytes",
            "render_views_backward", "octree_dump_canonical", "octree_read_level", "octree_info",
-           "octree_render_timing", "octree_build_timing", "oct_last_error"]
+           "octree_render_timing", "octree_build_timing", "octree_disk_stats", "oct_last_error"]
+OCT_MASTER_HBM, OCT_MASTER_HOST, OCT_MASTER_DISK = 0, 1, 2
 
 
 class CreateParams(ct.Structure):
     _fields_ = [("dims", ct.c_int32 * 3), ("channels", ct.c_int32), ("brick_size", ct.c_int32),
                 ("dtype", ct.c_int32), ("background", ct.c_double),
                 ("homog_threshold", ct.c_double), ("device_pool_bytes", ct.c_uint64),
-                ("master_on_host", ct.c_int32), ("reserved", ct.c_int32 * 3)]
+                ("master_on_host", ct.c_int32), ("page_cells", ct.c_int32),
+                ("reserved", ct.c_int32 * 2), ("host_cache_bytes", ct.c_uint64),
+                ("disk_path", ct.c_char_p)]
 
 
 class OctView(ct.Structure):
@@ -53,6 +56,11 @@ class UploadStats(ct.Structure):
                 ("bricks_total", ct.c_uint64), ("nodes_changed", ct.c_uint64),
                 ("bytes_written", ct.c_uint64), ("requests_seen", ct.c_uint64),
                 ("evictions", ct.c_uint64)]
+
+
+class DiskStats(ct.Structure):
+    _fields_ = [(k, ct.c_uint64) for k in ("pages", "frames", "hits", "loads", "fills", "writebacks",
+                                           "evictions", "waits", "bytes_read", "bytes_written")]
 
 
 class RenderStats(ct.Structure):
@@ -90,6 +98,7 @@ def _load():
     L.octree_info.argtypes = [vp, ct.POINTER(i32), ct.POINTER(u64), ct.POINTER(u64)]
     L.octree_render_timing.argtypes = [vp, i32, ct.POINTER(ct.c_double), ct.POINTER(u64)]
     L.octree_build_timing.argtypes = [vp, i32, ct.POINTER(ct.c_double), ct.POINTER(ct.c_double)]
+    L.octree_disk_stats.argtypes = [vp, ct.POINTER(DiskStats)]
     L.oct_last_error.restype = ct.c_char_p
     L.oct_last_error.argtypes = [vp]
     return L
@@ -194,7 +203,10 @@ class Octree:
 
     def __init__(self, dims, channels: int, brick: int, dtype: str = "u16",
                  background: float = 0.0, threshold: float = 0.0, pool_bytes: int = 0,
-                 master_on_host: bool = False, stream=None):
+                 master_on_host: bool = False, stream=None, disk_path: str | None = None,
+                 host_cache_bytes: int = 0, page_cells: int = 0):
+        """disk_path: keep the mipmap in pages in this file with host_cache_bytes of RAM
+        frames (the disk tier); master_on_host: in pinned host memory; else in HBM."""
         p = CreateParams()
         for a in range(3):
             p.dims[a] = int(dims[a])
@@ -202,7 +214,13 @@ class Octree:
         p.dtype = OCT_U16 if dtype == "u16" else OCT_F32
         p.background, p.homog_threshold = float(background), float(threshold)
         p.device_pool_bytes = int(pool_bytes)
-        p.master_on_host = 1 if master_on_host else 0
+        if disk_path is not None:
+            p.master_on_host = OCT_MASTER_DISK
+            p.disk_path = os.fsencode(disk_path)
+            p.host_cache_bytes = int(host_cache_bytes)
+            p.page_cells = int(page_cells)
+        else:
+            p.master_on_host = OCT_MASTER_HOST if master_on_host else OCT_MASTER_HBM
         h = ct.c_void_p()
         rc = lib.octree_create(ct.byref(p), _stream(stream), ct.byref(h))
         if rc != OCT_OK:
@@ -361,6 +379,13 @@ class Octree:
         ms, by = (ct.c_double * 4)(), (ct.c_double * 4)()
         self._check(lib.octree_build_timing(self.h, 1 if enable else 0, ms, by))
         return list(ms), list(by)
+
+    def disk_stats(self) -> dict:
+        """Disk-tier counters: pages, frames, hits, loads, fills, writebacks, evictions, waits,
+        bytes_read, bytes_written."""
+        st = DiskStats()
+        self._check(lib.octree_disk_stats(self.h, ct.byref(st)))
+        return {k: getattr(st, k) for k, _ in DiskStats._fields_}
 
     def dump(self) -> bytes:
         need = ct.c_size_t()

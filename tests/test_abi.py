@@ -38,7 +38,8 @@ def test_struct_layouts_match_header(native, tmp_path):
     """sizeof and the offset of every field, C compiler vs the ctypes mirrors."""
     import ctypes as ct
     structs = {"oct_create_params": native.CreateParams, "oct_view": native.OctView,
-               "oct_upload_stats": native.UploadStats, "oct_render_stats": native.RenderStats}
+               "oct_upload_stats": native.UploadStats, "oct_render_stats": native.RenderStats,
+               "oct_disk_stats": native.DiskStats}
     lines = []
     for cname, py in structs.items():
         lines.append(f'printf("%zu\\n", sizeof({cname}));')
@@ -61,8 +62,12 @@ def test_struct_layouts_match_header(native, tmp_path):
 def test_invalid_create_params_fail_without_gpu_work(native):
     """Argument validation happens before any device call."""
     import ctypes as ct
+    disk = native.OCT_MASTER_DISK
     for bad in [dict(brick=5), dict(brick=0), dict(channels=5), dict(channels=0),
-                dict(dims=(0, 4, 4)), dict(dtype=7), dict(background=1.5), dict(reserved=1)]:
+                dict(dims=(0, 4, 4)), dict(dtype=7), dict(background=1.5), dict(reserved=1),
+                dict(master=3), dict(master=disk), dict(master=disk, path=b"/tmp/x", brick=6),
+                dict(master=disk, path=b"/tmp/x", page_cells=3), dict(page_cells=2),
+                dict(cache=1 << 20), dict(path=b"/tmp/x")]:
         p = native.CreateParams()
         dims = bad.get("dims", (16, 16, 16))
         for a in range(3):
@@ -71,7 +76,11 @@ def test_invalid_create_params_fail_without_gpu_work(native):
         p.brick_size = bad.get("brick", 8)
         p.dtype = bad.get("dtype", 0)
         p.background = bad.get("background", 0.0)
-        p.reserved[2] = bad.get("reserved", 0)
+        p.reserved[1] = bad.get("reserved", 0)
+        p.master_on_host = bad.get("master", 0)
+        p.page_cells = bad.get("page_cells", 0)
+        p.host_cache_bytes = bad.get("cache", 0)
+        p.disk_path = bad.get("path", None)
         h = ct.c_void_p()
         assert native.lib.octree_create(ct.byref(p), None, ct.byref(h)) == native.OCT_EINVAL
         assert native.lib.oct_last_error(None)
