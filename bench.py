@@ -382,7 +382,8 @@ def _fs_type(path: str) -> str:
 def measure_disk(slabs, cfg, args, want, composited, hbm_ms_per_step) -> dict:
     """Disk tier: the streamed build + render step of the headline configuration with the
     mipmap kept in pages in a file (pages of 2x2x2 cells = 64^3 voxels, all channels) and RAM
-    frames for a third of the pages; one warm-up step, then one timed step.  Reports the
+    frames for half of the pages (about what one batch's insertion, half-sampling, statistics
+    and border gathers touch); one warm-up step, then one timed step.  Reports the
     step's rate, the page traffic of the timed step, and the final image against the in-HBM
     run's (the octree is the same, so the image must be equal)."""
     import shutil
@@ -403,7 +404,7 @@ def measure_disk(slabs, cfg, args, want, composited, hbm_ms_per_step) -> dict:
         ext = [-(-d // (1 << L)) for d in dims]
         n_pages += int(np.prod([-(-e // P) for e in ext]))
     page_bytes = P ** 3 * C * 2
-    frames = max(16, n_pages // 3)
+    frames = max(16, n_pages // 2)
     tmp = tempfile.mkdtemp(prefix="octree_pages_")
     path = os.path.join(tmp, "pages.bin")
     try:
@@ -413,23 +414,36 @@ def measure_disk(slabs, cfg, args, want, composited, hbm_ms_per_step) -> dict:
                                width=cfg["width"], height=cfg["height"], lod=cfg["lod"])
         img = torch.zeros((view.height, view.width, 4), dtype=torch.float32, device="cuda")
 
-        def step():
-            t.clear()
+        def step(tree):
+            tree.clear()
             for b, slab in enumerate(slabs):
-                t.insert_slices(-1, b * cfg["batch"], slab)
-                t.upload()
-                t.render([view], images=[img])
+                tree.insert_slices(-1, b * cfg["batch"], slab)
+                tree.upload()
+                tree.render([view], images=[img])
 
-        step()
+        def timed(tree):
+            step(tree)   # warm-up
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            step(tree)
+            torch.cuda.synchronize()
+            return time.perf_counter() - t0
+
+        step(t)
         torch.cuda.synchronize()
         s0 = t.disk_stats()
         t0 = time.perf_counter()
-        step()
+        step(t)
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
         s1 = t.disk_stats()
         err = float((img - want).abs().max().item())
         t.close()
+        # the same step with the whole mipmap in pinned host memory: what the kernels' traffic
+        # over the host link costs without the page file
+        th = Octree(dims, C, M, "u16", background=0, threshold=cfg["thr"], master_on_host=True)
+        el_host = timed(th)
+        th.close()
     finally:
         shutil.rmtree(tmp, ignore_errors=True)
     d = {k: s1[k] - s0[k] for k in ("hits", "loads", "fills", "writebacks", "evictions", "waits",
@@ -438,10 +452,11 @@ def measure_disk(slabs, cfg, args, want, composited, hbm_ms_per_step) -> dict:
         "config": (f"streamed build+render {dims[0]}x{dims[1]}x{dims[2]}x{C} u16, {M}^3 bricks, "
                    f"{len(slabs)} batches of {cfg['batch']} slices, one {cfg['width']}x"
                    f"{cfg['height']} view per batch; mipmap in {n_pages} pages of {P}^3 voxels "
-                   f"({page_bytes >> 20} MiB) in a file on {_fs_type(tmp)}, {frames} RAM frames"),
+                   f"({page_bytes / 2**20:.1f} MiB) in a file on {_fs_type(tmp)}, {frames} RAM frames"),
         "ms_per_step": round(el * 1e3, 2),
         "gsamples_per_s": round(composited / el / 1e9, 3),
         "hbm_master_ms_per_step": round(hbm_ms_per_step, 2),
+        "host_master_ms_per_step": round(el_host * 1e3, 2),
         "page_traffic": d,
         "file_read_gb_per_s": round(d["bytes_read"] / el / 1e9, 3),
         "file_write_gb_per_s": round(d["bytes_written"] / el / 1e9, 3),

@@ -859,15 +859,42 @@ int gather_paged(oct_handle *h, const std::vector<BrickJob> &jobs, int j0, int j
         int i1 = i0;
         for (; i1 < j1; i1++) {
             const BrickJob &jb = jobs[(size_t)i1];
+            const int L = jb.level, G = g.grid[L];
             const int b[3] = {jb.bx, jb.by, jb.bz};
-            int lo[3], hi[3];
+            // the kernel reads the mipmap only inside neighbours drawn from it (not AVG cells):
+            // per axis, the clamped source indices of the job's sub-box split by neighbour
+            // (o = 0: below the cell, 1: inside, 2: above)
+            int rlo[3][3], rhi[3][3];
             for (int a = 0; a < 3; a++) {
-                lo[a] = b[a] * M - 1 + jb.lo[a];
-                hi[a] = b[a] * M - 1 + jb.hi[a];
+                const int e = g.ext[L][a];
+                const int glo = std::min(std::max(b[a] * M - 1 + jb.lo[a], 0), e - 1);
+                const int ghi = std::min(std::max(b[a] * M - 1 + jb.hi[a], 0), e - 1);
+                rlo[a][0] = glo;
+                rhi[a][0] = std::min(ghi, b[a] * M - 1);
+                rlo[a][1] = std::max(glo, b[a] * M);
+                rhi[a][1] = std::min(ghi, b[a] * M + M - 1);
+                rlo[a][2] = std::max(glo, b[a] * M + M);
+                rhi[a][2] = ghi;
             }
             std::vector<int64_t> cp;
             std::vector<uint8_t> cw;
-            add_box_pages(g, jb.level, lo, hi, 0, cp, cw);
+            for (int oz = 0; oz < 3; oz++)
+                for (int oy = 0; oy < 3; oy++)
+                    for (int ox = 0; ox < 3; ox++) {
+                        const int o[3] = {ox, oy, oz};
+                        int lo[3], hi[3], nb[3];
+                        bool ok = true;
+                        for (int a = 0; a < 3; a++) {
+                            lo[a] = rlo[a][o[a]];
+                            hi[a] = rhi[a][o[a]];
+                            nb[a] = b[a] + o[a] - 1;
+                            ok = ok && lo[a] <= hi[a] && nb[a] >= 0 && nb[a] < G;
+                        }
+                        if (ok && h->cells[(size_t)cell_index(g, L, nb[0], nb[1], nb[2])].dev_kind != kAvg)
+                            add_box_pages(g, L, lo, hi, 0, cp, cw);
+                    }
+            std::sort(cp.begin(), cp.end());
+            cp.erase(std::unique(cp.begin(), cp.end()), cp.end());
             int fresh = 0;
             for (int64_t q : cp) fresh += std::find(pages.begin(), pages.end(), q) == pages.end();
             if (i1 > i0 && (int64_t)pages.size() + fresh > budget) break;
