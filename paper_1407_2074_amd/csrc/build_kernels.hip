@@ -456,14 +456,15 @@ constexpr int kGatherThreads = OCTRC_GATHER_THREADS;
 template <typename T, bool kPaged>
 __global__ void __launch_bounds__(kGatherThreads)
 k_gather(VolGeom g, MasterRef<const T> mr, const DevCell *table, uint8_t *pool, uint64_t brick_bytes,
-         const BrickJob *jobs, int n_jobs, float *slot_range, float background)
+         const BrickJob *jobs, int n_items, int zsplit, float *part, float background)
 {
     __shared__ int s_kind[27];
     __shared__ float s_avg[27][4];
     __shared__ float sf[kGatherThreads / 64];
     const int per = (int)(gridDim.x / kXcds);
-    const int jid = (int)(blockIdx.x % kXcds) * per + (int)(blockIdx.x / kXcds);
-    if (jid >= n_jobs) return;
+    const int item = (int)(blockIdx.x % kXcds) * per + (int)(blockIdx.x / kXcds);
+    if (item >= n_items) return;
+    const int jid = item / zsplit, zc = item % zsplit;
     const BrickJob job = jobs[jid];
     const int L = job.level, M = g.M, S = M + 2, G = g.grid[L];
     const int b[3] = {job.bx, job.by, job.bz};
@@ -490,6 +491,9 @@ k_gather(VolGeom g, MasterRef<const T> mr, const DevCell *table, uint8_t *pool, 
     }
     T *dst = (T *)(pool + (uint64_t)job.slot * brick_bytes);
     const int nx = job.hi[0] - job.lo[0] + 1, ny = job.hi[1] - job.lo[1] + 1;
+    // this workgroup's share of the job's slices
+    const int zper = (job.hi[2] - job.lo[2] + zsplit) / zsplit;
+    const int z_lo = job.lo[2] + zc * zper, z_hi = min(z_lo + zper - 1, job.hi[2]);
     for (int j = threadIdx.x; j < nx * ny; j += kGatherThreads) {
         const int x = job.lo[0] + j % nx, y = job.lo[1] + j / nx;
         // bordered position -> clamped level index, and which of the 3x3x3 neighbours holds it
@@ -499,7 +503,7 @@ k_gather(VolGeom g, MasterRef<const T> mr, const DevCell *table, uint8_t *pool, 
         const int oy = gy < b[1] * M ? 0 : (gy >= b[1] * M + M ? 2 : 1);
         const T *col = kPaged ? nullptr : melem<false>(g, mr, L, 0, gx, gy, 0);   // dense: column base
 #pragma unroll 4
-        for (int z = job.lo[2]; z <= job.hi[2]; z++) {
+        for (int z = z_lo; z <= z_hi; z++) {
             const int gz = min(max(b[2] * M - 1 + z, 0), ez - 1);
             const int oz = gz < b[2] * M ? 0 : (gz >= b[2] * M + M ? 2 : 1);
             const int nb = (oz * 3 + oy) * 3 + ox;
@@ -531,10 +535,31 @@ k_gather(VolGeom g, MasterRef<const T> mr, const DevCell *table, uint8_t *pool, 
         const float lo = block_reduce<float, MinF, kGatherThreads / 64>(mn[c], MinF{}, sf);
         const float hi = block_reduce<float, MaxF, kGatherThreads / 64>(mx[c], MaxF{}, sf);
         if (threadIdx.x == 0) {
-            float *r = slot_range + (int64_t)job.slot * 8;
-            r[c] = job.full ? lo : fminf(r[c], lo);
-            r[4 + c] = job.full ? hi : fmaxf(r[4 + c], hi);
+            part[(int64_t)item * 8 + c] = lo;
+            part[(int64_t)item * 8 + 4 + c] = hi;
         }
+    }
+}
+
+// The value range of what each job wrote, folded over its workgroups: the slot's skip range
+// is replaced by a whole-brick job and widened by a partial one (a superset stays a valid
+// bound).
+__global__ void __launch_bounds__(kThreads)
+k_gather_fold(const BrickJob *jobs, int n_jobs, int zsplit, int C, const float *part,
+              float *slot_range)
+{
+    const int j = blockIdx.x * kThreads + threadIdx.x;
+    if (j >= n_jobs) return;
+    const BrickJob &job = jobs[j];
+    float *r = slot_range + (int64_t)job.slot * 8;
+    for (int c = 0; c < C; c++) {
+        float lo = FLT_MAX, hi = -FLT_MAX;
+        for (int k = 0; k < zsplit; k++) {
+            lo = fminf(lo, part[((int64_t)j * zsplit + k) * 8 + c]);
+            hi = fmaxf(hi, part[((int64_t)j * zsplit + k) * 8 + 4 + c]);
+        }
+        r[c] = job.full ? lo : fminf(r[c], lo);
+        r[4 + c] = job.full ? hi : fmaxf(r[4 + c], hi);
     }
 }
 
@@ -731,20 +756,35 @@ hipError_t launch_apply_deltas(DevCell *table, float *miss_range, const CellDelt
     return hipGetLastError();
 }
 
+// Workgroups per job: a job's slices are split so that a whole-volume upload runs several
+// rounds of workgroups (one workgroup per 34^3 job left the last round mostly empty).
+static int gather_zsplit(const VolGeom &g) { return std::min(4, std::max(1, (g.M + 2) / 8)); }
+
+size_t gather_scratch_bytes(const VolGeom &g, int n)
+{
+    return (size_t)n * (size_t)gather_zsplit(g) * 8 * sizeof(float);
+}
+
 hipError_t launch_gather(const VolGeom &g, const void *master, const DevCell *table, void *pool,
                          uint64_t brick_bytes, const BrickJob *jobs, int n, float *slot_range,
-                         float background, hipStream_t s)
+                         float background, void *scratch, hipStream_t s)
 {
     if (n == 0) return hipSuccess;
-    const dim3 grid((unsigned)(ceil_div(n, kXcds) * kXcds));
+    const int zsplit = gather_zsplit(g), items = n * zsplit;
+    const dim3 grid((unsigned)(ceil_div(items, kXcds) * kXcds));
     by_type(g, [&](auto tv, auto paged) {
         using T = decltype(tv);
         constexpr bool kP = decltype(paged)::value;
         const MasterRef<T> m0 = master_ref<T>(g, (void *)master);
         const MasterRef<const T> mr{m0.base, m0.pages};
         hipLaunchKernelGGL((k_gather<T, kP>), grid, dim3(kGatherThreads), 0, s, g, mr, table,
-                           (uint8_t *)pool, brick_bytes, jobs, n, slot_range, background);
+                           (uint8_t *)pool, brick_bytes, jobs, items, zsplit, (float *)scratch,
+                           background);
     });
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_gather_fold, dim3(ceil_div(n, kThreads)), dim3(kThreads), 0, s, jobs, n,
+                       zsplit, g.C, (const float *)scratch, slot_range);
     return hipGetLastError();
 }
 

@@ -212,9 +212,11 @@ hipError_t launch_stats(const VolGeom &g, const void *master, const uint8_t *mas
                         void *scratch /* stats_scratch_bytes */, CellStat *out, hipStream_t s);
 hipError_t launch_apply_deltas(DevCell *table, float *miss_range, const CellDelta *d, int n,
                                hipStream_t s);
+// scratch: gather_scratch_bytes(g, n) bytes of device memory (per-workgroup value ranges)
+size_t gather_scratch_bytes(const VolGeom &g, int n);
 hipError_t launch_gather(const VolGeom &g, const void *master, const DevCell *table,
                          void *pool, uint64_t brick_bytes, const BrickJob *jobs, int n,
-                         float *slot_range, float background, hipStream_t s);
+                         float *slot_range, float background, void *scratch, hipStream_t s);
 hipError_t launch_ranges(const VolGeom &g, DevCell *table, const float *slot_range,
                          const float *miss_range, hipStream_t s);
 hipError_t launch_clear(const VolGeom &g, void *master, uint8_t *mask, double background,

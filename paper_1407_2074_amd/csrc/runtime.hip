@@ -848,7 +848,7 @@ int paged_batch(oct_handle *h, std::vector<int64_t> &pages, std::vector<uint8_t>
 // Bordered-brick gathers of jobs[j0 .. j1) (jobs_dev: the same jobs on the device) in runs
 // whose source pages fit a batch.
 int gather_paged(oct_handle *h, const std::vector<BrickJob> &jobs, int j0, int j1,
-                 const BrickJob *jobs_dev, const DevCell *table, hipStream_t s)
+                 const BrickJob *jobs_dev, const DevCell *table, void *scratch, hipStream_t s)
 {
     const VolGeom &g = h->g;
     const int M = g.M;
@@ -907,7 +907,7 @@ int gather_paged(oct_handle *h, const std::vector<BrickJob> &jobs, int j0, int j
         const int a0 = i0, n = i1 - i0;
         const int rc = paged_batch(h, pages, wr, s, [&]() -> int {
             HIPCHK(h, launch_gather(g, h->master, table, h->pool, h->brick_bytes, jobs_dev + a0, n,
-                                    h->slot_range, h->background_f, s));
+                                    h->slot_range, h->background_f, scratch, s));
             return OCT_OK;
         });
         if (rc) return rc;
@@ -1795,8 +1795,9 @@ int brick_pool_upload(oct_handle *h, uint64_t byte_budget, void *stream, oct_upl
     const size_t d_bytes = deltas.size() * sizeof(CellDelta);
     const size_t j_off = (d_bytes + 255) & ~(size_t)255;
     const size_t j_bytes = jobs.size() * sizeof(BrickJob);
+    const size_t gs_off = (j_off + j_bytes + 255) & ~(size_t)255;   // gather scratch
     if (d_bytes + j_bytes) {
-        int rc = stage_reserve(h, h->up, j_off + j_bytes);
+        int rc = stage_reserve(h, h->up, gs_off + gather_scratch_bytes(g, (int)jobs.size()));
         // renders read the node table and the pool: those of the other table's version (and
         // older) end first, all of them when a brick they may read is rewritten in place
         if (!rc) rc = (h->capped || in_place) ? wait_for_renders(h, s) : wait_for_renders_before(h, s, V);
@@ -1813,11 +1814,13 @@ int brick_pool_upload(oct_handle *h, uint64_t byte_budget, void *stream, oct_upl
         hipEvent_t e0 = bt_begin(h, s);
         const BrickJob *jobs_dev = (const BrickJob *)((uint8_t *)h->up.dev + j_off);
         if (h->pc) {
-            int rc2 = gather_paged(h, jobs, 0, (int)jobs.size(), jobs_dev, next, s);
+            int rc2 = gather_paged(h, jobs, 0, (int)jobs.size(), jobs_dev, next,
+                                   (uint8_t *)h->up.dev + gs_off, s);
             if (rc2) return rc2;
         } else {
             HIPCHK(h, launch_gather(g, h->master, next, h->pool, h->brick_bytes, jobs_dev,
-                                    (int)jobs.size(), h->slot_range, h->background_f, s));
+                                    (int)jobs.size(), h->slot_range, h->background_f,
+                                    (uint8_t *)h->up.dev + gs_off, s));
         }
         if (e0) {
             // per bordered voxel of each job's sub-box: the padded pool voxel written and the
@@ -2540,8 +2543,9 @@ int octree_dump_canonical(oct_handle *h, void *buf, size_t cap, size_t *needed)
                     if (!resident) {
                         // gather the bordered brick into the spare slot past the pool
                         slot = h->n_slots + h->n_cow;
-                        int rc = stage_reserve(h, h->up, sizeof(BrickJob));
+                        int rc = stage_reserve(h, h->up, 256 + gather_scratch_bytes(g, 1));
                         if (rc) return rc;
+                        void *gscratch = (uint8_t *)h->up.dev + 256;
                         BrickJob j{};
                         j.slot = (int32_t)slot;
                         j.level = L;
@@ -2555,12 +2559,12 @@ int octree_dump_canonical(oct_handle *h, void *buf, size_t cap, size_t *needed)
                         if (h->pc) {
                             const std::vector<BrickJob> one(1, j);
                             int rc2 = gather_paged(h, one, 0, 1, (const BrickJob *)h->up.dev,
-                                                   h->table, nullptr);
+                                                   h->table, gscratch, nullptr);
                             if (rc2) return rc2;
                         } else {
                             HIPCHK(h, launch_gather(g, h->master, h->table, h->pool, h->brick_bytes,
                                                     (const BrickJob *)h->up.dev, 1, h->slot_range,
-                                                    h->background_f, nullptr));
+                                                    h->background_f, gscratch, nullptr));
                         }
                         HIPCHK(h, hipDeviceSynchronize());
                     }
