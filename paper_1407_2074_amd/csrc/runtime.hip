@@ -192,6 +192,14 @@ struct oct_handle {
     float *miss_range = nullptr;
     uint64_t frame = 1;
     std::vector<uint64_t> last_used;
+    // paging-only uploads (capped pool, no data changed since the last full upload, nothing
+    // pending): which cells are brick nodes and which cell holds each slot, so that such an
+    // upload touches the render flags, the resident slots and the cells it changes, not every
+    // cell's host record
+    bool paging_ready = false;
+    std::vector<uint8_t> data_cell;
+    std::vector<int64_t> slot_cell;
+    uint64_t n_data = 0, n_resident = 0;
     std::vector<HCell> cells;
     std::vector<int32_t> free_slots;
     std::vector<std::vector<Box>> dirty;  // per level
@@ -581,6 +589,7 @@ void reset_host_state(oct_handle *h)
 {
     const VolGeom &g = h->g;
     const int C = g.C;
+    h->paging_ready = false;
     for (auto &c : h->cells) c = HCell();
     for (int L = 0; L <= g.N; L++) {
         const int G = g.grid[L];
@@ -1367,6 +1376,216 @@ int octree_insert_slices(oct_handle *h, int32_t channel, int32_t z0, int32_t nz,
     return octree_insert_block(h, channel, o, n, data, data_is_device, stream);
 }
 
+// Upload of a capped pool when no data changed since the last full upload and nothing is
+// pending: only residency changes.  Requested brick nodes get slots (coarser levels first; free
+// slots, then slots the last renders did not use, least recently used first, then a used finer
+// brick's slot for a coarser request), exactly as a full upload decides, but touching only the
+// render flags, the resident slots and the cells that change.
+static int upload_paging_only(oct_handle *h, uint64_t byte_budget, hipStream_t s,
+                              std::vector<CellDelta> &deltas, std::vector<BrickJob> &jobs,
+                              uint64_t &requests_seen, uint64_t &evictions, uint64_t &unserved)
+{
+    const VolGeom &g = h->g;
+    const int C = g.C;
+    HIPCHK(h, hipMemcpyAsync(h->flags_host, h->flags, (size_t)h->n_cells, hipMemcpyDeviceToHost, s));
+    HIPCHK(h, launch_fill_u8(h->flags, h->n_cells, 0, s));
+    HIPCHK(h, hipStreamSynchronize(s));
+    const uint8_t *fl = h->flags_host;
+    auto level_of = [&](int64_t ci) {
+        int L = 0;
+        while (L < g.N && ci >= g.cell_off[L + 1]) L++;
+        return L;
+    };
+    for (int64_t i = 0; i < h->n_cells; i++)
+        if (fl[i] == 1) h->last_used[(size_t)i] = h->frame;
+    // requests in the full upload's scan order: levels from the root down, cells in index order
+    std::vector<int64_t> reqs, idle, busy;
+    for (int L = g.N; L >= 0; L--) {
+        const int64_t n = (int64_t)g.grid[L] * g.grid[L] * g.grid[L];
+        for (int64_t ci = g.cell_off[L]; ci < g.cell_off[L] + n; ci++)
+            if (fl[ci] == 2 && h->data_cell[(size_t)ci] && h->cells[(size_t)ci].slot < 0) reqs.push_back(ci);
+    }
+    for (int64_t ci : h->slot_cell)
+        if (ci >= 0) (h->last_used[(size_t)ci] == h->frame ? busy : idle).push_back(ci);
+    requests_seen = reqs.size();
+    // the full upload's orders made total: (last use, level, scan position) and (level, scan
+    // position); inside a level the scan position is the cell index
+    std::sort(idle.begin(), idle.end(), [&](int64_t a, int64_t b) {
+        if (h->last_used[(size_t)a] != h->last_used[(size_t)b]) return h->last_used[(size_t)a] < h->last_used[(size_t)b];
+        const int la = level_of(a), lb = level_of(b);
+        return la != lb ? la < lb : a < b;
+    });
+    std::sort(busy.begin(), busy.end(), [&](int64_t a, int64_t b) {
+        const int la = level_of(a), lb = level_of(b);
+        return la != lb ? la < lb : a < b;
+    });
+    uint64_t budget_left = byte_budget ? byte_budget : UINT64_MAX;
+    std::vector<int64_t> changed;
+    size_t vi = 0, bi = 0;
+    for (int64_t ci : reqs) {
+        if (budget_left < h->brick_bytes) {
+            unserved++;
+            continue;
+        }
+        HCell &c = h->cells[(size_t)ci];
+        const int L = level_of(ci);
+        if (h->free_slots.empty()) {
+            int64_t victim;
+            if (vi < idle.size()) victim = idle[vi++];
+            else if (bi < busy.size() && level_of(busy[bi]) < L) victim = busy[bi++];
+            else {
+                unserved++;
+                continue;
+            }
+            HCell &v = h->cells[(size_t)victim];
+            h->free_slots.push_back(v.slot);
+            h->slot_cell[(size_t)v.slot] = -1;
+            v.slot = -1;
+            v.needs_gather = false;
+            changed.push_back(victim);
+            evictions++;
+            h->n_resident--;
+        }
+        c.slot = h->free_slots.back();
+        h->free_slots.pop_back();
+        h->slot_cell[(size_t)c.slot] = ci;
+        const int G = g.grid[L];
+        const int64_t li = ci - g.cell_off[L];
+        BrickJob j{};
+        j.slot = c.slot;
+        j.level = L;
+        j.bx = (int)(li % G);
+        j.by = (int)((li / G) % G);
+        j.bz = (int)(li / ((int64_t)G * G));
+        j.full = 1;
+        for (int a = 0; a < 3; a++) j.hi[a] = g.M + 1;
+        jobs.push_back(j);
+        budget_left -= h->brick_bytes;
+        c.needs_gather = false;
+        changed.push_back(ci);
+        h->n_resident++;
+    }
+    h->frame++;
+    // change events of the cells that changed residency: a resident brick is drawn from its
+    // slot (skip range = its AVG here, the brick's range comes from the gather); a missing one
+    // from its AVG with the value bound of the brick and its 26 neighbours
+    for (int64_t ci : changed) {
+        HCell &c = h->cells[(size_t)ci];
+        const bool res = c.slot >= 0;
+        float m[8];
+        for (int k = 0; k < 4; k++) m[k] = m[4 + k] = c.dev_avg[k];
+        if (!res) {
+            const int L = level_of(ci), G = g.grid[L];
+            const int64_t li = ci - g.cell_off[L];
+            const int x = (int)(li % G), y = (int)((li / G) % G), z = (int)(li / ((int64_t)G * G));
+            for (int dz = -1; dz <= 1; dz++)
+                for (int dy = -1; dy <= 1; dy++)
+                    for (int dx = -1; dx <= 1; dx++) {
+                        const int nx = x + dx, ny = y + dy, nz = z + dz;
+                        if (nx < 0 || ny < 0 || nz < 0 || nx >= G || ny >= G || nz >= G) continue;
+                        const int64_t ni = cell_index(g, L, nx, ny, nz);
+                        const HCell &nc = h->cells[(size_t)ni];
+                        if (!nc.inside) continue;
+                        const bool data = h->data_cell[(size_t)ni] != 0;
+                        for (int k = 0; k < C; k++) {
+                            const float lo = data ? (float)nc.bmin[k] : nc.dev_avg[k];
+                            const float hi = data ? (float)nc.bmax[k] : nc.dev_avg[k];
+                            m[k] = std::min(m[k], lo);
+                            m[4 + k] = std::max(m[4 + k], hi);
+                        }
+                    }
+        }
+        const int32_t kind = res ? kBrick : kBrickMissing, slot = res ? c.slot : -1;
+        bool diff = !c.dev_valid || c.dev_kind != kind || c.dev_slot != slot;
+        for (int k = 0; k < 8 && !diff; k++) diff = c.dev_miss[k] != m[k];
+        if (!diff) continue;
+        CellDelta d{};
+        d.index = (int32_t)ci;
+        d.kind = kind;
+        d.slot = slot;
+        for (int k = 0; k < 4; k++) {
+            d.avg[k] = c.dev_avg[k];
+            d.lo[k] = m[k];
+            d.hi[k] = m[4 + k];
+        }
+        deltas.push_back(d);
+        c.dev_kind = kind;
+        c.dev_slot = slot;
+        for (int k = 0; k < 8; k++) c.dev_miss[k] = m[k];
+        c.dev_valid = true;
+    }
+    return OCT_OK;
+}
+
+// Device side of an upload: change events into the other node table, gathers, skip bounds,
+// then the tables swap.
+static int upload_tail(oct_handle *h, hipStream_t s, int64_t V, bool in_place,
+                const std::vector<CellDelta> &deltas, const std::vector<BrickJob> &jobs,
+                uint64_t resident, uint64_t bricks_total, uint64_t pending, uint64_t requests_seen,
+                uint64_t evictions, uint64_t unserved, oct_upload_stats *out)
+{
+    const VolGeom &g = h->g;
+    const int C = g.C;
+    const size_t d_bytes = deltas.size() * sizeof(CellDelta);
+    const size_t j_off = (d_bytes + 255) & ~(size_t)255;
+    const size_t j_bytes = jobs.size() * sizeof(BrickJob);
+    const size_t gs_off = (j_off + j_bytes + 255) & ~(size_t)255;   // gather scratch
+    if (d_bytes + j_bytes) {
+        int rc = stage_reserve(h, h->up, gs_off + gather_scratch_bytes(g, (int)jobs.size()));
+        // renders read the node table and the pool: those of the other table's version (and
+        // older) end first, all of them when a brick they may read is rewritten in place
+        if (!rc) rc = (h->capped || in_place) ? wait_for_renders(h, s) : wait_for_renders_before(h, s, V);
+        if (rc) return rc;
+        if (d_bytes) std::memcpy(h->up.host, deltas.data(), d_bytes);
+        if (j_bytes) std::memcpy((uint8_t *)h->up.host + j_off, jobs.data(), j_bytes);
+        HIPCHK(h, hipMemcpyAsync(h->up.dev, h->up.host, j_off + j_bytes, hipMemcpyHostToDevice, s));
+        HIPCHK(h, hipEventRecord(h->up.ev, s));
+        DevCell *next = h->table_alt;
+        HIPCHK(h, hipMemcpyAsync(next, h->table, sizeof(DevCell) * (size_t)h->n_cells,
+                                 hipMemcpyDeviceToDevice, s));
+        HIPCHK(h, launch_apply_deltas(next, h->miss_range, (const CellDelta *)h->up.dev,
+                                      (int)deltas.size(), s));
+        hipEvent_t e0 = bt_begin(h, s);
+        const BrickJob *jobs_dev = (const BrickJob *)((uint8_t *)h->up.dev + j_off);
+        if (h->pc) {
+            int rc2 = gather_paged(h, jobs, 0, (int)jobs.size(), jobs_dev, next,
+                                   (uint8_t *)h->up.dev + gs_off, s);
+            if (rc2) return rc2;
+        } else {
+            HIPCHK(h, launch_gather(g, h->master, next, h->pool, h->brick_bytes, jobs_dev,
+                                    (int)jobs.size(), h->slot_range, h->background_f,
+                                    (uint8_t *)h->up.dev + gs_off, s));
+        }
+        if (e0) {
+            // per bordered voxel of each job's sub-box: the padded pool voxel written and the
+            // source level's C values read
+            double bytes = 0.0;
+            for (const BrickJob &jb : jobs) {
+                double nv = 1.0;
+                for (int a = 0; a < 3; a++) nv *= (double)(jb.hi[a] - jb.lo[a] + 1);
+                bytes += nv * (4.0 + (double)C) * (double)h->esz;
+            }
+            bt_end(h, e0, s, 3, bytes);
+        }
+        HIPCHK(h, launch_ranges(g, next, h->slot_range, h->miss_range, s));
+        h->table_alt = h->table;
+        h->table = next;
+        h->version++;
+    }
+    HIPCHK(h, hipEventRecord(h->ev_upload, s));
+    if (out) {
+        out->bricks_gathered = jobs.size();
+        out->bricks_resident = resident;
+        out->bricks_total = bricks_total;
+        out->nodes_changed = deltas.size();
+        out->bytes_written = jobs.size() * h->brick_bytes + d_bytes;
+        out->requests_seen = requests_seen;
+        out->evictions = evictions;
+    }
+    if (h->capped) return (pending || unserved) ? OCT_INCOMPLETE : OCT_OK;
+    return resident < bricks_total ? OCT_INCOMPLETE : OCT_OK;
+}
+
 int brick_pool_upload(oct_handle *h, uint64_t byte_budget, void *stream, oct_upload_stats *out)
 {
     if (!h) return OCT_EINVAL;
@@ -1400,6 +1619,22 @@ int brick_pool_upload(oct_handle *h, uint64_t byte_budget, void *stream, oct_upl
             h->free_slots.push_back(c.slot);
     };
     bool in_place = false;   // a brick renders may read is rewritten in its slot
+    bool dirty = false;
+    for (const auto &d : h->dirty) dirty = dirty || !d.empty();
+    std::vector<CellDelta> deltas;
+    std::vector<BrickJob> jobs;
+    uint64_t requests_seen = 0, evictions = 0, unserved = 0, resident = 0, pending = 0;
+    uint64_t bricks_total = 0;
+    if (h->capped && h->paging_ready && !dirty) {
+        int rc = upload_paging_only(h, byte_budget, s, deltas, jobs, requests_seen, evictions,
+                                    unserved);
+        if (rc) return rc;
+        resident = h->n_resident;
+        bricks_total = h->n_data;
+        return upload_tail(h, s, V, in_place, deltas, jobs, resident, bricks_total, pending,
+                           requests_seen, evictions, unserved, out);
+    }
+    h->paging_ready = false;
 
     // ---- 1. cells whose level data changed, and cells whose bordered region touches a change
     std::vector<int32_t> stat_cells;  // (L, x, y, z) quadruples
@@ -1615,9 +1850,7 @@ int brick_pool_upload(oct_handle *h, uint64_t byte_budget, void *stream, oct_upl
                                 near_change[cell_index(g, L, nx, ny, nz)] = 1;
                 }
     }
-    std::vector<BrickJob> jobs;
     uint64_t budget_left = byte_budget ? byte_budget : UINT64_MAX;
-    uint64_t bricks_total = 0;
     auto push_job = [&](HCell &c, int L, int x, int y, int z, bool full, const int32_t *bb) {
         BrickJob j{};
         j.slot = c.slot;
@@ -1674,7 +1907,6 @@ int brick_pool_upload(oct_handle *h, uint64_t byte_budget, void *stream, oct_upl
     // ---- 4. paging ("Brick Upload from RAM to GPU"): requested bricks get slots, coarser
     // levels first; free slots first, then slots unused by the last renders (least recently
     // used first), and when those run out a coarser request may take a used finer brick.
-    uint64_t requests_seen = 0, evictions = 0, unserved = 0;
     if (h->capped) {
         std::vector<int64_t> reqs, idle, busy;
         for (int L = g.N; L >= 0; L--) {
@@ -1735,7 +1967,6 @@ int brick_pool_upload(oct_handle *h, uint64_t byte_budget, void *stream, oct_upl
 
     // value bounds of missing bricks (their skip range): the brick and its 26 neighbours
     std::vector<float> miss((size_t)h->n_cells * 8, 0.0f);
-    uint64_t resident = 0, pending = 0;
     for (int L = g.N; L >= 0; L--) {
         const int G = g.grid[L];
         for (int z = 0; z < G; z++)
@@ -1766,7 +1997,6 @@ int brick_pool_upload(oct_handle *h, uint64_t byte_budget, void *stream, oct_upl
     }
 
     // ---- 5. change events for the node table, then the gathers, then the skip bounds
-    std::vector<CellDelta> deltas;
     for (int64_t i = 0; i < h->n_cells; i++) {
         HCell &c = h->cells[i];
         const int32_t slot = new_kind[i] == kBrick ? c.slot : -1;
@@ -1792,64 +2022,21 @@ int brick_pool_upload(oct_handle *h, uint64_t byte_budget, void *stream, oct_upl
         for (int k = 0; k < 8; k++) c.dev_miss[k] = m[k];
         c.dev_valid = true;
     }
-    const size_t d_bytes = deltas.size() * sizeof(CellDelta);
-    const size_t j_off = (d_bytes + 255) & ~(size_t)255;
-    const size_t j_bytes = jobs.size() * sizeof(BrickJob);
-    const size_t gs_off = (j_off + j_bytes + 255) & ~(size_t)255;   // gather scratch
-    if (d_bytes + j_bytes) {
-        int rc = stage_reserve(h, h->up, gs_off + gather_scratch_bytes(g, (int)jobs.size()));
-        // renders read the node table and the pool: those of the other table's version (and
-        // older) end first, all of them when a brick they may read is rewritten in place
-        if (!rc) rc = (h->capped || in_place) ? wait_for_renders(h, s) : wait_for_renders_before(h, s, V);
-        if (rc) return rc;
-        if (d_bytes) std::memcpy(h->up.host, deltas.data(), d_bytes);
-        if (j_bytes) std::memcpy((uint8_t *)h->up.host + j_off, jobs.data(), j_bytes);
-        HIPCHK(h, hipMemcpyAsync(h->up.dev, h->up.host, j_off + j_bytes, hipMemcpyHostToDevice, s));
-        HIPCHK(h, hipEventRecord(h->up.ev, s));
-        DevCell *next = h->table_alt;
-        HIPCHK(h, hipMemcpyAsync(next, h->table, sizeof(DevCell) * (size_t)h->n_cells,
-                                 hipMemcpyDeviceToDevice, s));
-        HIPCHK(h, launch_apply_deltas(next, h->miss_range, (const CellDelta *)h->up.dev,
-                                      (int)deltas.size(), s));
-        hipEvent_t e0 = bt_begin(h, s);
-        const BrickJob *jobs_dev = (const BrickJob *)((uint8_t *)h->up.dev + j_off);
-        if (h->pc) {
-            int rc2 = gather_paged(h, jobs, 0, (int)jobs.size(), jobs_dev, next,
-                                   (uint8_t *)h->up.dev + gs_off, s);
-            if (rc2) return rc2;
-        } else {
-            HIPCHK(h, launch_gather(g, h->master, next, h->pool, h->brick_bytes, jobs_dev,
-                                    (int)jobs.size(), h->slot_range, h->background_f,
-                                    (uint8_t *)h->up.dev + gs_off, s));
+    if (h->capped) {
+        // the state paging-only uploads start from
+        h->data_cell.assign((size_t)h->n_cells, 0);
+        h->slot_cell.assign((size_t)h->n_slots, -1);
+        for (int64_t ci = 0; ci < h->n_cells; ci++) {
+            h->data_cell[(size_t)ci] = new_kind[(size_t)ci] != kAvg;
+            const int32_t sl = h->cells[(size_t)ci].slot;
+            if (sl >= 0) h->slot_cell[(size_t)sl] = ci;
         }
-        if (e0) {
-            // per bordered voxel of each job's sub-box: the padded pool voxel written and the
-            // source level's C values read
-            double bytes = 0.0;
-            for (const BrickJob &jb : jobs) {
-                double nv = 1.0;
-                for (int a = 0; a < 3; a++) nv *= (double)(jb.hi[a] - jb.lo[a] + 1);
-                bytes += nv * (4.0 + (double)C) * (double)h->esz;
-            }
-            bt_end(h, e0, s, 3, bytes);
-        }
-        HIPCHK(h, launch_ranges(g, next, h->slot_range, h->miss_range, s));
-        h->table_alt = h->table;
-        h->table = next;
-        h->version++;
+        h->n_data = bricks_total;
+        h->n_resident = resident;
+        h->paging_ready = pending == 0;
     }
-    HIPCHK(h, hipEventRecord(h->ev_upload, s));
-    if (out) {
-        out->bricks_gathered = jobs.size();
-        out->bricks_resident = resident;
-        out->bricks_total = bricks_total;
-        out->nodes_changed = deltas.size();
-        out->bytes_written = jobs.size() * h->brick_bytes + d_bytes;
-        out->requests_seen = requests_seen;
-        out->evictions = evictions;
-    }
-    if (h->capped) return (pending || unserved) ? OCT_INCOMPLETE : OCT_OK;
-    return resident < bricks_total ? OCT_INCOMPLETE : OCT_OK;
+    return upload_tail(h, s, V, in_place, deltas, jobs, resident, bricks_total, pending,
+                       requests_seen, evictions, unserved, out);
 }
 
 // The render kernel a view runs in (views of one launch are grouped by class).
