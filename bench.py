@@ -108,6 +108,9 @@ def main():
                     help="stream workload: 2 = build and render on separate streams")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run a plain device copy of this size (counter calibration)")
+    ap.add_argument("--no-host-bricks", action="store_true",
+                    help="paging workload / leg: no host brick store (every paged brick is "
+                         "gathered from the pinned mipmap)")
     ap.add_argument("--scale", type=int, default=1, choices=[1, 2, 4],
                     help="paging workload / leg: 1 = 2048x2048x1024, 2 = half and 4 = quarter "
                          "size per axis")
@@ -734,7 +737,9 @@ def measure_paging(args) -> dict:
           flush=True)
     h2d = h2d_peak_gb_per_s()
     pool_bytes = (16 << 30) // (sc ** 3)
-    tree = Octree(dims, C, M, "u16", 0, 205, pool_bytes=pool_bytes, master_on_host=True)
+    store = not args.no_host_bricks
+    tree = Octree(dims, C, M, "u16", 0, 205, pool_bytes=pool_bytes, master_on_host=True,
+                  host_bricks=store)
     t_ins = time.perf_counter()
     zc = 64 // sc
     for z0 in range(0, dims[2], zc):
@@ -758,7 +763,7 @@ def measure_paging(args) -> dict:
     torch.cuda.synchronize()
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
           for _ in range(n_frames)]
-    comp = gathered = requests = evictions = 0
+    comp = gathered = requests = evictions = copied = 0
     tree.build_timing(True)    # gather kernel time of the frames' uploads (HIP events)
     t0 = time.perf_counter()
     up_s = 0.0
@@ -772,6 +777,7 @@ def measure_paging(args) -> dict:
         up = tree.upload(byte_budget=budget)
         up_s += time.perf_counter() - tu
         gathered += up["bricks_gathered"]
+        copied += up["bricks_from_store"]
         requests += up["requests_seen"]
         evictions += up["evictions"]
     torch.cuda.synchronize()
@@ -821,12 +827,15 @@ def measure_paging(args) -> dict:
         n_px += int(ok.sum())
         n_amb += int((~ok).sum())
     del ref
+    # host-link bytes: a gathered brick's source voxels, a copied brick's store entry (the
+    # bordered brick, channels unpadded) -- the same count for 3 channels
     paged_gbps = gathered * src_bytes / gather_s / 1e9 if gather_s > 0 else 0.0
     return {"metric": "out-of-core frames/s over a 64-frame orbit-and-dolly path",
             "value": round(n_frames / elapsed, 2), "unit": "frames/s", "n_gpus": 1,
             "higher_is_better": True, "data": "synthetic",
             "config": {"workload": f"{dims[0]}x{dims[1]}x{dims[2]}x3 u16, {blobs} blobs, 32^3 "
-                       f"bricks, master in pinned host memory, device pool {pool_bytes >> 20} "
+                       f"bricks, master in pinned host memory"
+                       f"{', host brick store' if store else ''}, device pool {pool_bytes >> 20} "
                        f"MiB, {W}x{H}, ERT 0.99, per-ray LOD, {budget >> 20} MiB upload budget "
                        "per frame"},
             "render_only_gsamples_per_s": round(comp / render_s / 1e9, 3),
@@ -834,6 +843,7 @@ def measure_paging(args) -> dict:
             "upload_host_ms_per_frame": round(up_s / n_frames * 1e3, 3),
             "gather_kernel_ms_per_frame": round(gather_s / n_frames * 1e3, 3),
             "paged_bricks": gathered,
+            "paged_bricks_from_store": copied,
             "paged_gb_per_s": round(paged_gbps, 2),
             "h2d_peak_gb_per_s": round(h2d, 2),
             "paged_frac_of_h2d_peak": round(paged_gbps / h2d, 3) if h2d > 0 else None,

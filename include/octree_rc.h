@@ -107,7 +107,12 @@ typedef struct {
     int32_t page_cells;         /* disk tier: cells per page edge, a power of two >= 2
                                    (0: 2); a page holds M*page_cells voxels per edge, all
                                    channels                                               */
-    int32_t reserved[2];        /* must be 0                                              */
+    int32_t host_bricks;        /* 1: keep every whole bordered brick the library gathers in a
+                                   host brick store (pinned host memory, channels unpadded;
+                                   the paper's brick pool in RAM), so that a brick paged in
+                                   again is copied as one contiguous block instead of being
+                                   gathered from the mipmap.  Needs a capped device pool.   */
+    int32_t reserved[1];        /* must be 0                                              */
     uint64_t host_cache_bytes;  /* disk tier: RAM for pages; must hold at least 16 pages
                                    (or every page)                                        */
     const char *disk_path;      /* disk tier: the page file, created (truncated) by
@@ -182,6 +187,7 @@ typedef struct {
     uint64_t bytes_written;     /* device bytes written for bricks and node entries        */
     uint64_t requests_seen;     /* missing bricks the renders since the last call asked for */
     uint64_t evictions;         /* resident bricks replaced by this call                   */
+    uint64_t bricks_from_store; /* of bricks_gathered: copied from the host brick store     */
 } oct_upload_stats;
 
 typedef struct {

@@ -456,7 +456,8 @@ constexpr int kGatherThreads = OCTRC_GATHER_THREADS;
 template <typename T, bool kPaged>
 __global__ void __launch_bounds__(kGatherThreads)
 k_gather(VolGeom g, MasterRef<const T> mr, const DevCell *table, uint8_t *pool, uint64_t brick_bytes,
-         const BrickJob *jobs, int n_items, int zsplit, float *part, float background)
+         const BrickJob *jobs, int n_items, int zsplit, float *part, float background,
+         uint8_t *store, uint64_t store_bytes)
 {
     __shared__ int s_kind[27];
     __shared__ float s_avg[27][4];
@@ -490,6 +491,9 @@ k_gather(VolGeom g, MasterRef<const T> mr, const DevCell *table, uint8_t *pool, 
         mx[c] = -FLT_MAX;
     }
     T *dst = (T *)(pool + (uint64_t)job.slot * brick_bytes);
+    // whole bricks may also go to the host brick store: C planes of S^3 elements
+    T *sto = (store && job.store >= 0) ? (T *)(store + (uint64_t)job.store * store_bytes) : nullptr;
+    const int64_t S3 = (int64_t)S * S * S;
     const int nx = job.hi[0] - job.lo[0] + 1, ny = job.hi[1] - job.lo[1] + 1;
     // this workgroup's share of the job's slices
     const int zper = (job.hi[2] - job.lo[2] + zsplit) / zsplit;
@@ -529,6 +533,9 @@ k_gather(VolGeom g, MasterRef<const T> mr, const DevCell *table, uint8_t *pool, 
             } else {
                 *(float4 *)(dst + i * 4) = make_float4(v[0], v[1], v[2], v[3]);
             }
+            if (sto)
+                for (int c = 0; c < kMaxC; c++)
+                    if (c < g.C) sto[c * S3 + i] = v[c];
         }
     }
     for (int c = 0; c < g.C; c++) {
@@ -546,12 +553,13 @@ k_gather(VolGeom g, MasterRef<const T> mr, const DevCell *table, uint8_t *pool, 
 // bound).
 __global__ void __launch_bounds__(kThreads)
 k_gather_fold(const BrickJob *jobs, int n_jobs, int zsplit, int C, const float *part,
-              float *slot_range)
+              float *slot_range, float *store_range)
 {
     const int j = blockIdx.x * kThreads + threadIdx.x;
     if (j >= n_jobs) return;
     const BrickJob &job = jobs[j];
     float *r = slot_range + (int64_t)job.slot * 8;
+    float *q = (store_range && job.store >= 0) ? store_range + (int64_t)job.store * 8 : nullptr;
     for (int c = 0; c < C; c++) {
         float lo = FLT_MAX, hi = -FLT_MAX;
         for (int k = 0; k < zsplit; k++) {
@@ -560,7 +568,53 @@ k_gather_fold(const BrickJob *jobs, int n_jobs, int zsplit, int C, const float *
         }
         r[c] = job.full ? lo : fminf(r[c], lo);
         r[4 + c] = job.full ? hi : fmaxf(r[4 + c], hi);
+        if (q) {   // stored whole bricks only
+            q[c] = lo;
+            q[4 + c] = hi;
+        }
     }
+}
+
+// Bricks from the host brick store into pool slots: a thread moves eight voxels, reading 16
+// bytes of each channel plane (whole, aligned words over the host link) and writing the
+// channel-interleaved, padded voxels.  Workgroup b takes chunk b % chunks of job b / chunks.
+template <typename T>
+__global__ void __launch_bounds__(kThreads)
+k_copy_bricks(int M, int C, uint8_t *pool, uint64_t brick_bytes, const CopyJob *jobs,
+              int chunks, const uint8_t *store, uint64_t store_bytes)
+{
+    const int S = M + 2;
+    const int64_t S3 = (int64_t)S * S * S;
+    const CopyJob job = jobs[blockIdx.x / chunks];
+    const int64_t v0 = ((int64_t)(blockIdx.x % chunks) * kThreads + threadIdx.x) * 8;
+    if (v0 >= S3) return;
+    const T *src = (const T *)(store + (uint64_t)job.store * store_bytes);
+    T *dst = (T *)(pool + (uint64_t)job.slot * brick_bytes);
+    Pack8<T> p[kMaxC];
+#pragma unroll
+    for (int c = 0; c < kMaxC; c++)
+        if (c < C) p[c] = Pack8<T>::load(src + c * S3 + v0);
+#pragma unroll
+    for (int e = 0; e < 8; e++) {
+        T v[4] = {(T)0, (T)0, (T)0, (T)0};
+#pragma unroll
+        for (int c = 0; c < kMaxC; c++)
+            if (c < C) v[c] = (T)p[c].at(e);
+        if constexpr (sizeof(T) == 2)
+            *(ushort4 *)(dst + (v0 + e) * 4) = make_ushort4(v[0], v[1], v[2], v[3]);
+        else
+            *(float4 *)(dst + (v0 + e) * 4) = make_float4(v[0], v[1], v[2], v[3]);
+    }
+}
+
+__global__ void __launch_bounds__(kThreads)
+k_copy_ranges(const CopyJob *jobs, int n, int C, const float *store_range, float *slot_range)
+{
+    const int j = blockIdx.x * kThreads + threadIdx.x;
+    if (j >= n) return;
+    for (int c = 0; c < C; c++)
+        for (int k = 0; k < 8; k += 4)
+            slot_range[(int64_t)jobs[j].slot * 8 + k + c] = store_range[(int64_t)jobs[j].store * 8 + k + c];
 }
 
 // ---------------------------------------------------------------------------------------
@@ -767,7 +821,8 @@ size_t gather_scratch_bytes(const VolGeom &g, int n)
 
 hipError_t launch_gather(const VolGeom &g, const void *master, const DevCell *table, void *pool,
                          uint64_t brick_bytes, const BrickJob *jobs, int n, float *slot_range,
-                         float background, void *scratch, hipStream_t s)
+                         float background, void *scratch, uint8_t *store, float *store_range,
+                         uint64_t store_bytes, hipStream_t s)
 {
     if (n == 0) return hipSuccess;
     const int zsplit = gather_zsplit(g), items = n * zsplit;
@@ -779,12 +834,33 @@ hipError_t launch_gather(const VolGeom &g, const void *master, const DevCell *ta
         const MasterRef<const T> mr{m0.base, m0.pages};
         hipLaunchKernelGGL((k_gather<T, kP>), grid, dim3(kGatherThreads), 0, s, g, mr, table,
                            (uint8_t *)pool, brick_bytes, jobs, items, zsplit, (float *)scratch,
-                           background);
+                           background, store, store_bytes);
     });
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_gather_fold, dim3(ceil_div(n, kThreads)), dim3(kThreads), 0, s, jobs, n,
-                       zsplit, g.C, (const float *)scratch, slot_range);
+                       zsplit, g.C, (const float *)scratch, slot_range, store_range);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_bricks(const VolGeom &g, void *pool, uint64_t brick_bytes,
+                              const CopyJob *jobs, int n, const uint8_t *store,
+                              const float *store_range, uint64_t store_bytes, float *slot_range,
+                              hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    const int64_t S = g.M + 2, words = S * S * S / 8;   // S is even: whole 8-voxel words
+    const int chunks = (int)ceil_div(words, kThreads);
+    if (g.dtype == 0)
+        hipLaunchKernelGGL(k_copy_bricks<uint16_t>, dim3((unsigned)(n * chunks)), dim3(kThreads), 0, s,
+                           g.M, g.C, (uint8_t *)pool, brick_bytes, jobs, chunks, store, store_bytes);
+    else
+        hipLaunchKernelGGL(k_copy_bricks<float>, dim3((unsigned)(n * chunks)), dim3(kThreads), 0, s,
+                           g.M, g.C, (uint8_t *)pool, brick_bytes, jobs, chunks, store, store_bytes);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_copy_ranges, dim3(ceil_div(n, kThreads)), dim3(kThreads), 0, s, jobs, n,
+                       g.C, store_range, slot_range);
     return hipGetLastError();
 }
 

@@ -169,7 +169,15 @@ struct BrickJob {       // one bordered brick to (re)build, whole or a sub-box o
     int32_t slot, level, bx, by, bz;
     int32_t full;       // 1: the sub-box is the whole bordered brick
     int32_t lo[3], hi[3];  // inclusive sub-box in bordered-brick coordinates 0..M+1
-    int32_t pad[4];
+    int32_t store;      // whole bricks: also written to host brick store entry `store` (-1: no)
+    int32_t pad[3];
+};
+
+// Host brick store (oct_create_params.host_bricks): entry e holds a bordered brick as C planes
+// of (M+2)^3 elements (channels not padded), at e * store_bytes in pinned host memory; its
+// value range (lo[4], hi[4]) in a device array.  A copy job moves entry `store` into `slot`.
+struct CopyJob {
+    int32_t slot, store;
 };
 static_assert(sizeof(BrickJob) == 64, "BrickJob layout");
 
@@ -214,9 +222,16 @@ hipError_t launch_apply_deltas(DevCell *table, float *miss_range, const CellDelt
                                hipStream_t s);
 // scratch: gather_scratch_bytes(g, n) bytes of device memory (per-workgroup value ranges)
 size_t gather_scratch_bytes(const VolGeom &g, int n);
+// store / store_range / store_bytes: the host brick store (NULL when there is none).
 hipError_t launch_gather(const VolGeom &g, const void *master, const DevCell *table,
                          void *pool, uint64_t brick_bytes, const BrickJob *jobs, int n,
-                         float *slot_range, float background, void *scratch, hipStream_t s);
+                         float *slot_range, float background, void *scratch, uint8_t *store,
+                         float *store_range, uint64_t store_bytes, hipStream_t s);
+// Bricks from the host brick store into pool slots, with their value ranges.
+hipError_t launch_copy_bricks(const VolGeom &g, void *pool, uint64_t brick_bytes,
+                              const CopyJob *jobs, int n, const uint8_t *store,
+                              const float *store_range, uint64_t store_bytes, float *slot_range,
+                              hipStream_t s);
 hipError_t launch_ranges(const VolGeom &g, DevCell *table, const float *slot_range,
                          const float *miss_range, hipStream_t s);
 hipError_t launch_clear(const VolGeom &g, void *master, uint8_t *mask, double background,

@@ -200,6 +200,15 @@ struct oct_handle {
     std::vector<uint8_t> data_cell;
     std::vector<int64_t> slot_cell;
     uint64_t n_data = 0, n_resident = 0;
+    // host brick store (host_bricks): one pinned entry per in-volume cell (channels unpadded),
+    // mapped for the kernels; which entries hold their cell's current bordered brick; the
+    // entries' value ranges on the device
+    uint8_t *store = nullptr;
+    uint8_t *store_dev = nullptr;
+    uint64_t store_bytes = 0;
+    std::vector<int32_t> store_idx;
+    std::vector<uint8_t> store_ok;
+    float *store_range = nullptr;
     std::vector<HCell> cells;
     std::vector<int32_t> free_slots;
     std::vector<std::vector<Box>> dirty;  // per level
@@ -558,8 +567,12 @@ bool valid_params(const oct_create_params *p, std::string &why)
         why = "u16 background must be an integer in [0, 65535]";
         return false;
     }
-    for (int i = 0; i < 2; i++)
-        if (p->reserved[i]) { why = "reserved fields must be 0"; return false; }
+    if (p->reserved[0]) { why = "reserved fields must be 0"; return false; }
+    if (p->host_bricks != 0 && p->host_bricks != 1) { why = "host_bricks must be 0 or 1"; return false; }
+    if (p->host_bricks && !p->device_pool_bytes) {
+        why = "host_bricks needs a capped device pool (device_pool_bytes)";
+        return false;
+    }
     if (p->master_on_host < OCT_MASTER_HBM || p->master_on_host > OCT_MASTER_DISK) {
         why = "master_on_host must be OCT_MASTER_HBM, _HOST or _DISK";
         return false;
@@ -590,6 +603,7 @@ void reset_host_state(oct_handle *h)
     const VolGeom &g = h->g;
     const int C = g.C;
     h->paging_ready = false;
+    std::fill(h->store_ok.begin(), h->store_ok.end(), 0);
     for (auto &c : h->cells) c = HCell();
     for (int L = 0; L <= g.N; L++) {
         const int G = g.grid[L];
@@ -916,7 +930,8 @@ int gather_paged(oct_handle *h, const std::vector<BrickJob> &jobs, int j0, int j
         const int a0 = i0, n = i1 - i0;
         const int rc = paged_batch(h, pages, wr, s, [&]() -> int {
             HIPCHK(h, launch_gather(g, h->master, table, h->pool, h->brick_bytes, jobs_dev + a0, n,
-                                    h->slot_range, h->background_f, scratch, s));
+                                    h->slot_range, h->background_f, scratch, h->store_dev,
+                                    h->store_range, h->store_bytes, s));
             return OCT_OK;
         });
         if (rc) return rc;
@@ -1123,6 +1138,32 @@ int octree_create(const oct_create_params *params, void *stream, oct_handle **ou
     if ((rc = dev_alloc((void **)&h->miss_range, sizeof(float) * 8 * (size_t)h->n_cells))) return bail(rc);
     if (hipHostMalloc((void **)&h->flags_host, (size_t)h->n_cells, hipHostMallocDefault) != hipSuccess)
         return bail(OCT_ENOMEM);
+    if (params->host_bricks) {
+        if (!h->capped) {
+            h->err = "host_bricks needs a device pool smaller than the octree's bricks";
+            return bail(OCT_EINVAL);
+        }
+        h->store_bytes = ((uint64_t)S * S * S * (uint64_t)g.C * h->esz + 255) & ~(uint64_t)255;
+        h->store_idx.assign((size_t)h->n_cells, -1);
+        int32_t ne = 0;
+        for (int L = 0; L <= N; L++) {
+            int nb[3];
+            for (int a = 0; a < 3; a++) nb[a] = (g.ext[L][a] + g.M - 1) / g.M;
+            const int G = g.grid[L];
+            for (int z = 0; z < nb[2]; z++)
+                for (int y = 0; y < nb[1]; y++)
+                    for (int x = 0; x < nb[0]; x++)
+                        h->store_idx[(size_t)(g.cell_off[L] + ((int64_t)z * G + y) * G + x)] = ne++;
+        }
+        h->store_ok.assign((size_t)ne, 0);
+        hipError_t e = hipHostMalloc((void **)&h->store, (size_t)ne * h->store_bytes, hipHostMallocMapped);
+        if (e == hipSuccess) e = hipHostGetDevicePointer((void **)&h->store_dev, h->store, 0);
+        if (e != hipSuccess) {
+            h->err = std::string("host brick store: ") + hipGetErrorString(e);
+            return bail(e == hipErrorOutOfMemory ? OCT_ENOMEM : OCT_EDEVICE);
+        }
+        if ((rc = dev_alloc((void **)&h->store_range, sizeof(float) * 8 * (size_t)ne))) return bail(rc);
+    }
     h->last_used.assign((size_t)h->n_cells, 0);
     if (hipStreamCreateWithFlags(&h->prep, hipStreamNonBlocking) != hipSuccess) return bail(OCT_EDEVICE);
     if (hipEventCreateWithFlags(&h->ins_ev, hipEventDisableTiming) != hipSuccess ||
@@ -1170,6 +1211,8 @@ int octree_destroy(oct_handle *h)
     }
     if (h->flags) (void)hipFree(h->flags);
     if (h->flags_host) (void)hipHostFree(h->flags_host);
+    if (h->store) (void)hipHostFree(h->store);
+    if (h->store_range) (void)hipFree(h->store_range);
     if (h->miss_range) (void)hipFree(h->miss_range);
     if (h->mask) (void)hipFree(h->mask);
     if (h->table) (void)hipFree(h->table);
@@ -1383,7 +1426,8 @@ int octree_insert_slices(oct_handle *h, int32_t channel, int32_t z0, int32_t nz,
 // render flags, the resident slots and the cells that change.
 static int upload_paging_only(oct_handle *h, uint64_t byte_budget, hipStream_t s,
                               std::vector<CellDelta> &deltas, std::vector<BrickJob> &jobs,
-                              uint64_t &requests_seen, uint64_t &evictions, uint64_t &unserved)
+                              std::vector<CopyJob> &copies, uint64_t &requests_seen,
+                              uint64_t &evictions, uint64_t &unserved)
 {
     const VolGeom &g = h->g;
     const int C = g.C;
@@ -1451,15 +1495,22 @@ static int upload_paging_only(oct_handle *h, uint64_t byte_budget, hipStream_t s
         h->slot_cell[(size_t)c.slot] = ci;
         const int G = g.grid[L];
         const int64_t li = ci - g.cell_off[L];
-        BrickJob j{};
-        j.slot = c.slot;
-        j.level = L;
-        j.bx = (int)(li % G);
-        j.by = (int)((li / G) % G);
-        j.bz = (int)(li / ((int64_t)G * G));
-        j.full = 1;
-        for (int a = 0; a < 3; a++) j.hi[a] = g.M + 1;
-        jobs.push_back(j);
+        const int32_t e = h->store ? h->store_idx[(size_t)ci] : -1;
+        if (e >= 0 && h->store_ok[(size_t)e]) {
+            copies.push_back(CopyJob{c.slot, e});
+        } else {
+            BrickJob j{};
+            j.slot = c.slot;
+            j.level = L;
+            j.bx = (int)(li % G);
+            j.by = (int)((li / G) % G);
+            j.bz = (int)(li / ((int64_t)G * G));
+            j.full = 1;
+            j.store = e;
+            if (e >= 0) h->store_ok[(size_t)e] = 1;
+            for (int a = 0; a < 3; a++) j.hi[a] = g.M + 1;
+            jobs.push_back(j);
+        }
         budget_left -= h->brick_bytes;
         c.needs_gather = false;
         changed.push_back(ci);
@@ -1521,7 +1572,7 @@ static int upload_paging_only(oct_handle *h, uint64_t byte_budget, hipStream_t s
 // then the tables swap.
 static int upload_tail(oct_handle *h, hipStream_t s, int64_t V, bool in_place,
                 const std::vector<CellDelta> &deltas, const std::vector<BrickJob> &jobs,
-                uint64_t resident, uint64_t bricks_total, uint64_t pending, uint64_t requests_seen,
+                const std::vector<CopyJob> &copies, uint64_t resident, uint64_t bricks_total, uint64_t pending, uint64_t requests_seen,
                 uint64_t evictions, uint64_t unserved, oct_upload_stats *out)
 {
     const VolGeom &g = h->g;
@@ -1529,8 +1580,10 @@ static int upload_tail(oct_handle *h, hipStream_t s, int64_t V, bool in_place,
     const size_t d_bytes = deltas.size() * sizeof(CellDelta);
     const size_t j_off = (d_bytes + 255) & ~(size_t)255;
     const size_t j_bytes = jobs.size() * sizeof(BrickJob);
-    const size_t gs_off = (j_off + j_bytes + 255) & ~(size_t)255;   // gather scratch
-    if (d_bytes + j_bytes) {
+    const size_t c_off = (j_off + j_bytes + 255) & ~(size_t)255;    // copies from the store
+    const size_t c_bytes = copies.size() * sizeof(CopyJob);
+    const size_t gs_off = (c_off + c_bytes + 255) & ~(size_t)255;   // gather scratch
+    if (d_bytes + j_bytes + c_bytes) {
         int rc = stage_reserve(h, h->up, gs_off + gather_scratch_bytes(g, (int)jobs.size()));
         // renders read the node table and the pool: those of the other table's version (and
         // older) end first, all of them when a brick they may read is rewritten in place
@@ -1538,7 +1591,8 @@ static int upload_tail(oct_handle *h, hipStream_t s, int64_t V, bool in_place,
         if (rc) return rc;
         if (d_bytes) std::memcpy(h->up.host, deltas.data(), d_bytes);
         if (j_bytes) std::memcpy((uint8_t *)h->up.host + j_off, jobs.data(), j_bytes);
-        HIPCHK(h, hipMemcpyAsync(h->up.dev, h->up.host, j_off + j_bytes, hipMemcpyHostToDevice, s));
+        if (c_bytes) std::memcpy((uint8_t *)h->up.host + c_off, copies.data(), c_bytes);
+        HIPCHK(h, hipMemcpyAsync(h->up.dev, h->up.host, c_off + c_bytes, hipMemcpyHostToDevice, s));
         HIPCHK(h, hipEventRecord(h->up.ev, s));
         DevCell *next = h->table_alt;
         HIPCHK(h, hipMemcpyAsync(next, h->table, sizeof(DevCell) * (size_t)h->n_cells,
@@ -1554,17 +1608,25 @@ static int upload_tail(oct_handle *h, hipStream_t s, int64_t V, bool in_place,
         } else {
             HIPCHK(h, launch_gather(g, h->master, next, h->pool, h->brick_bytes, jobs_dev,
                                     (int)jobs.size(), h->slot_range, h->background_f,
-                                    (uint8_t *)h->up.dev + gs_off, s));
+                                    (uint8_t *)h->up.dev + gs_off, h->store_dev, h->store_range,
+                                    h->store_bytes, s));
         }
+        HIPCHK(h, launch_copy_bricks(g, h->pool, h->brick_bytes,
+                                     (const CopyJob *)((uint8_t *)h->up.dev + c_off),
+                                     (int)copies.size(), h->store_dev, h->store_range,
+                                     h->store_bytes, h->slot_range, s));
         if (e0) {
             // per bordered voxel of each job's sub-box: the padded pool voxel written and the
-            // source level's C values read
+            // source level's C values read (plus the store entry written for stored bricks);
+            // per copied brick: the entry read and the padded brick written
             double bytes = 0.0;
+            const double s3 = (double)(g.M + 2) * (g.M + 2) * (g.M + 2);
             for (const BrickJob &jb : jobs) {
                 double nv = 1.0;
                 for (int a = 0; a < 3; a++) nv *= (double)(jb.hi[a] - jb.lo[a] + 1);
-                bytes += nv * (4.0 + (double)C) * (double)h->esz;
+                bytes += nv * (4.0 + (double)C + (jb.store >= 0 ? (double)C : 0.0)) * (double)h->esz;
             }
+            bytes += (double)copies.size() * s3 * (4.0 + (double)C) * (double)h->esz;
             bt_end(h, e0, s, 3, bytes);
         }
         HIPCHK(h, launch_ranges(g, next, h->slot_range, h->miss_range, s));
@@ -1574,11 +1636,12 @@ static int upload_tail(oct_handle *h, hipStream_t s, int64_t V, bool in_place,
     }
     HIPCHK(h, hipEventRecord(h->ev_upload, s));
     if (out) {
-        out->bricks_gathered = jobs.size();
+        out->bricks_gathered = jobs.size() + copies.size();
+        out->bricks_from_store = copies.size();
         out->bricks_resident = resident;
         out->bricks_total = bricks_total;
         out->nodes_changed = deltas.size();
-        out->bytes_written = jobs.size() * h->brick_bytes + d_bytes;
+        out->bytes_written = (jobs.size() + copies.size()) * h->brick_bytes + d_bytes;
         out->requests_seen = requests_seen;
         out->evictions = evictions;
     }
@@ -1623,16 +1686,17 @@ int brick_pool_upload(oct_handle *h, uint64_t byte_budget, void *stream, oct_upl
     for (const auto &d : h->dirty) dirty = dirty || !d.empty();
     std::vector<CellDelta> deltas;
     std::vector<BrickJob> jobs;
+    std::vector<CopyJob> copies;
     uint64_t requests_seen = 0, evictions = 0, unserved = 0, resident = 0, pending = 0;
     uint64_t bricks_total = 0;
     if (h->capped && h->paging_ready && !dirty) {
-        int rc = upload_paging_only(h, byte_budget, s, deltas, jobs, requests_seen, evictions,
-                                    unserved);
+        int rc = upload_paging_only(h, byte_budget, s, deltas, jobs, copies, requests_seen,
+                                    evictions, unserved);
         if (rc) return rc;
         resident = h->n_resident;
         bricks_total = h->n_data;
-        return upload_tail(h, s, V, in_place, deltas, jobs, resident, bricks_total, pending,
-                           requests_seen, evictions, unserved, out);
+        return upload_tail(h, s, V, in_place, deltas, jobs, copies, resident, bricks_total,
+                           pending, requests_seen, evictions, unserved, out);
     }
     h->paging_ready = false;
 
@@ -1851,7 +1915,16 @@ int brick_pool_upload(oct_handle *h, uint64_t byte_budget, void *stream, oct_upl
                 }
     }
     uint64_t budget_left = byte_budget ? byte_budget : UINT64_MAX;
+    // a whole brick is copied from the host brick store when the store holds it, else gathered
+    // (and, with a store, written to it too)
     auto push_job = [&](HCell &c, int L, int x, int y, int z, bool full, const int32_t *bb) {
+        const int32_t e = h->store ? h->store_idx[(size_t)cell_index(g, L, x, y, z)] : -1;
+        budget_left -= h->brick_bytes;
+        c.needs_gather = false;
+        if (full && e >= 0 && h->store_ok[(size_t)e]) {
+            copies.push_back(CopyJob{c.slot, e});
+            return;
+        }
         BrickJob j{};
         j.slot = c.slot;
         j.level = L;
@@ -1859,13 +1932,13 @@ int brick_pool_upload(oct_handle *h, uint64_t byte_budget, void *stream, oct_upl
         j.by = y;
         j.bz = z;
         j.full = full ? 1 : 0;
+        j.store = full ? e : -1;
+        if (full && e >= 0) h->store_ok[(size_t)e] = 1;
         for (int a = 0; a < 3; a++) {
             j.lo[a] = full ? 0 : bb[a];
             j.hi[a] = full ? S - 1 : bb[3 + a];
         }
         jobs.push_back(j);
-        budget_left -= h->brick_bytes;
-        c.needs_gather = false;
     };
     for (int L = g.N; L >= 0; L--) {  // coarse levels first
         const int G = g.grid[L];
@@ -1876,10 +1949,12 @@ int brick_pool_upload(oct_handle *h, uint64_t byte_budget, void *stream, oct_upl
                     HCell &c = h->cells[ci];
                     if (new_kind[ci] == kAvg) continue;
                     bricks_total++;
+                    const int32_t *bb = &border_box[(size_t)ci * 6];
+                    if (h->store && (near_change[ci] || (bb[3] >= 0 && bb[4] >= 0 && bb[5] >= 0)))
+                        h->store_ok[(size_t)h->store_idx[(size_t)ci]] = 0;   // its brick changed
                     if (c.slot < 0) continue;
                     // whole brick: new slot, deferred earlier, or a neighbour changed kind/AVG
                     bool full = c.needs_gather || near_change[ci];
-                    const int32_t *bb = &border_box[(size_t)ci * 6];
                     const bool part = !full && bb[3] >= 0 && bb[4] >= 0 && bb[5] >= 0;
                     if (full || part) {
                         if (budget_left >= h->brick_bytes) {
@@ -2035,7 +2110,7 @@ int brick_pool_upload(oct_handle *h, uint64_t byte_budget, void *stream, oct_upl
         h->n_resident = resident;
         h->paging_ready = pending == 0;
     }
-    return upload_tail(h, s, V, in_place, deltas, jobs, resident, bricks_total, pending,
+    return upload_tail(h, s, V, in_place, deltas, jobs, copies, resident, bricks_total, pending,
                        requests_seen, evictions, unserved, out);
 }
 
@@ -2740,6 +2815,7 @@ int octree_dump_canonical(oct_handle *h, void *buf, size_t cap, size_t *needed)
                         j.by = y;
                         j.bz = z;
                         j.full = 1;
+                        j.store = -1;
                         for (int a = 0; a < 3; a++) j.hi[a] = S - 1;
                         std::memcpy(h->up.host, &j, sizeof j);
                         HIPCHK(h, hipMemcpy(h->up.dev, h->up.host, sizeof j, hipMemcpyHostToDevice));
@@ -2751,7 +2827,8 @@ int octree_dump_canonical(oct_handle *h, void *buf, size_t cap, size_t *needed)
                         } else {
                             HIPCHK(h, launch_gather(g, h->master, h->table, h->pool, h->brick_bytes,
                                                     (const BrickJob *)h->up.dev, 1, h->slot_range,
-                                                    h->background_f, gscratch, nullptr));
+                                                    h->background_f, gscratch, nullptr, nullptr, 0,
+                                                    nullptr));
                         }
                         HIPCHK(h, hipDeviceSynchronize());
                     }

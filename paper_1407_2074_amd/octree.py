@@ -34,7 +34,8 @@ class CreateParams(ct.Structure):
                 ("dtype", ct.c_int32), ("background", ct.c_double),
                 ("homog_threshold", ct.c_double), ("device_pool_bytes", ct.c_uint64),
                 ("master_on_host", ct.c_int32), ("page_cells", ct.c_int32),
-                ("reserved", ct.c_int32 * 2), ("host_cache_bytes", ct.c_uint64),
+                ("host_bricks", ct.c_int32), ("reserved", ct.c_int32 * 1),
+                ("host_cache_bytes", ct.c_uint64),
                 ("disk_path", ct.c_char_p)]
 
 
@@ -55,7 +56,7 @@ class UploadStats(ct.Structure):
     _fields_ = [("bricks_gathered", ct.c_uint64), ("bricks_resident", ct.c_uint64),
                 ("bricks_total", ct.c_uint64), ("nodes_changed", ct.c_uint64),
                 ("bytes_written", ct.c_uint64), ("requests_seen", ct.c_uint64),
-                ("evictions", ct.c_uint64)]
+                ("evictions", ct.c_uint64), ("bricks_from_store", ct.c_uint64)]
 
 
 class DiskStats(ct.Structure):
@@ -204,9 +205,10 @@ class Octree:
     def __init__(self, dims, channels: int, brick: int, dtype: str = "u16",
                  background: float = 0.0, threshold: float = 0.0, pool_bytes: int = 0,
                  master_on_host: bool = False, stream=None, disk_path: str | None = None,
-                 host_cache_bytes: int = 0, page_cells: int = 0):
+                 host_cache_bytes: int = 0, page_cells: int = 0, host_bricks: bool = False):
         """disk_path: keep the mipmap in pages in this file with host_cache_bytes of RAM
-        frames (the disk tier); master_on_host: in pinned host memory; else in HBM."""
+        frames (the disk tier); master_on_host: in pinned host memory; else in HBM.
+        host_bricks: keep gathered bricks in a host brick store (capped pools)."""
         p = CreateParams()
         for a in range(3):
             p.dims[a] = int(dims[a])
@@ -214,6 +216,7 @@ class Octree:
         p.dtype = OCT_U16 if dtype == "u16" else OCT_F32
         p.background, p.homog_threshold = float(background), float(threshold)
         p.device_pool_bytes = int(pool_bytes)
+        p.host_bricks = 1 if host_bricks else 0
         if disk_path is not None:
             p.master_on_host = OCT_MASTER_DISK
             p.disk_path = os.fsencode(disk_path)

@@ -67,7 +67,8 @@ def test_invalid_create_params_fail_without_gpu_work(native):
                 dict(dims=(0, 4, 4)), dict(dtype=7), dict(background=1.5), dict(reserved=1),
                 dict(master=3), dict(master=disk), dict(master=disk, path=b"/tmp/x", brick=6),
                 dict(master=disk, path=b"/tmp/x", page_cells=3), dict(page_cells=2),
-                dict(cache=1 << 20), dict(path=b"/tmp/x")]:
+                dict(cache=1 << 20), dict(path=b"/tmp/x"), dict(host_bricks=2),
+                dict(host_bricks=1)]:
         p = native.CreateParams()
         dims = bad.get("dims", (16, 16, 16))
         for a in range(3):
@@ -76,7 +77,8 @@ def test_invalid_create_params_fail_without_gpu_work(native):
         p.brick_size = bad.get("brick", 8)
         p.dtype = bad.get("dtype", 0)
         p.background = bad.get("background", 0.0)
-        p.reserved[1] = bad.get("reserved", 0)
+        p.reserved[0] = bad.get("reserved", 0)
+        p.host_bricks = bad.get("host_bricks", 0)
         p.master_on_host = bad.get("master", 0)
         p.page_cells = bad.get("page_cells", 0)
         p.host_cache_bytes = bad.get("cache", 0)

@@ -133,3 +133,94 @@ def test_master_in_pinned_host_memory(orc, vol):
         (a,) = t.render([v])
         (b,) = full.render([v])
         assert torch.equal(a, b)
+
+
+@pytest.fixture(scope="module")
+def cap(vol):
+    """The largest working set of the four views (bricks resident once a view converged)."""
+    full = _tree(vol)
+    n_all = full.pool_slots - 1
+    ws = []
+    for v in _views():
+        t = _tree(vol, slots=n_all)
+        _, st = _converge(t, v)
+        ws.append(st["bricks_resident"])
+        t.close()
+    return max(ws)
+
+
+def _paged(vol, slots, **kw):
+    from paper_1407_2074_amd.octree import Octree
+    probe = Octree(DIMS, C, M, "u16", 0, THR)
+    bb = probe.brick_bytes
+    probe.close()
+    return Octree(DIMS, C, M, "u16", 0, THR, pool_bytes=slots * bb, **kw)
+
+
+def test_host_brick_store_pages_bricks_back_as_copies(orc, vol, cap):
+    """With a host brick store, bricks evicted and requested again come back as copies of the
+    stored bricks; every converged view equals the in-core image and the dump equals the
+    oracle's (residency aside)."""
+    import torch
+    full = _tree(vol)
+    views = _views()
+    t = _paged(vol, cap, host_bricks=True, master_on_host=True)
+    t.insert_block(-1, (0, 0, 0), vol)
+    t.upload()
+    copied = gathered = 0
+    for v in views + views:            # the second round re-requests evicted bricks
+        (want,) = full.render([v])
+        for it in range(80):
+            (img,) = t.render([v])
+            st = t.upload()
+            copied += st["bricks_from_store"]
+            gathered += st["bricks_gathered"] - st["bricks_from_store"]
+            if st["requests_seen"] == 0:
+                break
+        else:
+            pytest.fail("paging did not converge")
+        assert torch.equal(img, want)
+    assert copied > 0 and gathered > 0
+    ref, _ = _oracle_with_residency(orc, vol, t.dump())
+    (r,) = ref.render([views[0]])
+    (img,) = t.render([views[0]])
+    assert np.abs(img.cpu().numpy() - r).max() <= 1e-4
+
+
+def test_host_brick_store_follows_new_data(orc, cap):
+    """Bricks stored before more data arrives are not reused once their data (or a neighbour's
+    border data) changed: after the second half of the volume is inserted, paging converges to
+    the in-core image of the whole volume."""
+    import torch
+    vol = synth.gen_volume(DIMS, C, seed=13, n_blobs=60)
+    half = DIMS[2] // 2
+    t = _paged(vol, cap + 40, host_bricks=True)
+    full = _tree(vol)
+    views = _views()
+    t.insert_slices(-1, 0, np.ascontiguousarray(vol[:, :half]))
+    t.upload()
+    for v in views:                    # page (and store) bricks of the half volume
+        for it in range(80):
+            t.render([v])
+            if t.upload()["requests_seen"] == 0:
+                break
+    t.insert_slices(-1, half, np.ascontiguousarray(vol[:, half:]))
+    t.upload()
+    copied = 0
+    for v in views:
+        (want,) = full.render([v])
+        for it in range(80):
+            (img,) = t.render([v])
+            st = t.upload()
+            copied += st["bricks_from_store"]
+            if st["requests_seen"] == 0:
+                break
+        else:
+            pytest.fail("paging did not converge")
+        assert torch.equal(img, want)
+    want_dump = orc.Tree(vol, _full(C, DIMS), M, 0, THR)
+    ref, _ = _oracle_with_residency(orc, vol, t.dump())
+    (r,) = ref.render([views[1]])
+    (img,) = t.render([views[1]])
+    assert np.abs(img.cpu().numpy() - r).max() <= 1e-4
+    assert want_dump.levels == t.levels
