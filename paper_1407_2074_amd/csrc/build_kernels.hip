@@ -490,7 +490,8 @@ k_gather(VolGeom g, MasterRef<const T> mr, const DevCell *table, uint8_t *pool, 
         mn[c] = FLT_MAX;
         mx[c] = -FLT_MAX;
     }
-    T *dst = (T *)(pool + (uint64_t)job.slot * brick_bytes);
+    // slot < 0: the brick goes to the host brick store only (it is not resident)
+    T *dst = job.slot >= 0 ? (T *)(pool + (uint64_t)job.slot * brick_bytes) : nullptr;
     // whole bricks may also go to the host brick store: C planes of S^3 elements
     T *sto = (store && job.store >= 0) ? (T *)(store + (uint64_t)job.store * store_bytes) : nullptr;
     const int64_t S3 = (int64_t)S * S * S;
@@ -528,10 +529,12 @@ k_gather(VolGeom g, MasterRef<const T> mr, const DevCell *table, uint8_t *pool, 
                     mx[c] = fmaxf(mx[c], (float)v[c]);
                 }
             const int64_t i = ((int64_t)z * S + y) * S + x;
-            if constexpr (sizeof(T) == 2) {
-                *(ushort4 *)(dst + i * 4) = make_ushort4(v[0], v[1], v[2], v[3]);
-            } else {
-                *(float4 *)(dst + i * 4) = make_float4(v[0], v[1], v[2], v[3]);
+            if (dst) {
+                if constexpr (sizeof(T) == 2) {
+                    *(ushort4 *)(dst + i * 4) = make_ushort4(v[0], v[1], v[2], v[3]);
+                } else {
+                    *(float4 *)(dst + i * 4) = make_float4(v[0], v[1], v[2], v[3]);
+                }
             }
             if (sto)
                 for (int c = 0; c < kMaxC; c++)
@@ -558,7 +561,7 @@ k_gather_fold(const BrickJob *jobs, int n_jobs, int zsplit, int C, const float *
     const int j = blockIdx.x * kThreads + threadIdx.x;
     if (j >= n_jobs) return;
     const BrickJob &job = jobs[j];
-    float *r = slot_range + (int64_t)job.slot * 8;
+    float *r = job.slot >= 0 ? slot_range + (int64_t)job.slot * 8 : nullptr;
     float *q = (store_range && job.store >= 0) ? store_range + (int64_t)job.store * 8 : nullptr;
     for (int c = 0; c < C; c++) {
         float lo = FLT_MAX, hi = -FLT_MAX;
@@ -566,8 +569,10 @@ k_gather_fold(const BrickJob *jobs, int n_jobs, int zsplit, int C, const float *
             lo = fminf(lo, part[((int64_t)j * zsplit + k) * 8 + c]);
             hi = fmaxf(hi, part[((int64_t)j * zsplit + k) * 8 + 4 + c]);
         }
-        r[c] = job.full ? lo : fminf(r[c], lo);
-        r[4 + c] = job.full ? hi : fmaxf(r[4 + c], hi);
+        if (r) {
+            r[c] = job.full ? lo : fminf(r[c], lo);
+            r[4 + c] = job.full ? hi : fmaxf(r[4 + c], hi);
+        }
         if (q) {   // stored whole bricks only
             q[c] = lo;
             q[4 + c] = hi;

@@ -1624,7 +1624,8 @@ static int upload_tail(oct_handle *h, hipStream_t s, int64_t V, bool in_place,
             for (const BrickJob &jb : jobs) {
                 double nv = 1.0;
                 for (int a = 0; a < 3; a++) nv *= (double)(jb.hi[a] - jb.lo[a] + 1);
-                bytes += nv * (4.0 + (double)C + (jb.store >= 0 ? (double)C : 0.0)) * (double)h->esz;
+                bytes += nv * ((jb.slot >= 0 ? 4.0 : 0.0) + (double)C + (jb.store >= 0 ? (double)C : 0.0)) *
+                         (double)h->esz;
             }
             bytes += (double)copies.size() * s3 * (4.0 + (double)C) * (double)h->esz;
             bt_end(h, e0, s, 3, bytes);
@@ -1950,11 +1951,33 @@ int brick_pool_upload(oct_handle *h, uint64_t byte_budget, void *stream, oct_upl
                     if (new_kind[ci] == kAvg) continue;
                     bricks_total++;
                     const int32_t *bb = &border_box[(size_t)ci * 6];
-                    if (h->store && (near_change[ci] || (bb[3] >= 0 && bb[4] >= 0 && bb[5] >= 0)))
-                        h->store_ok[(size_t)h->store_idx[(size_t)ci]] = 0;   // its brick changed
+                    const bool changed = near_change[ci] || (bb[3] >= 0 && bb[4] >= 0 && bb[5] >= 0);
+                    if (h->store) {
+                        // the store holds every brick's current bordered brick: a changed brick
+                        // is gathered whole, into the store alone when it is not resident
+                        const int32_t e = h->store_idx[(size_t)ci];
+                        if (changed) h->store_ok[(size_t)e] = 0;
+                        if (c.slot < 0) {
+                            if (!h->store_ok[(size_t)e]) {
+                                BrickJob j{};
+                                j.slot = -1;
+                                j.level = L;
+                                j.bx = x;
+                                j.by = y;
+                                j.bz = z;
+                                j.full = 1;
+                                j.store = e;
+                                for (int a = 0; a < 3; a++) j.hi[a] = S - 1;
+                                jobs.push_back(j);
+                                h->store_ok[(size_t)e] = 1;
+                            }
+                            continue;
+                        }
+                    }
                     if (c.slot < 0) continue;
                     // whole brick: new slot, deferred earlier, or a neighbour changed kind/AVG
-                    bool full = c.needs_gather || near_change[ci];
+                    // (and, with a store, any change: the store keeps whole bricks)
+                    bool full = c.needs_gather || near_change[ci] || (h->store && changed);
                     const bool part = !full && bb[3] >= 0 && bb[4] >= 0 && bb[5] >= 0;
                     if (full || part) {
                         if (budget_left >= h->brick_bytes) {
