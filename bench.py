@@ -667,20 +667,27 @@ def bench_views(args):
     _, st = t.render(views, images=imgs, stats=True)
     for _ in range(3):
         t.render(views, images=imgs)
-    tb = _sync_time(lambda: t.render(views, images=imgs), max(args.steps, 10))
+    reps = max(args.steps, 10)
+    t.render_timing(True)      # ray-casting kernel time (HIP events), beside the wall time
+    tb = _sync_time(lambda: t.render(views, images=imgs), reps)
+    kb_ms, kb_n = t.render_timing(False)
 
     def single():
         for v, im in zip(views, imgs):
             t.render([v], images=[im])
 
     single()
-    ts = _sync_time(single, max(args.steps, 10))
+    t.render_timing(True)
+    ts = _sync_time(single, reps)
+    ks_ms, ks_n = t.render_timing(False)
     comp = st["positions_composited"]
     out = {"metric": "Gsamples/s, 64 views of 64^3 x 3 at 128x128", "value": round(comp / tb / 1e9, 3),
            "unit": "Gsamples/s", "n_gpus": 1, "higher_is_better": True, "data": "synthetic",
            "config": {"workload": "64 orbit views, 128x128, clip x >= 24, LOD 0, thr 205"},
            "batched_us_per_launch": round(tb * 1e6, 1), "us_per_frame": round(tb * 1e6 / 64, 2),
+           "batched_kernel_us_per_launch": round(kb_ms * 1e3 / kb_n, 1),
            "one_view_per_launch_us_per_frame": round(ts * 1e6 / 64, 2),
+           "one_view_kernel_us_per_launch": round(ks_ms * 1e3 / ks_n, 1),
            "one_view_per_launch_gsamples_per_s": round(comp / ts / 1e9, 3),
            "positions_composited": comp}
     print(json.dumps(out), flush=True)

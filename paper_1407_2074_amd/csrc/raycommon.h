@@ -129,21 +129,18 @@ template <int C>
 __host__ inline void host_build_tables(const DevView &V, ViewTables<C> &tb)
 {
     for (int c = 0; c < C; c++) {
+        float4 e[256];   // every entry once
+        for (int k = 0; k < 256; k++) e[k] = tf_entry(V, c, k);
         int run = 0;
         for (int k = 0; k < 256; k++) {
-            const float4 e0 = tf_entry(V, c, k);
-            const float4 e1 = k < 255 ? tf_entry(V, c, k + 1) : e0;
+            const float4 e0 = e[k], e1 = k < 255 ? e[k + 1] : e0;
             tb.lut[c][k][0] = e0;
             tb.lut[c][k][1] = make_float4(e1.x - e0.x, e1.y - e0.y, e1.z - e0.z, e1.w - e0.w);
             tb.pref[c][k] = run;
             run += e0.w != 0.0f ? 1 : 0;
         }
         tb.pref[c][256] = run;
-        for (int w = 0; w < 4; w++) {
-            int n = 0;
-            for (int k = 64 * w; k < 64 * w + 64; k++) n += tf_entry(V, c, k).w != 0.0f ? 1 : 0;
-            tb.wtot[c][w] = n;
-        }
+        for (int w = 0; w < 4; w++) tb.wtot[c][w] = tb.pref[c][64 * w + 64] - tb.pref[c][64 * w];
     }
 }
 

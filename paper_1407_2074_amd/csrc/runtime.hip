@@ -212,6 +212,8 @@ struct oct_handle {
     std::vector<HCell> cells;
     std::vector<int32_t> free_slots;
     std::vector<std::vector<Box>> dirty;  // per level
+    // transfer-function tables of recent views (control points -> table bytes)
+    std::vector<std::pair<std::vector<float>, std::vector<uint8_t>>> table_cache;
     // tile-group dispatch orders of the last few ordered views (geometry key bytes -> order)
     std::vector<std::pair<std::vector<uint8_t>, std::vector<int32_t>>> order_cache;
     std::string err;
@@ -344,15 +346,39 @@ size_t noalloc_record_bytes()
 }
 
 // Every view's transfer-function tables, built on the host into the launch's records.
-void fill_tables(int C, const DevView *dvs, int n_views, uint8_t *dst, size_t tbytes)
+// Every view's transfer-function tables, built on the host into the launch's records.  The
+// tables depend only on the control points, so the last few distinct ones are kept (views of
+// one request, or of one transfer function, share them); may_insert = false only looks up
+// (the call allocates nothing then).
+void fill_tables(oct_handle *h, const DevView *dvs, int n_views, uint8_t *dst, size_t tbytes,
+                 bool may_insert)
 {
+    const int C = h->g.C;
+    auto &cache = h->table_cache;
     for (int i = 0; i < n_views; i++) {
         uint8_t *t = dst + (size_t)i * tbytes;
+        float key[kMaxC * 40];
+        for (int c = 0; c < C; c++) {
+            std::memcpy(key + c * 40, dvs[i].tf_pos[c], 8 * sizeof(float));
+            std::memcpy(key + c * 40 + 8, dvs[i].tf_rgba[c], 32 * sizeof(float));
+        }
+        const size_t kb = (size_t)C * 40 * sizeof(float);
+        bool hit = false;
+        for (size_t e = 0; e < cache.size() && !hit; e++)
+            if (!std::memcmp(cache[e].first.data(), key, kb)) {
+                std::memcpy(t, cache[e].second.data(), tbytes);
+                hit = true;
+            }
+        if (hit) continue;
         switch (C) {
         case 1: host_build_tables<1>(dvs[i], *(ViewTables<1> *)t); break;
         case 2: host_build_tables<2>(dvs[i], *(ViewTables<2> *)t); break;
         case 3: host_build_tables<3>(dvs[i], *(ViewTables<3> *)t); break;
         default: host_build_tables<4>(dvs[i], *(ViewTables<4> *)t); break;
+        }
+        if (may_insert) {
+            if (cache.size() >= 64) cache.erase(cache.begin());
+            cache.emplace_back(std::vector<float>(key, key + C * 40), std::vector<uint8_t>(t, t + tbytes));
         }
     }
 }
@@ -2491,7 +2517,7 @@ int render_views(oct_handle *h, int32_t n_views, const oct_view *views, float *c
         dvs[i].rwait = (int32_t *)(dp + l.rw_off) + i;
         dvs[i].tables = dp + t_off + (size_t)i * tbytes;
     }
-    fill_tables(h->g.C, dvs.data(), n_views, hp + t_off, tbytes);
+    fill_tables(h, dvs.data(), n_views, hp + t_off, tbytes, true);
     std::memcpy(hp, dvs.data(), l.v_bytes);
     std::memcpy(hp + l.sv_off, split_views.data(), (size_t)pl.n_split * 4);
     std::memcpy(hp + l.rf_off, refine_views.data(), (size_t)pl.n_refine * 4);
@@ -2585,7 +2611,7 @@ int render_views_noalloc(oct_handle *h, int32_t n_views, const oct_view *views,
         }
         dvs[i].rwait = (int32_t *)(dp + l.rw_off) + i;
     }
-    fill_tables(h->g.C, dvs, n_views, hp + t_off, tbytes);
+    fill_tables(h, dvs, n_views, hp + t_off, tbytes, false);
     std::memcpy(hp + l.sv_off, split, (size_t)pl.n_split * 4);
     std::memcpy(hp + l.rf_off, refine, (size_t)pl.n_refine * 4);
     std::memset(hp + l.rw_off, 0, (size_t)n_views * 4);

@@ -144,14 +144,24 @@ def to_oct_views(views) -> np.ndarray:
     a["step"] = [v.step for v in views]
     a["ert_alpha"] = [v.ert_alpha for v in views]
     a["lod"] = [v.lod for v in views]
-    a["n_clip"] = [len(v.clips) for v in views]
-    for k, v in enumerate(views):
-        for i, pl in enumerate(v.clips):
-            a["clip"][k, i] = np.asarray(pl, f32)[:4]
-        C = np.asarray(v.tf_pos).shape[0]
-        a["tf_pos"][k, :C] = v.tf_pos
-        a["tf_rgba"][k, :C] = v.tf_rgba
-        a["window"][k, :C] = v.window
+    nc = [len(v.clips) for v in views]
+    a["n_clip"] = nc
+    if any(nc):             # one fill: every view's planes padded to three
+        pad = (0.0, 0.0, 0.0, 0.0)
+        a["clip"] = np.asarray([[tuple(pl[:4]) for pl in v.clips] + [pad] * (3 - len(v.clips))
+                                for v in views], f32)
+    cs = {len(v.tf_pos) for v in views}
+    if len(cs) == 1:        # one stacked fill per field
+        C = cs.pop()
+        a["tf_pos"][:, :C] = np.asarray([v.tf_pos for v in views], f32)
+        a["tf_rgba"][:, :C] = np.asarray([v.tf_rgba for v in views], f32)
+        a["window"][:, :C] = np.asarray([v.window for v in views], f32)
+    else:
+        for k, v in enumerate(views):
+            C = len(v.tf_pos)
+            a["tf_pos"][k, :C] = v.tf_pos
+            a["tf_rgba"][k, :C] = v.tf_rgba
+            a["window"][k, :C] = v.window
     a["no_skip"] = [getattr(v, "no_skip", 0) for v in views]
     a["depth_segments"] = [getattr(v, "depth_segments", 0) for v in views]
     a["mode"] = [getattr(v, "mode", 0) for v in views]
