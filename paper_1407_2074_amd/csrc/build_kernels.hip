@@ -453,7 +453,9 @@ k_apply_deltas(DevCell *table, float *miss_range, const CellDelta *d, int n)
 #endif
 constexpr int kGatherThreads = OCTRC_GATHER_THREADS;
 
-template <typename T, bool kPaged>
+// kStore: the launch writes whole bricks to the host brick store as well (its own
+// instantiation, so the common one keeps its few registers).
+template <typename T, bool kPaged, bool kStore>
 __global__ void __launch_bounds__(kGatherThreads)
 k_gather(VolGeom g, MasterRef<const T> mr, const DevCell *table, uint8_t *pool, uint64_t brick_bytes,
          const BrickJob *jobs, int n_items, int zsplit, float *part, float background,
@@ -491,9 +493,9 @@ k_gather(VolGeom g, MasterRef<const T> mr, const DevCell *table, uint8_t *pool, 
         mx[c] = -FLT_MAX;
     }
     // slot < 0: the brick goes to the host brick store only (it is not resident)
-    T *dst = job.slot >= 0 ? (T *)(pool + (uint64_t)job.slot * brick_bytes) : nullptr;
+    T *dst = (!kStore || job.slot >= 0) ? (T *)(pool + (uint64_t)job.slot * brick_bytes) : nullptr;
     // whole bricks may also go to the host brick store: C planes of S^3 elements
-    T *sto = (store && job.store >= 0) ? (T *)(store + (uint64_t)job.store * store_bytes) : nullptr;
+    T *sto = (kStore && job.store >= 0) ? (T *)(store + (uint64_t)job.store * store_bytes) : nullptr;
     const int64_t S3 = (int64_t)S * S * S;
     const int nx = job.hi[0] - job.lo[0] + 1, ny = job.hi[1] - job.lo[1] + 1;
     // this workgroup's share of the job's slices
@@ -529,16 +531,17 @@ k_gather(VolGeom g, MasterRef<const T> mr, const DevCell *table, uint8_t *pool, 
                     mx[c] = fmaxf(mx[c], (float)v[c]);
                 }
             const int64_t i = ((int64_t)z * S + y) * S + x;
-            if (dst) {
+            if (!kStore || dst) {
                 if constexpr (sizeof(T) == 2) {
                     *(ushort4 *)(dst + i * 4) = make_ushort4(v[0], v[1], v[2], v[3]);
                 } else {
                     *(float4 *)(dst + i * 4) = make_float4(v[0], v[1], v[2], v[3]);
                 }
             }
-            if (sto)
-                for (int c = 0; c < kMaxC; c++)
-                    if (c < g.C) sto[c * S3 + i] = v[c];
+            if constexpr (kStore)
+                if (sto)
+                    for (int c = 0; c < kMaxC; c++)
+                        if (c < g.C) sto[c * S3 + i] = v[c];
         }
     }
     for (int c = 0; c < g.C; c++) {
@@ -837,9 +840,14 @@ hipError_t launch_gather(const VolGeom &g, const void *master, const DevCell *ta
         constexpr bool kP = decltype(paged)::value;
         const MasterRef<T> m0 = master_ref<T>(g, (void *)master);
         const MasterRef<const T> mr{m0.base, m0.pages};
-        hipLaunchKernelGGL((k_gather<T, kP>), grid, dim3(kGatherThreads), 0, s, g, mr, table,
-                           (uint8_t *)pool, brick_bytes, jobs, items, zsplit, (float *)scratch,
-                           background, store, store_bytes);
+        if (store)
+            hipLaunchKernelGGL((k_gather<T, kP, true>), grid, dim3(kGatherThreads), 0, s, g, mr,
+                               table, (uint8_t *)pool, brick_bytes, jobs, items, zsplit,
+                               (float *)scratch, background, store, store_bytes);
+        else
+            hipLaunchKernelGGL((k_gather<T, kP, false>), grid, dim3(kGatherThreads), 0, s, g, mr,
+                               table, (uint8_t *)pool, brick_bytes, jobs, items, zsplit,
+                               (float *)scratch, background, store, store_bytes);
     });
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
