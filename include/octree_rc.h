@@ -254,8 +254,8 @@ int brick_pool_upload(oct_handle *h, uint64_t byte_budget, void *stream, oct_upl
  * to [height][width][4] float32 for view i; only the tiles [tile_begin, tile_begin+count)
  * are written (for OCT_MISSING_REFINE views only by the pass in which no ray waited).
  * ckpt_ws: NULL, or a device workspace of render_ckpt_bytes() bytes that receives what
- * render_views_backward needs (transmittance checkpoints; for MIP views the position of each
- * channel's maximum).  `out` (may be NULL) returns sample counts; passing it synchronises the
+ * render_views_backward needs (the transmittance before every evaluated position; for MIP
+ * views the position of each channel's maximum).  `out` (may be NULL) returns sample counts; passing it synchronises the
  * stream.  Views of any mode, missing-brick rule and transform may share a launch.
  * Errors: OCT_EINVAL (e.g. a refinement view without refine_state, n_xform other than 0 or
  * C, a refinement view with checkpoints), OCT_EDEVICE. */
@@ -296,14 +296,14 @@ size_t render_refine_bytes(const oct_handle *h, const oct_view *view);
  *   dL_dvoxels device [C][Dz][Dy][Dx] float32 or NULL: gradient w.r.t. the level-0 voxel
  *              values, defined for views with lod 0 on an octree whose level-0 nodes all hold
  *              bricks (threshold 0, everything inserted)
- * DVR views are differentiated through every position (transmittance checkpoints replayed back
- * to front); MIP views through the sample at which each channel first reaches its maximum
+ * DVR views are differentiated through every position (walked back to front with the
+ * transmittances the forward recorded); MIP views through the sample at which each channel first reaches its maximum
  * (with or without channel transforms).  DVR views with channel transforms and views whose
  * missing-brick rule is not OCT_MISSING_AVG are not differentiable here (OCT_EINVAL).
  * The workspace must have been filled by the last render_views call that used it, with the
  * same views, and no upload or clear that changed the octree may come between the two.
  * Ordering: the backward follows every render and backward issued earlier on this handle, on
- * any stream (they share its table-gradient accumulators and replay scratch).
+ * any stream (they share its table-gradient accumulators).
  * Errors: OCT_EINVAL (e.g. voxel gradients requested where not defined, a workspace not filled
  * by a render of this handle, views that differ from the forward's, an octree changed since
  * the forward), OCT_EDEVICE. */

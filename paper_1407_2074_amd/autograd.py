@@ -2,9 +2,9 @@
 
 Gradients of an image loss flow to the transfer-function control-point RGBA values (positions
 fixed) and, for lod-0 views of an octree whose level-0 nodes all hold bricks, to the level-0
-voxel values.  Torch only provides memory, streams and the autograd graph; the forward (with
-transmittance checkpoints every 64 positions) and the adjoint are the HIP kernels behind the
-C ABI.
+voxel values.  Torch only provides memory, streams and the autograd graph; the forward (which
+records the transmittance before every position it evaluates) and the adjoint are the HIP
+kernels behind the C ABI.
 """
 from __future__ import annotations
 

@@ -1,20 +1,19 @@
 // Adjoint of the forward ray caster: gradients of a scalar image loss with respect to the
 // transfer-function control-point RGBA values and to the level-0 voxel values.
 //
-// The forward stored, per ray, the transmittance T before positions 0, 64, 128, ... and the
-// first position it did not evaluate (for a ray split into depth segments: T from the start
-// of the segment, plus each segment's composite, from which a wave walking one segment gets
-// the transmittance in front of it and the colour/opacity behind it).  Per 64-position block,
-// last to first, a lane
-//   1. replays the segment forward from its checkpoint, writing T before each position to a
-//      per-wave scratch area ([position][lane], coalesced), and
-//   2. walks the segment back to front.  With Bc / Ba the colour / opacity of everything
-//      behind an event (as seen with transmittance 1), an event e with transmittance T_e,
-//      opacity a_e and colour rgb_e receives
-//          dL/drgb_e = gC * T_e * a_e
-//          dL/da_e   = T_e * (gC . (rgb_e - Bc) + gA * (1 - Ba))
-//      and then Bc <- a_e rgb_e + (1 - a_e) Bc, Ba <- a_e + (1 - a_e) Ba,
-//      where (gC, gA) = dL/d(pixel RGBA).
+// The forward stored, per ray, the transmittance T before every position it evaluated, T after
+// the last one and the first position it did not evaluate (for a ray split into depth segments:
+// T from the start of the segment, plus each segment's composite, from which a wave walking one
+// segment gets the transmittance in front of it, its transmittance at the end and the
+// colour/opacity behind it).  A lane walks its positions back to front.  A position the forward
+// skipped is transparent in every channel, so T is the same before and after it; before any
+// other position T is the recorded value.  With Bc / Ba the colour / opacity of everything
+// behind an event (as seen with transmittance 1), an event e with transmittance T_e, opacity a_e
+// and colour rgb_e receives
+//     dL/drgb_e = gC * T_e * a_e
+//     dL/da_e   = T_e * (gC . (rgb_e - Bc) + gA * (1 - Ba))
+// and then Bc <- a_e rgb_e + (1 - a_e) Bc, Ba <- a_e + (1 - a_e) Ba,
+// where (gC, gA) = dL/d(pixel RGBA).
 // The event gradient flows into the two table entries it interpolated and through them into at
 // most three consecutive transfer-function control points (summed per lane in registers over a
 // window of three control points, added to an LDS accumulator per workgroup when an event leaves
@@ -243,8 +242,7 @@ template <typename T, int C, bool kVox>
 __global__ void __launch_bounds__(kThreads)
 k_render_backward(VolGeom g, const DevCell *__restrict__ table, const uint8_t *__restrict__ pool,
                   uint64_t brick_bytes, const DevView *__restrict__ views,
-                  const WgItem *__restrict__ items, float *__restrict__ scratch, float *dvox,
-                  float *dctrl)
+                  const WgItem *__restrict__ items, float *dvox, float *dctrl)
 {
     __shared__ ViewTables<C> tb;
     __shared__ float s_dctrl[C][8][4];
@@ -270,7 +268,6 @@ k_render_backward(VolGeom g, const DevCell *__restrict__ table, const uint8_t *_
         ulo[c] = -V.ulo[c] * usc[c];   // table coordinate u = s * usc + ulo
     }
     const float step = V.step;
-    float *wscr = scratch + ((int64_t)blockIdx.x * kThreads + wave * 64) * kCkptStride;
 
     if (wave < it.ntiles) {
         const int tile = it.tile0 + wave;
@@ -289,9 +286,7 @@ k_render_backward(VolGeom g, const DevCell *__restrict__ table, const uint8_t *_
             gA = gi.w;
         }
         const int64_t nvox0 = (int64_t)g.dims[0] * g.dims[1] * g.dims[2];
-        // one cell cache for both walks: the back walk starts where the replay ended
-        Marcher<T, C> mf(g, table, pool, brick_bytes, ray.L);
-        Marcher<T, C> &mb = mf;
+        Marcher<T, C> mb(g, table, pool, brick_bytes, ray.L);
         float Bc[3] = {0.0f, 0.0f, 0.0f}, Ba = 0.0f;
         CubeAcc<C> acc(dvox, nvox0, g.dims);
         // control-point gradients, through the table construction: an event interpolating
@@ -319,9 +314,10 @@ k_render_backward(VolGeom g, const DevCell *__restrict__ table, const uint8_t *_
                     wacc[c][j][q] = 0.0f;
                 }
         };
-        // the checkpoint blocks this wave walks: all of the ray, or the blocks of its depth
-        // segment (the forward split the ray the same way); then T holds the transmittance in
-        // front of the segment and (Bc, Ba) start as the composite of the segments behind it
+        // the 64-position blocks this wave walks: all of the ray, or the blocks of its depth
+        // segment (the forward split the ray the same way); then T_front holds the
+        // transmittance in front of the segment and (Bc, Ba) start as the composite of the
+        // segments behind it
         const int nb = (n_end + kCkptStride - 1) / kCkptStride;
         int b_lo = 0, b_hi = nb;
         float T_front = 1.0f;
@@ -342,29 +338,16 @@ k_render_backward(VolGeom g, const DevCell *__restrict__ table, const uint8_t *_
                 Ba = 1.0f - Tb;
             }
         }
-        for (int sg = b_hi - 1; sg >= b_lo; sg--) {
-            const int k0 = sg * kCkptStride;
-            const int k1 = min(k0 + kCkptStride, n_end);
-            // 1. forward replay: transmittance before each position of the segment
-            float Tr = T_front * V.ckpt[pix * V.nseg + sg];
-            for (int k = k0; k < k1; k++) {
-                const float tk = ray.t0 + (float)k * step;
-                if (!(tk < ray.t1)) break;
-                float p[3];
-                for (int q = 0; q < 3; q++) {
-                    const float m = tk * ray.d[q];
-                    p[q] = ray.o[q] + m;
-                }
-                wscr[(k - k0) * 64 + lane] = Tr;
-                Sample<C> sm;
-                mf.sample(p, sm);
-                for (int c = 0; c < C; c++) {
-                    const Classified q = classify(sm.s[c], ulo[c], usc[c], tb.lut[c]);
-                    Tr = Tr - Tr * __builtin_fmaf(q.fr, q.de.w, q.e0.w);
-                }
-            }
-            // 2. back-to-front walk
-            for (int k = k1 - 1; k >= k0; k--) {
+        // positions of this wave, walked back to front; Tn: the transmittance after the
+        // current position (after the walk's last position to begin with)
+        const int64_t npix = (int64_t)V.width * V.height;
+        const int k_lo = b_lo * kCkptStride, k_hi = min(b_hi * kCkptStride, n_end);
+        float Tn = 0.0f;
+        if (k_hi > k_lo)
+            Tn = V.nsplit > 1 ? T_front * V.part[((int64_t)it.seg * npix + pix) * 4 + 3]
+                              : V.ckpt[(int64_t)n_end * npix + pix];
+        {
+            for (int k = k_hi - 1; k >= k_lo; k--) {
                 const float tk = ray.t0 + (float)k * step;
                 if (!(tk < ray.t1)) continue;
                 float p[3];
@@ -376,19 +359,27 @@ k_render_backward(VolGeom g, const DevCell *__restrict__ table, const uint8_t *_
                 mb.sample(p, sm);
                 Classified cq[C];
                 float rgba[C][4], Tc[C];
-                float Tp = wscr[(k - k0) * 64 + lane];
                 if (kVox && sm.brick) {
                     // the corner cube of this sample (level-0 index of its lower corner)
                     const int kx = sm.org[0] + sm.ii[0], ky = sm.org[1] + sm.ii[1],
                               kz = sm.org[2] + sm.ii[2];
                     if (kx != acc.kx || ky != acc.ky || kz != acc.kz) acc.move_to(kx, ky, kz);
                 }
+                bool opaque = false;
                 for (int c = 0; c < C; c++) {
                     cq[c] = classify(sm.s[c], ulo[c], usc[c], tb.lut[c]);
                     rgba[c][0] = __builtin_fmaf(cq[c].fr, cq[c].de.x, cq[c].e0.x);
                     rgba[c][1] = __builtin_fmaf(cq[c].fr, cq[c].de.y, cq[c].e0.y);
                     rgba[c][2] = __builtin_fmaf(cq[c].fr, cq[c].de.z, cq[c].e0.z);
                     rgba[c][3] = __builtin_fmaf(cq[c].fr, cq[c].de.w, cq[c].e0.w);
+                    opaque |= rgba[c][3] != 0.0f;
+                }
+                // the transmittance before this position: recorded by the forward, or, for a
+                // position transparent in every channel (the forward may have skipped it), the
+                // one after it
+                float Tp = opaque ? T_front * V.ckpt[(int64_t)k * npix + pix] : Tn;
+                Tn = Tp;
+                for (int c = 0; c < C; c++) {
                     Tc[c] = Tp;
                     Tp = Tp - Tp * rgba[c][3];
                 }
@@ -642,7 +633,7 @@ __global__ void k_lut_to_ctrl(const DevView *views, int n_views, int C, float *d
 template <typename T>
 hipError_t launch_bw_typed(const VolGeom &g, const DevCell *table, const void *pool,
                            uint64_t brick_bytes, const DevView *views, const WgItem *items,
-                           int n_items, float *scratch, float *dvox, float *dctrl, hipStream_t s)
+                           int n_items, float *dvox, float *dctrl, hipStream_t s)
 {
     const dim3 grid(n_items), block(kThreads);
     const uint8_t *p = (const uint8_t *)pool;
@@ -650,10 +641,10 @@ hipError_t launch_bw_typed(const VolGeom &g, const DevCell *table, const void *p
     do {                                                                                          \
         if (dvox)                                                                                 \
             hipLaunchKernelGGL((k_render_backward<TT, CC, true>), grid, block, 0, s, g, table, p,  \
-                               brick_bytes, views, items, scratch, dvox, dctrl);                  \
+                               brick_bytes, views, items, dvox, dctrl);                           \
         else                                                                                      \
             hipLaunchKernelGGL((k_render_backward<TT, CC, false>), grid, block, 0, s, g, table, p, \
-                               brick_bytes, views, items, scratch, dvox, dctrl);                  \
+                               brick_bytes, views, items, dvox, dctrl);                           \
     } while (0)
     switch (g.C) {
     case 1: OCTRC_BW(T, 1); break;
@@ -669,15 +660,14 @@ hipError_t launch_bw_typed(const VolGeom &g, const DevCell *table, const void *p
 
 hipError_t launch_render_backward(const VolGeom &g, const DevCell *table, const void *pool,
                                   uint64_t brick_bytes, const DevView *views, const WgItem *items,
-                                  int n_items, float *scratch, float *dvox, float *dctrl,
-                                  hipStream_t s)
+                                  int n_items, float *dvox, float *dctrl, hipStream_t s)
 {
     if (n_items == 0) return hipSuccess;
     if (g.dtype == 0)
-        return launch_bw_typed<uint16_t>(g, table, pool, brick_bytes, views, items, n_items, scratch,
-                                         dvox, dctrl, s);
-    return launch_bw_typed<float>(g, table, pool, brick_bytes, views, items, n_items, scratch, dvox,
-                                  dctrl, s);
+        return launch_bw_typed<uint16_t>(g, table, pool, brick_bytes, views, items, n_items, dvox,
+                                         dctrl, s);
+    return launch_bw_typed<float>(g, table, pool, brick_bytes, views, items, n_items, dvox, dctrl,
+                                  s);
 }
 
 hipError_t launch_render_backward_mip(const VolGeom &g, const DevCell *table, const void *pool,

@@ -112,11 +112,13 @@ struct DevView {
     float tf_pos[kMaxC][8];
     float tf_rgba[kMaxC][8][4];
     float *image;
-    // checkpoint workspace of this view (NULL: none): the transmittance before positions
-    // 0, 64, 128, ... of every ray ([pixel][nseg]) and the first position not evaluated
+    // checkpoint workspace of this view (NULL: none): the transmittance before every
+    // evaluated position k of every ray ([k][pixel], k < npos; from the start of the ray's depth
+    // segment), after the last one (at k = the end position, rays not split), and the first
+    // position not evaluated
     float *ckpt;
     int32_t *nend;
-    int32_t nseg;
+    int32_t npos;
     // forward without early termination or checkpoints: each ray is marched as nsplit depth
     // segments by different waves; segment s of a ray with n positions takes positions
     // [n s / nsplit, n (s+1) / nsplit) and writes (C, T) to part[s][pixel]; a combine pass
@@ -240,7 +242,7 @@ hipError_t launch_fill_f32(float *p, int64_t n, float v, hipStream_t s);
 hipError_t launch_fill_u8(uint8_t *p, int64_t n, uint8_t v, hipStream_t s);
 
 // ---- launchers (render path) ----
-constexpr int kCkptStride = 64;   // positions per transmittance checkpoint segment
+constexpr int kCkptStride = 64;   // depth segments of differentiable renders: whole blocks of this many positions
 
 // flags (may be NULL): per node-table cell, set to 1 when a render interpolated the cell's
 // resident brick and to 2 when it needed the cell's brick but found it missing.
@@ -266,12 +268,11 @@ hipError_t launch_view_mask(const VolGeom &g, const DevView *views, int n_views,
 // modes: bit 0 = some split view is DVR, bit 1 = some split view is MIP.
 hipError_t launch_combine(const DevView *views, const int32_t *split_views, int n_split,
                           int C, int modes, int64_t max_pixels, hipStream_t s);
-// Adjoint of DVR views: scratch holds kCkptStride floats per lane of the launch (n_items * 512
-// lanes); control-point gradients are added to dctrl [view][C][8][4] (views' user_index).
+// Adjoint of DVR views (from the transmittances their forward recorded); control-point
+// gradients are added to dctrl [view][C][8][4] (views' user_index).
 hipError_t launch_render_backward(const VolGeom &g, const DevCell *table, const void *pool,
                                   uint64_t brick_bytes, const DevView *views, const WgItem *items,
-                                  int n_items, float *scratch, float *dvox, float *dctrl,
-                                  hipStream_t s);
+                                  int n_items, float *dvox, float *dctrl, hipStream_t s);
 // Adjoint of MIP views: one lane per pixel, through the samples at the recorded maxima.
 hipError_t launch_render_backward_mip(const VolGeom &g, const DevCell *table, const void *pool,
                                       uint64_t brick_bytes, const DevView *views,

@@ -149,7 +149,7 @@ render_body(const VolGeom &g, const DevCell *__restrict__ table, const uint8_t *
         nominal = kk;
     }
     // segment s of a split ray: positions [n s / S, n (s+1) / S) of its n positions; when
-    // checkpoints are written the bounds are whole 64-position blocks instead, blocks
+    // transmittances are recorded the bounds are whole 64-position blocks instead, blocks
     // [nb s / S, nb (s+1) / S) of nb = ceil(n / 64), as the adjoint walks them
     int k_begin = 0, k_end = nominal;
     if (split && ckpt) {
@@ -163,7 +163,8 @@ render_body(const VolGeom &g, const DevCell *__restrict__ table, const uint8_t *
 
     // transmittance and colour from the segment's start (the whole ray when not split)
     float Tr = 1.0f, Cr = 0.0f, Cg = 0.0f, Cb = 0.0f;
-    int k = k_begin, composited = 0, trilinear = 0, next_ck = k_begin;
+    int k = k_begin, composited = 0, trilinear = 0;
+    const int64_t npix_ck = (int64_t)V.width * V.height;
     // How a position is found to lie in the cached cell. u16 bricks test the brick coordinates
     // of every position (few instructions, no per-cell set-up). f32 bricks keep the range of
     // positions k_lo..k_hi that lie at least 1/64 voxel inside the cell (and one step away from
@@ -222,11 +223,9 @@ render_body(const VolGeom &g, const DevCell *__restrict__ table, const uint8_t *
     while (live) {
         if (k >= k_end) break;
         const float tk = t0 + (float)k * step;
-        if (ckpt) {
-            // transmittance before every 64th position (unchanged across skipped positions)
-            for (; next_ck <= k; next_ck += kCkptStride)
-                ckpt[pix * V.nseg + next_ck / kCkptStride] = Tr;
-        }
+        // transmittance before every evaluated position (positions skipped as transparent
+        // keep it unchanged, and the adjoint carries it across them)
+        if (ckpt) ckpt[(int64_t)k * npix_ck + pix] = Tr;
         float p[3];
 #pragma unroll
         for (int q = 0; q < 3; q++) {
@@ -478,11 +477,9 @@ render_body(const VolGeom &g, const DevCell *__restrict__ table, const uint8_t *
         // ray (a skip may have jumped past it); a split ray (no early termination) ends at n
         const int n_end = ray.hit ? (live ? nominal : k) : 0;
         if (V.nend && it.seg == 0) V.nend[pix] = n_end;
-        // checkpoint blocks that begin inside a final skipped run keep the transmittance of
-        // the jump (split: up to the end of this segment's blocks)
-        if (ckpt)
-            for (; next_ck < min(n_end, k_end); next_ck += kCkptStride)
-                ckpt[pix * V.nseg + next_ck / kCkptStride] = Tr;
+        // and the transmittance after the last evaluated position (a split ray's segment keeps
+        // it in its partial result)
+        if (ckpt && !split) ckpt[(int64_t)n_end * npix_ck + pix] = Tr;
     }
     if (kCount && counters) {
         const bool first = it.seg == 0;   // rays and nominal positions counted once

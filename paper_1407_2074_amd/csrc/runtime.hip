@@ -2179,16 +2179,16 @@ static bool view_differentiable(const oct_view &v)
     return v.mode == OCT_MODE_MIP || v.n_xform == 0;
 }
 
-// Checkpoint workspace: per view, [pixel][nseg] float32 transmittances then [pixel] int32
-// end positions; nseg covers the longest possible ray (the box diagonal) in 64-position
-// segments.  MIP views hold [pixel][4] int32 positions of the channel maxima instead.
-static int view_nseg(const oct_handle *h, const oct_view &v)
+// Checkpoint workspace: per view, [position][pixel] float32 transmittances then [pixel] int32
+// end positions; the positions cover the longest possible ray (the box diagonal) plus the end
+// position.  MIP views hold [pixel][4] int32 positions of the channel maxima instead.
+static int view_npos(const oct_handle *h, const oct_view &v)
 {
     const double diag = std::sqrt((double)h->g.dims[0] * h->g.dims[0] +
                                   (double)h->g.dims[1] * h->g.dims[1] +
                                   (double)h->g.dims[2] * h->g.dims[2]);
     const double nmax = std::ceil(diag / (double)v.step) + 2.0;
-    return (int)std::ceil(nmax / kCkptStride);
+    return (int)nmax + 1;
 }
 
 // Depth segments of a view's rays; the forward, the differentiable forward and the adjoint
@@ -2206,13 +2206,14 @@ static int view_segments(const oct_handle *h, const oct_view &v)
     return auto_segments(h->g, v);
 }
 
-// Checkpoint workspace of one view: [pixel][nseg] float32 transmittance before each block of
-// 64 positions (from the start of the block's depth segment), [pixel] int32 end positions,
-// then for a split view [segment][pixel] float4 (C, T) of every depth segment.
+// Checkpoint workspace of one view: [position][pixel] float32 transmittance before each
+// evaluated position (from the start of its depth segment) and, for rays not split, after the
+// last one; [pixel] int32 end positions; then for a split view [segment][pixel] float4 (C, T)
+// of every depth segment.
 static size_t view_ckpt_part_offset(const oct_handle *h, const oct_view &v)
 {
     const size_t npix = (size_t)v.width * v.height;
-    return (npix * (size_t)view_nseg(h, v) * 4 + npix * 4 + 15) & ~(size_t)15;
+    return (npix * (size_t)view_npos(h, v) * 4 + npix * 4 + 15) & ~(size_t)15;
 }
 
 static size_t view_ckpt_bytes(const oct_handle *h, const oct_view &v)
@@ -2390,9 +2391,9 @@ static int plan_launch(oct_handle *h, int32_t n_views, const oct_view *views,
             if (ws && views[i].mode == OCT_MODE_MIP) {
                 dv.amax = (int32_t *)ws;
             } else if (ws) {
-                dv.nseg = view_nseg(h, views[i]);
+                dv.npos = view_npos(h, views[i]);
                 dv.ckpt = (float *)ws;
-                dv.nend = (int32_t *)(ws + npix * dv.nseg * 4);
+                dv.nend = (int32_t *)(ws + npix * dv.npos * 4);
             }
             const int tiles = dv.tiles_x * ((views[i].height + OCT_TILE - 1) / OCT_TILE);
             const int tb = std::min(views[i].tile_begin, tiles);
@@ -2655,7 +2656,7 @@ int render_views_backward(oct_handle *h, int32_t n_views, const oct_view *views,
         return fail(h, OCT_EINVAL, "backward needs views, dL/dimages, the forward workspace and dL/dctrl");
     const VolGeom &g = h->g;
     {
-        // the replay must see the octree and the views that the forward's checkpoints came from
+        // the backward must see the octree and the views that the forward's record came from
         const CkptRec *r = nullptr;
         for (const auto &e : h->ckpt_log)
             if (e.ws == ckpt_ws) r = &e;
@@ -2715,9 +2716,9 @@ int render_views_backward(oct_handle *h, int32_t n_views, const oct_view *views,
             }
             continue;
         }
-        dvs[i].nseg = view_nseg(h, views[i]);
+        dvs[i].npos = view_npos(h, views[i]);
         dvs[i].ckpt = (float *)((uint8_t *)ckpt_ws + ck_off);
-        dvs[i].nend = (int32_t *)((uint8_t *)ckpt_ws + ck_off + npix * dvs[i].nseg * 4);
+        dvs[i].nend = (int32_t *)((uint8_t *)ckpt_ws + ck_off + npix * dvs[i].npos * 4);
         ck_off += view_ckpt_bytes(h, views[i]);
         const int tiles = dvs[i].tiles_x * ((views[i].height + OCT_TILE - 1) / OCT_TILE);
         const int tb = std::min(views[i].tile_begin, tiles);
@@ -2740,10 +2741,9 @@ int render_views_backward(oct_handle *h, int32_t n_views, const oct_view *views,
                     items.push_back(w);
                 }
     }
-    // device temporaries: per-view table gradients, then the replay scratch
+    // device temporaries: per-view table gradients (MIP views)
     const size_t dl_bytes = ((size_t)n_views * dlut_floats * 4 + 255) & ~(size_t)255;
-    const size_t scr_bytes = items.size() * (size_t)kRenderTilesPerWg * 64 * kCkptStride * 4;
-    if (dl_bytes + scr_bytes > h->bw_tmp_cap) {
+    if (dl_bytes > h->bw_tmp_cap) {
         // an earlier backward on any stream may still use the temporaries
         for (auto &r : h->rs)
             if (r.st.ev) HIPCHK(h, hipEventSynchronize(r.st.ev));
@@ -2751,8 +2751,8 @@ int render_views_backward(oct_handle *h, int32_t n_views, const oct_view *views,
         if (h->bw_tmp) HIPCHK(h, hipFree(h->bw_tmp));
         h->bw_tmp = nullptr;
         h->bw_tmp_cap = 0;
-        HIPCHK(h, hipMalloc(&h->bw_tmp, dl_bytes + scr_bytes));
-        h->bw_tmp_cap = dl_bytes + scr_bytes;
+        HIPCHK(h, hipMalloc(&h->bw_tmp, dl_bytes));
+        h->bw_tmp_cap = dl_bytes;
     }
     float *dlut = (float *)h->bw_tmp;
     for (int i = 0; i < n_views; i++) dvs[i].dlut = dlut + (size_t)i * dlut_floats;
@@ -2772,7 +2772,7 @@ int render_views_backward(oct_handle *h, int32_t n_views, const oct_view *views,
     std::memcpy(hp + i_off, items.data(), i_bytes);
     HIPCHK(h, hipMemcpyAsync(rs.st.dev, hp, i_off + i_bytes, hipMemcpyHostToDevice, s));
     // the forward that wrote the checkpoints and every earlier backward (which shared the
-    // table-gradient accumulators and the replay scratch) may run on other streams: wait for
+    // table-gradient accumulators) may run on other streams: wait for
     // the last launch of every render slot (a slot's older launches ended before its reuse)
     rc = wait_for(h, s, h->ev_upload);
     if (!rc) rc = wait_for_renders(h, s);
@@ -2780,8 +2780,7 @@ int render_views_backward(oct_handle *h, int32_t n_views, const oct_view *views,
     if (!mip_items.empty()) HIPCHK(h, launch_fill_f32(dlut, (int64_t)n_views * dlut_floats, 0.0f, s));
     uint8_t *dp = (uint8_t *)rs.st.dev;
     HIPCHK(h, launch_render_backward(g, h->table, h->pool, h->brick_bytes, (const DevView *)dp,
-                                     (const WgItem *)(dp + i_off), (int)n_dvr_items,
-                                     (float *)((uint8_t *)h->bw_tmp + dl_bytes), dL_dvoxels,
+                                     (const WgItem *)(dp + i_off), (int)n_dvr_items, dL_dvoxels,
                                      dL_dctrl, s));
     HIPCHK(h, launch_render_backward_mip(g, h->table, h->pool, h->brick_bytes, (const DevView *)dp,
                                          (const WgItem *)(dp + i_off) + n_dvr_items,
