@@ -303,7 +303,7 @@ def main():
     if not args.no_adjoint:
         out["adjoint"] = {k: v for k, v in measure_adjoint(args).items()
                           if k in ("value", "unit", "forward_ms", "adjoint_ms", "adjoint_tf_only_ms",
-                                   "config")}
+                                   "kernel_ms", "config")}
     final_img = img.clone()
     if not args.no_build:
         out["mip"] = measure_mip(tree, cfg, args)
@@ -549,6 +549,15 @@ def measure_adjoint(args) -> dict:
     tf = _sync_time(fwd, args.steps)
     tb = _sync_time(bwd, args.steps)
     tb_tf = _sync_time(bwd_tf_only, args.steps)
+    # kernel time alone (HIP events around the ray-casting / adjoint kernel of each call); the
+    # wall times above also hold each call's record copy and host work between kernels
+    kms = {}
+    for name, fn in (("forward", fwd), ("adjoint", bwd), ("adjoint_tf_only", bwd_tf_only)):
+        t.render_timing(True)
+        for _ in range(args.steps):
+            fn()
+        ms, n = t.render_timing(False)
+        kms[name] = round(ms / max(n, 1), 3)
     nom, comp = st["positions_nominal"], st["positions_composited"]
     out = {"metric": "adjoint Gsamples/s", "value": round(nom / (tf + tb) / 1e9, 3),
            "unit": "Gsamples/s (nominal positions per forward+adjoint)", "n_gpus": 1,
@@ -559,6 +568,7 @@ def measure_adjoint(args) -> dict:
                                   "perturbed-TF target; forward with checkpoints + adjoint"},
            "forward_ms": round(tf * 1e3, 3), "adjoint_ms": round(tb * 1e3, 3),
            "adjoint_tf_only_ms": round(tb_tf * 1e3, 3),
+           "kernel_ms": kms,
            "forward_gsamples_per_s": round(comp / tf / 1e9, 3),
            "adjoint_gsamples_per_s": round(nom / tb / 1e9, 3),
            "positions_nominal": nom, "positions_composited": comp,

@@ -339,8 +339,9 @@ int octree_info(const oct_handle *h, int32_t *levels, uint64_t *brick_bytes,
 /* Render-kernel timing, for measurement.  Each call waits for the renders recorded so far and
  * returns in *total_ms / *launches (either may be NULL) their summed ray-casting kernel time
  * and count; then enable = 1 clears the totals and (re)starts recording -- every later
- * render_views records HIP events around its ray-casting kernel on the call's stream -- and
- * enable = 0 stops recording.  The table and combine passes of a render are not included.
+ * render_views records HIP events around its ray-casting kernel on the call's stream, and
+ * every later render_views_backward around its kernel for DVR views -- and enable = 0 stops
+ * recording.  The table and combine passes of a render are not included.
  * Errors: OCT_EINVAL, OCT_EDEVICE. */
 int octree_render_timing(oct_handle *h, int32_t enable, double *total_ms, uint64_t *launches);
 

@@ -246,7 +246,7 @@ k_render_backward(VolGeom g, const DevCell *__restrict__ table, const uint8_t *_
 {
     __shared__ ViewTables<C> tb;
     __shared__ float s_dctrl[C][8][4];
-    __shared__ int s_segj[C][256];     // table entry k = (1 - f) ctrl[j] + f ctrl[j + 1]
+    __shared__ uint8_t s_segj[C][256];   // table entry k = (1 - f) ctrl[j] + f ctrl[j + 1], j < 8
     __shared__ float s_segf[C][256];
 
     const WgItem it = items[blockIdx.x];

@@ -67,6 +67,7 @@ struct RenderSlot {
     bool k_pending = false;
     int64_t version = -1;   // node-table version the slot's last launch read
     hipEvent_t prep = nullptr;   // end of the launch's preparation on the handle's prep stream
+    hipStream_t stream = nullptr;   // the stream of the slot's last launch (st.ev recorded on it)
 };
 
 // Default depth segments per ray for views without early termination or checkpoints: the
@@ -297,10 +298,18 @@ int collect_kernel_time(oct_handle *h, RenderSlot &r)
     return OCT_OK;
 }
 
+// A slot needs no wait when its last launch was on s itself (stream order; a stream is not
+// destroyed while work on it is pending, so a later stream at the same address follows it) or
+// has ended.  Each wait left out is a barrier the GPU does not process between launches.
+static bool slot_pending_for(const RenderSlot &r, hipStream_t s)
+{
+    return r.st.ev && r.stream != s && hipEventQuery(r.st.ev) != hipSuccess;
+}
+
 int wait_for_renders(oct_handle *h, hipStream_t s)
 {
     for (auto &r : h->rs)
-        if (r.st.ev) HIPCHK(h, hipStreamWaitEvent(s, r.st.ev, 0));
+        if (slot_pending_for(r, s)) HIPCHK(h, hipStreamWaitEvent(s, r.st.ev, 0));
     return OCT_OK;
 }
 
@@ -310,7 +319,7 @@ int wait_for_renders(oct_handle *h, hipStream_t s)
 int wait_for_renders_before(oct_handle *h, hipStream_t s, int64_t v)
 {
     for (auto &r : h->rs)
-        if (r.st.ev && r.version < v) HIPCHK(h, hipStreamWaitEvent(s, r.st.ev, 0));
+        if (r.version < v && slot_pending_for(r, s)) HIPCHK(h, hipStreamWaitEvent(s, r.st.ev, 0));
     return OCT_OK;
 }
 
@@ -2556,6 +2565,7 @@ int render_views(oct_handle *h, int32_t n_views, const oct_view *views, float *c
         collect_stats(hp, l, n_views, out);
     }
     HIPCHK(h, hipEventRecord(rs.st.ev, s));
+    rs.stream = s;
     if (ckpt_ws) ckpt_log_put(h, ckpt_ws, n_views, views);
     return OCT_OK;
 }
@@ -2643,6 +2653,7 @@ int render_views_noalloc(oct_handle *h, int32_t n_views, const oct_view *views,
         collect_stats(hp, l, n_views, out);
     }
     HIPCHK(h, hipEventRecord(rs.st.ev, s));
+    rs.stream = s;
     if (ckpt_ws) ckpt_log_put(h, ckpt_ws, n_views, views);
     return OCT_OK;
 }
@@ -2765,29 +2776,44 @@ int render_views_backward(oct_handle *h, int32_t n_views, const oct_view *views,
     RenderSlot &rs = h->rs[h->next_rs];
     h->next_rs = (h->next_rs + 1) % kRenderSlots;
     int rc = stage_reserve(h, rs.st, i_off + i_bytes);
+    if (!rc) rc = collect_kernel_time(h, rs);
     if (rc) return rc;
     rs.version = h->version;
     uint8_t *hp = (uint8_t *)rs.st.host;
     std::memcpy(hp, dvs.data(), v_bytes);
     std::memcpy(hp + i_off, items.data(), i_bytes);
-    HIPCHK(h, hipMemcpyAsync(rs.st.dev, hp, i_off + i_bytes, hipMemcpyHostToDevice, s));
+    // the record copy runs on the prep stream, so that it overlaps the work queued before it
+    if (!rs.prep) HIPCHK(h, hipEventCreateWithFlags(&rs.prep, hipEventDisableTiming));
+    HIPCHK(h, hipMemcpyAsync(rs.st.dev, hp, i_off + i_bytes, hipMemcpyHostToDevice, h->prep));
+    HIPCHK(h, hipEventRecord(rs.prep, h->prep));
     // the forward that wrote the checkpoints and every earlier backward (which shared the
     // table-gradient accumulators) may run on other streams: wait for
     // the last launch of every render slot (a slot's older launches ended before its reuse)
-    rc = wait_for(h, s, h->ev_upload);
+    rc = wait_for(h, s, rs.prep);
+    if (!rc) rc = wait_for(h, s, h->ev_upload);
     if (!rc) rc = wait_for_renders(h, s);
     if (rc) return rc;
     if (!mip_items.empty()) HIPCHK(h, launch_fill_f32(dlut, (int64_t)n_views * dlut_floats, 0.0f, s));
     uint8_t *dp = (uint8_t *)rs.st.dev;
+    if (h->ktime && n_dvr_items) {
+        if (!rs.k0) HIPCHK(h, hipEventCreate(&rs.k0));
+        if (!rs.k1) HIPCHK(h, hipEventCreate(&rs.k1));
+        HIPCHK(h, hipEventRecord(rs.k0, s));
+    }
     HIPCHK(h, launch_render_backward(g, h->table, h->pool, h->brick_bytes, (const DevView *)dp,
                                      (const WgItem *)(dp + i_off), (int)n_dvr_items, dL_dvoxels,
                                      dL_dctrl, s));
+    if (h->ktime && n_dvr_items) {
+        HIPCHK(h, hipEventRecord(rs.k1, s));
+        rs.k_pending = true;
+    }
     HIPCHK(h, launch_render_backward_mip(g, h->table, h->pool, h->brick_bytes, (const DevView *)dp,
                                          (const WgItem *)(dp + i_off) + n_dvr_items,
                                          (int)mip_items.size(), dL_dvoxels, s));
     // MIP views accumulate table gradients (V.dlut); DVR views add to dL/dctrl directly
     if (!mip_items.empty()) HIPCHK(h, launch_lut_to_ctrl((const DevView *)dp, n_views, g.C, dL_dctrl, s));
     HIPCHK(h, hipEventRecord(rs.st.ev, s));
+    rs.stream = s;
     return OCT_OK;
 }
 
