@@ -281,7 +281,11 @@ int render_views(oct_handle *h, int32_t n_views, const oct_view *views, float *c
 int render_views_noalloc(oct_handle *h, int32_t n_views, const oct_view *views,
                          float *const *images, void *ckpt_ws, void *stream, oct_render_stats *out);
 
-/* Bytes of checkpoint workspace render_views needs for these views (0 on bad arguments). */
+/* Bytes of checkpoint workspace render_views needs for these views (0 on bad arguments):
+ * for a DVR view about 4 bytes per pixel per position of the longest possible ray (the volume
+ * diagonal over the step, plus 3) plus 4 per pixel, and 16 per pixel per depth segment when
+ * its rays are split (0.93 GB for 512x512 pixels over a 256^3 volume at step 0.5); for a MIP
+ * view 16 per pixel. */
 size_t render_ckpt_bytes(const oct_handle *h, int32_t n_views, const oct_view *views);
 
 /* Bytes of refinement state for one view (32 per pixel; 0 on bad arguments).  The state holds
