@@ -442,6 +442,13 @@ def measure_disk(slabs, cfg, args, want, composited, hbm_ms_per_step) -> dict:
         s1 = t.disk_stats()
         err = float((img - want).abs().max().item())
         t.close()
+        # the same with the frames in device memory (pages copied through a staging page)
+        td = Octree(dims, C, M, "u16", background=0, threshold=cfg["thr"], disk_path=path,
+                    host_cache_bytes=frames * page_bytes, page_cells=page_cells, device_frames=True)
+        el_dev = timed(td)
+        err_dev = float((img - want).abs().max().item())
+        sd = td.disk_stats()
+        td.close()
         # the same step with the whole mipmap in pinned host memory: what the kernels' traffic
         # over the host link costs without the page file
         th = Octree(dims, C, M, "u16", background=0, threshold=cfg["thr"], master_on_host=True)
@@ -455,7 +462,8 @@ def measure_disk(slabs, cfg, args, want, composited, hbm_ms_per_step) -> dict:
         "config": (f"streamed build+render {dims[0]}x{dims[1]}x{dims[2]}x{C} u16, {M}^3 bricks, "
                    f"{len(slabs)} batches of {cfg['batch']} slices, one {cfg['width']}x"
                    f"{cfg['height']} view per batch; mipmap in {n_pages} pages of {P}^3 voxels "
-                   f"({page_bytes / 2**20:.1f} MiB) in a file on {_fs_type(tmp)}, {frames} RAM frames"),
+                   f"({page_bytes / 2**20:.1f} MiB) in a file on {_fs_type(tmp)}, {frames} frames in "
+                   f"pinned host memory (device_frames: in device memory)"),
         "ms_per_step": round(el * 1e3, 2),
         "gsamples_per_s": round(composited / el / 1e9, 3),
         "hbm_master_ms_per_step": round(hbm_ms_per_step, 2),
@@ -464,6 +472,10 @@ def measure_disk(slabs, cfg, args, want, composited, hbm_ms_per_step) -> dict:
         "file_read_gb_per_s": round(d["bytes_read"] / el / 1e9, 3),
         "file_write_gb_per_s": round(d["bytes_written"] / el / 1e9, 3),
         "final_image_max_abs_diff_vs_hbm_master": err,
+        "device_frames": {"ms_per_step": round(el_dev * 1e3, 2),
+                          "gsamples_per_s": round(composited / el_dev / 1e9, 3),
+                          "loads_two_steps": sd["loads"], "writebacks_two_steps": sd["writebacks"],
+                          "final_image_max_abs_diff_vs_hbm_master": err_dev},
     }
 
 

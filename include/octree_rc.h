@@ -97,13 +97,12 @@ typedef struct {
                                    written by the kernels over the host link;
                                    OCT_MASTER_DISK (2): the disk tier ("Brick Upload from
                                    Disk to RAM", Fig. 5): the levels are cut into pages of
-                                   page_cells^3 cells, stored in the file disk_path; RAM
-                                   holds an LRU set of host_cache_bytes of them (pinned,
-                                   accessed by the kernels over the host link).  A page
-                                   modified by insertion is written back before its RAM
-                                   frame is reused; a page that device work in flight still
-                                   uses is not removed (the call waits for that work).
-                                   Needs M a power of two.                                 */
+                                   page_cells^3 cells, stored in the file disk_path; an LRU
+                                   set of host_cache_bytes of them is held in frames (see
+                                   disk_frames).  A page modified by insertion is written
+                                   back before its frame is reused; a page that device work
+                                   in flight still uses is not removed (the call waits for
+                                   that work).  Needs M a power of two.                    */
     int32_t page_cells;         /* disk tier: cells per page edge, a power of two >= 2
                                    (0: 2); a page holds M*page_cells voxels per edge, all
                                    channels                                               */
@@ -112,9 +111,16 @@ typedef struct {
                                    the paper's brick pool in RAM), so that a brick paged in
                                    again is copied as one contiguous block instead of being
                                    gathered from the mipmap.  Needs a capped device pool.   */
-    int32_t reserved[1];        /* must be 0                                              */
-    uint64_t host_cache_bytes;  /* disk tier: RAM for pages; must hold at least 16 pages
-                                   (or every page)                                        */
+    int32_t disk_frames;        /* disk tier: where its page frames live.
+                                   OCT_FRAMES_HOST (0): pinned host memory (the paper's RAM
+                                   tier), read and written by the kernels over the host link;
+                                   OCT_FRAMES_DEVICE (1): device memory; a page moves between
+                                   the file and its frame through a pinned staging page, and
+                                   the kernels read and write frames in HBM.  Must be 0
+                                   without the disk tier.                                  */
+    uint64_t host_cache_bytes;  /* disk tier: bytes of page frames (host or device memory,
+                                   see disk_frames); must hold at least 16 pages (or every
+                                   page)                                                  */
     const char *disk_path;      /* disk tier: the page file, created (truncated) by
                                    octree_create and removed by octree_destroy            */
 } oct_create_params;
@@ -122,6 +128,8 @@ typedef struct {
 #define OCT_MASTER_HBM 0
 #define OCT_MASTER_HOST 1
 #define OCT_MASTER_DISK 2
+#define OCT_FRAMES_HOST 0
+#define OCT_FRAMES_DEVICE 1
 
 /* Counters of the disk tier since octree_create (octree_disk_stats). */
 typedef struct {

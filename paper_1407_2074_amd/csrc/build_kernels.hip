@@ -934,6 +934,14 @@ hipError_t launch_fill_u8(uint8_t *p, int64_t n, uint8_t v, hipStream_t s)
     return hipGetLastError();
 }
 
+hipError_t launch_fill_u16(uint16_t *p, int64_t n, uint16_t v, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill<uint16_t>, dim3((unsigned)std::min<int64_t>(ceil_div(n, kThreads), 65536)),
+                       dim3(kThreads), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
 hipError_t launch_fill_f32(float *p, int64_t n, float v, hipStream_t s)
 {
     if (n == 0) return hipSuccess;

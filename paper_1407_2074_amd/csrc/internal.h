@@ -239,6 +239,7 @@ hipError_t launch_ranges(const VolGeom &g, DevCell *table, const float *slot_ran
 hipError_t launch_clear(const VolGeom &g, void *master, uint8_t *mask, double background,
                         hipStream_t s);
 hipError_t launch_fill_f32(float *p, int64_t n, float v, hipStream_t s);
+hipError_t launch_fill_u16(uint16_t *p, int64_t n, uint16_t v, hipStream_t s);
 hipError_t launch_fill_u8(uint8_t *p, int64_t n, uint8_t v, hipStream_t s);
 
 // ---- launchers (render path) ----

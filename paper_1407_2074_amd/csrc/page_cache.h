@@ -7,7 +7,10 @@
 //
 // Plain C++ and POSIX I/O, no device calls: the device side (which frames a batch of kernels
 // uses, and when that batch has finished) comes in through `seq` numbers and two callbacks,
-// so the policy is testable on the host alone.
+// so the policy is testable on the host alone.  The frames are either host memory the cache
+// reads and writes directly, or memory it cannot address (device memory): then every page
+// moves through a host staging buffer and three callbacks copy it in, copy it out and fill a
+// frame with the background.
 #pragma once
 
 #include <fcntl.h>
@@ -40,16 +43,50 @@ public:
     using WaitFn = std::function<void(uint64_t)>;
     using DoneFn = std::function<bool(uint64_t)>;
     using FillFn = std::function<void(uint8_t *)>;
+    // Frames the cache cannot address: load(f, src) copies a page from host memory into frame
+    // f, store(f, dst) the frame's page into host memory, fill(f) fills frame f with the
+    // background; each has finished when it returns (false: failed).  `staging` is a host
+    // buffer of one page for the file I/O.
+    struct FrameIO {
+        std::function<bool(int, const uint8_t *)> load;
+        std::function<bool(int, uint8_t *)> store;
+        std::function<bool(int)> fill;
+        uint8_t *staging = nullptr;
+    };
 
     ~PageCache() { close(); }
 
     // Creates (truncates) the page file and takes `frames` (n_frames * page_bytes bytes of
     // host memory owned by the caller) as the RAM set.  Returns false with `err` set on failure.
+    // `fill` fills a host page with the background.
     bool open(const std::string &path, int64_t n_pages, size_t page_bytes, uint8_t *frames,
               int n_frames, FillFn fill, std::string &err)
     {
+        if (!frames) {
+            err = "page cache: bad geometry";
+            return false;
+        }
+        return open_impl(path, n_pages, page_bytes, frames, FrameIO{}, n_frames, std::move(fill), err);
+    }
+
+    // The same with n_frames frames that only `io` reaches.
+    bool open(const std::string &path, int64_t n_pages, size_t page_bytes, FrameIO io,
+              int n_frames, FillFn fill, std::string &err)
+    {
+        if (!io.load || !io.store || !io.fill || !io.staging) {
+            err = "page cache: incomplete frame callbacks";
+            return false;
+        }
+        return open_impl(path, n_pages, page_bytes, nullptr, std::move(io), n_frames,
+                         std::move(fill), err);
+    }
+
+private:
+    bool open_impl(const std::string &path, int64_t n_pages, size_t page_bytes, uint8_t *frames,
+                   FrameIO io, int n_frames, FillFn fill, std::string &err)
+    {
         close();
-        if (n_pages < 1 || page_bytes == 0 || !frames || n_frames < 1) {
+        if (n_pages < 1 || page_bytes == 0 || n_frames < 1) {
             err = "page cache: bad geometry";
             return false;
         }
@@ -61,6 +98,7 @@ public:
         path_ = path;
         page_bytes_ = page_bytes;
         frames_ = frames;
+        fio_ = std::move(io);
         fill_ = std::move(fill);
         page_frame_.assign((size_t)n_pages, -1);
         on_disk_.assign((size_t)n_pages, 0);
@@ -74,6 +112,7 @@ public:
         return true;
     }
 
+public:
     // Closes and removes the page file (it only backs this process's octree).
     void close()
     {
@@ -88,6 +127,8 @@ public:
     int64_t n_pages() const { return (int64_t)page_frame_.size(); }
     size_t page_bytes() const { return page_bytes_; }
     int frame_of(int64_t page) const { return page_frame_[(size_t)page]; }
+    bool device_frames() const { return frames_ == nullptr; }
+    // host frames only
     uint8_t *frame_ptr(int f) const { return frames_ + (size_t)f * page_bytes_; }
     bool dirty(int f) const { return dirty_[(size_t)f] != 0; }
     bool on_disk(int64_t page) const { return on_disk_[(size_t)page] != 0; }
@@ -126,11 +167,20 @@ public:
                     if (!evict(f, err)) return -2;
                 }
                 if (on_disk_[(size_t)p]) {
-                    if (!io(false, p, frame_ptr(f), err)) return -2;
+                    if (device_frames()) {
+                        if (!io(false, p, fio_.staging, err)) return -2;
+                        if (!fio_.load(f, fio_.staging)) return fail_frame("load", p, err);
+                    } else if (!io(false, p, frame_ptr(f), err)) {
+                        return -2;
+                    }
                     stats.loads++;
                     stats.bytes_read += page_bytes_;
                 } else {
-                    fill_(frame_ptr(f));
+                    if (device_frames()) {
+                        if (!fio_.fill(f)) return fail_frame("fill", p, err);
+                    } else {
+                        fill_(frame_ptr(f));
+                    }
                     stats.fills++;
                 }
                 frame_page_[(size_t)f] = p;
@@ -152,6 +202,7 @@ public:
         const int f = page_frame_[(size_t)p];
         if (f >= 0) {
             wait(last_seq_[(size_t)f]);
+            if (device_frames()) return fio_.store(f, dst) || fail_frame("read", p, err) == 0;
             std::memcpy(dst, frame_ptr(f), page_bytes_);
             return true;
         }
@@ -196,7 +247,12 @@ private:
     {
         const int64_t p = frame_page_[(size_t)f];
         if (dirty_[(size_t)f]) {
-            if (!io(true, p, frame_ptr(f), err)) return false;
+            if (device_frames()) {
+                if (!fio_.store(f, fio_.staging)) return fail_frame("write-back", p, err) == 0;
+                if (!io(true, p, fio_.staging, err)) return false;
+            } else if (!io(true, p, frame_ptr(f), err)) {
+                return false;
+            }
             on_disk_[(size_t)p] = 1;
             stats.writebacks++;
             stats.bytes_written += page_bytes_;
@@ -206,6 +262,13 @@ private:
         dirty_[(size_t)f] = 0;
         stats.evictions++;
         return true;
+    }
+
+    // -2 (an I/O error) with err set, for a failed frame copy or fill of page p
+    static int fail_frame(const char *what, int64_t p, std::string &err)
+    {
+        err = std::string("page cache: frame ") + what + " of page " + std::to_string(p) + " failed";
+        return -2;
     }
 
     bool io(bool wr, int64_t p, uint8_t *buf, std::string &err)
@@ -229,7 +292,8 @@ private:
     int fd_ = -1;
     std::string path_;
     size_t page_bytes_ = 0;
-    uint8_t *frames_ = nullptr;
+    uint8_t *frames_ = nullptr;   // host frames, or NULL: frames reached through fio_
+    FrameIO fio_;
     FillFn fill_;
     std::vector<int32_t> page_frame_;   // frame holding each page, -1: not in RAM
     std::vector<uint8_t> on_disk_;      // the file holds the page's last written contents

@@ -177,12 +177,15 @@ struct oct_handle {
     // paging (capped pool): render flags per cell, missing-brick value bounds, LRU stamps
     bool capped = false;
     bool master_host = false;
-    void *master_alloc = nullptr;  // host allocation when the master (or its RAM frames) lives in pinned memory
+    void *master_alloc = nullptr;  // host allocation when the master (or its host frames) lives in pinned memory
     // disk tier: page file with its RAM frames (master_alloc), the device page table (master)
     // and its pinned mirror, and the build-kernel batches in flight (sequence number, end
     // event) that the frames' pinning waits for
     PageCache *pc = nullptr;
-    uint8_t *frames_dev = nullptr;
+    uint8_t *frames_dev = nullptr;   // the frames as the kernels address them
+    bool frames_own = false;         // frames_dev is a device allocation (device frames)
+    uint8_t *pg_stage = nullptr;     // device frames: pinned staging page for the file I/O
+    hipStream_t pg_copy = nullptr;   // device frames: stream of the page copies and fills
     void **ptab_host = nullptr;
     hipEvent_t ptab_ev = nullptr;
     uint64_t pg_seq = 0;
@@ -602,7 +605,10 @@ bool valid_params(const oct_create_params *p, std::string &why)
         why = "u16 background must be an integer in [0, 65535]";
         return false;
     }
-    if (p->reserved[0]) { why = "reserved fields must be 0"; return false; }
+    if (p->disk_frames != OCT_FRAMES_HOST && p->disk_frames != OCT_FRAMES_DEVICE) {
+        why = "disk_frames must be OCT_FRAMES_HOST or OCT_FRAMES_DEVICE";
+        return false;
+    }
     if (p->host_bricks != 0 && p->host_bricks != 1) { why = "host_bricks must be 0 or 1"; return false; }
     if (p->host_bricks && !p->device_pool_bytes) {
         why = "host_bricks needs a capped device pool (device_pool_bytes)";
@@ -626,8 +632,8 @@ bool valid_params(const oct_create_params *p, std::string &why)
             why = "the disk tier needs disk_path";
             return false;
         }
-    } else if (p->page_cells || p->host_cache_bytes || p->disk_path) {
-        why = "page_cells, host_cache_bytes and disk_path belong to the disk tier";
+    } else if (p->page_cells || p->host_cache_bytes || p->disk_path || p->disk_frames) {
+        why = "page_cells, host_cache_bytes, disk_path and disk_frames belong to the disk tier";
         return false;
     }
     return true;
@@ -1123,9 +1129,19 @@ int octree_create(const oct_create_params *params, void *stream, oct_handle **ou
                      " bytes (or every page)";
             return bail(OCT_EINVAL);
         }
-        // RAM frames (pinned, mapped for the kernels), the device page table and its mirror
-        hipError_t e = hipHostMalloc(&h->master_alloc, (size_t)n_frames * page_bytes, hipHostMallocMapped);
-        if (e == hipSuccess) e = hipHostGetDevicePointer((void **)&h->frames_dev, h->master_alloc, 0);
+        // frames (pinned and mapped for the kernels, or device memory with a pinned staging
+        // page and a copy stream), the device page table and its host mirror
+        const bool dev_frames = params->disk_frames == OCT_FRAMES_DEVICE;
+        hipError_t e = hipSuccess;
+        if (dev_frames) {
+            if ((rc = dev_alloc((void **)&h->frames_dev, (size_t)n_frames * page_bytes))) return bail(rc);
+            h->frames_own = true;
+            e = hipHostMalloc((void **)&h->pg_stage, page_bytes, hipHostMallocDefault);
+            if (e == hipSuccess) e = hipStreamCreateWithFlags(&h->pg_copy, hipStreamNonBlocking);
+        } else {
+            e = hipHostMalloc(&h->master_alloc, (size_t)n_frames * page_bytes, hipHostMallocMapped);
+            if (e == hipSuccess) e = hipHostGetDevicePointer((void **)&h->frames_dev, h->master_alloc, 0);
+        }
         if (e == hipSuccess) e = hipHostMalloc((void **)&h->ptab_host, (size_t)np * sizeof(void *), hipHostMallocDefault);
         if (e != hipSuccess) {
             h->err = std::string("disk tier frames: ") + hipGetErrorString(e);
@@ -1141,12 +1157,40 @@ int octree_create(const oct_create_params *params, void *stream, oct_handle **ou
         h->pc = new (std::nothrow) PageCache();
         if (!h->pc) return bail(OCT_ENOMEM);
         std::string perr;
-        if (!h->pc->open(params->disk_path, np, page_bytes, (uint8_t *)h->master_alloc, (int)n_frames,
-                         [u16, bg, page_bytes](uint8_t *f) {
-                             if (u16) std::fill_n((uint16_t *)f, page_bytes / 2, (uint16_t)bg);
-                             else std::fill_n((float *)f, page_bytes / 4, (float)bg);
-                         },
-                         perr)) {
+        auto host_fill = [u16, bg, page_bytes](uint8_t *f) {
+            if (u16) std::fill_n((uint16_t *)f, page_bytes / 2, (uint16_t)bg);
+            else std::fill_n((float *)f, page_bytes / 4, (float)bg);
+        };
+        bool opened;
+        if (dev_frames) {
+            // each copy or fill has finished when the callback returns: a frame is only
+            // touched here while no device work uses it (the cache waits for that first)
+            PageCache::FrameIO io;
+            io.staging = h->pg_stage;
+            io.load = [h, page_bytes](int f, const uint8_t *src) {
+                return hipMemcpyAsync(h->frames_dev + (size_t)f * page_bytes, src, page_bytes,
+                                      hipMemcpyHostToDevice, h->pg_copy) == hipSuccess &&
+                       hipStreamSynchronize(h->pg_copy) == hipSuccess;
+            };
+            io.store = [h, page_bytes](int f, uint8_t *dst) {
+                return hipMemcpyAsync(dst, h->frames_dev + (size_t)f * page_bytes, page_bytes,
+                                      hipMemcpyDeviceToHost, h->pg_copy) == hipSuccess &&
+                       hipStreamSynchronize(h->pg_copy) == hipSuccess;
+            };
+            io.fill = [h, page_bytes, u16, bg](int f) {
+                uint8_t *p = h->frames_dev + (size_t)f * page_bytes;
+                const hipError_t fe =
+                    u16 ? launch_fill_u16((uint16_t *)p, (int64_t)(page_bytes / 2), (uint16_t)bg, h->pg_copy)
+                        : launch_fill_f32((float *)p, (int64_t)(page_bytes / 4), (float)bg, h->pg_copy);
+                return fe == hipSuccess && hipStreamSynchronize(h->pg_copy) == hipSuccess;
+            };
+            opened = h->pc->open(params->disk_path, np, page_bytes, std::move(io), (int)n_frames,
+                                 host_fill, perr);
+        } else {
+            opened = h->pc->open(params->disk_path, np, page_bytes, (uint8_t *)h->master_alloc,
+                                 (int)n_frames, host_fill, perr);
+        }
+        if (!opened) {
             h->err = perr;
             return bail(OCT_EINVAL);
         }
@@ -1234,13 +1278,18 @@ int octree_destroy(oct_handle *h)
     if (h->pc) {
         pg_wait(h, UINT64_MAX);
         delete h->pc;   // removes the page file
+    }
+    if (h->p.master_on_host == OCT_MASTER_DISK) {
         for (hipEvent_t e : h->pg_free) (void)hipEventDestroy(e);
         if (h->ptab_ev) (void)hipEventDestroy(h->ptab_ev);
         if (h->ptab_host) (void)hipHostFree(h->ptab_host);
         if (h->master) (void)hipFree(h->master);   // the device page table
         if (h->master_alloc) (void)hipHostFree(h->master_alloc);
+        if (h->frames_own) (void)hipFree(h->frames_dev);
+        if (h->pg_stage) (void)hipHostFree(h->pg_stage);
+        if (h->pg_copy) (void)hipStreamDestroy(h->pg_copy);
     } else if (h->master_alloc) {
-        (void)hipHostFree(h->master_alloc);
+        (void)hipHostFree(h->master_alloc);   // the pinned master (master is its device address)
     } else if (h->master) {
         (void)hipFree(h->master);
     }

@@ -27,6 +27,7 @@ EXPORTS = ["octree_create", "octree_destroy", "octree_clear", "octree_insert_blo
            "render_views_backward", "octree_dump_canonical", "octree_read_level", "octree_info",
            "octree_render_timing", "octree_build_timing", "octree_disk_stats", "oct_last_error"]
 OCT_MASTER_HBM, OCT_MASTER_HOST, OCT_MASTER_DISK = 0, 1, 2
+OCT_FRAMES_HOST, OCT_FRAMES_DEVICE = 0, 1
 
 
 class CreateParams(ct.Structure):
@@ -34,7 +35,7 @@ class CreateParams(ct.Structure):
                 ("dtype", ct.c_int32), ("background", ct.c_double),
                 ("homog_threshold", ct.c_double), ("device_pool_bytes", ct.c_uint64),
                 ("master_on_host", ct.c_int32), ("page_cells", ct.c_int32),
-                ("host_bricks", ct.c_int32), ("reserved", ct.c_int32 * 1),
+                ("host_bricks", ct.c_int32), ("disk_frames", ct.c_int32),
                 ("host_cache_bytes", ct.c_uint64),
                 ("disk_path", ct.c_char_p)]
 
@@ -215,9 +216,11 @@ class Octree:
     def __init__(self, dims, channels: int, brick: int, dtype: str = "u16",
                  background: float = 0.0, threshold: float = 0.0, pool_bytes: int = 0,
                  master_on_host: bool = False, stream=None, disk_path: str | None = None,
-                 host_cache_bytes: int = 0, page_cells: int = 0, host_bricks: bool = False):
-        """disk_path: keep the mipmap in pages in this file with host_cache_bytes of RAM
-        frames (the disk tier); master_on_host: in pinned host memory; else in HBM.
+                 host_cache_bytes: int = 0, page_cells: int = 0, host_bricks: bool = False,
+                 device_frames: bool = False):
+        """disk_path: keep the mipmap in pages in this file with host_cache_bytes of page
+        frames (the disk tier), in pinned host memory or, with device_frames, in device
+        memory; master_on_host: in pinned host memory; else in HBM.
         host_bricks: keep gathered bricks in a host brick store (capped pools)."""
         p = CreateParams()
         for a in range(3):
@@ -232,6 +235,7 @@ class Octree:
             p.disk_path = os.fsencode(disk_path)
             p.host_cache_bytes = int(host_cache_bytes)
             p.page_cells = int(page_cells)
+            p.disk_frames = OCT_FRAMES_DEVICE if device_frames else OCT_FRAMES_HOST
         else:
             p.master_on_host = OCT_MASTER_HOST if master_on_host else OCT_MASTER_HBM
         h = ct.c_void_p()

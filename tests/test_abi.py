@@ -64,7 +64,8 @@ def test_invalid_create_params_fail_without_gpu_work(native):
     import ctypes as ct
     disk = native.OCT_MASTER_DISK
     for bad in [dict(brick=5), dict(brick=0), dict(channels=5), dict(channels=0),
-                dict(dims=(0, 4, 4)), dict(dtype=7), dict(background=1.5), dict(reserved=1),
+                dict(dims=(0, 4, 4)), dict(dtype=7), dict(background=1.5), dict(frames=1),
+                dict(master=disk, path=b"/tmp/x", cache=1 << 30, frames=2),
                 dict(master=3), dict(master=disk), dict(master=disk, path=b"/tmp/x", brick=6),
                 dict(master=disk, path=b"/tmp/x", page_cells=3), dict(page_cells=2),
                 dict(cache=1 << 20), dict(path=b"/tmp/x"), dict(host_bricks=2),
@@ -77,7 +78,7 @@ def test_invalid_create_params_fail_without_gpu_work(native):
         p.brick_size = bad.get("brick", 8)
         p.dtype = bad.get("dtype", 0)
         p.background = bad.get("background", 0.0)
-        p.reserved[0] = bad.get("reserved", 0)
+        p.disk_frames = bad.get("frames", 0)
         p.host_bricks = bad.get("host_bricks", 0)
         p.master_on_host = bad.get("master", 0)
         p.page_cells = bad.get("page_cells", 0)
