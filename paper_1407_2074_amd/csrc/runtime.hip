@@ -1524,30 +1524,45 @@ static int upload_paging_only(oct_handle *h, uint64_t byte_budget, hipStream_t s
         while (L < g.N && ci >= g.cell_off[L + 1]) L++;
         return L;
     };
-    for (int64_t i = 0; i < h->n_cells; i++)
-        if (fl[i] == 1) h->last_used[(size_t)i] = h->frame;
-    // requests in the full upload's scan order: levels from the root down, cells in index order
-    std::vector<int64_t> reqs, idle, busy;
+    // one pass over the flags, levels from the root down and cells in index order (the full
+    // upload's scan order, which the requests keep): the cells used now, and the requests
+    std::vector<int64_t> reqs;
     for (int L = g.N; L >= 0; L--) {
         const int64_t n = (int64_t)g.grid[L] * g.grid[L] * g.grid[L];
-        for (int64_t ci = g.cell_off[L]; ci < g.cell_off[L] + n; ci++)
-            if (fl[ci] == 2 && h->data_cell[(size_t)ci] && h->cells[(size_t)ci].slot < 0) reqs.push_back(ci);
+        for (int64_t ci = g.cell_off[L]; ci < g.cell_off[L] + n; ci++) {
+            if (fl[ci] == 1) h->last_used[(size_t)ci] = h->frame;
+            else if (fl[ci] == 2 && h->data_cell[(size_t)ci] && h->cells[(size_t)ci].slot < 0)
+                reqs.push_back(ci);
+        }
     }
-    for (int64_t ci : h->slot_cell)
-        if (ci >= 0) (h->last_used[(size_t)ci] == h->frame ? busy : idle).push_back(ci);
     requests_seen = reqs.size();
-    // the full upload's orders made total: (last use, level, scan position) and (level, scan
-    // position); inside a level the scan position is the cell index
-    std::sort(idle.begin(), idle.end(), [&](int64_t a, int64_t b) {
-        if (h->last_used[(size_t)a] != h->last_used[(size_t)b]) return h->last_used[(size_t)a] < h->last_used[(size_t)b];
-        const int la = level_of(a), lb = level_of(b);
-        return la != lb ? la < lb : a < b;
-    });
-    std::sort(busy.begin(), busy.end(), [&](int64_t a, int64_t b) {
-        const int la = level_of(a), lb = level_of(b);
-        return la != lb ? la < lb : a < b;
-    });
+    // resident cells as (last use, level, cell) keys: the full upload's victim orders made total
+    // are (last use, level, scan position) for cells not used now and (level, scan position)
+    // for the others; inside a level the scan position is the cell index
+    struct VKey {
+        uint64_t used;
+        int32_t level;
+        int64_t ci;
+        bool operator<(const VKey &o) const
+        {
+            if (used != o.used) return used < o.used;
+            return level != o.level ? level < o.level : ci < o.ci;
+        }
+    };
+    std::vector<VKey> idle, busy;
+    for (int64_t ci : h->slot_cell)
+        if (ci >= 0) {
+            const uint64_t u = h->last_used[(size_t)ci];
+            if (u == h->frame) busy.push_back(VKey{0, level_of(ci), ci});
+            else idle.push_back(VKey{u, level_of(ci), ci});
+        }
+    // at most one victim per request that the budget admits: order only those
     uint64_t budget_left = byte_budget ? byte_budget : UINT64_MAX;
+    const size_t admit = std::min<uint64_t>(reqs.size(), budget_left / h->brick_bytes);
+    const size_t n_idle = std::min(idle.size(), admit);
+    std::partial_sort(idle.begin(), idle.begin() + n_idle, idle.end());
+    const size_t n_busy = std::min(busy.size(), admit - n_idle);
+    std::partial_sort(busy.begin(), busy.begin() + n_busy, busy.end());
     std::vector<int64_t> changed;
     size_t vi = 0, bi = 0;
     for (int64_t ci : reqs) {
@@ -1559,8 +1574,8 @@ static int upload_paging_only(oct_handle *h, uint64_t byte_budget, hipStream_t s
         const int L = level_of(ci);
         if (h->free_slots.empty()) {
             int64_t victim;
-            if (vi < idle.size()) victim = idle[vi++];
-            else if (bi < busy.size() && level_of(busy[bi]) < L) victim = busy[bi++];
+            if (vi < n_idle) victim = idle[vi++].ci;
+            else if (bi < n_busy && busy[bi].level < L) victim = busy[bi++].ci;
             else {
                 unserved++;
                 continue;
