@@ -323,8 +323,12 @@ class Octree:
                       for v in views]
         if len(images) != len(views):
             raise ValueError("one image per view")
+        f32 = torch.float32
         for k, (v, im) in enumerate(zip(views, images)):
-            self._check_buffer(im, f"images[{k}]", torch.float32, (v.height, v.width, 4))
+            # one expression for the common case; the full check names what is wrong
+            if not (type(im) is torch.Tensor and im.is_cuda and im.dtype is f32
+                    and im.shape == (v.height, v.width, 4) and im.is_contiguous()):
+                self._check_buffer(im, f"images[{k}]", f32, (v.height, v.width, 4))
         ova = to_oct_views(views)
         if refine is not None:
             if len(refine) != len(views):
@@ -369,8 +373,11 @@ class Octree:
         import torch
         if len(dL_dimages) != len(views):
             raise ValueError("one image gradient per view")
+        f32 = torch.float32
         for k, (v, g) in enumerate(zip(views, dL_dimages)):
-            self._check_buffer(g, f"dL_dimages[{k}]", torch.float32, (v.height, v.width, 4))
+            if not (type(g) is torch.Tensor and g.is_cuda and g.dtype is f32
+                    and g.shape == (v.height, v.width, 4) and g.is_contiguous()):
+                self._check_buffer(g, f"dL_dimages[{k}]", f32, (v.height, v.width, 4))
         self._check_buffer(ckpt, "ckpt", None, min_bytes=self.ckpt_bytes(views))
         self._check_buffer(dctrl, "dctrl", torch.float32, min_bytes=len(views) * self.C * 8 * 4 * 4)
         if dvox is not None:
