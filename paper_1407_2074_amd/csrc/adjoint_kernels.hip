@@ -151,6 +151,27 @@ struct Marcher {
 // Voxel gradients of one lane's current corner cube (lower corner k, level-0 indices), summed in
 // registers while consecutive positions interpolate in the same cube; a step of one along an
 // axis keeps the four corners the two cubes share, the others are added to memory.
+// Blocked voxel-gradient scratch: [C] planes of blocks of 2^sx x 2^sy x 2^sz voxels
+// (sx + sy + sz = 4: 16 floats, one 64-byte line), blocks x-fastest.  The shape code is
+// sx + 4 sy + 16 sz.
+struct BlockShape {
+    int sx, sy, sz;
+    int64_t nbx, nby, plane;
+    __host__ __device__ BlockShape(int code, const int32_t *dims)
+        : sx(code & 3), sy((code >> 2) & 3), sz((code >> 4) & 3),
+          nbx((dims[0] + (1 << sx) - 1) >> sx), nby((dims[1] + (1 << sy) - 1) >> sy),
+          plane((nbx * nby * ((dims[2] + (1 << sz) - 1) >> sz)) << 4)
+    {
+    }
+    __host__ __device__ int64_t index(int64_t x, int64_t y, int64_t z) const
+    {
+        return ((((z >> sz) * nby + (y >> sy)) * nbx + (x >> sx)) << 4) +
+               ((((z & ((1 << sz) - 1)) << sy | (y & ((1 << sy) - 1))) << sx) | (x & ((1 << sx) - 1)));
+    }
+};
+
+// The gradients go to dvox as [C][Dz][Dy][Dx] (shape code < 0), or to the blocked scratch,
+// where the corners that the lanes of a wave flush together share more lines.
 template <int C>
 struct CubeAcc {
     float v[C][8];
@@ -158,8 +179,11 @@ struct CubeAcc {
     float *dvox;
     int64_t nvox0;
     int dims[3];
+    bool blocked;
+    BlockShape bs;
 
-    __device__ CubeAcc(float *d, int64_t n, const int32_t *dm) : dvox(d), nvox0(n)
+    __device__ CubeAcc(float *d, int64_t n, const int32_t *dm, int shape)
+        : dvox(d), nvox0(n), blocked(shape >= 0), bs(shape >= 0 ? shape : 0, dm)
     {
         dims[0] = dm[0];
         dims[1] = dm[1];
@@ -176,10 +200,17 @@ struct CubeAcc {
         const int gx = min(max(kx + (Q & 1), 0), dims[0] - 1);
         const int gy = min(max(ky + ((Q >> 1) & 1), 0), dims[1] - 1);
         const int gz = min(max(kz + (Q >> 2), 0), dims[2] - 1);
-        const int64_t vi = ((int64_t)gz * dims[1] + gy) * dims[0] + gx;
+        int64_t vi, pl;
+        if (blocked) {
+            vi = bs.index(gx, gy, gz);
+            pl = bs.plane;
+        } else {
+            vi = ((int64_t)gz * dims[1] + gy) * dims[0] + gx;
+            pl = nvox0;
+        }
 #pragma unroll
         for (int c = 0; c < C; c++) {
-            if (v[c][Q] != 0.0f) atomicAdd(dvox + c * nvox0 + vi, v[c][Q]);
+            if (v[c][Q] != 0.0f) atomicAdd(dvox + c * pl + vi, v[c][Q]);
             v[c][Q] = 0.0f;
         }
     }
@@ -242,7 +273,7 @@ template <typename T, int C, bool kVox>
 __global__ void __launch_bounds__(kThreads)
 k_render_backward(VolGeom g, const DevCell *__restrict__ table, const uint8_t *__restrict__ pool,
                   uint64_t brick_bytes, const DevView *__restrict__ views,
-                  const WgItem *__restrict__ items, float *dvox, float *dctrl)
+                  const WgItem *__restrict__ items, float *dvox, int vg_shape, float *dctrl)
 {
     __shared__ ViewTables<C> tb;
     __shared__ float s_dctrl[C][8][4];
@@ -288,7 +319,7 @@ k_render_backward(VolGeom g, const DevCell *__restrict__ table, const uint8_t *_
         const int64_t nvox0 = (int64_t)g.dims[0] * g.dims[1] * g.dims[2];
         Marcher<T, C> mb(g, table, pool, brick_bytes, ray.L);
         float Bc[3] = {0.0f, 0.0f, 0.0f}, Ba = 0.0f;
-        CubeAcc<C> acc(dvox, nvox0, g.dims);
+        CubeAcc<C> acc(dvox, nvox0, g.dims, vg_shape);
         // control-point gradients, through the table construction: an event interpolating
         // entries (i, i + 1) with weights (1 - fr, fr) reaches the control points of those two
         // entries (table entry k = (1 - f_k) ctrl[j_k] + f_k ctrl[j_k + 1]), i.e. at most three
@@ -633,7 +664,7 @@ __global__ void k_lut_to_ctrl(const DevView *views, int n_views, int C, float *d
 template <typename T>
 hipError_t launch_bw_typed(const VolGeom &g, const DevCell *table, const void *pool,
                            uint64_t brick_bytes, const DevView *views, const WgItem *items,
-                           int n_items, float *dvox, float *dctrl, hipStream_t s)
+                           int n_items, float *dvox, int vg_shape, float *dctrl, hipStream_t s)
 {
     const dim3 grid(n_items), block(kThreads);
     const uint8_t *p = (const uint8_t *)pool;
@@ -641,10 +672,10 @@ hipError_t launch_bw_typed(const VolGeom &g, const DevCell *table, const void *p
     do {                                                                                          \
         if (dvox)                                                                                 \
             hipLaunchKernelGGL((k_render_backward<TT, CC, true>), grid, block, 0, s, g, table, p,  \
-                               brick_bytes, views, items, dvox, dctrl);                           \
+                               brick_bytes, views, items, dvox, vg_shape, dctrl);                 \
         else                                                                                      \
             hipLaunchKernelGGL((k_render_backward<TT, CC, false>), grid, block, 0, s, g, table, p, \
-                               brick_bytes, views, items, dvox, dctrl);                           \
+                               brick_bytes, views, items, dvox, vg_shape, dctrl);                 \
     } while (0)
     switch (g.C) {
     case 1: OCTRC_BW(T, 1); break;
@@ -660,14 +691,47 @@ hipError_t launch_bw_typed(const VolGeom &g, const DevCell *table, const void *p
 
 hipError_t launch_render_backward(const VolGeom &g, const DevCell *table, const void *pool,
                                   uint64_t brick_bytes, const DevView *views, const WgItem *items,
-                                  int n_items, float *dvox, float *dctrl, hipStream_t s)
+                                  int n_items, float *dvox, int vg_shape, float *dctrl,
+                                  hipStream_t s)
 {
     if (n_items == 0) return hipSuccess;
     if (g.dtype == 0)
         return launch_bw_typed<uint16_t>(g, table, pool, brick_bytes, views, items, n_items, dvox,
-                                         dctrl, s);
-    return launch_bw_typed<float>(g, table, pool, brick_bytes, views, items, n_items, dvox, dctrl,
-                                  s);
+                                         vg_shape, dctrl, s);
+    return launch_bw_typed<float>(g, table, pool, brick_bytes, views, items, n_items, dvox,
+                                  vg_shape, dctrl, s);
+}
+
+size_t voxgrad_blocked_floats(const VolGeom &g, int shape)
+{
+    return (size_t)BlockShape(shape, g.dims).plane * (size_t)g.C;
+}
+
+namespace {
+// dvox[c][z][y][x] += blk at the blocked index of (x, y, z) in plane c; one voxel per thread
+__global__ void __launch_bounds__(256)
+k_voxgrad_unblock(VolGeom g, int shape, const float *__restrict__ blk, float *__restrict__ dvox)
+{
+    const int64_t nx = g.dims[0], ny = g.dims[1];
+    const int64_t nvox0 = nx * ny * g.dims[2];
+    const BlockShape bs(shape, g.dims);
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < nvox0 * g.C;
+         i += (int64_t)gridDim.x * 256) {
+        const int64_t c = i / nvox0, v = i - c * nvox0;
+        const int64_t x = v % nx, y = (v / nx) % ny, z = v / (nx * ny);
+        dvox[i] += blk[c * bs.plane + bs.index(x, y, z)];
+    }
+}
+}  // namespace
+
+hipError_t launch_voxgrad_unblock(const VolGeom &g, int shape, const float *blk, float *dvox,
+                                  hipStream_t s)
+{
+    const int64_t n = (int64_t)g.dims[0] * g.dims[1] * g.dims[2] * g.C;
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_voxgrad_unblock, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 1 << 20)),
+                       dim3(256), 0, s, g, shape, blk, dvox);
+    return hipGetLastError();
 }
 
 hipError_t launch_render_backward_mip(const VolGeom &g, const DevCell *table, const void *pool,

@@ -270,10 +270,17 @@ hipError_t launch_view_mask(const VolGeom &g, const DevView *views, int n_views,
 hipError_t launch_combine(const DevView *views, const int32_t *split_views, int n_split,
                           int C, int modes, int64_t max_pixels, hipStream_t s);
 // Adjoint of DVR views (from the transmittances their forward recorded); control-point
-// gradients are added to dctrl [view][C][8][4] (views' user_index).
+// gradients are added to dctrl [view][C][8][4] (views' user_index), voxel gradients (dvox not
+// NULL) to dvox as [C][Dz][Dy][Dx] (shape < 0), or to a scratch of
+// voxgrad_blocked_floats(g, shape) floats in blocks of 2^sx x 2^sy x 2^sz voxels (shape =
+// sx + 4 sy + 16 sz, sx + sy + sz = 4) that launch_voxgrad_unblock then adds to dvox.
 hipError_t launch_render_backward(const VolGeom &g, const DevCell *table, const void *pool,
                                   uint64_t brick_bytes, const DevView *views, const WgItem *items,
-                                  int n_items, float *dvox, float *dctrl, hipStream_t s);
+                                  int n_items, float *dvox, int shape, float *dctrl,
+                                  hipStream_t s);
+size_t voxgrad_blocked_floats(const VolGeom &g, int shape);
+hipError_t launch_voxgrad_unblock(const VolGeom &g, int shape, const float *blk, float *dvox,
+                                  hipStream_t s);
 // Adjoint of MIP views: one lane per pixel, through the samples at the recorded maxima.
 hipError_t launch_render_backward_mip(const VolGeom &g, const DevCell *table, const void *pool,
                                       uint64_t brick_bytes, const DevView *views,

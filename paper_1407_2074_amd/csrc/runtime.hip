@@ -172,8 +172,10 @@ struct oct_handle {
     std::vector<BuildTimed> btimed;
     std::vector<hipEvent_t> bt_free;
     double bt_ms[4] = {0, 0, 0, 0}, bt_bytes[4] = {0, 0, 0, 0};
-    void *bw_tmp = nullptr;      // adjoint: table-gradient accumulators + replay scratch
+    void *bw_tmp = nullptr;      // adjoint: table-gradient accumulators (MIP views)
     size_t bw_tmp_cap = 0;
+    float *vg_blk = nullptr;     // adjoint: blocked voxel-gradient scratch
+    size_t vg_blk_cap = 0;
     // paging (capped pool): render flags per cell, missing-brick value bounds, LRU stamps
     bool capped = false;
     bool master_host = false;
@@ -1305,6 +1307,7 @@ int octree_destroy(oct_handle *h)
     if (h->slot_range) (void)hipFree(h->slot_range);
     if (h->ins_stage) (void)hipFree(h->ins_stage);
     if (h->bw_tmp) (void)hipFree(h->bw_tmp);
+    if (h->vg_blk) (void)hipFree(h->vg_blk);
     for (const auto &r : h->btimed) {
         (void)hipEventDestroy(r.e0);
         (void)hipEventDestroy(r.e1);
@@ -2831,6 +2834,39 @@ int render_views_backward(oct_handle *h, int32_t n_views, const oct_view *views,
     }
     float *dlut = (float *)h->bw_tmp;
     for (int i = 0; i < n_views; i++) dvs[i].dlut = dlut + (size_t)i * dlut_floats;
+    // voxel gradients of DVR views first go to a scratch of 16-voxel blocks, added to
+    // dL/dvoxels at the end: the corners that the lanes of a wave flush together then share
+    // more 64-byte lines.  Lanes spread over the image plane and, by their entry points, along
+    // the rays, so the block is 1 voxel along the axis closest to the first view's direction, 8
+    // along the farthest and 2 along the other.  Volumes whose scratch would pass
+    // kVoxBlockedMax go to dL/dvoxels directly.
+    constexpr size_t kVoxBlockedMax = (size_t)4 << 30;
+    int vg_shape = -1;
+    if (dL_dvoxels && !items.empty()) {
+        const float *f = dvs[(size_t)items[0].view].f;
+        int ax[3] = {0, 1, 2};
+        std::sort(ax, ax + 3, [&](int a, int b) {
+            return std::fabs(f[a]) != std::fabs(f[b]) ? std::fabs(f[a]) > std::fabs(f[b]) : a < b;
+        });
+        int sh[3];
+        sh[ax[0]] = 0;
+        sh[ax[1]] = 1;
+        sh[ax[2]] = 3;
+        vg_shape = sh[0] + 4 * sh[1] + 16 * sh[2];
+    }
+    const size_t vg_bytes = vg_shape >= 0 ? voxgrad_blocked_floats(g, vg_shape) * sizeof(float) : 0;
+    const bool vg_blocked = vg_shape >= 0 && vg_bytes <= kVoxBlockedMax;
+    if (!vg_blocked) vg_shape = -1;
+    if (vg_blocked && vg_bytes > h->vg_blk_cap) {
+        for (auto &r : h->rs)
+            if (r.st.ev) HIPCHK(h, hipEventSynchronize(r.st.ev));
+        HIPCHK(h, hipStreamSynchronize(s));
+        if (h->vg_blk) HIPCHK(h, hipFree(h->vg_blk));
+        h->vg_blk = nullptr;
+        h->vg_blk_cap = 0;
+        HIPCHK(h, hipMalloc((void **)&h->vg_blk, vg_bytes));
+        h->vg_blk_cap = vg_bytes;
+    }
 
     const size_t n_dvr_items = items.size();
     items.insert(items.end(), mip_items.begin(), mip_items.end());
@@ -2858,6 +2894,7 @@ int render_views_backward(oct_handle *h, int32_t n_views, const oct_view *views,
     if (!rc) rc = wait_for_renders(h, s);
     if (rc) return rc;
     if (!mip_items.empty()) HIPCHK(h, launch_fill_f32(dlut, (int64_t)n_views * dlut_floats, 0.0f, s));
+    if (vg_blocked) HIPCHK(h, launch_fill_f32(h->vg_blk, (int64_t)(vg_bytes / sizeof(float)), 0.0f, s));
     uint8_t *dp = (uint8_t *)rs.st.dev;
     if (h->ktime && n_dvr_items) {
         if (!rs.k0) HIPCHK(h, hipEventCreate(&rs.k0));
@@ -2865,8 +2902,8 @@ int render_views_backward(oct_handle *h, int32_t n_views, const oct_view *views,
         HIPCHK(h, hipEventRecord(rs.k0, s));
     }
     HIPCHK(h, launch_render_backward(g, h->table, h->pool, h->brick_bytes, (const DevView *)dp,
-                                     (const WgItem *)(dp + i_off), (int)n_dvr_items, dL_dvoxels,
-                                     dL_dctrl, s));
+                                     (const WgItem *)(dp + i_off), (int)n_dvr_items,
+                                     vg_blocked ? h->vg_blk : dL_dvoxels, vg_shape, dL_dctrl, s));
     if (h->ktime && n_dvr_items) {
         HIPCHK(h, hipEventRecord(rs.k1, s));
         rs.k_pending = true;
@@ -2874,6 +2911,7 @@ int render_views_backward(oct_handle *h, int32_t n_views, const oct_view *views,
     HIPCHK(h, launch_render_backward_mip(g, h->table, h->pool, h->brick_bytes, (const DevView *)dp,
                                          (const WgItem *)(dp + i_off) + n_dvr_items,
                                          (int)mip_items.size(), dL_dvoxels, s));
+    if (vg_blocked) HIPCHK(h, launch_voxgrad_unblock(g, vg_shape, h->vg_blk, dL_dvoxels, s));
     // MIP views accumulate table gradients (V.dlut); DVR views add to dL/dctrl directly
     if (!mip_items.empty()) HIPCHK(h, launch_lut_to_ctrl((const DevView *)dp, n_views, g.C, dL_dctrl, s));
     HIPCHK(h, hipEventRecord(rs.st.ev, s));
