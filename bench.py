@@ -577,7 +577,7 @@ def measure_adjoint(args) -> dict:
            "ms_per_step": round((tf + tb) * 1e3, 3), "higher_is_better": True,
            "dtype": "f32", "data": "synthetic",
            "config": {"workload": "256^3x3 f32, 64^3 bricks, 512x512, LOD 0, L2 loss vs "
-                                  "perturbed-TF target; forward with checkpoints + adjoint"},
+                                  "perturbed-TF target; forward recording transmittances + adjoint"},
            "forward_ms": round(tf * 1e3, 3), "adjoint_ms": round(tb * 1e3, 3),
            "adjoint_tf_only_ms": round(tb_tf * 1e3, 3),
            "kernel_ms": kms,
