@@ -151,21 +151,20 @@ struct Marcher {
 // Voxel gradients of one lane's current corner cube (lower corner k, level-0 indices), summed in
 // registers while consecutive positions interpolate in the same cube; a step of one along an
 // axis keeps the four corners the two cubes share, the others are added to memory.
-// Blocked voxel-gradient scratch: [C] planes of blocks of 2^sx x 2^sy x 2^sz voxels
-// (sx + sy + sz = 4: 16 floats, one 64-byte line), blocks x-fastest.  The shape code is
-// sx + 4 sy + 16 sz.
+// Blocked voxel-gradient scratch: [C] planes of blocks of 2^sx x 2^sy x 2^sz voxels (each
+// shift 0..7), blocks x-fastest.  The shape code is sx + 8 sy + 64 sz.
 struct BlockShape {
-    int sx, sy, sz;
+    int sx, sy, sz, sb;
     int64_t nbx, nby, plane;
     __host__ __device__ BlockShape(int code, const int32_t *dims)
-        : sx(code & 3), sy((code >> 2) & 3), sz((code >> 4) & 3),
+        : sx(code & 7), sy((code >> 3) & 7), sz((code >> 6) & 7), sb(sx + sy + sz),
           nbx((dims[0] + (1 << sx) - 1) >> sx), nby((dims[1] + (1 << sy) - 1) >> sy),
-          plane((nbx * nby * ((dims[2] + (1 << sz) - 1) >> sz)) << 4)
+          plane((nbx * nby * ((dims[2] + (1 << sz) - 1) >> sz)) << sb)
     {
     }
     __host__ __device__ int64_t index(int64_t x, int64_t y, int64_t z) const
     {
-        return ((((z >> sz) * nby + (y >> sy)) * nbx + (x >> sx)) << 4) +
+        return ((((z >> sz) * nby + (y >> sy)) * nbx + (x >> sx)) << sb) +
                ((((z & ((1 << sz) - 1)) << sy | (y & ((1 << sy) - 1))) << sx) | (x & ((1 << sx) - 1)));
     }
 };

@@ -273,7 +273,7 @@ hipError_t launch_combine(const DevView *views, const int32_t *split_views, int 
 // gradients are added to dctrl [view][C][8][4] (views' user_index), voxel gradients (dvox not
 // NULL) to dvox as [C][Dz][Dy][Dx] (shape < 0), or to a scratch of
 // voxgrad_blocked_floats(g, shape) floats in blocks of 2^sx x 2^sy x 2^sz voxels (shape =
-// sx + 4 sy + 16 sz, sx + sy + sz = 4) that launch_voxgrad_unblock then adds to dvox.
+// sx + 8 sy + 64 sz) that launch_voxgrad_unblock then adds to dvox.
 hipError_t launch_render_backward(const VolGeom &g, const DevCell *table, const void *pool,
                                   uint64_t brick_bytes, const DevView *views, const WgItem *items,
                                   int n_items, float *dvox, int shape, float *dctrl,

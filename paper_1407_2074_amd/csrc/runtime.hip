@@ -2852,7 +2852,7 @@ int render_views_backward(oct_handle *h, int32_t n_views, const oct_view *views,
         sh[ax[0]] = 0;
         sh[ax[1]] = 1;
         sh[ax[2]] = 3;
-        vg_shape = sh[0] + 4 * sh[1] + 16 * sh[2];
+        vg_shape = sh[0] + 8 * sh[1] + 64 * sh[2];
     }
     const size_t vg_bytes = vg_shape >= 0 ? voxgrad_blocked_floats(g, vg_shape) * sizeof(float) : 0;
     const bool vg_blocked = vg_shape >= 0 && vg_bytes <= kVoxBlockedMax;
