@@ -707,18 +707,42 @@ size_t voxgrad_blocked_floats(const VolGeom &g, int shape)
 }
 
 namespace {
-// dvox[c][z][y][x] += blk at the blocked index of (x, y, z) in plane c; one voxel per thread
+// dvox[c][z][y][x] += the scratch's value of (x, y, z) in plane c; one block per thread (the
+// block's values are contiguous, and neighbouring threads hold neighbouring blocks, which are
+// neighbours along x in dvox)
 __global__ void __launch_bounds__(256)
 k_voxgrad_unblock(VolGeom g, int shape, const float *__restrict__ blk, float *__restrict__ dvox)
 {
-    const int64_t nx = g.dims[0], ny = g.dims[1];
-    const int64_t nvox0 = nx * ny * g.dims[2];
     const BlockShape bs(shape, g.dims);
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < nvox0 * g.C;
+    const int64_t nx = g.dims[0], ny = g.dims[1], nz = g.dims[2];
+    const int64_t nvox0 = nx * ny * nz;
+    const int64_t nblk = bs.plane >> bs.sb;
+    const int per = 1 << bs.sb;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < nblk * g.C;
          i += (int64_t)gridDim.x * 256) {
-        const int64_t c = i / nvox0, v = i - c * nvox0;
-        const int64_t x = v % nx, y = (v / nx) % ny, z = v / (nx * ny);
-        dvox[i] += blk[c * bs.plane + bs.index(x, y, z)];
+        const int64_t c = i / nblk, b = i - c * nblk;
+        const int64_t bx = b % bs.nbx, by = (b / bs.nbx) % bs.nby, bz = b / (bs.nbx * bs.nby);
+        const float *src = blk + c * bs.plane + (b << bs.sb);
+        auto add = [&](int e, float v) {
+            const int64_t x = (bx << bs.sx) + (e & ((1 << bs.sx) - 1));
+            const int64_t y = (by << bs.sy) + ((e >> bs.sx) & ((1 << bs.sy) - 1));
+            const int64_t z = (bz << bs.sz) + (e >> (bs.sx + bs.sy));
+            if (x < nx && y < ny && z < nz) dvox[c * nvox0 + (z * ny + y) * nx + x] += v;
+        };
+        if (per == 16) {   // one 64-byte block: four 16-byte loads
+            float4 q[4];
+#pragma unroll
+            for (int k = 0; k < 4; k++) q[k] = ((const float4 *)src)[k];
+#pragma unroll
+            for (int k = 0; k < 4; k++) {
+                add(4 * k, q[k].x);
+                add(4 * k + 1, q[k].y);
+                add(4 * k + 2, q[k].z);
+                add(4 * k + 3, q[k].w);
+            }
+        } else {
+            for (int e = 0; e < per; e++) add(e, src[e]);
+        }
     }
 }
 }  // namespace
@@ -726,7 +750,8 @@ k_voxgrad_unblock(VolGeom g, int shape, const float *__restrict__ blk, float *__
 hipError_t launch_voxgrad_unblock(const VolGeom &g, int shape, const float *blk, float *dvox,
                                   hipStream_t s)
 {
-    const int64_t n = (int64_t)g.dims[0] * g.dims[1] * g.dims[2] * g.C;
+    const BlockShape bs(shape, g.dims);
+    const int64_t n = (bs.plane >> bs.sb) * g.C;
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_voxgrad_unblock, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 1 << 20)),
                        dim3(256), 0, s, g, shape, blk, dvox);
