@@ -314,8 +314,11 @@ size_t render_refine_bytes(const oct_handle *h, const oct_view *view);
  * missing-brick rule is not OCT_MISSING_AVG are not differentiable here (OCT_EINVAL).
  * The workspace must have been filled by the last render_views call that used it, with the
  * same views, and no upload or clear that changed the octree may come between the two.
+ * Voxel gradients of DVR views are first summed in a device scratch of the size of dL_dvoxels
+ * (in 16-voxel blocks, allocated on first use and kept by the handle; volumes whose scratch
+ * would pass 4 GiB are summed into dL_dvoxels directly), then added to dL_dvoxels.
  * Ordering: the backward follows every render and backward issued earlier on this handle, on
- * any stream (they share its table-gradient accumulators).
+ * any stream (they share its table-gradient accumulators and gradient scratch).
  * Errors: OCT_EINVAL (e.g. voxel gradients requested where not defined, a workspace not filled
  * by a render of this handle, views that differ from the forward's, an octree changed since
  * the forward), OCT_EDEVICE. */
