@@ -1532,7 +1532,16 @@ static int upload_paging_only(oct_handle *h, uint64_t byte_budget, hipStream_t s
     std::vector<int64_t> reqs;
     for (int L = g.N; L >= 0; L--) {
         const int64_t n = (int64_t)g.grid[L] * g.grid[L] * g.grid[L];
-        for (int64_t ci = g.cell_off[L]; ci < g.cell_off[L] + n; ci++) {
+        const int64_t end = g.cell_off[L] + n;
+        for (int64_t ci = g.cell_off[L]; ci < end; ci++) {
+            if ((ci & 7) == 0 && ci + 8 <= end) {   // most cells are unflagged: skip zero words
+                uint64_t w;
+                std::memcpy(&w, fl + ci, 8);
+                if (!w) {
+                    ci += 7;
+                    continue;
+                }
+            }
             if (fl[ci] == 1) h->last_used[(size_t)ci] = h->frame;
             else if (fl[ci] == 2 && h->data_cell[(size_t)ci] && h->cells[(size_t)ci].slot < 0)
                 reqs.push_back(ci);
